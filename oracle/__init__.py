@@ -1,0 +1,15 @@
+"""CPU oracle of the Flow Fields hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the package smoke check and
+the benchmark's CPU-baseline leg, never by the GPU library or its binding.
+The plain-integer path lives in ``ff_oracle.c`` (plain C, scalar loops) and
+is reached through the ctypes wrappers in ``oracle.core``; the float cost of
+the learned-descriptor form and its gradient live in ``oracle.float_cost``
+(NumPy, float64).
+"""
+from .core import (UNSET, build, lib, blur, descriptor, descriptors_all, cost, nn, init_coarse, seed_level,
+                   propagate, random_search, rs_offset, rs_radius, consistency, flow_fields, mix64)
+
+__all__ = ["UNSET", "build", "lib", "blur", "descriptor", "descriptors_all", "cost", "nn", "init_coarse",
+           "seed_level", "propagate", "random_search", "rs_offset", "rs_radius", "consistency",
+           "flow_fields", "mix64"]

@@ -1,0 +1,189 @@
+"""ctypes wrappers of the plain-C oracle (``ff_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every wrapper takes
+and returns NumPy arrays in the layouts documented at the top of
+``ff_oracle.c``; no GPU code is involved.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+UNSET = 0xFFFFFFFF
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ff_oracle.c")
+_LIB = os.path.join(_HERE, "libff_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host compiler (plain -O2, OpenMP threads)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i, u64, dbl = C.c_int, C.c_uint64, C.c_double
+        L.or_blur.argtypes = [P, i, i, i, P]
+        L.or_descriptor.argtypes = [P, i, i, i, P]
+        L.or_cost.argtypes = [P, P, i, i, i, i, i, i, i, i]
+        L.or_cost.restype = C.c_uint32
+        L.or_nn.argtypes = [P, P, i, i, i, P, P, i]
+        L.or_init_coarse.argtypes = [P, P, P, i, i, i, i, P, P, P]
+        L.or_seed_level.argtypes = [P, P, P, P, i, i, i, i, P, P, P]
+        L.or_propagate.argtypes = [P, P, i, i, i, i, i, P, P, P, i]
+        L.or_random_search.argtypes = [P, P, i, i, i, i, i, u64, i, i, i, P, P, P, i]
+        L.or_mix64.argtypes = [u64]
+        L.or_mix64.restype = u64
+        L.or_rs_offset.argtypes = [u64, i, i, i, i, i, i, P, P]
+        L.or_rs_radius.argtypes = [i, i, i]
+        L.or_rs_radius.restype = i
+        L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
+        L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
+        L.or_flow_fields.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def cells(W: int, H: int, n: int):
+    return -(-W // n), -(-H // n)
+
+
+def blur(img: np.ndarray, n: int) -> np.ndarray:
+    img = _u8(img)
+    H, W = img.shape
+    out = np.empty_like(img)
+    lib().or_blur(_p(img), W, H, n, _p(out))
+    return out
+
+
+def descriptor(blurred: np.ndarray, n: int) -> np.ndarray:
+    b = _u8(blurred)
+    H, W = b.shape
+    out = np.empty((H, W, 16), np.uint8)
+    lib().or_descriptor(_p(b), W, H, n, _p(out))
+    return out
+
+
+def descriptors_all(img: np.ndarray, levels: int):
+    return [descriptor(blur(img, 1 << l), 1 << l) for l in range(levels)]
+
+
+def cost(Da, Db, n: int, r: int, x: int, y: int, fx: int, fy: int) -> int:
+    H, W = Da.shape[:2]
+    return int(lib().or_cost(_p(Da), _p(Db), W, H, n, r, x, y, fx, fy))
+
+
+def nn(Da1, Db1, nc: int, nthreads: int = 1):
+    H, W = Da1.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    idx = np.empty((Hc, Wc), np.int32)
+    dist = np.empty((Hc, Wc), np.int64)
+    lib().or_nn(_p(Da1), _p(Db1), W, H, nc, _p(idx), _p(dist), nthreads)
+    return idx, dist
+
+
+def init_coarse(idx, Da, Db, nc: int, r: int = 3):
+    H, W = Da.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    flow = np.empty((Hc, Wc, 2), np.int16)
+    cost_ = np.empty((Hc, Wc), np.uint32)
+    ne = np.zeros(1, np.uint64)
+    idx = np.ascontiguousarray(idx, np.int32)
+    lib().or_init_coarse(_p(idx), _p(Da), _p(Db), W, H, nc, r, _p(flow), _p(cost_), _p(ne))
+    return flow, cost_, int(ne[0])
+
+
+def seed_level(cflow, ccost, Da, Db, n: int, r: int = 3):
+    H, W = Da.shape[:2]
+    Wn, Hn = cells(W, H, n)
+    flow = np.empty((Hn, Wn, 2), np.int16)
+    cost_ = np.empty((Hn, Wn), np.uint32)
+    ne = np.zeros(1, np.uint64)
+    cflow = np.ascontiguousarray(cflow, np.int16)
+    ccost = np.ascontiguousarray(ccost, np.uint32)
+    lib().or_seed_level(_p(cflow), _p(ccost), _p(Da), _p(Db), W, H, n, r, _p(flow), _p(cost_), _p(ne))
+    return flow, cost_, int(ne[0])
+
+
+def propagate(Da, Db, n: int, pass_: int, flow, cost_, r: int = 3, nthreads: int = 1):
+    """In-place propagation step on copies; returns (flow, cost, n_evals)."""
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_propagate(_p(Da), _p(Db), W, H, n, r, pass_, _p(flow), _p(cost_), _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def rs_radius(n: int, R_num: int, R_den: int) -> int:
+    return int(lib().or_rs_radius(n, R_num, R_den))
+
+
+def random_search(Da, Db, n: int, Rn: int, seed: int, stream: int, level: int, pass_: int, flow, cost_,
+                  r: int = 3, nthreads: int = 1):
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_random_search(_p(Da), _p(Db), W, H, n, r, Rn, seed, stream, level, pass_, _p(flow), _p(cost_),
+                           _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def mix64(z: int) -> int:
+    return int(lib().or_mix64(z))
+
+
+def rs_offset(seed: int, stream: int, level: int, pass_: int, j: int, i: int, Rn: int):
+    ox, oy = C.c_int(), C.c_int()
+    lib().or_rs_offset(seed, stream, level, pass_, j, i, Rn, C.byref(ox), C.byref(oy))
+    return ox.value, oy.value
+
+
+def consistency(fa, ca, fb, cb, eps: float = 1.0):
+    H, W = ca.shape
+    keep = np.empty((H, W), np.uint8)
+    args = [np.ascontiguousarray(a) for a in (fa, ca, fb, cb)]
+    lib().or_consistency(*[_p(a) for a in args], W, H, float(eps), _p(keep))
+    return keep
+
+
+def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
+                eps: float = 1.0, seed: int = 12345, nthreads: int = 1) -> dict:
+    img1, img2 = _u8(img1), _u8(img2)
+    H, W = img1.shape
+    out = {
+        "flow_fwd": np.empty((H, W, 2), np.int16), "flow_bwd": np.empty((H, W, 2), np.int16),
+        "cost_fwd": np.empty((H, W), np.uint32), "cost_bwd": np.empty((H, W), np.uint32),
+        "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
+    }
+    ne = np.zeros(2, np.uint64)
+    rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, float(eps), seed,
+                              nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
+                              _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    out["n_evals"] = (int(ne[0]), int(ne[1]))
+    return out

@@ -1,0 +1,402 @@
+/*
+ * ff_oracle.c -- plain, slow CPU oracle of the Flow Fields hot path
+ * (Bailer, Taetz, Stricker, "Flow Fields: Dense Correspondence Fields for
+ * Highly Accurate Large Displacement Optical Flow Estimation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library; it is written from the paper's
+ * description of the method, in the paper's order, with plain scalar loops.
+ *
+ * What it computes (readings of the paper are marked R#, listed in full in
+ * the design notes of the repository):
+ *   blur        scale-space low-pass I^n (Sec. 3.2; Sec. 3.6 low-pass and
+ *               replicate border), R12: integer box filter of half-width
+ *               max(1, n/2), rounded half up.
+ *   descriptor  per-pixel 16-byte feature of I^n: 4x4 samples with spacing 2n
+ *               (F2 reading of Sec. 3.6, features taken after low-pass), R13.
+ *   cost        matching error E_n of the subsampled patch P^n_r (Eq. 3):
+ *               sum over (2r+1)^2 patch positions of the byte-wise SAD of the
+ *               two descriptors, replicate border at every read.
+ *   nn          exact nearest neighbour of every coarsest-grid pixel over all
+ *               pixels of the other image under squared L2 of the level-1
+ *               descriptors (stands in for the kd-tree of Sec. 3.1 with leaf
+ *               size 1, R4); ties go to the smallest linear index.
+ *   init        initial flow F = q - p (Eq. 1 / Eq. 4 with |L| = 1) and its
+ *               cost at the coarsest scale.
+ *   seed_level  coarse-to-fine hand-over (Sec. 3.2): grid pixels shared with
+ *               the coarser grid keep its flow (same full-resolution pixel)
+ *               and re-evaluate the cost; all others start UNSET.
+ *   propagate   one propagation step (Eq. 2) in direction d = pass mod 4
+ *               (R2: d cycle right-down, left-up, left-down, right-up) run
+ *               as two checkerboard half-sweeps (R1), odd (i+j) first (R11);
+ *               candidate order own, horizontal, vertical, strict "<" (R3);
+ *               candidates whose target leaves the image are rejected (R9).
+ *   random_search  one random-search step (Sec. 3.1) with integer offsets
+ *               uniform on [-R_n, R_n]^2, R_n = floor(R * n) (R5, R6), drawn
+ *               from a counter-based generator: SplitMix64's output mixer
+ *               (Steele, Lea, Flood, OOPSLA 2014) applied as
+ *               mix(seed ^ mix(counter)), mapped to a range by Lemire's
+ *               multiply-shift (ACM TOMACS 2019).
+ *   consistency forward-backward check (Sec. 3.7): keep p iff
+ *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14).
+ *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
+ *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
+ *               random-search steps between them, forward and backward.
+ *
+ * Layouts: images uint8 [H][W]; descriptors uint8 [H][W][16]; a level grid
+ * of scale n has ceil(W/n) x ceil(H/n) cells, cell (i, j) <-> pixel
+ * (i*n, j*n); flows int16 [cells][2] (dx, dy); costs uint32 [cells] with
+ * 0xFFFFFFFF = UNSET (its flow is (0, 0)).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_UNSET 0xFFFFFFFFu
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+int or_version(void) { return 1; }
+
+/* Scale-space image I^n (Sec. 3.2 scale spaces; Sec. 3.6 low-pass; Sec. 3.6
+ * border condition): every output pixel is the rounded mean of the
+ * (2h+1)x(2h+1) window around it, h = max(1, n/2), pixels outside the image
+ * replaced by the nearest inside pixel. */
+void or_blur(const uint8_t *img, int W, int H, int n, uint8_t *out)
+{
+    int h = n / 2 < 1 ? 1 : n / 2;
+    int64_t area = (int64_t)(2 * h + 1) * (2 * h + 1);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t s = 0;
+            for (int dy = -h; dy <= h; ++dy)
+                for (int dx = -h; dx <= h; ++dx)
+                    s += img[(size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            out[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
+        }
+}
+
+/* Per-pixel feature of scale n: 16 samples of I^n on a 4x4 grid with spacing
+ * 2n centred on the pixel, channel 4*gy + gx <-> offset n*(2gx-3, 2gy-3),
+ * replicate border. */
+void or_descriptor(const uint8_t *blurred, int W, int H, int n, uint8_t *desc)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int gy = 0; gy < 4; ++gy)
+                for (int gx = 0; gx < 4; ++gx) {
+                    int sx = clampi(x + n * (2 * gx - 3), 0, W - 1);
+                    int sy = clampi(y + n * (2 * gy - 3), 0, H - 1);
+                    desc[((size_t)y * W + x) * 16 + 4 * gy + gx] = blurred[(size_t)sy * W + sx];
+                }
+}
+
+/* Matching error E_n(p, f) of the subsampled patch P^n_r (Eq. 3): every n-th
+ * pixel within radius r*n of p in image a against the same pattern around
+ * p + f in image b; each patch position contributes the sum of absolute
+ * differences of the two 16-byte descriptors; reads outside the image take
+ * the nearest inside pixel. */
+uint32_t or_cost(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r,
+                 int x, int y, int fx, int fy)
+{
+    uint32_t s = 0;
+    for (int v = -r; v <= r; ++v)
+        for (int u = -r; u <= r; ++u) {
+            int ax = clampi(x + n * u, 0, W - 1), ay = clampi(y + n * v, 0, H - 1);
+            int bx = clampi(x + fx + n * u, 0, W - 1), by = clampi(y + fy + n * v, 0, H - 1);
+            const uint8_t *a = Da + ((size_t)ay * W + ax) * 16;
+            const uint8_t *b = Db + ((size_t)by * W + bx) * 16;
+            for (int c = 0; c < 16; ++c)
+                s += (uint32_t)abs((int)a[c] - (int)b[c]);
+        }
+    return s;
+}
+
+/* Exact nearest neighbour (stands in for the kd-tree candidate set of
+ * Sec. 3.1): for every cell of the grid of scale nc, the pixel q of image b
+ * whose level-1 descriptor has the smallest squared L2 distance to the
+ * cell's pixel descriptor in image a; ties -> smallest q.y*W + q.x. */
+void or_nn(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc,
+           int32_t *best_idx, int64_t *best_dist, int nthreads)
+{
+    int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
+    int64_t N = (int64_t)W * H;
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (int k = 0; k < Wc * Hc; ++k) {
+        int i = k % Wc, j = k / Wc;
+        const uint8_t *a = Da1 + ((size_t)(j * nc) * W + (size_t)(i * nc)) * 16;
+        int64_t bd = INT64_MAX;
+        int32_t bi = -1;
+        for (int64_t q = 0; q < N; ++q) {
+            const uint8_t *b = Db1 + (size_t)q * 16;
+            int64_t d = 0;
+            for (int c = 0; c < 16; ++c) {
+                int64_t e = (int64_t)a[c] - (int64_t)b[c];
+                d += e * e;
+            }
+            if (d < bd) { bd = d; bi = (int32_t)q; }
+        }
+        best_idx[k] = bi;
+        best_dist[k] = bd;
+    }
+}
+
+/* Initial flow of the coarsest scale (Eq. 1 / Eq. 4 with one candidate):
+ * F(p) = q - p, cost = E_nc(p, F(p)). */
+void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
+                    int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
+    for (int j = 0; j < Hc; ++j)
+        for (int i = 0; i < Wc; ++i) {
+            int k = j * Wc + i, x = i * nc, y = j * nc;
+            int qx = best_idx[k] % W, qy = best_idx[k] / W;
+            flow[2 * k] = (int16_t)(qx - x);
+            flow[2 * k + 1] = (int16_t)(qy - y);
+            cost[k] = or_cost(Da, Db, W, H, nc, r, x, y, qx - x, qy - y);
+            *n_evals += 1;
+        }
+}
+
+/* Hand-over from scale 2n to scale n (Sec. 3.2): cell (i, j) with i and j
+ * even is the same full-resolution pixel as coarse cell (i/2, j/2) and takes
+ * its flow as a seed (flows are kept in full-resolution pixel units); its
+ * cost is re-evaluated with E_n.  All other cells start UNSET and receive a
+ * value in the first propagation step. */
+void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db,
+                   int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n), Wc = ceil_div(W, 2 * n);
+    for (int j = 0; j < Hn; ++j)
+        for (int i = 0; i < Wn; ++i) {
+            int k = j * Wn + i;
+            flow[2 * k] = 0;
+            flow[2 * k + 1] = 0;
+            cost[k] = OR_UNSET;
+            if ((i & 1) || (j & 1)) continue;
+            int kc = (j / 2) * Wc + i / 2;
+            if (ccost[kc] == OR_UNSET) continue;
+            int fx = cflow[2 * kc], fy = cflow[2 * kc + 1];
+            flow[2 * k] = (int16_t)fx;
+            flow[2 * k + 1] = (int16_t)fy;
+            cost[k] = or_cost(Da, Db, W, H, n, r, i * n, j * n, fx, fy);
+            *n_evals += 1;
+        }
+}
+
+/* Source cells of propagation direction d (Eq. 2 for d = 0; the other three
+ * quadrants for d = 1..3). */
+static void prop_sources(int d, int *hdi, int *vdj)
+{
+    static const int H_[4] = {-1, +1, +1, -1};
+    static const int V_[4] = {-1, +1, -1, +1};
+    *hdi = H_[d & 3];
+    *vdj = V_[d & 3];
+}
+
+/* One propagation step (Eq. 2) at scale n: for every cell the flow is the
+ * best of its own flow and the flows of its horizontal and vertical source
+ * cells, by E_n with strict improvement.  Run as two half-sweeps: first all
+ * cells with (i+j) odd, then all with (i+j) even; a cell only reads cells of
+ * the other colour, so the result does not depend on the visiting order. */
+void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
+                  int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
+{
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
+    prop_sources(pass & 3, &hdi, &vdj);
+    (void)nthreads;
+    for (int colour = 1; colour >= 0; --colour) {
+        uint64_t cnt = 0;
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+ : cnt) schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+        for (int j = 0; j < Hn; ++j)
+            for (int i = 0; i < Wn; ++i) {
+                if (((i + j) & 1) != colour) continue;
+                int k = j * Wn + i, x = i * n, y = j * n;
+                uint32_t bc = cost[k];
+                int bfx = flow[2 * k], bfy = flow[2 * k + 1];
+                for (int s = 0; s < 2; ++s) {
+                    int si = s == 0 ? i + hdi : i, sj = s == 0 ? j : j + vdj;
+                    if (si < 0 || si >= Wn || sj < 0 || sj >= Hn) continue;
+                    int ks = sj * Wn + si;
+                    if (cost[ks] == OR_UNSET) continue;
+                    int fx = flow[2 * ks], fy = flow[2 * ks + 1];
+                    if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
+                    if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
+                    uint32_t e = or_cost(Da, Db, W, H, n, r, x, y, fx, fy);
+                    cnt += 1;
+                    if (e < bc) { bc = e; bfx = fx; bfy = fy; }
+                }
+                cost[k] = bc;
+                flow[2 * k] = (int16_t)bfx;
+                flow[2 * k + 1] = (int16_t)bfy;
+            }
+        *n_evals += cnt;
+    }
+}
+
+/* SplitMix64 output mixer (Steele, Lea, Flood 2014). */
+uint64_t or_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Counter of one random draw: direction stream, level, step, cell. */
+uint64_t or_rs_counter(int stream, int level, int pass, int j, int i)
+{
+    return ((uint64_t)(stream & 0xFF) << 56) | ((uint64_t)(level & 0xFF) << 48) |
+           ((uint64_t)(pass & 0xFFFF) << 32) | ((uint64_t)(j & 0xFFFF) << 16) | (uint64_t)(i & 0xFFFF);
+}
+
+/* Integer random-search offset of a cell, uniform on [-Rn, Rn]^2: the low
+ * and high 32-bit halves of the draw are mapped to [0, 2Rn] by
+ * multiply-shift. */
+void or_rs_offset(uint64_t seed, int stream, int level, int pass, int j, int i, int Rn, int *ox, int *oy)
+{
+    uint64_t h = or_mix64(seed ^ or_mix64(or_rs_counter(stream, level, pass, j, i)));
+    uint64_t span = (uint64_t)(2 * Rn + 1);
+    *ox = (int)(((h & 0xFFFFFFFFULL) * span) >> 32) - Rn;
+    *oy = (int)(((h >> 32) * span) >> 32) - Rn;
+}
+
+/* One random-search step (Sec. 3.1): every set cell tries its flow plus a
+ * random offset and keeps it if E_n strictly decreases.  Offset (0, 0) and
+ * targets outside the image are skipped. */
+void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int Rn,
+                      uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
+                      uint64_t *n_evals, int nthreads)
+{
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n);
+    uint64_t cnt = 0;
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+ : cnt) schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (int j = 0; j < Hn; ++j)
+        for (int i = 0; i < Wn; ++i) {
+            int k = j * Wn + i, x = i * n, y = j * n, ox, oy;
+            if (cost[k] == OR_UNSET) continue;
+            or_rs_offset(seed, stream, level, pass, j, i, Rn, &ox, &oy);
+            if (ox == 0 && oy == 0) continue;
+            int fx = flow[2 * k] + ox, fy = flow[2 * k + 1] + oy;
+            if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
+            uint32_t e = or_cost(Da, Db, W, H, n, r, x, y, fx, fy);
+            cnt += 1;
+            if (e < cost[k]) {
+                cost[k] = e;
+                flow[2 * k] = (int16_t)fx;
+                flow[2 * k + 1] = (int16_t)fy;
+            }
+        }
+    *n_evals += cnt;
+}
+
+/* Forward-backward consistency (Sec. 3.7): keep pixel p of field a iff it is
+ * set, its target q = p + F_a(p) is set in field b and
+ * |F_a(p) + F_b(q)|^2 < eps^2 (integer flows, exact). */
+void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
+                    int W, int H, double eps, uint8_t *keep)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t k = (size_t)y * W + x;
+            keep[k] = 0;
+            if (ca[k] == OR_UNSET) continue;
+            int qx = x + fa[2 * k], qy = y + fa[2 * k + 1];
+            size_t kq = (size_t)qy * W + qx;
+            if (cb[kq] == OR_UNSET) continue;
+            int64_t dx = fa[2 * k] + fb[2 * kq], dy = fa[2 * k + 1] + fb[2 * kq + 1];
+            keep[k] = (double)(dx * dx + dy * dy) < eps * eps;
+        }
+}
+
+/* R_n = floor(R * n) with R = R_num / R_den (R6). */
+int or_rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
+
+/* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b. */
+static void flow_one_direction(const uint8_t *const *Da, const uint8_t *const *Db, int W, int H, int L,
+                               int T, int r, int R_num, int R_den, uint64_t seed, int stream,
+                               int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
+{
+    int nc = 1 << (L - 1);
+    int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
+    size_t cells0 = (size_t)W * H;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)Wc * Hc);
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)Wc * Hc);
+    int16_t *fl[2];
+    uint32_t *co[2];
+    for (int b = 0; b < 2; ++b) {
+        fl[b] = (int16_t *)malloc(sizeof(int16_t) * 2 * cells0);
+        co[b] = (uint32_t *)malloc(sizeof(uint32_t) * cells0);
+    }
+    or_nn(Da[0], Db[0], W, H, nc, idx, dist, nthreads);
+    int cur = 0;
+    or_init_coarse(idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
+    for (int level = L - 1; level >= 0; --level) {
+        int n = 1 << level;
+        if (level < L - 1) {
+            or_seed_level(fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
+            cur ^= 1;
+        }
+        int Rn = or_rs_radius(n, R_num, R_den);
+        for (int t = 0; t < T; ++t) {
+            or_propagate(Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
+            if (t < T - 1)
+                or_random_search(Da[level], Db[level], W, H, n, r, Rn, seed, stream, level, t, fl[cur],
+                                 co[cur], n_evals, nthreads);
+        }
+    }
+    memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells0);
+    memcpy(cost_out, co[cur], sizeof(uint32_t) * cells0);
+    for (int b = 0; b < 2; ++b) { free(fl[b]); free(co[b]); }
+    free(idx);
+    free(dist);
+}
+
+/* The whole hot path for one image pair: scale-space descriptors of both
+ * images at every level, forward field (img1 -> img2, stream 0), backward
+ * field (img2 -> img1, stream 1) and both consistency masks.
+ * n_evals[0], n_evals[1]: number of E_n evaluations of each direction. */
+int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r,
+                   int R_num, int R_den, double eps, uint64_t seed, int nthreads,
+                   int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                   uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+{
+    if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
+        R_num < 0 || R_den < 1)
+        return 1;
+    size_t np = (size_t)W * H;
+    uint8_t *blur = (uint8_t *)malloc(np);
+    uint8_t *D1[7], *D2[7];
+    for (int l = 0; l < L; ++l) {
+        int n = 1 << l;
+        D1[l] = (uint8_t *)malloc(np * 16);
+        D2[l] = (uint8_t *)malloc(np * 16);
+        or_blur(img1, W, H, n, blur);
+        or_descriptor(blur, W, H, n, D1[l]);
+        or_blur(img2, W, H, n, blur);
+        or_descriptor(blur, W, H, n, D2[l]);
+    }
+    n_evals[0] = n_evals[1] = 0;
+    flow_one_direction((const uint8_t *const *)D1, (const uint8_t *const *)D2, W, H, L, T, r, R_num, R_den,
+                       seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+    flow_one_direction((const uint8_t *const *)D2, (const uint8_t *const *)D1, W, H, L, T, r, R_num, R_den,
+                       seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+    or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
+    if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
+    for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
+    free(blur);
+    return 0;
+}

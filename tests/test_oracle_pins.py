@@ -1,0 +1,448 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test ties one oracle function to something other than itself: a value
+worked by hand, a library routine, a closed form, an invariant of the method
+or brute force on tiny inputs.  Sections cited are those of Bailer, Taetz,
+Stricker, "Flow Fields" (the journal version).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from ffgen import make_pair, random_images, translated_crops
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+UNSET = oracle.UNSET
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line)
+    return rows
+
+
+# ---------------------------------------------------------------- blur (Sec. 3.2, Sec. 3.6)
+
+def test_blur_hand_worked_example():
+    rows = [list(map(int, r.split())) for r in _read_golden("blur_desc_5x4.txt")]
+    img = np.array(rows[:4], np.uint8)
+    expect = np.array(rows[4:], np.uint8)
+    assert np.array_equal(oracle.blur(img, 1), expect)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
+def test_blur_equals_library_box_sum(n):
+    img, _ = random_images(11 + n, 37, 53, kind="uniform")
+    h = max(1, n // 2)
+    k = np.ones((2 * h + 1, 2 * h + 1), np.int64)
+    s = ndi.correlate(img.astype(np.int64), k, mode="nearest")
+    A = (2 * h + 1) ** 2
+    assert np.array_equal(oracle.blur(img, n), ((s + A // 2) // A).astype(np.uint8))
+
+
+def test_blur_constant_image_is_constant():
+    img = np.full((9, 13), 77, np.uint8)
+    for n in (1, 4, 16):
+        assert np.all(oracle.blur(img, n) == 77)
+
+
+# ---------------------------------------------------------------- descriptor (Sec. 3.6, F2)
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_descriptor_channels_are_edge_padded_shifts(n):
+    b, _ = random_images(5, 23, 31, kind="uniform")
+    d = oracle.descriptor(b, n)
+    m = 3 * n
+    p = np.pad(b, m, mode="edge")
+    H, W = b.shape
+    for gy in range(4):
+        for gx in range(4):
+            oy, ox = n * (2 * gy - 3), n * (2 * gx - 3)
+            assert np.array_equal(d[..., 4 * gy + gx], p[m + oy:m + oy + H, m + ox:m + ox + W])
+
+
+def test_descriptor_constant_image():
+    d = oracle.descriptor(np.full((7, 6), 200, np.uint8), 2)
+    assert np.all(d == 200)
+
+
+# ---------------------------------------------------------------- cost E_n (Eq. 3)
+
+W13 = np.array([1, 1, 2, 2, 3, 3, 4, 3, 3, 2, 2, 1, 1], np.int64)
+
+
+def _weighted_13x13(Ba, Bb, n, p, q):
+    """E_n in the interior written on the blurred images: every descriptor
+    channel is one blurred sample, patch offset u plus descriptor offset
+    2g-3 covers a = -6..6 with multiplicity W13[a+6] per axis."""
+    s = 0
+    for b in range(-6, 7):
+        for a in range(-6, 7):
+            va = int(Ba[p[1] + n * b, p[0] + n * a])
+            vb = int(Bb[q[1] + n * b, q[0] + n * a])
+            s += W13[a + 6] * W13[b + 6] * abs(va - vb)
+    return s
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_cost_interior_weighted_identity(n):
+    H, W = 40 + 12 * n, 44 + 12 * n
+    ia, ib = random_images(3 * n, H, W)
+    Ba, Bb = oracle.blur(ia, n), oracle.blur(ib, n)
+    Da, Db = oracle.descriptor(Ba, n), oracle.descriptor(Bb, n)
+    rng = np.random.default_rng(n)
+    lo = 6 * n
+    for _ in range(25):
+        p = (int(rng.integers(lo, W - lo)), int(rng.integers(lo, H - lo)))
+        q = (int(rng.integers(lo, W - lo)), int(rng.integers(lo, H - lo)))
+        e = oracle.cost(Da, Db, n, 3, p[0], p[1], q[0] - p[0], q[1] - p[1])
+        assert e == _weighted_13x13(Ba, Bb, n, p, q)
+
+
+def test_cost_border_is_edge_replication():
+    n, r = 2, 3
+    ia, ib = random_images(9, 20, 26)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    M = 3 * n * 2 + 30
+    Pa = np.ascontiguousarray(np.pad(Da, ((M, M), (M, M), (0, 0)), mode="edge"))
+    Pb = np.ascontiguousarray(np.pad(Db, ((M, M), (M, M), (0, 0)), mode="edge"))
+    H, W = ia.shape
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        x, y = int(rng.integers(0, W)), int(rng.integers(0, H))
+        tx, ty = int(rng.integers(0, W)), int(rng.integers(0, H))
+        e = oracle.cost(Da, Db, n, r, x, y, tx - x, ty - y)
+        e_pad = oracle.cost(Pa, Pb, n, r, x + M, y + M, tx - x, ty - y)
+        assert e == e_pad
+
+
+def test_cost_zero_symmetry_and_bound():
+    ia, ib = random_images(4, 18, 22)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    assert oracle.cost(Da, Da, 1, 3, 5, 7, 0, 0) == 0
+    rng = np.random.default_rng(1)
+    for _ in range(30):
+        x, y = int(rng.integers(0, 22)), int(rng.integers(0, 18))
+        tx, ty = int(rng.integers(0, 22)), int(rng.integers(0, 18))
+        e = oracle.cost(Da, Db, 1, 3, x, y, tx - x, ty - y)
+        # roles of the images swapped, seen from the target pixel
+        assert e == oracle.cost(Db, Da, 1, 3, tx, ty, x - tx, y - ty)
+        assert e <= 49 * 16 * 255
+    white = np.full_like(Da, 255)
+    black = np.zeros_like(Da)
+    assert oracle.cost(white, black, 1, 3, 3, 3, 1, 1) == 49 * 16 * 255
+
+
+# ---------------------------------------------------------------- NN seed (Sec. 3.1 / 3.2 init)
+
+@pytest.mark.parametrize("nc", [1, 2, 4])
+def test_nn_equals_numpy_brute_force(nc):
+    ia, ib = random_images(21 + nc, 17, 23, kind="uniform")
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    idx, dist = oracle.nn(Da, Db, nc, nthreads=2)
+    H, W = ia.shape
+    q = Da[::nc, ::nc].reshape(-1, 16).astype(np.int64)
+    refs = Db.reshape(-1, 16).astype(np.int64)
+    d = ((q[:, None, :] - refs[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(idx.reshape(-1), np.argmin(d, axis=1))  # first minimum = smallest index
+    assert np.array_equal(dist.reshape(-1), d.min(axis=1))
+
+
+def test_nn_ties_go_to_smallest_index():
+    ia, _ = random_images(2, 12, 14)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = np.full_like(Da, 100)
+    idx, _ = oracle.nn(Da, Db, 2)
+    assert np.all(idx == 0)
+    Db = Db.copy()
+    Db[5, 7] = Da[4, 6]
+    Db[9, 2] = Da[4, 6]
+    idx, dist = oracle.nn(Da, Db, 2)
+    assert idx[2, 3] == 5 * 14 + 7 and dist[2, 3] == 0
+
+
+def test_init_coarse_flow_is_target_minus_pixel():
+    ia, ib = random_images(8, 21, 27)
+    nc = 4
+    Da1 = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db1 = oracle.descriptor(oracle.blur(ib, 1), 1)
+    Dac = oracle.descriptor(oracle.blur(ia, nc), nc)
+    Dbc = oracle.descriptor(oracle.blur(ib, nc), nc)
+    idx, _ = oracle.nn(Da1, Db1, nc)
+    flow, cost, ne = oracle.init_coarse(idx, Dac, Dbc, nc)
+    Hc, Wc = idx.shape
+    assert ne == Hc * Wc
+    for j in range(Hc):
+        for i in range(Wc):
+            qx, qy = idx[j, i] % 27, idx[j, i] // 27
+            assert tuple(flow[j, i]) == (qx - i * nc, qy - j * nc)
+            assert 0 <= i * nc + flow[j, i, 0] < 27 and 0 <= j * nc + flow[j, i, 1] < 21
+
+
+# ---------------------------------------------------------------- level seeding (Sec. 3.2)
+
+def test_seed_level_keeps_shared_pixels_and_unsets_others():
+    ia, ib = random_images(12, 19, 25)
+    n = 2
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    Wc, Hc = -(-25 // 4), -(-19 // 4)
+    rng = np.random.default_rng(3)
+    cflow = np.stack([rng.integers(-3, 4, (Hc, Wc)), rng.integers(-3, 4, (Hc, Wc))], -1).astype(np.int16)
+    ccost = rng.integers(0, 1000, (Hc, Wc)).astype(np.uint32)
+    ccost[1, 2] = UNSET
+    cflow[1, 2] = 0
+    flow, cost, ne = oracle.seed_level(cflow, ccost, Da, Db, n)
+    Hn, Wn = cost.shape
+    assert (Wn, Hn) == (13, 10)
+    n_set = 0
+    for j in range(Hn):
+        for i in range(Wn):
+            if i % 2 == 0 and j % 2 == 0 and ccost[j // 2, i // 2] != UNSET:
+                assert tuple(flow[j, i]) == tuple(cflow[j // 2, i // 2])
+                fx, fy = map(int, flow[j, i])
+                assert cost[j, i] == oracle.cost(Da, Db, n, 3, i * n, j * n, fx, fy)
+                n_set += 1
+            else:
+                assert cost[j, i] == UNSET and tuple(flow[j, i]) == (0, 0)
+    assert ne == n_set
+
+
+# ---------------------------------------------------------------- propagation (Eq. 2, Fig. 4)
+
+QUADRANT = {0: (+1, +1), 1: (-1, -1), 2: (-1, +1), 3: (+1, -1)}
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3])
+def test_propagation_spreads_into_its_quadrant(d):
+    """A lone seed spreads within one 90-degree quadrant per step (Fig. 4a/c);
+    the first direction is right and down (Sec. 3.1).  With two
+    half-sweeps, odd cells first, one step reaches Manhattan distance 2."""
+    ia, ib = random_images(30 + d, 24, 24)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    flow = np.zeros((24, 24, 2), np.int16)
+    cost = np.full((24, 24), UNSET, np.uint32)
+    i0, j0 = 12, 10
+    cost[j0, i0] = 5
+    flow2, cost2, ne = oracle.propagate(Da, Db, 1, d, flow, cost)
+    sx, sy = QUADRANT[d]
+    expect = {(i0 + sx * a, j0 + sy * b) for a in range(3) for b in range(3) if a + b <= 2}
+    got = {(i, j) for j in range(24) for i in range(24) if cost2[j, i] != UNSET}
+    assert got == expect
+    # one evaluation per new cell: the diagonal cell's second source holds the
+    # flow it has just taken and is skipped
+    assert ne == 5
+    assert np.all(flow2 == 0)
+
+
+def test_propagation_is_monotone_and_consistent():
+    ia, ib = random_images(40, 20, 28)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    idx, _ = oracle.nn(Da, Db, 1)
+    flow, cost, _ = oracle.init_coarse(idx, Da, Db, 1)
+    for t in range(4):
+        f2, c2, _ = oracle.propagate(Da, Db, 1, t, flow, cost)
+        assert np.all(c2 <= cost)
+        for j in range(20):
+            for i in range(28):
+                fx, fy = map(int, f2[j, i])
+                assert c2[j, i] == oracle.cost(Da, Db, 1, 3, i, j, fx, fy)
+        # every new flow came from a cell of the old or half-updated field
+        old = {tuple(v) for v in flow.reshape(-1, 2)}
+        assert {tuple(v) for v in f2.reshape(-1, 2)} <= old
+        flow, cost = f2, c2
+
+
+def test_propagation_half_sweep_optimality():
+    """After a step, an even cell (second half-sweep) is at least as good as
+    both of its source flows, which it read in their final state."""
+    ia, ib = random_images(41, 18, 26)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    idx, _ = oracle.nn(Da, Db, 1)
+    flow, cost, _ = oracle.init_coarse(idx, Da, Db, 1)
+    for d in range(4):
+        f2, c2, _ = oracle.propagate(Da, Db, 1, d, flow, cost)
+        hx, vy = {0: (-1, -1), 1: (1, 1), 2: (1, -1), 3: (-1, 1)}[d]
+        for j in range(18):
+            for i in range(26):
+                if (i + j) % 2:
+                    continue
+                for (si, sj) in ((i + hx, j), (i, j + vy)):
+                    if 0 <= si < 26 and 0 <= sj < 18:
+                        fx, fy = map(int, f2[sj, si])
+                        if 0 <= i + fx < 26 and 0 <= j + fy < 18:
+                            assert c2[j, i] <= oracle.cost(Da, Db, 1, 3, i, j, fx, fy)
+
+
+# ---------------------------------------------------------------- random search (Sec. 3.1)
+
+def test_splitmix64_known_answer():
+    expect = [int(s, 16) for s in _read_golden("splitmix64_seed0.txt")]
+    M = (1 << 64) - 1
+    x, got = 0, []
+    for _ in range(3):
+        x = (x + 0x9E3779B97F4A7C15) & M
+        got.append(oracle.mix64(x))
+    assert got == expect
+
+
+def test_rs_offsets_uniform_on_square():
+    for Rn in (1, 2, 6):
+        side = 2 * Rn + 1
+        counts = np.zeros((side, side), np.int64)
+        for j in range(60):
+            for i in range(100):
+                ox, oy = oracle.rs_offset(12345, 0, 2, 1, j, i, Rn)
+                assert -Rn <= ox <= Rn and -Rn <= oy <= Rn
+                counts[oy + Rn, ox + Rn] += 1
+        exp = counts.sum() / side ** 2
+        chi2 = ((counts - exp) ** 2 / exp).sum()
+        dof = side ** 2 - 1
+        assert chi2 < dof + 6 * np.sqrt(2 * dof)
+    a = [oracle.rs_offset(7, 0, 0, 0, 0, i, 6) for i in range(64)]
+    for other in ([oracle.rs_offset(7, 1, 0, 0, 0, i, 6) for i in range(64)],
+                  [oracle.rs_offset(7, 0, 1, 0, 0, i, 6) for i in range(64)],
+                  [oracle.rs_offset(7, 0, 0, 1, 0, i, 6) for i in range(64)],
+                  [oracle.rs_offset(8, 0, 0, 0, 0, i, 6) for i in range(64)]):
+        assert sum(x == y for x, y in zip(a, other)) < 16
+
+
+def test_rs_radius_floor():
+    assert [oracle.rs_radius(n, 1, 1) for n in (1, 2, 4, 8)] == [1, 2, 4, 8]
+    assert [oracle.rs_radius(n, 3, 2) for n in (1, 2, 4, 8, 16)] == [1, 3, 6, 12, 24]
+
+
+def test_random_search_never_worsens_and_moves_locally():
+    ia, ib = random_images(50, 22, 30)
+    n = 2
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    idx, _ = oracle.nn(oracle.descriptor(oracle.blur(ia, 1), 1), oracle.descriptor(oracle.blur(ib, 1), 1), n)
+    flow, cost, _ = oracle.init_coarse(idx, Da, Db, n)
+    cost[0, 0] = UNSET
+    flow[0, 0] = 0
+    f2, c2, ne = oracle.random_search(Da, Db, n, 2, 99, 0, 1, 0, flow, cost)
+    assert np.all(c2 <= cost)
+    assert c2[0, 0] == UNSET
+    moved = np.any(f2 != flow, axis=-1)
+    assert moved.any()
+    assert np.abs(f2.astype(int) - flow.astype(int)).max() <= 2
+    assert ne <= cost.size - 1
+
+
+# ---------------------------------------------------------------- consistency (Sec. 3.7)
+
+def test_consistency_closed_form():
+    H, W = 10, 12
+    fa = np.zeros((H, W, 2), np.int16)
+    fa[..., 0] = 3
+    fa[..., 1] = -1
+    fb = -fa.copy()
+    ca = np.zeros((H, W), np.uint32)
+    cb = np.zeros((H, W), np.uint32)
+    # every target must be in the image: the method never holds an outside target
+    xs, ys = np.meshgrid(np.arange(W), np.arange(H))
+    out = (xs + 3 >= W) | (ys - 1 < 0)
+    ca[out] = UNSET
+    fa[out] = 0
+    keep = oracle.consistency(fa, ca, fb, cb, 1.0)
+    assert np.array_equal(keep.astype(bool), ~out)
+    fb2 = fb.copy()
+    fb2[4, 7] = (-3, 2)  # off by one px from the inverse of (3, -1) at pixel (4, 5)
+    keep2 = oracle.consistency(fa, ca, fb2, cb, 1.0)
+    assert keep2[5, 4] == 0 and keep2.sum() == keep.sum() - 1
+    assert oracle.consistency(fa, ca, fb2, cb, 1.5)[5, 4] == 1   # |d| = 1 < 1.5
+    cb2 = cb.copy()
+    cb2[4, 7] = UNSET
+    assert oracle.consistency(fa, ca, fb, cb2, 5.0)[5, 4] == 0
+
+
+def test_consistency_kept_sets_are_in_bijection():
+    p = make_pair(1)
+    o = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4)
+    kf, kb = o["keep_fwd"].astype(bool), o["keep_bwd"].astype(bool)
+    ff, fb = o["flow_fwd"].astype(int), o["flow_bwd"].astype(int)
+    ys, xs = np.nonzero(kf)
+    qx, qy = xs + ff[ys, xs, 0], ys + ff[ys, xs, 1]
+    assert np.all(kb[qy, qx])
+    assert np.array_equal(fb[qy, qx], -ff[ys, xs])
+    assert kf.sum() == kb.sum()
+
+
+# ---------------------------------------------------------------- whole field (Sec. 3.2)
+
+def test_identical_images_give_zero_field():
+    img, _ = random_images(60, 48, 64)
+    o = oracle.flow_fields(img, img, 3, 4, nthreads=2)
+    for k in ("flow_fwd", "flow_bwd"):
+        assert np.all(o[k] == 0)
+    assert np.all(o["cost_fwd"] == 0) and np.all(o["cost_bwd"] == 0)
+    assert np.all(o["keep_fwd"] == 1)
+
+
+@pytest.mark.parametrize("t", [(5, -3), (-9, 4), (0, 7)])
+def test_integer_translation_exact_recovery(t):
+    img1, img2 = translated_crops(70, 56, 72, t[0], t[1])
+    o = oracle.flow_fields(img1, img2, 3, 4, nthreads=2)
+    H, W = img1.shape
+    m = 7  # blur 1 + descriptor 3 + patch 3 pixels of support at n = 1
+    ys, xs = np.mgrid[0:H, 0:W]
+    inner = (xs >= m) & (xs < W - m) & (ys >= m) & (ys < H - m)
+    inner &= (xs + t[0] >= m) & (xs + t[0] < W - m) & (ys + t[1] >= m) & (ys + t[1] < H - m)
+    assert inner.sum() > 500
+    f = o["flow_fwd"]
+    assert np.all(f[inner][:, 0] == t[0]) and np.all(f[inner][:, 1] == t[1])
+    assert np.all(o["cost_fwd"][inner] == 0)
+
+
+def test_final_cost_recomputes_and_bounds_exhaustive_min():
+    ia, ib = random_images(80, 24, 32)
+    o = oracle.flow_fields(ia, ib, 2, 4, nthreads=2)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    H, W = ia.shape
+    for (y, x) in [(0, 0), (5, 9), (23, 31), (12, 16), (3, 28)]:
+        fx, fy = map(int, o["flow_fwd"][y, x])
+        c = int(o["cost_fwd"][y, x])
+        assert c == oracle.cost(Da, Db, 1, 3, x, y, fx, fy)
+        best = min(oracle.cost(Da, Db, 1, 3, x, y, qx - x, qy - y) for qy in range(H) for qx in range(W))
+        assert c >= best
+
+
+def test_thread_count_does_not_change_results():
+    p = make_pair(1)
+    a = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=1)
+    b = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=5)
+    for k in ("flow_fwd", "flow_bwd", "cost_fwd", "cost_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(a[k], b[k])
+    assert a["n_evals"] == b["n_evals"]
+
+
+def test_evaluation_count_bound():
+    """At most 2 evaluations per cell and propagation step and 1 per random
+    search step, plus one per seed: 4*2 + 3 = 11 per cell and scale at four
+    steps (the count quoted in Sec. 4.2 for the upsampling strategy)."""
+    p = make_pair(1)
+    L, T = 3, 4
+    o = oracle.flow_fields(p.img1, p.img2, L, T, nthreads=4)
+    H, W = p.img1.shape
+    bound = 0
+    for l in range(L):
+        n = 1 << l
+        cells = (-(-W // n)) * (-(-H // n))
+        bound += cells * (2 * T + T - 1) + cells  # + one seed evaluation per cell at most
+    assert max(o["n_evals"]) <= bound
+    assert min(o["n_evals"]) > 0
