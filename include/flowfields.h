@@ -1,0 +1,155 @@
+/*
+ * flowfields.h -- C ABI of the MI355X (gfx950) Flow Fields hot path.
+ *
+ * Method: Bailer, Taetz, Stricker, "Flow Fields: Dense Correspondence Fields
+ * for Highly Accurate Large Displacement Optical Flow Estimation" (journal
+ * version).  Two images in, a dense displacement field F(p) = M(p) - p out
+ * (Sec. 3, notation), for both directions, plus the forward-backward
+ * consistency masks (Sec. 3.7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Every pointer argument is a DEVICE pointer owned by the caller, unless
+ *    its comment says "host".  The library never allocates, frees or
+ *    synchronises; each call only enqueues kernels on `stream` (a
+ *    hipStream_t passed as void*, NULL = the default stream) and returns.
+ *  * Images: uint8 [H][W], row-major, pitch W.
+ *  * Descriptors: uint8 [H][W][16], row-major, 16 bytes per pixel.
+ *  * Level grid of scale n: ceil(W/n) x ceil(H/n) cells, row-major; cell
+ *    (i, j) is the full-resolution pixel (i*n, j*n).  Flows: int16 [cells][2]
+ *    = (dx, dy) in full-resolution pixels.  Costs: uint32 [cells]; the value
+ *    0xFFFFFFFF marks an UNSET cell, whose flow is (0, 0).
+ *  * n_evals: optional (may be NULL) device uint64 counter; every patch-cost
+ *    evaluation the call performs adds 1 to it (atomically).
+ *  * Argument errors (NULL required pointer, W or H outside [1, 32767],
+ *    levels outside [1, 7], iters outside [1, 64], radius outside [0, 7],
+ *    n not a power of two in [1, 64], too small a workspace) return
+ *    FF_ERR_ARG / FF_ERR_WORKSPACE before anything is enqueued.  A failed
+ *    launch returns FF_ERR_LAUNCH.  Faults inside kernels surface at the
+ *    caller's next synchronisation of `stream`.
+ *  * Calls are re-entrant; calls on different streams may overlap when they
+ *    write disjoint buffers.
+ */
+#ifndef FLOWFIELDS_H
+#define FLOWFIELDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FF_OK = 0,
+    FF_ERR_ARG = 1,
+    FF_ERR_LAUNCH = 2,
+    FF_ERR_WORKSPACE = 3,
+    FF_ERR_UNSUPPORTED = 4
+} ff_status;
+
+#define FF_UNSET_COST 0xFFFFFFFFu
+
+/* Schedule of one Flow Field computation (Sec. 3.1, 3.2; parameters Sec. 4.1). */
+typedef struct {
+    int32_t levels;  /* L: scales n = 2^(L-1), ..., 2, 1 (the paper's k = L-1) */
+    int32_t iters;   /* T: propagation steps per scale; T-1 random-search steps sit between them */
+    int32_t radius;  /* r: patch of (2r+1)^2 positions, subsampled by n (Eq. 3) */
+    int32_t R_num;   /* random-search distance R = R_num / R_den; at scale n the */
+    int32_t R_den;   /*   integer offset bound is R_n = floor(R_num * n / R_den) */
+    float eps;       /* consistency threshold: keep iff |F(p) + F_b(p + F(p))| < eps */
+    uint64_t seed;   /* key of the counter-based random-search generator */
+} ff_params;
+
+/* Library version (host). */
+int ff_version(void);
+
+/* Human-readable name of a status (host, static string). */
+const char *ff_status_str(ff_status s);
+
+/* Scale-space image I^n and per-pixel descriptors of scale n (Sec. 3.2 scale
+ * spaces, Sec. 3.6 low-pass and border condition).
+ * blurred[y][x] = round-half-up mean of img over the (2h+1)^2 window,
+ * h = max(1, n/2), replicate border; desc[y][x][4*gy+gx] =
+ * blurred[clamp(y + n*(2gy-3))][clamp(x + n*(2gx-3))], gx, gy in 0..3.
+ * img: [H][W]; blurred: [H][W] output; desc: [H][W][16] output;
+ * hsum: [H][W] uint16 scratch. */
+ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum,
+                         uint8_t *blurred, uint8_t *desc, void *stream);
+
+/* Initial flow of the coarsest scale nc (Sec. 3.1 initialisation, Eq. 1;
+ * Sec. 3.2 Eq. 4 with a single candidate): for every cell p of the grid of
+ * scale nc, the exact nearest neighbour q over ALL pixels of image b of the
+ * level-1 descriptor of p in image a under squared L2 distance (ties: the
+ * smallest q.y*W + q.x), computed on int8 matrix cores; then F(p) = q - p and
+ * cost(p) = E_nc(p, F(p)) with the scale-nc descriptors.
+ * desc_a1, desc_b1: level-1 descriptors [H][W][16]; desc_ac, desc_bc:
+ * scale-nc descriptors; nb_scratch: int32 [ceil(W*H/32)*32] scratch;
+ * nn_key: uint64 [cells] output, (squared distance << 32) | q;
+ * flow, cost: grid of scale nc, outputs. */
+ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac,
+                     const uint8_t *desc_bc, int32_t W, int32_t H, int32_t nc, int32_t radius,
+                     int32_t *nb_scratch, uint64_t *nn_key, int16_t *flow, uint32_t *cost,
+                     uint64_t *n_evals, void *stream);
+
+/* Coarse-to-fine hand-over from scale 2n to scale n (Sec. 3.2): cells with
+ * both grid indices even are the same pixel as a coarse cell and take its
+ * flow as a seed, with the cost re-evaluated at scale n; all other cells
+ * become UNSET.  coarse_flow/coarse_cost: grid of scale 2n (inputs);
+ * flow/cost: grid of scale n (outputs). */
+ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost, const uint8_t *desc_a,
+                        const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t radius,
+                        int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
+
+/* One propagation step (Sec. 3.1, Eq. 2) at scale n, direction
+ * d = pass mod 4 (0: from left and top; 1: from right and bottom; 2: from
+ * right and top; 3: from left and bottom).  Run as two checkerboard
+ * half-sweeps, cells with (i+j) odd first: each cell keeps the best of its
+ * own flow, its horizontal and then its vertical source cell's flow by
+ * E_n (strictly lower wins; sources that are UNSET, equal to the held flow or
+ * point outside the image are skipped).  flow/cost: grid of scale n, in/out. */
+ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                             int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
+                             void *stream);
+
+/* One random-search step (Sec. 3.1) at scale n: every set cell tries
+ * F + o with o uniform on [-Rn, Rn]^2 and keeps it if E_n is strictly
+ * lower; o = (0, 0) and targets outside the image are skipped.  o is drawn
+ * from h = mix(seed ^ mix(ctr)), mix = SplitMix64's output mixer (Steele,
+ * Lea, Flood 2014), ctr = stream_id<<56 | level<<48 | pass<<32 | j<<16 | i;
+ * ox = (lo32(h) * (2Rn+1)) >> 32) - Rn, oy likewise from hi32(h) (Lemire's
+ * multiply-shift).  flow/cost: grid of scale n, in/out. */
+ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                           int32_t radius, int32_t Rn, uint64_t seed, int32_t stream_id, int32_t level,
+                           int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
+
+/* Forward-backward consistency (Sec. 3.7): keep_a[p] = 1 iff p is set in
+ * field a, q = p + F_a(p) is set in field b and |F_a(p) + F_b(q)|^2 < eps^2
+ * (exact integer test).  Full-resolution fields [H][W][2] / [H][W].
+ * keep_b (nullable) receives the same test with the roles swapped. */
+ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                const uint32_t *cost_b, int32_t W, int32_t H, float eps, uint8_t *keep_a,
+                                uint8_t *keep_b, void *stream);
+
+/* Bytes of device workspace ff_flow_fields needs for a W x H pair (host). */
+size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);
+
+/* The whole hot path for one image pair (Sec. 3.2 multi-scale Flow Fields
+ * and Sec. 3.7 consistency): descriptors of both images at every scale, the
+ * forward field img1 -> img2 (random-search stream 0) and the backward field
+ * img2 -> img1 (stream 1), each from the exact NN seed through L scales of T
+ * propagation and T-1 random-search steps, then both consistency masks.
+ * params: host pointer.  ws: device workspace of ff_workspace_bytes bytes.
+ * flow_fwd/flow_bwd: [H][W][2]; cost_fwd/cost_bwd: [H][W];
+ * keep_fwd/keep_bwd: [H][W] (keep_bwd nullable);
+ * n_evals: nullable uint64 [2], evaluations per direction (overwritten). */
+ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, int32_t H,
+                         const ff_params *params, void *ws, size_t ws_bytes, int16_t *flow_fwd,
+                         int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd,
+                         uint8_t *keep_bwd, uint64_t *n_evals, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOWFIELDS_H */

@@ -1,0 +1,12 @@
+"""MI355X-native Flow Fields hot path (Bailer, Taetz, Stricker, "Flow Fields").
+
+The work runs in hand-written HIP kernels for gfx950 behind the C ABI of
+include/flowfields.h (``libflowfields.so``); this package is its thin
+Python binding.
+"""
+from .ffi import FlowFieldsError, lib  # noqa: F401
+from .flowfields import (FlowFields, Params, consistency_filter, descriptors, flow_fields,  # noqa: F401
+                         init_nn, propagate_level, random_search, rs_radius, seed_level, workspace_bytes)
+
+__all__ = ["FlowFieldsError", "lib", "FlowFields", "Params", "consistency_filter", "descriptors", "flow_fields",
+           "init_nn", "propagate_level", "random_search", "rs_radius", "seed_level", "workspace_bytes"]

@@ -1,0 +1,287 @@
+// C ABI of the Flow Fields hot path (declared in include/flowfields.h):
+// argument validation, workspace carving and the per-level schedule of
+// Sec. 3.2 (coarsest NN seed, then per scale: seeding, T propagation steps
+// with T-1 random-search steps in between), forward and backward fields
+// enqueued together, then the consistency check of Sec. 3.7.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/flowfields.h"
+#include "ff_internal.h"
+
+namespace {
+
+constexpr int kMaxLevels = 7;
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline bool is_pow2(int n) { return n >= 1 && n <= 64 && (n & (n - 1)) == 0; }
+inline bool dims_ok(int W, int H) { return W >= 1 && H >= 1 && W <= 32767 && H <= 32767; }
+
+ff_status from_hip(hipError_t e) { return e == hipSuccess ? FF_OK : FF_ERR_LAUNCH; }
+
+bool params_ok(const ff_params *p) {
+  return p && p->levels >= 1 && p->levels <= kMaxLevels && p->iters >= 1 && p->iters <= 64 && p->radius >= 0 &&
+         p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20;
+}
+
+int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
+
+// Device workspace of ff_flow_fields, carved in this order.
+struct Layout {
+  size_t hsum, blur, desc, nb, keys, grids, evals, total;
+  size_t N, Npad, M;
+  int L;
+};
+
+Layout layout(int W, int H, const ff_params *p) {
+  Layout l{};
+  l.L = p->levels;
+  l.N = (size_t)W * H;
+  l.Npad = (l.N + 31) & ~(size_t)31;
+  const int nc = 1 << (p->levels - 1);
+  l.M = (size_t)ceil_div(W, nc) * ceil_div(H, nc);
+  size_t off = 0;
+  l.hsum = off; off = align256(off + 2 * l.L * l.N * sizeof(uint16_t));
+  l.blur = off; off = align256(off + 2 * l.L * l.N);
+  l.desc = off; off = align256(off + 2 * l.L * l.N * 16);
+  l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
+  l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
+  l.grids = off;
+  for (int lv = 1; lv < l.L; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
+  l.evals = off; off = align256(off + 2 * sizeof(uint64_t));
+  l.total = off;
+  return l;
+}
+
+ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int radius, int16_t *flow,
+                            uint32_t *cost, uint64_t *n_evals) {
+  ffh::LevelArgs a{};
+  a.ndir = 1;
+  a.W = W;
+  a.H = H;
+  a.n = n;
+  a.Wn = ceil_div(W, n);
+  a.Hn = ceil_div(H, n);
+  a.radius = radius;
+  a.dir[0].Da = Da;
+  a.dir[0].Db = Db;
+  a.dir[0].flow = reinterpret_cast<int32_t *>(flow);
+  a.dir[0].cost = cost;
+  a.dir[0].n_evals = reinterpret_cast<unsigned long long *>(n_evals);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ff_version(void) { return 1; }
+
+const char *ff_status_str(ff_status s) {
+  switch (s) {
+    case FF_OK: return "ok";
+    case FF_ERR_ARG: return "invalid argument";
+    case FF_ERR_LAUNCH: return "kernel launch failed";
+    case FF_ERR_WORKSPACE: return "workspace too small";
+    case FF_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum, uint8_t *blurred,
+                         uint8_t *desc, void *stream) {
+  if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || !is_pow2(n)) return FF_ERR_ARG;
+  ffh::DescJobs jobs{};
+  jobs.W = W;
+  jobs.H = H;
+  jobs.count = 1;
+  jobs.job[0] = {img, hsum, blurred, desc, n};
+  return from_hip(ffh::launch_descriptors(jobs, (hipStream_t)stream));
+}
+
+ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac, const uint8_t *desc_bc,
+                     int32_t W, int32_t H, int32_t nc, int32_t radius, int32_t *nb_scratch, uint64_t *nn_key,
+                     int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream) {
+  if (!desc_a1 || !desc_b1 || !desc_ac || !desc_bc || !nb_scratch || !nn_key || !flow || !cost || !dims_ok(W, H) ||
+      !is_pow2(nc) || radius < 0 || radius > 7)
+    return FF_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  ffh::NNArgs nn{};
+  nn.ndir = 1;
+  nn.W = W;
+  nn.H = H;
+  nn.nc = nc;
+  nn.Wc = ceil_div(W, nc);
+  nn.M = nn.Wc * ceil_div(H, nc);
+  nn.N = W * H;
+  nn.dir[0] = {desc_a1, desc_b1, nb_scratch, nn_key};
+  hipError_t e = ffh::launch_nn(nn, s);
+  if (e != hipSuccess) return FF_ERR_LAUNCH;
+  ffh::LevelArgs a = one_dir_args(desc_ac, desc_bc, W, H, nc, radius, flow, cost, n_evals);
+  a.dir[0].nn_key = nn_key;
+  a.dir[0].Dq1 = desc_a1;
+  return from_hip(ffh::launch_init_coarse(a, s));
+}
+
+ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost, const uint8_t *desc_a,
+                        const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t radius, int16_t *flow,
+                        uint32_t *cost, uint64_t *n_evals, void *stream) {
+  if (!coarse_flow || !coarse_cost || !desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !is_pow2(n) ||
+      n > 32 || radius < 0 || radius > 7)
+    return FF_ERR_ARG;
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, flow, cost, n_evals);
+  a.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
+  a.dir[0].ccost = coarse_cost;
+  return from_hip(ffh::launch_seed_level(a, (hipStream_t)stream));
+}
+
+ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                             int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
+                             void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !is_pow2(n) || radius < 0 || radius > 7 ||
+      pass < 0 || pass > 0xFFFF)
+    return FF_ERR_ARG;
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, flow, cost, n_evals);
+  a.pass = pass;
+  return from_hip(ffh::launch_propagate(a, (hipStream_t)stream));
+}
+
+ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                           int32_t radius, int32_t Rn, uint64_t seed, int32_t stream_id, int32_t level, int32_t pass,
+                           int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !is_pow2(n) || radius < 0 || radius > 7 ||
+      Rn < 0 || Rn > 32767 || pass < 0 || pass > 0xFFFF || level < 0 || level > 0xFF || stream_id < 0 ||
+      stream_id > 0xFF)
+    return FF_ERR_ARG;
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, flow, cost, n_evals);
+  a.Rn = Rn;
+  a.seed = seed;
+  a.level = level;
+  a.pass = pass;
+  a.dir[0].stream_id = stream_id;
+  return from_hip(ffh::launch_random_search(a, (hipStream_t)stream));
+}
+
+ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                const uint32_t *cost_b, int32_t W, int32_t H, float eps, uint8_t *keep_a,
+                                uint8_t *keep_b, void *stream) {
+  if (!flow_a || !cost_a || !flow_b || !cost_b || !keep_a || !dims_ok(W, H) || !(eps >= 0.0f)) return FF_ERR_ARG;
+  return from_hip(ffh::launch_consistency(flow_a, cost_a, flow_b, cost_b, W, H, eps, keep_a, keep_b,
+                                          (hipStream_t)stream));
+}
+
+size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params) {
+  if (!dims_ok(W, H) || !params_ok(params)) return 0;
+  return layout(W, H, params).total;
+}
+
+ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, int32_t H, const ff_params *params,
+                         void *ws, size_t ws_bytes, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd,
+                         uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals, void *stream) {
+  if (!img1 || !img2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !dims_ok(W, H) ||
+      !params_ok(params) || !(params->eps >= 0.0f))
+    return FF_ERR_ARG;
+  const Layout lay = layout(W, H, params);
+  if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int L = params->levels, T = params->iters, r = params->radius;
+  char *base = static_cast<char *>(ws);
+  const uint8_t *img[2] = {img1, img2};
+
+  // descriptors of both images at every scale
+  uint8_t *desc[2][kMaxLevels];
+  ffh::DescJobs jobs{};
+  jobs.W = W;
+  jobs.H = H;
+  jobs.count = 2 * L;
+  for (int im = 0; im < 2; ++im)
+    for (int lv = 0; lv < L; ++lv) {
+      const int z = im * L + lv;
+      desc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.desc) + (size_t)z * lay.N * 16;
+      jobs.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
+                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, desc[im][lv], 1 << lv};
+    }
+  hipError_t e = ffh::launch_descriptors(jobs, s);
+  if (e != hipSuccess) return FF_ERR_LAUNCH;
+
+  uint64_t *evals = n_evals ? n_evals : reinterpret_cast<uint64_t *>(base + lay.evals);
+  if ((e = ffh::launch_fill_u64(evals, 0, 2, s)) != hipSuccess) return FF_ERR_LAUNCH;
+
+  // level grids: scale 1 lives in the caller's outputs
+  int32_t *gflow[kMaxLevels][2];
+  uint32_t *gcost[kMaxLevels][2];
+  gflow[0][0] = reinterpret_cast<int32_t *>(flow_fwd);
+  gflow[0][1] = reinterpret_cast<int32_t *>(flow_bwd);
+  gcost[0][0] = cost_fwd;
+  gcost[0][1] = cost_bwd;
+  size_t off = lay.grids;
+  for (int lv = 1; lv < L; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    for (int dr = 0; dr < 2; ++dr) {
+      gflow[lv][dr] = reinterpret_cast<int32_t *>(base + off) + (size_t)dr * 2 * cells;
+      gcost[lv][dr] = reinterpret_cast<uint32_t *>(gflow[lv][dr] + cells);
+    }
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
+
+  // exact NN seeds of the coarsest grid, both directions
+  const int nc = 1 << (L - 1);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(base + lay.keys);
+  int32_t *nb = reinterpret_cast<int32_t *>(base + lay.nb);
+  ffh::NNArgs nn{};
+  nn.ndir = 2;
+  nn.W = W;
+  nn.H = H;
+  nn.nc = nc;
+  nn.Wc = ceil_div(W, nc);
+  nn.M = (int)lay.M;
+  nn.N = (int)lay.N;
+  for (int dr = 0; dr < 2; ++dr)
+    nn.dir[dr] = {desc[dr][0], desc[dr ^ 1][0], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
+  if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+
+  ffh::LevelArgs a{};
+  a.ndir = 2;
+  a.W = W;
+  a.H = H;
+  a.radius = r;
+  a.seed = params->seed;
+  for (int dr = 0; dr < 2; ++dr) {
+    a.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
+    a.dir[dr].stream_id = dr;
+  }
+  for (int lv = L - 1; lv >= 0; --lv) {
+    const int n = 1 << lv;
+    a.n = n;
+    a.Wn = ceil_div(W, n);
+    a.Hn = ceil_div(H, n);
+    a.level = lv;
+    a.Rn = rs_radius(n, params->R_num, params->R_den);
+    for (int dr = 0; dr < 2; ++dr) {
+      a.dir[dr].Da = desc[dr][lv];
+      a.dir[dr].Db = desc[dr ^ 1][lv];
+      a.dir[dr].flow = gflow[lv][dr];
+      a.dir[dr].cost = gcost[lv][dr];
+      a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+      a.dir[dr].Dq1 = desc[dr][0];
+      a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+      a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+    }
+    e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
+    if (e != hipSuccess) return FF_ERR_LAUNCH;
+    for (int t = 0; t < T; ++t) {
+      a.pass = t;
+      if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if (t < T - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    }
+  }
+  return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
+                                          keep_bwd, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Scale-space low-pass and per-pixel descriptors (Sec. 3.2 scale spaces,
+// Sec. 3.6 low-pass filtering and replicate border condition).
+//
+// I^n: integer box filter of half-width h = max(1, n/2), rounded half up,
+// computed separably (row sums, then column sums of the row sums; both are
+// exact in integers).  Descriptor of scale n: the 16 samples of I^n on a 4x4
+// grid with spacing 2n around the pixel, stored as one 16-byte vector per
+// pixel so that a patch position costs one 128-bit load.
+//
+// All (image, scale) jobs of a call run in one launch per stage: blockIdx.z
+// selects the job.
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+using ffk::clampi;
+
+__global__ __launch_bounds__(256) void k_hsum(ffh::DescJobs jobs) {
+  const ffh::DescJob &jb = jobs.job[blockIdx.z];
+  const int W = jobs.W, H = jobs.H;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int h = max(1, jb.n >> 1);
+  const uint8_t *row = jb.img + (size_t)y * W;
+  uint32_t s = 0;
+  for (int dx = -h; dx <= h; ++dx) s += row[clampi(x + dx, W - 1)];
+  jb.hsum[(size_t)y * W + x] = (uint16_t)s;
+}
+
+__global__ __launch_bounds__(256) void k_vsum(ffh::DescJobs jobs) {
+  const ffh::DescJob &jb = jobs.job[blockIdx.z];
+  const int W = jobs.W, H = jobs.H;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int h = max(1, jb.n >> 1);
+  const uint32_t area = (uint32_t)((2 * h + 1) * (2 * h + 1));
+  uint32_t s = 0;
+  for (int dy = -h; dy <= h; ++dy) s += jb.hsum[(size_t)clampi(y + dy, H - 1) * W + x];
+  jb.blurred[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
+}
+
+__global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
+  const ffh::DescJob &jb = jobs.job[blockIdx.z];
+  const int W = jobs.W, H = jobs.H;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int n = jb.n;
+  uint32_t w[4];
+#pragma unroll
+  for (int gy = 0; gy < 4; ++gy) {
+    const uint8_t *row = jb.blurred + (size_t)clampi(y + n * (2 * gy - 3), H - 1) * W;
+    uint32_t v = 0;
+#pragma unroll
+    for (int gx = 0; gx < 4; ++gx) v |= (uint32_t)row[clampi(x + n * (2 * gx - 3), W - 1)] << (8 * gx);
+    w[gy] = v;
+  }
+  reinterpret_cast<uint4 *>(jb.desc)[(size_t)y * W + x] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+}  // namespace
+
+namespace ffh {
+
+hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
+  if (jobs.count <= 0) return hipSuccess;
+  dim3 grid((jobs.W + 255) / 256, jobs.H, jobs.count);
+  hipLaunchKernelGGL(k_hsum, grid, dim3(256), 0, stream, jobs);
+  hipLaunchKernelGGL(k_vsum, grid, dim3(256), 0, stream, jobs);
+  hipLaunchKernelGGL(k_desc, grid, dim3(256), 0, stream, jobs);
+  return hipGetLastError();
+}
+
+}  // namespace ffh

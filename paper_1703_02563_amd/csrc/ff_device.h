@@ -1,0 +1,106 @@
+// Device-side helpers of the Flow Fields kernels (gfx950).
+//
+// Patch cost E_n of Eq. 3 on 16-byte descriptors: each patch position adds
+// the byte-wise SAD of two descriptors, four bytes per v_sad_u8.  Reads
+// outside the image take the nearest inside pixel (Sec. 3.6 border
+// condition).  The counter-based generator of the random search is
+// SplitMix64's output mixer (Steele, Lea, Flood 2014) applied as
+// mix(seed ^ mix(counter)), mapped to [0, 2R] by Lemire's multiply-shift.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffk {
+
+constexpr uint32_t kUnset = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int clampi(int v, int hi) { return min(max(v, 0), hi); }
+
+__device__ __forceinline__ uint32_t sad16(const uint4 a, const uint4 b, uint32_t acc) {
+  acc = __builtin_amdgcn_sad_u8(a.x, b.x, acc);
+  acc = __builtin_amdgcn_sad_u8(a.y, b.y, acc);
+  acc = __builtin_amdgcn_sad_u8(a.z, b.z, acc);
+  acc = __builtin_amdgcn_sad_u8(a.w, b.w, acc);
+  return acc;
+}
+
+__device__ __forceinline__ int flow_x(int32_t f) { return (int)(int16_t)(f & 0xFFFF); }
+__device__ __forceinline__ int flow_y(int32_t f) { return f >> 16; }
+__device__ __forceinline__ int32_t pack_flow(int fx, int fy) {
+  return (int32_t)(((uint32_t)fy << 16) | ((uint32_t)fx & 0xFFFFu));
+}
+
+// E_n(p, f) for one candidate flow.
+template <int R>
+__device__ __forceinline__ uint32_t patch_cost(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db,
+                                               int W, int H, int n, int x, int y, int fx, int fy) {
+  const int Wm = W - 1, Hm = H - 1;
+  uint32_t s = 0;
+#pragma unroll 1
+  for (int v = -R; v <= R; ++v) {
+    const uint4 *ra = Da + (size_t)clampi(y + n * v, Hm) * W;
+    const uint4 *rb = Db + (size_t)clampi(y + fy + n * v, Hm) * W;
+#pragma unroll
+    for (int u = -R; u <= R; ++u) {
+      const uint4 a = ra[clampi(x + n * u, Wm)];
+      const uint4 b = rb[clampi(x + fx + n * u, Wm)];
+      s = sad16(a, b, s);
+    }
+  }
+  return s;
+}
+
+// E_n(p, f1) and E_n(p, f2) sharing the reads of image a; a disabled
+// candidate is neither read nor summed.
+template <int R>
+__device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db, int W,
+                                            int H, int n, int x, int y, int f1x, int f1y, bool en1, int f2x,
+                                            int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
+  const int Wm = W - 1, Hm = H - 1;
+  uint32_t s1 = 0, s2 = 0;
+#pragma unroll 1
+  for (int v = -R; v <= R; ++v) {
+    const uint4 *ra = Da + (size_t)clampi(y + n * v, Hm) * W;
+    const uint4 *rb1 = Db + (size_t)clampi(y + f1y + n * v, Hm) * W;
+    const uint4 *rb2 = Db + (size_t)clampi(y + f2y + n * v, Hm) * W;
+#pragma unroll
+    for (int u = -R; u <= R; ++u) {
+      const uint4 a = ra[clampi(x + n * u, Wm)];
+      if (en1) s1 = sad16(a, rb1[clampi(x + f1x + n * u, Wm)], s1);
+      if (en2) s2 = sad16(a, rb2[clampi(x + f2x + n * u, Wm)], s2);
+    }
+  }
+  c1 = s1;
+  c2 = s2;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Random-search offset of cell (i, j): uniform on [-Rn, Rn]^2.
+__device__ __forceinline__ void rs_offset(uint64_t seed, int stream_id, int level, int pass, int j, int i,
+                                          int Rn, int &ox, int &oy) {
+  const uint64_t ctr = ((uint64_t)(stream_id & 0xFF) << 56) | ((uint64_t)(level & 0xFF) << 48) |
+                       ((uint64_t)(pass & 0xFFFF) << 32) | ((uint64_t)(j & 0xFFFF) << 16) |
+                       (uint64_t)(i & 0xFFFF);
+  const uint64_t h = mix64(seed ^ mix64(ctr));
+  const uint32_t span = (uint32_t)(2 * Rn + 1);
+  ox = (int)__umulhi((uint32_t)h, span) - Rn;
+  oy = (int)__umulhi((uint32_t)(h >> 32), span) - Rn;
+}
+
+// Adds a per-lane count (0, 1 or 2) of the whole wave to a global counter
+// with one atomic per wave.
+__device__ __forceinline__ void wave_count_add(unsigned long long *counter, int cnt) {
+  if (counter == nullptr) return;
+  const unsigned long long b1 = __ballot(cnt >= 1);
+  const unsigned long long b2 = __ballot(cnt >= 2);
+  const int total = __popcll(b1) + __popcll(b2);
+  if ((threadIdx.x & 63) == 0 && total) atomicAdd(counter, (unsigned long long)total);
+}
+
+}  // namespace ffk

@@ -1,0 +1,75 @@
+// Host-side interface between the C ABI (ff_api.hip) and the kernel
+// translation units.  Every launcher enqueues on `stream` and returns the
+// launch status; none allocates or synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffh {
+
+constexpr int kMaxJobs = 16;   // descriptor jobs per launch: 2 images x 7 levels (+ slack)
+constexpr int kMaxDirs = 2;    // forward and backward field in one launch
+
+// One scale-space descriptor job: image -> blurred -> descriptors at scale n.
+struct DescJob {
+  const uint8_t *img;
+  uint16_t *hsum;
+  uint8_t *blurred;
+  uint8_t *desc;
+  int n;
+};
+struct DescJobs {
+  DescJob job[kMaxJobs];
+  int count;
+  int W, H;
+};
+hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream);
+
+// Fills `count` 64-bit words with `value`.
+hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t count, hipStream_t stream);
+
+// Brute-force NN of the coarsest grid on int8 matrix cores.
+struct NNDir {
+  const uint8_t *Dq;   // level-1 descriptors of the image holding the query cells
+  const uint8_t *Dr;   // level-1 descriptors of the reference image
+  int32_t *nb;         // per-reference squared norm of (d - 128), padded to a multiple of 32
+  uint64_t *keys;      // per-query packed result (see ff_nn.hip)
+};
+struct NNArgs {
+  NNDir dir[kMaxDirs];
+  int ndir;
+  int W, H, nc, Wc, M, N;
+};
+hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
+
+// Per-direction state of a level grid.
+struct LevelDir {
+  const uint8_t *Da;   // scale-n descriptors of the source image
+  const uint8_t *Db;   // scale-n descriptors of the target image
+  int32_t *flow;       // packed (dx, dy) int16 pairs, [cells]
+  uint32_t *cost;      // [cells]
+  const int32_t *cflow;   // coarser grid (seeding only)
+  const uint32_t *ccost;
+  const uint64_t *nn_key; // coarsest init only
+  const uint8_t *Dq1;     // level-1 descriptors of the source image (coarsest init only)
+  unsigned long long *n_evals;
+  int stream_id;
+};
+struct LevelArgs {
+  LevelDir dir[kMaxDirs];
+  int ndir;
+  int W, H, n, Wn, Hn, radius;
+  int Rn, level, pass;
+  uint64_t seed;
+};
+hipError_t launch_init_coarse(const LevelArgs &a, hipStream_t stream);
+hipError_t launch_seed_level(const LevelArgs &a, hipStream_t stream);
+hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream);  // both half-sweeps
+hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
+
+// Consistency of field a against field b (full resolution).
+hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
+                              int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream);
+
+}  // namespace ffh

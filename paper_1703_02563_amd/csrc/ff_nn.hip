@@ -1,0 +1,172 @@
+// Exact brute-force nearest neighbour of the coarsest-grid cells (stands in
+// for the kd-tree candidate search of Sec. 3.1 with one candidate; the
+// initial flow of Eq. 1 / Eq. 4 is F = q - p).
+//
+// ||a - b||^2 = |a|^2 + |b|^2 - 2 a.b is a dense contraction over the 16
+// descriptor bytes.  Bytes v are shifted to int8 (v - 128, a plain xor with
+// 0x80), which leaves the distance unchanged, and the dot products of 32
+// queries x 32 references run on v_mfma_i32_32x32x16_i8 (exact in int32).
+//
+// Argmin with ties to the smallest reference index, without a compare and
+// select per pair: per (query, reference) the lane forms the score
+//     s = 4096 * dot - (2048 * |b|^2 + t) = -(2048 * (|b|^2 - 2 dot) + t)
+// with t the tile index inside the current chunk (t < 2048), one
+// v_lshl_add per pair, and keeps max(s) with v_max3 over two tiles.  Since
+// |b|^2 - 2 dot = dist - |a|^2 lies in [-2^18, 2^20), s never overflows and
+// max(s) is the smallest distance, then the smallest tile.  Within a lane
+// the reference column is fixed, so (distance, tile) orders references by
+// index.  At the end of the chunk each lane decodes its best, the 32 lanes
+// holding the same queries reduce (distance, index) as one 64-bit key, and
+// one atomicMin per query merges chunks and waves.
+//
+// Key written to global memory: ((dist - |a|^2 + 2^20) << 32) | index; the
+// init kernel adds |a|^2 back.  Padding references (index >= N) carry
+// |b|^2 = 2^20 - 1 and zero bytes, so their score is below every real one.
+#include <climits>
+
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kTilesPerChunk = 1024;  // <= 2048: the tile index must fit 11 bits
+constexpr int kQB = 2;                // 32-query blocks per wave (B operand reuse)
+constexpr int kWaves = 4;
+constexpr int kNbPad = (1 << 20) - 1;
+
+__global__ __launch_bounds__(256) void k_nn_norms(ffh::NNArgs a) {
+  const ffh::NNDir d = a.dir[blockIdx.y];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Npad = (a.N + 31) & ~31;
+  if (idx >= Npad) return;
+  int s = kNbPad;
+  if (idx < a.N) {
+    const uint4 v = reinterpret_cast<const uint4 *>(d.Dr)[idx];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int e = (int)((w[k] >> (8 * b)) & 0xFF) - 128;
+        s += e * e;
+      }
+  }
+  d.nb[idx] = s;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t *dst, uint64_t value, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = value;
+}
+
+// Negation the compiler cannot see through: with an opaque addend,
+// (acc << 12) + nk stays one v_lshl_add_u32 instead of a shift and a
+// subtract.  Only the addend goes through asm; the matrix-core results are
+// read by ordinary instructions, so the compiler keeps its MFMA
+// read-after-write wait states.
+__device__ __forceinline__ int opaque_neg(int v) {
+  int r;
+  asm("v_sub_u32 %0, 0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
+__device__ __forceinline__ long load_i8x8(const uint8_t *p) {
+  // 8 descriptor bytes -> 8 int8 (v - 128)
+  return (long)(*reinterpret_cast<const unsigned long long *>(p) ^ 0x8080808080808080ull);
+}
+
+__global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
+  const ffh::NNDir d = a.dir[blockIdx.z];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, kh = lane >> 5;
+  const int M = a.M, N = a.N, W = a.W;
+  const int m0 = blockIdx.x * (32 * kQB);
+  const int ntiles = (N + 31) >> 5;
+  const int t0 = blockIdx.y * kTilesPerChunk;
+  const int t1 = min(t0 + kTilesPerChunk, ntiles);
+  if (t0 + wave >= t1) return;  // wave-uniform: no tile for this wave
+
+  long aop[kQB];
+#pragma unroll
+  for (int qb = 0; qb < kQB; ++qb) {
+    const int m = min(m0 + qb * 32 + col, M - 1);
+    const int i = m % a.Wc, j = m / a.Wc;
+    const size_t pix = (size_t)(j * a.nc) * W + (size_t)(i * a.nc);
+    aop[qb] = load_i8x8(d.Dq + pix * 16 + kh * 8);
+  }
+
+  int best[kQB][16];
+#pragma unroll
+  for (int qb = 0; qb < kQB; ++qb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) best[qb][r] = INT_MIN;
+
+  const v16i zero = {0};
+  for (int t = t0 + wave; t < t1; t += 2 * kWaves) {
+    // two tiles per step (the second repeats the first at the odd tail)
+    const int tb = (t + kWaves < t1) ? t + kWaves : t;
+    const int ra = t * 32 + col, rb = tb * 32 + col;
+    const long ba = ra < N ? load_i8x8(d.Dr + (size_t)ra * 16 + kh * 8) : 0;
+    const long bb = rb < N ? load_i8x8(d.Dr + (size_t)rb * 16 + kh * 8) : 0;
+    const int nka = opaque_neg((d.nb[ra] << 11) | (t - t0));
+    const int nkb = opaque_neg((d.nb[rb] << 11) | (tb - t0));
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb) {
+      const v16i acc_a = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], ba, zero, 0, 0, 0);
+      const v16i acc_b = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], bb, zero, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int sa = acc_a[r] * 4096 + nka;
+        const int sb = acc_b[r] * 4096 + nkb;
+        best[qb][r] = max(best[qb][r], max(sa, sb));
+      }
+    }
+  }
+
+#pragma unroll
+  for (int qb = 0; qb < kQB; ++qb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int key = -best[qb][r];
+      const int dd = key >> 11;        // dist - |a|^2
+      const int tl = key & 2047;       // tile inside the chunk
+      const uint32_t ref = (uint32_t)((t0 + tl) * 32 + col);
+      unsigned long long v = ((unsigned long long)(uint32_t)(dd + (1 << 20)) << 32) | ref;
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+      }
+      const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+      const int m = m0 + qb * 32 + row;
+      if (col == 0 && m < M) atomicMin(reinterpret_cast<unsigned long long *>(d.keys) + m, v);
+    }
+}
+
+}  // namespace
+
+namespace ffh {
+
+hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, dst, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_nn(const NNArgs &args, hipStream_t stream) {
+  const int Npad = (args.N + 31) & ~31;
+  hipLaunchKernelGGL(k_nn_norms, dim3((Npad + 255) / 256, args.ndir), dim3(256), 0, stream, args);
+  for (int k = 0; k < args.ndir; ++k) {
+    hipError_t e = launch_fill_u64(args.dir[k].keys, ~0ull, args.M, stream);
+    if (e != hipSuccess) return e;
+  }
+  const int ntiles = Npad / 32;
+  dim3 grid((args.M + 32 * kQB - 1) / (32 * kQB), (ntiles + kTilesPerChunk - 1) / kTilesPerChunk, args.ndir);
+  hipLaunchKernelGGL(k_nn, grid, dim3(64 * kWaves), 0, stream, args);
+  return hipGetLastError();
+}
+
+}  // namespace ffh

@@ -1,0 +1,280 @@
+// Level-grid kernels of the Flow Fields schedule (Sec. 3.1, 3.2, 3.7).
+//
+//  * k_init_coarse: initial flow F = q - p of the coarsest grid from the NN
+//    keys, cost E_nc (Eq. 1 / Eq. 4 with one candidate).
+//  * k_seed_level:  coarse-to-fine hand-over: cells with even (i, j) are the
+//    coarse cell's pixel and keep its flow (cost re-evaluated at scale n);
+//    the rest start UNSET (Sec. 3.2).
+//  * k_prop_half:   one checkerboard half-sweep of a propagation step
+//    (Eq. 2): cells of one colour read only cells of the other colour, so
+//    every cell of the colour updates in parallel.  Candidate order own,
+//    horizontal source, vertical source; strictly lower cost wins.
+//  * k_random_search: one random-search step (Sec. 3.1) with integer
+//    offsets from the counter-based generator.
+//  * k_consistency: forward-backward check (Sec. 3.7).
+//
+// One lane per cell; both directions of a pair run in one launch
+// (blockIdx.z).  Each kernel counts the patch-cost evaluations it performs
+// with one atomic per wave.
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+using ffk::clampi;
+using ffk::kUnset;
+
+template <int R>
+__global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cells = a.Wn * a.Hn;
+  int cnt = 0;
+  if (m < cells) {
+    const int i = m % a.Wn, j = m / a.Wn;
+    const int x = i * a.n, y = j * a.n;
+    const uint64_t key = d.nn_key[m];
+    const uint32_t q = (uint32_t)key;
+    const int dd = (int)(uint32_t)(key >> 32) - (1 << 20);
+    const uint4 qa = reinterpret_cast<const uint4 *>(d.Dq1)[(size_t)y * a.W + x];
+    const uint32_t w[4] = {qa.x, qa.y, qa.z, qa.w};
+    int na = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int e = (int)((w[k] >> (8 * b)) & 0xFF) - 128;
+        na += e * e;
+      }
+    const_cast<uint64_t *>(d.nn_key)[m] = ((uint64_t)(uint32_t)(dd + na) << 32) | q;
+    const int fx = (int)(q % (uint32_t)a.W) - x, fy = (int)(q / (uint32_t)a.W) - y;
+    d.flow[m] = ffk::pack_flow(fx, fy);
+    d.cost[m] = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db),
+                                   a.W, a.H, a.n, x, y, fx, fy);
+    cnt = 1;
+  }
+  ffk::wave_count_add(d.n_evals, cnt);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = 0;
+  if (m < a.Wn * a.Hn) {
+    const int i = m % a.Wn, j = m / a.Wn;
+    int32_t f = 0;
+    uint32_t c = kUnset;
+    if (!((i | j) & 1)) {
+      const int Wc = (a.Wn + 1) >> 1;
+      const int kc = (j >> 1) * Wc + (i >> 1);
+      if (d.ccost[kc] != kUnset) {
+        f = d.cflow[kc];
+        c = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db),
+                               a.W, a.H, a.n, i * a.n, j * a.n, ffk::flow_x(f), ffk::flow_y(f));
+        cnt = 1;
+      }
+    }
+    d.flow[m] = f;
+    d.cost[m] = c;
+  }
+  ffk::wave_count_add(d.n_evals, cnt);
+}
+
+// Half-sweep of colour `colour` ((i + j) & 1 == colour) of propagation step
+// `a.pass`.  Grid: x over half-columns, y over rows, z over directions.
+template <int R>
+__global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int kx = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int i = 2 * kx + ((colour + j) & 1);
+  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n;
+  int cnt = 0;
+  if (i < Wn && j < Hn) {
+    const int dir = a.pass & 3;
+    const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
+    const int vdj = (dir == 0 || dir == 2) ? -1 : 1;
+    const int k = j * Wn + i;
+    const int x = i * n, y = j * n;
+    const uint32_t c0 = d.cost[k];
+    const int32_t f0 = d.flow[k];
+    const bool set0 = c0 != kUnset;
+    // horizontal source
+    const int hi = i + hdi;
+    bool hv = false;
+    int32_t fh = 0;
+    if (hi >= 0 && hi < Wn) {
+      const int ks = j * Wn + hi;
+      if (d.cost[ks] != kUnset) {
+        fh = d.flow[ks];
+        const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
+        hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+      }
+    }
+    // vertical source: validity except the "held flow" rule, which depends
+    // on the horizontal outcome
+    const int vj = j + vdj;
+    bool vb = false;
+    int32_t fv = 0;
+    if (vj >= 0 && vj < Hn) {
+      const int ks = vj * Wn + i;
+      if (d.cost[ks] != kUnset) {
+        fv = d.flow[ks];
+        const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
+        vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
+      }
+    }
+    // E(p, fv) need not be computed in the shared pass when fv equals fh
+    // (same evaluation) or the held flow f0 (then it is only evaluated if
+    // the horizontal source replaced f0, which is rare)
+    const bool vcomp = vb && !(hv && fv == fh) && !(set0 && fv == f0);
+    uint32_t eh = 0, ev = 0;
+    if (hv || vcomp)
+      ffk::patch_cost2<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db), W, H, n,
+                          x, y, ffk::flow_x(fh), ffk::flow_y(fh), hv, ffk::flow_x(fv), ffk::flow_y(fv), vcomp,
+                          eh, ev);
+    uint32_t bc = c0;
+    int32_t bf = f0;
+    if (hv) {
+      cnt = 1;
+      if (eh < bc) { bc = eh; bf = fh; }
+    }
+    if (vb && (bc == kUnset || fv != bf)) {
+      cnt += 1;
+      uint32_t e;
+      if (hv && fv == fh)
+        e = eh;
+      else if (vcomp)
+        e = ev;
+      else  // fv == f0 after the horizontal source replaced it; the stored
+            // cost of a caller-made state need not equal E(p, f0)
+        e = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db), W, H,
+                               n, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
+      if (e < bc) { bc = e; bf = fv; }
+    }
+    if (bc != c0 || bf != f0) {
+      d.cost[k] = bc;
+      d.flow[k] = bf;
+    }
+  }
+  ffk::wave_count_add(d.n_evals, cnt);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  int cnt = 0;
+  if (i < a.Wn && j < a.Hn) {
+    const int k = j * a.Wn + i;
+    const uint32_t c0 = d.cost[k];
+    if (c0 != kUnset) {
+      int ox, oy;
+      ffk::rs_offset(a.seed, d.stream_id, a.level, a.pass, j, i, a.Rn, ox, oy);
+      const int32_t f0 = d.flow[k];
+      const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
+      const int x = i * a.n, y = j * a.n;
+      if ((ox | oy) != 0 && x + fx >= 0 && x + fx < a.W && y + fy >= 0 && y + fy < a.H) {
+        const uint32_t e = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da),
+                                              reinterpret_cast<const uint4 *>(d.Db), a.W, a.H, a.n, x, y, fx, fy);
+        cnt = 1;
+        if (e < c0) {
+          d.cost[k] = e;
+          d.flow[k] = ffk::pack_flow(fx, fy);
+        }
+      }
+    }
+  }
+  ffk::wave_count_add(d.n_evals, cnt);
+}
+
+__global__ __launch_bounds__(256) void k_consistency(const int32_t *fa, const uint32_t *ca, const int32_t *fb,
+                                                     const uint32_t *cb, int W, int H, double eps2,
+                                                     uint8_t *keep) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const size_t k = (size_t)y * W + x;
+  uint8_t out = 0;
+  if (ca[k] != kUnset) {
+    const int32_t f = fa[k];
+    const int qx = x + ffk::flow_x(f), qy = y + ffk::flow_y(f);
+    const size_t kq = (size_t)qy * W + qx;
+    // fields made by the method never point outside; caller-made ones may
+    if (qx >= 0 && qx < W && qy >= 0 && qy < H && cb[kq] != kUnset) {
+      const int32_t g = fb[kq];
+      const int64_t dx = ffk::flow_x(f) + ffk::flow_x(g), dy = ffk::flow_y(f) + ffk::flow_y(g);
+      out = (double)(dx * dx + dy * dy) < eps2;
+    }
+  }
+  keep[k] = out;
+}
+
+#define FF_RADIUS_SWITCH(R_, CALL)                                              \
+  switch (R_) {                                                                 \
+    case 0: CALL(0); break;                                                     \
+    case 1: CALL(1); break;                                                     \
+    case 2: CALL(2); break;                                                     \
+    case 3: CALL(3); break;                                                     \
+    case 4: CALL(4); break;                                                     \
+    case 5: CALL(5); break;                                                     \
+    case 6: CALL(6); break;                                                     \
+    case 7: CALL(7); break;                                                     \
+    default: return hipErrorInvalidValue;                                       \
+  }
+
+}  // namespace
+
+namespace ffh {
+
+hipError_t launch_init_coarse(const LevelArgs &a, hipStream_t stream) {
+  const int cells = a.Wn * a.Hn;
+  dim3 grid((cells + 255) / 256, 1, a.ndir);
+#define CALL(R) hipLaunchKernelGGL(k_init_coarse<R>, grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a.radius, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_level(const LevelArgs &a, hipStream_t stream) {
+  const int cells = a.Wn * a.Hn;
+  dim3 grid((cells + 255) / 256, 1, a.ndir);
+#define CALL(R) hipLaunchKernelGGL(k_seed_level<R>, grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a.radius, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream) {
+  const int half = (a.Wn + 1) / 2;
+  dim3 grid((half + 63) / 64, (a.Hn + 3) / 4, a.ndir);
+  for (int colour = 1; colour >= 0; --colour) {
+#define CALL(R) hipLaunchKernelGGL(k_prop_half<R>, grid, dim3(256), 0, stream, a, colour)
+    FF_RADIUS_SWITCH(a.radius, CALL)
+#undef CALL
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream) {
+  dim3 grid((a.Wn + 63) / 64, (a.Hn + 3) / 4, a.ndir);
+#define CALL(R) hipLaunchKernelGGL(k_random_search<R>, grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a.radius, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W,
+                              int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream) {
+  dim3 grid((W + 255) / 256, H);
+  const double eps2 = (double)eps * (double)eps;
+  hipLaunchKernelGGL(k_consistency, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
+                     reinterpret_cast<const int32_t *>(fb), cb, W, H, eps2, keep_a);
+  if (keep_b)
+    hipLaunchKernelGGL(k_consistency, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fb), cb,
+                       reinterpret_cast<const int32_t *>(fa), ca, W, H, eps2, keep_b);
+  return hipGetLastError();
+}
+
+}  // namespace ffh

@@ -1,0 +1,84 @@
+"""ctypes binding of ``libflowfields.so`` (the C ABI in include/flowfields.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  If the library is missing this module raises; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflowfields.so")
+
+FF_OK, FF_ERR_ARG, FF_ERR_LAUNCH, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED = range(5)
+UNSET = 0xFFFFFFFF
+
+
+class FlowFieldsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})" if what else status_str(status))
+
+
+class FFParams(C.Structure):
+    """Mirror of ff_params."""
+    _fields_ = [
+        ("levels", C.c_int32),
+        ("iters", C.c_int32),
+        ("radius", C.c_int32),
+        ("R_num", C.c_int32),
+        ("R_den", C.c_int32),
+        ("eps", C.c_float),
+        ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes); P = pointer-sized integer (device address)
+_P = C.c_void_p
+_I32 = C.c_int32
+_SIGS = {
+    "ff_version": (C.c_int, []),
+    "ff_status_str": (C.c_char_p, [C.c_int]),
+    "ff_descriptors": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "ff_init_nn": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
+    "ff_seed_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "ff_propagate_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "ff_random_search": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, C.c_uint64, _I32, _I32, _I32, _P, _P,
+                                   _P, _P]),
+    "ff_consistency_filter": (C.c_int, [_P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P, _P]),
+    "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
+    "ff_flow_fields": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P, _P,
+                                 _P, _P]),
+}
+
+
+def lib():
+    """Loads the library (once); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FlowFieldsError(FF_ERR_UNSUPPORTED,
+                                  f"{LIB_PATH} is not built (python -m paper_1703_02563_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    try:
+        return lib().ff_status_str(s).decode()
+    except FlowFieldsError:
+        return f"status {s}"
+
+
+def check(status: int, what: str):
+    if status != FF_OK:
+        raise FlowFieldsError(status, what)

@@ -1,0 +1,172 @@
+"""Python entry points of the Flow Fields hot path (same names as the C ABI).
+
+Tensors are CUDA tensors (device memory); PyTorch provides allocation and the
+current stream, the library does the work.  Layouts follow
+include/flowfields.h: images uint8 [H, W]; descriptors uint8 [H, W, 16];
+level grids of scale n have ceil(H/n) x ceil(W/n) cells with flows int16
+[Hn, Wn, 2] = (dx, dy) and costs stored as int32 [Hn, Wn] holding the
+uint32 bit pattern (0xFFFFFFFF, i.e. -1, marks an UNSET cell).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import ffi
+from .ffi import FFParams, check, lib
+
+UNSET_I32 = -1  # 0xFFFFFFFF viewed as int32
+
+
+@dataclasses.dataclass
+class Params:
+    """Schedule of one Flow Field computation (see ff_params)."""
+    levels: int = 5
+    iters: int = 6
+    radius: int = 3
+    R_num: int = 1
+    R_den: int = 1
+    eps: float = 1.0
+    seed: int = 12345
+
+    def to_c(self) -> FFParams:
+        return FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed)
+
+
+def _stream():
+    return C_void(torch.cuda.current_stream().cuda_stream)
+
+
+def C_void(v):
+    import ctypes
+    return ctypes.c_void_p(v)
+
+
+def _ptr(t: torch.Tensor | None, dtype=None, what: str = "tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    return C_void(t.data_ptr())
+
+
+def cells(W: int, H: int, n: int):
+    return -(-W // n), -(-H // n)
+
+
+def rs_radius(n: int, R_num: int, R_den: int) -> int:
+    return (R_num * n) // R_den
+
+
+def descriptors(img: torch.Tensor, n: int):
+    """Scale-space image and 16-byte descriptors of scale n."""
+    H, W = img.shape
+    hsum = torch.empty((H, W), dtype=torch.int16, device=img.device)
+    blurred = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    desc = torch.empty((H, W, 16), dtype=torch.uint8, device=img.device)
+    check(lib().ff_descriptors(_ptr(img, torch.uint8, "img"), W, H, n, _ptr(hsum), _ptr(blurred), _ptr(desc),
+                               _stream()), "ff_descriptors")
+    return blurred, desc
+
+
+def init_nn(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, radius: int = 3, n_evals: torch.Tensor | None = None):
+    """Exact NN seed of the coarsest grid; returns (flow, cost, nn_key)."""
+    H, W = desc_a1.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    dev = desc_a1.device
+    nb = torch.empty(((W * H + 31) // 32) * 32, dtype=torch.int32, device=dev)
+    key = torch.empty((Hc, Wc), dtype=torch.int64, device=dev)
+    flow = torch.empty((Hc, Wc, 2), dtype=torch.int16, device=dev)
+    cost = torch.empty((Hc, Wc), dtype=torch.int32, device=dev)
+    check(lib().ff_init_nn(_ptr(desc_a1, torch.uint8), _ptr(desc_b1, torch.uint8), _ptr(desc_ac, torch.uint8),
+                           _ptr(desc_bc, torch.uint8), W, H, nc, radius, _ptr(nb), _ptr(key), _ptr(flow),
+                           _ptr(cost), _ptr(n_evals, torch.int64), _stream()), "ff_init_nn")
+    return flow, cost, key
+
+
+def seed_level(cflow, ccost, desc_a, desc_b, n: int, radius: int = 3, n_evals=None):
+    H, W = desc_a.shape[:2]
+    Wn, Hn = cells(W, H, n)
+    flow = torch.empty((Hn, Wn, 2), dtype=torch.int16, device=desc_a.device)
+    cost = torch.empty((Hn, Wn), dtype=torch.int32, device=desc_a.device)
+    check(lib().ff_seed_level(_ptr(cflow, torch.int16), _ptr(ccost, torch.int32), _ptr(desc_a, torch.uint8),
+                              _ptr(desc_b, torch.uint8), W, H, n, radius, _ptr(flow), _ptr(cost),
+                              _ptr(n_evals, torch.int64), _stream()), "ff_seed_level")
+    return flow, cost
+
+
+def propagate_level(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int = 3, n_evals=None):
+    """One propagation step, in place on (flow, cost)."""
+    H, W = desc_a.shape[:2]
+    check(lib().ff_propagate_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, pass_,
+                                   _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
+                                   _stream()), "ff_propagate_level")
+
+
+def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, level: int, pass_: int, flow, cost,
+                  radius: int = 3, n_evals=None):
+    """One random-search step, in place on (flow, cost)."""
+    H, W = desc_a.shape[:2]
+    check(lib().ff_random_search(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, Rn, seed,
+                                 stream_id, level, pass_, _ptr(flow, torch.int16), _ptr(cost, torch.int32),
+                                 _ptr(n_evals, torch.int64), _stream()), "ff_random_search")
+
+
+def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: bool = True):
+    H, W = cost_a.shape
+    keep_a = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device)
+    keep_b = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device) if both else None
+    check(lib().ff_consistency_filter(_ptr(flow_a, torch.int16), _ptr(cost_a, torch.int32), _ptr(flow_b, torch.int16),
+                                      _ptr(cost_b, torch.int32), W, H, eps, _ptr(keep_a), _ptr(keep_b), _stream()),
+          "ff_consistency_filter")
+    return keep_a, keep_b
+
+
+def workspace_bytes(W: int, H: int, params: Params) -> int:
+    p = params.to_c()
+    return int(lib().ff_workspace_bytes(W, H, p))
+
+
+class FlowFields:
+    """Reusable buffers for repeated ff_flow_fields calls on one frame size."""
+
+    def __init__(self, W: int, H: int, params: Params, device="cuda"):
+        self.W, self.H, self.params = W, H, params
+        self._cp = params.to_c()
+        nbytes = int(lib().ff_workspace_bytes(W, H, self._cp))
+        if nbytes == 0:
+            raise ffi.FlowFieldsError(ffi.FF_ERR_ARG, "ff_workspace_bytes")
+        dev = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.out = {
+            "flow_fwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
+            "flow_bwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
+            "cost_fwd": torch.empty((H, W), dtype=torch.int32, device=dev),
+            "cost_bwd": torch.empty((H, W), dtype=torch.int32, device=dev),
+            "keep_fwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
+            "keep_bwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
+            "n_evals": torch.zeros(2, dtype=torch.int64, device=dev),
+        }
+
+    def __call__(self, img1: torch.Tensor, img2: torch.Tensor) -> dict:
+        if tuple(img1.shape) != (self.H, self.W) or tuple(img2.shape) != (self.H, self.W):
+            raise ValueError("image shape does not match")
+        o = self.out
+        check(lib().ff_flow_fields(_ptr(img1, torch.uint8, "img1"), _ptr(img2, torch.uint8, "img2"), self.W, self.H,
+                                   self._cp, _ptr(self.ws), self.ws.numel(), _ptr(o["flow_fwd"]), _ptr(o["flow_bwd"]),
+                                   _ptr(o["cost_fwd"]), _ptr(o["cost_bwd"]), _ptr(o["keep_fwd"]),
+                                   _ptr(o["keep_bwd"]), _ptr(o["n_evals"]), _stream()), "ff_flow_fields")
+        return o
+
+
+def flow_fields(img1: torch.Tensor, img2: torch.Tensor, params: Params | None = None) -> dict:
+    """Forward and backward Flow Fields of one pair plus consistency masks."""
+    params = params or Params()
+    H, W = img1.shape
+    ff = FlowFields(W, H, params, device=img1.device)
+    return {k: v for k, v in ff(img1, img2).items()}

@@ -1,0 +1,75 @@
+"""The C ABI library loads, exports every symbol its header declares and
+rejects bad arguments before touching the GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1703_02563_amd as ff
+from paper_1703_02563_amd import ffi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(ff_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ffi.lib()
+    names = _declared()
+    assert {"ff_init_nn", "ff_propagate_level", "ff_random_search", "ff_consistency_filter",
+            "ff_flow_fields"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert lib.ff_version() >= 1
+
+
+def test_status_strings():
+    assert ffi.status_str(0) == "ok"
+    assert "invalid" in ffi.status_str(1)
+    assert "workspace" in ffi.status_str(3)
+
+
+def test_workspace_bytes_and_validation():
+    lib = ffi.lib()
+    p = ff.Params(levels=5, iters=6).to_c()
+    n = lib.ff_workspace_bytes(1024, 436, C.byref(p))
+    assert n > 1024 * 436 * 16 * 10  # at least the ten descriptor maps
+    for bad in (dict(levels=0), dict(levels=8), dict(iters=0), dict(radius=8), dict(R_den=0)):
+        q = ff.Params(**{**dict(levels=5, iters=6), **bad}).to_c()
+        assert lib.ff_workspace_bytes(64, 64, C.byref(q)) == 0
+    assert lib.ff_workspace_bytes(0, 10, C.byref(p)) == 0
+    assert lib.ff_workspace_bytes(40000, 10, C.byref(p)) == 0
+
+
+def test_bad_arguments_return_before_any_launch():
+    lib = ffi.lib()
+    p = ff.Params().to_c()
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # NULL image
+    assert lib.ff_flow_fields(None, fake, 64, 64, C.byref(p), fake, 1 << 30, fake, fake, fake, fake, fake, None,
+                              None, None) == ffi.FF_ERR_ARG
+    # too small a workspace
+    assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 16, fake, fake, fake, fake, fake, None, None,
+                              None) == ffi.FF_ERR_WORKSPACE
+    # bad sizes / scales / passes
+    assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_propagate_level(fake, fake, 5, 5, 1, 3, -1, fake, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_consistency_filter(fake, fake, fake, None, 5, 5, 1.0, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_init_nn(fake, fake, fake, fake, 5, 5, 6, 3, fake, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+
+
+def test_python_binding_rejects_host_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        ff.descriptors(torch.zeros((4, 4), dtype=torch.uint8), 1)

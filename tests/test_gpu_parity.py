@@ -1,0 +1,211 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every kernel is compared element by element with the oracle on the same
+seeded inputs: sizes that span several tiles with ragged tails, the
+degenerate shapes (1x1, 1xN, Nx1, grids smaller than one coarse cell) and
+the full-size workloads.  The evaluation counters must match as well.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1703_02563_amd as ff
+from ffgen import CONFIG_PARAMS, FF_SEED, make_pair, random_images
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def as_u32(t):
+    return host(t).view(np.uint32)
+
+
+def counter():
+    return torch.zeros(1, dtype=torch.int64, device="cuda")
+
+
+SHAPES = [(37, 53), (1, 1), (1, 40), (33, 1), (120, 160), (9, 300)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
+def test_descriptors_bit_exact(shape, n):
+    img, _ = random_images(100 + n, *shape, kind="uniform")
+    blurred, desc = ff.descriptors(dev(img), n)
+    eb = oracle.blur(img, n)
+    assert np.array_equal(host(blurred), eb)
+    assert np.array_equal(host(desc), oracle.descriptor(eb, n))
+
+
+def _descs(img, levels):
+    return oracle.descriptors_all(img, levels)
+
+
+@pytest.mark.parametrize("shape,nc", [((17, 23), 1), ((40, 60), 4), ((61, 95), 8), ((3, 5), 2), ((1, 1), 1),
+                                      ((130, 257), 4), ((7, 200), 16)])
+def test_init_nn_bit_exact(shape, nc):
+    ia, ib = random_images(7 * nc + shape[0], *shape)
+    L = nc.bit_length()
+    Da, Db = _descs(ia, L), _descs(ib, L)
+    idx, dist = oracle.nn(Da[0], Db[0], nc, nthreads=NT)
+    eflow, ecost, ene = oracle.init_coarse(idx, Da[L - 1], Db[L - 1], nc)
+    cnt = counter()
+    flow, cost, key = ff.init_nn(dev(Da[0]), dev(Db[0]), dev(Da[L - 1]), dev(Db[L - 1]), nc, n_evals=cnt)
+    k = host(key).view(np.uint64)
+    assert np.array_equal((k & 0xFFFFFFFF).astype(np.int64), idx.astype(np.int64))
+    assert np.array_equal((k >> 32).astype(np.int64), dist)
+    assert np.array_equal(host(flow), eflow)
+    assert np.array_equal(as_u32(cost), ecost)
+    assert int(host(cnt)[0]) == ene
+
+
+def test_init_nn_ties_smallest_index():
+    ia, _ = random_images(5, 24, 36)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = np.full_like(Da, 100)          # every reference identical
+    Db[20, 30] = Da[8, 12]               # two exact matches of one query
+    Db[21, 3] = Da[8, 12]
+    idx, dist = oracle.nn(Da, Db, 4)
+    _, _, key = ff.init_nn(dev(Da), dev(Db), dev(Da), dev(Db), 4)
+    k = host(key).view(np.uint64)
+    assert np.array_equal((k & 0xFFFFFFFF).astype(np.int64), idx.astype(np.int64))
+    assert idx[2, 3] == 20 * 36 + 30
+
+
+def _random_level_state(seed, H, W, n, unset_frac=0.3):
+    rng = np.random.default_rng(seed)
+    Wn, Hn = -(-W // n), -(-H // n)
+    ys, xs = np.mgrid[0:Hn, 0:Wn] * n
+    tx = rng.integers(0, W, size=(Hn, Wn))
+    ty = rng.integers(0, H, size=(Hn, Wn))
+    # a few coherent patches so that "same flow" skips happen
+    tx[: Hn // 2, : Wn // 2] = np.clip(xs[: Hn // 2, : Wn // 2] + 3, 0, W - 1)
+    ty[: Hn // 2, : Wn // 2] = np.clip(ys[: Hn // 2, : Wn // 2] - 1, 0, H - 1)
+    flow = np.stack([tx - xs, ty - ys], -1).astype(np.int16)
+    cost = rng.integers(0, 60000, size=(Hn, Wn)).astype(np.uint32)
+    un = rng.random((Hn, Wn)) < unset_frac
+    cost[un] = oracle.UNSET
+    flow[un] = 0
+    return flow, cost
+
+
+@pytest.mark.parametrize("shape,n", [((45, 70), 1), ((61, 83), 2), ((50, 50), 4), ((1, 31), 1), ((29, 1), 2)])
+def test_seed_level_bit_exact(shape, n):
+    H, W = shape
+    ia, ib = random_images(300 + n, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    cflow, ccost = _random_level_state(n, H, W, 2 * n)
+    ef, ec, ene = oracle.seed_level(cflow, ccost, Da, Db, n)
+    cnt = counter()
+    f, c = ff.seed_level(dev(cflow), dev(ccost.view(np.int32)), dev(Da), dev(Db), n, n_evals=cnt)
+    assert np.array_equal(host(f), ef)
+    assert np.array_equal(as_u32(c), ec)
+    assert int(host(cnt)[0]) == ene
+
+
+@pytest.mark.parametrize("shape,n", [((45, 70), 1), ((61, 83), 2), ((64, 96), 4), ((1, 31), 1), ((29, 1), 1),
+                                     ((200, 300), 1)])
+@pytest.mark.parametrize("pass_", [0, 1, 2, 3, 5])
+def test_propagate_bit_exact(shape, n, pass_):
+    H, W = shape
+    ia, ib = random_images(400 + n + pass_, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    flow, cost = _random_level_state(pass_, H, W, n)
+    ef, ec, ene = oracle.propagate(Da, Db, n, pass_, flow, cost, nthreads=NT)
+    gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
+    ff.propagate_level(dev(Da), dev(Db), n, pass_, gf, gc, n_evals=cnt)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ene
+
+
+@pytest.mark.parametrize("shape,n,Rn", [((45, 70), 1, 1), ((61, 83), 2, 3), ((64, 96), 4, 6), ((1, 31), 1, 1),
+                                        ((200, 300), 1, 2), ((30, 40), 2, 0)])
+def test_random_search_bit_exact(shape, n, Rn):
+    H, W = shape
+    ia, ib = random_images(500 + n, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    flow, cost = _random_level_state(Rn, H, W, n)
+    for stream_id, level, pass_ in [(0, 0, 0), (1, 2, 3), (0, 4, 1)]:
+        ef, ec, ene = oracle.random_search(Da, Db, n, Rn, FF_SEED, stream_id, level, pass_, flow, cost,
+                                           nthreads=NT)
+        gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
+        ff.random_search(dev(Da), dev(Db), n, Rn, FF_SEED, stream_id, level, pass_, gf, gc, n_evals=cnt)
+        assert np.array_equal(host(gf), ef)
+        assert np.array_equal(as_u32(gc), ec)
+        assert int(host(cnt)[0]) == ene
+
+
+def test_consistency_bit_exact():
+    p = make_pair(1)
+    o = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=NT)
+    ka, kb = ff.consistency_filter(dev(o["flow_fwd"]), dev(o["cost_fwd"].view(np.int32)), dev(o["flow_bwd"]),
+                                   dev(o["cost_bwd"].view(np.int32)), 1.0)
+    assert np.array_equal(host(ka), o["keep_fwd"])
+    assert np.array_equal(host(kb), o["keep_bwd"])
+    for eps in (0.5, 1.5, 3.0):
+        e = oracle.consistency(o["flow_fwd"], o["cost_fwd"], o["flow_bwd"], o["cost_bwd"], eps)
+        g, _ = ff.consistency_filter(dev(o["flow_fwd"]), dev(o["cost_fwd"].view(np.int32)), dev(o["flow_bwd"]),
+                                     dev(o["cost_bwd"].view(np.int32)), eps, both=False)
+        assert np.array_equal(host(g), e)
+
+
+def _compare_full(img1, img2, params: ff.Params):
+    o = oracle.flow_fields(img1, img2, params.levels, params.iters, params.radius, params.R_num, params.R_den,
+                           params.eps, params.seed, nthreads=NT)
+    g = ff.flow_fields(dev(img1), dev(img2), params)
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(host(g[k]), o[k]), k
+    for k in ("cost_fwd", "cost_bwd"):
+        assert np.array_equal(as_u32(g[k]), o[k]), k
+    assert tuple(int(v) for v in host(g["n_evals"])) == o["n_evals"]
+    return o
+
+
+@pytest.mark.parametrize("shape,L,T,R", [((1, 1), 1, 1, (1, 1)), ((1, 37), 2, 2, (1, 1)), ((23, 1), 3, 3, (1, 1)),
+                                         ((5, 7), 4, 2, (1, 1)), ((31, 45), 3, 4, (3, 2)), ((48, 64), 1, 3, (1, 1)),
+                                         ((66, 97), 4, 5, (2, 1)), ((40, 50), 2, 4, (0, 1))])
+def test_flow_fields_small_shapes(shape, L, T, R):
+    ia, ib = random_images(600 + L * T, *shape)
+    _compare_full(ia, ib, ff.Params(levels=L, iters=T, R_num=R[0], R_den=R[1]))
+
+
+def test_flow_fields_radius_variants():
+    ia, ib = random_images(700, 40, 56)
+    for r in (0, 1, 2, 5):
+        _compare_full(ia, ib, ff.Params(levels=2, iters=3, radius=r))
+
+
+@pytest.mark.parametrize("config", [1, 2, 3])
+def test_flow_fields_configs_bit_exact(config):
+    p = make_pair(config)
+    c = CONFIG_PARAMS[config]
+    o = _compare_full(p.img1, p.img2, ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den,
+                                                eps=c.eps, seed=c.seed))
+    print(f"config {config}: n_evals {o['n_evals']}", flush=True)
+
+
+def test_flow_fields_repeat_is_deterministic():
+    p = make_pair(1)
+    c = CONFIG_PARAMS[1]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    f = ff.FlowFields(160, 120, prm)
+    a = {k: host(v).copy() for k, v in f(dev(p.img1), dev(p.img2)).items()}
+    b = {k: host(v).copy() for k, v in f(dev(p.img1), dev(p.img2)).items()}
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
