@@ -37,12 +37,88 @@ def cpu_baseline(pair, c, threads):
             "sample": f"one full {W}x{H} pair (descriptors, fwd+bwd fields, consistency), {dt:.2f} s"}
 
 
+# Integer-VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# 32-bit op (v_sad_u8: four byte |a-b| plus accumulate) per lane per clock.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per patch evaluation
+
+
+# HBM traffic of the scale-1 level kernel (one direction, one ff_run_level
+# launch on the 1024x436 pair) from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE; profiles/level_kernel_counters_1024x436.md), scaled by what the
+# same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
+TRAFFIC_BYTES = 10481.1 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "4492553d6ae0d7ce"
+LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_device.h",
+                 "paper_1703_02563_amd/csrc/ff_internal.h")
+
+
+def level_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in LEVEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def roofline_level0(ff, torch, img1, img2, params, reps):
+    """Times the scale-1 level kernel (one direction, one launch of
+    ff_run_level from the scale-2 seeds) with HIP events on the current
+    stream; algorithmic work = patch evaluations x 196 v_sad_u8 lane-ops."""
+    H, W = img1.shape
+    L = params.levels
+    Da = [ff.descriptors(img1, 1 << lv)[1] for lv in range(L)]
+    Db = [ff.descriptors(img2, 1 << lv)[1] for lv in range(L)]
+    _, _, key = ff.init_nn(Da[0], Db[0], Da[L - 1], Db[L - 1], 1 << (L - 1))
+    dev = img1.device
+    prev = None
+    for lv in range(L - 1, 0, -1):
+        Wn, Hn = -(-W // (1 << lv)), -(-H // (1 << lv))
+        fl = torch.empty((Hn, Wn, 2), dtype=torch.int16, device=dev)
+        co = torch.empty((Hn, Wn), dtype=torch.int32, device=dev)
+        if prev is None:
+            ff.run_level(Da[lv], Db[lv], lv, params, 0, 1, fl, co, nn_key=key)
+        else:
+            ff.run_level(Da[lv], Db[lv], lv, params, 0, 2, fl, co, coarse_flow=prev[0], coarse_cost=prev[1])
+        prev = (fl, co)
+    fl0 = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
+    co0 = torch.empty((H, W), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def launch(counter=None):
+        ff.run_level(Da[0], Db[0], 0, params, 0, 2, fl0, co0, coarse_flow=prev[0], coarse_cost=prev[1],
+                     n_evals=counter)
+
+    for _ in range(3):
+        launch()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        launch(cnt)
+        b.record()
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+    evals = int(cnt.item()) / reps
+    achieved = evals * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5),
+            "traffic": round(TRAFFIC_BYTES) if level_sources_sha() == TRAFFIC_SOURCES_SHA else None,
+            "kernel": "k_level<0,*> (scale 1, forward, one launch of ff_run_level)",
+            "avg_launch_ms": round(ms, 5), "evals_per_launch": evals,
+            "algorithmic_ops_per_launch": evals * SAD_OPS_PER_EVAL}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Flow Fields pair workload is not sharded across GPUs "
@@ -64,6 +140,9 @@ def main():
     dev = torch.device("cuda:0")
     img1 = torch.from_numpy(pair.img1).to(dev)
     img2 = torch.from_numpy(pair.img2).to(dev)
+    from paper_1703_02563_amd import autotune
+    tuned = autotune.load(W, H, params)
+    log(f"bench: level-kernel variants {ff.level_variants()} ({'tuned' if tuned else 'defaults'})")
     runner = ff.FlowFields(W, H, params, device=dev)
     log(f"bench: {W}x{H} L={c.levels} T={c.iters}, warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -82,6 +161,19 @@ def main():
     q = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=out["keep_fwd"].cpu().numpy())
     log(f"bench: {ms:.3f} ms/step, {value:.1f} Mpix/s, n_evals {n_evals}, quality {q}")
 
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {nbytes} bytes")
+
+    log("bench: roofline of the scale-1 level kernel")
+    roof = roofline_level0(ff, torch, img1, img2, params, reps=20)
+    log(f"bench: roofline {roof}")
+
     base = None
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
@@ -98,7 +190,7 @@ def main():
                    "n_evals": n_evals, "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                    "epe10": round(q["epe10"], 4), "kept_density": round(q["kept_density"], 4),
                    "kept_epe": round(q["kept_epe"], 4)},
-        "roofline": None,
+        "roofline": roof,
         "cpu_baseline": base,
     }
     print(json.dumps(rec), flush=True)

@@ -131,6 +131,34 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                 const uint32_t *cost_b, int32_t W, int32_t H, float eps, uint8_t *keep_a,
                                 uint8_t *keep_b, void *stream);
 
+/* All steps of one scale (Sec. 3.2): T propagation steps with T-1
+ * random-search steps between them (RS stream `stream_id`, level index
+ * `level`, n = 2^level), starting from
+ *   mode 0: the state already in flow/cost;
+ *   mode 1: the coarsest-scale NN seeds (nn_key from ff_init_nn, low 32 bits
+ *           = target pixel index; costs evaluated here);
+ *   mode 2: seeds from the grid of scale 2n (coarse_flow/coarse_cost), as
+ *           ff_seed_level.
+ * Equivalent to the corresponding sequence of ff_seed_level,
+ * ff_propagate_level and ff_random_search calls (same fields, same
+ * evaluation count); radius 3 runs in temporally blocked launches that keep
+ * the state on chip.  desc_a/desc_b: scale-n descriptors; params: host. */
+ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
+                       const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
+                       const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
+                       uint64_t *n_evals, void *stream);
+
+/* Launch configuration (tile size, workgroup size, load unrolling) of the
+ * temporally blocked level kernel that ff_flow_fields uses for patch radius 3
+ * at scale n = 2^log2n, log2n in [0, 6].  A process-wide table (host),
+ * written by the autotuner; it changes speed only, never results.  Setting
+ * it while another thread runs ff_flow_fields is a race.
+ * ff_set_level_variant returns FF_ERR_ARG for log2n or variant out of range;
+ * ff_get_level_variant returns -1 for log2n out of range. */
+int32_t ff_level_variant_count(void);
+int32_t ff_get_level_variant(int32_t log2n);
+ff_status ff_set_level_variant(int32_t log2n, int32_t variant);
+
 /* Bytes of device workspace ff_flow_fields needs for a W x H pair (host). */
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);
 

@@ -1,0 +1,89 @@
+"""Autotuner of the level-kernel launch configuration.
+
+The temporally blocked level kernel comes in several variants (tile size,
+workgroup size, load unrolling; see ff_level_variant_count).  Results never
+depend on the variant; speed does, and differently at every scale.  The tuner
+times complete ff_flow_fields calls with HIP events on the current stream and
+picks, scale by scale (coordinate descent from the current table), the
+fastest variant.  Tables are cached in a JSON file keyed by device name,
+frame size and schedule.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import flowfields as ffm
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _key(W, H, params: ffm.Params) -> str:
+    name = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    return f"{name}|{W}x{H}|L{params.levels}|T{params.iters}|r{params.radius}"
+
+
+def time_call(fn, reps: int = 10, warmup: int = 2) -> float:
+    """Median milliseconds of fn() over reps, HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int = 10, verbose: bool = False):
+    """Returns (table, log) with table[log2 n] = fastest variant."""
+    H, W = img1.shape
+    runner = ffm.FlowFields(W, H, params, device=img1.device)
+    nvar = int(ffm.lib().ff_level_variant_count())
+    table = ffm.level_variants()
+    log = []
+    for lv in range(params.levels):
+        best = None
+        for v in range(nvar):
+            trial = list(table)
+            trial[lv] = v
+            ffm.set_level_variants(trial)
+            ms = time_call(lambda: runner(img1, img2), reps=reps)
+            log.append({"log2n": lv, "variant": v, "ms": ms})
+            if verbose:
+                print(f"autotune: log2n={lv} variant={v} {ms:.4f} ms", flush=True)
+            if best is None or ms < best[1]:
+                best = (v, ms)
+        table[lv] = best[0]
+    ffm.set_level_variants(table)
+    return table, log
+
+
+def load(W: int, H: int, params: ffm.Params, path: str = DEFAULT_CACHE) -> bool:
+    """Applies a cached table if one exists for this device and shape."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        cache = json.load(f)
+    table = cache.get(_key(W, H, params))
+    if table is None:
+        return False
+    ffm.set_level_variants(table)
+    return True
+
+
+def save(W: int, H: int, params: ffm.Params, table, path: str = DEFAULT_CACHE) -> None:
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    cache[_key(W, H, params)] = list(table)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)

@@ -76,6 +76,42 @@ ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, 
   return a;
 }
 
+// The passes of one scale as temporally blocked launches: each launch runs
+// the longest run of passes whose halo fits the kernel's window.  k.dir[]
+// must hold the per-direction pointers; the scale fields are set here.
+hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_params *p, int first_mode,
+                             hipStream_t s) {
+  const int n = 1 << lv, T = p->iters;
+  k.W = W;
+  k.H = H;
+  k.n = n;
+  k.Wn = ceil_div(W, n);
+  k.Hn = ceil_div(H, n);
+  k.level = lv;
+  k.Rn = rs_radius(n, p->R_num, p->R_den);
+  k.seed = p->seed;
+  k.T = T;
+  int t0 = 0;
+  while (t0 < T) {
+    int t1 = t0 + 1, h[4];
+    for (;;) {
+      if (t1 >= T) break;
+      ffh::level_halo(t0, t1 + 1, h);
+      if (h[0] > ffh::kLevelHalo || h[1] > ffh::kLevelHalo || h[2] > ffh::kLevelHalo || h[3] > ffh::kLevelHalo)
+        break;
+      ++t1;
+    }
+    ffh::level_halo(t0, t1, k.halo);
+    k.t_begin = t0;
+    k.t_end = t1;
+    k.mode = t0 > 0 ? ffh::kLevelContinue : first_mode;
+    hipError_t e = ffh::launch_level(k, s);
+    if (e != hipSuccess) return e;
+    t0 = t1;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -175,6 +211,58 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                           (hipStream_t)stream));
 }
 
+ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
+                       const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
+                       const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
+                       uint64_t *n_evals, void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !params_ok(params) || level < 0 ||
+      level >= kMaxLevels || stream_id < 0 || stream_id > 0xFF || mode < 0 || mode > 2 || (mode == 1 && !nn_key) ||
+      (mode == 2 && (!coarse_flow || !coarse_cost)))
+    return FF_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 1 << level, r = params->radius, T = params->iters;
+  if (r == 3) {
+    ffh::LevelKArgs k{};
+    k.ndir = 1;
+    k.dir[0].Da = desc_a;
+    k.dir[0].Db = desc_b;
+    k.dir[0].flow = reinterpret_cast<int32_t *>(flow);
+    k.dir[0].cost = cost;
+    k.dir[0].nn_key = nn_key;
+    k.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
+    k.dir[0].ccost = coarse_cost;
+    k.dir[0].n_evals = reinterpret_cast<unsigned long long *>(n_evals);
+    k.dir[0].stream_id = stream_id;
+    const int first = mode == 1 ? ffh::kLevelInit : (mode == 2 ? ffh::kLevelSeed : ffh::kLevelContinue);
+    return from_hip(run_level_blocked(k, W, H, level, params, first, s));
+  }
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, r, flow, cost, n_evals);
+  a.level = level;
+  a.seed = params->seed;
+  a.Rn = rs_radius(n, params->R_num, params->R_den);
+  a.dir[0].stream_id = stream_id;
+  a.dir[0].nn_key = nn_key;
+  a.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
+  a.dir[0].ccost = coarse_cost;
+  hipError_t e = hipSuccess;
+  if (mode == 1) return FF_ERR_UNSUPPORTED;  // the per-step path seeds through ff_init_nn
+  if (mode == 2) e = ffh::launch_seed_level(a, s);
+  for (int t = 0; t < T && e == hipSuccess; ++t) {
+    a.pass = t;
+    e = ffh::launch_propagate(a, s);
+    if (e == hipSuccess && t < T - 1) e = ffh::launch_random_search(a, s);
+  }
+  return from_hip(e);
+}
+
+int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
+
+int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }
+
+ff_status ff_set_level_variant(int32_t log2n, int32_t variant) {
+  return ffh::set_level_variant(log2n, variant) ? FF_OK : FF_ERR_ARG;
+}
+
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params) {
   if (!dims_ok(W, H) || !params_ok(params)) return 0;
   return layout(W, H, params).total;
@@ -244,6 +332,31 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   for (int dr = 0; dr < 2; ++dr)
     nn.dir[dr] = {desc[dr][0], desc[dr ^ 1][0], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+
+  if (r == 3) {
+    // temporally blocked level kernels: one launch per run of passes
+    ffh::LevelKArgs k{};
+    k.ndir = 2;
+    for (int dr = 0; dr < 2; ++dr) {
+      k.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
+      k.dir[dr].stream_id = dr;
+    }
+    for (int lv = L - 1; lv >= 0; --lv) {
+      for (int dr = 0; dr < 2; ++dr) {
+        k.dir[dr].Da = desc[dr][lv];
+        k.dir[dr].Db = desc[dr ^ 1][lv];
+        k.dir[dr].flow = gflow[lv][dr];
+        k.dir[dr].cost = gcost[lv][dr];
+        k.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+        k.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+        k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+      }
+      const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
+      if ((e = run_level_blocked(k, W, H, lv, params, mode, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    }
+    return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
+                                            keep_bwd, s));
+  }
 
   ffh::LevelArgs a{};
   a.ndir = 2;

@@ -93,6 +93,17 @@ __device__ __forceinline__ void rs_offset(uint64_t seed, int stream_id, int leve
   oy = (int)__umulhi((uint32_t)(h >> 32), span) - Rn;
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup b
+// runs on XCD b % 8), and every XCD has its own L2.  This bijection of
+// [0, nwg) gives each XCD one contiguous range of logical work items, so
+// neighbouring tiles (which read neighbouring descriptors) share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+  constexpr int kXcd = 8;
+  const int q = nwg / kXcd, r = nwg % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // Adds a per-lane count (0, 1 or 2) of the whole wave to a global counter
 // with one atomic per wave.
 __device__ __forceinline__ void wave_count_add(unsigned long long *counter, int cnt) {

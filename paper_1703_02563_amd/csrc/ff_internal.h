@@ -68,6 +68,41 @@ hipError_t launch_seed_level(const LevelArgs &a, hipStream_t stream);
 hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream);  // both half-sweeps
 hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
 
+// Temporally blocked run of propagation / random-search steps of one scale
+// (patch radius 3).  Passes [t_begin, t_end) of T; a random-search step
+// follows pass t iff t < T - 1.  halo[] = half-sweeps reading the left,
+// right, top, bottom side over the run (at most kLevelHalo each).
+constexpr int kLevelHalo = 6;
+constexpr int kLevelContinue = 0;  // state from the level grid in global memory
+constexpr int kLevelInit = 1;      // coarsest scale: flows from the NN keys
+constexpr int kLevelSeed = 2;      // seeds from the coarser grid, other cells UNSET
+struct LevelKDir {
+  const uint8_t *Da;
+  const uint8_t *Db;
+  int32_t *flow;
+  uint32_t *cost;
+  const int32_t *cflow;
+  const uint32_t *ccost;
+  const uint64_t *nn_key;
+  unsigned long long *n_evals;
+  int stream_id;
+};
+struct LevelKArgs {
+  LevelKDir dir[kMaxDirs];
+  int ndir;
+  int W, H, n, Wn, Hn, level, Rn;
+  uint64_t seed;
+  int t_begin, t_end, T;
+  int mode;
+  int tiles_x;  // set by launch_level
+  int halo[4];
+};
+hipError_t launch_level(LevelKArgs a, hipStream_t stream);
+void level_halo(int t_begin, int t_end, int halo[4]);
+int level_variant_count();
+int get_level_variant(int log2n);
+bool set_level_variant(int log2n, int variant);
+
 // Consistency of field a against field b (full resolution).
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
                               int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream);

@@ -1,0 +1,369 @@
+// Temporally blocked level kernel: a run of propagation steps (Eq. 2) and
+// random-search steps (Sec. 3.1) of one scale in one launch (Sec. 3.2
+// schedule), for patch radius 3.
+//
+// Each workgroup owns a TW x TH tile of the level grid and keeps the flow
+// and cost of the tile plus a halo in LDS.  A half-sweep that reads sources
+// on one side can only update correctly the cells whose source lies inside
+// the currently valid window, so the valid window loses one cell on every
+// side the half-sweep reads from.  The halo of a run equals the number of
+// half-sweeps that read each side, so after the last step exactly the owned
+// tile is valid and is written back.  Cells of the halo are computed
+// redundantly by the neighbouring workgroups; evaluations are counted only
+// for owned cells, so the count equals the unblocked schedule's.
+//
+// The scale-n descriptors of image a are staged in LDS on the level
+// lattice (virtual cell (i+u, j+v) -> pixel clamp((i+u)n, (j+v)n)), which is
+// exactly where E_n reads them.  Image b is read at p + f + n(u, v) with f
+// per cell, straight from global memory; waves whose lanes all read inside
+// the image use immediate load offsets (no clamps).
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+using ffk::clampi;
+using ffk::kUnset;
+
+constexpr int kR = 3;
+constexpr int kHalo = ffh::kLevelHalo;
+
+template <int TW, int TH>
+struct Geo {
+  static constexpr int LW = TW + 2 * kHalo, LH = TH + 2 * kHalo;  // state window
+  static constexpr int DW = LW + 2 * kR, DH = LH + 2 * kR;        // descriptor window
+};
+
+// E_n(p, f) with image-a descriptors from LDS.  `pa` points at the LDS
+// descriptor of the cell itself; (bx, by) = p + f in pixels.
+template <int LOG2N, int DW, bool UNROLL>
+__device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int H, int bx,
+                                              int by, bool fast) {
+  constexpr int n = 1 << LOG2N;
+  uint32_t s = 0;
+  if (fast) {
+    // every lane of the wave reads inside the image: no clamps, immediate
+    // offsets along the row; with UNROLL all 49 loads are issued at once
+    const uint4 *pb = Db + (size_t)(by - kR * n) * W + (bx - kR * n);
+#pragma unroll(UNROLL ? 2 * kR + 1 : 1)
+    for (int v = 0; v < 2 * kR + 1; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+#pragma unroll
+      for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], pb[u * n], s);
+      pb += (size_t)n * W;
+    }
+  } else {
+    const int Wm = W - 1, Hm = H - 1;
+#pragma unroll(UNROLL ? 2 * kR + 1 : 1)
+    for (int v = 0; v < 2 * kR + 1; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+      const uint4 *rb = Db + (size_t)clampi(by + (v - kR) * n, Hm) * W;
+#pragma unroll
+      for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], rb[clampi(bx + (u - kR) * n, Wm)], s);
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ bool interior(int bx, int by, int n, int W, int H) {
+  return bx - kR * n >= 0 && bx + kR * n < W && by - kR * n >= 0 && by + kR * n < H;
+}
+
+// Wave-uniform choice of the unclamped path for candidate target (bx, by).
+__device__ __forceinline__ bool wave_fast(bool active, int bx, int by, int n, int W, int H) {
+  const bool in = bx - kR * n >= 0 && bx + kR * n < W && by - kR * n >= 0 && by + kR * n < H;
+  return __all(!active || in);
+}
+
+template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
+__device__ __forceinline__ void level_body(const ffh::LevelKArgs &a) {
+  using G = Geo<TW, TH>;
+  constexpr int n = 1 << LOG2N;
+  __shared__ int32_t s_flow[G::LH * G::LW];
+  __shared__ uint32_t s_cost[G::LH * G::LW];
+  __shared__ uint4 s_da[G::DH * G::DW];
+  __shared__ unsigned int s_cnt;
+
+  // one workgroup per (direction, tile); XCD-aware order
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = wg % tiles;
+  const ffh::LevelKDir d = a.dir[wg / tiles];
+  const int tid = threadIdx.x;
+  const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
+  const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
+  const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
+  const int gi0 = ti0 - kHalo, gj0 = tj0 - kHalo;  // grid coords of window cell (0, 0)
+  const uint4 *Db = reinterpret_cast<const uint4 *>(d.Db);
+  if (tid == 0) s_cnt = 0;
+
+  // image-a descriptors on the level lattice around the window
+  {
+    const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
+    for (int k = tid; k < G::DH * G::DW; k += kThreads) {
+      const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
+      s_da[k] = Da[(size_t)clampi(vj * n, H - 1) * W + clampi(vi * n, W - 1)];
+    }
+  }
+  __syncthreads();
+
+  int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
+  auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
+
+  // initial state of the valid window
+  {
+    const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+    const int rw = rr - rl, rh = rb - rt;
+    const int Wc = (Wn + 1) >> 1;
+    for (int base = 0; base < rw * rh; base += kThreads) {
+      const int k = base + tid;
+      int cnt = 0;
+      if (k < rw * rh) {
+        const int i = rl + k % rw, j = rt + k / rw;
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        int32_t f = 0;
+        uint32_t c = kUnset;
+        bool eval = false;
+        if (a.mode == ffh::kLevelContinue) {
+          f = d.flow[(size_t)j * Wn + i];
+          c = d.cost[(size_t)j * Wn + i];
+        } else if (a.mode == ffh::kLevelInit) {
+          const uint32_t q = (uint32_t)d.nn_key[(size_t)j * Wn + i];
+          f = ffk::pack_flow((int)(q % (uint32_t)W) - i * n, (int)(q / (uint32_t)W) - j * n);
+          eval = true;
+        } else if (!((i | j) & 1)) {
+          const int kc = (j >> 1) * Wc + (i >> 1);
+          if (d.ccost[kc] != kUnset) {
+            f = d.cflow[kc];
+            eval = true;
+          }
+        }
+        s_flow[l] = f;
+        s_cost[l] = c;
+        if (eval) {
+          const int bx = i * n + ffk::flow_x(f), by = j * n + ffk::flow_y(f);
+          const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+          s_cost[l] = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, false);
+          cnt = owned(i, j);
+        }
+      }
+      const int tot = __popcll(__ballot(cnt));
+      if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+    }
+  }
+  __syncthreads();
+
+  for (int t = a.t_begin; t < a.t_end; ++t) {
+    const int dir = t & 3;
+    const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
+    const int vdj = (dir == 0 || dir == 2) ? -1 : 1;
+    for (int colour = 1; colour >= 0; --colour) {
+      if (hdi < 0) --ml; else --mr;
+      if (vdj < 0) --mt; else --mb;
+      const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+      const int hw = (rr - rl + 1) >> 1, rh = rb - rt;
+      for (int base = 0; base < hw * rh; base += kThreads) {
+        const int k = base + tid;
+        const int j = rt + (k < hw * rh ? k / hw : 0);
+        const int i = rl + ((colour + j + rl) & 1) + 2 * (k % max(hw, 1));
+        const bool live = k < hw * rh && i < rr;
+        int cnt = 0;
+        // candidate checks (Eq. 2 with the skip rules)
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        const int x = i * n, y = j * n;
+        uint32_t c0 = kUnset;
+        int32_t f0 = 0, fh = 0, fv = 0;
+        bool hv = false, vb = false;
+        if (live) {
+          c0 = s_cost[l];
+          f0 = s_flow[l];
+          const bool set0_ = c0 != kUnset;
+          if (i + hdi >= 0 && i + hdi < Wn && s_cost[l + hdi] != kUnset) {
+            fh = s_flow[l + hdi];
+            const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
+            hv = !(set0_ && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+          }
+          if (j + vdj >= 0 && j + vdj < Hn && s_cost[l + vdj * G::LW] != kUnset) {
+            fv = s_flow[l + vdj * G::LW];
+            const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
+            vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
+          }
+        }
+        const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+        uint32_t bc = c0;
+        int32_t bf = f0;
+        uint32_t eh = 0;
+        if (__any(hv)) {
+          const int bx = x + ffk::flow_x(fh), by = y + ffk::flow_y(fh);
+          const bool fast = wave_fast(hv, bx, by, n, W, H);
+          if (hv) {
+            eh = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
+            cnt = 1;
+            if (eh < bc) { bc = eh; bf = fh; }
+          }
+        }
+        const bool vev = vb && (bc == kUnset || fv != bf);
+        const bool vcomp = vev && !(hv && fv == fh);
+        if (__any(vcomp)) {
+          const int bx = x + ffk::flow_x(fv), by = y + ffk::flow_y(fv);
+          const bool fast = wave_fast(vcomp, bx, by, n, W, H);
+          if (vcomp) {
+            const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
+            if (e < bc) { bc = e; bf = fv; }
+          }
+        }
+        if (vev) cnt += 1;  // an evaluation of fv == fh repeats eh, which did not win
+        if (live && (bc != c0 || bf != f0)) {
+          s_cost[l] = bc;
+          s_flow[l] = bf;
+        }
+        if (!owned(i, j)) cnt = 0;
+        const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2));
+        if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+      }
+      __syncthreads();
+    }
+    if (t < a.T - 1) {  // random search over the whole valid window
+      const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+      const int rw = rr - rl, rh = rb - rt;
+      for (int base = 0; base < rw * rh; base += kThreads) {
+        const int k = base + tid;
+        const bool live = k < rw * rh;
+        const int i = rl + (live ? k % rw : 0), j = rt + (live ? k / rw : 0);
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        bool act = false;
+        int fx = 0, fy = 0;
+        uint32_t c0 = kUnset;
+        if (live) {
+          c0 = s_cost[l];
+          if (c0 != kUnset) {
+            int ox, oy;
+            ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+            const int32_t f0 = s_flow[l];
+            fx = ffk::flow_x(f0) + ox;
+            fy = ffk::flow_y(f0) + oy;
+            const int tx = i * n + fx, ty = j * n + fy;
+            act = (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
+          }
+        }
+        int cnt = 0;
+        if (__any(act)) {
+          const int bx = i * n + fx, by = j * n + fy;
+          const bool fast = wave_fast(act, bx, by, n, W, H);
+          if (act) {
+            const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+            const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
+            cnt = owned(i, j);
+            if (e < c0) {
+              s_cost[l] = e;
+              s_flow[l] = ffk::pack_flow(fx, fy);
+            }
+          }
+        }
+        const int tot = __popcll(__ballot(cnt));
+        if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+      }
+      __syncthreads();
+    }
+  }
+
+  // write back the owned tile
+  const int ow = oi1 - ti0, oh = oj1 - tj0;
+  for (int k = tid; k < ow * oh; k += kThreads) {
+    const int i = ti0 + k % ow, j = tj0 + k / ow;
+    const int l = (j - gj0) * G::LW + (i - gi0);
+    d.flow[(size_t)j * Wn + i] = s_flow[l];
+    d.cost[(size_t)j * Wn + i] = s_cost[l];
+  }
+  if (tid == 0 && s_cnt && d.n_evals) atomicAdd(d.n_evals, (unsigned long long)s_cnt);
+}
+
+template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
+__global__ __launch_bounds__(kThreads) void k_level(ffh::LevelKArgs a) {
+  level_body<LOG2N, TW, TH, kThreads, UNROLL>(a);
+}
+
+// One wave per SIMD: up to 512 VGPRs, so every load of an evaluation (both
+// candidates of a propagation step) can be in flight at once.
+template <int LOG2N, int TW, int TH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_level_wide(ffh::LevelKArgs a) {
+  level_body<LOG2N, TW, TH, 256, true>(a);
+}
+
+// Tile / workgroup variants of the level kernel (see ffh::kLevelVariants).
+template <int LOG2N, int TW, int TH, int THREADS, bool UNROLL>
+hipError_t launch_v(const ffh::LevelKArgs &a, hipStream_t stream) {
+  ffh::LevelKArgs b = a;
+  b.tiles_x = (a.Wn + TW - 1) / TW;
+  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, UNROLL>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  return hipGetLastError();
+}
+
+template <int LOG2N, int TW, int TH>
+hipError_t launch_wide(const ffh::LevelKArgs &a, hipStream_t stream) {
+  ffh::LevelKArgs b = a;
+  b.tiles_x = (a.Wn + TW - 1) / TW;
+  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  hipLaunchKernelGGL((k_level_wide<LOG2N, TW, TH>), dim3(tiles * a.ndir), dim3(256), 0, stream, b);
+  return hipGetLastError();
+}
+
+template <int LOG2N>
+hipError_t launch_n(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_v<LOG2N, 64, 32, 1024, false>(a, stream);
+    case 1: return launch_v<LOG2N, 32, 16, 1024, false>(a, stream);
+    case 2: return launch_v<LOG2N, 32, 16, 256, true>(a, stream);
+    case 3: return launch_v<LOG2N, 16, 16, 256, true>(a, stream);
+    case 4: return launch_v<LOG2N, 32, 32, 512, true>(a, stream);
+    case 5: return launch_wide<LOG2N, 32, 16>(a, stream);
+    case 6: return launch_wide<LOG2N, 16, 16>(a, stream);
+    case 7: return launch_wide<LOG2N, 16, 8>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Per-scale variant table (index log2 n); written by ff_set_level_variant.
+int g_variant[7] = {2, 2, 3, 3, 3, 3, 3};
+
+}  // namespace
+
+namespace ffh {
+
+int level_variant_count() { return 8; }
+
+int get_level_variant(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant[log2n] : -1; }
+
+bool set_level_variant(int log2n, int variant) {
+  if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= level_variant_count()) return false;
+  g_variant[log2n] = variant;
+  return true;
+}
+
+hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
+  int log2n = 0;
+  while ((1 << log2n) < a.n) ++log2n;
+  const int v = get_level_variant(log2n);
+  switch (log2n) {
+    case 0: return launch_n<0>(a, v, stream);
+    case 1: return launch_n<1>(a, v, stream);
+    case 2: return launch_n<2>(a, v, stream);
+    case 3: return launch_n<3>(a, v, stream);
+    case 4: return launch_n<4>(a, v, stream);
+    case 5: return launch_n<5>(a, v, stream);
+    case 6: return launch_n<6>(a, v, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+void level_halo(int t_begin, int t_end, int halo[4]) {
+  halo[0] = halo[1] = halo[2] = halo[3] = 0;
+  for (int t = t_begin; t < t_end; ++t) {
+    const int d = t & 3;
+    halo[(d == 0 || d == 3) ? 0 : 1] += 2;
+    halo[(d == 0 || d == 2) ? 2 : 3] += 2;
+  }
+}
+
+}  // namespace ffh

@@ -79,13 +79,19 @@ __device__ __forceinline__ long load_i8x8(const uint8_t *p) {
 }
 
 __global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
-  const ffh::NNDir d = a.dir[blockIdx.z];
+  // one workgroup per (direction, reference chunk, query block), query
+  // block fastest; XCD-aware order keeps the workgroups of one chunk on one L2
+  const int nqb = (a.M + 32 * kQB - 1) / (32 * kQB);
+  const int ntiles = (a.N + 31) >> 5;
+  const int nchunk = (ntiles + kTilesPerChunk - 1) / kTilesPerChunk;
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  const int qblk = wg % nqb, chunk = (wg / nqb) % nchunk;
+  const ffh::NNDir d = a.dir[wg / (nqb * nchunk)];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, kh = lane >> 5;
   const int M = a.M, N = a.N, W = a.W;
-  const int m0 = blockIdx.x * (32 * kQB);
-  const int ntiles = (N + 31) >> 5;
-  const int t0 = blockIdx.y * kTilesPerChunk;
+  const int m0 = qblk * (32 * kQB);
+  const int t0 = chunk * kTilesPerChunk;
   const int t1 = min(t0 + kTilesPerChunk, ntiles);
   if (t0 + wave >= t1) return;  // wave-uniform: no tile for this wave
 
@@ -164,8 +170,9 @@ hipError_t launch_nn(const NNArgs &args, hipStream_t stream) {
     if (e != hipSuccess) return e;
   }
   const int ntiles = Npad / 32;
-  dim3 grid((args.M + 32 * kQB - 1) / (32 * kQB), (ntiles + kTilesPerChunk - 1) / kTilesPerChunk, args.ndir);
-  hipLaunchKernelGGL(k_nn, grid, dim3(64 * kWaves), 0, stream, args);
+  const int nqb = (args.M + 32 * kQB - 1) / (32 * kQB);
+  const int nchunk = (ntiles + kTilesPerChunk - 1) / kTilesPerChunk;
+  hipLaunchKernelGGL(k_nn, dim3(nqb * nchunk * args.ndir), dim3(64 * kWaves), 0, stream, args);
   return hipGetLastError();
 }
 

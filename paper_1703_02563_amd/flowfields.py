@@ -117,6 +117,16 @@ def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, le
                                  _ptr(n_evals, torch.int64), _stream()), "ff_random_search")
 
 
+def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: int, flow, cost, nn_key=None,
+              coarse_flow=None, coarse_cost=None, n_evals=None):
+    """All steps of one scale, in place on (flow, cost); see ff_run_level."""
+    H, W = desc_a.shape[:2]
+    check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, level, params.to_c(),
+                             stream_id, mode, _ptr(nn_key, torch.int64), _ptr(coarse_flow, torch.int16),
+                             _ptr(coarse_cost, torch.int32), _ptr(flow, torch.int16), _ptr(cost, torch.int32),
+                             _ptr(n_evals, torch.int64), _stream()), "ff_run_level")
+
+
 def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: bool = True):
     H, W = cost_a.shape
     keep_a = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device)
@@ -125,6 +135,17 @@ def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: b
                                       _ptr(cost_b, torch.int32), W, H, eps, _ptr(keep_a), _ptr(keep_b), _stream()),
           "ff_consistency_filter")
     return keep_a, keep_b
+
+
+def level_variants() -> list:
+    """Current level-kernel variant per scale (index log2 n)."""
+    return [int(lib().ff_get_level_variant(k)) for k in range(7)]
+
+
+def set_level_variants(table) -> None:
+    """Sets the level-kernel variant of every scale (index log2 n)."""
+    for k, v in enumerate(table):
+        check(lib().ff_set_level_variant(k, int(v)), "ff_set_level_variant")
 
 
 def workspace_bytes(W: int, H: int, params: Params) -> int:

@@ -209,3 +209,72 @@ def test_flow_fields_repeat_is_deterministic():
     b = {k: host(v).copy() for k, v in f(dev(p.img1), dev(p.img2)).items()}
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_level_kernel_variants_bit_exact(config):
+    """Every launch variant of the level kernel gives the same field."""
+    p = make_pair(config)
+    c = CONFIG_PARAMS[config]
+    prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den)
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed,
+                           nthreads=NT)
+    saved = ff.level_variants()
+    try:
+        for v in range(int(ff.lib().ff_level_variant_count())):
+            ff.set_level_variants([v] * 7)
+            g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+            for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
+                assert np.array_equal(host(g[k]), o[k]), (v, k)
+            assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"]), v
+            assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], v
+    finally:
+        ff.set_level_variants(saved)
+
+
+@pytest.mark.parametrize("shape,level,T,R", [((61, 83), 0, 6, (1, 1)), ((61, 83), 1, 4, (3, 2)),
+                                             ((130, 200), 2, 6, (1, 1)), ((45, 70), 0, 9, (2, 1)),
+                                             ((33, 1), 0, 3, (1, 1)), ((200, 260), 0, 6, (1, 1))])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_run_level_bit_exact(shape, level, T, R, mode):
+    """ff_run_level equals the oracle's step sequence for that scale."""
+    H, W = shape
+    n = 1 << level
+    prm = ff.Params(levels=level + 1, iters=T, R_num=R[0], R_den=R[1])
+    ia, ib = random_images(800 + level * 10 + mode, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    Wn, Hn = -(-W // n), -(-H // n)
+    key = cflow = ccost = None
+    if mode == 0:
+        flow, cost = _random_level_state(3, H, W, n)
+        ne0 = 0
+    elif mode == 1:
+        Da1 = oracle.descriptor(oracle.blur(ia, 1), 1)
+        Db1 = oracle.descriptor(oracle.blur(ib, 1), 1)
+        idx, _ = oracle.nn(Da1, Db1, n, nthreads=NT)
+        flow, cost, ne0 = oracle.init_coarse(idx, Da, Db, n)
+        key = dev(idx.astype(np.int64))
+    else:
+        cflow, ccost = _random_level_state(4, H, W, 2 * n)
+        flow, cost, ne0 = oracle.seed_level(cflow, ccost, Da, Db, n)
+    ef, ec, ne = flow, cost, ne0
+    Rn = oracle.rs_radius(n, *R)
+    for t in range(T):
+        ef, ec, k = oracle.propagate(Da, Db, n, t, ef, ec, nthreads=NT)
+        ne += k
+        if t < T - 1:
+            ef, ec, k = oracle.random_search(Da, Db, n, Rn, prm.seed, 0, level, t, ef, ec, nthreads=NT)
+            ne += k
+    if mode == 0:
+        gf, gc = dev(flow), dev(cost.view(np.int32))
+    else:
+        gf = torch.empty((Hn, Wn, 2), dtype=torch.int16, device="cuda")
+        gc = torch.empty((Hn, Wn), dtype=torch.int32, device="cuda")
+    cnt = counter()
+    ff.run_level(dev(Da), dev(Db), level, prm, 0, mode, gf, gc, nn_key=key,
+                 coarse_flow=None if cflow is None else dev(cflow),
+                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ne
