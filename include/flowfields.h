@@ -148,6 +148,26 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
                        uint64_t *n_evals, void *stream);
 
+/* Float patch cost of learned features (Sec. 3.5 learned data term read as
+ * a sum of squared differences over the subsampled patch of Eq. 3, with the
+ * replicate border of Sec. 3.6):
+ *   cost[e] = sum_{v,u=-r..r} sum_{c<16} (f1(clamp(p+n(u,v)))[c] - f2(clamp(p+f+n(u,v)))[c])^2
+ * for entry e = (x, y, fx, fy) = pixel p and flow f (int32 [count][4]).
+ * f1, f2: float32 [H][W][16]; cost: float32 [count], accumulated in
+ * float32 by fused multiply-adds in the order v, u, c. */
+ff_status ff_cost_f32_fwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
+                          const int32_t *entries, int32_t count, float *cost, void *stream);
+
+/* Gradient of sum_e grad_cost[e] * cost[e] with respect to f1 and f2
+ * (d/df1 = +2 g (f1 - f2), d/df2 = -2 g (f1 - f2) at every patch position).
+ * Contributions are summed in 64-bit fixed point (2^-32 units) with integer
+ * atomics, so the result is deterministic; every |2 g (f1 - f2)| must stay
+ * below 2^31.  acc_scratch: int64 [2][H][W][16] scratch (cleared here);
+ * grad_f1, grad_f2: float32 [H][W][16] outputs (overwritten). */
+ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
+                          const int32_t *entries, int32_t count, const float *grad_cost, int64_t *acc_scratch,
+                          float *grad_f1, float *grad_f2, void *stream);
+
 /* Launch configuration (tile size, workgroup size, load unrolling) of the
  * temporally blocked level kernel that ff_flow_fields uses for patch radius 3
  * at scale n = 2^log2n, log2n in [0, 6].  A process-wide table (host),

@@ -255,6 +255,47 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
   return from_hip(e);
 }
 
+ff_status ff_cost_f32_fwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
+                          const int32_t *entries, int32_t count, float *cost, void *stream) {
+  if (!f1 || !f2 || (count > 0 && (!entries || !cost)) || !dims_ok(W, H) || !is_pow2(n) || radius < 0 ||
+      radius > 7 || count < 0)
+    return FF_ERR_ARG;
+  ffh::CostArgs a{};
+  a.f1 = f1;
+  a.f2 = f2;
+  a.entries = reinterpret_cast<const int4 *>(entries);
+  a.count = count;
+  a.W = W;
+  a.H = H;
+  a.n = n;
+  a.radius = radius;
+  a.cost = cost;
+  return from_hip(ffh::launch_cost_fwd(a, (hipStream_t)stream));
+}
+
+ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
+                          const int32_t *entries, int32_t count, const float *grad_cost, int64_t *acc_scratch,
+                          float *grad_f1, float *grad_f2, void *stream) {
+  if (!f1 || !f2 || (count > 0 && (!entries || !grad_cost)) || !acc_scratch || !grad_f1 || !grad_f2 ||
+      !dims_ok(W, H) || !is_pow2(n) || radius < 0 || radius > 7 || count < 0)
+    return FF_ERR_ARG;
+  ffh::CostArgs a{};
+  a.f1 = f1;
+  a.f2 = f2;
+  a.entries = reinterpret_cast<const int4 *>(entries);
+  a.count = count;
+  a.W = W;
+  a.H = H;
+  a.n = n;
+  a.radius = radius;
+  a.grad_cost = grad_cost;
+  a.acc1 = acc_scratch;
+  a.acc2 = acc_scratch + (size_t)W * H * 16;
+  a.grad_f1 = grad_f1;
+  a.grad_f2 = grad_f2;
+  return from_hip(ffh::launch_cost_bwd(a, (hipStream_t)stream));
+}
+
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
 
 int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }

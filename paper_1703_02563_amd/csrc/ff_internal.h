@@ -103,6 +103,21 @@ int level_variant_count();
 int get_level_variant(int log2n);
 bool set_level_variant(int log2n, int variant);
 
+// Float patch cost of 16-channel float32 feature maps (learned data term).
+struct CostArgs {
+  const float *f1;       // [H][W][16]
+  const float *f2;       // [H][W][16]
+  const int4 *entries;   // [count] = (x, y, fx, fy)
+  int count;
+  int W, H, n, radius;
+  float *cost;            // forward output [count]
+  const float *grad_cost; // backward input [count]
+  int64_t *acc1, *acc2;   // backward fixed-point accumulators [H][W][16]
+  float *grad_f1, *grad_f2;
+};
+hipError_t launch_cost_fwd(const CostArgs &a, hipStream_t stream);
+hipError_t launch_cost_bwd(const CostArgs &a, hipStream_t stream);
+
 // Consistency of field a against field b (full resolution).
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
                               int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream);

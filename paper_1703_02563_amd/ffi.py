@@ -53,6 +53,8 @@ _SIGS = {
     "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
     "ff_run_level": (C.c_int, [_P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P, _P, _P,
                                _P]),
+    "ff_cost_f32_fwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "ff_cost_f32_bwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),
     "ff_level_variant_count": (C.c_int32, []),
     "ff_get_level_variant": (C.c_int32, [_I32]),
     "ff_set_level_variant": (C.c_int, [_I32, _I32]),
