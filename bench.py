@@ -111,12 +111,40 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
             "algorithmic_ops_per_launch": evals * SAD_OPS_PER_EVAL}
 
 
+def batched_throughput(ff, torch, reps):
+    """64 pairs of uneven sizes (256-1280 x 192-512, 12 polygon layers, t in
+    +-100 px) in one ff_flow_fields_batched call, replayed from a HIP graph."""
+    from ffgen import CONFIG_PARAMS, batch_shapes, make_pair
+    from paper_1703_02563_amd.batch import BatchFlowFields
+    c = CONFIG_PARAMS[4]
+    shapes = batch_shapes()
+    prm = ff.Params(levels=c.levels, iters=c.iters, radius=c.radius, R_num=c.R_num, R_den=c.R_den, eps=c.eps,
+                    seed=c.seed)
+    b = BatchFlowFields(shapes, prm)
+    for k, shp in enumerate(shapes):
+        p = make_pair(4, k, shape=shp)
+        b.set_pair(k, torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda())
+    b.capture()
+    for _ in range(2):
+        b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    mpix = sum(h * w for h, w in shapes) / 1e6
+    return {"pairs": len(shapes), "mpix": round(mpix, 3), "ms_per_batch": round(dt * 1e3, 3),
+            "mpix_per_s": round(mpix / dt, 2), "graph": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-pair measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -170,6 +198,12 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {nbytes} bytes")
 
+    batched = None
+    if not args.no_batch:
+        log("bench: batched 64-pair workload (graph replay)")
+        batched = batched_throughput(ff, torch, reps=5)
+        log(f"bench: batched {batched}")
+
     log("bench: roofline of the scale-1 level kernel")
     roof = roofline_level0(ff, torch, img1, img2, params, reps=20)
     log(f"bench: roofline {roof}")
@@ -189,7 +223,7 @@ def main():
                    "W": W, "H": H, "levels": c.levels, "iters": c.iters, "R": f"{c.R_num}/{c.R_den}",
                    "n_evals": n_evals, "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                    "epe10": round(q["epe10"], 4), "kept_density": round(q["kept_density"], 4),
-                   "kept_epe": round(q["kept_epe"], 4)},
+                   "kept_epe": round(q["kept_epe"], 4), "batched": batched},
         "roofline": roof,
         "cpu_baseline": base,
     }

@@ -148,6 +148,41 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
                        uint64_t *n_evals, void *stream);
 
+/* One pair of a batch (host struct; every pointer is a device pointer):
+ * images [H][W]; outputs as for ff_flow_fields; keep_bwd and n_evals ([2])
+ * may be NULL. */
+typedef struct {
+    const uint8_t *img1, *img2;
+    int32_t W, H;
+    int16_t *flow_fwd, *flow_bwd;
+    uint32_t *cost_fwd, *cost_bwd;
+    uint8_t *keep_fwd, *keep_bwd;
+    uint64_t *n_evals;
+} ff_pair;
+
+/* Device workspace for a batch (host): the sum of the pairs' shares. */
+size_t ff_batch_workspace_bytes(const ff_pair *pairs, int32_t npairs, const ff_params *params);
+
+/* Bytes of the batch table (host). */
+size_t ff_batch_table_bytes(int32_t npairs);
+
+/* Writes into table_host (host memory, ff_batch_table_bytes bytes) the
+ * device-side record of every pair: its buffers and its share of `ws`
+ * (device address of the workspace, not dereferenced here).  The caller
+ * copies the table to device memory once; it stays valid as long as the
+ * pairs' buffers and `ws` do.  1 <= npairs <= 256. */
+ff_status ff_batch_table(const ff_pair *pairs, int32_t npairs, const ff_params *params, void *ws,
+                         size_t ws_bytes, void *table_host, size_t table_bytes);
+
+/* Forward and backward Flow Fields plus consistency masks of every pair of a
+ * batch (pairs of different sizes), each stage as one persistent launch over
+ * all pairs' work items (rows, NN blocks, tiles); per pair the results are
+ * those of ff_flow_fields.  pairs: host array (sizes, for the launch
+ * geometry); table: device copy of ff_batch_table's output; radius must be 3
+ * (FF_ERR_UNSUPPORTED otherwise).  Enqueues kernels only (capturable). */
+ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_params *params,
+                                 const void *table, void *ws, size_t ws_bytes, void *stream);
+
 /* Float patch cost of learned features (Sec. 3.5 learned data term read as
  * a sum of squared differences over the subsampled patch of Eq. 3, with the
  * replicate border of Sec. 3.6):

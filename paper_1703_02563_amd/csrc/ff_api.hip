@@ -76,6 +76,18 @@ ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, 
   return a;
 }
 
+// End of the longest run of passes starting at t0 whose halo fits the level
+// kernel's window.
+int run_end(int t0, int T) {
+  int t1 = t0 + 1, h[4];
+  while (t1 < T) {
+    ffh::level_halo(t0, t1 + 1, h);
+    if (h[0] > ffh::kLevelHalo || h[1] > ffh::kLevelHalo || h[2] > ffh::kLevelHalo || h[3] > ffh::kLevelHalo) break;
+    ++t1;
+  }
+  return t1;
+}
+
 // The passes of one scale as temporally blocked launches: each launch runs
 // the longest run of passes whose halo fits the kernel's window.  k.dir[]
 // must hold the per-direction pointers; the scale fields are set here.
@@ -93,14 +105,7 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   k.T = T;
   int t0 = 0;
   while (t0 < T) {
-    int t1 = t0 + 1, h[4];
-    for (;;) {
-      if (t1 >= T) break;
-      ffh::level_halo(t0, t1 + 1, h);
-      if (h[0] > ffh::kLevelHalo || h[1] > ffh::kLevelHalo || h[2] > ffh::kLevelHalo || h[3] > ffh::kLevelHalo)
-        break;
-      ++t1;
-    }
+    const int t1 = run_end(t0, T);
     ffh::level_halo(t0, t1, k.halo);
     k.t_begin = t0;
     k.t_end = t1;
@@ -294,6 +299,144 @@ ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H
   a.grad_f1 = grad_f1;
   a.grad_f2 = grad_f2;
   return from_hip(ffh::launch_cost_bwd(a, (hipStream_t)stream));
+}
+
+// ---- batches -------------------------------------------------------------
+
+static bool batch_ok(const ff_pair *pairs, int32_t npairs, const ff_params *p) {
+  if (!pairs || npairs < 1 || npairs > ffh::kMaxBatch || !params_ok(p)) return false;
+  for (int i = 0; i < npairs; ++i) {
+    const ff_pair &q = pairs[i];
+    if (!q.img1 || !q.img2 || !q.flow_fwd || !q.flow_bwd || !q.cost_fwd || !q.cost_bwd || !q.keep_fwd ||
+        !dims_ok(q.W, q.H))
+      return false;
+  }
+  return true;
+}
+
+size_t ff_batch_workspace_bytes(const ff_pair *pairs, int32_t npairs, const ff_params *params) {
+  if (!batch_ok(pairs, npairs, params)) return 0;
+  size_t total = 0;
+  for (int i = 0; i < npairs; ++i) total = align256(total + layout(pairs[i].W, pairs[i].H, params).total);
+  return total;
+}
+
+size_t ff_batch_table_bytes(int32_t npairs) {
+  return (npairs < 1 || npairs > ffh::kMaxBatch) ? 0 : sizeof(ffh::BatchPair) * (size_t)npairs;
+}
+
+ff_status ff_batch_table(const ff_pair *pairs, int32_t npairs, const ff_params *params, void *ws, size_t ws_bytes,
+                         void *table_host, size_t table_bytes) {
+  if (!batch_ok(pairs, npairs, params) || !ws || !table_host) return FF_ERR_ARG;
+  if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params) || table_bytes < ff_batch_table_bytes(npairs))
+    return FF_ERR_WORKSPACE;
+  ffh::BatchPair *tab = static_cast<ffh::BatchPair *>(table_host);
+  char *base = static_cast<char *>(ws);
+  size_t off = 0;
+  const int L = params->levels;
+  for (int i = 0; i < npairs; ++i) {
+    const ff_pair &q = pairs[i];
+    const Layout lay = layout(q.W, q.H, params);
+    char *b = base + off;
+    ffh::BatchPair t;
+    std::memset(&t, 0, sizeof(t));
+    t.img[0] = q.img1;
+    t.img[1] = q.img2;
+    t.W = q.W;
+    t.H = q.H;
+    for (int im = 0; im < 2; ++im) {
+      for (int lv = 0; lv < L; ++lv) {
+        const size_t z = (size_t)(im * L + lv);
+        t.hsum[im][lv] = reinterpret_cast<uint16_t *>(b + lay.hsum) + z * lay.N;
+        t.blur[im][lv] = reinterpret_cast<uint8_t *>(b + lay.blur) + z * lay.N;
+        t.desc[im][lv] = reinterpret_cast<uint8_t *>(b + lay.desc) + z * lay.N * 16;
+      }
+      t.nb[im] = reinterpret_cast<int32_t *>(b + lay.nb) + (size_t)im * lay.Npad;
+      t.keys[im] = reinterpret_cast<uint64_t *>(b + lay.keys) + (size_t)im * lay.M;
+    }
+    t.gflow[0][0] = reinterpret_cast<int32_t *>(q.flow_fwd);
+    t.gflow[0][1] = reinterpret_cast<int32_t *>(q.flow_bwd);
+    t.gcost[0][0] = q.cost_fwd;
+    t.gcost[0][1] = q.cost_bwd;
+    size_t g = lay.grids;
+    for (int lv = 1; lv < L; ++lv) {
+      const size_t cells = (size_t)ceil_div(q.W, 1 << lv) * ceil_div(q.H, 1 << lv);
+      for (int dr = 0; dr < 2; ++dr) {
+        t.gflow[lv][dr] = reinterpret_cast<int32_t *>(b + g) + (size_t)dr * 2 * cells;
+        t.gcost[lv][dr] = reinterpret_cast<uint32_t *>(t.gflow[lv][dr] + cells);
+      }
+      g = align256(g + 2 * cells * 2 * sizeof(uint32_t));
+    }
+    t.keep[0] = q.keep_fwd;
+    t.keep[1] = q.keep_bwd;
+    t.evals = reinterpret_cast<unsigned long long *>(q.n_evals ? q.n_evals
+                                                               : reinterpret_cast<uint64_t *>(b + lay.evals));
+    tab[i] = t;
+    off = align256(off + lay.total);
+  }
+  return FF_OK;
+}
+
+ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_params *params, const void *table,
+                                 void *ws, size_t ws_bytes, void *stream) {
+  if (!batch_ok(pairs, npairs, params) || !table || !ws || !(params->eps >= 0.0f)) return FF_ERR_ARG;
+  if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
+  if (params->radius != 3) return FF_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const int L = params->levels, T = params->iters, nc = 1 << (L - 1);
+  ffh::BatchStage st{};
+  st.pairs = static_cast<const ffh::BatchPair *>(table);
+  st.npairs = npairs;
+  st.L = L;
+  auto fill = [&](auto items_of) {
+    st.prefix[0] = 0;
+    for (int i = 0; i < npairs; ++i) st.prefix[i + 1] = st.prefix[i] + items_of(pairs[i].W, pairs[i].H);
+    st.total = st.prefix[npairs];
+  };
+  hipError_t e;
+  // descriptors: (pair, image * L + scale, row)
+  fill([&](int, int H) { return 2 * L * H; });
+  if ((e = ffh::launch_batch_descriptors(st, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  // NN: norms (pair, image, 256 refs), keys (pair, direction, 256 queries), NN items
+  ffh::BatchStage norms = st, keysf = st, nn = st;
+  norms.n = keysf.n = nn.n = nc;
+  {
+    auto set = [&](ffh::BatchStage &b, auto items_of) {
+      b.prefix[0] = 0;
+      for (int i = 0; i < npairs; ++i) b.prefix[i + 1] = b.prefix[i] + items_of(pairs[i].W, pairs[i].H);
+      b.total = b.prefix[npairs];
+    };
+    set(norms, [&](int W, int H) { return 2 * (int)((((size_t)W * H + 31) / 32 * 32 + 255) / 256); });
+    set(keysf, [&](int W, int H) { return 2 * ((ceil_div(W, nc) * ceil_div(H, nc) + 255) / 256); });
+    set(nn, [&](int W, int H) { return ffh::batch_nn_items(W, H, L); });
+  }
+  if ((e = ffh::launch_batch_nn(norms, keysf, nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  // scales, coarse to fine: one persistent launch per run of passes
+  for (int lv = L - 1; lv >= 0; --lv) {
+    const int n = 1 << lv;
+    fill([&](int W, int H) { return 2 * ffh::level_tiles(ceil_div(W, n), ceil_div(H, n), lv); });
+    st.n = n;
+    st.lv = lv;
+    ffh::LevelKArgs k{};
+    k.ndir = 2;
+    k.n = n;
+    k.level = lv;
+    k.Rn = rs_radius(n, params->R_num, params->R_den);
+    k.seed = params->seed;
+    k.T = T;
+    int t0 = 0;
+    while (t0 < T) {
+      const int t1 = run_end(t0, T);
+      ffh::level_halo(t0, t1, k.halo);
+      k.t_begin = t0;
+      k.t_end = t1;
+      k.mode = t0 > 0 ? ffh::kLevelContinue : (lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed);
+      if ((e = ffh::launch_batch_level(k, st, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      t0 = t1;
+    }
+  }
+  fill([&](int, int H) { return 2 * H; });
+  return from_hip(ffh::launch_batch_consistency(st, params->eps, s));
 }
 
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }

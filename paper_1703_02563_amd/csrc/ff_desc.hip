@@ -9,6 +9,8 @@
 //
 // All (image, scale) jobs of a call run in one launch per stage: blockIdx.z
 // selects the job.
+#include <algorithm>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -58,9 +60,82 @@ __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
   reinterpret_cast<uint4 *>(jb.desc)[(size_t)y * W + x] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// ---- batches: items = (pair, image * L + scale, row) ---------------------
+struct RowItem {
+  const ffh::BatchPair *bp;
+  int im, lv, y;
+};
+
+__device__ __forceinline__ RowItem row_item(const ffh::BatchStage &st, int item) {
+  const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+  const ffh::BatchPair &bp = st.pairs[p];
+  const int local = item - st.prefix[p];
+  const int z = local / bp.H;
+  return {&bp, z / st.L, z % st.L, local % bp.H};
+}
+
+__global__ __launch_bounds__(256) void k_hsum_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const RowItem r = row_item(st, item);
+    const int W = r.bp->W, h = max(1, (1 << r.lv) >> 1);
+    const uint8_t *row = r.bp->img[r.im] + (size_t)r.y * W;
+    uint16_t *out = r.bp->hsum[r.im][r.lv] + (size_t)r.y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      uint32_t s = 0;
+      for (int dx = -h; dx <= h; ++dx) s += row[clampi(x + dx, W - 1)];
+      out[x] = (uint16_t)s;
+    }
+  });
+}
+
+__global__ __launch_bounds__(256) void k_vsum_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const RowItem r = row_item(st, item);
+    const int W = r.bp->W, H = r.bp->H, h = max(1, (1 << r.lv) >> 1);
+    const uint32_t area = (uint32_t)((2 * h + 1) * (2 * h + 1));
+    const uint16_t *hs = r.bp->hsum[r.im][r.lv];
+    uint8_t *out = r.bp->blur[r.im][r.lv] + (size_t)r.y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      uint32_t s = 0;
+      for (int dy = -h; dy <= h; ++dy) s += hs[(size_t)clampi(r.y + dy, H - 1) * W + x];
+      out[x] = (uint8_t)((s + area / 2) / area);
+    }
+  });
+}
+
+__global__ __launch_bounds__(256) void k_desc_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const RowItem r = row_item(st, item);
+    const int W = r.bp->W, H = r.bp->H, n = 1 << r.lv;
+    const uint8_t *b = r.bp->blur[r.im][r.lv];
+    uint4 *out = reinterpret_cast<uint4 *>(r.bp->desc[r.im][r.lv]) + (size_t)r.y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      uint32_t w[4];
+#pragma unroll
+      for (int gy = 0; gy < 4; ++gy) {
+        const uint8_t *row = b + (size_t)clampi(r.y + n * (2 * gy - 3), H - 1) * W;
+        uint32_t v = 0;
+#pragma unroll
+        for (int gx = 0; gx < 4; ++gx) v |= (uint32_t)row[clampi(x + n * (2 * gx - 3), W - 1)] << (8 * gx);
+        w[gy] = v;
+      }
+      out[x] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  });
+}
+
 }  // namespace
 
 namespace ffh {
+
+hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream) {
+  if (rows.total <= 0) return hipSuccess;
+  const dim3 grid(((std::min(rows.total, 4096) + 7) / 8) * 8);
+  hipLaunchKernelGGL(k_hsum_batch, grid, dim3(256), 0, stream, rows);
+  hipLaunchKernelGGL(k_vsum_batch, grid, dim3(256), 0, stream, rows);
+  hipLaunchKernelGGL(k_desc_batch, grid, dim3(256), 0, stream, rows);
+  return hipGetLastError();
+}
 
 hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
   if (jobs.count <= 0) return hipSuccess;

@@ -104,6 +104,30 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Pair owning `item` in a batch stage: the largest p with prefix[p] <= item.
+__device__ __forceinline__ int batch_pair(const int *prefix, int npairs, int item) {
+  int lo = 0, hi = npairs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent launch over `total` work items: XCD x (workgroups b with
+// b % 8 == x) owns one contiguous range of items and its workgroups stride
+// through it.  The grid size must be a positive multiple of 8.
+template <typename F>
+__device__ __forceinline__ void for_items(int total, F &&f) {
+  constexpr int kXcd = 8;
+  const int G = gridDim.x, b = blockIdx.x, x = b % kXcd, k = b / kXcd;
+  const int gx = G / kXcd;
+  const int q = total / kXcd, r = total % kXcd;
+  const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  const int cnt = q + (x < r ? 1 : 0);
+  for (int it = k; it < cnt; it += gx) f(start + it);
+}
+
 // Adds a per-lane count (0, 1 or 2) of the whole wave to a global counter
 // with one atomic per wave.
 __device__ __forceinline__ void wave_count_add(unsigned long long *counter, int cnt) {

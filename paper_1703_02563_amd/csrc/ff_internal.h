@@ -103,6 +103,41 @@ int level_variant_count();
 int get_level_variant(int log2n);
 bool set_level_variant(int log2n, int variant);
 
+// ---- batches of pairs of different sizes (one launch per stage) ----------
+constexpr int kMaxBatch = 256;
+constexpr int kMaxScales = 7;
+
+// Device-side record of one pair of a batch: inputs, outputs and the pair's
+// share of the workspace (all device pointers).
+struct BatchPair {
+  const uint8_t *img[2];
+  int W, H;
+  uint16_t *hsum[2][kMaxScales];
+  uint8_t *blur[2][kMaxScales];
+  uint8_t *desc[2][kMaxScales];
+  int32_t *nb[2];
+  uint64_t *keys[2];
+  int32_t *gflow[kMaxScales][2];
+  uint32_t *gcost[kMaxScales][2];
+  uint8_t *keep[2];
+  unsigned long long *evals;  // [2]
+};
+
+// Work items of one stage: pair p owns items [prefix[p], prefix[p+1]).
+struct BatchStage {
+  const BatchPair *pairs;
+  int npairs, total;
+  int L, n, lv;  // scales of the schedule, scale of this stage
+  int prefix[kMaxBatch + 1];
+};
+hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream);
+hipError_t launch_batch_nn(const BatchStage &norms, const BatchStage &fill, const BatchStage &nn, hipStream_t stream);
+hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &tiles, hipStream_t stream);
+hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream_t stream);
+// items per pair of each stage (host)
+int batch_nn_items(int W, int H, int L);
+int level_tiles(int Wn, int Hn, int log2n);  // tiles of one direction, current variant of that scale
+
 // Float patch cost of 16-channel float32 feature maps (learned data term).
 struct CostArgs {
   const float *f1;       // [H][W][16]

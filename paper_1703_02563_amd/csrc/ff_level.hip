@@ -17,6 +17,8 @@
 // exactly where E_n reads them.  Image b is read at p + f + n(u, v) with f
 // per cell, straight from global memory; waves whose lanes all read inside
 // the image use immediate load offsets (no clamps).
+#include <algorithm>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -75,8 +77,10 @@ __device__ __forceinline__ bool wave_fast(bool active, int bx, int by, int n, in
   return __all(!active || in);
 }
 
+// The run of passes for tile `tile` of one direction `d` (a holds the
+// pair's sizes and the schedule).  All threads of the workgroup call it.
 template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
-__device__ __forceinline__ void level_body(const ffh::LevelKArgs &a) {
+__device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   using G = Geo<TW, TH>;
   constexpr int n = 1 << LOG2N;
   __shared__ int32_t s_flow[G::LH * G::LW];
@@ -84,11 +88,6 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a) {
   __shared__ uint4 s_da[G::DH * G::DW];
   __shared__ unsigned int s_cnt;
 
-  // one workgroup per (direction, tile); XCD-aware order
-  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
-  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = wg % tiles;
-  const ffh::LevelKDir d = a.dir[wg / tiles];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
   const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
@@ -278,21 +277,62 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a) {
   if (tid == 0 && s_cnt && d.n_evals) atomicAdd(d.n_evals, (unsigned long long)s_cnt);
 }
 
+// One workgroup per (direction, tile) of one pair; XCD-aware order.
 template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
 __global__ __launch_bounds__(kThreads) void k_level(ffh::LevelKArgs a) {
-  level_body<LOG2N, TW, TH, kThreads, UNROLL>(a);
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  level_body<LOG2N, TW, TH, kThreads, UNROLL>(a, a.dir[wg / tiles], wg % tiles);
 }
 
-// One wave per SIMD: up to 512 VGPRs, so every load of an evaluation (both
-// candidates of a propagation step) can be in flight at once.
-template <int LOG2N, int TW, int TH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_level_wide(ffh::LevelKArgs a) {
-  level_body<LOG2N, TW, TH, 256, true>(a);
+// Persistent launch over the (pair, direction, tile) items of a batch.
+template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
+__global__ __launch_bounds__(kThreads) void k_level_batch(ffh::LevelKArgs base, ffh::BatchStage st) {
+  constexpr int n = 1 << LOG2N;
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    ffh::LevelKArgs a = base;
+    a.W = bp.W;
+    a.H = bp.H;
+    a.Wn = (bp.W + n - 1) / n;
+    a.Hn = (bp.H + n - 1) / n;
+    a.tiles_x = (a.Wn + TW - 1) / TW;
+    const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+    const int local = item - st.prefix[p];
+    const int dir = local / tiles, lv = st.lv;
+    ffh::LevelKDir d;
+    d.Da = bp.desc[dir][lv];
+    d.Db = bp.desc[dir ^ 1][lv];
+    d.flow = bp.gflow[lv][dir];
+    d.cost = bp.gcost[lv][dir];
+    d.cflow = lv + 1 < st.L ? bp.gflow[lv + 1][dir] : nullptr;
+    d.ccost = lv + 1 < st.L ? bp.gcost[lv + 1][dir] : nullptr;
+    d.nn_key = bp.keys[dir];
+    d.n_evals = bp.evals + dir;
+    d.stream_id = dir;
+    level_body<LOG2N, TW, TH, kThreads, UNROLL>(a, d, local % tiles);
+    __syncthreads();  // the next item reuses the LDS window
+  });
 }
 
-// Tile / workgroup variants of the level kernel (see ffh::kLevelVariants).
+// Tile / workgroup variants of the level kernel.
+struct Variant {
+  int tw, th;
+};
+constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}};
+constexpr int kNumVariants = 5;
+
 template <int LOG2N, int TW, int TH, int THREADS, bool UNROLL>
-hipError_t launch_v(const ffh::LevelKArgs &a, hipStream_t stream) {
+hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
+  if (batch) {
+    if (batch->total <= 0) return hipSuccess;
+    // persistent: enough workgroups to fill the chip, a multiple of 8
+    const int grid = ((std::min(batch->total, 2048) + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, UNROLL>), dim3(grid), dim3(THREADS), 0, stream, a,
+                       *batch);
+    return hipGetLastError();
+  }
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
@@ -300,26 +340,28 @@ hipError_t launch_v(const ffh::LevelKArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int LOG2N, int TW, int TH>
-hipError_t launch_wide(const ffh::LevelKArgs &a, hipStream_t stream) {
-  ffh::LevelKArgs b = a;
-  b.tiles_x = (a.Wn + TW - 1) / TW;
-  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
-  hipLaunchKernelGGL((k_level_wide<LOG2N, TW, TH>), dim3(tiles * a.ndir), dim3(256), 0, stream, b);
-  return hipGetLastError();
+template <int LOG2N>
+hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int variant, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_v<LOG2N, 64, 32, 1024, false>(a, batch, stream);
+    case 1: return launch_v<LOG2N, 32, 16, 1024, false>(a, batch, stream);
+    case 2: return launch_v<LOG2N, 32, 16, 256, true>(a, batch, stream);
+    case 3: return launch_v<LOG2N, 16, 16, 256, true>(a, batch, stream);
+    case 4: return launch_v<LOG2N, 32, 32, 512, true>(a, batch, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template <int LOG2N>
-hipError_t launch_n(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
-  switch (variant) {
-    case 0: return launch_v<LOG2N, 64, 32, 1024, false>(a, stream);
-    case 1: return launch_v<LOG2N, 32, 16, 1024, false>(a, stream);
-    case 2: return launch_v<LOG2N, 32, 16, 256, true>(a, stream);
-    case 3: return launch_v<LOG2N, 16, 16, 256, true>(a, stream);
-    case 4: return launch_v<LOG2N, 32, 32, 512, true>(a, stream);
-    case 5: return launch_wide<LOG2N, 32, 16>(a, stream);
-    case 6: return launch_wide<LOG2N, 16, 16>(a, stream);
-    case 7: return launch_wide<LOG2N, 16, 8>(a, stream);
+hipError_t dispatch(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int log2n, int variant,
+                    hipStream_t stream) {
+  switch (log2n) {
+    case 0: return launch_n<0>(a, batch, variant, stream);
+    case 1: return launch_n<1>(a, batch, variant, stream);
+    case 2: return launch_n<2>(a, batch, variant, stream);
+    case 3: return launch_n<3>(a, batch, variant, stream);
+    case 4: return launch_n<4>(a, batch, variant, stream);
+    case 5: return launch_n<5>(a, batch, variant, stream);
+    case 6: return launch_n<6>(a, batch, variant, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -331,7 +373,7 @@ int g_variant[7] = {2, 2, 3, 3, 3, 3, 3};
 
 namespace ffh {
 
-int level_variant_count() { return 8; }
+int level_variant_count() { return kNumVariants; }
 
 int get_level_variant(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant[log2n] : -1; }
 
@@ -341,20 +383,27 @@ bool set_level_variant(int log2n, int variant) {
   return true;
 }
 
+static int log2_of(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
-  int log2n = 0;
-  while ((1 << log2n) < a.n) ++log2n;
+  const int l2 = log2_of(a.n);
+  return dispatch(a, nullptr, l2, get_level_variant(l2), stream);
+}
+
+hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, hipStream_t stream) {
+  const int l2 = log2_of(base.n);
+  return dispatch(base, &st, l2, get_level_variant(l2), stream);
+}
+
+int level_tiles(int Wn, int Hn, int log2n) {
   const int v = get_level_variant(log2n);
-  switch (log2n) {
-    case 0: return launch_n<0>(a, v, stream);
-    case 1: return launch_n<1>(a, v, stream);
-    case 2: return launch_n<2>(a, v, stream);
-    case 3: return launch_n<3>(a, v, stream);
-    case 4: return launch_n<4>(a, v, stream);
-    case 5: return launch_n<5>(a, v, stream);
-    case 6: return launch_n<6>(a, v, stream);
-    default: return hipErrorInvalidValue;
-  }
+  if (v < 0) return 0;
+  const Variant t = kVariants[v];
+  return ((Wn + t.tw - 1) / t.tw) * ((Hn + t.th - 1) / t.th);
 }
 
 void level_halo(int t_begin, int t_end, int halo[4]) {

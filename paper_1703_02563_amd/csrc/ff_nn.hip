@@ -22,6 +22,7 @@
 // Key written to global memory: ((dist - |a|^2 + 2^20) << 32) | index; the
 // init kernel adds |a|^2 back.  Padding references (index >= N) carry
 // |b|^2 = 2^20 - 1 and zero bytes, so their score is below every real one.
+#include <algorithm>
 #include <climits>
 
 #include "ff_device.h"
@@ -78,22 +79,20 @@ __device__ __forceinline__ long load_i8x8(const uint8_t *p) {
   return (long)(*reinterpret_cast<const unsigned long long *>(p) ^ 0x8080808080808080ull);
 }
 
-__global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
-  // one workgroup per (direction, reference chunk, query block), query
-  // block fastest; XCD-aware order keeps the workgroups of one chunk on one L2
-  const int nqb = (a.M + 32 * kQB - 1) / (32 * kQB);
-  const int ntiles = (a.N + 31) >> 5;
-  const int nchunk = (ntiles + kTilesPerChunk - 1) / kTilesPerChunk;
-  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  const int qblk = wg % nqb, chunk = (wg / nqb) % nchunk;
-  const ffh::NNDir d = a.dir[wg / (nqb * nchunk)];
+// Query block `qblk` (32 * kQB queries) against reference chunk `chunk` of
+// one direction.  All threads of the workgroup call it.
+__device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W, int nc, int Wc, int qblk,
+                                        int chunk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, kh = lane >> 5;
-  const int M = a.M, N = a.N, W = a.W;
+  const int ntiles = (N + 31) >> 5;
   const int m0 = qblk * (32 * kQB);
   const int t0 = chunk * kTilesPerChunk;
   const int t1 = min(t0 + kTilesPerChunk, ntiles);
   if (t0 + wave >= t1) return;  // wave-uniform: no tile for this wave
+  struct {
+    int Wc, nc;
+  } a = {Wc, nc};
 
   long aop[kQB];
 #pragma unroll
@@ -152,9 +151,99 @@ __global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
     }
 }
 
+__device__ __forceinline__ int nn_qblocks(int M) { return (M + 32 * kQB - 1) / (32 * kQB); }
+__device__ __forceinline__ int nn_chunks(int N) {
+  return (((N + 31) >> 5) + kTilesPerChunk - 1) / kTilesPerChunk;
+}
+
+// One workgroup per (direction, reference chunk, query block) of one pair,
+// query block fastest; XCD-aware order keeps the workgroups of one chunk on
+// one L2.
+__global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
+  const int nqb = nn_qblocks(a.M), nchunk = nn_chunks(a.N);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  nn_body(a.dir[wg / (nqb * nchunk)], a.M, a.N, a.W, a.nc, a.Wc, wg % nqb, (wg / nqb) % nchunk);
+}
+
+// ---- batches -----------------------------------------------------------
+// Squared norms of both images' level-1 descriptors (items: pair, image,
+// 256 references); the first item of a pair also clears its counters.
+__global__ __launch_bounds__(256) void k_nn_norms_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    const int N = bp.W * bp.H, Npad = (N + 31) & ~31;
+    const int blocks = (Npad + 255) / 256;
+    const int local = item - st.prefix[p];
+    const int im = local / blocks, idx = (local % blocks) * 256 + threadIdx.x;
+    if (local == 0 && threadIdx.x < 2) bp.evals[threadIdx.x] = 0;
+    if (idx >= Npad) return;
+    int s = kNbPad;
+    if (idx < N) {
+      const uint4 v = reinterpret_cast<const uint4 *>(bp.desc[im][0])[idx];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      s = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int e = (int)((w[k] >> (8 * b)) & 0xFF) - 128;
+          s += e * e;
+        }
+    }
+    bp.nb[im][idx] = s;
+  });
+}
+
+// Key initialisation (items: pair, direction, 256 queries).
+__global__ __launch_bounds__(256) void k_nn_fill_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    const int M = ((bp.W + st.n - 1) / st.n) * ((bp.H + st.n - 1) / st.n);
+    const int blocks = (M + 255) / 256;
+    const int local = item - st.prefix[p];
+    const int dir = local / blocks, m = (local % blocks) * 256 + threadIdx.x;
+    if (m < M) bp.keys[dir][m] = ~0ull;
+  });
+}
+
+// NN of every pair (items: pair, direction, chunk, query block).
+__global__ __launch_bounds__(256) void k_nn_batch(ffh::BatchStage st) {
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    const int nc = st.n, Wc = (bp.W + nc - 1) / nc;
+    const int M = Wc * ((bp.H + nc - 1) / nc), N = bp.W * bp.H;
+    const int nqb = nn_qblocks(M), nchunk = nn_chunks(N);
+    const int local = item - st.prefix[p];
+    const int dir = local / (nqb * nchunk);
+    const ffh::NNDir d = {bp.desc[dir][0], bp.desc[dir ^ 1][0], bp.nb[dir ^ 1], bp.keys[dir]};
+    nn_body(d, M, N, bp.W, nc, Wc, local % nqb, (local / nqb) % nchunk);
+  });
+}
+
 }  // namespace
 
 namespace ffh {
+
+int batch_nn_items(int W, int H, int L) {
+  const int nc = 1 << (L - 1);
+  const int M = ((W + nc - 1) / nc) * ((H + nc - 1) / nc), N = W * H;
+  const int nqb = (M + 32 * kQB - 1) / (32 * kQB);
+  const int nchunk = (((N + 31) >> 5) + kTilesPerChunk - 1) / kTilesPerChunk;
+  return 2 * nqb * nchunk;
+}
+
+static int persistent_grid(int total, int cap) { return ((std::min(std::max(total, 1), cap) + 7) / 8) * 8; }
+
+hipError_t launch_batch_nn(const BatchStage &norms, const BatchStage &fill, const BatchStage &nn,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_nn_norms_batch, dim3(persistent_grid(norms.total, 4096)), dim3(256), 0, stream, norms);
+  hipLaunchKernelGGL(k_nn_fill_batch, dim3(persistent_grid(fill.total, 4096)), dim3(256), 0, stream, fill);
+  hipLaunchKernelGGL(k_nn_batch, dim3(persistent_grid(nn.total, 2048)), dim3(64 * kWaves), 0, stream, nn);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;

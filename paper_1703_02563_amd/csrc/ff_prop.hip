@@ -16,6 +16,8 @@
 // One lane per cell; both directions of a pair run in one launch
 // (blockIdx.z).  Each kernel counts the patch-cost evaluations it performs
 // with one atomic per wave.
+#include <algorithm>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -211,6 +213,36 @@ __global__ __launch_bounds__(256) void k_consistency(const int32_t *fa, const ui
   keep[k] = out;
 }
 
+// Batches: items = (pair, direction, row); direction 1 writes the backward
+// mask when the pair has one.
+__global__ __launch_bounds__(256) void k_consistency_batch(ffh::BatchStage st, double eps2) {
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    const int local = item - st.prefix[p];
+    const int dir = local / bp.H, y = local % bp.H, W = bp.W, H = bp.H;
+    uint8_t *keep = bp.keep[dir];
+    if (keep == nullptr) return;
+    const int32_t *fa = bp.gflow[0][dir], *fb = bp.gflow[0][dir ^ 1];
+    const uint32_t *ca = bp.gcost[0][dir], *cb = bp.gcost[0][dir ^ 1];
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      const size_t k = (size_t)y * W + x;
+      uint8_t out = 0;
+      if (ca[k] != kUnset) {
+        const int32_t f = fa[k];
+        const int qx = x + ffk::flow_x(f), qy = y + ffk::flow_y(f);
+        const size_t kq = (size_t)qy * W + qx;
+        if (qx >= 0 && qx < W && qy >= 0 && qy < H && cb[kq] != kUnset) {
+          const int32_t g = fb[kq];
+          const int64_t dx = ffk::flow_x(f) + ffk::flow_x(g), dy = ffk::flow_y(f) + ffk::flow_y(g);
+          out = (double)(dx * dx + dy * dy) < eps2;
+        }
+      }
+      keep[k] = out;
+    }
+  });
+}
+
 #define FF_RADIUS_SWITCH(R_, CALL)                                              \
   switch (R_) {                                                                 \
     case 0: CALL(0); break;                                                     \
@@ -262,6 +294,13 @@ hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream) {
 #define CALL(R) hipLaunchKernelGGL(k_random_search<R>, grid, dim3(256), 0, stream, a)
   FF_RADIUS_SWITCH(a.radius, CALL)
 #undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream_t stream) {
+  if (rows.total <= 0) return hipSuccess;
+  const dim3 grid(((std::min(rows.total, 4096) + 7) / 8) * 8);
+  hipLaunchKernelGGL(k_consistency_batch, grid, dim3(256), 0, stream, rows, (double)eps * (double)eps);
   return hipGetLastError();
 }
 

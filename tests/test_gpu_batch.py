@@ -1,0 +1,99 @@
+"""Batched Flow Fields: every pair of a batch equals its single-pair result,
+which the other GPU tests pin to the oracle; a few pairs are compared with
+the oracle directly.  Results do not depend on batch order, and graph
+replays repeat the eager results."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1703_02563_amd as ff
+from ffgen import CONFIG_PARAMS, batch_shapes, make_pair, random_images
+from paper_1703_02563_amd.batch import BatchFlowFields
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+KEYS = ("flow_fwd", "flow_bwd", "cost_fwd", "cost_bwd", "keep_fwd", "keep_bwd", "n_evals")
+
+
+def _host(out):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().copy() for k, v in out.items()}
+
+
+def _check_oracle(img1, img2, got, prm):
+    o = oracle.flow_fields(img1, img2, prm.levels, prm.iters, prm.radius, prm.R_num, prm.R_den, prm.eps, prm.seed,
+                           nthreads=NT)
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(got[k], o[k]), k
+    for k in ("cost_fwd", "cost_bwd"):
+        assert np.array_equal(got[k].view(np.uint32), o[k]), k
+    assert tuple(int(v) for v in got["n_evals"]) == o["n_evals"]
+
+
+def test_small_ragged_batch_matches_oracle():
+    shapes = [(1, 1), (5, 300), (40, 30), (120, 160), (37, 53), (2, 2), (61, 95)]
+    prm = ff.Params(levels=3, iters=4)
+    b = BatchFlowFields(shapes, prm)
+    imgs = [random_images(900 + k, H, W) for k, (H, W) in enumerate(shapes)]
+    for k, (a, c) in enumerate(imgs):
+        b.set_pair(k, torch.from_numpy(a).cuda(), torch.from_numpy(c).cuda())
+    outs = [_host(o) for o in b.run()]
+    for k, (a, c) in enumerate(imgs):
+        _check_oracle(a, c, outs[k], prm)
+
+
+def _config4_batch(n_pairs, order=None):
+    shapes = batch_shapes()[:n_pairs]
+    order = list(range(n_pairs)) if order is None else order
+    c = CONFIG_PARAMS[4]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    b = BatchFlowFields([shapes[k] for k in order], prm)
+    pairs = {}
+    for slot, k in enumerate(order):
+        p = make_pair(4, k, shape=shapes[k])
+        pairs[k] = p
+        b.set_pair(slot, torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda())
+    return b, pairs, prm, order
+
+
+def test_config4_batch_equals_single_pair_path():
+    n = 64
+    b, pairs, prm, order = _config4_batch(n)
+    outs = [_host(o) for o in b.run()]
+    for k in range(n):
+        p = pairs[k]
+        single = _host(ff.flow_fields(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), prm))
+        for key in KEYS:
+            assert np.array_equal(outs[k][key], single[key]), (k, key)
+    for k in (0, 17):  # and straight against the oracle
+        _check_oracle(pairs[k].img1, pairs[k].img2, outs[k], prm)
+
+
+def test_batch_order_does_not_matter():
+    n = 12
+    b1, _, _, _ = _config4_batch(n)
+    perm = list(np.random.default_rng(3).permutation(n))
+    b2, _, _, order = _config4_batch(n, perm)
+    o1 = [_host(o) for o in b1.run()]
+    o2 = [_host(o) for o in b2.run()]
+    for slot, k in enumerate(order):
+        for key in KEYS:
+            assert np.array_equal(o2[slot][key], o1[k][key]), (k, key)
+
+
+def test_graph_replay_repeats_eager_results():
+    b, _, _, _ = _config4_batch(6)
+    eager = [_host(o) for o in b.run()]
+    b.capture()
+    for rep in range(3):
+        for o in b.out:  # clobber the outputs between replays
+            o["flow_fwd"].fill_(7)
+            o["cost_fwd"].fill_(-5)
+        torch.cuda.synchronize()
+        got = [_host(o) for o in b.replay()]
+        for k in range(len(eager)):
+            for key in KEYS:
+                assert np.array_equal(got[k][key], eager[k][key]), (rep, k, key)
