@@ -23,7 +23,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with the host compiler (plain -O2, OpenMP threads)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC", _SRC,
+                               "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +54,11 @@ def lib():
         L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
         L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
+        L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
+        L.or_cost_f32.restype = C.c_uint32
+        L.or_quantize_u8.argtypes = [P, C.c_int64, P]
+        L.or_flow_fields_f32.argtypes = [P, P, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
+        L.or_flow_fields_f32.restype = i
         _lib = L
     return _lib
 
@@ -183,6 +189,47 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
     rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, float(eps), seed,
                               nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
                               _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    out["n_evals"] = (int(ne[0]), int(ne[1]))
+    return out
+
+
+def cost_f32(Fa, Fb, n: int, r: int, x: int, y: int, fx: int, fy: int) -> float:
+    """Single-precision learned-feature cost (fused multiply-adds, order v, u, c)."""
+    Fa = np.ascontiguousarray(Fa, np.float32)
+    Fb = np.ascontiguousarray(Fb, np.float32)
+    H, W = Fa.shape[:2]
+    bits = lib().or_cost_f32(_p(Fa), _p(Fb), W, H, n, r, x, y, fx, fy)
+    return float(np.array([bits], np.uint32).view(np.float32)[0])
+
+
+def quantize_u8(f) -> np.ndarray:
+    f = np.ascontiguousarray(f, np.float32)
+    q = np.empty(f.shape, np.uint8)
+    lib().or_quantize_u8(_p(f), f.size, _p(q))
+    return q
+
+
+def flow_fields_f32(F1, F2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
+                    eps: float = 1.0, seed: int = 12345, nthreads: int = 1) -> dict:
+    """The multi-scale schedule on learned float features F1[l], F2[l]
+    (float32 [H][W][16] per scale 2^l); costs come back as float32."""
+    F1 = [np.ascontiguousarray(f, np.float32) for f in F1]
+    F2 = [np.ascontiguousarray(f, np.float32) for f in F2]
+    H, W = F1[0].shape[:2]
+    arr1 = (C.c_void_p * levels)(*[f.ctypes.data for f in F1])
+    arr2 = (C.c_void_p * levels)(*[f.ctypes.data for f in F2])
+    out = {
+        "flow_fwd": np.empty((H, W, 2), np.int16), "flow_bwd": np.empty((H, W, 2), np.int16),
+        "cost_fwd": np.empty((H, W), np.uint32), "cost_bwd": np.empty((H, W), np.uint32),
+        "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
+    }
+    ne = np.zeros(2, np.uint64)
+    rc = lib().or_flow_fields_f32(C.cast(arr1, C.c_void_p), C.cast(arr2, C.c_void_p), W, H, levels, iters, radius,
+                                  R_num, R_den, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]),
+                                  _p(out["cost_fwd"]), _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]),
+                                  _p(ne))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     out["n_evals"] = (int(ne[0]), int(ne[1]))

@@ -52,6 +52,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -118,6 +119,63 @@ uint32_t or_cost(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int 
     return s;
 }
 
+/* A matching error as an unsigned 32-bit key: the integer SAD itself, or
+ * the bit pattern of a non-negative float cost (non-negative IEEE-754
+ * singles order exactly like their bit patterns), so one schedule serves
+ * both data terms.  0xFFFFFFFF (UNSET) is above every such value. */
+typedef uint32_t (*or_cost_fn)(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx,
+                               int fy);
+
+static uint32_t cost_u8(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy)
+{
+    return or_cost((const uint8_t *)A, (const uint8_t *)B, W, H, n, r, x, y, fx, fy);
+}
+
+/* Learned-feature matching error (Sec. 3.5 learned data term, read as the
+ * sum of squared differences of 16-channel float features over the
+ * subsampled patch of Eq. 3, replicate border): one fused multiply-add per
+ * term in the order v, u, c, in single precision. */
+uint32_t or_cost_f32(const float *fa, const float *fb, int W, int H, int n, int r, int x, int y, int fx, int fy)
+{
+    float acc = 0.0f;
+    for (int v = -r; v <= r; ++v)
+        for (int u = -r; u <= r; ++u) {
+            int ax = clampi(x + n * u, 0, W - 1), ay = clampi(y + n * v, 0, H - 1);
+            int bx = clampi(x + fx + n * u, 0, W - 1), by = clampi(y + fy + n * v, 0, H - 1);
+            const float *a = fa + ((size_t)ay * W + ax) * 16;
+            const float *b = fb + ((size_t)by * W + bx) * 16;
+            for (int c = 0; c < 16; ++c) {
+                float d = a[c] - b[c];
+                acc = fmaf(d, d, acc);
+            }
+        }
+    uint32_t bits;
+    memcpy(&bits, &acc, sizeof bits);
+    return bits;
+}
+
+static uint32_t cost_f32(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy)
+{
+    return or_cost_f32((const float *)A, (const float *)B, W, H, n, r, x, y, fx, fy);
+}
+
+/* Learned features to bytes for the NN seed: with lo, hi the range of all
+ * values, q = clamp(rint((f - lo) * (255 / (hi - lo))), 0, 255) in single
+ * precision. */
+void or_quantize_u8(const float *f, int64_t count, uint8_t *q)
+{
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < count; ++i) {
+        lo = fminf(lo, f[i]);
+        hi = fmaxf(hi, f[i]);
+    }
+    float s = hi > lo ? 255.0f / (hi - lo) : 0.0f;
+    for (int64_t i = 0; i < count; ++i) {
+        float t = rintf((f[i] - lo) * s);
+        q[i] = (uint8_t)fminf(fmaxf(t, 0.0f), 255.0f);
+    }
+}
+
 /* Exact nearest neighbour (stands in for the kd-tree candidate set of
  * Sec. 3.1): for every cell of the grid of scale nc, the pixel q of image b
  * whose level-1 descriptor has the smallest squared L2 distance to the
@@ -152,8 +210,8 @@ void or_nn(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc,
 
 /* Initial flow of the coarsest scale (Eq. 1 / Eq. 4 with one candidate):
  * F(p) = q - p, cost = E_nc(p, F(p)). */
-void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
-                    int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+static void init_coarse_g(or_cost_fn E, const int32_t *best_idx, const void *Da, const void *Db, int W, int H,
+                          int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     for (int j = 0; j < Hc; ++j)
@@ -162,9 +220,15 @@ void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *D
             int qx = best_idx[k] % W, qy = best_idx[k] / W;
             flow[2 * k] = (int16_t)(qx - x);
             flow[2 * k + 1] = (int16_t)(qy - y);
-            cost[k] = or_cost(Da, Db, W, H, nc, r, x, y, qx - x, qy - y);
+            cost[k] = E(Da, Db, W, H, nc, r, x, y, qx - x, qy - y);
             *n_evals += 1;
         }
+}
+
+void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
+                    int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    init_coarse_g(cost_u8, best_idx, Da, Db, W, H, nc, r, flow, cost, n_evals);
 }
 
 /* Hand-over from scale 2n to scale n (Sec. 3.2): cell (i, j) with i and j
@@ -172,8 +236,8 @@ void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *D
  * its flow as a seed (flows are kept in full-resolution pixel units); its
  * cost is re-evaluated with E_n.  All other cells start UNSET and receive a
  * value in the first propagation step. */
-void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db,
-                   int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+static void seed_level_g(or_cost_fn E, const int16_t *cflow, const uint32_t *ccost, const void *Da, const void *Db,
+                         int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), Wc = ceil_div(W, 2 * n);
     for (int j = 0; j < Hn; ++j)
@@ -188,9 +252,15 @@ void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *D
             int fx = cflow[2 * kc], fy = cflow[2 * kc + 1];
             flow[2 * k] = (int16_t)fx;
             flow[2 * k + 1] = (int16_t)fy;
-            cost[k] = or_cost(Da, Db, W, H, n, r, i * n, j * n, fx, fy);
+            cost[k] = E(Da, Db, W, H, n, r, i * n, j * n, fx, fy);
             *n_evals += 1;
         }
+}
+
+void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db,
+                   int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    seed_level_g(cost_u8, cflow, ccost, Da, Db, W, H, n, r, flow, cost, n_evals);
 }
 
 /* Source cells of propagation direction d (Eq. 2 for d = 0; the other three
@@ -208,8 +278,8 @@ static void prop_sources(int d, int *hdi, int *vdj)
  * cells, by E_n with strict improvement.  Run as two half-sweeps: first all
  * cells with (i+j) odd, then all with (i+j) even; a cell only reads cells of
  * the other colour, so the result does not depend on the visiting order. */
-void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
-                  int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
+static void propagate_g(or_cost_fn E, const void *Da, const void *Db, int W, int H, int n, int r, int pass,
+                        int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
     prop_sources(pass & 3, &hdi, &vdj);
@@ -233,7 +303,7 @@ void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int
                     int fx = flow[2 * ks], fy = flow[2 * ks + 1];
                     if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
                     if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
-                    uint32_t e = or_cost(Da, Db, W, H, n, r, x, y, fx, fy);
+                    uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy);
                     cnt += 1;
                     if (e < bc) { bc = e; bfx = fx; bfy = fy; }
                 }
@@ -243,6 +313,12 @@ void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int
             }
         *n_evals += cnt;
     }
+}
+
+void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
+                  int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
+{
+    propagate_g(cost_u8, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
 }
 
 /* SplitMix64 output mixer (Steele, Lea, Flood 2014). */
@@ -274,9 +350,9 @@ void or_rs_offset(uint64_t seed, int stream, int level, int pass, int j, int i, 
 /* One random-search step (Sec. 3.1): every set cell tries its flow plus a
  * random offset and keeps it if E_n strictly decreases.  Offset (0, 0) and
  * targets outside the image are skipped. */
-void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int Rn,
-                      uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
-                      uint64_t *n_evals, int nthreads)
+static void random_search_g(or_cost_fn E, const void *Da, const void *Db, int W, int H, int n, int r, int Rn,
+                            uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
+                            uint64_t *n_evals, int nthreads)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n);
     uint64_t cnt = 0;
@@ -292,7 +368,7 @@ void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n,
             if (ox == 0 && oy == 0) continue;
             int fx = flow[2 * k] + ox, fy = flow[2 * k + 1] + oy;
             if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
-            uint32_t e = or_cost(Da, Db, W, H, n, r, x, y, fx, fy);
+            uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy);
             cnt += 1;
             if (e < cost[k]) {
                 cost[k] = e;
@@ -301,6 +377,13 @@ void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n,
             }
         }
     *n_evals += cnt;
+}
+
+void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int Rn,
+                      uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
+                      uint64_t *n_evals, int nthreads)
+{
+    random_search_g(cost_u8, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals, nthreads);
 }
 
 /* Forward-backward consistency (Sec. 3.7): keep pixel p of field a iff it is
@@ -326,9 +409,10 @@ void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, co
 int or_rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
 
 /* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b. */
-static void flow_one_direction(const uint8_t *const *Da, const uint8_t *const *Db, int W, int H, int L,
-                               int T, int r, int R_num, int R_den, uint64_t seed, int stream,
-                               int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
+static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
+                               const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
+                               uint64_t seed, int stream, int nthreads, int16_t *flow_out, uint32_t *cost_out,
+                               uint64_t *n_evals)
 {
     int nc = 1 << (L - 1);
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
@@ -341,21 +425,21 @@ static void flow_one_direction(const uint8_t *const *Da, const uint8_t *const *D
         fl[b] = (int16_t *)malloc(sizeof(int16_t) * 2 * cells0);
         co[b] = (uint32_t *)malloc(sizeof(uint32_t) * cells0);
     }
-    or_nn(Da[0], Db[0], W, H, nc, idx, dist, nthreads);
+    or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
     int cur = 0;
-    or_init_coarse(idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
+    init_coarse_g(E, idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
     for (int level = L - 1; level >= 0; --level) {
         int n = 1 << level;
         if (level < L - 1) {
-            or_seed_level(fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
+            seed_level_g(E, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
             cur ^= 1;
         }
         int Rn = or_rs_radius(n, R_num, R_den);
         for (int t = 0; t < T; ++t) {
-            or_propagate(Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
+            propagate_g(E, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
             if (t < T - 1)
-                or_random_search(Da[level], Db[level], W, H, n, r, Rn, seed, stream, level, t, fl[cur],
-                                 co[cur], n_evals, nthreads);
+                random_search_g(E, Da[level], Db[level], W, H, n, r, Rn, seed, stream, level, t, fl[cur],
+                                co[cur], n_evals, nthreads);
         }
     }
     memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells0);
@@ -390,13 +474,42 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
         or_descriptor(blur, W, H, n, D2[l]);
     }
     n_evals[0] = n_evals[1] = 0;
-    flow_one_direction((const uint8_t *const *)D1, (const uint8_t *const *)D2, W, H, L, T, r, R_num, R_den,
-                       seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
-    flow_one_direction((const uint8_t *const *)D2, (const uint8_t *const *)D1, W, H, L, T, r, R_num, R_den,
-                       seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+    flow_one_direction(cost_u8, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
+                       R_num, R_den, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+    flow_one_direction(cost_u8, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
+                       R_num, R_den, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
     free(blur);
+    return 0;
+}
+
+/* The same multi-scale schedule on learned float features: F1[l], F2[l] are
+ * the 16-channel float32 feature maps of scale 2^l of both images; the NN
+ * seed runs on their level-1 maps quantised to bytes (or_quantize_u8), the
+ * matching error is or_cost_f32 (costs are returned as float bit patterns).
+ */
+int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, int H, int L, int T, int r,
+                       int R_num, int R_den, double eps, uint64_t seed, int nthreads, int16_t *flow_fwd,
+                       int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd,
+                       uint8_t *keep_bwd, uint64_t *n_evals)
+{
+    if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
+        R_num < 0 || R_den < 1)
+        return 1;
+    size_t np = (size_t)W * H;
+    uint8_t *q1 = (uint8_t *)malloc(np * 16), *q2 = (uint8_t *)malloc(np * 16);
+    or_quantize_u8(F1[0], (int64_t)np * 16, q1);
+    or_quantize_u8(F2[0], (int64_t)np * 16, q2);
+    n_evals[0] = n_evals[1] = 0;
+    flow_one_direction(cost_f32, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
+                       R_den, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+    flow_one_direction(cost_f32, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
+                       R_den, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+    or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
+    if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
+    free(q1);
+    free(q2);
     return 0;
 }
