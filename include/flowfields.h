@@ -203,6 +203,79 @@ ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H
                           const int32_t *entries, int32_t count, const float *grad_cost, int64_t *acc_scratch,
                           float *grad_f1, float *grad_f2, void *stream);
 
+/* Workspace bytes of ff_flow_fields_f32 (host). */
+size_t ff_workspace_bytes_f32(int32_t W, int32_t H, const ff_params *params);
+
+/* The multi-scale Flow Fields schedule (Sec. 3.2) on learned features
+ * instead of the byte descriptors: feat1[l], feat2[l] (host arrays of
+ * `levels` device pointers) are float32 [H][W][16] feature maps of scale
+ * 2^l.  The NN seed runs on the level-1 maps quantised to bytes (as
+ * ff_quantize_u8) on int8 matrix cores; every other matching error is the
+ * float32 squared-difference patch cost of ff_cost_f32_fwd.  Costs are
+ * returned as the bit patterns of the float32 values (UNSET = 0xFFFFFFFF);
+ * the rest as ff_flow_fields. */
+ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat2, int32_t W, int32_t H,
+                             const ff_params *params, void *ws, size_t ws_bytes, int16_t *flow_fwd,
+                             int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd,
+                             uint8_t *keep_bwd, uint64_t *n_evals, void *stream);
+
+/* ---- learned descriptor network (DescNet) ---------------------------------
+ * Stands in for the CNN data term the paper reports (Sec. 3.5, results in
+ * Sec. 4.7): three 3x3 convolutions 1 -> 32 -> 32 -> 16, ReLU after the
+ * first two, "same" zero padding.  Activations are NHWC [B][H][W][C], bf16
+ * stored as uint16 bit patterns; weights [cout][9][cin] bf16, tap index
+ * 3*(dy+1) + (dx+1); matrix-core products with float32 accumulation.
+ * Supported (cin, cout): (1, 32), (32, 32), (32, 16), and (16, 32) for the
+ * data gradient of the last layer. */
+
+/* out[p][co] = bias[co] + sum_{tap, ci} w[co][tap][ci] * in[p + d(tap)][ci],
+ * then max(0, .) if relu; written as float32 and/or bf16 (either nullable,
+ * not both); bias nullable. */
+ff_status ff_conv3x3_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                         const uint16_t *w, const float *bias, int32_t relu, float *out_f32, uint16_t *out_bf16,
+                         void *stream);
+
+/* Gradient with respect to the input of a (cin -> cout) layer: the same
+ * convolution of gout ([B][H][W][cout] bf16) with the weights rotated by 180
+ * degrees and transposed (written to wflip_scratch, cin*9*cout bf16). */
+ff_status ff_conv3x3_bwd_data(const uint16_t *gout, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                              const uint16_t *w, uint16_t *wflip_scratch, float *gin_f32, uint16_t *gin_bf16,
+                              void *stream);
+
+/* Scratch bytes of ff_conv3x3_bwd_weight (host). */
+size_t ff_conv3x3_wgrad_scratch_bytes(int32_t B, int32_t H, int32_t cin, int32_t cout);
+
+/* gw[co][tap][ci] = sum_p gout[p][co] * in[p + d(tap)][ci], gbias[co] =
+ * sum_p gout[p][co] (gbias nullable), float32; per-row-band partial sums are
+ * added in a fixed order (deterministic).  in: bf16; gout: float32. */
+ff_status ff_conv3x3_bwd_weight(const uint16_t *in, const float *gout, int32_t B, int32_t H, int32_t W,
+                                int32_t cin, int32_t cout, float *scratch, size_t scratch_bytes, float *gw,
+                                float *gbias, void *stream);
+
+/* ReLU backward: out = grad where act > 0 (act = the layer's bf16 output;
+ * NULL passes grad through), written as float32 and/or bf16. */
+ff_status ff_relu_bwd(const uint16_t *act, const float *grad, int64_t count, float *grad_out,
+                      uint16_t *grad_out_bf16, void *stream);
+
+/* float32 -> bf16 (round to nearest even). */
+ff_status ff_f32_to_bf16(const float *x, int64_t count, uint16_t *y, void *stream);
+
+/* Network input from image bytes: v / 255 - 0.5 as bf16. */
+ff_status ff_image_to_bf16(const uint8_t *img, int64_t count, uint16_t *out, void *stream);
+
+/* One Adam step (Kingma and Ba 2015) on float32 parameters with bias
+ * correction for step >= 1; param_bf16 (nullable) receives the bf16 copy. */
+ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int32_t count, float lr,
+                       float beta1, float beta2, float eps, int32_t step, uint16_t *param_bf16, void *stream);
+
+/* Scratch bytes of ff_quantize_u8 (host). */
+size_t ff_quantize_scratch_bytes(void);
+
+/* Learned features to bytes for the matrix-core NN seed: with lo, hi the
+ * minimum and maximum over all `count` values, q = clamp(rint((f - lo) *
+ * (255 / (hi - lo))), 0, 255) in float32 (q = 0 if hi == lo). */
+ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream);
+
 /* Launch configuration (tile size, workgroup size, load unrolling) of the
  * temporally blocked level kernel that ff_flow_fields uses for patch radius 3
  * at scale n = 2^log2n, log2n in [0, 6].  A process-wide table (host),

@@ -439,6 +439,222 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
   return from_hip(ffh::launch_batch_consistency(st, params->eps, s));
 }
 
+// ---- Flow Fields on learned float features ----------------------------------
+
+struct LayoutF32 {
+  size_t q, qscratch, nb, keys, grids, evals, total;
+  size_t N, Npad, M;
+};
+
+static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
+  LayoutF32 l{};
+  l.N = (size_t)W * H;
+  l.Npad = (l.N + 31) & ~(size_t)31;
+  const int nc = 1 << (p->levels - 1);
+  l.M = (size_t)ceil_div(W, nc) * ceil_div(H, nc);
+  size_t off = 0;
+  l.q = off; off = align256(off + 2 * l.N * 16);
+  l.qscratch = off; off = align256(off + 2 * 512 * sizeof(float));
+  l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
+  l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
+  l.grids = off;
+  for (int lv = 1; lv < p->levels; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
+  l.evals = off; off = align256(off + 2 * sizeof(uint64_t));
+  l.total = off;
+  return l;
+}
+
+size_t ff_workspace_bytes_f32(int32_t W, int32_t H, const ff_params *params) {
+  if (!dims_ok(W, H) || !params_ok(params)) return 0;
+  return layout_f32(W, H, params).total;
+}
+
+ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat2, int32_t W, int32_t H,
+                             const ff_params *params, void *ws, size_t ws_bytes, int16_t *flow_fwd, int16_t *flow_bwd,
+                             uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd,
+                             uint64_t *n_evals, void *stream) {
+  if (!feat1 || !feat2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !dims_ok(W, H) ||
+      !params_ok(params) || !(params->eps >= 0.0f))
+    return FF_ERR_ARG;
+  const int L = params->levels, T = params->iters, r = params->radius;
+  for (int lv = 0; lv < L; ++lv)
+    if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
+  const LayoutF32 lay = layout_f32(W, H, params);
+  if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *base = static_cast<char *>(ws);
+  hipError_t e;
+  // bytes of the level-1 features for the matrix-core NN seed
+  uint8_t *q[2];
+  for (int im = 0; im < 2; ++im) {
+    q[im] = reinterpret_cast<uint8_t *>(base + lay.q) + (size_t)im * lay.N * 16;
+    float *qs = reinterpret_cast<float *>(base + lay.qscratch) + im * 512;
+    if ((e = ffh::launch_quantize(im ? feat2[0] : feat1[0], (long long)lay.N * 16, qs, q[im], s)) != hipSuccess)
+      return FF_ERR_LAUNCH;
+  }
+  uint64_t *evals = n_evals ? n_evals : reinterpret_cast<uint64_t *>(base + lay.evals);
+  if ((e = ffh::launch_fill_u64(evals, 0, 2, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  int32_t *gflow[kMaxLevels][2];
+  uint32_t *gcost[kMaxLevels][2];
+  gflow[0][0] = reinterpret_cast<int32_t *>(flow_fwd);
+  gflow[0][1] = reinterpret_cast<int32_t *>(flow_bwd);
+  gcost[0][0] = cost_fwd;
+  gcost[0][1] = cost_bwd;
+  size_t off = lay.grids;
+  for (int lv = 1; lv < L; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    for (int dr = 0; dr < 2; ++dr) {
+      gflow[lv][dr] = reinterpret_cast<int32_t *>(base + off) + (size_t)dr * 2 * cells;
+      gcost[lv][dr] = reinterpret_cast<uint32_t *>(gflow[lv][dr] + cells);
+    }
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
+  const int nc = 1 << (L - 1);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(base + lay.keys);
+  int32_t *nb = reinterpret_cast<int32_t *>(base + lay.nb);
+  ffh::NNArgs nn{};
+  nn.ndir = 2;
+  nn.W = W;
+  nn.H = H;
+  nn.nc = nc;
+  nn.Wc = ceil_div(W, nc);
+  nn.M = (int)lay.M;
+  nn.N = (int)lay.N;
+  for (int dr = 0; dr < 2; ++dr) nn.dir[dr] = {q[dr], q[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
+  if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  const float *const *feat[2] = {feat1, feat2};
+  ffh::LevelArgs a{};
+  a.ndir = 2;
+  a.fcost = 1;
+  a.W = W;
+  a.H = H;
+  a.radius = r;
+  a.seed = params->seed;
+  for (int dr = 0; dr < 2; ++dr) {
+    a.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
+    a.dir[dr].stream_id = dr;
+  }
+  for (int lv = L - 1; lv >= 0; --lv) {
+    const int n = 1 << lv;
+    a.n = n;
+    a.Wn = ceil_div(W, n);
+    a.Hn = ceil_div(H, n);
+    a.level = lv;
+    a.Rn = rs_radius(n, params->R_num, params->R_den);
+    for (int dr = 0; dr < 2; ++dr) {
+      a.dir[dr].Da = feat[dr][lv];
+      a.dir[dr].Db = feat[dr ^ 1][lv];
+      a.dir[dr].flow = gflow[lv][dr];
+      a.dir[dr].cost = gcost[lv][dr];
+      a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+      a.dir[dr].Dq1 = q[dr];
+      a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+      a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+    }
+    e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
+    if (e != hipSuccess) return FF_ERR_LAUNCH;
+    for (int t = 0; t < T; ++t) {
+      a.pass = t;
+      if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if (t < T - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    }
+  }
+  return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
+                                          keep_bwd, s));
+}
+
+// ---- learned descriptor network ------------------------------------------
+
+static bool conv_shape_ok(int B, int H, int W, int cin, int cout) {
+  return B >= 1 && dims_ok(W, H) && (long long)B * H * W < (1ll << 31) &&
+         ((cin == 1 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 16) ||
+          (cin == 16 && cout == 32));
+}
+
+ff_status ff_conv3x3_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                         const uint16_t *w, const float *bias, int32_t relu, float *out_f32, uint16_t *out_bf16,
+                         void *stream) {
+  if (!in || !w || (!out_f32 && !out_bf16) || !conv_shape_ok(B, H, W, cin, cout)) return FF_ERR_ARG;
+  ffh::ConvArgs a{};
+  a.in = in;
+  a.w = w;
+  a.bias = bias;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  a.cin = cin;
+  a.cout = cout;
+  a.relu = relu != 0;
+  a.out_f32 = out_f32;
+  a.out_bf16 = out_bf16;
+  return from_hip(ffh::launch_conv_fwd(a, (hipStream_t)stream));
+}
+
+ff_status ff_conv3x3_bwd_data(const uint16_t *gout, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                              const uint16_t *w, uint16_t *wflip_scratch, float *gin_f32, uint16_t *gin_bf16,
+                              void *stream) {
+  if (!gout || !w || !wflip_scratch || (!gin_f32 && !gin_bf16) || !conv_shape_ok(B, H, W, cout, cin))
+    return FF_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (ffh::launch_weight_flip(w, wflip_scratch, cin, cout, s) != hipSuccess) return FF_ERR_LAUNCH;
+  return ff_conv3x3_fwd(gout, B, H, W, cout, cin, wflip_scratch, nullptr, 0, gin_f32, gin_bf16, stream);
+}
+
+size_t ff_conv3x3_wgrad_scratch_bytes(int32_t B, int32_t H, int32_t cin, int32_t cout) {
+  if (B < 1 || H < 1) return 0;
+  return (size_t)ffh::wgrad_blocks(B, H) * (size_t)(cout * 9 * cin + cout) * sizeof(float);
+}
+
+ff_status ff_conv3x3_bwd_weight(const uint16_t *in, const float *gout, int32_t B, int32_t H, int32_t W, int32_t cin,
+                                int32_t cout, float *scratch, size_t scratch_bytes, float *gw, float *gbias,
+                                void *stream) {
+  if (!in || !gout || !scratch || !gw || !conv_shape_ok(B, H, W, cin, cout) || cin == 16) return FF_ERR_ARG;
+  if (scratch_bytes < ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout)) return FF_ERR_WORKSPACE;
+  ffh::ConvArgs a{};
+  a.in = in;
+  a.gout = gout;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  a.cin = cin;
+  a.cout = cout;
+  a.partial = scratch;
+  return from_hip(ffh::launch_wgrad(a, gw, gbias, (hipStream_t)stream));
+}
+
+ff_status ff_relu_bwd(const uint16_t *act, const float *grad, int64_t count, float *grad_out, uint16_t *grad_out_bf16,
+                      void *stream) {
+  if (!grad || (!grad_out && !grad_out_bf16) || count < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_relu_bwd(act, grad, grad_out, grad_out_bf16, count, (hipStream_t)stream));
+}
+
+ff_status ff_f32_to_bf16(const float *x, int64_t count, uint16_t *y, void *stream) {
+  if (!x || !y || count < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_f32_to_bf16(x, y, count, (hipStream_t)stream));
+}
+
+ff_status ff_image_to_bf16(const uint8_t *img, int64_t count, uint16_t *out, void *stream) {
+  if (!img || !out || count < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_image_to_bf16(img, out, count, (hipStream_t)stream));
+}
+
+ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int32_t count, float lr, float beta1,
+                       float beta2, float eps, int32_t step, uint16_t *param_bf16, void *stream) {
+  if (!param || !grad || !m || !v || count < 0 || step < 1 || !(lr >= 0.0f)) return FF_ERR_ARG;
+  return from_hip(ffh::launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, param_bf16,
+                                   (hipStream_t)stream));
+}
+
+size_t ff_quantize_scratch_bytes(void) { return 256 * 2 * sizeof(float); }
+
+ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream) {
+  if (!f || !scratch || !q || count < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_quantize(f, count, scratch, q, (hipStream_t)stream));
+}
+
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
 
 int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }

@@ -1,0 +1,335 @@
+// Learned descriptor network kernels: 3x3 convolutions in NHWC with bf16
+// operands and float32 accumulation on matrix cores, their backward passes,
+// the Adam update, and the quantisation of learned features to bytes.
+//
+// Convolution as an implicit GEMM: 32 output pixels x 32 output channels per
+// wave, K = 9 taps x Cin in chunks of 16 (one v_mfma_f32_32x32x16_bf16 per
+// chunk).  A lane holds 8 consecutive input channels of one tap of one pixel
+// (one 16-byte load, zero outside the image: "same" zero padding) and the
+// matching 8 weights of one output channel.  Layout: activations
+// [B][H][W][C], weights [Cout][9][Cin] (tap = 3 * (dy + 1) + (dx + 1)).
+//
+// The data gradient is the same convolution with the weights rotated by 180
+// degrees and transposed ([Cin][9][Cout]).  The weight gradient sums over
+// all pixels; each workgroup writes a partial sum of its rows and a second
+// kernel adds the partials in a fixed order, so it is deterministic.
+#include <algorithm>
+
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_fwd(ffh::ConvArgs a) {
+  static_assert(CIN == 1 || CIN % 16 == 0, "Cin must be 1 or a multiple of 16");
+  static_assert(COUT <= 32, "Cout <= 32");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, kh = lane >> 5;
+  const long long P = (long long)a.B * a.H * a.W;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * 32;
+  if (p0 >= P) return;  // wave-uniform
+  const long long p = p0 + row;
+  const bool pv = p < P;
+  const int x = pv ? (int)(p % a.W) : 0, y = pv ? (int)((p / a.W) % a.H) : 0;
+  const long long img = pv ? p / ((long long)a.W * a.H) : 0;
+  const uint16_t *in = a.in;
+  const int col = row;  // output channel held by this lane in the B operand
+  f32x16 acc = {0};
+  if constexpr (CIN == 1) {
+    // K = 9 taps padded to 16: lane half kh holds taps 8*kh .. 8*kh+7
+    uint16_t av[8], bv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int tap = 8 * kh + e;
+      uint16_t va = 0, vb = 0;
+      if (tap < 9) {
+        const int sx = x + tap % 3 - 1, sy = y + tap / 3 - 1;
+        if (pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+          va = in[((img * a.H + sy) * a.W + sx)];
+        if (col < COUT) vb = a.w[col * 9 + tap];
+      }
+      av[e] = va;
+      bv[e] = vb;
+    }
+    uint4 ua, ub;
+    __builtin_memcpy(&ua, av, 16);
+    __builtin_memcpy(&ub, bv, 16);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int sx = x + tap % 3 - 1, sy = y + tap / 3 - 1;
+      const bool sv = pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H;
+      // addresses stay inside the buffers even for lanes whose value is zeroed
+      const int cx = ffk::clampi(sx, a.W - 1), cy = ffk::clampi(sy, a.H - 1);
+      const uint4 *src = reinterpret_cast<const uint4 *>(in + ((img * a.H + cy) * a.W + cx) * CIN);
+      const uint4 *wsrc = reinterpret_cast<const uint4 *>(a.w + ((size_t)min(col, COUT - 1) * 9 + tap) * CIN);
+#pragma unroll
+      for (int cc = 0; cc < CIN / 16; ++cc) {
+        const uint4 ua = sv ? src[cc * 2 + kh] : make_uint4(0, 0, 0, 0);
+        const uint4 ub = col < COUT ? wsrc[cc * 2 + kh] : make_uint4(0, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
+      }
+    }
+  }
+  if (col >= COUT) return;
+  const float bias = a.bias ? a.bias[col] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const long long q = p0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+    if (q >= P) continue;
+    float v = acc[r] + bias;
+    if (a.relu) v = fmaxf(v, 0.0f);
+    if (a.out_f32) a.out_f32[q * COUT + col] = v;
+    if (a.out_bf16) a.out_bf16[q * COUT + col] = f32_to_bf16(v);
+  }
+}
+
+// W'[ci][tap][co] = W[co][8 - tap][ci]
+__global__ __launch_bounds__(256) void k_flip(const uint16_t *w, uint16_t *wf, int cin, int cout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cin * 9 * cout) return;
+  const int co = i % cout, tap = (i / cout) % 9, ci = i / (cout * 9);
+  wf[i] = w[((size_t)co * 9 + (8 - tap)) * cin + ci];
+}
+
+// Partial weight and bias gradients of one row band: item = (image, row).
+// Thread t accumulates output channels co = t % COUT and input channels
+// ci = t / COUT + k * (256 / COUT) for all 9 taps.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad_partial(ffh::ConvArgs a, int rows_per_block) {
+  constexpr int TPC = 256 / COUT;                  // threads per output channel
+  constexpr int CPT = (CIN + TPC - 1) / TPC;       // input channels per thread
+  __shared__ float s_g[64][COUT];
+  __shared__ float s_in[3][66][CIN];
+  const int tid = threadIdx.x, co = tid % COUT, cg = tid / COUT;
+  float acc[9][CPT];
+  float bacc = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) acc[t][k] = 0.0f;
+  const int nrows = a.B * a.H;
+  const int r0 = blockIdx.x * rows_per_block, r1 = min(r0 + rows_per_block, nrows);
+  for (int rr = r0; rr < r1; ++rr) {
+    const int img = rr / a.H, y = rr % a.H;
+    for (int x0 = 0; x0 < a.W; x0 += 64) {
+      __syncthreads();
+      for (int k = tid; k < 64 * COUT; k += 256) {
+        const int px = k / COUT, c = k % COUT, x = x0 + px;
+        s_g[px][c] = x < a.W ? a.gout[(((long long)img * a.H + y) * a.W + x) * COUT + c] : 0.0f;
+      }
+      for (int k = tid; k < 3 * 66 * CIN; k += 256) {
+        const int c = k % CIN, xx = (k / CIN) % 66, dy = k / (CIN * 66);
+        const int sx = x0 + xx - 1, sy = y + dy - 1;
+        float v = 0.0f;
+        if (sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+          v = bf16_to_f32(a.in[(((long long)img * a.H + sy) * a.W + sx) * CIN + c]);
+        s_in[dy][xx][c] = v;
+      }
+      __syncthreads();
+      const int np = min(64, a.W - x0);
+      for (int px = 0; px < np; ++px) {
+        const float g = s_g[px][co];
+        if (cg == 0) bacc += g;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            const int ci = cg + k * TPC;
+            if (ci < CIN) acc[t][k] = __fmaf_rn(g, s_in[t / 3][px + t % 3][ci], acc[t][k]);
+          }
+      }
+    }
+  }
+  float *part = a.partial + (size_t)blockIdx.x * (COUT * 9 * CIN + COUT);
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int ci = cg + k * TPC;
+      if (ci < CIN) part[((size_t)co * 9 + t) * CIN + ci] = acc[t][k];
+    }
+  if (cg == 0) part[COUT * 9 * CIN + co] = bacc;
+}
+
+// Sum of the partials in block order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, int nblocks, int len, float *gw,
+                                                      float *gbias, int nw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * len + i];
+  if (i < nw) gw[i] = s; else if (gbias) gbias[i - nw] = s;
+}
+
+// grad_pre = grad_post where the post-activation is positive, else 0; also
+// the bf16 copy for the next matrix-core pass.
+__global__ __launch_bounds__(256) void k_relu_bwd(const uint16_t *act, const float *g, float *gout, uint16_t *gout_bf16,
+                                                  long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float v = (act == nullptr || bf16_to_f32(act[i]) > 0.0f) ? g[i] : 0.0f;
+  if (gout) gout[i] = v;
+  if (gout_bf16) gout_bf16[i] = f32_to_bf16(v);
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float *x, uint16_t *y, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = f32_to_bf16(x[i]);
+}
+
+// Image bytes -> network input v / 255 - 0.5 (bf16).
+__global__ __launch_bounds__(256) void k_image_to_bf16(const uint8_t *img, uint16_t *out, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = f32_to_bf16((float)img[i] * (1.0f / 255.0f) - 0.5f);
+}
+
+// Adam (Kingma and Ba 2015) with bias correction; writes the bf16 copy.
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int count, float lr,
+                                              float b1, float b2, float eps, float c1, float c2, uint16_t *p_bf16) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  if (p_bf16) p_bf16[i] = f32_to_bf16(pi);
+}
+
+// Per-map range of float features (block partials, then one block).
+__global__ __launch_bounds__(256) void k_minmax_partial(const float *f, long long count, float *part) {
+  __shared__ float s_lo[256], s_hi[256];
+  float lo = INFINITY, hi = -INFINITY;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long long)gridDim.x * 256) {
+    lo = fminf(lo, f[i]);
+    hi = fmaxf(hi, f[i]);
+  }
+  s_lo[threadIdx.x] = lo;
+  s_hi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + s]);
+      s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s_lo[0];
+    part[2 * blockIdx.x + 1] = s_hi[0];
+  }
+}
+
+// q = clamp(rint((f - lo) * (255 / (hi - lo))), 0, 255); the range is the
+// min and max over the partials (order-independent).
+__global__ __launch_bounds__(256) void k_quantize(const float *f, long long count, const float *part, int nparts,
+                                                  uint8_t *q) {
+  float lo = INFINITY, hi = -INFINITY;
+  for (int k = 0; k < nparts; ++k) {
+    lo = fminf(lo, part[2 * k]);
+    hi = fmaxf(hi, part[2 * k + 1]);
+  }
+  const float s = hi > lo ? 255.0f / (hi - lo) : 0.0f;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float t = rintf((f[i] - lo) * s);
+  q[i] = (uint8_t)fminf(fmaxf(t, 0.0f), 255.0f);
+}
+
+}  // namespace
+
+namespace ffh {
+
+static unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t stream) {
+  const long long P = (long long)a.B * a.H * a.W;
+  const unsigned grid = (unsigned)((P + 127) / 128);
+  if (P == 0) return hipSuccess;
+  if (a.cin == 1 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<1, 32>), dim3(grid), dim3(256), 0, stream, a);
+  else if (a.cin == 32 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<32, 32>), dim3(grid), dim3(256), 0, stream, a);
+  else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_conv_fwd<32, 16>), dim3(grid), dim3(256), 0, stream, a);
+  else if (a.cin == 16 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<16, 32>), dim3(grid), dim3(256), 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_flip(const uint16_t *w, uint16_t *wf, int cin, int cout, hipStream_t stream) {
+  hipLaunchKernelGGL(k_flip, dim3(blocks_of((long long)cin * 9 * cout)), dim3(256), 0, stream, w, wf, cin, cout);
+  return hipGetLastError();
+}
+
+int wgrad_blocks(int B, int H) { return std::min(B * H, 1024); }
+
+hipError_t launch_wgrad(const ConvArgs &a, float *gw, float *gbias, hipStream_t stream) {
+  const int nrows = a.B * a.H, nb = wgrad_blocks(a.B, a.H);
+  const int rpb = (nrows + nb - 1) / nb;
+  const int used = (nrows + rpb - 1) / rpb;
+  if (a.cin == 1 && a.cout == 32) hipLaunchKernelGGL((k_wgrad_partial<1, 32>), dim3(used), dim3(256), 0, stream, a, rpb);
+  else if (a.cin == 32 && a.cout == 32) hipLaunchKernelGGL((k_wgrad_partial<32, 32>), dim3(used), dim3(256), 0, stream, a, rpb);
+  else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_wgrad_partial<32, 16>), dim3(used), dim3(256), 0, stream, a, rpb);
+  else return hipErrorInvalidValue;
+  const int nw = a.cout * 9 * a.cin, len = nw + a.cout;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_of(len)), dim3(256), 0, stream, a.partial, used, len, gw, gbias, nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_bwd(const uint16_t *act, const float *g, float *gout, uint16_t *gout_bf16, long long count,
+                           hipStream_t stream) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_of(count)), dim3(256), 0, stream, act, g, gout, gout_bf16, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, long long count, hipStream_t stream) {
+  if (count > 0) hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_of(count)), dim3(256), 0, stream, x, y, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_to_bf16(const uint8_t *img, uint16_t *out, long long count, hipStream_t stream) {
+  if (count > 0) hipLaunchKernelGGL(k_image_to_bf16, dim3(blocks_of(count)), dim3(256), 0, stream, img, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, float lr, float b1, float b2,
+                       float eps, int step, uint16_t *p_bf16, hipStream_t stream) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  if (count > 0)
+    hipLaunchKernelGGL(k_adam, dim3(blocks_of(count)), dim3(256), 0, stream, p, g, m, v, count, lr, b1, b2, eps, c1,
+                       c2, p_bf16);
+  return hipGetLastError();
+}
+
+constexpr int kQuantParts = 256;
+
+hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_minmax_partial, dim3(kQuantParts), dim3(256), 0, stream, f, count, part);
+  hipLaunchKernelGGL(k_quantize, dim3(blocks_of(count)), dim3(256), 0, stream, f, count, part, kQuantParts, q);
+  return hipGetLastError();
+}
+
+}  // namespace ffh

@@ -75,6 +75,63 @@ __device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const 
   c2 = s2;
 }
 
+// Matching-error policies of the per-step kernels.  Both return a 32-bit
+// key: the integer SAD of 16-byte descriptors, or the bit pattern of the
+// non-negative float32 sum of squared differences of 16-channel float
+// features (one fused multiply-add per term, order v, u, c), which orders
+// exactly like the float values.
+struct CostU8 {
+  template <int R>
+  __device__ static uint32_t eval(const void *Da, const void *Db, int W, int H, int n, int x, int y, int fx,
+                                  int fy) {
+    return patch_cost<R>(static_cast<const uint4 *>(Da), static_cast<const uint4 *>(Db), W, H, n, x, y, fx, fy);
+  }
+  template <int R>
+  __device__ static void eval2(const void *Da, const void *Db, int W, int H, int n, int x, int y, int f1x, int f1y,
+                               bool en1, int f2x, int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
+    patch_cost2<R>(static_cast<const uint4 *>(Da), static_cast<const uint4 *>(Db), W, H, n, x, y, f1x, f1y, en1, f2x,
+                   f2y, en2, c1, c2);
+  }
+};
+
+struct CostF32 {
+  template <int R>
+  __device__ static uint32_t eval(const void *Da, const void *Db, int W, int H, int n, int x, int y, int fx,
+                                  int fy) {
+    const float4 *fa = static_cast<const float4 *>(Da), *fb = static_cast<const float4 *>(Db);
+    const int Wm = W - 1, Hm = H - 1;
+    float acc = 0.0f;
+#pragma unroll 1
+    for (int v = -R; v <= R; ++v) {
+      const size_t ra = (size_t)clampi(y + n * v, Hm) * W, rb = (size_t)clampi(y + fy + n * v, Hm) * W;
+#pragma unroll
+      for (int u = -R; u <= R; ++u) {
+        const float4 *a = fa + (ra + clampi(x + n * u, Wm)) * 4;
+        const float4 *b = fb + (rb + clampi(x + fx + n * u, Wm)) * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float4 p = a[k], q = b[k];
+          float d = p.x - q.x;
+          acc = __fmaf_rn(d, d, acc);
+          d = p.y - q.y;
+          acc = __fmaf_rn(d, d, acc);
+          d = p.z - q.z;
+          acc = __fmaf_rn(d, d, acc);
+          d = p.w - q.w;
+          acc = __fmaf_rn(d, d, acc);
+        }
+      }
+    }
+    return __float_as_uint(acc);
+  }
+  template <int R>
+  __device__ static void eval2(const void *Da, const void *Db, int W, int H, int n, int x, int y, int f1x, int f1y,
+                               bool en1, int f2x, int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
+    c1 = en1 ? eval<R>(Da, Db, W, H, n, x, y, f1x, f1y) : 0u;
+    c2 = en2 ? eval<R>(Da, Db, W, H, n, x, y, f2x, f2y) : 0u;
+  }
+};
+
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

@@ -45,8 +45,8 @@ hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
 
 // Per-direction state of a level grid.
 struct LevelDir {
-  const uint8_t *Da;   // scale-n descriptors of the source image
-  const uint8_t *Db;   // scale-n descriptors of the target image
+  const void *Da;      // scale-n descriptors (or float features) of the source image
+  const void *Db;      // scale-n descriptors (or float features) of the target image
   int32_t *flow;       // packed (dx, dy) int16 pairs, [cells]
   uint32_t *cost;      // [cells]
   const int32_t *cflow;   // coarser grid (seeding only)
@@ -59,6 +59,7 @@ struct LevelDir {
 struct LevelArgs {
   LevelDir dir[kMaxDirs];
   int ndir;
+  int fcost;  // 0: byte descriptors, SAD; 1: float32 16-channel features, SSD
   int W, H, n, Wn, Hn, radius;
   int Rn, level, pass;
   uint64_t seed;
@@ -152,6 +153,29 @@ struct CostArgs {
 };
 hipError_t launch_cost_fwd(const CostArgs &a, hipStream_t stream);
 hipError_t launch_cost_bwd(const CostArgs &a, hipStream_t stream);
+
+// 3x3 convolution, NHWC bf16 activations, weights [cout][9][cin] bf16.
+struct ConvArgs {
+  const uint16_t *in;  // [B][H][W][cin] bf16
+  const uint16_t *w;   // [cout][9][cin] bf16
+  const float *bias;   // [cout] (nullable)
+  int B, H, W, cin, cout, relu;
+  float *out_f32;      // [B][H][W][cout] (nullable)
+  uint16_t *out_bf16;  // [B][H][W][cout] (nullable)
+  const float *gout;   // weight gradient: upstream gradient [B][H][W][cout] f32
+  float *partial;      // weight gradient: per-block partial sums
+};
+hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t stream);
+hipError_t launch_weight_flip(const uint16_t *w, uint16_t *wf, int cin, int cout, hipStream_t stream);
+int wgrad_blocks(int B, int H);
+hipError_t launch_wgrad(const ConvArgs &a, float *gw, float *gbias, hipStream_t stream);
+hipError_t launch_relu_bwd(const uint16_t *act, const float *g, float *gout, uint16_t *gout_bf16, long long count,
+                           hipStream_t stream);
+hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, long long count, hipStream_t stream);
+hipError_t launch_image_to_bf16(const uint8_t *img, uint16_t *out, long long count, hipStream_t stream);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, float lr, float b1, float b2,
+                       float eps, int step, uint16_t *p_bf16, hipStream_t stream);
+hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream);
 
 // Consistency of field a against field b (full resolution).
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,

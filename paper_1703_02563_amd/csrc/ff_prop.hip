@@ -26,7 +26,7 @@ namespace {
 using ffk::clampi;
 using ffk::kUnset;
 
-template <int R>
+template <int R, class Cost>
 __global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
   const ffh::LevelDir d = a.dir[blockIdx.z];
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,14 +51,14 @@ __global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
     const_cast<uint64_t *>(d.nn_key)[m] = ((uint64_t)(uint32_t)(dd + na) << 32) | q;
     const int fx = (int)(q % (uint32_t)a.W) - x, fy = (int)(q / (uint32_t)a.W) - y;
     d.flow[m] = ffk::pack_flow(fx, fy);
-    d.cost[m] = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db),
+    d.cost[m] = Cost::template eval<R>(d.Da, d.Db,
                                    a.W, a.H, a.n, x, y, fx, fy);
     cnt = 1;
   }
   ffk::wave_count_add(d.n_evals, cnt);
 }
 
-template <int R>
+template <int R, class Cost>
 __global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
   const ffh::LevelDir d = a.dir[blockIdx.z];
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
       const int kc = (j >> 1) * Wc + (i >> 1);
       if (d.ccost[kc] != kUnset) {
         f = d.cflow[kc];
-        c = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db),
+        c = Cost::template eval<R>(d.Da, d.Db,
                                a.W, a.H, a.n, i * a.n, j * a.n, ffk::flow_x(f), ffk::flow_y(f));
         cnt = 1;
       }
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
 
 // Half-sweep of colour `colour` ((i + j) & 1 == colour) of propagation step
 // `a.pass`.  Grid: x over half-columns, y over rows, z over directions.
-template <int R>
+template <int R, class Cost>
 __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour) {
   const ffh::LevelDir d = a.dir[blockIdx.z];
   const int kx = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
     const bool vcomp = vb && !(hv && fv == fh) && !(set0 && fv == f0);
     uint32_t eh = 0, ev = 0;
     if (hv || vcomp)
-      ffk::patch_cost2<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db), W, H, n,
+      Cost::template eval2<R>(d.Da, d.Db, W, H, n,
                           x, y, ffk::flow_x(fh), ffk::flow_y(fh), hv, ffk::flow_x(fv), ffk::flow_y(fv), vcomp,
                           eh, ev);
     uint32_t bc = c0;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
         e = ev;
       else  // fv == f0 after the horizontal source replaced it; the stored
             // cost of a caller-made state need not equal E(p, f0)
-        e = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da), reinterpret_cast<const uint4 *>(d.Db), W, H,
+        e = Cost::template eval<R>(d.Da, d.Db, W, H,
                                n, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
       if (e < bc) { bc = e; bf = fv; }
     }
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
   ffk::wave_count_add(d.n_evals, cnt);
 }
 
-template <int R>
+template <int R, class Cost>
 __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
   const ffh::LevelDir d = a.dir[blockIdx.z];
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -179,8 +179,7 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
       const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
       const int x = i * a.n, y = j * a.n;
       if ((ox | oy) != 0 && x + fx >= 0 && x + fx < a.W && y + fy >= 0 && y + fy < a.H) {
-        const uint32_t e = ffk::patch_cost<R>(reinterpret_cast<const uint4 *>(d.Da),
-                                              reinterpret_cast<const uint4 *>(d.Db), a.W, a.H, a.n, x, y, fx, fy);
+        const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.n, x, y, fx, fy);
         cnt = 1;
         if (e < c0) {
           d.cost[k] = e;
@@ -243,17 +242,23 @@ __global__ __launch_bounds__(256) void k_consistency_batch(ffh::BatchStage st, d
   });
 }
 
-#define FF_RADIUS_SWITCH(R_, CALL)                                              \
+#define FF_RADIUS_SWITCH_C(R_, CALL, C_)                                        \
   switch (R_) {                                                                 \
-    case 0: CALL(0); break;                                                     \
-    case 1: CALL(1); break;                                                     \
-    case 2: CALL(2); break;                                                     \
-    case 3: CALL(3); break;                                                     \
-    case 4: CALL(4); break;                                                     \
-    case 5: CALL(5); break;                                                     \
-    case 6: CALL(6); break;                                                     \
-    case 7: CALL(7); break;                                                     \
+    case 0: CALL(0, C_); break;                                                 \
+    case 1: CALL(1, C_); break;                                                 \
+    case 2: CALL(2, C_); break;                                                 \
+    case 3: CALL(3, C_); break;                                                 \
+    case 4: CALL(4, C_); break;                                                 \
+    case 5: CALL(5, C_); break;                                                 \
+    case 6: CALL(6, C_); break;                                                 \
+    case 7: CALL(7, C_); break;                                                 \
     default: return hipErrorInvalidValue;                                       \
+  }
+#define FF_RADIUS_SWITCH(A_, CALL)                                              \
+  if ((A_).fcost) {                                                             \
+    FF_RADIUS_SWITCH_C((A_).radius, CALL, ffk::CostF32)                         \
+  } else {                                                                      \
+    FF_RADIUS_SWITCH_C((A_).radius, CALL, ffk::CostU8)                          \
   }
 
 }  // namespace
@@ -263,8 +268,8 @@ namespace ffh {
 hipError_t launch_init_coarse(const LevelArgs &a, hipStream_t stream) {
   const int cells = a.Wn * a.Hn;
   dim3 grid((cells + 255) / 256, 1, a.ndir);
-#define CALL(R) hipLaunchKernelGGL(k_init_coarse<R>, grid, dim3(256), 0, stream, a)
-  FF_RADIUS_SWITCH(a.radius, CALL)
+#define CALL(R, C) hipLaunchKernelGGL((k_init_coarse<R, C>), grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a, CALL)
 #undef CALL
   return hipGetLastError();
 }
@@ -272,8 +277,8 @@ hipError_t launch_init_coarse(const LevelArgs &a, hipStream_t stream) {
 hipError_t launch_seed_level(const LevelArgs &a, hipStream_t stream) {
   const int cells = a.Wn * a.Hn;
   dim3 grid((cells + 255) / 256, 1, a.ndir);
-#define CALL(R) hipLaunchKernelGGL(k_seed_level<R>, grid, dim3(256), 0, stream, a)
-  FF_RADIUS_SWITCH(a.radius, CALL)
+#define CALL(R, C) hipLaunchKernelGGL((k_seed_level<R, C>), grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a, CALL)
 #undef CALL
   return hipGetLastError();
 }
@@ -282,8 +287,8 @@ hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream) {
   const int half = (a.Wn + 1) / 2;
   dim3 grid((half + 63) / 64, (a.Hn + 3) / 4, a.ndir);
   for (int colour = 1; colour >= 0; --colour) {
-#define CALL(R) hipLaunchKernelGGL(k_prop_half<R>, grid, dim3(256), 0, stream, a, colour)
-    FF_RADIUS_SWITCH(a.radius, CALL)
+#define CALL(R, C) hipLaunchKernelGGL((k_prop_half<R, C>), grid, dim3(256), 0, stream, a, colour)
+    FF_RADIUS_SWITCH(a, CALL)
 #undef CALL
   }
   return hipGetLastError();
@@ -291,8 +296,8 @@ hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream) {
 
 hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream) {
   dim3 grid((a.Wn + 63) / 64, (a.Hn + 3) / 4, a.ndir);
-#define CALL(R) hipLaunchKernelGGL(k_random_search<R>, grid, dim3(256), 0, stream, a)
-  FF_RADIUS_SWITCH(a.radius, CALL)
+#define CALL(R, C) hipLaunchKernelGGL((k_random_search<R, C>), grid, dim3(256), 0, stream, a)
+  FF_RADIUS_SWITCH(a, CALL)
 #undef CALL
   return hipGetLastError();
 }

@@ -55,6 +55,19 @@ _SIGS = {
                                _P]),
     "ff_cost_f32_fwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "ff_cost_f32_bwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),
+    "ff_conv3x3_fwd": (C.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _P, _P, _I32, _P, _P, _P]),
+    "ff_conv3x3_bwd_data": (C.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P]),
+    "ff_conv3x3_wgrad_scratch_bytes": (C.c_size_t, [_I32, _I32, _I32, _I32]),
+    "ff_conv3x3_bwd_weight": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, C.c_size_t, _P, _P, _P]),
+    "ff_relu_bwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
+    "ff_f32_to_bf16": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "ff_image_to_bf16": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "ff_adam_step": (C.c_int, [_P, _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float, _I32, _P, _P]),
+    "ff_quantize_scratch_bytes": (C.c_size_t, []),
+    "ff_quantize_u8": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "ff_workspace_bytes_f32": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
+    "ff_flow_fields_f32": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P,
+                                     _P, _P, _P]),
     "ff_level_variant_count": (C.c_int32, []),
     "ff_get_level_variant": (C.c_int32, [_I32]),
     "ff_set_level_variant": (C.c_int, [_I32, _I32]),

@@ -58,3 +58,231 @@ class PatchCost(torch.autograd.Function):
 
 def patch_cost(f1, f2, entries, n: int = 1, radius: int = 3):
     return PatchCost.apply(f1, f2, entries, n, radius)
+
+
+# ---------------------------------------------------------------------------
+# DescNet: three 3x3 convolutions 1 -> 32 -> 32 -> 16 (ReLU after the first
+# two), bf16 weights and activations, float32 accumulation, all passes in the
+# library's kernels.  Float32 master weights, Adam in a kernel.
+# ---------------------------------------------------------------------------
+
+import ctypes as _C
+import math as _math
+
+LAYERS = ((1, 32, True), (32, 32, True), (32, 16, False))
+
+
+def _bf16_bits(t: torch.Tensor) -> torch.Tensor:
+    """float32 tensor -> uint16 bit patterns of its bf16 rounding (kernel)."""
+    t = t.contiguous().float()
+    out = torch.empty(t.shape, dtype=torch.int16, device=t.device)
+    check(lib().ff_f32_to_bf16(_ptr(t, torch.float32), t.numel(), _ptr(out), _stream()), "ff_f32_to_bf16")
+    return out
+
+
+def bf16_bits_to_f32(bits: torch.Tensor) -> torch.Tensor:
+    """uint16 bf16 bit patterns (int16 tensor) -> float32 (exact)."""
+    return (bits.to(torch.int32) << 16).view(torch.float32)
+
+
+class DescNet:
+    """Weights, Adam state and the forward/backward passes of the network."""
+
+    def __init__(self, seed: int = 0, device="cuda"):
+        g = torch.Generator().manual_seed(seed)
+        self.device = torch.device(device)
+        self.w, self.b = [], []
+        for cin, cout, _ in LAYERS:
+            std = _math.sqrt(2.0 / (9 * cin))
+            self.w.append((torch.randn((cout, 9, cin), generator=g) * std).float().to(self.device))
+            self.b.append(torch.zeros(cout, dtype=torch.float32, device=self.device))
+        self.m = [torch.zeros_like(t) for t in self.w + self.b]
+        self.v = [torch.zeros_like(t) for t in self.w + self.b]
+        self.step = 0
+        self._sync_bf16()
+
+    def _sync_bf16(self):
+        self.wb = [_bf16_bits(w) for w in self.w]
+
+    def state_dict(self):
+        return {"w": [w.cpu() for w in self.w], "b": [b.cpu() for b in self.b], "step": self.step}
+
+    def load_state_dict(self, sd):
+        self.w = [w.to(self.device).float() for w in sd["w"]]
+        self.b = [b.to(self.device).float() for b in sd["b"]]
+        self.step = int(sd.get("step", 0))
+        self._sync_bf16()
+
+    def input_from_images(self, imgs: torch.Tensor) -> torch.Tensor:
+        """uint8 [B, H, W] -> bf16 bits [B, H, W, 1] (v / 255 - 0.5)."""
+        imgs = imgs.contiguous()
+        out = torch.empty(imgs.shape + (1,), dtype=torch.int16, device=imgs.device)
+        check(lib().ff_image_to_bf16(_ptr(imgs, torch.uint8), imgs.numel(), _ptr(out), _stream()), "ff_image_to_bf16")
+        return out
+
+    def forward(self, x_bits: torch.Tensor, keep: bool = False):
+        """x_bits: bf16 bits [B, H, W, 1]; returns float32 features [B, H, W, 16]
+        (and the bf16 activations of every layer input when keep=True)."""
+        B, H, W, _ = x_bits.shape
+        acts = [x_bits]
+        out = None
+        for k, (cin, cout, relu) in enumerate(LAYERS):
+            last = k == len(LAYERS) - 1
+            o32 = torch.empty((B, H, W, cout), dtype=torch.float32, device=x_bits.device) if last else None
+            o16 = None if last else torch.empty((B, H, W, cout), dtype=torch.int16, device=x_bits.device)
+            check(lib().ff_conv3x3_fwd(_ptr(acts[-1]), B, H, W, cin, cout, _ptr(self.wb[k]), _ptr(self.b[k]),
+                                       int(relu), _ptr(o32), _ptr(o16), _stream()), "ff_conv3x3_fwd")
+            if last:
+                out = o32
+            else:
+                acts.append(o16)
+        return (out, acts) if keep else out
+
+    def backward(self, acts, grad_out: torch.Tensor):
+        """Gradients (w, b) of all layers for upstream float32 grad_out
+        [B, H, W, 16] of the features."""
+        B, H, W, _ = grad_out.shape
+        gws, gbs = [None] * 3, [None] * 3
+        g32 = grad_out.contiguous().float()
+        for k in range(len(LAYERS) - 1, -1, -1):
+            cin, cout, relu = LAYERS[k]
+            nbytes = int(lib().ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout))
+            scratch = torch.empty(nbytes // 4, dtype=torch.float32, device=grad_out.device)
+            gw = torch.empty((cout, 9, cin), dtype=torch.float32, device=grad_out.device)
+            gb = torch.empty(cout, dtype=torch.float32, device=grad_out.device)
+            check(lib().ff_conv3x3_bwd_weight(_ptr(acts[k]), _ptr(g32, torch.float32), B, H, W, cin, cout,
+                                              _ptr(scratch), nbytes, _ptr(gw), _ptr(gb), _stream()),
+                  "ff_conv3x3_bwd_weight")
+            gws[k], gbs[k] = gw, gb
+            if k == 0:
+                break
+            # gradient of the layer input, then through the previous ReLU
+            g16 = _bf16_bits(g32)
+            flip = torch.empty((cin, 9, cout), dtype=torch.int16, device=grad_out.device)
+            gin = torch.empty((B, H, W, cin), dtype=torch.float32, device=grad_out.device)
+            check(lib().ff_conv3x3_bwd_data(_ptr(g16), B, H, W, cin, cout, _ptr(self.wb[k]), _ptr(flip), _ptr(gin),
+                                            None, _stream()), "ff_conv3x3_bwd_data")
+            g32 = torch.empty_like(gin)
+            check(lib().ff_relu_bwd(_ptr(acts[k]), _ptr(gin, torch.float32), gin.numel(), _ptr(g32), None,
+                                    _stream()), "ff_relu_bwd")
+        return gws, gbs
+
+    def adam(self, gws, gbs, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        params = self.w + self.b
+        grads = gws + gbs
+        for k, (p, g) in enumerate(zip(params, grads)):
+            wbits = self.wb[k] if k < len(self.w) else None
+            g = g.contiguous()  # named, so the buffer outlives the launch
+            check(lib().ff_adam_step(_ptr(p, torch.float32), _ptr(g, torch.float32), _ptr(self.m[k]),
+                                     _ptr(self.v[k]), p.numel(), lr, b1, b2, eps, self.step, _ptr(wbits), _stream()),
+                  "ff_adam_step")
+
+    def features(self, img: torch.Tensor) -> torch.Tensor:
+        """uint8 [H, W] -> float32 [H, W, 16]."""
+        return self.forward(self.input_from_images(img[None]))[0]
+
+
+def triplets(flow: torch.Tensor, keep: torch.Tensor, count: int, rng: "np.random.Generator"):
+    """Anchors p among the pixels kept by the plain consistency check,
+    positive p + F(p), negative = positive + an offset of Chebyshev radius
+    2..8 px (in-image).  Returns int32 [count, 4] entries (x, y, fx, fy) for
+    the positive and the negative."""
+    import numpy as np
+    H, W = keep.shape
+    k = keep.cpu().numpy().astype(bool)
+    f = flow.cpu().numpy().astype(np.int64)
+    ys, xs = np.nonzero(k)
+    if len(xs) == 0:
+        raise ValueError("no consistent matches")
+    sel = rng.integers(0, len(xs), size=count * 2)
+    xs, ys = xs[sel], ys[sel]
+    fx, fy = f[ys, xs, 0], f[ys, xs, 1]
+    ox = rng.integers(-8, 9, size=len(xs))
+    oy = rng.integers(-8, 9, size=len(xs))
+    cheb = np.maximum(np.abs(ox), np.abs(oy))
+    ok = (cheb >= 2) & (xs + fx + ox >= 0) & (xs + fx + ox < W) & (ys + fy + oy >= 0) & (ys + fy + oy < H)
+    idx = np.nonzero(ok)[0][:count]
+    pos = np.stack([xs[idx], ys[idx], fx[idx], fy[idx]], 1).astype(np.int32)
+    neg = np.stack([xs[idx], ys[idx], fx[idx] + ox[idx], fy[idx] + oy[idx]], 1).astype(np.int32)
+    return pos, neg
+
+
+def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.0, lr: float = 1e-3):
+    """One Adam step of the triplet hinge max(0, margin + C(p, pos) - C(p, neg))
+    averaged over anchors of every pair in `batch` = [(img1, img2, flow, keep)]
+    with the plain method's flows and consistency masks."""
+    B = len(batch)
+    H, W = batch[0][0].shape
+    imgs = torch.stack([b[0] for b in batch] + [b[1] for b in batch])   # [2B, H, W]
+    feats, acts = net.forward(net.input_from_images(imgs), keep=True)
+    feats = feats.detach().requires_grad_(True)
+    loss = 0.0
+    total = 0
+    for k, (_, _, flow, keep) in enumerate(batch):
+        pos, neg = triplets(flow, keep, samples, rng)
+        if len(pos) == 0:
+            continue
+        pe = torch.from_numpy(pos).to(feats.device)
+        ne = torch.from_numpy(neg).to(feats.device)
+        cp = patch_cost(feats[k], feats[B + k], pe, 1, 3)
+        cn = patch_cost(feats[k], feats[B + k], ne, 1, 3)
+        loss = loss + torch.relu(margin + cp - cn).sum()
+        total += len(pos)
+    loss = loss / max(total, 1)
+    loss.backward()
+    gws, gbs = net.backward(acts, feats.grad)
+    net.adam(gws, gbs, lr=lr)
+    return float(loss.detach())
+
+
+def learned_flow_fields(net: DescNet, img1: torch.Tensor, img2: torch.Tensor, params, blurred=None) -> dict:
+    """Flow Fields on DescNet features of the scale-space images I^n
+    (ff_flow_fields_f32).  Returns the same keys as flow_fields; costs are
+    float32 bit patterns."""
+    from .flowfields import descriptors
+    H, W = img1.shape
+    L = params.levels
+    if blurred is None:
+        blurred = [(descriptors(img1, 1 << lv)[0], descriptors(img2, 1 << lv)[0]) for lv in range(L)]
+    f1 = [net.features(b[0]).contiguous() for b in blurred]
+    f2 = [net.features(b[1]).contiguous() for b in blurred]
+    return flow_fields_f32(f1, f2, params)
+
+
+def flow_fields_f32(f1, f2, params) -> dict:
+    """ff_flow_fields_f32 on per-scale float32 feature maps [H, W, 16]."""
+    H, W, _ = f1[0].shape
+    L = params.levels
+    cp = params.to_c()
+    dev = f1[0].device
+    nbytes = int(lib().ff_workspace_bytes_f32(W, H, cp))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = {
+        "flow_fwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
+        "flow_bwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
+        "cost_fwd": torch.empty((H, W), dtype=torch.int32, device=dev),
+        "cost_bwd": torch.empty((H, W), dtype=torch.int32, device=dev),
+        "keep_fwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
+        "keep_bwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
+        "n_evals": torch.zeros(2, dtype=torch.int64, device=dev),
+    }
+    a1 = (_C.c_void_p * L)(*[t.data_ptr() for t in f1])
+    a2 = (_C.c_void_p * L)(*[t.data_ptr() for t in f2])
+    for t in list(f1) + list(f2):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (H, W, 16):
+            raise ValueError("features must be contiguous float32 CUDA tensors [H, W, 16]")
+    check(lib().ff_flow_fields_f32(_C.cast(a1, _C.c_void_p), _C.cast(a2, _C.c_void_p), W, H, cp, _ptr(ws),
+                                   ws.numel(), _ptr(out["flow_fwd"]), _ptr(out["flow_bwd"]), _ptr(out["cost_fwd"]),
+                                   _ptr(out["cost_bwd"]), _ptr(out["keep_fwd"]), _ptr(out["keep_bwd"]),
+                                   _ptr(out["n_evals"]), _stream()), "ff_flow_fields_f32")
+    return out
+
+
+def quantize_u8(f: torch.Tensor) -> torch.Tensor:
+    f = f.contiguous()
+    q = torch.empty(f.shape, dtype=torch.uint8, device=f.device)
+    scratch = torch.empty(int(lib().ff_quantize_scratch_bytes()) // 4, dtype=torch.float32, device=f.device)
+    check(lib().ff_quantize_u8(_ptr(f, torch.float32), f.numel(), _ptr(scratch), _ptr(q), _stream()),
+          "ff_quantize_u8")
+    return q

@@ -1,0 +1,29 @@
+"""Float64 reference of the descriptor network (torch.nn.functional.conv2d),
+optionally rounding to bfloat16 where the GPU kernels round."""
+import torch
+import torch.nn.functional as F
+
+LAYERS = ((1, 32, True), (32, 32, True), (32, 16, False))
+
+
+def torch_weight(w):
+    """[cout][9][cin] (tap = 3*ky + kx) -> conv2d layout [cout][cin][3][3]."""
+    cout, _, cin = w.shape
+    return w.reshape(cout, 3, 3, cin).permute(0, 3, 1, 2)
+
+
+def bf16(t):
+    return t.to(torch.bfloat16).to(t.dtype)
+
+
+def forward(x, ws, bs, round_bf16=False):
+    """x: [B, H, W, 1] -> features [B, H, W, 16] (float64)."""
+    h = x.permute(0, 3, 1, 2)
+    for k, (cin, cout, relu) in enumerate(LAYERS):
+        w = torch_weight(bf16(ws[k]) if round_bf16 else ws[k])
+        h = F.conv2d(h, w, bs[k], padding=1)
+        if relu:
+            h = torch.relu(h)
+        if round_bf16 and k < len(LAYERS) - 1:
+            h = bf16(h)
+    return h.permute(0, 2, 3, 1)

@@ -1,0 +1,226 @@
+"""Learned-descriptor form on the GPU: convolution kernels against float64
+torch.nn.functional.conv2d and its autograd, the whole network's gradient
+against the float64 reference (bf16 rounding emulated where the kernels
+round) and float64 finite differences, Adam against its formula, the
+quantiser and the learned-feature Flow Fields against the oracle bit for
+bit, and a short training run."""
+import os
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle
+import paper_1703_02563_amd as ff
+from descnet_ref import LAYERS, bf16, forward, torch_weight
+from paper_1703_02563_amd import learned as Lm
+from test_learned_oracle import feature_canvas, feature_pyramid
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+
+
+def bits(t64):
+    """float64 CPU tensor of bf16-representable values -> bf16 bit patterns on the GPU."""
+    return Lm._bf16_bits(t64.float().cuda())
+
+
+def _rand(shape, seed, scale=1.0):
+    g = torch.Generator().manual_seed(seed)
+    return bf16(torch.randn(shape, generator=g, dtype=torch.float64) * scale)
+
+
+# float32 accumulation of K bf16 x bf16 products (exact in float32):
+# |err| <= K * 2^-24 * sum|products|
+def _bound(x, w, K):
+    return K * 2.0 ** -24 * F.conv2d(x.abs(), w.abs(), padding=1) + 1e-6
+
+
+@pytest.mark.parametrize("cin,cout", [(1, 32), (32, 32), (32, 16), (16, 32)])
+@pytest.mark.parametrize("B,H,W", [(1, 37, 53), (2, 16, 70), (1, 1, 1)])
+def test_conv_forward_matches_f64(cin, cout, B, H, W):
+    x = _rand((B, H, W, cin), 10 + cin + H)
+    w = _rand((cout, 9, cin), 20 + cout, (2.0 / (9 * cin)) ** 0.5)
+    b = torch.randn(cout, generator=torch.Generator().manual_seed(3), dtype=torch.float64) * 0.1
+    # every device argument is a named tensor: a temporary would be freed and
+    # its memory reused for the next argument before the kernel runs
+    xd, wd, bd = bits(x), bits(w), b.float().cuda()
+    for relu in (0, 1):
+        out = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+        ff.ffi.check(ff.lib().ff_conv3x3_fwd(Lm._ptr(xd), B, H, W, cin, cout, Lm._ptr(wd), Lm._ptr(bd), relu,
+                                             Lm._ptr(out), None, Lm._stream()), "ff_conv3x3_fwd")
+        xt, wt = x.permute(0, 3, 1, 2), torch_weight(w)
+        ref = F.conv2d(xt, wt, b.float().double(), padding=1)
+        if relu:
+            ref = torch.relu(ref)
+        tol = _bound(xt, wt, 9 * cin)
+        got = out.cpu().double().permute(0, 3, 1, 2)
+        assert torch.all((got - ref).abs() <= tol), float(((got - ref).abs() - tol).max())
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 16)])
+def test_conv_data_and_weight_gradients_match_f64_autograd(cin, cout):
+    B, H, W = 2, 23, 41
+    x = _rand((B, H, W, cin), 5)
+    w = _rand((cout, 9, cin), 6, (2.0 / (9 * cin)) ** 0.5)
+    go = _rand((B, H, W, cout), 7)
+    xt = x.permute(0, 3, 1, 2).clone().requires_grad_(True)
+    wt = torch_weight(w).clone().requires_grad_(True)
+    bt = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    (F.conv2d(xt, wt, bt, padding=1) * go.permute(0, 3, 1, 2)).sum().backward()
+    # data gradient
+    xd, wd, god, go32 = bits(x), bits(w), bits(go), go.float().cuda()
+    flip = torch.empty((cin, 9, cout), dtype=torch.int16, device="cuda")
+    gin = torch.empty((B, H, W, cin), dtype=torch.float32, device="cuda")
+    ff.ffi.check(ff.lib().ff_conv3x3_bwd_data(Lm._ptr(god), B, H, W, cin, cout, Lm._ptr(wd), Lm._ptr(flip),
+                                              Lm._ptr(gin), None, Lm._stream()), "ff_conv3x3_bwd_data")
+    ref = xt.grad.permute(0, 2, 3, 1)
+    tol = 9 * cout * 2.0 ** -24 * F.conv2d(go.abs().permute(0, 3, 1, 2),
+                                            torch_weight(w).abs().flip(2, 3).transpose(0, 1),
+                                            padding=1).permute(0, 2, 3, 1) + 1e-6
+    assert torch.all((gin.cpu().double() - ref).abs() <= tol)
+    # weight and bias gradients (float32 sums over all pixels)
+    nbytes = int(ff.lib().ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout))
+    scratch = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    gw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+    ff.ffi.check(ff.lib().ff_conv3x3_bwd_weight(Lm._ptr(xd), Lm._ptr(go32), B, H, W, cin, cout,
+                                                Lm._ptr(scratch), nbytes, Lm._ptr(gw), Lm._ptr(gb), Lm._stream()),
+                 "ff_conv3x3_bwd_weight")
+    gw_ref = wt.grad.permute(0, 2, 3, 1).reshape(cout, 9, cin)
+    P = B * H * W
+    absw = torch.zeros_like(gw_ref)  # sum |g * x| per weight, the accumulation error scale
+    xa = F.pad(x.abs().permute(0, 3, 1, 2), (1, 1, 1, 1))
+    for tap in range(9):
+        ky, kx = tap // 3, tap % 3
+        xs = xa[:, :, ky:ky + H, kx:kx + W]
+        absw[:, tap, :] = torch.einsum("bchw,bdhw->dc", xs, go.abs().permute(0, 3, 1, 2))
+    assert torch.all((gw.cpu().double() - gw_ref).abs() <= P * 2.0 ** -24 * absw + 1e-6)
+    assert torch.allclose(gb.cpu().double(), bt.grad, rtol=0, atol=P * 2.0 ** -24 * float(go.abs().sum()) + 1e-6)
+
+
+def test_wgrad_is_deterministic():
+    B, H, W, cin, cout = 4, 64, 96, 32, 32
+    x = bits(_rand((B, H, W, cin), 8))
+    go = _rand((B, H, W, cout), 9).float().cuda()
+    nbytes = int(ff.lib().ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout))
+    outs = []
+    for _ in range(2):
+        scratch = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        gw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+        ff.ffi.check(ff.lib().ff_conv3x3_bwd_weight(Lm._ptr(x), Lm._ptr(go), B, H, W, cin, cout, Lm._ptr(scratch),
+                                                    nbytes, Lm._ptr(gw), None, Lm._stream()), "wgrad")
+        outs.append(gw.cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
+def _net_and_crop(seed=0):
+    net = Lm.DescNet(seed=seed)
+    g = torch.Generator().manual_seed(seed + 1)
+    for k in range(3):  # non-zero biases exercise the bias gradient
+        net.b[k] = (torch.randn(net.b[k].shape, generator=g) * 0.1).cuda()
+    img = (torch.rand((1, 48, 64), generator=g) * 255).round().to(torch.uint8)
+    return net, img
+
+
+def test_network_gradient_matches_f64_reference():
+    """GPU forward/backward vs float64 autograd with the same bf16 roundings,
+    and vs float64 central differences of the unrounded network (64x48)."""
+    net, img = _net_and_crop()
+    x_bits = net.input_from_images(img.cuda())
+    feats, acts = net.forward(x_bits, keep=True)
+    probe = torch.randn((1, 48, 64, 16), generator=torch.Generator().manual_seed(5), dtype=torch.float64)
+    gws, gbs = net.backward(acts, probe.float().cuda())
+    x64 = Lm.bf16_bits_to_f32(x_bits).cpu().double()
+    ws = [w.cpu().double().requires_grad_(True) for w in net.w]
+    bs = [b.cpu().double().requires_grad_(True) for b in net.b]
+    ref = forward(x64, ws, bs, round_bf16=True)
+    # forward: identical bf16 roundings except where float32 sums straddle a rounding boundary
+    rel = float((feats.cpu().double() - ref.detach()).norm() / ref.detach().norm())
+    assert rel < 2e-3, rel
+    (ref * probe).sum().backward()
+    for k in range(3):
+        rw = float((gws[k].cpu().double() - ws[k].grad).norm() / ws[k].grad.norm())
+        rb = float((gbs[k].cpu().double() - bs[k].grad).norm() / bs[k].grad.norm())
+        assert rw < 2e-2 and rb < 2e-2, (k, rw, rb)
+    # central differences of the float64 network at the bf16 weights
+    w64 = [bf16(w.detach()) for w in ws]
+    b64 = [b.detach() for b in bs]
+    rng = np.random.default_rng(7)
+    h = 1e-4
+    for k in range(3):
+        errs, mags = [], []
+        for _ in range(8):
+            idx = tuple(int(rng.integers(0, s)) for s in w64[k].shape)
+            wp = [w.clone() for w in w64]
+            wm = [w.clone() for w in w64]
+            wp[k][idx] += h
+            wm[k][idx] -= h
+            num = float(((forward(x64, wp, b64) - forward(x64, wm, b64)) * probe).sum() / (2 * h))
+            errs.append(abs(num - float(gws[k][idx])))
+            mags.append(abs(num))
+        assert max(errs) <= 0.05 * max(max(mags), 1.0), (k, errs, mags)
+
+
+def test_adam_step_matches_formula():
+    n = 1000
+    g = torch.Generator().manual_seed(2)
+    p0 = torch.randn(n, generator=g)
+    grads = [torch.randn(n, generator=g) for _ in range(3)]
+    p = p0.clone().cuda()
+    m = torch.zeros(n, device="cuda")
+    v = torch.zeros(n, device="cuda")
+    pr, mr, vr = p0.double().numpy(), np.zeros(n), np.zeros(n)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t, gr in enumerate(grads, start=1):
+        grd = gr.cuda()
+        ff.ffi.check(ff.lib().ff_adam_step(Lm._ptr(p), Lm._ptr(grd), Lm._ptr(m), Lm._ptr(v), n, lr, b1, b2, eps,
+                                           t, None, Lm._stream()), "adam")
+        gd = gr.double().numpy()
+        mr = b1 * mr + (1 - b1) * gd
+        vr = b2 * vr + (1 - b2) * gd * gd
+        pr = pr - lr * (mr / (1 - b1 ** t)) / (np.sqrt(vr / (1 - b2 ** t)) + eps)
+    assert np.allclose(p.cpu().double().numpy(), pr, rtol=0, atol=1e-6)
+
+
+def test_quantize_matches_oracle():
+    f = feature_canvas(3, 40, 60)
+    q = Lm.quantize_u8(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert np.array_equal(q, oracle.quantize_u8(f))
+
+
+@pytest.mark.parametrize("shape,L,T", [((40, 56), 3, 4), ((33, 1), 2, 3), ((1, 1), 1, 1), ((120, 160), 3, 4),
+                                       ((61, 95), 4, 5)])
+def test_learned_flow_fields_bit_exact(shape, L, T):
+    H, W = shape
+    pad = 10
+    canvas = feature_canvas(11 + H, H + 2 * pad, W + 2 * pad)
+    F1 = canvas[pad:pad + H, pad:pad + W].copy()
+    F2 = canvas[pad - 3:pad - 3 + H, pad + 2:pad + 2 + W].copy() + feature_canvas(12, H, W) * 0.05
+    m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
+    prm = ff.Params(levels=L, iters=T)
+    o = oracle.flow_fields_f32(m1, m2, L, T, nthreads=NT)
+    g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2], prm)
+    torch.cuda.synchronize()
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(g[k].cpu().numpy(), o[k]), k
+    for k in ("cost_fwd", "cost_bwd"):
+        assert np.array_equal(g[k].cpu().numpy().view(np.uint32), o[k]), k
+    assert tuple(int(v) for v in g["n_evals"].cpu()) == o["n_evals"]
+
+
+def test_training_reduces_the_triplet_loss():
+    from ffgen import make_pair
+    net = Lm.DescNet(seed=0)
+    prm = ff.Params(levels=3, iters=4)
+    batch = []
+    for k in range(4):
+        p = make_pair(5, k, shape=(96, 128))
+        i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+        o = ff.flow_fields(i1, i2, prm)
+        batch.append((i1, i2, o["flow_fwd"], o["keep_fwd"]))
+    rng = np.random.default_rng(0)
+    losses = [Lm.train_step(net, batch, rng, samples=512, lr=3e-3) for _ in range(40)]
+    assert np.isfinite(losses).all()
+    assert np.mean(losses[-5:]) < 0.8 * np.mean(losses[:5]), losses
