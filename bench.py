@@ -138,6 +138,79 @@ def batched_throughput(ff, torch, reps):
             "mpix_per_s": round(mpix / dt, 2), "graph": True}
 
 
+def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
+    """DescNet trained on the plain method's consistent matches (16 training
+    pairs of the learned workload), judged by ground-truth EPE on two held-out
+    pairs against the plain field (fallback to plain when it is worse), then
+    timed on the 1024x436 pair: descriptor network on every scale image of
+    both images + learned-feature fields fwd+bwd + consistency."""
+    import numpy as np
+
+    from ffgen import epe_stats, make_pair
+    from paper_1703_02563_amd import learned as Lm
+
+    def dev_pair(cfg, k):
+        p = make_pair(cfg, k)
+        return p, torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+
+    batch = []
+    for k in range(args.train_pairs):
+        _, i1, i2 = dev_pair(5, k)
+        o = ff.flow_fields(i1, i2, params)
+        batch.append((i1, i2, Lm.TripletSampler(o["flow_fwd"], o["keep_fwd"])))
+    net = Lm.DescNet(seed=0)
+    rng = np.random.default_rng(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for s in range(args.train_steps):
+        losses.append(Lm.train_step(net, batch, rng, samples=args.train_samples, lr=args.train_lr))
+        if (s + 1) % 20 == 0:
+            log(f"bench: learned training step {s + 1} loss {losses[-1]:.4f}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def epe(o, p):
+        return epe_stats(o["flow_fwd"].cpu().numpy(), p.flow_gt, p.occ, keep=o["keep_fwd"].cpu().numpy())
+
+    val_plain, val_learned = [], []
+    for k in range(args.val_pairs):
+        p, i1, i2 = dev_pair(5, args.train_pairs + k)
+        val_plain.append(epe(ff.flow_fields(i1, i2, params), p)["epe"])
+        val_learned.append(epe(Lm.learned_flow_fields(net, i1, i2, params), p)["epe"])
+    fallback = float(np.mean(val_learned)) > float(np.mean(val_plain))
+
+    run = lambda: Lm.learned_flow_fields(net, img1, img2, params)  # noqa: E731
+    for _ in range(2):
+        run()
+    torch.cuda.synchronize()
+    reps = max(3, min(args.steps, 20))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    scales = Lm.scale_images(img1, img2, params.levels)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        Lm.learned_features(net, scales)
+    e1.record()
+    torch.cuda.synchronize()
+    net_ms = e0.elapsed_time(e1) / reps
+    q = epe(out, pair)
+    H, W = img1.shape
+    return {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 3),
+            "descnet_ms": round(net_ms, 3), "ratio_vs_plain": round(plain_ms / ms, 4),
+            "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4), "kept_epe": round(q["kept_epe"], 4),
+            "kept_density": round(q["kept_density"], 4),
+            "val_epe_plain": [round(v, 4) for v in val_plain], "val_epe_learned": [round(v, 4) for v in val_learned],
+            "fallback_to_plain": fallback, "train_pairs": args.train_pairs, "train_steps": args.train_steps,
+            "train_samples_per_pair": args.train_samples, "train_s": round(train_s, 2),
+            "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)] if losses else None,
+            "dtype": "bf16 network, f32 cost"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +218,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-pair measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-descriptor measurement")
+    ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--val-pairs", type=int, default=4, help="held-out pairs of the EPE judge")
+    ap.add_argument("--train-pairs", type=int, default=16)
+    ap.add_argument("--train-samples", type=int, default=1024, help="triplets per training pair and step")
+    ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -204,6 +283,12 @@ def main():
         batched = batched_throughput(ff, torch, reps=5)
         log(f"bench: batched {batched}")
 
+    learned = None
+    if not args.no_learned:
+        log(f"bench: learned descriptors ({args.train_steps} training steps on {args.train_pairs} pairs)")
+        learned = learned_leg(ff, torch, img1, img2, params, pair, ms, args)
+        log(f"bench: learned {learned}")
+
     log("bench: roofline of the scale-1 level kernel")
     roof = roofline_level0(ff, torch, img1, img2, params, reps=20)
     log(f"bench: roofline {roof}")
@@ -223,7 +308,7 @@ def main():
                    "W": W, "H": H, "levels": c.levels, "iters": c.iters, "R": f"{c.R_num}/{c.R_den}",
                    "n_evals": n_evals, "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                    "epe10": round(q["epe10"], 4), "kept_density": round(q["kept_density"], 4),
-                   "kept_epe": round(q["kept_epe"], 4), "batched": batched},
+                   "kept_epe": round(q["kept_epe"], 4), "batched": batched, "learned": learned},
         "roofline": roof,
         "cpu_baseline": base,
     }

@@ -263,6 +263,17 @@ ff_status ff_f32_to_bf16(const float *x, int64_t count, uint16_t *y, void *strea
 /* Network input from image bytes: v / 255 - 0.5 as bf16. */
 ff_status ff_image_to_bf16(const uint8_t *img, int64_t count, uint16_t *out, void *stream);
 
+/* Unit length per pixel of 16-channel float32 features [pixels][16]
+ * (16-byte aligned): out = feat / sqrt(|feat|^2 + delta), delta > 0;
+ * inv_norm (nullable, [pixels]) receives 1 / sqrt(|feat|^2 + delta) for the
+ * backward pass.  out may alias feat. */
+ff_status ff_l2norm16_fwd(const float *feat, int64_t pixels, float delta, float *out, float *inv_norm, void *stream);
+
+/* Backward of ff_l2norm16_fwd: grad_in = inv_norm * (grad - out * <grad, out>)
+ * per pixel; grad_in may alias grad. */
+ff_status ff_l2norm16_bwd(const float *out, const float *inv_norm, const float *grad, int64_t pixels,
+                          float *grad_in, void *stream);
+
 /* One Adam step (Kingma and Ba 2015) on float32 parameters with bias
  * correction for step >= 1; param_bf16 (nullable) receives the bf16 copy. */
 ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int32_t count, float lr,

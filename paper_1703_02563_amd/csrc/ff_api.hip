@@ -568,6 +568,8 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
 
 // ---- learned descriptor network ------------------------------------------
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 static bool conv_shape_ok(int B, int H, int W, int cin, int cout) {
   return B >= 1 && dims_ok(W, H) && (long long)B * H * W < (1ll << 31) &&
          ((cin == 1 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 16) ||
@@ -646,6 +648,19 @@ ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int3
   if (!param || !grad || !m || !v || count < 0 || step < 1 || !(lr >= 0.0f)) return FF_ERR_ARG;
   return from_hip(ffh::launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, param_bf16,
                                    (hipStream_t)stream));
+}
+
+ff_status ff_l2norm16_fwd(const float *feat, int64_t pixels, float delta, float *out, float *inv_norm, void *stream) {
+  if (!feat || !out || pixels < 0 || !(delta > 0.0f) || !aligned16(feat) || !aligned16(out)) return FF_ERR_ARG;
+  return from_hip(ffh::launch_l2norm16_fwd(feat, pixels, delta, out, inv_norm, (hipStream_t)stream));
+}
+
+ff_status ff_l2norm16_bwd(const float *out, const float *inv_norm, const float *grad, int64_t pixels, float *grad_in,
+                          void *stream) {
+  if (!out || !inv_norm || !grad || !grad_in || pixels < 0 || !aligned16(out) || !aligned16(grad) ||
+      !aligned16(grad_in))
+    return FF_ERR_ARG;
+  return from_hip(ffh::launch_l2norm16_bwd(out, inv_norm, grad, pixels, grad_in, (hipStream_t)stream));
 }
 
 size_t ff_quantize_scratch_bytes(void) { return 256 * 2 * sizeof(float); }

@@ -219,6 +219,44 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m
   if (p_bf16) p_bf16[i] = f32_to_bf16(pi);
 }
 
+// Unit length per pixel of 16-channel features: y = f / sqrt(|f|^2 + delta).
+__global__ __launch_bounds__(256) void k_l2norm16_fwd(const float4 *f, long long P, float delta, float4 *y,
+                                                      float *inv_norm) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float4 v[4];
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = f[p * 4 + k];
+    s += v[k].x * v[k].x + v[k].y * v[k].y + v[k].z * v[k].z + v[k].w * v[k].w;
+  }
+  const float r = 1.0f / sqrtf(s + delta);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) y[p * 4 + k] = make_float4(v[k].x * r, v[k].y * r, v[k].z * r, v[k].w * r);
+  if (inv_norm) inv_norm[p] = r;
+}
+
+// dL/df = r * (g - y * <g, y>) with r = 1 / sqrt(|f|^2 + delta).
+__global__ __launch_bounds__(256) void k_l2norm16_bwd(const float4 *y, const float *inv_norm, const float4 *g,
+                                                      long long P, float4 *gin) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float4 yv[4], gv[4];
+  float d = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    yv[k] = y[p * 4 + k];
+    gv[k] = g[p * 4 + k];
+    d += yv[k].x * gv[k].x + yv[k].y * gv[k].y + yv[k].z * gv[k].z + yv[k].w * gv[k].w;
+  }
+  const float r = inv_norm[p];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    gin[p * 4 + k] = make_float4(r * (gv[k].x - yv[k].x * d), r * (gv[k].y - yv[k].y * d),
+                                 r * (gv[k].z - yv[k].z * d), r * (gv[k].w - yv[k].w * d));
+}
+
 // Per-map range of float features (block partials, then one block).
 __global__ __launch_bounds__(256) void k_minmax_partial(const float *f, long long count, float *part) {
   __shared__ float s_lo[256], s_hi[256];
@@ -320,6 +358,22 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, 
   if (count > 0)
     hipLaunchKernelGGL(k_adam, dim3(blocks_of(count)), dim3(256), 0, stream, p, g, m, v, count, lr, b1, b2, eps, c1,
                        c2, p_bf16);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2norm16_fwd(const float *f, long long P, float delta, float *y, float *inv_norm,
+                               hipStream_t stream) {
+  if (P > 0)
+    hipLaunchKernelGGL(k_l2norm16_fwd, dim3(blocks_of(P)), dim3(256), 0, stream, reinterpret_cast<const float4 *>(f),
+                       P, delta, reinterpret_cast<float4 *>(y), inv_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2norm16_bwd(const float *y, const float *inv_norm, const float *g, long long P, float *gin,
+                               hipStream_t stream) {
+  if (P > 0)
+    hipLaunchKernelGGL(k_l2norm16_bwd, dim3(blocks_of(P)), dim3(256), 0, stream, reinterpret_cast<const float4 *>(y),
+                       inv_norm, reinterpret_cast<const float4 *>(g), P, reinterpret_cast<float4 *>(gin));
   return hipGetLastError();
 }
 

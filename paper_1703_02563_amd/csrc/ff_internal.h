@@ -173,6 +173,10 @@ hipError_t launch_relu_bwd(const uint16_t *act, const float *g, float *gout, uin
                            hipStream_t stream);
 hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, long long count, hipStream_t stream);
 hipError_t launch_image_to_bf16(const uint8_t *img, uint16_t *out, long long count, hipStream_t stream);
+hipError_t launch_l2norm16_fwd(const float *f, long long P, float delta, float *y, float *inv_norm,
+                               hipStream_t stream);
+hipError_t launch_l2norm16_bwd(const float *y, const float *inv_norm, const float *g, long long P, float *gin,
+                               hipStream_t stream);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, float lr, float b1, float b2,
                        float eps, int step, uint16_t *p_bf16, hipStream_t stream);
 hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream);

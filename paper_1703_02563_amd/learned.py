@@ -88,9 +88,12 @@ def bf16_bits_to_f32(bits: torch.Tensor) -> torch.Tensor:
 class DescNet:
     """Weights, Adam state and the forward/backward passes of the network."""
 
-    def __init__(self, seed: int = 0, device="cuda"):
+    def __init__(self, seed: int = 0, device="cuda", normalize: bool = True, delta: float = 1e-4):
         g = torch.Generator().manual_seed(seed)
         self.device = torch.device(device)
+        # unit-length output features: the triplet margin then has a fixed
+        # scale (squared distances per pixel in [0, 4])
+        self.normalize, self.delta = normalize, float(delta)
         self.w, self.b = [], []
         for cin, cout, _ in LAYERS:
             std = _math.sqrt(2.0 / (9 * cin))
@@ -136,6 +139,11 @@ class DescNet:
                 out = o32
             else:
                 acts.append(o16)
+        if self.normalize:
+            inv = torch.empty((B, H, W), dtype=torch.float32, device=x_bits.device)
+            check(lib().ff_l2norm16_fwd(_ptr(out), out.numel() // 16, self.delta, _ptr(out), _ptr(inv), _stream()),
+                  "ff_l2norm16_fwd")
+            acts.append((out, inv))
         return (out, acts) if keep else out
 
     def backward(self, acts, grad_out: torch.Tensor):
@@ -144,6 +152,12 @@ class DescNet:
         B, H, W, _ = grad_out.shape
         gws, gbs = [None] * 3, [None] * 3
         g32 = grad_out.contiguous().float()
+        if self.normalize:
+            y, inv = acts[len(LAYERS)]
+            gn = torch.empty_like(g32)
+            check(lib().ff_l2norm16_bwd(_ptr(y), _ptr(inv), _ptr(g32, torch.float32), g32.numel() // 16, _ptr(gn),
+                                        _stream()), "ff_l2norm16_bwd")
+            g32 = gn
         for k in range(len(LAYERS) - 1, -1, -1):
             cin, cout, relu = LAYERS[k]
             nbytes = int(lib().ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout))
@@ -183,51 +197,85 @@ class DescNet:
         return self.forward(self.input_from_images(img[None]))[0]
 
 
-def triplets(flow: torch.Tensor, keep: torch.Tensor, count: int, rng: "np.random.Generator"):
-    """Anchors p among the pixels kept by the plain consistency check,
-    positive p + F(p), negative = positive + an offset of Chebyshev radius
-    2..8 px (in-image).  Returns int32 [count, 4] entries (x, y, fx, fy) for
-    the positive and the negative."""
-    import numpy as np
-    H, W = keep.shape
-    k = keep.cpu().numpy().astype(bool)
-    f = flow.cpu().numpy().astype(np.int64)
-    ys, xs = np.nonzero(k)
-    if len(xs) == 0:
-        raise ValueError("no consistent matches")
-    sel = rng.integers(0, len(xs), size=count * 2)
-    xs, ys = xs[sel], ys[sel]
-    fx, fy = f[ys, xs, 0], f[ys, xs, 1]
-    ox = rng.integers(-8, 9, size=len(xs))
-    oy = rng.integers(-8, 9, size=len(xs))
-    cheb = np.maximum(np.abs(ox), np.abs(oy))
-    ok = (cheb >= 2) & (xs + fx + ox >= 0) & (xs + fx + ox < W) & (ys + fy + oy >= 0) & (ys + fy + oy < H)
-    idx = np.nonzero(ok)[0][:count]
-    pos = np.stack([xs[idx], ys[idx], fx[idx], fy[idx]], 1).astype(np.int32)
-    neg = np.stack([xs[idx], ys[idx], fx[idx] + ox[idx], fy[idx] + oy[idx]], 1).astype(np.int32)
-    return pos, neg
+class TripletSampler:
+    """Anchors for the triplet loss of one image pair: the pixels kept by the
+    plain method's consistency check, with their plain flows (host copy made
+    once).  sample() draws anchors p, the positive p + F(p) and a negative =
+    positive + an offset of Chebyshev radius 2..8 px that stays in the image."""
+
+    def __init__(self, flow: torch.Tensor, keep: torch.Tensor):
+        import numpy as np
+        self.H, self.W = keep.shape
+        k = keep.cpu().numpy().astype(bool)
+        f = flow.cpu().numpy().astype(np.int64)
+        self.ys, self.xs = np.nonzero(k)
+        self.fx, self.fy = f[self.ys, self.xs, 0], f[self.ys, self.xs, 1]
+
+    def __len__(self):
+        return len(self.xs)
+
+    def sample(self, count: int, rng, negatives: int = 1):
+        """int32 entries (x, y, fx, fy): positives [m, 4] and negatives
+        [m, 4] (negatives == 1) or [m, negatives, 4] candidates, m <= count.
+        A candidate offset that fails (radius < 2 or out of the image) is
+        replaced by the anchor's first valid one."""
+        import numpy as np
+        if len(self.xs) == 0:
+            raise ValueError("no consistent matches")
+        K = max(1, int(negatives))
+        sel = rng.integers(0, len(self.xs), size=count * 2)
+        xs, ys, fx, fy = self.xs[sel], self.ys[sel], self.fx[sel], self.fy[sel]
+        ox = rng.integers(-8, 9, size=(len(xs), K))
+        oy = rng.integers(-8, 9, size=(len(xs), K))
+        tx, ty = (xs + fx)[:, None] + ox, (ys + fy)[:, None] + oy
+        ok = (np.maximum(np.abs(ox), np.abs(oy)) >= 2) & (tx >= 0) & (tx < self.W) & (ty >= 0) & (ty < self.H)
+        idx = np.nonzero(ok.any(1))[0][:count]
+        ok, ox, oy = ok[idx], ox[idx], oy[idx]
+        first = ok.argmax(1)
+        r = np.arange(len(idx))
+        ox = np.where(ok, ox, ox[r, first][:, None])
+        oy = np.where(ok, oy, oy[r, first][:, None])
+        pos = np.stack([xs[idx], ys[idx], fx[idx], fy[idx]], 1).astype(np.int32)
+        neg = np.stack([np.broadcast_to(xs[idx, None], ox.shape), np.broadcast_to(ys[idx, None], ox.shape),
+                        fx[idx, None] + ox, fy[idx, None] + oy], 2).astype(np.int32)
+        return pos, (neg[:, 0] if negatives == 1 else neg)
 
 
-def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.0, lr: float = 1e-3):
+def triplets(flow: torch.Tensor, keep: torch.Tensor, count: int, rng):
+    """One-off TripletSampler(flow, keep).sample(count, rng)."""
+    return TripletSampler(flow, keep).sample(count, rng)
+
+
+def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.0, lr: float = 1e-3,
+               negatives: int = 1):
     """One Adam step of the triplet hinge max(0, margin + C(p, pos) - C(p, neg))
     averaged over anchors of every pair in `batch` = [(img1, img2, flow, keep)]
-    with the plain method's flows and consistency masks."""
+    (or [(img1, img2, TripletSampler)]) with the plain method's flows and
+    consistency masks.  The costs enter as means over the 49 patch samples
+    (per-pixel squared distances of unit features lie in [0, 4], so the
+    margin has a fixed scale).  With negatives > 1 each anchor draws that many
+    candidate negatives and keeps the one of lowest current cost (hardest)."""
     B = len(batch)
-    H, W = batch[0][0].shape
     imgs = torch.stack([b[0] for b in batch] + [b[1] for b in batch])   # [2B, H, W]
     feats, acts = net.forward(net.input_from_images(imgs), keep=True)
     feats = feats.detach().requires_grad_(True)
     loss = 0.0
     total = 0
-    for k, (_, _, flow, keep) in enumerate(batch):
-        pos, neg = triplets(flow, keep, samples, rng)
+    for k, item in enumerate(batch):
+        sampler = item[2] if len(item) == 3 else TripletSampler(item[2], item[3])
+        pos, neg = sampler.sample(samples, rng, negatives)
         if len(pos) == 0:
             continue
         pe = torch.from_numpy(pos).to(feats.device)
         ne = torch.from_numpy(neg).to(feats.device)
+        if negatives > 1:
+            with torch.no_grad():
+                cand = ne.reshape(-1, 4).contiguous()
+                c = cost_f32(feats[k].detach(), feats[B + k].detach(), cand, 1, 3).reshape(len(pos), negatives)
+                ne = ne[torch.arange(len(pos), device=ne.device), c.argmin(1)].contiguous()
         cp = patch_cost(feats[k], feats[B + k], pe, 1, 3)
         cn = patch_cost(feats[k], feats[B + k], ne, 1, 3)
-        loss = loss + torch.relu(margin + cp - cn).sum()
+        loss = loss + torch.relu(margin + (cp - cn) * (1.0 / 49.0)).sum()
         total += len(pos)
     loss = loss / max(total, 1)
     loss.backward()
@@ -236,18 +284,27 @@ def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.
     return float(loss.detach())
 
 
-def learned_flow_fields(net: DescNet, img1: torch.Tensor, img2: torch.Tensor, params, blurred=None) -> dict:
-    """Flow Fields on DescNet features of the scale-space images I^n
+def scale_images(img1: torch.Tensor, img2: torch.Tensor, levels: int) -> torch.Tensor:
+    """Scale-space images B_n (n = 2^l) of both images, uint8 [2L, H, W]:
+    rows 0..L-1 are img1's scales, rows L..2L-1 img2's."""
+    from .flowfields import descriptors
+    return torch.stack([descriptors(img, 1 << lv)[0] for img in (img1, img2) for lv in range(levels)])
+
+
+def learned_features(net: DescNet, scales: torch.Tensor) -> torch.Tensor:
+    """DescNet features of every scale image in one batched pass: float32 [2L, H, W, 16]."""
+    return net.forward(net.input_from_images(scales))
+
+
+def learned_flow_fields(net: DescNet, img1: torch.Tensor, img2: torch.Tensor, params, scales=None) -> dict:
+    """Flow Fields on DescNet features of the scale-space images B_n
     (ff_flow_fields_f32).  Returns the same keys as flow_fields; costs are
     float32 bit patterns."""
-    from .flowfields import descriptors
-    H, W = img1.shape
     L = params.levels
-    if blurred is None:
-        blurred = [(descriptors(img1, 1 << lv)[0], descriptors(img2, 1 << lv)[0]) for lv in range(L)]
-    f1 = [net.features(b[0]).contiguous() for b in blurred]
-    f2 = [net.features(b[1]).contiguous() for b in blurred]
-    return flow_fields_f32(f1, f2, params)
+    if scales is None:
+        scales = scale_images(img1, img2, L)
+    feats = learned_features(net, scales)
+    return flow_fields_f32([feats[lv] for lv in range(L)], [feats[L + lv] for lv in range(L)], params)
 
 
 def flow_fields_f32(f1, f2, params) -> dict:

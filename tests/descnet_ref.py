@@ -16,8 +16,14 @@ def bf16(t):
     return t.to(torch.bfloat16).to(t.dtype)
 
 
-def forward(x, ws, bs, round_bf16=False):
-    """x: [B, H, W, 1] -> features [B, H, W, 16] (float64)."""
+def l2norm(h, delta):
+    """Per-pixel unit length over the channel axis (dim 1): h / sqrt(|h|^2 + delta)."""
+    return h / torch.sqrt((h * h).sum(1, keepdim=True) + delta)
+
+
+def forward(x, ws, bs, round_bf16=False, delta=None):
+    """x: [B, H, W, 1] -> features [B, H, W, 16] (float64); delta not None
+    appends the per-pixel normalisation of the output."""
     h = x.permute(0, 3, 1, 2)
     for k, (cin, cout, relu) in enumerate(LAYERS):
         w = torch_weight(bf16(ws[k]) if round_bf16 else ws[k])
@@ -26,4 +32,6 @@ def forward(x, ws, bs, round_bf16=False):
             h = torch.relu(h)
         if round_bf16 and k < len(LAYERS) - 1:
             h = bf16(h)
+    if delta is not None:
+        h = l2norm(h, delta)
     return h.permute(0, 2, 3, 1)

@@ -115,8 +115,8 @@ def test_wgrad_is_deterministic():
     assert torch.equal(outs[0], outs[1])
 
 
-def _net_and_crop(seed=0):
-    net = Lm.DescNet(seed=seed)
+def _net_and_crop(seed=0, normalize=True):
+    net = Lm.DescNet(seed=seed, normalize=normalize)
     g = torch.Generator().manual_seed(seed + 1)
     for k in range(3):  # non-zero biases exercise the bias gradient
         net.b[k] = (torch.randn(net.b[k].shape, generator=g) * 0.1).cuda()
@@ -124,10 +124,14 @@ def _net_and_crop(seed=0):
     return net, img
 
 
-def test_network_gradient_matches_f64_reference():
+@pytest.mark.parametrize("normalize", [False, True])
+def test_network_gradient_matches_f64_reference(normalize):
     """GPU forward/backward vs float64 autograd with the same bf16 roundings,
-    and vs float64 central differences of the unrounded network (64x48)."""
-    net, img = _net_and_crop()
+    and (un-normalised network) vs float64 central differences of the
+    unrounded network (64x48).  The normalisation layer's own kernels are
+    checked against float64 autograd in test_l2norm_forward_and_backward."""
+    net, img = _net_and_crop(normalize=normalize)
+    delta = net.delta if normalize else None
     x_bits = net.input_from_images(img.cuda())
     feats, acts = net.forward(x_bits, keep=True)
     probe = torch.randn((1, 48, 64, 16), generator=torch.Generator().manual_seed(5), dtype=torch.float64)
@@ -135,7 +139,7 @@ def test_network_gradient_matches_f64_reference():
     x64 = Lm.bf16_bits_to_f32(x_bits).cpu().double()
     ws = [w.cpu().double().requires_grad_(True) for w in net.w]
     bs = [b.cpu().double().requires_grad_(True) for b in net.b]
-    ref = forward(x64, ws, bs, round_bf16=True)
+    ref = forward(x64, ws, bs, round_bf16=True, delta=delta)
     # forward: identical bf16 roundings except where float32 sums straddle a rounding boundary
     rel = float((feats.cpu().double() - ref.detach()).norm() / ref.detach().norm())
     assert rel < 2e-3, rel
@@ -144,6 +148,8 @@ def test_network_gradient_matches_f64_reference():
         rw = float((gws[k].cpu().double() - ws[k].grad).norm() / ws[k].grad.norm())
         rb = float((gbs[k].cpu().double() - bs[k].grad).norm() / bs[k].grad.norm())
         assert rw < 2e-2 and rb < 2e-2, (k, rw, rb)
+    if normalize:
+        return
     # central differences of the float64 network at the bf16 weights
     w64 = [bf16(w.detach()) for w in ws]
     b64 = [b.detach() for b in bs]
@@ -161,6 +167,27 @@ def test_network_gradient_matches_f64_reference():
             errs.append(abs(num - float(gws[k][idx])))
             mags.append(abs(num))
         assert max(errs) <= 0.05 * max(max(mags), 1.0), (k, errs, mags)
+
+
+def test_l2norm_forward_and_backward():
+    from descnet_ref import l2norm
+    g0 = torch.Generator().manual_seed(6)
+    f = torch.randn((2, 13, 17, 16), generator=g0) * 3
+    f[0, 0, 0] = 0.0  # zero feature: finite thanks to delta
+    g = torch.randn((2, 13, 17, 16), generator=g0)
+    fd, gd = f.cuda(), g.cuda()
+    y = torch.empty_like(fd)
+    inv = torch.empty((2, 13, 17), device="cuda")
+    ff.ffi.check(ff.lib().ff_l2norm16_fwd(Lm._ptr(fd), 2 * 13 * 17, 1e-4, Lm._ptr(y), Lm._ptr(inv), Lm._stream()),
+                 "l2norm fwd")
+    gin = torch.empty_like(fd)
+    ff.ffi.check(ff.lib().ff_l2norm16_bwd(Lm._ptr(y), Lm._ptr(inv), Lm._ptr(gd), 2 * 13 * 17, Lm._ptr(gin),
+                                          Lm._stream()), "l2norm bwd")
+    f64 = f.double().permute(0, 3, 1, 2).requires_grad_(True)
+    ref = l2norm(f64, float(np.float32(1e-4)))
+    (ref * g.double().permute(0, 3, 1, 2)).sum().backward()
+    assert torch.allclose(y.cpu().double(), ref.detach().permute(0, 2, 3, 1), rtol=0, atol=2e-6)
+    assert torch.allclose(gin.cpu().double(), f64.grad.permute(0, 2, 3, 1), rtol=1e-4, atol=1e-4)
 
 
 def test_adam_step_matches_formula():
@@ -224,3 +251,27 @@ def test_training_reduces_the_triplet_loss():
     losses = [Lm.train_step(net, batch, rng, samples=512, lr=3e-3) for _ in range(40)]
     assert np.isfinite(losses).all()
     assert np.mean(losses[-5:]) < 0.8 * np.mean(losses[:5]), losses
+
+
+def test_learned_path_end_to_end_matches_oracle_on_the_network_features():
+    """Scale images -> DescNet -> learned Flow Fields: the schedule on the
+    GPU's own features is bit-exact to the oracle run on the same features."""
+    from ffgen import make_pair
+    net = Lm.DescNet(seed=3)
+    p = make_pair(1, 0)
+    prm = ff.Params(levels=3, iters=4)
+    i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+    scales = Lm.scale_images(i1, i2, 3)
+    feats = Lm.learned_features(net, scales)
+    g = Lm.learned_flow_fields(net, i1, i2, prm, scales=scales)
+    torch.cuda.synchronize()
+    # the scale images are the plain path's blur, which the oracle pins
+    sc = scales.cpu().numpy()
+    for lv in range(3):
+        assert np.array_equal(sc[lv], oracle.blur(p.img1, 1 << lv))
+        assert np.array_equal(sc[3 + lv], oracle.blur(p.img2, 1 << lv))
+    fc = feats.cpu().numpy()
+    o = oracle.flow_fields_f32([fc[lv] for lv in range(3)], [fc[3 + lv] for lv in range(3)], 3, 4, nthreads=NT)
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(g[k].cpu().numpy(), o[k]), k
+    assert tuple(int(v) for v in g["n_evals"].cpu()) == o["n_evals"]
