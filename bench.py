@@ -71,7 +71,9 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     L = params.levels
     Da = [ff.descriptors(img1, 1 << lv)[1] for lv in range(L)]
     Db = [ff.descriptors(img2, 1 << lv)[1] for lv in range(L)]
-    _, _, key = ff.init_nn(Da[0], Db[0], Da[L - 1], Db[L - 1], 1 << (L - 1))
+    Da1 = ff.descriptors(img1, 1, rowmajor=True)[2]
+    Db1 = ff.descriptors(img2, 1, rowmajor=True)[2]
+    _, _, key = ff.init_nn(Da1, Db1, Da[L - 1], Db[L - 1], 1 << (L - 1))
     dev = img1.device
     prev = None
     for lv in range(L - 1, 0, -1):
@@ -140,8 +142,9 @@ def batched_throughput(ff, torch, reps):
 
 def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
     """DescNet trained on the plain method's consistent matches (16 training
-    pairs of the learned workload), judged by ground-truth EPE on two held-out
-    pairs against the plain field (fallback to plain when it is worse), then
+    pairs of the learned workload), judged by the mean ground-truth EPE on
+    held-out pairs of that workload against the plain field (fallback to
+    plain when it is worse), then
     timed on the 1024x436 pair: descriptor network on every scale image of
     both images + learned-feature fields fwd+bwd + consistency."""
     import numpy as np

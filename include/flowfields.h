@@ -72,10 +72,24 @@ const char *ff_status_str(ff_status s);
  * blurred[y][x] = round-half-up mean of img over the (2h+1)^2 window,
  * h = max(1, n/2), replicate border; desc[y][x][4*gy+gx] =
  * blurred[clamp(y + n*(2gy-3))][clamp(x + n*(2gx-3))], gx, gy in 0..3.
- * img: [H][W]; blurred: [H][W] output; desc: [H][W][16] output;
- * hsum: [H][W] uint16 scratch. */
+ * img: [H][W]; blurred: [H][W] output; hsum: [H][W] uint16 scratch;
+ * desc: the descriptor MAP of scale n (output, ff_descriptor_map_bytes);
+ * desc_rowmajor (nullable): the same descriptors as plain [H][W][16] (the
+ * input of ff_init_nn's nearest-neighbour search).
+ * Descriptor map layout (every entry point that takes a "descriptor map"
+ * expects it): P = 3n, Wp = W + 2P; Hp = H + 2P rows of Wp 16-byte entries;
+ * entry (y + P, col(x + P)) holds desc[clamp(y)][clamp(x)] for x in
+ * [-P, W + P), y in [-P, H + P) (replicated border), where inside a row the
+ * pixels are grouped by phase, col(c) = (c mod n)*floor(Wp/n) +
+ * min(c mod n, Wp mod n) + floor(c/n): the samples x + n*u of a patch row
+ * are adjacent and a radius-3 patch around any in-image pixel needs no
+ * clamping.  n <= 64. */
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum,
-                         uint8_t *blurred, uint8_t *desc, void *stream);
+                         uint8_t *blurred, uint8_t *desc, uint8_t *desc_rowmajor, void *stream);
+
+/* Bytes of a descriptor map of scale n (host): (W + 6n) * (H + 6n) * 16;
+ * 0 for invalid sizes. */
+size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n);
 
 /* Initial flow of the coarsest scale nc (Sec. 3.1 initialisation, Eq. 1;
  * Sec. 3.2 Eq. 4 with a single candidate): for every cell p of the grid of
@@ -83,8 +97,9 @@ ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, ui
  * level-1 descriptor of p in image a under squared L2 distance (ties: the
  * smallest q.y*W + q.x), computed on int8 matrix cores; then F(p) = q - p and
  * cost(p) = E_nc(p, F(p)) with the scale-nc descriptors.
- * desc_a1, desc_b1: level-1 descriptors [H][W][16]; desc_ac, desc_bc:
- * scale-nc descriptors; nb_scratch: int32 [ceil(W*H/32)*32] scratch;
+ * desc_a1, desc_b1: level-1 descriptors, plain [H][W][16] (desc_rowmajor of
+ * ff_descriptors); desc_ac, desc_bc: descriptor maps of scale nc;
+ * nb_scratch: int32 [ceil(W*H/32)*32] scratch;
  * nn_key: uint64 [cells] output, (squared distance << 32) | q;
  * flow, cost: grid of scale nc, outputs. */
 ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac,
@@ -95,8 +110,9 @@ ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8
 /* Coarse-to-fine hand-over from scale 2n to scale n (Sec. 3.2): cells with
  * both grid indices even are the same pixel as a coarse cell and take its
  * flow as a seed, with the cost re-evaluated at scale n; all other cells
- * become UNSET.  coarse_flow/coarse_cost: grid of scale 2n (inputs);
- * flow/cost: grid of scale n (outputs). */
+ * become UNSET.  desc_a, desc_b: descriptor maps of scale n;
+ * coarse_flow/coarse_cost: grid of scale 2n (inputs); flow/cost: grid of
+ * scale n (outputs). */
 ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost, const uint8_t *desc_a,
                         const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t radius,
                         int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
@@ -107,7 +123,8 @@ ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost,
  * half-sweeps, cells with (i+j) odd first: each cell keeps the best of its
  * own flow, its horizontal and then its vertical source cell's flow by
  * E_n (strictly lower wins; sources that are UNSET, equal to the held flow or
- * point outside the image are skipped).  flow/cost: grid of scale n, in/out. */
+ * point outside the image are skipped).  desc_a, desc_b: descriptor maps of
+ * scale n; flow/cost: grid of scale n, in/out. */
 ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
                              int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
                              void *stream);
@@ -118,7 +135,8 @@ ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32
  * from h = mix(seed ^ mix(ctr)), mix = SplitMix64's output mixer (Steele,
  * Lea, Flood 2014), ctr = stream_id<<56 | level<<48 | pass<<32 | j<<16 | i;
  * ox = (lo32(h) * (2Rn+1)) >> 32) - Rn, oy likewise from hi32(h) (Lemire's
- * multiply-shift).  flow/cost: grid of scale n, in/out. */
+ * multiply-shift).  desc_a, desc_b: descriptor maps of scale n; flow/cost:
+ * grid of scale n, in/out. */
 ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
                            int32_t radius, int32_t Rn, uint64_t seed, int32_t stream_id, int32_t level,
                            int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
@@ -142,7 +160,7 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
  * Equivalent to the corresponding sequence of ff_seed_level,
  * ff_propagate_level and ff_random_search calls (same fields, same
  * evaluation count); radius 3 runs in temporally blocked launches that keep
- * the state on chip.  desc_a/desc_b: scale-n descriptors; params: host. */
+ * the state on chip.  desc_a/desc_b: descriptor maps of scale n; params: host. */
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,

@@ -8,6 +8,7 @@
 #include <cstring>
 
 #include "../../include/flowfields.h"
+#include "ff_device.h"
 #include "ff_internal.h"
 
 namespace {
@@ -30,10 +31,16 @@ int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) /
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc, nb, keys, grids, evals, total;
+  size_t hsum, blur, desc[2][kMaxLevels], desc1, nb, keys, grids, evals, total;
   size_t N, Npad, M;
   int L;
 };
+
+// Bytes of a padded scale-n descriptor map (replicated border of 3n pixels).
+size_t desc_map_bytes(int W, int H, int n) {
+  const size_t P = (size_t)ffk::desc_pad(n);
+  return (W + 2 * P) * (H + 2 * P) * 16;
+}
 
 Layout layout(int W, int H, const ff_params *p) {
   Layout l{};
@@ -45,7 +52,12 @@ Layout layout(int W, int H, const ff_params *p) {
   size_t off = 0;
   l.hsum = off; off = align256(off + 2 * l.L * l.N * sizeof(uint16_t));
   l.blur = off; off = align256(off + 2 * l.L * l.N);
-  l.desc = off; off = align256(off + 2 * l.L * l.N * 16);
+  for (int im = 0; im < 2; ++im)
+    for (int lv = 0; lv < l.L; ++lv) {
+      l.desc[im][lv] = off;
+      off = align256(off + desc_map_bytes(W, H, 1 << lv));
+    }
+  l.desc1 = off; off = align256(off + 2 * l.N * 16);
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
   l.grids = off;
@@ -117,6 +129,31 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   return hipSuccess;
 }
 
+// The passes of one scale with one launch per step over all cells: the
+// coarsest scale's NN initialisation or the seeding from the coarser scale,
+// then T propagation passes (two half-sweeps each) with T-1 random searches.
+// a.dir[] must hold the per-direction pointers; the scale fields are set here.
+hipError_t run_level_steps(ffh::LevelArgs a, int W, int H, int lv, int L, const ff_params *p, hipStream_t s) {
+  const int n = 1 << lv;
+  a.W = W;
+  a.H = H;
+  a.n = n;
+  a.Wn = ceil_div(W, n);
+  a.Hn = ceil_div(H, n);
+  a.level = lv;
+  a.Rn = rs_radius(n, p->R_num, p->R_den);
+  a.radius = p->radius;
+  a.seed = p->seed;
+  hipError_t e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
+  if (e != hipSuccess) return e;
+  for (int t = 0; t < p->iters; ++t) {
+    a.pass = t;
+    if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return e;
+    if (t < p->iters - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -134,14 +171,20 @@ const char *ff_status_str(ff_status s) {
   return "unknown status";
 }
 
+size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n) {
+  if (!dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1))) return 0;
+  return desc_map_bytes(W, H, n);
+}
+
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum, uint8_t *blurred,
-                         uint8_t *desc, void *stream) {
-  if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || !is_pow2(n)) return FF_ERR_ARG;
+                         uint8_t *desc, uint8_t *desc_rowmajor, void *stream) {
+  if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1)))
+    return FF_ERR_ARG;
   ffh::DescJobs jobs{};
   jobs.W = W;
   jobs.H = H;
   jobs.count = 1;
-  jobs.job[0] = {img, hsum, blurred, desc, n};
+  jobs.job[0] = {img, hsum, blurred, desc, desc_rowmajor, n};
   return from_hip(ffh::launch_descriptors(jobs, (hipStream_t)stream));
 }
 
@@ -349,8 +392,9 @@ ff_status ff_batch_table(const ff_pair *pairs, int32_t npairs, const ff_params *
         const size_t z = (size_t)(im * L + lv);
         t.hsum[im][lv] = reinterpret_cast<uint16_t *>(b + lay.hsum) + z * lay.N;
         t.blur[im][lv] = reinterpret_cast<uint8_t *>(b + lay.blur) + z * lay.N;
-        t.desc[im][lv] = reinterpret_cast<uint8_t *>(b + lay.desc) + z * lay.N * 16;
+        t.desc[im][lv] = reinterpret_cast<uint8_t *>(b + lay.desc[im][lv]);
       }
+      t.desc1[im] = reinterpret_cast<uint8_t *>(b + lay.desc1) + (size_t)im * lay.N * 16;
       t.nb[im] = reinterpret_cast<int32_t *>(b + lay.nb) + (size_t)im * lay.Npad;
       t.keys[im] = reinterpret_cast<uint64_t *>(b + lay.keys) + (size_t)im * lay.M;
     }
@@ -479,7 +523,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
   if (!feat1 || !feat2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !dims_ok(W, H) ||
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
-  const int L = params->levels, T = params->iters, r = params->radius;
+  const int L = params->levels, r = params->radius;
   for (int lv = 0; lv < L; ++lv)
     if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
   const LayoutF32 lay = layout_f32(W, H, params);
@@ -538,12 +582,6 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
     a.dir[dr].stream_id = dr;
   }
   for (int lv = L - 1; lv >= 0; --lv) {
-    const int n = 1 << lv;
-    a.n = n;
-    a.Wn = ceil_div(W, n);
-    a.Hn = ceil_div(H, n);
-    a.level = lv;
-    a.Rn = rs_radius(n, params->R_num, params->R_den);
     for (int dr = 0; dr < 2; ++dr) {
       a.dir[dr].Da = feat[dr][lv];
       a.dir[dr].Db = feat[dr ^ 1][lv];
@@ -554,13 +592,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
       a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
       a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
     }
-    e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
-    if (e != hipSuccess) return FF_ERR_LAUNCH;
-    for (int t = 0; t < T; ++t) {
-      a.pass = t;
-      if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
-      if (t < T - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
-    }
+    if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
   return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                           keep_bwd, s));
@@ -692,23 +724,26 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   const Layout lay = layout(W, H, params);
   if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  const int L = params->levels, T = params->iters, r = params->radius;
+  const int L = params->levels, r = params->radius;
   char *base = static_cast<char *>(ws);
   const uint8_t *img[2] = {img1, img2};
 
   // descriptors of both images at every scale
-  uint8_t *desc[2][kMaxLevels];
+  uint8_t *desc[2][kMaxLevels], *desc1[2];
   ffh::DescJobs jobs{};
   jobs.W = W;
   jobs.H = H;
   jobs.count = 2 * L;
-  for (int im = 0; im < 2; ++im)
+  for (int im = 0; im < 2; ++im) {
+    desc1[im] = reinterpret_cast<uint8_t *>(base + lay.desc1) + (size_t)im * lay.N * 16;
     for (int lv = 0; lv < L; ++lv) {
       const int z = im * L + lv;
-      desc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.desc) + (size_t)z * lay.N * 16;
+      desc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.desc[im][lv]);
       jobs.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
-                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, desc[im][lv], 1 << lv};
+                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, desc[im][lv],
+                     lv == 0 ? desc1[im] : nullptr, 1 << lv};
     }
+  }
   hipError_t e = ffh::launch_descriptors(jobs, s);
   if (e != hipSuccess) return FF_ERR_LAUNCH;
 
@@ -745,7 +780,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   nn.M = (int)lay.M;
   nn.N = (int)lay.N;
   for (int dr = 0; dr < 2; ++dr)
-    nn.dir[dr] = {desc[dr][0], desc[dr ^ 1][0], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
+    nn.dir[dr] = {desc1[dr], desc1[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
 
   if (r == 3) {
@@ -766,6 +801,16 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         k.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
         k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
+      if (ffh::level_stepwise(lv)) {
+        ffh::LevelArgs a{};
+        a.ndir = 2;
+        for (int dr = 0; dr < 2; ++dr) {
+          const ffh::LevelKDir &kd = k.dir[dr];
+          a.dir[dr] = {kd.Da, kd.Db, kd.flow, kd.cost, kd.cflow, kd.ccost, kd.nn_key, desc1[dr], kd.n_evals, dr};
+        }
+        if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
+        continue;
+      }
       const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
       if ((e = run_level_blocked(k, W, H, lv, params, mode, s)) != hipSuccess) return FF_ERR_LAUNCH;
     }
@@ -784,29 +829,17 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     a.dir[dr].stream_id = dr;
   }
   for (int lv = L - 1; lv >= 0; --lv) {
-    const int n = 1 << lv;
-    a.n = n;
-    a.Wn = ceil_div(W, n);
-    a.Hn = ceil_div(H, n);
-    a.level = lv;
-    a.Rn = rs_radius(n, params->R_num, params->R_den);
     for (int dr = 0; dr < 2; ++dr) {
       a.dir[dr].Da = desc[dr][lv];
       a.dir[dr].Db = desc[dr ^ 1][lv];
       a.dir[dr].flow = gflow[lv][dr];
       a.dir[dr].cost = gcost[lv][dr];
       a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
-      a.dir[dr].Dq1 = desc[dr][0];
+      a.dir[dr].Dq1 = desc1[dr];
       a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
       a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
     }
-    e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
-    if (e != hipSuccess) return FF_ERR_LAUNCH;
-    for (int t = 0; t < T; ++t) {
-      a.pass = t;
-      if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
-      if (t < T - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
-    }
+    if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
   return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                           keep_bwd, s));

@@ -5,7 +5,9 @@
 // computed separably (row sums, then column sums of the row sums; both are
 // exact in integers).  Descriptor of scale n: the 16 samples of I^n on a 4x4
 // grid with spacing 2n around the pixel, stored as one 16-byte vector per
-// pixel so that a patch position costs one 128-bit load.
+// pixel so that a patch position costs one 128-bit load; the pixels of each
+// row are stored in phase order (x mod n, then x / n), and the map carries a
+// replicated border of 3n pixels (desc_col, desc_index).
 //
 // All (image, scale) jobs of a call run in one launch per stage: blockIdx.z
 // selects the job.
@@ -42,22 +44,34 @@ __global__ __launch_bounds__(256) void k_vsum(ffh::DescJobs jobs) {
   jb.blurred[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
 }
 
-__global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
-  const ffh::DescJob &jb = jobs.job[blockIdx.z];
-  const int W = jobs.W, H = jobs.H;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
-  const int n = jb.n;
+// The 16 samples of the scale-n descriptor of pixel (x, y) (in the image).
+__device__ __forceinline__ uint4 descriptor_at(const uint8_t *blurred, int W, int H, int n, int x, int y) {
   uint32_t w[4];
 #pragma unroll
   for (int gy = 0; gy < 4; ++gy) {
-    const uint8_t *row = jb.blurred + (size_t)clampi(y + n * (2 * gy - 3), H - 1) * W;
+    const uint8_t *row = blurred + (size_t)clampi(y + n * (2 * gy - 3), H - 1) * W;
     uint32_t v = 0;
 #pragma unroll
     for (int gx = 0; gx < 4; ++gx) v |= (uint32_t)row[clampi(x + n * (2 * gx - 3), W - 1)] << (8 * gx);
     w[gy] = v;
   }
-  reinterpret_cast<uint4 *>(jb.desc)[(size_t)y * W + x] = make_uint4(w[0], w[1], w[2], w[3]);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// One thread per stored entry (padded row yp, column c; coalesced 16-byte
+// stores): the descriptor of the clamped pixel.  Entries that are image
+// pixels also go to the row-major copy when one is requested.
+__global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
+  const ffh::DescJob &jb = jobs.job[blockIdx.z];
+  const int W = jobs.W, H = jobs.H, n = jb.n, l2 = __builtin_ctz(n);
+  const int P = ffk::desc_pad(n), Wp = W + 2 * P, Hp = H + 2 * P;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, yp = blockIdx.y;
+  if (c >= Wp || yp >= Hp) return;
+  const int xr = ffk::desc_pixel(c, l2, Wp) - P, yr = yp - P;
+  const uint4 d = descriptor_at(jb.blurred, W, H, n, clampi(xr, W - 1), clampi(yr, H - 1));
+  reinterpret_cast<uint4 *>(jb.desc)[(size_t)yp * Wp + c] = d;
+  if (jb.compact && xr >= 0 && xr < W && yr >= 0 && yr < H)
+    reinterpret_cast<uint4 *>(jb.compact)[(size_t)yr * W + xr] = d;
 }
 
 // ---- batches: items = (pair, image * L + scale, row) ---------------------
@@ -103,23 +117,22 @@ __global__ __launch_bounds__(256) void k_vsum_batch(ffh::BatchStage st) {
   });
 }
 
+// Item (pair, image, scale, image row y): padded row y + P, and for the
+// first and last image rows also the border rows they replicate; scale 1
+// items also write the row-major copy used by the NN seed.
 __global__ __launch_bounds__(256) void k_desc_batch(ffh::BatchStage st) {
   ffk::for_items(st.total, [&](int item) {
     const RowItem r = row_item(st, item);
     const int W = r.bp->W, H = r.bp->H, n = 1 << r.lv;
+    const int P = ffk::desc_pad(n), Wp = W + 2 * P;
     const uint8_t *b = r.bp->blur[r.im][r.lv];
-    uint4 *out = reinterpret_cast<uint4 *>(r.bp->desc[r.im][r.lv]) + (size_t)r.y * W;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-      uint32_t w[4];
-#pragma unroll
-      for (int gy = 0; gy < 4; ++gy) {
-        const uint8_t *row = b + (size_t)clampi(r.y + n * (2 * gy - 3), H - 1) * W;
-        uint32_t v = 0;
-#pragma unroll
-        for (int gx = 0; gx < 4; ++gx) v |= (uint32_t)row[clampi(x + n * (2 * gx - 3), W - 1)] << (8 * gx);
-        w[gy] = v;
-      }
-      out[x] = make_uint4(w[0], w[1], w[2], w[3]);
+    uint4 *map = reinterpret_cast<uint4 *>(r.bp->desc[r.im][r.lv]);
+    const int yp0 = r.y == 0 ? 0 : r.y + P, yp1 = r.y == H - 1 ? H + 2 * P : r.y + P + 1;
+    for (int c = threadIdx.x; c < Wp; c += blockDim.x) {
+      const int xr = ffk::desc_pixel(c, r.lv, Wp) - P;
+      const uint4 d = descriptor_at(b, W, H, n, clampi(xr, W - 1), r.y);
+      for (int yp = yp0; yp < yp1; ++yp) map[(size_t)yp * Wp + c] = d;
+      if (r.lv == 0 && xr >= 0 && xr < W) reinterpret_cast<uint4 *>(r.bp->desc1[r.im])[(size_t)r.y * W + xr] = d;
     }
   });
 }
@@ -142,7 +155,10 @@ hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
   dim3 grid((jobs.W + 255) / 256, jobs.H, jobs.count);
   hipLaunchKernelGGL(k_hsum, grid, dim3(256), 0, stream, jobs);
   hipLaunchKernelGGL(k_vsum, grid, dim3(256), 0, stream, jobs);
-  hipLaunchKernelGGL(k_desc, grid, dim3(256), 0, stream, jobs);
+  int pmax = 0;
+  for (int k = 0; k < jobs.count; ++k) pmax = std::max(pmax, ffk::desc_pad(jobs.job[k].n));
+  const dim3 gpad((jobs.W + 2 * pmax + 255) / 256, jobs.H + 2 * pmax, jobs.count);
+  hipLaunchKernelGGL(k_desc, gpad, dim3(256), 0, stream, jobs);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Device-side helpers of the Flow Fields kernels (gfx950).
 //
 // Patch cost E_n of Eq. 3 on 16-byte descriptors: each patch position adds
-// the byte-wise SAD of two descriptors, four bytes per v_sad_u8.  Reads
+// the byte-wise SAD of two descriptors, four bytes per v_sad_u8.  Descriptor
+// rows are stored in phase order (desc_col).  Reads
 // outside the image take the nearest inside pixel (Sec. 3.6 border
 // condition).  The counter-based generator of the random search is
 // SplitMix64's output mixer (Steele, Lea, Flood 2014) applied as
@@ -25,6 +26,40 @@ __device__ __forceinline__ uint32_t sad16(const uint4 a, const uint4 b, uint32_t
   return acc;
 }
 
+// Scale-n descriptor maps keep their rows in image order, but the pixels of
+// a row are grouped by phase x mod n: pixel x sits at column
+// (x mod n) * floor(W / n) + min(x mod n, W mod n) + floor(x / n).  The
+// samples x + n*u of a patch row then occupy consecutive columns, as do the
+// patch rows of neighbouring grid cells.  For n = 1 this is the identity.
+__device__ __forceinline__ int desc_col(int x, int log2n, int W) {
+  const int r = x & ((1 << log2n) - 1);
+  return r * (W >> log2n) + min(r, W & ((1 << log2n) - 1)) + (x >> log2n);
+}
+
+// Scale-n descriptor maps also carry a border of kDescPad * n replicated
+// pixels on every side: the map holds D(clamp(x), clamp(y)) for x in
+// [-P, W + P), y in [-P, H + P), P = kDescPad * n, rows of width W + 2P in
+// phase order.  A radius-3 patch around any in-image target then reads the
+// map without clamping.  P is a multiple of n, so phases are unchanged.
+constexpr int kDescPad = 3;
+
+__host__ __device__ __forceinline__ int desc_pad(int n) { return kDescPad * n; }
+
+// Inverse of desc_col: the pixel stored at column c.
+__device__ __forceinline__ int desc_pixel(int c, int log2n, int W) {
+  const int q = W >> log2n, m = W & ((1 << log2n) - 1);
+  if (c < (q + 1) * m) return c / (q + 1) + ((c % (q + 1)) << log2n);
+  const int c2 = c - (q + 1) * m;
+  return m + c2 / q + ((c2 % q) << log2n);
+}
+
+// Index of pixel (x, y), x in [-P, W + P), y in [-P, H + P), in a padded
+// scale-2^log2n descriptor map of a W-wide image.
+__device__ __forceinline__ size_t desc_index(int x, int y, int log2n, int W) {
+  const int P = kDescPad << log2n, Wp = W + 2 * P;
+  return (size_t)(y + P) * Wp + desc_col(x + P, log2n, Wp);
+}
+
 __device__ __forceinline__ int flow_x(int32_t f) { return (int)(int16_t)(f & 0xFFFF); }
 __device__ __forceinline__ int flow_y(int32_t f) { return f >> 16; }
 __device__ __forceinline__ int32_t pack_flow(int fx, int fy) {
@@ -35,16 +70,16 @@ __device__ __forceinline__ int32_t pack_flow(int fx, int fy) {
 template <int R>
 __device__ __forceinline__ uint32_t patch_cost(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db,
                                                int W, int H, int n, int x, int y, int fx, int fy) {
-  const int Wm = W - 1, Hm = H - 1;
+  const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
   uint32_t s = 0;
 #pragma unroll 1
   for (int v = -R; v <= R; ++v) {
-    const uint4 *ra = Da + (size_t)clampi(y + n * v, Hm) * W;
-    const uint4 *rb = Db + (size_t)clampi(y + fy + n * v, Hm) * W;
+    const uint4 *ra = Da + (size_t)(clampi(y + n * v, Hm) + P) * Wp;
+    const uint4 *rb = Db + (size_t)(clampi(y + fy + n * v, Hm) + P) * Wp;
 #pragma unroll
     for (int u = -R; u <= R; ++u) {
-      const uint4 a = ra[clampi(x + n * u, Wm)];
-      const uint4 b = rb[clampi(x + fx + n * u, Wm)];
+      const uint4 a = ra[desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
+      const uint4 b = rb[desc_col(clampi(x + fx + n * u, Wm) + P, l2, Wp)];
       s = sad16(a, b, s);
     }
   }
@@ -57,18 +92,18 @@ template <int R>
 __device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db, int W,
                                             int H, int n, int x, int y, int f1x, int f1y, bool en1, int f2x,
                                             int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
-  const int Wm = W - 1, Hm = H - 1;
+  const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
   uint32_t s1 = 0, s2 = 0;
 #pragma unroll 1
   for (int v = -R; v <= R; ++v) {
-    const uint4 *ra = Da + (size_t)clampi(y + n * v, Hm) * W;
-    const uint4 *rb1 = Db + (size_t)clampi(y + f1y + n * v, Hm) * W;
-    const uint4 *rb2 = Db + (size_t)clampi(y + f2y + n * v, Hm) * W;
+    const uint4 *ra = Da + (size_t)(clampi(y + n * v, Hm) + P) * Wp;
+    const uint4 *rb1 = Db + (size_t)(clampi(y + f1y + n * v, Hm) + P) * Wp;
+    const uint4 *rb2 = Db + (size_t)(clampi(y + f2y + n * v, Hm) + P) * Wp;
 #pragma unroll
     for (int u = -R; u <= R; ++u) {
-      const uint4 a = ra[clampi(x + n * u, Wm)];
-      if (en1) s1 = sad16(a, rb1[clampi(x + f1x + n * u, Wm)], s1);
-      if (en2) s2 = sad16(a, rb2[clampi(x + f2x + n * u, Wm)], s2);
+      const uint4 a = ra[desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
+      if (en1) s1 = sad16(a, rb1[desc_col(clampi(x + f1x + n * u, Wm) + P, l2, Wp)], s1);
+      if (en2) s2 = sad16(a, rb2[desc_col(clampi(x + f2x + n * u, Wm) + P, l2, Wp)], s2);
     }
   }
   c1 = s1;

@@ -16,7 +16,8 @@ struct DescJob {
   const uint8_t *img;
   uint16_t *hsum;
   uint8_t *blurred;
-  uint8_t *desc;
+  uint8_t *desc;     // padded, phase-ordered map (see desc_index)
+  uint8_t *compact;  // nullable: row-major [H][W][16] copy (the NN seed's input)
   int n;
 };
 struct DescJobs {
@@ -103,6 +104,7 @@ void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();
 int get_level_variant(int log2n);
 bool set_level_variant(int log2n, int variant);
+bool level_stepwise(int log2n);  // the table selects the step-wise schedule for this scale
 
 // ---- batches of pairs of different sizes (one launch per stage) ----------
 constexpr int kMaxBatch = 256;
@@ -115,7 +117,8 @@ struct BatchPair {
   int W, H;
   uint16_t *hsum[2][kMaxScales];
   uint8_t *blur[2][kMaxScales];
-  uint8_t *desc[2][kMaxScales];
+  uint8_t *desc[2][kMaxScales];  // padded maps
+  uint8_t *desc1[2];             // row-major scale-1 descriptors (NN seed)
   int32_t *nb[2];
   uint64_t *keys[2];
   int32_t *gflow[kMaxScales][2];

@@ -15,8 +15,9 @@
 // The scale-n descriptors of image a are staged in LDS on the level
 // lattice (virtual cell (i+u, j+v) -> pixel clamp((i+u)n, (j+v)n)), which is
 // exactly where E_n reads them.  Image b is read at p + f + n(u, v) with f
-// per cell, straight from global memory; waves whose lanes all read inside
-// the image use immediate load offsets (no clamps).
+// per cell, straight from global memory.  The descriptor maps are padded
+// with a replicated border of 3n pixels and their rows are in phase order,
+// so every patch read is unclamped and contiguous at every scale.
 #include <algorithm>
 
 #include "ff_device.h"
@@ -37,44 +38,24 @@ struct Geo {
 };
 
 // E_n(p, f) with image-a descriptors from LDS.  `pa` points at the LDS
-// descriptor of the cell itself; (bx, by) = p + f in pixels.
+// descriptor of the cell itself; (bx, by) = p + f in pixels, inside the
+// image, so the whole patch lies in the padded map of image b: no clamps,
+// the samples of a patch row are consecutive stored columns (phase order)
+// loaded with immediate offsets; with UNROLL all 49 loads are issued at once.
 template <int LOG2N, int DW, bool UNROLL>
-__device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int H, int bx,
-                                              int by, bool fast) {
-  constexpr int n = 1 << LOG2N;
+__device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int bx, int by) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n;
+  const int Wp = W + 2 * P;
   uint32_t s = 0;
-  if (fast) {
-    // every lane of the wave reads inside the image: no clamps, immediate
-    // offsets along the row; with UNROLL all 49 loads are issued at once
-    const uint4 *pb = Db + (size_t)(by - kR * n) * W + (bx - kR * n);
-#pragma unroll(UNROLL ? 2 * kR + 1 : 1)
-    for (int v = 0; v < 2 * kR + 1; ++v) {
-      const uint4 *ra = pa + (v - kR) * DW - kR;
+  const uint4 *pb = Db + ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+#pragma unroll UNROLL ? 2 * kR + 1 : 1
+  for (int v = 0; v < 2 * kR + 1; ++v) {
+    const uint4 *ra = pa + (v - kR) * DW - kR;
 #pragma unroll
-      for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], pb[u * n], s);
-      pb += (size_t)n * W;
-    }
-  } else {
-    const int Wm = W - 1, Hm = H - 1;
-#pragma unroll(UNROLL ? 2 * kR + 1 : 1)
-    for (int v = 0; v < 2 * kR + 1; ++v) {
-      const uint4 *ra = pa + (v - kR) * DW - kR;
-      const uint4 *rb = Db + (size_t)clampi(by + (v - kR) * n, Hm) * W;
-#pragma unroll
-      for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], rb[clampi(bx + (u - kR) * n, Wm)], s);
-    }
+    for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], pb[u], s);
+    pb += (size_t)n * Wp;
   }
   return s;
-}
-
-__device__ __forceinline__ bool interior(int bx, int by, int n, int W, int H) {
-  return bx - kR * n >= 0 && bx + kR * n < W && by - kR * n >= 0 && by + kR * n < H;
-}
-
-// Wave-uniform choice of the unclamped path for candidate target (bx, by).
-__device__ __forceinline__ bool wave_fast(bool active, int bx, int by, int n, int W, int H) {
-  const bool in = bx - kR * n >= 0 && bx + kR * n < W && by - kR * n >= 0 && by + kR * n < H;
-  return __all(!active || in);
 }
 
 // The run of passes for tile `tile` of one direction `d` (a holds the
@@ -101,7 +82,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
     for (int k = tid; k < G::DH * G::DW; k += kThreads) {
       const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
-      s_da[k] = Da[(size_t)clampi(vj * n, H - 1) * W + clampi(vi * n, W - 1)];
+      s_da[k] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
     }
   }
   __syncthreads();
@@ -142,7 +123,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if (eval) {
           const int bx = i * n + ffk::flow_x(f), by = j * n + ffk::flow_y(f);
           const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-          s_cost[l] = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, false);
+          s_cost[l] = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, bx, by);
           cnt = owned(i, j);
         }
       }
@@ -192,24 +173,16 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         uint32_t bc = c0;
         int32_t bf = f0;
         uint32_t eh = 0;
-        if (__any(hv)) {
-          const int bx = x + ffk::flow_x(fh), by = y + ffk::flow_y(fh);
-          const bool fast = wave_fast(hv, bx, by, n, W, H);
-          if (hv) {
-            eh = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
-            cnt = 1;
-            if (eh < bc) { bc = eh; bf = fh; }
-          }
+        if (hv) {
+          eh = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, x + ffk::flow_x(fh), y + ffk::flow_y(fh));
+          cnt = 1;
+          if (eh < bc) { bc = eh; bf = fh; }
         }
         const bool vev = vb && (bc == kUnset || fv != bf);
         const bool vcomp = vev && !(hv && fv == fh);
-        if (__any(vcomp)) {
-          const int bx = x + ffk::flow_x(fv), by = y + ffk::flow_y(fv);
-          const bool fast = wave_fast(vcomp, bx, by, n, W, H);
-          if (vcomp) {
-            const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
-            if (e < bc) { bc = e; bf = fv; }
-          }
+        if (vcomp) {
+          const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, x + ffk::flow_x(fv), y + ffk::flow_y(fv));
+          if (e < bc) { bc = e; bf = fv; }
         }
         if (vev) cnt += 1;  // an evaluation of fv == fh repeats eh, which did not win
         if (live && (bc != c0 || bf != f0)) {
@@ -246,17 +219,13 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           }
         }
         int cnt = 0;
-        if (__any(act)) {
-          const int bx = i * n + fx, by = j * n + fy;
-          const bool fast = wave_fast(act, bx, by, n, W, H);
-          if (act) {
-            const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-            const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, H, bx, by, fast);
-            cnt = owned(i, j);
-            if (e < c0) {
-              s_cost[l] = e;
-              s_flow[l] = ffk::pack_flow(fx, fy);
-            }
+        if (act) {
+          const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+          const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, i * n + fx, j * n + fy);
+          cnt = owned(i, j);
+          if (e < c0) {
+            s_cost[l] = e;
+            s_flow[l] = ffk::pack_flow(fx, fy);
           }
         }
         const int tot = __popcll(__ballot(cnt));
@@ -277,9 +246,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   if (tid == 0 && s_cnt && d.n_evals) atomicAdd(d.n_evals, (unsigned long long)s_cnt);
 }
 
-// One workgroup per (direction, tile) of one pair; XCD-aware order.
+// One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
+// four waves per SIMD: the register budget (128 VGPRs) then keeps the 49
+// loads of a patch in flight together instead of one after another.
 template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
-__global__ __launch_bounds__(kThreads) void k_level(ffh::LevelKArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
   level_body<LOG2N, TW, TH, kThreads, UNROLL>(a, a.dir[wg / tiles], wg % tiles);
@@ -287,7 +258,8 @@ __global__ __launch_bounds__(kThreads) void k_level(ffh::LevelKArgs a) {
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
 template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
-__global__ __launch_bounds__(kThreads) void k_level_batch(ffh::LevelKArgs base, ffh::BatchStage st) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_level_batch(
+    ffh::LevelKArgs base, ffh::BatchStage st) {
   constexpr int n = 1 << LOG2N;
   ffk::for_items(st.total, [&](int item) {
     const int p = ffk::batch_pair(st.prefix, st.npairs, item);
@@ -316,7 +288,10 @@ __global__ __launch_bounds__(kThreads) void k_level_batch(ffh::LevelKArgs base, 
   });
 }
 
-// Tile / workgroup variants of the level kernel.
+// Tile / workgroup variants of the level kernel.  Index kNumVariants of the
+// per-scale table selects the step-wise schedule instead (one launch per
+// half-sweep or random-search step over all cells, no halo): better where
+// the grid is too small to give every compute unit a tile.
 struct Variant {
   int tw, th;
 };
@@ -373,9 +348,18 @@ int g_variant[7] = {2, 2, 3, 3, 3, 3, 3};
 
 namespace ffh {
 
-int level_variant_count() { return kNumVariants; }
+int level_variant_count() { return kNumVariants + 1; }  // + the step-wise schedule
 
 int get_level_variant(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant[log2n] : -1; }
+
+bool level_stepwise(int log2n) { return get_level_variant(log2n) == kNumVariants; }
+
+// Blocked kernel variant used where the table asks for the step-wise
+// schedule but the caller only has the blocked form (batches, ff_run_level).
+static int blocked_variant(int log2n) {
+  const int v = get_level_variant(log2n);
+  return v == kNumVariants ? 3 : v;
+}
 
 bool set_level_variant(int log2n, int variant) {
   if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= level_variant_count()) return false;
@@ -391,16 +375,16 @@ static int log2_of(int n) {
 
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
   const int l2 = log2_of(a.n);
-  return dispatch(a, nullptr, l2, get_level_variant(l2), stream);
+  return dispatch(a, nullptr, l2, blocked_variant(l2), stream);
 }
 
 hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, hipStream_t stream) {
   const int l2 = log2_of(base.n);
-  return dispatch(base, &st, l2, get_level_variant(l2), stream);
+  return dispatch(base, &st, l2, blocked_variant(l2), stream);
 }
 
 int level_tiles(int Wn, int Hn, int log2n) {
-  const int v = get_level_variant(log2n);
+  const int v = blocked_variant(log2n);
   if (v < 0) return 0;
   const Variant t = kVariants[v];
   return ((Wn + t.tw - 1) / t.tw) * ((Hn + t.th - 1) / t.th);

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_nn_norms_batch(ffh::BatchStage st) {
     if (idx >= Npad) return;
     int s = kNbPad;
     if (idx < N) {
-      const uint4 v = reinterpret_cast<const uint4 *>(bp.desc[im][0])[idx];
+      const uint4 v = reinterpret_cast<const uint4 *>(bp.desc1[im])[idx];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
       s = 0;
 #pragma unroll
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_nn_batch(ffh::BatchStage st) {
     const int nqb = nn_qblocks(M), nchunk = nn_chunks(N);
     const int local = item - st.prefix[p];
     const int dir = local / (nqb * nchunk);
-    const ffh::NNDir d = {bp.desc[dir][0], bp.desc[dir ^ 1][0], bp.nb[dir ^ 1], bp.keys[dir]};
+    const ffh::NNDir d = {bp.desc1[dir], bp.desc1[dir ^ 1], bp.nb[dir ^ 1], bp.keys[dir]};
     nn_body(d, M, N, bp.W, nc, Wc, local % nqb, (local / nqb) % nchunk);
   });
 }

@@ -43,7 +43,8 @@ _I32 = C.c_int32
 _SIGS = {
     "ff_version": (C.c_int, []),
     "ff_status_str": (C.c_char_p, [C.c_int]),
-    "ff_descriptors": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "ff_descriptors": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P]),
+    "ff_descriptor_map_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_init_nn": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "ff_seed_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_propagate_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),

@@ -63,15 +63,31 @@ def rs_radius(n: int, R_num: int, R_den: int) -> int:
     return (R_num * n) // R_den
 
 
-def descriptors(img: torch.Tensor, n: int):
-    """Scale-space image and 16-byte descriptors of scale n."""
+def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False):
+    """Scale-space image and the descriptor map of scale n: uint8
+    [H + 6n, W + 6n, 16], a replicated border of 3n pixels, the pixels of a
+    row in phase order (x mod n, then x // n); the layout every entry point
+    taking a descriptor map expects (see ff_descriptors).  rowmajor=True also
+    returns the plain [H, W, 16] descriptors (the NN seed's input)."""
     H, W = img.shape
+    P = 3 * n
     hsum = torch.empty((H, W), dtype=torch.int16, device=img.device)
     blurred = torch.empty((H, W), dtype=torch.uint8, device=img.device)
-    desc = torch.empty((H, W, 16), dtype=torch.uint8, device=img.device)
+    desc = torch.empty((H + 2 * P, W + 2 * P, 16), dtype=torch.uint8, device=img.device)
+    plain = torch.empty((H, W, 16), dtype=torch.uint8, device=img.device) if rowmajor else None
+    assert desc.numel() == int(lib().ff_descriptor_map_bytes(W, H, n))
     check(lib().ff_descriptors(_ptr(img, torch.uint8, "img"), W, H, n, _ptr(hsum), _ptr(blurred), _ptr(desc),
-                               _stream()), "ff_descriptors")
-    return blurred, desc
+                               _ptr(plain), _stream()), "ff_descriptors")
+    return (blurred, desc, plain) if rowmajor else (blurred, desc)
+
+
+def _map_dims(desc_a, desc_b, n: int):
+    """(W, H) of the image behind two descriptor maps of scale n."""
+    Hp, Wp = desc_a.shape[:2]
+    W, H = Wp - 6 * n, Hp - 6 * n
+    if W < 1 or H < 1 or tuple(desc_b.shape) != tuple(desc_a.shape) or desc_a.shape[2:] != (16,):
+        raise ValueError("descriptor maps must both be uint8 [H + 6n, W + 6n, 16]")
+    return W, H
 
 
 def init_nn(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, radius: int = 3, n_evals: torch.Tensor | None = None):
@@ -83,6 +99,8 @@ def init_nn(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, radius: int = 3, n_eval
     key = torch.empty((Hc, Wc), dtype=torch.int64, device=dev)
     flow = torch.empty((Hc, Wc, 2), dtype=torch.int16, device=dev)
     cost = torch.empty((Hc, Wc), dtype=torch.int32, device=dev)
+    if _map_dims(desc_ac, desc_bc, nc) != (W, H) or tuple(desc_b1.shape) != (H, W, 16):
+        raise ValueError("init_nn: level-1 descriptors [H, W, 16] and scale-nc maps of the same image size")
     check(lib().ff_init_nn(_ptr(desc_a1, torch.uint8), _ptr(desc_b1, torch.uint8), _ptr(desc_ac, torch.uint8),
                            _ptr(desc_bc, torch.uint8), W, H, nc, radius, _ptr(nb), _ptr(key), _ptr(flow),
                            _ptr(cost), _ptr(n_evals, torch.int64), _stream()), "ff_init_nn")
@@ -90,7 +108,7 @@ def init_nn(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, radius: int = 3, n_eval
 
 
 def seed_level(cflow, ccost, desc_a, desc_b, n: int, radius: int = 3, n_evals=None):
-    H, W = desc_a.shape[:2]
+    W, H = _map_dims(desc_a, desc_b, n)
     Wn, Hn = cells(W, H, n)
     flow = torch.empty((Hn, Wn, 2), dtype=torch.int16, device=desc_a.device)
     cost = torch.empty((Hn, Wn), dtype=torch.int32, device=desc_a.device)
@@ -102,7 +120,7 @@ def seed_level(cflow, ccost, desc_a, desc_b, n: int, radius: int = 3, n_evals=No
 
 def propagate_level(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int = 3, n_evals=None):
     """One propagation step, in place on (flow, cost)."""
-    H, W = desc_a.shape[:2]
+    W, H = _map_dims(desc_a, desc_b, n)
     check(lib().ff_propagate_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, pass_,
                                    _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
                                    _stream()), "ff_propagate_level")
@@ -111,7 +129,7 @@ def propagate_level(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int 
 def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, level: int, pass_: int, flow, cost,
                   radius: int = 3, n_evals=None):
     """One random-search step, in place on (flow, cost)."""
-    H, W = desc_a.shape[:2]
+    W, H = _map_dims(desc_a, desc_b, n)
     check(lib().ff_random_search(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, Rn, seed,
                                  stream_id, level, pass_, _ptr(flow, torch.int16), _ptr(cost, torch.int32),
                                  _ptr(n_evals, torch.int64), _stream()), "ff_random_search")
@@ -120,7 +138,7 @@ def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, le
 def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: int, flow, cost, nn_key=None,
               coarse_flow=None, coarse_cost=None, n_evals=None):
     """All steps of one scale, in place on (flow, cost); see ff_run_level."""
-    H, W = desc_a.shape[:2]
+    W, H = _map_dims(desc_a, desc_b, 1 << level)
     check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, level, params.to_c(),
                              stream_id, mode, _ptr(nn_key, torch.int64), _ptr(coarse_flow, torch.int16),
                              _ptr(coarse_cost, torch.int32), _ptr(flow, torch.int16), _ptr(cost, torch.int32),

@@ -61,8 +61,9 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 16, fake, fake, fake, fake, fake, None, None,
                               None) == ffi.FF_ERR_WORKSPACE
     # bad sizes / scales / passes
-    assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None) == ffi.FF_ERR_ARG
-    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 128, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_propagate_level(fake, fake, 5, 5, 1, 3, -1, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter(fake, fake, fake, None, 5, 5, 1.0, fake, None, None) == ffi.FF_ERR_ARG
@@ -73,3 +74,13 @@ def test_python_binding_rejects_host_tensors():
     import torch
     with pytest.raises(ValueError):
         ff.descriptors(torch.zeros((4, 4), dtype=torch.uint8), 1)
+
+
+def test_descriptor_map_bytes():
+    """Padded descriptor maps: (W + 6n) x (H + 6n) entries of 16 bytes."""
+    lib = ff.lib()
+    for W, H, n in [(1024, 436, 1), (1024, 436, 16), (1, 1, 64), (37, 53, 4)]:
+        assert lib.ff_descriptor_map_bytes(W, H, n) == (W + 6 * n) * (H + 6 * n) * 16
+    assert lib.ff_descriptor_map_bytes(0, 5, 1) == 0
+    assert lib.ff_descriptor_map_bytes(5, 5, 3) == 0
+    assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0

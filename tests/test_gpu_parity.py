@@ -36,6 +36,33 @@ def counter():
     return torch.zeros(1, dtype=torch.int64, device="cuda")
 
 
+def phase_columns(Wp, n):
+    """Stored column of every column c of a padded map row (phase order:
+    c mod n, then c // n), as documented for ff_descriptors."""
+    c = np.arange(Wp)
+    r = c % n
+    return r * (Wp // n) + np.minimum(r, Wp % n) + c // n
+
+
+def to_lib(D, n):
+    """Row-major [H][W][16] descriptors -> the library's descriptor map:
+    replicated border of 3n pixels, rows in phase order."""
+    P = 3 * n
+    H, W = D.shape[:2]
+    padded = D[np.clip(np.arange(-P, H + P), 0, H - 1)][:, np.clip(np.arange(-P, W + P), 0, W - 1)]
+    out = np.empty_like(padded)
+    out[:, phase_columns(W + 2 * P, n)] = padded
+    return out
+
+
+def from_lib(M, n):
+    """Descriptor map -> row-major [H][W][16] (drops the border)."""
+    P = 3 * n
+    Hp, Wp = M.shape[:2]
+    padded = M[:, phase_columns(Wp, n)]
+    return np.ascontiguousarray(padded[P:Hp - P, P:Wp - P])
+
+
 SHAPES = [(37, 53), (1, 1), (1, 40), (33, 1), (120, 160), (9, 300)]
 
 
@@ -43,10 +70,15 @@ SHAPES = [(37, 53), (1, 1), (1, 40), (33, 1), (120, 160), (9, 300)]
 @pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
 def test_descriptors_bit_exact(shape, n):
     img, _ = random_images(100 + n, *shape, kind="uniform")
-    blurred, desc = ff.descriptors(dev(img), n)
+    blurred, desc, plain = ff.descriptors(dev(img), n, rowmajor=True)
     eb = oracle.blur(img, n)
+    ed = oracle.descriptor(eb, n)
     assert np.array_equal(host(blurred), eb)
-    assert np.array_equal(host(desc), oracle.descriptor(eb, n))
+    assert np.array_equal(host(plain), ed)
+    assert np.array_equal(from_lib(host(desc), n), ed)
+    assert np.array_equal(host(desc), to_lib(ed, n))  # the replicated border as well
+    Wp = shape[1] + 6 * n
+    assert sorted(phase_columns(Wp, n)) == list(range(Wp))  # a permutation
 
 
 def _descs(img, levels):
@@ -62,7 +94,8 @@ def test_init_nn_bit_exact(shape, nc):
     idx, dist = oracle.nn(Da[0], Db[0], nc, nthreads=NT)
     eflow, ecost, ene = oracle.init_coarse(idx, Da[L - 1], Db[L - 1], nc)
     cnt = counter()
-    flow, cost, key = ff.init_nn(dev(Da[0]), dev(Db[0]), dev(Da[L - 1]), dev(Db[L - 1]), nc, n_evals=cnt)
+    flow, cost, key = ff.init_nn(dev(Da[0]), dev(Db[0]), dev(to_lib(Da[L - 1], nc)), dev(to_lib(Db[L - 1], nc)), nc,
+                                 n_evals=cnt)
     k = host(key).view(np.uint64)
     assert np.array_equal((k & 0xFFFFFFFF).astype(np.int64), idx.astype(np.int64))
     assert np.array_equal((k >> 32).astype(np.int64), dist)
@@ -78,7 +111,7 @@ def test_init_nn_ties_smallest_index():
     Db[20, 30] = Da[8, 12]               # two exact matches of one query
     Db[21, 3] = Da[8, 12]
     idx, dist = oracle.nn(Da, Db, 4)
-    _, _, key = ff.init_nn(dev(Da), dev(Db), dev(Da), dev(Db), 4)
+    _, _, key = ff.init_nn(dev(Da), dev(Db), dev(to_lib(Da, 4)), dev(to_lib(Db, 4)), 4)
     k = host(key).view(np.uint64)
     assert np.array_equal((k & 0xFFFFFFFF).astype(np.int64), idx.astype(np.int64))
     assert idx[2, 3] == 20 * 36 + 30
@@ -110,7 +143,8 @@ def test_seed_level_bit_exact(shape, n):
     cflow, ccost = _random_level_state(n, H, W, 2 * n)
     ef, ec, ene = oracle.seed_level(cflow, ccost, Da, Db, n)
     cnt = counter()
-    f, c = ff.seed_level(dev(cflow), dev(ccost.view(np.int32)), dev(Da), dev(Db), n, n_evals=cnt)
+    f, c = ff.seed_level(dev(cflow), dev(ccost.view(np.int32)), dev(to_lib(Da, n)), dev(to_lib(Db, n)), n,
+                         n_evals=cnt)
     assert np.array_equal(host(f), ef)
     assert np.array_equal(as_u32(c), ec)
     assert int(host(cnt)[0]) == ene
@@ -127,7 +161,7 @@ def test_propagate_bit_exact(shape, n, pass_):
     flow, cost = _random_level_state(pass_, H, W, n)
     ef, ec, ene = oracle.propagate(Da, Db, n, pass_, flow, cost, nthreads=NT)
     gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
-    ff.propagate_level(dev(Da), dev(Db), n, pass_, gf, gc, n_evals=cnt)
+    ff.propagate_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), n, pass_, gf, gc, n_evals=cnt)
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ene
@@ -145,7 +179,8 @@ def test_random_search_bit_exact(shape, n, Rn):
         ef, ec, ene = oracle.random_search(Da, Db, n, Rn, FF_SEED, stream_id, level, pass_, flow, cost,
                                            nthreads=NT)
         gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
-        ff.random_search(dev(Da), dev(Db), n, Rn, FF_SEED, stream_id, level, pass_, gf, gc, n_evals=cnt)
+        ff.random_search(dev(to_lib(Da, n)), dev(to_lib(Db, n)), n, Rn, FF_SEED, stream_id, level, pass_, gf, gc,
+                         n_evals=cnt)
         assert np.array_equal(host(gf), ef)
         assert np.array_equal(as_u32(gc), ec)
         assert int(host(cnt)[0]) == ene
@@ -272,7 +307,7 @@ def test_run_level_bit_exact(shape, level, T, R, mode):
         gf = torch.empty((Hn, Wn, 2), dtype=torch.int16, device="cuda")
         gc = torch.empty((Hn, Wn), dtype=torch.int32, device="cuda")
     cnt = counter()
-    ff.run_level(dev(Da), dev(Db), level, prm, 0, mode, gf, gc, nn_key=key,
+    ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, prm, 0, mode, gf, gc, nn_key=key,
                  coarse_flow=None if cflow is None else dev(cflow),
                  coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
     assert np.array_equal(host(gf), ef)
