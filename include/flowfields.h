@@ -152,7 +152,9 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
 /* All steps of one scale (Sec. 3.2): T propagation steps with T-1
  * random-search steps between them (RS stream `stream_id`, level index
  * `level`, n = 2^level), starting from
- *   mode 0: the state already in flow/cost;
+ *   mode 0: the state already in flow/cost, which must be consistent:
+ *           every set cell's cost equals E_n of its flow (as every state
+ *           the library writes is);
  *   mode 1: the coarsest-scale NN seeds (nn_key from ff_init_nn, low 32 bits
  *           = target pixel index; costs evaluated here);
  *   mode 2: seeds from the grid of scale 2n (coarse_flow/coarse_cost), as
@@ -160,7 +162,8 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
  * Equivalent to the corresponding sequence of ff_seed_level,
  * ff_propagate_level and ff_random_search calls (same fields, same
  * evaluation count); radius 3 runs in temporally blocked launches that keep
- * the state on chip.  desc_a/desc_b: descriptor maps of scale n; params: host. */
+ * the state on chip and skip evaluations whose value the consistent state
+ * already fixes.  desc_a/desc_b: descriptor maps of scale n; params: host. */
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,

@@ -35,6 +35,7 @@ template <int TW, int TH>
 struct Geo {
   static constexpr int LW = TW + 2 * kHalo, LH = TH + 2 * kHalo;  // state window
   static constexpr int DW = LW + 2 * kR, DH = LH + 2 * kR;        // descriptor window
+  static_assert(2 * LW * LH < 65536, "queue entries are 16-bit: cell * 2 + vertical");
 };
 
 // E_n(p, f) with image-a descriptors from LDS.  `pa` points at the LDS
@@ -67,7 +68,9 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   __shared__ int32_t s_flow[G::LH * G::LW];
   __shared__ uint32_t s_cost[G::LH * G::LW];
   __shared__ uint4 s_da[G::DH * G::DW];
-  __shared__ unsigned int s_cnt;
+  __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
+  __shared__ uint8_t s_flags[G::LH * G::LW];           // candidate flags of the current half-sweep
+  __shared__ unsigned int s_cnt, s_qlen;
 
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
@@ -75,7 +78,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
   const int gi0 = ti0 - kHalo, gj0 = tj0 - kHalo;  // grid coords of window cell (0, 0)
   const uint4 *Db = reinterpret_cast<const uint4 *>(d.Db);
-  if (tid == 0) s_cnt = 0;
+  if (tid == 0) {
+    s_cnt = 0;
+    s_qlen = 0;
+  }
 
   // image-a descriptors on the level lattice around the window
   {
@@ -142,54 +148,92 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       if (vdj < 0) --mt; else --mb;
       const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
       const int hw = (rr - rl + 1) >> 1, rh = rb - rt;
+      // Cells of this colour in the valid window, thread-strided.
+      auto cell = [&](int k, int &i, int &j) {
+        j = rt + (k < hw * rh ? k / hw : 0);
+        i = rl + ((colour + j + rl) & 1) + 2 * (k % max(hw, 1));
+        return k < hw * rh && i < rr;
+      };
+      // (1) candidate checks (Eq. 2 with the skip rules).  Only evaluations
+      // whose value can matter are queued: the vertical source is not
+      // evaluated when it repeats the horizontal one or the cell's own flow
+      // (its value is then known not to win).  The cell's cost slot holds
+      // the key cost*4 + rank (own 0, horizontal 1, vertical 2; UNSET stays
+      // all ones) and evaluations lower it with an LDS atomic min: the
+      // smallest key is exactly the sequential strict-< choice with ties
+      // kept by the earlier candidate.
       for (int base = 0; base < hw * rh; base += kThreads) {
-        const int k = base + tid;
-        const int j = rt + (k < hw * rh ? k / hw : 0);
-        const int i = rl + ((colour + j + rl) & 1) + 2 * (k % max(hw, 1));
-        const bool live = k < hw * rh && i < rr;
-        int cnt = 0;
-        // candidate checks (Eq. 2 with the skip rules)
+        int i, j;
+        const bool live = cell(base + tid, i, j);
         const int l = (j - gj0) * G::LW + (i - gi0);
-        const int x = i * n, y = j * n;
-        uint32_t c0 = kUnset;
-        int32_t f0 = 0, fh = 0, fv = 0;
-        bool hv = false, vb = false;
+        bool hv = false, vcomp = false;
         if (live) {
-          c0 = s_cost[l];
-          f0 = s_flow[l];
-          const bool set0_ = c0 != kUnset;
+          const uint32_t c0 = s_cost[l];
+          const int32_t f0 = s_flow[l];
+          const bool set0 = c0 != kUnset;
+          const int x = i * n, y = j * n;
+          bool vb = false, vsame_h = false, vsame_0 = false;
+          int32_t fh = 0;
           if (i + hdi >= 0 && i + hdi < Wn && s_cost[l + hdi] != kUnset) {
             fh = s_flow[l + hdi];
             const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
-            hv = !(set0_ && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+            hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
           }
           if (j + vdj >= 0 && j + vdj < Hn && s_cost[l + vdj * G::LW] != kUnset) {
-            fv = s_flow[l + vdj * G::LW];
+            const int32_t fv = s_flow[l + vdj * G::LW];
             const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
             vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
+            vsame_h = hv && fv == fh;
+            vsame_0 = set0 && fv == f0;
           }
+          vcomp = vb && !vsame_h && !vsame_0;
+          s_flags[l] = (uint8_t)(hv | (vb << 1) | (vsame_h << 2) | (vsame_0 << 3) | (vcomp << 4));
+          s_cost[l] = set0 ? c0 << 2 : kUnset;
         }
-        const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-        uint32_t bc = c0;
-        int32_t bf = f0;
-        uint32_t eh = 0;
-        if (hv) {
-          eh = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, x + ffk::flow_x(fh), y + ffk::flow_y(fh));
-          cnt = 1;
-          if (eh < bc) { bc = eh; bf = fh; }
+        const uint64_t bh = __ballot(hv), bv = __ballot(vcomp);
+        const int nh = __popcll(bh), nv = __popcll(bv);
+        int q0 = 0;
+        if ((tid & 63) == 0 && nh + nv) q0 = (int)atomicAdd(&s_qlen, (unsigned)(nh + nv));
+        q0 = __shfl(q0, 0);
+        const int lane = tid & 63;
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        if (hv) s_queue[q0 + __popcll(bh & below)] = (uint16_t)(l << 1);
+        if (vcomp) s_queue[q0 + nh + __popcll(bv & below)] = (uint16_t)((l << 1) | 1);
+      }
+      __syncthreads();
+      // (2) the queued evaluations, densely over all lanes
+      {
+        const int qlen = (int)s_qlen;
+        for (int q = tid; q < qlen; q += kThreads) {
+          const int e = s_queue[q], l = e >> 1, vert = e & 1;
+          const int li = l % G::LW, lj = l / G::LW;
+          const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
+          const uint4 *pa = s_da + (lj + kR) * G::DW + (li + kR);
+          const uint32_t c = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, (gi0 + li) * n + ffk::flow_x(f),
+                                                             (gj0 + lj) * n + ffk::flow_y(f));
+          atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
         }
-        const bool vev = vb && (bc == kUnset || fv != bf);
-        const bool vcomp = vev && !(hv && fv == fh);
-        if (vcomp) {
-          const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, x + ffk::flow_x(fv), y + ffk::flow_y(fv));
-          if (e < bc) { bc = e; bf = fv; }
+      }
+      __syncthreads();
+      if (tid == 0) s_qlen = 0;
+      // (3) new state and evaluation count of every cell
+      for (int base = 0; base < hw * rh; base += kThreads) {
+        int i, j;
+        const bool live = cell(base + tid, i, j);
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        int cnt = 0;
+        if (live) {
+          const uint32_t key = s_cost[l];
+          const int fl = s_flags[l], rank = key == kUnset ? 0 : (int)(key & 3);
+          const bool hv = fl & 1, vb = fl & 2, vsame_h = fl & 4, vsame_0 = fl & 8;
+          cnt = hv;
+          // the vertical source counts as evaluated unless it equals the
+          // best flow after the horizontal step
+          if (vb) cnt += vsame_h ? (rank == 0) : vsame_0 ? (rank == 1) : 1;
+          if (rank) s_flow[l] = s_flow[rank == 1 ? l + hdi : l + vdj * G::LW];
+          s_cost[l] = key == kUnset ? kUnset : key >> 2;
+          if (!owned(i, j)) cnt = 0;
         }
-        if (vev) cnt += 1;  // an evaluation of fv == fh repeats eh, which did not win
-        if (live && (bc != c0 || bf != f0)) {
-          s_cost[l] = bc;
-          s_flow[l] = bf;
-        }
-        if (!owned(i, j)) cnt = 0;
         const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2));
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
       }

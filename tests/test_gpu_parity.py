@@ -282,7 +282,10 @@ def test_run_level_bit_exact(shape, level, T, R, mode):
     Wn, Hn = -(-W // n), -(-H // n)
     key = cflow = ccost = None
     if mode == 0:
+        # a consistent state (cost = E_n of the flow), as ff_run_level requires
         flow, cost = _random_level_state(3, H, W, n)
+        for j, i in zip(*np.nonzero(cost != oracle.UNSET)):
+            cost[j, i] = oracle.cost(Da, Db, n, 3, i * n, j * n, int(flow[j, i, 0]), int(flow[j, i, 1]))
         ne0 = 0
     elif mode == 1:
         Da1 = oracle.descriptor(oracle.blur(ia, 1), 1)
