@@ -41,27 +41,44 @@ struct Geo {
 // E_n(p, f) with image-a descriptors from LDS.  `pa` points at the LDS
 // descriptor of the cell itself; (bx, by) = p + f in pixels, inside the
 // image, so the whole patch lies in the padded map of image b: no clamps,
-// the samples of a patch row are consecutive stored columns (phase order)
-// loaded with immediate offsets; with UNROLL all 49 loads are issued at once.
-template <int LOG2N, int DW, bool UNROLL>
+// and the samples of a patch row are consecutive stored columns (phase
+// order) loaded with immediate offsets.  EV selects the load schedule:
+// 0 rows one after another, 1 rows unrolled (the compiler interleaves),
+// 2 all 49 loads issued before any arithmetic (needs ~200 registers).
+template <int LOG2N, int DW, int EV>
 __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int bx, int by) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n;
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
   const int Wp = W + 2 * P;
   uint32_t s = 0;
   const uint4 *pb = Db + ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
-#pragma unroll UNROLL ? 2 * kR + 1 : 1
-  for (int v = 0; v < 2 * kR + 1; ++v) {
-    const uint4 *ra = pa + (v - kR) * DW - kR;
+  if constexpr (EV == 2) {
+    uint4 b[K * K];
 #pragma unroll
-    for (int u = 0; u < 2 * kR + 1; ++u) s = ffk::sad16(ra[u], pb[u], s);
-    pb += (size_t)n * Wp;
+    for (int v = 0; v < K; ++v)
+#pragma unroll
+      for (int u = 0; u < K; ++u) b[v * K + u] = pb[(size_t)v * n * Wp + u];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+#pragma unroll
+      for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], b[v * K + u], s);
+    }
+  } else {
+#pragma unroll EV ? K : 1
+    for (int v = 0; v < K; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+#pragma unroll
+      for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], pb[u], s);
+      pb += (size_t)n * Wp;
+    }
   }
   return s;
 }
 
 // The run of passes for tile `tile` of one direction `d` (a holds the
 // pair's sizes and the schedule).  All threads of the workgroup call it.
-template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
+template <int LOG2N, int TW, int TH, int kThreads, int EV>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   using G = Geo<TW, TH>;
   constexpr int n = 1 << LOG2N;
@@ -129,7 +146,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if (eval) {
           const int bx = i * n + ffk::flow_x(f), by = j * n + ffk::flow_y(f);
           const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-          s_cost[l] = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, bx, by);
+          s_cost[l] = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
           cnt = owned(i, j);
         }
       }
@@ -209,7 +226,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           const int li = l % G::LW, lj = l / G::LW;
           const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
           const uint4 *pa = s_da + (lj + kR) * G::DW + (li + kR);
-          const uint32_t c = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, (gi0 + li) * n + ffk::flow_x(f),
+          const uint32_t c = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, (gi0 + li) * n + ffk::flow_x(f),
                                                              (gj0 + lj) * n + ffk::flow_y(f));
           atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
         }
@@ -265,7 +282,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         int cnt = 0;
         if (act) {
           const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-          const uint32_t e = eval_cell<LOG2N, G::DW, UNROLL>(pa, Db, W, i * n + fx, j * n + fy);
+          const uint32_t e = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, i * n + fx, j * n + fy);
           cnt = owned(i, j);
           if (e < c0) {
             s_cost[l] = e;
@@ -291,18 +308,18 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 }
 
 // One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
-// four waves per SIMD: the register budget (128 VGPRs) then keeps the 49
+// four waves per SIMD (two with EV = 2): the register budget then keeps the
 // loads of a patch in flight together instead of one after another.
-template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_level(ffh::LevelKArgs a) {
+template <int LOG2N, int TW, int TH, int kThreads, int EV>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  level_body<LOG2N, TW, TH, kThreads, UNROLL>(a, a.dir[wg / tiles], wg % tiles);
+  level_body<LOG2N, TW, TH, kThreads, EV>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
-template <int LOG2N, int TW, int TH, int kThreads, bool UNROLL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_level_batch(
+template <int LOG2N, int TW, int TH, int kThreads, int EV>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level_batch(
     ffh::LevelKArgs base, ffh::BatchStage st) {
   constexpr int n = 1 << LOG2N;
   ffk::for_items(st.total, [&](int item) {
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     d.nn_key = bp.keys[dir];
     d.n_evals = bp.evals + dir;
     d.stream_id = dir;
-    level_body<LOG2N, TW, TH, kThreads, UNROLL>(a, d, local % tiles);
+    level_body<LOG2N, TW, TH, kThreads, EV>(a, d, local % tiles);
     __syncthreads();  // the next item reuses the LDS window
   });
 }
@@ -339,34 +356,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
 struct Variant {
   int tw, th;
 };
-constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}};
-constexpr int kNumVariants = 5;
+constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}, {32, 16}, {16, 16}, {32, 32}};
+constexpr int kNumVariants = 8;
 
-template <int LOG2N, int TW, int TH, int THREADS, bool UNROLL>
+template <int LOG2N, int TW, int TH, int THREADS, int EV>
 hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
   if (batch) {
     if (batch->total <= 0) return hipSuccess;
     // persistent: enough workgroups to fill the chip, a multiple of 8
     const int grid = ((std::min(batch->total, 2048) + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, UNROLL>), dim3(grid), dim3(THREADS), 0, stream, a,
+    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, EV>), dim3(grid), dim3(THREADS), 0, stream, a,
                        *batch);
     return hipGetLastError();
   }
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
-  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, UNROLL>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
   return hipGetLastError();
 }
 
 template <int LOG2N>
 hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int variant, hipStream_t stream) {
   switch (variant) {
-    case 0: return launch_v<LOG2N, 64, 32, 1024, false>(a, batch, stream);
-    case 1: return launch_v<LOG2N, 32, 16, 1024, false>(a, batch, stream);
-    case 2: return launch_v<LOG2N, 32, 16, 256, true>(a, batch, stream);
-    case 3: return launch_v<LOG2N, 16, 16, 256, true>(a, batch, stream);
-    case 4: return launch_v<LOG2N, 32, 32, 512, true>(a, batch, stream);
+    case 0: return launch_v<LOG2N, 64, 32, 1024, 0>(a, batch, stream);
+    case 1: return launch_v<LOG2N, 32, 16, 1024, 0>(a, batch, stream);
+    case 2: return launch_v<LOG2N, 32, 16, 256, 1>(a, batch, stream);
+    case 3: return launch_v<LOG2N, 16, 16, 256, 1>(a, batch, stream);
+    case 4: return launch_v<LOG2N, 32, 32, 512, 1>(a, batch, stream);
+    case 5: return launch_v<LOG2N, 32, 16, 256, 2>(a, batch, stream);
+    case 6: return launch_v<LOG2N, 16, 16, 256, 2>(a, batch, stream);
+    case 7: return launch_v<LOG2N, 32, 32, 512, 2>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
