@@ -45,11 +45,11 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 
 # HBM traffic of the scale-1 level kernel (one direction, one ff_run_level
 # launch on the 1024x436 pair) from two rocprofv3 --pmc runs (FETCH_SIZE,
-# WRITE_SIZE; profiles/level_kernel_counters_1024x436.md), scaled by what the
+# WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10481.1 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "4492553d6ae0d7ce"
+TRAFFIC_BYTES = 10599.9 * 1024 * 2.0 + 3500.2 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "814080d4e9fc0c2e"
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_device.h",
                  "paper_1703_02563_amd/csrc/ff_internal.h")
 
@@ -252,7 +252,8 @@ def main():
     img2 = torch.from_numpy(pair.img2).to(dev)
     from paper_1703_02563_amd import autotune
     tuned = autotune.load(W, H, params)
-    log(f"bench: level-kernel variants {ff.level_variants()} ({'tuned' if tuned else 'defaults'})")
+    log(f"bench: level-kernel variants {ff.level_variants()} ({'tuned' if tuned else 'defaults'}; "
+        f"cache {autotune.DEFAULT_CACHE}, key {autotune._key(W, H, params)})")
     runner = ff.FlowFields(W, H, params, device=dev)
     log(f"bench: {W}x{H} L={c.levels} T={c.iters}, warmup {args.warmup}")
     for _ in range(args.warmup):

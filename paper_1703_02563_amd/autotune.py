@@ -5,8 +5,8 @@ workgroup size, load unrolling; see ff_level_variant_count).  Results never
 depend on the variant; speed does, and differently at every scale.  The tuner
 times complete ff_flow_fields calls with HIP events on the current stream and
 picks, scale by scale (coordinate descent from the current table), the
-fastest variant.  Tables are cached in a JSON file keyed by device name,
-frame size and schedule.
+fastest variant.  Tables are cached in a JSON file keyed by GPU
+architecture, frame size and schedule.
 """
 from __future__ import annotations
 
@@ -21,8 +21,10 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 
 def _key(W, H, params: ffm.Params) -> str:
-    name = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
-    return f"{name}|{W}x{H}|L{params.levels}|T{params.iters}|r{params.radius}"
+    # the architecture (not the marketing name, which depends on how the
+    # runtime was started) identifies the kernels' target
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    return f"{arch}|{W}x{H}|L{params.levels}|T{params.iters}|r{params.radius}"
 
 
 def time_call(fn, reps: int = 10, warmup: int = 2) -> float:
