@@ -295,6 +295,16 @@ ff_status ff_l2norm16_fwd(const float *feat, int64_t pixels, float delta, float 
 ff_status ff_l2norm16_bwd(const float *out, const float *inv_norm, const float *grad, int64_t pixels,
                           float *grad_in, void *stream);
 
+/* Triplet hinge of the descriptor training (learned data term, Sec. 3.5):
+ * cost: float32 [2m], the patch costs of m anchors at their positive
+ * (cost[0..m)) and negative (cost[m..2m)) matches.
+ * loss[0] = weight * sum_k max(0, margin + scale * (cost[k] - cost[m+k]));
+ * grad_cost[k] = +weight*scale, grad_cost[m+k] = -weight*scale where the
+ * hinge is active, 0 elsewhere (the input of ff_cost_f32_bwd).  The sum is
+ * taken in a fixed order (deterministic). */
+ff_status ff_triplet_hinge(const float *cost, int32_t m, float margin, float scale, float weight, float *grad_cost,
+                           float *loss, void *stream);
+
 /* One Adam step (Kingma and Ba 2015) on float32 parameters with bias
  * correction for step >= 1; param_bf16 (nullable) receives the bf16 copy. */
 ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int32_t count, float lr,

@@ -695,6 +695,12 @@ ff_status ff_l2norm16_bwd(const float *out, const float *inv_norm, const float *
   return from_hip(ffh::launch_l2norm16_bwd(out, inv_norm, grad, pixels, grad_in, (hipStream_t)stream));
 }
 
+ff_status ff_triplet_hinge(const float *cost, int32_t m, float margin, float scale, float weight, float *grad_cost,
+                           float *loss, void *stream) {
+  if (!cost || !grad_cost || !loss || m < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_triplet_hinge(cost, m, margin, scale, weight, grad_cost, loss, (hipStream_t)stream));
+}
+
 size_t ff_quantize_scratch_bytes(void) { return 256 * 2 * sizeof(float); }
 
 ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream) {

@@ -257,6 +257,32 @@ __global__ __launch_bounds__(256) void k_l2norm16_bwd(const float4 *y, const flo
                                  r * (gv[k].z - yv[k].z * d), r * (gv[k].w - yv[k].w * d));
 }
 
+// Triplet hinge of m (positive, negative) cost pairs: cost[0..m) positives,
+// cost[m..2m) negatives.  Loss = weight * sum_k max(0, margin + scale *
+// (cost[k] - cost[m + k])); grad[k] = +weight*scale and grad[m + k] =
+// -weight*scale where the hinge is active, else 0.  One workgroup: the
+// loss is summed in a fixed order (thread-strided partials, then a tree),
+// so it is deterministic.
+__global__ __launch_bounds__(1024) void k_triplet_hinge(const float *cost, int m, float margin, float scale,
+                                                        float weight, float *grad, float *loss) {
+  __shared__ float s_part[1024];
+  float acc = 0.0f;
+  for (int k = threadIdx.x; k < m; k += 1024) {
+    const float h = margin + scale * (cost[k] - cost[m + k]);
+    const bool on = h > 0.0f;
+    acc += on ? h : 0.0f;
+    grad[k] = on ? weight * scale : 0.0f;
+    grad[m + k] = on ? -weight * scale : 0.0f;
+  }
+  s_part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_part[threadIdx.x] += s_part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = weight * s_part[0];
+}
+
 // Per-map range of float features (block partials, then one block).
 __global__ __launch_bounds__(256) void k_minmax_partial(const float *f, long long count, float *part) {
   __shared__ float s_lo[256], s_hi[256];
@@ -374,6 +400,12 @@ hipError_t launch_l2norm16_bwd(const float *y, const float *inv_norm, const floa
   if (P > 0)
     hipLaunchKernelGGL(k_l2norm16_bwd, dim3(blocks_of(P)), dim3(256), 0, stream, reinterpret_cast<const float4 *>(y),
                        inv_norm, reinterpret_cast<const float4 *>(g), P, reinterpret_cast<float4 *>(gin));
+  return hipGetLastError();
+}
+
+hipError_t launch_triplet_hinge(const float *cost, int m, float margin, float scale, float weight, float *grad,
+                                float *loss, hipStream_t stream) {
+  hipLaunchKernelGGL(k_triplet_hinge, dim3(1), dim3(1024), 0, stream, cost, m, margin, scale, weight, grad, loss);
   return hipGetLastError();
 }
 

@@ -176,6 +176,8 @@ hipError_t launch_relu_bwd(const uint16_t *act, const float *g, float *gout, uin
                            hipStream_t stream);
 hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, long long count, hipStream_t stream);
 hipError_t launch_image_to_bf16(const uint8_t *img, uint16_t *out, long long count, hipStream_t stream);
+hipError_t launch_triplet_hinge(const float *cost, int m, float margin, float scale, float weight, float *grad,
+                                float *loss, hipStream_t stream);
 hipError_t launch_l2norm16_fwd(const float *f, long long P, float delta, float *y, float *inv_norm,
                                hipStream_t stream);
 hipError_t launch_l2norm16_bwd(const float *y, const float *inv_norm, const float *g, long long P, float *gin,

@@ -25,11 +25,13 @@ def cost_f32(f1: torch.Tensor, f2: torch.Tensor, entries: torch.Tensor, n: int =
     return cost
 
 
-def cost_f32_grad(f1, f2, entries, grad_cost, n: int = 1, radius: int = 3):
+def cost_f32_grad(f1, f2, entries, grad_cost, n: int = 1, radius: int = 3, out=None, acc=None):
+    """Gradients (d/df1, d/df2) of sum_e grad_cost[e] * cost[e]; `out` may
+    name the two output tensors, `acc` the int64 [2, H, W, 16] scratch."""
     H, W, _ = f1.shape
-    acc = torch.empty((2, H, W, 16), dtype=torch.int64, device=f1.device)
-    g1 = torch.empty_like(f1)
-    g2 = torch.empty_like(f2)
+    if acc is None:
+        acc = torch.empty((2, H, W, 16), dtype=torch.int64, device=f1.device)
+    g1, g2 = out if out is not None else (torch.empty_like(f1), torch.empty_like(f2))
     check(lib().ff_cost_f32_bwd(_ptr(f1, torch.float32, "f1"), _ptr(f2, torch.float32, "f2"), W, H, n, radius,
                                 _ptr(entries, torch.int32, "entries"), entries.shape[0],
                                 _ptr(grad_cost, torch.float32, "grad_cost"), _ptr(acc), _ptr(g1), _ptr(g2),
@@ -246,42 +248,59 @@ def triplets(flow: torch.Tensor, keep: torch.Tensor, count: int, rng):
     return TripletSampler(flow, keep).sample(count, rng)
 
 
+def triplet_hinge(cost: torch.Tensor, m: int, margin: float, scale: float, weight: float):
+    """ff_triplet_hinge: (loss [1], grad_cost [2m]) of costs [2m] (positives, then negatives)."""
+    grad = torch.empty_like(cost)
+    loss = torch.empty(1, dtype=torch.float32, device=cost.device)
+    check(lib().ff_triplet_hinge(_ptr(cost, torch.float32), m, margin, scale, weight, _ptr(grad), _ptr(loss),
+                                 _stream()), "ff_triplet_hinge")
+    return loss, grad
+
+
 def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.0, lr: float = 1e-3,
                negatives: int = 1):
-    """One Adam step of the triplet hinge max(0, margin + C(p, pos) - C(p, neg))
+    """One Adam step of the triplet hinge max(0, margin + (C(p, pos) - C(p, neg)) / 49)
     averaged over anchors of every pair in `batch` = [(img1, img2, flow, keep)]
     (or [(img1, img2, TripletSampler)]) with the plain method's flows and
     consistency masks.  The costs enter as means over the 49 patch samples
     (per-pixel squared distances of unit features lie in [0, 4], so the
     margin has a fixed scale).  With negatives > 1 each anchor draws that many
-    candidate negatives and keeps the one of lowest current cost (hardest)."""
+    candidate negatives and keeps the one of lowest current cost (hardest).
+    Every pass runs in the library's kernels: network forward, patch costs,
+    hinge, cost backward into the feature gradient, network backward, Adam.
+    Triplet sampling is host-side data preparation."""
     B = len(batch)
     imgs = torch.stack([b[0] for b in batch] + [b[1] for b in batch])   # [2B, H, W]
     feats, acts = net.forward(net.input_from_images(imgs), keep=True)
-    feats = feats.detach().requires_grad_(True)
-    loss = 0.0
-    total = 0
+    dev = feats.device
+    H, W = imgs.shape[1:]
+    picks = []
     for k, item in enumerate(batch):
         sampler = item[2] if len(item) == 3 else TripletSampler(item[2], item[3])
         pos, neg = sampler.sample(samples, rng, negatives)
-        if len(pos) == 0:
-            continue
-        pe = torch.from_numpy(pos).to(feats.device)
-        ne = torch.from_numpy(neg).to(feats.device)
-        if negatives > 1:
-            with torch.no_grad():
-                cand = ne.reshape(-1, 4).contiguous()
-                c = cost_f32(feats[k].detach(), feats[B + k].detach(), cand, 1, 3).reshape(len(pos), negatives)
-                ne = ne[torch.arange(len(pos), device=ne.device), c.argmin(1)].contiguous()
-        cp = patch_cost(feats[k], feats[B + k], pe, 1, 3)
-        cn = patch_cost(feats[k], feats[B + k], ne, 1, 3)
-        loss = loss + torch.relu(margin + (cp - cn) * (1.0 / 49.0)).sum()
-        total += len(pos)
-    loss = loss / max(total, 1)
-    loss.backward()
-    gws, gbs = net.backward(acts, feats.grad)
+        pe = torch.from_numpy(pos).to(dev)
+        ne = torch.from_numpy(neg).to(dev)
+        if negatives > 1 and len(pos):
+            cand = ne.reshape(-1, 4).contiguous()
+            c = cost_f32(feats[k], feats[B + k], cand, 1, 3).reshape(len(pos), negatives)
+            ne = ne[torch.arange(len(pos), device=dev), c.argmin(1)]
+        picks.append(torch.cat([pe, ne]).contiguous())
+    total = sum(len(e) // 2 for e in picks)
+    grad = torch.empty_like(feats)
+    acc = torch.empty((2, H, W, 16), dtype=torch.int64, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    for k, entries in enumerate(picks):
+        m = len(entries) // 2
+        gcost = torch.empty(0, dtype=torch.float32, device=dev)
+        if m:
+            cost = cost_f32(feats[k], feats[B + k], entries, 1, 3)
+            lk, gcost = triplet_hinge(cost, m, margin, 1.0 / 49.0, 1.0 / max(total, 1))
+            loss += lk
+        # with no entries the backward writes zero gradients
+        cost_f32_grad(feats[k], feats[B + k], entries, gcost, 1, 3, out=(grad[k], grad[B + k]), acc=acc)
+    gws, gbs = net.backward(acts, grad)
     net.adam(gws, gbs, lr=lr)
-    return float(loss.detach())
+    return float(loss)
 
 
 def scale_images(img1: torch.Tensor, img2: torch.Tensor, levels: int) -> torch.Tensor:

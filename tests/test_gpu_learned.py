@@ -275,3 +275,35 @@ def test_learned_path_end_to_end_matches_oracle_on_the_network_features():
     for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
         assert np.array_equal(g[k].cpu().numpy(), o[k]), k
     assert tuple(int(v) for v in g["n_evals"].cpu()) == o["n_evals"]
+
+
+def test_triplet_hinge_kernel_and_gradient_match_autograd():
+    """ff_triplet_hinge + ff_cost_f32_bwd give the loss and feature gradients
+    of relu(margin + (C_pos - C_neg) / 49) summed and weighted, as torch
+    autograd through PatchCost does (same kernels underneath, float64 sums)."""
+    H, W = 40, 56
+    g0 = torch.Generator().manual_seed(9)
+    f1 = torch.randn((H, W, 16), generator=g0).cuda()
+    f2 = torch.randn((H, W, 16), generator=g0).cuda()
+    rng = np.random.default_rng(3)
+    m = 300
+    xs, ys = rng.integers(0, W, m), rng.integers(0, H, m)
+    pos = np.stack([xs, ys, rng.integers(-xs, W - xs), rng.integers(-ys, H - ys)], 1)
+    neg = np.stack([xs, ys, rng.integers(-xs, W - xs), rng.integers(-ys, H - ys)], 1)
+    entries = torch.from_numpy(np.concatenate([pos, neg]).astype(np.int32)).cuda()
+    margin, weight = 1.0, 1.0 / m
+    cost = Lm.cost_f32(f1, f2, entries)
+    loss, gcost = Lm.triplet_hinge(cost, m, margin, 1.0 / 49.0, weight)
+    c = cost.double().cpu()
+    h = margin + (c[:m] - c[m:]) / 49.0
+    assert abs(float(loss) - float(torch.relu(h).sum()) * weight) <= 1e-5 * max(1.0, abs(float(loss)))
+    on = (h > 0).double() * weight / 49.0
+    assert torch.allclose(gcost.double().cpu(), torch.cat([on, -on]), rtol=1e-6, atol=0)
+    assert 0 < int((h > 0).sum()) < m  # both branches exercised
+    g1, g2 = Lm.cost_f32_grad(f1, f2, entries, gcost)
+    a1, a2 = f1.clone().requires_grad_(True), f2.clone().requires_grad_(True)
+    cp = Lm.patch_cost(a1, a2, entries[:m].contiguous())
+    cn = Lm.patch_cost(a1, a2, entries[m:].contiguous())
+    (torch.relu(margin + (cp - cn) / 49.0).sum() * weight).backward()
+    assert torch.allclose(g1, a1.grad, rtol=1e-5, atol=1e-6)
+    assert torch.allclose(g2, a2.grad, rtol=1e-5, atol=1e-6)
