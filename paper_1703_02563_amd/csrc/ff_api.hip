@@ -486,7 +486,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
 // ---- Flow Fields on learned float features ----------------------------------
 
 struct LayoutF32 {
-  size_t q, qscratch, nb, keys, grids, evals, total;
+  size_t q, qscratch, nb, keys, grids, evals, pf[2][kMaxLevels], total;
   size_t N, Npad, M;
 };
 
@@ -498,7 +498,7 @@ static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
   l.M = (size_t)ceil_div(W, nc) * ceil_div(H, nc);
   size_t off = 0;
   l.q = off; off = align256(off + 2 * l.N * 16);
-  l.qscratch = off; off = align256(off + 2 * 512 * sizeof(float));
+  l.qscratch = off; off = align256(off + 2 * ff_quantize_scratch_bytes());
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
   l.grids = off;
@@ -507,6 +507,12 @@ static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
     off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
   }
   l.evals = off; off = align256(off + 2 * sizeof(uint64_t));
+  if (p->radius == 3)  // padded float maps of the blocked level kernel
+    for (int im = 0; im < 2; ++im)
+      for (int lv = 0; lv < p->levels; ++lv) {
+        l.pf[im][lv] = off;
+        off = align256(off + desc_map_bytes(W, H, 1 << lv) * 4);
+      }
   l.total = off;
   return l;
 }
@@ -535,7 +541,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
   uint8_t *q[2];
   for (int im = 0; im < 2; ++im) {
     q[im] = reinterpret_cast<uint8_t *>(base + lay.q) + (size_t)im * lay.N * 16;
-    float *qs = reinterpret_cast<float *>(base + lay.qscratch) + im * 512;
+    float *qs = reinterpret_cast<float *>(base + lay.qscratch + im * ff_quantize_scratch_bytes());
     if ((e = ffh::launch_quantize(im ? feat2[0] : feat1[0], (long long)lay.N * 16, qs, q[im], s)) != hipSuccess)
       return FF_ERR_LAUNCH;
   }
@@ -570,6 +576,38 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
   for (int dr = 0; dr < 2; ++dr) nn.dir[dr] = {q[dr], q[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
   const float *const *feat[2] = {feat1, feat2};
+  if (r == 3) {
+    // temporally blocked level kernels on padded, phase-ordered float maps
+    const uint8_t *pf[2][kMaxLevels];
+    for (int im = 0; im < 2; ++im)
+      for (int lv = 0; lv < L; ++lv) {
+        float *m = reinterpret_cast<float *>(base + lay.pf[im][lv]);
+        if ((e = ffh::launch_pad_features(feat[im][lv], W, H, 1 << lv, m, s)) != hipSuccess) return FF_ERR_LAUNCH;
+        pf[im][lv] = reinterpret_cast<const uint8_t *>(m);
+      }
+    ffh::LevelKArgs k{};
+    k.ndir = 2;
+    k.fcost = 1;
+    for (int dr = 0; dr < 2; ++dr) {
+      k.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
+      k.dir[dr].stream_id = dr;
+    }
+    for (int lv = L - 1; lv >= 0; --lv) {
+      for (int dr = 0; dr < 2; ++dr) {
+        k.dir[dr].Da = pf[dr][lv];
+        k.dir[dr].Db = pf[dr ^ 1][lv];
+        k.dir[dr].flow = gflow[lv][dr];
+        k.dir[dr].cost = gcost[lv][dr];
+        k.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+        k.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+        k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+      }
+      const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
+      if ((e = run_level_blocked(k, W, H, lv, params, mode, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    }
+    return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
+                                            keep_bwd, s));
+  }
   ffh::LevelArgs a{};
   a.ndir = 2;
   a.fcost = 1;
@@ -701,7 +739,7 @@ ff_status ff_triplet_hinge(const float *cost, int32_t m, float margin, float sca
   return from_hip(ffh::launch_triplet_hinge(cost, m, margin, scale, weight, grad_cost, loss, (hipStream_t)stream));
 }
 
-size_t ff_quantize_scratch_bytes(void) { return 256 * 2 * sizeof(float); }
+size_t ff_quantize_scratch_bytes(void) { return (256 + 1) * 2 * sizeof(float); }
 
 ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream) {
   if (!f || !scratch || !q || count < 0) return FF_ERR_ARG;

@@ -307,15 +307,34 @@ __global__ __launch_bounds__(256) void k_minmax_partial(const float *f, long lon
   }
 }
 
-// q = clamp(rint((f - lo) * (255 / (hi - lo))), 0, 255); the range is the
-// min and max over the partials (order-independent).
-__global__ __launch_bounds__(256) void k_quantize(const float *f, long long count, const float *part, int nparts,
-                                                  uint8_t *q) {
+// The range over the partials (min and max are order-independent), into
+// part[2 * nparts], part[2 * nparts + 1].
+__global__ __launch_bounds__(256) void k_minmax_final(float *part, int nparts) {
+  __shared__ float s_lo[256], s_hi[256];
   float lo = INFINITY, hi = -INFINITY;
-  for (int k = 0; k < nparts; ++k) {
+  for (int k = threadIdx.x; k < nparts; k += 256) {
     lo = fminf(lo, part[2 * k]);
     hi = fmaxf(hi, part[2 * k + 1]);
   }
+  s_lo[threadIdx.x] = lo;
+  s_hi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + w]);
+      s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * nparts] = s_lo[0];
+    part[2 * nparts + 1] = s_hi[0];
+  }
+}
+
+// q = clamp(rint((f - lo) * (255 / (hi - lo))), 0, 255).
+__global__ __launch_bounds__(256) void k_quantize(const float *f, long long count, const float *range, uint8_t *q) {
+  const float lo = range[0], hi = range[1];
   const float s = hi > lo ? 255.0f / (hi - lo) : 0.0f;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -414,7 +433,8 @@ constexpr int kQuantParts = 256;
 hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_minmax_partial, dim3(kQuantParts), dim3(256), 0, stream, f, count, part);
-  hipLaunchKernelGGL(k_quantize, dim3(blocks_of(count)), dim3(256), 0, stream, f, count, part, kQuantParts, q);
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, stream, part, kQuantParts);
+  hipLaunchKernelGGL(k_quantize, dim3(blocks_of(count)), dim3(256), 0, stream, f, count, part + 2 * kQuantParts, q);
   return hipGetLastError();
 }
 

@@ -86,9 +86,30 @@ __global__ __launch_bounds__(256) void k_fixed_to_float(const int64_t *acc, floa
   if (i < count) out[i] = (float)((double)acc[i] * (1.0 / kFix));
 }
 
+// Padded, phase-ordered copy of a float feature map (the layout of the
+// descriptor maps with 64-byte entries): one thread per stored entry.
+__global__ __launch_bounds__(256) void k_pad_features(const float4 *f, int W, int H, int log2n, float4 *out) {
+  const int P = ffk::desc_pad(1 << log2n), Wp = W + 2 * P, Hp = H + 2 * P;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, yp = blockIdx.y;
+  if (c >= Wp || yp >= Hp) return;
+  const int x = clampi(ffk::desc_pixel(c, log2n, Wp) - P, W - 1), y = clampi(yp - P, H - 1);
+  const float4 *src = f + ((size_t)y * W + x) * 4;
+  float4 *dst = out + ((size_t)yp * Wp + c) * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dst[k] = src[k];
+}
+
 }  // namespace
 
 namespace ffh {
+
+hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream) {
+  const int P = ffk::desc_pad(n);
+  const dim3 grid((W + 2 * P + 255) / 256, H + 2 * P);
+  hipLaunchKernelGGL(k_pad_features, grid, dim3(256), 0, stream, reinterpret_cast<const float4 *>(f), W, H,
+                     __builtin_ctz(n), reinterpret_cast<float4 *>(out));
+  return hipGetLastError();
+}
 
 hipError_t launch_cost_fwd(const CostArgs &a, hipStream_t stream) {
   if (a.count <= 0) return hipSuccess;

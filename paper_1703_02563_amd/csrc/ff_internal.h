@@ -96,9 +96,12 @@ struct LevelKArgs {
   uint64_t seed;
   int t_begin, t_end, T;
   int mode;
+  int fcost;    // 0: byte descriptor maps; 1: padded float feature maps (64-byte entries)
   int tiles_x;  // set by launch_level
   int halo[4];
 };
+// Padded, phase-ordered copy of a float [H][W][16] feature map of scale n.
+hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream);
 hipError_t launch_level(LevelKArgs a, hipStream_t stream);
 void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();

@@ -76,15 +76,58 @@ __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__re
   return s;
 }
 
+// Float learned-feature cost (Eq. 3 with the squared-difference data term)
+// of cell pixel (ax, ay) and target (bx, by) on padded, phase-ordered float
+// maps (64-byte entries, same indexing as the descriptor maps): float32
+// fused multiply-adds in the order v, u, c; returned as its bit pattern.
+template <int LOG2N>
+__device__ __forceinline__ uint32_t eval_cell_f32(const float4 *__restrict__ A, const float4 *__restrict__ B, int W,
+                                                  int ax, int ay, int bx, int by) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const size_t row = (size_t)n * (W + 2 * P) * 4;
+  const float4 *pa = A + 4 * ffk::desc_index(ax - kR * n, ay - kR * n, LOG2N, W);
+  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+  float s = 0.0f;
+#pragma unroll 1
+  for (int v = 0; v < K; ++v) {
+    // the 2 x 28 loads of a patch row first (one round trip per row), then
+    // the 112 multiply-adds in their fixed order
+    float4 x[4 * K], y[4 * K];
+#pragma unroll
+    for (int q = 0; q < 4 * K; ++q) {
+      x[q] = pa[q];
+      y[q] = pb[q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4 * K; ++q) {
+      float e = x[q].x - y[q].x;
+      s = __fmaf_rn(e, e, s);
+      e = x[q].y - y[q].y;
+      s = __fmaf_rn(e, e, s);
+      e = x[q].z - y[q].z;
+      s = __fmaf_rn(e, e, s);
+      e = x[q].w - y[q].w;
+      s = __fmaf_rn(e, e, s);
+    }
+    pa += row;
+    pb += row;
+  }
+  return __float_as_uint(s);
+}
+
 // The run of passes for tile `tile` of one direction `d` (a holds the
 // pair's sizes and the schedule).  All threads of the workgroup call it.
-template <int LOG2N, int TW, int TH, int kThreads, int EV>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   using G = Geo<TW, TH>;
   constexpr int n = 1 << LOG2N;
   __shared__ int32_t s_flow[G::LH * G::LW];
   __shared__ uint32_t s_cost[G::LH * G::LW];
-  __shared__ uint4 s_da[G::DH * G::DW];
+  // byte descriptors of image a on the level lattice (float features are
+  // read from their padded map instead); 64-bit keys for float costs
+  __shared__ uint4 s_da[F32 ? 1 : G::DH * G::DW];
+  __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
   __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
   __shared__ uint8_t s_flags[G::LH * G::LW];           // candidate flags of the current half-sweep
   __shared__ unsigned int s_cnt, s_qlen;
@@ -101,7 +144,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   }
 
   // image-a descriptors on the level lattice around the window
-  {
+  if constexpr (!F32) {
     const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
     for (int k = tid; k < G::DH * G::DW; k += kThreads) {
       const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
@@ -109,6 +152,16 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     }
   }
   __syncthreads();
+  // E_n of grid cell (i, j) and target pixel (bx, by)
+  auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
+    if constexpr (F32) {
+      return eval_cell_f32<LOG2N>(reinterpret_cast<const float4 *>(d.Da), reinterpret_cast<const float4 *>(d.Db), W,
+                                  i * n, j * n, bx, by);
+    } else {
+      const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+      return eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
+    }
+  };
 
   int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
   auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
@@ -144,9 +197,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         s_flow[l] = f;
         s_cost[l] = c;
         if (eval) {
-          const int bx = i * n + ffk::flow_x(f), by = j * n + ffk::flow_y(f);
-          const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-          s_cost[l] = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
+          s_cost[l] = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
           cnt = owned(i, j);
         }
       }
@@ -205,7 +256,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           }
           vcomp = vb && !vsame_h && !vsame_0;
           s_flags[l] = (uint8_t)(hv | (vb << 1) | (vsame_h << 2) | (vsame_0 << 3) | (vcomp << 4));
-          s_cost[l] = set0 ? c0 << 2 : kUnset;
+          if constexpr (F32)
+            s_key[l] = set0 ? (unsigned long long)c0 << 2 : ~0ull;
+          else
+            s_cost[l] = set0 ? c0 << 2 : kUnset;
         }
         const uint64_t bh = __ballot(hv), bv = __ballot(vcomp);
         const int nh = __popcll(bh), nv = __popcll(bv);
@@ -223,12 +277,13 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         const int qlen = (int)s_qlen;
         for (int q = tid; q < qlen; q += kThreads) {
           const int e = s_queue[q], l = e >> 1, vert = e & 1;
-          const int li = l % G::LW, lj = l / G::LW;
+          const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
           const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
-          const uint4 *pa = s_da + (lj + kR) * G::DW + (li + kR);
-          const uint32_t c = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, (gi0 + li) * n + ffk::flow_x(f),
-                                                             (gj0 + lj) * n + ffk::flow_y(f));
-          atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+          const uint32_t c = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+          if constexpr (F32)
+            atomicMin(&s_key[l], ((unsigned long long)c << 2) | (unsigned long long)(1 + vert));
+          else
+            atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
         }
       }
       __syncthreads();
@@ -240,15 +295,28 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         const int l = (j - gj0) * G::LW + (i - gi0);
         int cnt = 0;
         if (live) {
-          const uint32_t key = s_cost[l];
-          const int fl = s_flags[l], rank = key == kUnset ? 0 : (int)(key & 3);
+          bool unset;
+          int rank;
+          uint32_t cost;
+          if constexpr (F32) {
+            const unsigned long long key = s_key[l];
+            unset = key == ~0ull;
+            rank = unset ? 0 : (int)(key & 3);
+            cost = unset ? kUnset : (uint32_t)(key >> 2);
+          } else {
+            const uint32_t key = s_cost[l];
+            unset = key == kUnset;
+            rank = unset ? 0 : (int)(key & 3);
+            cost = unset ? kUnset : key >> 2;
+          }
+          const int fl = s_flags[l];
           const bool hv = fl & 1, vb = fl & 2, vsame_h = fl & 4, vsame_0 = fl & 8;
           cnt = hv;
           // the vertical source counts as evaluated unless it equals the
           // best flow after the horizontal step
           if (vb) cnt += vsame_h ? (rank == 0) : vsame_0 ? (rank == 1) : 1;
           if (rank) s_flow[l] = s_flow[rank == 1 ? l + hdi : l + vdj * G::LW];
-          s_cost[l] = key == kUnset ? kUnset : key >> 2;
+          s_cost[l] = cost;
           if (!owned(i, j)) cnt = 0;
         }
         const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2));
@@ -281,8 +349,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         }
         int cnt = 0;
         if (act) {
-          const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-          const uint32_t e = eval_cell<LOG2N, G::DW, EV>(pa, Db, W, i * n + fx, j * n + fy);
+          const uint32_t e = evalc(i, j, i * n + fx, j * n + fy);
           cnt = owned(i, j);
           if (e < c0) {
             s_cost[l] = e;
@@ -315,6 +382,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV 
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
   level_body<LOG2N, TW, TH, kThreads, EV>(a, a.dir[wg / tiles], wg % tiles);
+}
+
+// Float learned features (padded float maps in LevelKDir::Da/Db).
+template <int LOG2N, int TW, int TH, int kThreads>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_level_f32(
+    ffh::LevelKArgs a) {
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  level_body<LOG2N, TW, TH, kThreads, 1, true>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
@@ -374,6 +450,29 @@ hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipS
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
   hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
   return hipGetLastError();
+}
+
+template <int LOG2N, int TW, int TH, int THREADS>
+hipError_t launch_f32(const ffh::LevelKArgs &a, hipStream_t stream) {
+  ffh::LevelKArgs b = a;
+  b.tiles_x = (a.Wn + TW - 1) / TW;
+  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  hipLaunchKernelGGL((k_level_f32<LOG2N, TW, TH, THREADS>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  return hipGetLastError();
+}
+
+// Float features: 32x16 tiles at the two finest scales, 16x16 above.
+hipError_t dispatch_f32(const ffh::LevelKArgs &a, int log2n, hipStream_t stream) {
+  switch (log2n) {
+    case 0: return launch_f32<0, 32, 16, 256>(a, stream);
+    case 1: return launch_f32<1, 32, 16, 256>(a, stream);
+    case 2: return launch_f32<2, 16, 16, 256>(a, stream);
+    case 3: return launch_f32<3, 16, 16, 256>(a, stream);
+    case 4: return launch_f32<4, 16, 16, 256>(a, stream);
+    case 5: return launch_f32<5, 16, 16, 256>(a, stream);
+    case 6: return launch_f32<6, 16, 16, 256>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int LOG2N>
@@ -439,6 +538,7 @@ static int log2_of(int n) {
 
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
   const int l2 = log2_of(a.n);
+  if (a.fcost) return dispatch_f32(a, l2, stream);
   return dispatch(a, nullptr, l2, blocked_variant(l2), stream);
 }
 
