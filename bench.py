@@ -252,7 +252,8 @@ def main():
     img2 = torch.from_numpy(pair.img2).to(dev)
     from paper_1703_02563_amd import autotune
     tuned = autotune.load(W, H, params)
-    log(f"bench: level-kernel variants {ff.level_variants()} ({'tuned' if tuned else 'defaults'}; "
+    log(f"bench: level-kernel variants {ff.level_variants()}, passes per launch {ff.level_passes(0)} "
+        f"({'tuned' if tuned else 'defaults'}; "
         f"cache {autotune.DEFAULT_CACHE}, key {autotune._key(W, H, params)})")
     runner = ff.FlowFields(W, H, params, device=dev)
     log(f"bench: {W}x{H} L={c.levels} T={c.iters}, warmup {args.warmup}")

@@ -329,6 +329,16 @@ int32_t ff_level_variant_count(void);
 int32_t ff_get_level_variant(int32_t log2n);
 ff_status ff_set_level_variant(int32_t log2n, int32_t variant);
 
+/* Most propagation steps per temporally blocked launch at scale 2^log2n, for
+ * the byte-descriptor path (cost_kind 0) or the learned float features
+ * (cost_kind 1); 0 = as many as the kernel's halo allows (the default).
+ * Shorter runs recompute less halo but need more launches; results never
+ * change.  Process-wide table (host), like the variant table.  The setter
+ * returns FF_ERR_ARG for log2n outside [0, 6], cost_kind not 0/1 or passes
+ * outside [0, 64]; the getter -1. */
+int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind);
+ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes);
+
 /* Bytes of device workspace ff_flow_fields needs for a W x H pair (host). */
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);
 

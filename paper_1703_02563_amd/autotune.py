@@ -45,27 +45,43 @@ def time_call(fn, reps: int = 10, warmup: int = 2) -> float:
 
 
 def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int = 10, verbose: bool = False):
-    """Returns (table, log) with table[log2 n] = fastest variant."""
+    """Returns (table, log): table = {"variants": [...], "passes": [...]},
+    the fastest level-kernel variant and then the fastest run length (most
+    propagation steps per launch, 0 = no limit) of every scale."""
     H, W = img1.shape
     runner = ffm.FlowFields(W, H, params, device=img1.device)
     nvar = int(ffm.lib().ff_level_variant_count())
     table = ffm.level_variants()
+    passes = ffm.level_passes(0)
     log = []
-    for lv in range(params.levels):
+
+    def best_of(choices, apply):
         best = None
-        for v in range(nvar):
+        for c in choices:
+            apply(c)
+            ms = time_call(lambda: runner(img1, img2), reps=reps)
+            log.append({"log2n": lv, "choice": c, "ms": ms})
+            if verbose:
+                print(f"autotune: log2n={lv} {c} {ms:.4f} ms", flush=True)
+            if best is None or ms < best[1]:
+                best = (c, ms)
+        return best[0]
+
+    for lv in range(params.levels):
+        def set_variant(v):
             trial = list(table)
             trial[lv] = v
             ffm.set_level_variants(trial)
-            ms = time_call(lambda: runner(img1, img2), reps=reps)
-            log.append({"log2n": lv, "variant": v, "ms": ms})
-            if verbose:
-                print(f"autotune: log2n={lv} variant={v} {ms:.4f} ms", flush=True)
-            if best is None or ms < best[1]:
-                best = (v, ms)
-        table[lv] = best[0]
-    ffm.set_level_variants(table)
-    return table, log
+        table[lv] = best_of([("variant", v) for v in range(nvar)], lambda c: set_variant(c[1]))[1]
+        ffm.set_level_variants(table)
+    for lv in range(params.levels):
+        def set_passes(p):
+            trial = list(passes)
+            trial[lv] = p
+            ffm.set_level_passes(trial, 0)
+        passes[lv] = best_of([("passes", p) for p in (0, 3, 2, 1)], lambda c: set_passes(c[1]))[1]
+        ffm.set_level_passes(passes, 0)
+    return {"variants": table, "passes": passes}, log
 
 
 def load(W: int, H: int, params: ffm.Params, path: str = DEFAULT_CACHE) -> bool:
@@ -74,10 +90,14 @@ def load(W: int, H: int, params: ffm.Params, path: str = DEFAULT_CACHE) -> bool:
         return False
     with open(path) as f:
         cache = json.load(f)
-    table = cache.get(_key(W, H, params))
-    if table is None:
+    entry = cache.get(_key(W, H, params))
+    if entry is None:
         return False
-    ffm.set_level_variants(table)
+    if isinstance(entry, list):  # variants only
+        entry = {"variants": entry}
+    ffm.set_level_variants(entry["variants"])
+    if "passes" in entry:
+        ffm.set_level_passes(entry["passes"], 0)
     return True
 
 
@@ -86,6 +106,6 @@ def save(W: int, H: int, params: ffm.Params, table, path: str = DEFAULT_CACHE) -
     if os.path.exists(path):
         with open(path) as f:
             cache = json.load(f)
-    cache[_key(W, H, params)] = list(table)
+    cache[_key(W, H, params)] = table if isinstance(table, dict) else list(table)
     with open(path, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -89,10 +89,10 @@ ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, 
 }
 
 // End of the longest run of passes starting at t0 whose halo fits the level
-// kernel's window.
-int run_end(int t0, int T) {
+// kernel's window, at most maxp passes (maxp <= 0: no limit).
+int run_end(int t0, int T, int maxp) {
   int t1 = t0 + 1, h[4];
-  while (t1 < T) {
+  while (t1 < T && (maxp <= 0 || t1 - t0 < maxp)) {
     ffh::level_halo(t0, t1 + 1, h);
     if (h[0] > ffh::kLevelHalo || h[1] > ffh::kLevelHalo || h[2] > ffh::kLevelHalo || h[3] > ffh::kLevelHalo) break;
     ++t1;
@@ -117,7 +117,7 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   k.T = T;
   int t0 = 0;
   while (t0 < T) {
-    const int t1 = run_end(t0, T);
+    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, k.fcost));
     ffh::level_halo(t0, t1, k.halo);
     k.t_begin = t0;
     k.t_end = t1;
@@ -470,7 +470,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.T = T;
     int t0 = 0;
     while (t0 < T) {
-      const int t1 = run_end(t0, T);
+      const int t1 = run_end(t0, T, ffh::get_level_passes(lv, 0));
       ffh::level_halo(t0, t1, k.halo);
       k.t_begin = t0;
       k.t_end = t1;
@@ -747,6 +747,12 @@ ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t 
 }
 
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
+
+int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind) { return ffh::get_level_passes(log2n, cost_kind); }
+
+ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes) {
+  return ffh::set_level_passes(log2n, cost_kind, passes) ? FF_OK : FF_ERR_ARG;
+}
 
 int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }
 

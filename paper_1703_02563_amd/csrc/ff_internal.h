@@ -108,6 +108,8 @@ int level_variant_count();
 int get_level_variant(int log2n);
 bool set_level_variant(int log2n, int variant);
 bool level_stepwise(int log2n);  // the table selects the step-wise schedule for this scale
+int get_level_passes(int log2n, int fcost);  // most propagation steps per blocked launch (0: no limit)
+bool set_level_passes(int log2n, int fcost, int passes);
 
 // ---- batches of pairs of different sizes (one launch per stage) ----------
 constexpr int kMaxBatch = 256;

@@ -506,6 +506,11 @@ hipError_t dispatch(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
 
 // Per-scale variant table (index log2 n); written by ff_set_level_variant.
 int g_variant[7] = {2, 2, 3, 3, 3, 3, 3};
+// Most propagation steps per launch, per cost kind and scale (0: as many as
+// the halo allows).  Shorter runs recompute less halo at the price of more
+// launches; the float features' evaluations are expensive enough that one
+// step per launch is fastest at every scale (measured at 1024x436).
+int g_passes[2][7] = {{0, 0, 0, 0, 0, 0, 0}, {1, 1, 1, 1, 1, 1, 1}};
 
 }  // namespace
 
@@ -516,6 +521,16 @@ int level_variant_count() { return kNumVariants + 1; }  // + the step-wise sched
 int get_level_variant(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant[log2n] : -1; }
 
 bool level_stepwise(int log2n) { return get_level_variant(log2n) == kNumVariants; }
+
+int get_level_passes(int log2n, int fcost) {
+  return (log2n >= 0 && log2n < 7 && (fcost == 0 || fcost == 1)) ? g_passes[fcost][log2n] : -1;
+}
+
+bool set_level_passes(int log2n, int fcost, int passes) {
+  if (log2n < 0 || log2n >= 7 || (fcost != 0 && fcost != 1) || passes < 0 || passes > 64) return false;
+  g_passes[fcost][log2n] = passes;
+  return true;
+}
 
 // Blocked kernel variant used where the table asks for the step-wise
 // schedule but the caller only has the blocked form (batches, ff_run_level).

@@ -166,6 +166,16 @@ def set_level_variants(table) -> None:
         check(lib().ff_set_level_variant(k, int(v)), "ff_set_level_variant")
 
 
+def level_passes(cost_kind: int = 0) -> list:
+    """Most propagation steps per blocked launch, per scale (0 = no limit)."""
+    return [int(lib().ff_get_level_passes(l2, cost_kind)) for l2 in range(7)]
+
+
+def set_level_passes(table, cost_kind: int = 0) -> None:
+    for l2, p in enumerate(table):
+        check(lib().ff_set_level_passes(l2, cost_kind, int(p)), "ff_set_level_passes")
+
+
 def workspace_bytes(W: int, H: int, params: Params) -> int:
     p = params.to_c()
     return int(lib().ff_workspace_bytes(W, H, p))

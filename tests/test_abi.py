@@ -84,3 +84,15 @@ def test_descriptor_map_bytes():
     assert lib.ff_descriptor_map_bytes(0, 5, 1) == 0
     assert lib.ff_descriptor_map_bytes(5, 5, 3) == 0
     assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0
+
+
+def test_level_passes_table_validation():
+    lib = ff.lib()
+    assert lib.ff_get_level_passes(0, 0) == 0 and lib.ff_get_level_passes(7, 0) == -1
+    assert lib.ff_get_level_passes(0, 2) == -1
+    assert lib.ff_set_level_passes(0, 0, 65) == ffi.FF_ERR_ARG
+    assert lib.ff_set_level_passes(-1, 0, 1) == ffi.FF_ERR_ARG
+    assert lib.ff_set_level_passes(0, 3, 1) == ffi.FF_ERR_ARG
+    old = lib.ff_get_level_passes(2, 1)
+    assert lib.ff_set_level_passes(2, 1, 3) == ffi.FF_OK and lib.ff_get_level_passes(2, 1) == 3
+    assert lib.ff_set_level_passes(2, 1, old) == ffi.FF_OK

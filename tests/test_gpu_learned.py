@@ -217,9 +217,10 @@ def test_quantize_matches_oracle():
     assert np.array_equal(q, oracle.quantize_u8(f))
 
 
-@pytest.mark.parametrize("shape,L,T", [((40, 56), 3, 4), ((33, 1), 2, 3), ((1, 1), 1, 1), ((120, 160), 3, 4),
-                                       ((61, 95), 4, 5)])
-def test_learned_flow_fields_bit_exact(shape, L, T):
+@pytest.mark.parametrize("shape,L,T,passes", [((40, 56), 3, 4, 0), ((33, 1), 2, 3, 0), ((1, 1), 1, 1, 0),
+                                              ((120, 160), 3, 4, 0), ((61, 95), 4, 5, 0), ((61, 95), 4, 5, 1),
+                                              ((120, 160), 3, 4, 2)])
+def test_learned_flow_fields_bit_exact(shape, L, T, passes):
     H, W = shape
     pad = 10
     canvas = feature_canvas(11 + H, H + 2 * pad, W + 2 * pad)
@@ -228,8 +229,14 @@ def test_learned_flow_fields_bit_exact(shape, L, T):
     m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
     prm = ff.Params(levels=L, iters=T)
     o = oracle.flow_fields_f32(m1, m2, L, T, nthreads=NT)
-    g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2], prm)
-    torch.cuda.synchronize()
+    saved = ff.level_passes(1)
+    try:
+        ff.set_level_passes([passes] * 7, 1)
+        g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2],
+                               prm)
+        torch.cuda.synchronize()
+    finally:
+        ff.set_level_passes(saved, 1)
     for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
         assert np.array_equal(g[k].cpu().numpy(), o[k]), k
     for k in ("cost_fwd", "cost_bwd"):

@@ -316,3 +316,22 @@ def test_run_level_bit_exact(shape, level, T, R, mode):
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_run_length_does_not_change_results(passes):
+    """Shorter runs of steps per blocked launch give the same field."""
+    p = make_pair(1)
+    c = CONFIG_PARAMS[1]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
+    saved = ff.level_passes(0)
+    try:
+        ff.set_level_passes([passes] * 7, 0)
+        g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+        for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+            assert np.array_equal(host(g[k]), o[k]), k
+        assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"])
+        assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
+    finally:
+        ff.set_level_passes(saved, 0)
