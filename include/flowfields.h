@@ -167,7 +167,12 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
-                       uint64_t *n_evals, void *stream);
+                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, void *stream);
+
+/* Scratch bytes of ff_run_level (host): a second grid of scale 2^level
+ * (flow and cost), which the launches of a scale alternate with flow/cost
+ * so that no launch reads cells it is writing.  0 for invalid sizes. */
+size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level);
 
 /* One pair of a batch (host struct; every pointer is a device pointer):
  * images [H][W]; outputs as for ff_flow_fields; keep_bwd and n_evals ([2])

@@ -31,7 +31,7 @@ int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) /
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc[2][kMaxLevels], desc1, nb, keys, grids, evals, total;
+  size_t hsum, blur, desc[2][kMaxLevels], desc1, nb, keys, grids, sgrids, evals, total;
   size_t N, Npad, M;
   int L;
 };
@@ -65,9 +65,27 @@ Layout layout(int W, int H, const ff_params *p) {
     const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
     off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
   }
+  l.sgrids = off;
+  for (int lv = 0; lv < l.L; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
   l.evals = off; off = align256(off + 2 * sizeof(uint64_t));
   l.total = off;
   return l;
+}
+
+// Second buffers of the level grids (flow then cost per direction), carved
+// from `base + off` for scales 0..L-1.
+void carve_second_grids(char *base, size_t off, int W, int H, int L, int32_t *sflow[][2], uint32_t *scost[][2]) {
+  for (int lv = 0; lv < L; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    for (int dr = 0; dr < 2; ++dr) {
+      sflow[lv][dr] = reinterpret_cast<int32_t *>(base + off) + (size_t)dr * 2 * cells;
+      scost[lv][dr] = reinterpret_cast<uint32_t *>(sflow[lv][dr] + cells);
+    }
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
 }
 
 ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int radius, int16_t *flow,
@@ -89,22 +107,42 @@ ffh::LevelArgs one_dir_args(const uint8_t *Da, const uint8_t *Db, int W, int H, 
 }
 
 // End of the longest run of passes starting at t0 whose halo fits the level
-// kernel's window, at most maxp passes (maxp <= 0: no limit).
-int run_end(int t0, int T, int maxp) {
+// kernel's window (halo cells per side), at most maxp passes (maxp <= 0: no
+// limit).
+int run_end(int t0, int T, int maxp, int halo = ffh::kLevelHalo) {
   int t1 = t0 + 1, h[4];
   while (t1 < T && (maxp <= 0 || t1 - t0 < maxp)) {
     ffh::level_halo(t0, t1 + 1, h);
-    if (h[0] > ffh::kLevelHalo || h[1] > ffh::kLevelHalo || h[2] > ffh::kLevelHalo || h[3] > ffh::kLevelHalo) break;
+    if (h[0] > halo || h[1] > halo || h[2] > halo || h[3] > halo) break;
     ++t1;
   }
   return t1;
 }
 
+// Runs of passes of one scale: [t0, t1) pairs; the number of launches.
+int level_runs(int lv, int T, int fcost, int runs[][2]) {
+  int m = 0, t0 = 0;
+  while (t0 < T) {
+    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), fcost ? ffh::kLevelHaloF32 : ffh::kLevelHalo);
+    runs[m][0] = t0;
+    runs[m][1] = t1;
+    ++m;
+    t0 = t1;
+  }
+  return m;
+}
+
 // The passes of one scale as temporally blocked launches: each launch runs
-// the longest run of passes whose halo fits the kernel's window.  k.dir[]
-// must hold the per-direction pointers; the scale fields are set here.
+// the longest run of passes whose halo fits the kernel's window (and the
+// run-length table).  k.dir[] must hold the per-direction pointers, flow/cost
+// being the level grid that receives the result; the scale fields are set
+// here.  A continuing launch reads the grid the previous launch wrote and
+// writes the other one (sflow/scost: one more grid per direction, needed
+// only when the scale takes more than one launch), so that no workgroup
+// reads cells another workgroup of the same launch is writing; the last
+// launch writes flow/cost.
 hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_params *p, int first_mode,
-                             hipStream_t s) {
+                             hipStream_t s, int32_t *const *sflow = nullptr, uint32_t *const *scost = nullptr) {
   const int n = 1 << lv, T = p->iters;
   k.W = W;
   k.H = H;
@@ -115,16 +153,47 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   k.Rn = rs_radius(n, p->R_num, p->R_den);
   k.seed = p->seed;
   k.T = T;
-  int t0 = 0;
-  while (t0 < T) {
-    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, k.fcost));
-    ffh::level_halo(t0, t1, k.halo);
-    k.t_begin = t0;
-    k.t_end = t1;
-    k.mode = t0 > 0 ? ffh::kLevelContinue : first_mode;
+  int runs[64][2];
+  const int m = level_runs(lv, T, k.fcost, runs);
+  const bool two = m > 1 || first_mode == ffh::kLevelContinue;
+  if (two && (!sflow || !scost)) return hipErrorInvalidValue;
+  int32_t *main_f[ffh::kMaxDirs];
+  uint32_t *main_c[ffh::kMaxDirs];
+  for (int dr = 0; dr < k.ndir; ++dr) {
+    main_f[dr] = k.dir[dr].flow;
+    main_c[dr] = k.dir[dr].cost;
+  }
+  for (int r = 0; r < m; ++r) {
+    const bool to_main = ((m - 1 - r) & 1) == 0;  // the last launch writes the level grid
+    for (int dr = 0; dr < k.ndir; ++dr) {
+      if (r > 0 || first_mode == ffh::kLevelContinue) {
+        // a continuing run reads what the previous run wrote (the caller's
+        // state for a first continuing run: it sits in flow/cost and is
+        // copied to the second buffer below when the first run writes there)
+        k.dir[dr].flow_in = r > 0 ? k.dir[dr].flow : main_f[dr];
+        k.dir[dr].cost_in = r > 0 ? k.dir[dr].cost : main_c[dr];
+      }
+      k.dir[dr].flow = to_main ? main_f[dr] : sflow[dr];
+      k.dir[dr].cost = to_main ? main_c[dr] : scost[dr];
+    }
+    if (r == 0 && first_mode == ffh::kLevelContinue && to_main) {
+      // the first continuing run would read and write the caller's grid:
+      // move the input to the second buffer first
+      const size_t cells = (size_t)k.Wn * k.Hn;
+      for (int dr = 0; dr < k.ndir; ++dr) {
+        hipError_t e = hipMemcpyAsync(sflow[dr], main_f[dr], cells * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(scost[dr], main_c[dr], cells * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        k.dir[dr].flow_in = sflow[dr];
+        k.dir[dr].cost_in = scost[dr];
+      }
+    }
+    ffh::level_halo(runs[r][0], runs[r][1], k.halo);
+    k.t_begin = runs[r][0];
+    k.t_end = runs[r][1];
+    k.mode = r > 0 ? ffh::kLevelContinue : first_mode;
     hipError_t e = ffh::launch_level(k, s);
     if (e != hipSuccess) return e;
-    t0 = t1;
   }
   return hipSuccess;
 }
@@ -259,14 +328,20 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                           (hipStream_t)stream));
 }
 
+size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level) {
+  if (!dims_ok(W, H) || level < 0 || level >= kMaxLevels) return 0;
+  return (size_t)ceil_div(W, 1 << level) * ceil_div(H, 1 << level) * 2 * sizeof(uint32_t);
+}
+
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
-                       uint64_t *n_evals, void *stream) {
+                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, void *stream) {
   if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !params_ok(params) || level < 0 ||
       level >= kMaxLevels || stream_id < 0 || stream_id > 0xFF || mode < 0 || mode > 2 || (mode == 1 && !nn_key) ||
       (mode == 2 && (!coarse_flow || !coarse_cost)))
     return FF_ERR_ARG;
+  if (!scratch || scratch_bytes < ff_run_level_scratch_bytes(W, H, level)) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int n = 1 << level, r = params->radius, T = params->iters;
   if (r == 3) {
@@ -282,7 +357,9 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
     k.dir[0].n_evals = reinterpret_cast<unsigned long long *>(n_evals);
     k.dir[0].stream_id = stream_id;
     const int first = mode == 1 ? ffh::kLevelInit : (mode == 2 ? ffh::kLevelSeed : ffh::kLevelContinue);
-    return from_hip(run_level_blocked(k, W, H, level, params, first, s));
+    int32_t *sf[1] = {static_cast<int32_t *>(scratch)};
+    uint32_t *sc[1] = {reinterpret_cast<uint32_t *>(sf[0] + (size_t)ceil_div(W, n) * ceil_div(H, n))};
+    return from_hip(run_level_blocked(k, W, H, level, params, first, s, sf, sc));
   }
   ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, r, flow, cost, n_evals);
   a.level = level;
@@ -411,6 +488,7 @@ ff_status ff_batch_table(const ff_pair *pairs, int32_t npairs, const ff_params *
       }
       g = align256(g + 2 * cells * 2 * sizeof(uint32_t));
     }
+    carve_second_grids(b, lay.sgrids, q.W, q.H, L, t.sflow, t.scost);
     t.keep[0] = q.keep_fwd;
     t.keep[1] = q.keep_bwd;
     t.evals = reinterpret_cast<unsigned long long *>(q.n_evals ? q.n_evals
@@ -468,15 +546,17 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.Rn = rs_radius(n, params->R_num, params->R_den);
     k.seed = params->seed;
     k.T = T;
-    int t0 = 0;
-    while (t0 < T) {
-      const int t1 = run_end(t0, T, ffh::get_level_passes(lv, 0));
-      ffh::level_halo(t0, t1, k.halo);
-      k.t_begin = t0;
-      k.t_end = t1;
-      k.mode = t0 > 0 ? ffh::kLevelContinue : (lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed);
+    int runs[64][2];
+    const int m = level_runs(lv, T, 0, runs);
+    for (int r = 0; r < m; ++r) {
+      // runs alternate between the two grid buffers; the last writes gflow/gcost
+      st.dst = ((m - 1 - r) & 1) ? 1 : 0;
+      st.src = st.dst ^ 1;
+      ffh::level_halo(runs[r][0], runs[r][1], k.halo);
+      k.t_begin = runs[r][0];
+      k.t_end = runs[r][1];
+      k.mode = r > 0 ? ffh::kLevelContinue : (lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed);
       if ((e = ffh::launch_batch_level(k, st, s)) != hipSuccess) return FF_ERR_LAUNCH;
-      t0 = t1;
     }
   }
   fill([&](int, int H) { return 2 * H; });
@@ -486,7 +566,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
 // ---- Flow Fields on learned float features ----------------------------------
 
 struct LayoutF32 {
-  size_t q, qscratch, nb, keys, grids, evals, pf[2][kMaxLevels], total;
+  size_t q, qscratch, nb, keys, grids, sgrids, evals, pf[2][kMaxLevels], total;
   size_t N, Npad, M;
 };
 
@@ -503,6 +583,11 @@ static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
   l.grids = off;
   for (int lv = 1; lv < p->levels; ++lv) {
+    const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
+    off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
+  }
+  l.sgrids = off;
+  for (int lv = 0; lv < p->levels; ++lv) {
     const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
     off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
   }
@@ -585,6 +670,9 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
         if ((e = ffh::launch_pad_features(feat[im][lv], W, H, 1 << lv, m, s)) != hipSuccess) return FF_ERR_LAUNCH;
         pf[im][lv] = reinterpret_cast<const uint8_t *>(m);
       }
+    int32_t *sflow[kMaxLevels][2];
+    uint32_t *scost[kMaxLevels][2];
+    carve_second_grids(base, lay.sgrids, W, H, L, sflow, scost);
     ffh::LevelKArgs k{};
     k.ndir = 2;
     k.fcost = 1;
@@ -603,7 +691,8 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
         k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
       const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
-      if ((e = run_level_blocked(k, W, H, lv, params, mode, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if ((e = run_level_blocked(k, W, H, lv, params, mode, s, sflow[lv], scost[lv])) != hipSuccess)
+        return FF_ERR_LAUNCH;
     }
     return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                             keep_bwd, s));
@@ -835,6 +924,9 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
 
   if (r == 3) {
     // temporally blocked level kernels: one launch per run of passes
+    int32_t *sflow[kMaxLevels][2];
+    uint32_t *scost[kMaxLevels][2];
+    carve_second_grids(base, lay.sgrids, W, H, L, sflow, scost);
     ffh::LevelKArgs k{};
     k.ndir = 2;
     for (int dr = 0; dr < 2; ++dr) {
@@ -862,7 +954,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         continue;
       }
       const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
-      if ((e = run_level_blocked(k, W, H, lv, params, mode, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if ((e = run_level_blocked(k, W, H, lv, params, mode, s, sflow[lv], scost[lv])) != hipSuccess)
+        return FF_ERR_LAUNCH;
     }
     return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                             keep_bwd, s));

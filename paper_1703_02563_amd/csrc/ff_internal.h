@@ -75,14 +75,17 @@ hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
 // follows pass t iff t < T - 1.  halo[] = half-sweeps reading the left,
 // right, top, bottom side over the run (at most kLevelHalo each).
 constexpr int kLevelHalo = 6;
+constexpr int kLevelHaloF32 = 2;  // the float-feature kernels keep a halo of 2: one step per launch
 constexpr int kLevelContinue = 0;  // state from the level grid in global memory
 constexpr int kLevelInit = 1;      // coarsest scale: flows from the NN keys
 constexpr int kLevelSeed = 2;      // seeds from the coarser grid, other cells UNSET
 struct LevelKDir {
   const uint8_t *Da;
   const uint8_t *Db;
-  int32_t *flow;
+  int32_t *flow;            // written: the owned cells after the run
   uint32_t *cost;
+  const int32_t *flow_in;   // read by a continuing run (never the buffer it writes:
+  const uint32_t *cost_in;  // other workgroups of the launch write theirs meanwhile)
   const int32_t *cflow;
   const uint32_t *ccost;
   const uint64_t *nn_key;
@@ -128,6 +131,8 @@ struct BatchPair {
   uint64_t *keys[2];
   int32_t *gflow[kMaxScales][2];
   uint32_t *gcost[kMaxScales][2];
+  int32_t *sflow[kMaxScales][2];  // second buffer of each level grid (runs alternate)
+  uint32_t *scost[kMaxScales][2];
   uint8_t *keep[2];
   unsigned long long *evals;  // [2]
 };
@@ -137,6 +142,7 @@ struct BatchStage {
   const BatchPair *pairs;
   int npairs, total;
   int L, n, lv;  // scales of the schedule, scale of this stage
+  int src, dst;  // level stages: grid buffer read (continuing runs) and written, 0 = gflow/gcost, 1 = sflow/scost
   int prefix[kMaxBatch + 1];
 };
 hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream);

@@ -31,9 +31,9 @@ using ffk::kUnset;
 constexpr int kR = 3;
 constexpr int kHalo = ffh::kLevelHalo;
 
-template <int TW, int TH>
+template <int TW, int TH, int HALO = kHalo>
 struct Geo {
-  static constexpr int LW = TW + 2 * kHalo, LH = TH + 2 * kHalo;  // state window
+  static constexpr int LW = TW + 2 * HALO, LH = TH + 2 * HALO;  // state window
   static constexpr int DW = LW + 2 * kR, DH = LH + 2 * kR;        // descriptor window
   static_assert(2 * LW * LH < 65536, "queue entries are 16-bit: cell * 2 + vertical");
 };
@@ -116,17 +116,51 @@ __device__ __forceinline__ uint32_t eval_cell_f32(const float4 *__restrict__ A, 
   return __float_as_uint(s);
 }
 
+// As eval_cell_f32 with image a's lattice samples from LDS: `pa` points at
+// the cell's 4 float4 in an LDS window of row length DW cells.
+template <int LOG2N, int DW>
+__device__ __forceinline__ uint32_t eval_cell_f32_lds(const float4 *pa, const float4 *__restrict__ B, int W, int bx,
+                                                      int by) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const size_t row = (size_t)n * (W + 2 * P) * 4;
+  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+  float s = 0.0f;
+#pragma unroll 1
+  for (int v = 0; v < K; ++v) {
+    float4 y[4 * K];
+#pragma unroll
+    for (int q = 0; q < 4 * K; ++q) y[q] = pb[q];
+    __builtin_amdgcn_sched_barrier(0);
+    const float4 *ra = pa + ((v - kR) * DW - kR) * 4;
+#pragma unroll
+    for (int q = 0; q < 4 * K; ++q) {
+      const float4 x = ra[q];
+      float e = x.x - y[q].x;
+      s = __fmaf_rn(e, e, s);
+      e = x.y - y[q].y;
+      s = __fmaf_rn(e, e, s);
+      e = x.z - y[q].z;
+      s = __fmaf_rn(e, e, s);
+      e = x.w - y[q].w;
+      s = __fmaf_rn(e, e, s);
+    }
+    pb += row;
+  }
+  return __float_as_uint(s);
+}
+
 // The run of passes for tile `tile` of one direction `d` (a holds the
 // pair's sizes and the schedule).  All threads of the workgroup call it.
-template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
-  using G = Geo<TW, TH>;
+  using G = Geo<TW, TH, HALO>;
   constexpr int n = 1 << LOG2N;
   __shared__ int32_t s_flow[G::LH * G::LW];
   __shared__ uint32_t s_cost[G::LH * G::LW];
   // byte descriptors of image a on the level lattice (float features are
   // read from their padded map instead); 64-bit keys for float costs
   __shared__ uint4 s_da[F32 ? 1 : G::DH * G::DW];
+  __shared__ float4 s_daf[F32 ? 4 * G::DH * G::DW : 1];
   __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
   __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
   __shared__ uint8_t s_flags[G::LH * G::LW];           // candidate flags of the current half-sweep
@@ -136,7 +170,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
   const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
   const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
-  const int gi0 = ti0 - kHalo, gj0 = tj0 - kHalo;  // grid coords of window cell (0, 0)
+  const int gi0 = ti0 - HALO, gj0 = tj0 - HALO;  // grid coords of window cell (0, 0)
   const uint4 *Db = reinterpret_cast<const uint4 *>(d.Db);
   if (tid == 0) {
     s_cnt = 0;
@@ -150,13 +184,19 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
       s_da[k] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
     }
+  } else {
+    const float4 *Da = reinterpret_cast<const float4 *>(d.Da);
+    for (int k = tid; k < 4 * G::DH * G::DW; k += kThreads) {
+      const int c = k >> 2, vi = gi0 - kR + c % G::DW, vj = gj0 - kR + c / G::DW;
+      s_daf[k] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
+    }
   }
   __syncthreads();
   // E_n of grid cell (i, j) and target pixel (bx, by)
   auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
     if constexpr (F32) {
-      return eval_cell_f32<LOG2N>(reinterpret_cast<const float4 *>(d.Da), reinterpret_cast<const float4 *>(d.Db), W,
-                                  i * n, j * n, bx, by);
+      const float4 *pa = s_daf + 4 * ((j - gj0 + kR) * G::DW + (i - gi0 + kR));
+      return eval_cell_f32_lds<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by);
     } else {
       const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
       return eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
@@ -181,8 +221,8 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         uint32_t c = kUnset;
         bool eval = false;
         if (a.mode == ffh::kLevelContinue) {
-          f = d.flow[(size_t)j * Wn + i];
-          c = d.cost[(size_t)j * Wn + i];
+          f = d.flow_in[(size_t)j * Wn + i];
+          c = d.cost_in[(size_t)j * Wn + i];
         } else if (a.mode == ffh::kLevelInit) {
           const uint32_t q = (uint32_t)d.nn_key[(size_t)j * Wn + i];
           f = ffk::pack_flow((int)(q % (uint32_t)W) - i * n, (int)(q / (uint32_t)W) - j * n);
@@ -386,11 +426,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV 
 
 // Float learned features (padded float maps in LevelKDir::Da/Db).
 template <int LOG2N, int TW, int TH, int kThreads>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_level_f32(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_level_f32(
     ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  level_body<LOG2N, TW, TH, kThreads, 1, true>(a, a.dir[wg / tiles], wg % tiles);
+  level_body<LOG2N, TW, TH, kThreads, 1, true, ffh::kLevelHaloF32>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
@@ -413,8 +453,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV 
     ffh::LevelKDir d;
     d.Da = bp.desc[dir][lv];
     d.Db = bp.desc[dir ^ 1][lv];
-    d.flow = bp.gflow[lv][dir];
-    d.cost = bp.gcost[lv][dir];
+    d.flow = st.dst ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
+    d.cost = st.dst ? bp.scost[lv][dir] : bp.gcost[lv][dir];
+    d.flow_in = st.src ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
+    d.cost_in = st.src ? bp.scost[lv][dir] : bp.gcost[lv][dir];
     d.cflow = lv + 1 < st.L ? bp.gflow[lv + 1][dir] : nullptr;
     d.ccost = lv + 1 < st.L ? bp.gcost[lv + 1][dir] : nullptr;
     d.nn_key = bp.keys[dir];
@@ -461,11 +503,11 @@ hipError_t launch_f32(const ffh::LevelKArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Float features: 32x16 tiles at the two finest scales, 16x16 above.
+// Float features: 16x16 tiles (image a's samples staged in LDS, 64 bytes each).
 hipError_t dispatch_f32(const ffh::LevelKArgs &a, int log2n, hipStream_t stream) {
   switch (log2n) {
-    case 0: return launch_f32<0, 32, 16, 256>(a, stream);
-    case 1: return launch_f32<1, 32, 16, 256>(a, stream);
+    case 0: return launch_f32<0, 16, 16, 256>(a, stream);
+    case 1: return launch_f32<1, 16, 16, 256>(a, stream);
     case 2: return launch_f32<2, 16, 16, 256>(a, stream);
     case 3: return launch_f32<3, 16, 16, 256>(a, stream);
     case 4: return launch_f32<4, 16, 16, 256>(a, stream);

@@ -139,10 +139,12 @@ def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: 
               coarse_flow=None, coarse_cost=None, n_evals=None):
     """All steps of one scale, in place on (flow, cost); see ff_run_level."""
     W, H = _map_dims(desc_a, desc_b, 1 << level)
+    nbytes = int(lib().ff_run_level_scratch_bytes(W, H, level))
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=desc_a.device)
     check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, level, params.to_c(),
                              stream_id, mode, _ptr(nn_key, torch.int64), _ptr(coarse_flow, torch.int16),
                              _ptr(coarse_cost, torch.int32), _ptr(flow, torch.int16), _ptr(cost, torch.int32),
-                             _ptr(n_evals, torch.int64), _stream()), "ff_run_level")
+                             _ptr(scratch), nbytes, _ptr(n_evals, torch.int64), _stream()), "ff_run_level")
 
 
 def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: bool = True):

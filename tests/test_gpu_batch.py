@@ -97,3 +97,29 @@ def test_graph_replay_repeats_eager_results():
         for k in range(len(eager)):
             for key in KEYS:
                 assert np.array_equal(got[k][key], eager[k][key]), (rep, k, key)
+
+
+def test_batch_with_multi_launch_scales_equals_single_pair_path():
+    """Run-length limits make every scale take several launches: the batch
+    path alternates its grid buffers like the single-pair path."""
+    from paper_1703_02563_amd.batch import BatchFlowFields
+    c = CONFIG_PARAMS[4]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    shapes = [(192, 256), (231, 300), (200, 451)]
+    sp = ff.level_passes(0)
+    try:
+        ff.set_level_passes([1, 2, 1, 3, 2, 0, 0], 0)
+        b = BatchFlowFields(shapes, prm)
+        imgs = []
+        for k, shp in enumerate(shapes):
+            p = make_pair(4, k, shape=shp)
+            i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+            imgs.append((i1, i2))
+            b.set_pair(k, i1, i2)
+        b.run()
+        for k, (i1, i2) in enumerate(imgs):
+            g = ff.flow_fields(i1, i2, prm)
+            for key in ("flow_fwd", "flow_bwd", "keep_fwd"):
+                assert torch.equal(b.out[k][key], g[key]), (k, key)
+    finally:
+        ff.set_level_passes(sp, 0)

@@ -335,3 +335,75 @@ def test_run_length_does_not_change_results(passes):
         assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
     finally:
         ff.set_level_passes(saved, 0)
+
+
+@pytest.mark.parametrize("table", [([4, 7, 6, 6, 6, 3, 3], [1, 2, 2, 3, 3, 0, 0]),
+                                   ([2, 5, 3, 7, 6, 3, 3], [1, 1, 1, 1, 1, 1, 1]),
+                                   ([0, 1, 4, 2, 8, 3, 3], [3, 2, 0, 1, 2, 0, 0])])
+@pytest.mark.parametrize("case", [(2, 0), (5, 16)])
+def test_mixed_variant_and_run_length_tables_bit_exact(table, case):
+    """Launch tables mixing variants and run lengths per scale (as the
+    autotuner writes them) on 1024x436 pairs: every scale that takes several
+    launches alternates its two grid buffers."""
+    cfg, k = case
+    p = make_pair(cfg, k)
+    c = CONFIG_PARAMS[2]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
+    sv, sp = ff.level_variants(), ff.level_passes(0)
+    try:
+        ff.set_level_variants(table[0])
+        ff.set_level_passes(table[1], 0)
+        for _ in range(2):
+            g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+            for key in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+                assert np.array_equal(host(g[key]), o[key]), key
+            assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"])
+            assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
+    finally:
+        ff.set_level_variants(sv)
+        ff.set_level_passes(sp, 0)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("passes", [1, 2])
+def test_run_level_multi_launch_bit_exact(mode, passes):
+    """ff_run_level split into several launches (odd and even counts, a
+    continuing first run included) equals the oracle's step sequence."""
+    H, W, level, T = 130, 200, 0, 5
+    n = 1
+    prm = ff.Params(levels=1, iters=T)
+    ia, ib = random_images(950 + mode + passes, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    if mode == 0:
+        flow, cost = _random_level_state(5, H, W, n)
+        for j, i in zip(*np.nonzero(cost != oracle.UNSET)):
+            cost[j, i] = oracle.cost(Da, Db, n, 3, i * n, j * n, int(flow[j, i, 0]), int(flow[j, i, 1]))
+        ne = 0
+        gf, gc = dev(flow), dev(cost.view(np.int32))
+        cflow = ccost = None
+    else:
+        cflow, ccost = _random_level_state(6, H, W, 2)
+        flow, cost, ne = oracle.seed_level(cflow, ccost, Da, Db, n)
+        gf = torch.empty((H, W, 2), dtype=torch.int16, device="cuda")
+        gc = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    ef, ec = flow, cost
+    for t in range(T):
+        ef, ec, k = oracle.propagate(Da, Db, n, t, ef, ec, nthreads=NT)
+        ne += k
+        if t < T - 1:
+            ef, ec, k = oracle.random_search(Da, Db, n, 1, prm.seed, 0, level, t, ef, ec, nthreads=NT)
+            ne += k
+    sp = ff.level_passes(0)
+    try:
+        ff.set_level_passes([passes] * 7, 0)
+        cnt = counter()
+        ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, prm, 0, mode, gf, gc,
+                     coarse_flow=None if cflow is None else dev(cflow),
+                     coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
+    finally:
+        ff.set_level_passes(sp, 0)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ne
