@@ -32,7 +32,7 @@ namespace {
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kTilesPerChunk = 1024;  // <= 2048: the tile index must fit 11 bits
+constexpr int kTilesPerChunk = 512;   // <= 2048: the tile index must fit 11 bits
 constexpr int kQB = 2;                // 32-query blocks per wave (B operand reuse)
 constexpr int kWaves = 4;
 constexpr int kNbPad = (1 << 20) - 1;
@@ -74,6 +74,15 @@ __device__ __forceinline__ int opaque_neg(int v) {
   return r;
 }
 
+// Pins a loaded value to a register after `after` is computed (an empty
+// asm with register operands; it touches no memory), so the load that
+// produces it is waited for only at the end of the iteration that
+// prefetches it.
+__device__ __forceinline__ int pin(int v, int after) {
+  asm volatile("" : "+v"(v) : "v"(after));
+  return v;
+}
+
 __device__ __forceinline__ long load_i8x8(const uint8_t *p) {
   // 8 descriptor bytes -> 8 int8 (v - 128)
   return (long)(*reinterpret_cast<const unsigned long long *>(p) ^ 0x8080808080808080ull);
@@ -110,14 +119,34 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
     for (int r = 0; r < 16; ++r) best[qb][r] = INT_MIN;
 
   const v16i zero = {0};
-  for (int t = t0 + wave; t < t1; t += 2 * kWaves) {
-    // two tiles per step (the second repeats the first at the odd tail)
+  // Operands of the two tiles of step t (the second repeats the first at the
+  // odd tail): loads from a clamped index, so they need no branch; padding
+  // references get zero bytes by a select and the padding norm from nb.
+  struct Step {
+    long ba, bb;
+    int na, nb;
+  };
+  auto fetch = [&](int t) {
     const int tb = (t + kWaves < t1) ? t + kWaves : t;
     const int ra = t * 32 + col, rb = tb * 32 + col;
-    const long ba = ra < N ? load_i8x8(d.Dr + (size_t)ra * 16 + kh * 8) : 0;
-    const long bb = rb < N ? load_i8x8(d.Dr + (size_t)rb * 16 + kh * 8) : 0;
-    const int nka = opaque_neg((d.nb[ra] << 11) | (t - t0));
-    const int nkb = opaque_neg((d.nb[rb] << 11) | (tb - t0));
+    Step st;
+    st.ba = load_i8x8(d.Dr + (size_t)min(ra, N - 1) * 16 + kh * 8);
+    st.bb = load_i8x8(d.Dr + (size_t)min(rb, N - 1) * 16 + kh * 8);
+    if (ra >= N) st.ba = 0;
+    if (rb >= N) st.bb = 0;
+    st.na = d.nb[ra];
+    st.nb = d.nb[rb];
+    return st;
+  };
+  Step cur = fetch(t0 + wave);
+  for (int t = t0 + wave; t < t1; t += 2 * kWaves) {
+    // the next step's operands are in flight while this step computes
+    const int tn = t + 2 * kWaves;
+    const Step nxt = fetch(tn < t1 ? tn : t);
+    const int tb = (t + kWaves < t1) ? t + kWaves : t;
+    const long ba = cur.ba, bb = cur.bb;
+    const int nka = opaque_neg((cur.na << 11) | (t - t0));
+    const int nkb = opaque_neg((cur.nb << 11) | (tb - t0));
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
       const v16i acc_a = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], ba, zero, 0, 0, 0);
@@ -129,6 +158,9 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
         best[qb][r] = max(best[qb][r], max(sa, sb));
       }
     }
+    cur = nxt;
+    cur.na = pin(cur.na, best[kQB - 1][15]);
+    cur.nb = pin(cur.nb, best[kQB - 1][15]);
   }
 
 #pragma unroll
