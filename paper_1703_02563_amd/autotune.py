@@ -44,10 +44,12 @@ def time_call(fn, reps: int = 10, warmup: int = 2) -> float:
     return times[len(times) // 2]
 
 
-def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int = 10, verbose: bool = False):
+def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int = 10, verbose: bool = False,
+         rounds: int = 2):
     """Returns (table, log): table = {"variants": [...], "passes": [...]},
     the fastest level-kernel variant and then the fastest run length (most
-    propagation steps per launch, 0 = no limit) of every scale."""
+    propagation steps per launch, 0 = no limit) of every scale, by
+    coordinate descent repeated `rounds` times (the two interact)."""
     H, W = img1.shape
     runner = ffm.FlowFields(W, H, params, device=img1.device)
     nvar = int(ffm.lib().ff_level_variant_count())
@@ -67,20 +69,21 @@ def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int =
                 best = (c, ms)
         return best[0]
 
-    for lv in range(params.levels):
-        def set_variant(v):
-            trial = list(table)
-            trial[lv] = v
-            ffm.set_level_variants(trial)
-        table[lv] = best_of([("variant", v) for v in range(nvar)], lambda c: set_variant(c[1]))[1]
-        ffm.set_level_variants(table)
-    for lv in range(params.levels):
-        def set_passes(p):
-            trial = list(passes)
-            trial[lv] = p
-            ffm.set_level_passes(trial, 0)
-        passes[lv] = best_of([("passes", p) for p in (0, 3, 2, 1)], lambda c: set_passes(c[1]))[1]
-        ffm.set_level_passes(passes, 0)
+    for _ in range(rounds):
+        for lv in range(params.levels):
+            def set_variant(v):
+                trial = list(table)
+                trial[lv] = v
+                ffm.set_level_variants(trial)
+            table[lv] = best_of([("variant", v) for v in range(nvar)], lambda c: set_variant(c[1]))[1]
+            ffm.set_level_variants(table)
+        for lv in range(params.levels):
+            def set_passes(p):
+                trial = list(passes)
+                trial[lv] = p
+                ffm.set_level_passes(trial, 0)
+            passes[lv] = best_of([("passes", p) for p in (0, 3, 2, 1)], lambda c: set_passes(c[1]))[1]
+            ffm.set_level_passes(passes, 0)
     return {"variants": table, "passes": passes}, log
 
 

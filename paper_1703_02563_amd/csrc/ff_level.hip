@@ -467,15 +467,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV 
   });
 }
 
-// Tile / workgroup variants of the level kernel.  Index kNumVariants of the
+// Tile / workgroup variants of the level kernel (tile, threads, load
+// schedule: see launch_n).  Index kNumVariants of the
 // per-scale table selects the step-wise schedule instead (one launch per
 // half-sweep or random-search step over all cells, no halo): better where
 // the grid is too small to give every compute unit a tile.
 struct Variant {
   int tw, th;
 };
-constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}, {32, 16}, {16, 16}, {32, 32}};
-constexpr int kNumVariants = 8;
+constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}, {32, 16},
+                                 {16, 16}, {32, 32}, {8, 8},   {16, 16}, {16, 16}};
+constexpr int kNumVariants = 11;
 
 template <int LOG2N, int TW, int TH, int THREADS, int EV>
 hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
@@ -528,6 +530,9 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 5: return launch_v<LOG2N, 32, 16, 256, 2>(a, batch, stream);
     case 6: return launch_v<LOG2N, 16, 16, 256, 2>(a, batch, stream);
     case 7: return launch_v<LOG2N, 32, 32, 512, 2>(a, batch, stream);
+    case 8: return launch_v<LOG2N, 8, 8, 256, 2>(a, batch, stream);
+    case 9: return launch_v<LOG2N, 16, 16, 512, 2>(a, batch, stream);
+    case 10: return launch_v<LOG2N, 16, 16, 1024, 1>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
