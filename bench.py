@@ -122,7 +122,10 @@ def batched_throughput(ff, torch, reps):
     shapes = batch_shapes()
     prm = ff.Params(levels=c.levels, iters=c.iters, radius=c.radius, R_num=c.R_num, R_den=c.R_den, eps=c.eps,
                     seed=c.seed)
-    b = BatchFlowFields(shapes, prm)
+    from paper_1703_02563_amd import autotune
+    tables = autotune.load_batch(len(shapes), prm)
+    log(f"bench: batch launch tables {tables if tables else '(process-wide)'}")
+    b = BatchFlowFields(shapes, prm, tables=tables)
     for k, shp in enumerate(shapes):
         p = make_pair(4, k, shape=shp)
         b.set_pair(k, torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda())

@@ -52,7 +52,14 @@ def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int =
     coordinate descent repeated `rounds` times (the two interact)."""
     H, W = img1.shape
     runner = ffm.FlowFields(W, H, params, device=img1.device)
+    return tune_call(lambda: runner(img1, img2), params.levels, reps, verbose, rounds)
+
+
+def tune_call(fn, levels: int, reps: int = 10, verbose: bool = False, rounds: int = 2, variants=None):
+    """tune() for any timed call `fn` (a batch, for instance); `variants`
+    restricts the variant indices tried."""
     nvar = int(ffm.lib().ff_level_variant_count())
+    choices = list(range(nvar)) if variants is None else list(variants)
     table = ffm.level_variants()
     passes = ffm.level_passes(0)
     log = []
@@ -61,7 +68,7 @@ def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int =
         best = None
         for c in choices:
             apply(c)
-            ms = time_call(lambda: runner(img1, img2), reps=reps)
+            ms = time_call(fn, reps=reps)
             log.append({"log2n": lv, "choice": c, "ms": ms})
             if verbose:
                 print(f"autotune: log2n={lv} {c} {ms:.4f} ms", flush=True)
@@ -70,14 +77,14 @@ def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int =
         return best[0]
 
     for _ in range(rounds):
-        for lv in range(params.levels):
+        for lv in range(levels):
             def set_variant(v):
                 trial = list(table)
                 trial[lv] = v
                 ffm.set_level_variants(trial)
-            table[lv] = best_of([("variant", v) for v in range(nvar)], lambda c: set_variant(c[1]))[1]
+            table[lv] = best_of([("variant", v) for v in choices], lambda c: set_variant(c[1]))[1]
             ffm.set_level_variants(table)
-        for lv in range(params.levels):
+        for lv in range(levels):
             def set_passes(p):
                 trial = list(passes)
                 trial[lv] = p
@@ -85,6 +92,29 @@ def tune(img1: torch.Tensor, img2: torch.Tensor, params: ffm.Params, reps: int =
             passes[lv] = best_of([("passes", p) for p in (0, 3, 2, 1)], lambda c: set_passes(c[1]))[1]
             ffm.set_level_passes(passes, 0)
     return {"variants": table, "passes": passes}, log
+
+
+def batch_key(npairs: int, params: ffm.Params) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    return f"{arch}|batch{npairs}|L{params.levels}|T{params.iters}|r{params.radius}"
+
+
+def load_batch(npairs: int, params: ffm.Params, path: str = DEFAULT_CACHE):
+    """The cached table of batches of `npairs` pairs, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(batch_key(npairs, params))
+
+
+def save_entry(key: str, table, path: str = DEFAULT_CACHE) -> None:
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    cache[key] = table
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
 
 
 def load(W: int, H: int, params: ffm.Params, path: str = DEFAULT_CACHE) -> bool:
