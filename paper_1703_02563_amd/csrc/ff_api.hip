@@ -828,7 +828,7 @@ ff_status ff_triplet_hinge(const float *cost, int32_t m, float margin, float sca
   return from_hip(ffh::launch_triplet_hinge(cost, m, margin, scale, weight, grad_cost, loss, (hipStream_t)stream));
 }
 
-size_t ff_quantize_scratch_bytes(void) { return (256 + 1) * 2 * sizeof(float); }
+size_t ff_quantize_scratch_bytes(void) { return (1024 + 1) * 2 * sizeof(float); }
 
 ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream) {
   if (!f || !scratch || !q || count < 0) return FF_ERR_ARG;

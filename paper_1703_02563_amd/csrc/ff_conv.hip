@@ -75,32 +75,50 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ffh::ConvArgs a) {
     __builtin_memcpy(&ub, bv, 16);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
   } else {
+    // every operand of the 9 taps is loaded before the first product, so
+    // the wave waits for memory once instead of once per product
+    constexpr int KC = CIN / 16;
+    uint4 ua[9 * KC], ub[9 * KC];
+    int valid = 0;  // bit tap: the tap's pixel lies in the image (else zero padding)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int sx = x + tap % 3 - 1, sy = y + tap / 3 - 1;
-      const bool sv = pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H;
+      valid |= (pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H) << tap;
       // addresses stay inside the buffers even for lanes whose value is zeroed
       const int cx = ffk::clampi(sx, a.W - 1), cy = ffk::clampi(sy, a.H - 1);
       const uint4 *src = reinterpret_cast<const uint4 *>(in + ((img * a.H + cy) * a.W + cx) * CIN);
       const uint4 *wsrc = reinterpret_cast<const uint4 *>(a.w + ((size_t)min(col, COUT - 1) * 9 + tap) * CIN);
 #pragma unroll
-      for (int cc = 0; cc < CIN / 16; ++cc) {
-        const uint4 ua = sv ? src[cc * 2 + kh] : make_uint4(0, 0, 0, 0);
-        const uint4 ub = col < COUT ? wsrc[cc * 2 + kh] : make_uint4(0, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
+      for (int cc = 0; cc < KC; ++cc) {
+        ua[tap * KC + cc] = src[cc * 2 + kh];
+        ub[tap * KC + cc] = wsrc[cc * 2 + kh];
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 9 * KC; ++k) {
+      const uint4 va = (valid >> (k / KC)) & 1 ? ua[k] : zero4;
+      const uint4 vb = col < COUT ? ub[k] : zero4;
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(va), as_bf16x8(vb), acc, 0, 0, 0);
     }
   }
   if (col >= COUT) return;
   const float bias = a.bias ? a.bias[col] : 0.0f;
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    v[r] = acc[r] + bias;
+    if (a.relu) v[r] = fmaxf(v[r], 0.0f);
+  }
+  const bool full = p0 + 32 <= P;  // wave-uniform: no row outside the batch
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const long long q = p0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-    if (q >= P) continue;
-    float v = acc[r] + bias;
-    if (a.relu) v = fmaxf(v, 0.0f);
-    if (a.out_f32) a.out_f32[q * COUT + col] = v;
-    if (a.out_bf16) a.out_bf16[q * COUT + col] = f32_to_bf16(v);
+    if (full || q < P) {
+      if (a.out_f32) a.out_f32[q * COUT + col] = v[r];
+      if (a.out_bf16) a.out_bf16[q * COUT + col] = f32_to_bf16(v[r]);
+    }
   }
 }
 
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(256) void k_minmax_partial(const float *f, long lon
 __global__ __launch_bounds__(256) void k_minmax_final(float *part, int nparts) {
   __shared__ float s_lo[256], s_hi[256];
   float lo = INFINITY, hi = -INFINITY;
-  for (int k = threadIdx.x; k < nparts; k += 256) {
+  for (int k = threadIdx.x; k < nparts; k += 256) {  // min and max: any order gives the same result
     lo = fminf(lo, part[2 * k]);
     hi = fmaxf(hi, part[2 * k + 1]);
   }
@@ -428,7 +446,7 @@ hipError_t launch_triplet_hinge(const float *cost, int m, float margin, float sc
   return hipGetLastError();
 }
 
-constexpr int kQuantParts = 256;
+constexpr int kQuantParts = 1024;
 
 hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream) {
   if (count <= 0) return hipSuccess;

@@ -87,16 +87,15 @@ __global__ __launch_bounds__(256) void k_fixed_to_float(const int64_t *acc, floa
 }
 
 // Padded, phase-ordered copy of a float feature map (the layout of the
-// descriptor maps with 64-byte entries): one thread per stored entry.
+// descriptor maps with 64-byte entries): one thread per 16-byte quarter of a
+// stored entry, so consecutive lanes store consecutive bytes.
 __global__ __launch_bounds__(256) void k_pad_features(const float4 *f, int W, int H, int log2n, float4 *out) {
   const int P = ffk::desc_pad(1 << log2n), Wp = W + 2 * P, Hp = H + 2 * P;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x, yp = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x, yp = blockIdx.y;
+  const int c = q >> 2;
   if (c >= Wp || yp >= Hp) return;
   const int x = clampi(ffk::desc_pixel(c, log2n, Wp) - P, W - 1), y = clampi(yp - P, H - 1);
-  const float4 *src = f + ((size_t)y * W + x) * 4;
-  float4 *dst = out + ((size_t)yp * Wp + c) * 4;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  out[((size_t)yp * Wp + c) * 4 + (q & 3)] = f[((size_t)y * W + x) * 4 + (q & 3)];
 }
 
 }  // namespace
@@ -105,7 +104,7 @@ namespace ffh {
 
 hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream) {
   const int P = ffk::desc_pad(n);
-  const dim3 grid((W + 2 * P + 255) / 256, H + 2 * P);
+  const dim3 grid((4 * (W + 2 * P) + 255) / 256, H + 2 * P);
   hipLaunchKernelGGL(k_pad_features, grid, dim3(256), 0, stream, reinterpret_cast<const float4 *>(f), W, H,
                      __builtin_ctz(n), reinterpret_cast<float4 *>(out));
   return hipGetLastError();
