@@ -43,13 +43,14 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per patch evaluation
 
 
-# HBM traffic of the scale-1 level kernel (one direction, one ff_run_level
-# launch on the 1024x436 pair) from two rocprofv3 --pmc runs (FETCH_SIZE,
+# HBM traffic per launch of the scale-1 level kernel (one direction of the
+# 1024x436 pair, the launches of ff_run_level) from two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10599.9 * 1024 * 2.0 + 3500.2 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "814080d4e9fc0c2e"
+TRAFFIC_BYTES = 10426.6 * 1024 * 2.0 + 3510.8 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "cd016c6df3457daa"
+TRAFFIC_VARIANT, TRAFFIC_PASSES = 2, 1  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_device.h",
                  "paper_1703_02563_amd/csrc/ff_internal.h")
 
@@ -102,13 +103,18 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
         launch(cnt)
         b.record()
     torch.cuda.synchronize()
-    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
-    evals = int(cnt.item()) / reps
+    # one ff_run_level call = `launches` launches of the scale-1 level kernel
+    launches = int(ff.lib().ff_level_launches(params.iters, 0, 0))
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps / launches
+    evals = int(cnt.item()) / reps / launches
     achieved = evals * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
+    traffic = None
+    if level_sources_sha() == TRAFFIC_SOURCES_SHA and ff.level_variants()[0] == TRAFFIC_VARIANT \
+            and ff.level_passes(0)[0] == TRAFFIC_PASSES:
+        traffic = round(TRAFFIC_BYTES)
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5),
-            "traffic": round(TRAFFIC_BYTES) if level_sources_sha() == TRAFFIC_SOURCES_SHA else None,
-            "kernel": "k_level<0,*> (scale 1, forward, one launch of ff_run_level)",
+            "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
+            "kernel": f"k_level<0,*> (scale 1, forward; ff_run_level = {launches} launches, averages per launch)",
             "avg_launch_ms": round(ms, 5), "evals_per_launch": evals,
             "algorithmic_ops_per_launch": evals * SAD_OPS_PER_EVAL}
 

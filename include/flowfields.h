@@ -344,6 +344,10 @@ ff_status ff_set_level_variant(int32_t log2n, int32_t variant);
 int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind);
 ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes);
 
+/* Number of blocked launches the current tables give one scale 2^log2n of
+ * a schedule with `iters` propagation steps (host); -1 if out of range. */
+int32_t ff_level_launches(int32_t iters, int32_t log2n, int32_t cost_kind);
+
 /* Bytes of device workspace ff_flow_fields needs for a W x H pair (host). */
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);
 

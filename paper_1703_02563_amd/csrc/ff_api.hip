@@ -839,6 +839,12 @@ int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
 
 int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind) { return ffh::get_level_passes(log2n, cost_kind); }
 
+int32_t ff_level_launches(int32_t iters, int32_t log2n, int32_t cost_kind) {
+  if (iters < 1 || iters > 64 || ffh::get_level_passes(log2n, cost_kind) < 0) return -1;
+  int runs[64][2];
+  return level_runs(log2n, iters, cost_kind, runs);
+}
+
 ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes) {
   return ffh::set_level_passes(log2n, cost_kind, passes) ? FF_OK : FF_ERR_ARG;
 }

@@ -78,6 +78,7 @@ _SIGS = {
     "ff_set_level_variant": (C.c_int, [_I32, _I32]),
     "ff_get_level_passes": (C.c_int32, [_I32, _I32]),
     "ff_set_level_passes": (C.c_int, [_I32, _I32, _I32]),
+    "ff_level_launches": (C.c_int32, [_I32, _I32, _I32]),
     "ff_flow_fields": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P, _P,
                                  _P, _P]),
 }

@@ -96,3 +96,17 @@ def test_level_passes_table_validation():
     old = lib.ff_get_level_passes(2, 1)
     assert lib.ff_set_level_passes(2, 1, 3) == ffi.FF_OK and lib.ff_get_level_passes(2, 1) == 3
     assert lib.ff_set_level_passes(2, 1, old) == ffi.FF_OK
+
+
+def test_level_launches_follow_the_run_length_table():
+    """Launches per scale: the halo of the blocked kernel holds 6 steps
+    (3 per side pair), the run-length table caps a run."""
+    lib = ff.lib()
+    old = lib.ff_get_level_passes(1, 0)
+    try:
+        for passes, T, expect in [(0, 6, 1), (0, 9, 2), (1, 6, 6), (2, 6, 3), (3, 6, 2), (4, 7, 2), (0, 1, 1)]:
+            assert lib.ff_set_level_passes(1, 0, passes) == ffi.FF_OK
+            assert lib.ff_level_launches(T, 1, 0) == expect, (passes, T)
+    finally:
+        lib.ff_set_level_passes(1, 0, old)
+    assert lib.ff_level_launches(0, 1, 0) == -1 and lib.ff_level_launches(6, 9, 0) == -1
