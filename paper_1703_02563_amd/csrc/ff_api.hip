@@ -123,7 +123,7 @@ int run_end(int t0, int T, int maxp, int halo = ffh::kLevelHalo) {
 int level_runs(int lv, int T, int fcost, int runs[][2]) {
   int m = 0, t0 = 0;
   while (t0 < T) {
-    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), fcost ? ffh::kLevelHaloF32 : ffh::kLevelHalo);
+    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), fcost ? ffh::kLevelHaloF32 : ffh::level_window_halo(lv));
     runs[m][0] = t0;
     runs[m][1] = t1;
     ++m;
@@ -548,6 +548,8 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.T = T;
     int runs[64][2];
     const int m = level_runs(lv, T, 0, runs);
+    bool maps_fit = true;
+    for (int i = 0; i < npairs; ++i) maps_fit = maps_fit && ffh::level_map_fits(pairs[i].W, pairs[i].H, lv);
     for (int r = 0; r < m; ++r) {
       // runs alternate between the two grid buffers; the last writes gflow/gcost
       st.dst = ((m - 1 - r) & 1) ? 1 : 0;
@@ -556,7 +558,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
       k.t_begin = runs[r][0];
       k.t_end = runs[r][1];
       k.mode = r > 0 ? ffh::kLevelContinue : (lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed);
-      if ((e = ffh::launch_batch_level(k, st, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if ((e = ffh::launch_batch_level(k, st, maps_fit, s)) != hipSuccess) return FF_ERR_LAUNCH;
     }
   }
   fill([&](int, int H) { return 2 * H; });

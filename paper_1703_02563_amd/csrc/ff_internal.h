@@ -106,6 +106,8 @@ struct LevelKArgs {
 // Padded, phase-ordered copy of a float [H][W][16] feature map of scale n.
 hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream);
 hipError_t launch_level(LevelKArgs a, hipStream_t stream);
+int level_window_halo(int log2n);              // halo of the blocked kernel the table selects
+bool level_map_fits(int W, int H, int log2n);  // scale-n map under 2^31 bytes (quad evaluations)
 void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();
 int get_level_variant(int log2n);
@@ -147,7 +149,7 @@ struct BatchStage {
 };
 hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream);
 hipError_t launch_batch_nn(const BatchStage &norms, const BatchStage &fill, const BatchStage &nn, hipStream_t stream);
-hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &tiles, hipStream_t stream);
+hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &tiles, bool maps_fit, hipStream_t stream);
 hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream_t stream);
 // items per pair of each stage (host)
 int batch_nn_items(int W, int H, int L);

@@ -19,6 +19,7 @@
 // with a replicated border of 3n pixels and their rows are in phase order,
 // so every patch read is unclamped and contiguous at every scale.
 #include <algorithm>
+#include <type_traits>
 
 #include "ff_device.h"
 #include "ff_internal.h"
@@ -44,7 +45,8 @@ struct Geo {
 // and the samples of a patch row are consecutive stored columns (phase
 // order) loaded with immediate offsets.  EV selects the load schedule:
 // 0 rows one after another, 1 rows unrolled (the compiler interleaves),
-// 2 all 49 loads issued before any arithmetic (needs ~200 registers).
+// 2 all 49 loads issued before any arithmetic (needs ~200 registers); EV 3
+// evaluates with a quad of lanes instead (eval_quad).
 template <int LOG2N, int DW, int EV>
 __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int bx, int by) {
   constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
@@ -73,6 +75,42 @@ __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__re
       pb += (size_t)n * Wp;
     }
   }
+  return s;
+}
+
+// E_n(p, f) evaluated by the four lanes of a quad (lanes 4k .. 4k+3 of a
+// wave, all active): lane r takes patch columns u = r and u = r + 4 (none for
+// r = 3) of all seven rows, so one load instruction of a quad covers four
+// consecutive samples (64 contiguous bytes of a patch row) instead of one
+// sample per lane spread over 64 patches.  Image b is read through a buffer
+// resource over its padded map (the row offset rides in the scalar offset);
+// the partial sums are added across the quad, every lane returns the total.
+// Requires a map of less than 2^31 bytes.
+template <int LOG2N, int DW>
+__device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
+                                              int r) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const int rowb = n * (W + 2 * P) * 16;
+  const int u1 = r, u2 = min(r + 4, K - 1);
+  const int off = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
+  uint4 b1[K], b2[K];
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u1 * 16, v * rowb, 0);
+    const auto y = __builtin_amdgcn_raw_buffer_load_b128(db, off + u2 * 16, v * rowb, 0);
+    b1[v] = make_uint4(x[0], x[1], x[2], x[3]);
+    b2[v] = make_uint4(y[0], y[1], y[2], y[3]);
+  }
+  const uint4 *ra1 = pa - kR * DW - kR + u1, *ra2 = pa - kR * DW - kR + u2;
+  uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    s1 = ffk::sad16(ra1[v * DW], b1[v], s1);
+    s2 = ffk::sad16(ra2[v * DW], b2[v], s2);
+  }
+  uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
   return s;
 }
 
@@ -155,6 +193,11 @@ template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   using G = Geo<TW, TH, HALO>;
   constexpr int n = 1 << LOG2N;
+  // EV 3: every evaluation by a quad of lanes (eval_quad); the candidate
+  // flows of a random-search step are then parked in s_flags
+  constexpr bool QUAD = EV == 3;
+  constexpr int kQuads = kThreads / 4;
+  using FlagT = std::conditional_t<QUAD, uint32_t, uint8_t>;
   __shared__ int32_t s_flow[G::LH * G::LW];
   __shared__ uint32_t s_cost[G::LH * G::LW];
   // byte descriptors of image a on the level lattice (float features are
@@ -163,10 +206,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   __shared__ float4 s_daf[F32 ? 4 * G::DH * G::DW : 1];
   __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
   __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
-  __shared__ uint8_t s_flags[G::LH * G::LW];           // candidate flags of the current half-sweep
+  __shared__ FlagT s_flags[G::LH * G::LW];             // candidate flags of the current half-sweep
   __shared__ unsigned int s_cnt, s_qlen;
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, qr = tid & 3;
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
   const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
   const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
@@ -202,6 +245,23 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       return eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
     }
   };
+  // the same by a quad of lanes (QUAD only)
+  [[maybe_unused]] const __amdgpu_buffer_rsrc_t db_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(d.Db), (short)0,
+      (int)((size_t)(H + 2 * ffk::desc_pad(n)) * (W + 2 * ffk::desc_pad(n)) * 16), 0x00020000);
+  auto evalq = [&](int i, int j, int bx, int by) -> uint32_t {
+    const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+    return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+  };
+  // queue append of the lanes with `on` set (one LDS atomic per wave)
+  auto enqueue = [&](bool on, uint16_t e) {
+    const uint64_t b = __ballot(on);
+    int q0 = 0;
+    if ((tid & 63) == 0 && b) q0 = (int)atomicAdd(&s_qlen, (unsigned)__popcll(b));
+    q0 = __shfl(q0, 0);
+    const int lane = tid & 63;
+    if (on) s_queue[q0 + __popcll(b & (lane ? (~0ull >> (64 - lane)) : 0ull))] = e;
+  };
 
   int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
   auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
@@ -214,6 +274,8 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     for (int base = 0; base < rw * rh; base += kThreads) {
       const int k = base + tid;
       int cnt = 0;
+      [[maybe_unused]] bool k_eval = false;
+      [[maybe_unused]] uint16_t k_l = 0;
       if (k < rw * rh) {
         const int i = rl + k % rw, j = rt + k / rw;
         const int l = (j - gj0) * G::LW + (i - gi0);
@@ -237,15 +299,35 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         s_flow[l] = f;
         s_cost[l] = c;
         if (eval) {
-          s_cost[l] = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+          if constexpr (!QUAD) s_cost[l] = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
           cnt = owned(i, j);
         }
+        if constexpr (QUAD) k_eval = eval;
+        k_l = (uint16_t)l;
       }
+      if constexpr (QUAD) enqueue(k_eval, k_l);
       const int tot = __popcll(__ballot(cnt));
       if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
     }
   }
   __syncthreads();
+  if constexpr (QUAD) {
+    if (a.mode != ffh::kLevelContinue) {  // the seed evaluations, a quad each
+      const int qlen = (int)s_qlen;
+      for (int base = 0; base < qlen; base += kQuads) {
+        const int q = base + (tid >> 2);
+        if (q < qlen) {
+          const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+          const int32_t f = s_flow[l];
+          const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+          if (qr == 0) s_cost[l] = c;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_qlen = 0;
+      __syncthreads();
+    }
+  }
 
   for (int t = a.t_begin; t < a.t_end; ++t) {
     const int dir = t & 3;
@@ -313,7 +395,19 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       }
       __syncthreads();
       // (2) the queued evaluations, densely over all lanes
-      {
+      if constexpr (QUAD) {
+        const int qlen = (int)s_qlen;
+        for (int base = 0; base < qlen; base += kQuads) {
+          const int q = base + (tid >> 2);
+          if (q < qlen) {
+            const int e = s_queue[q], l = e >> 1, vert = e & 1;
+            const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+            const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
+            const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+            if (qr == 0) atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+          }
+        }
+      } else {
         const int qlen = (int)s_qlen;
         for (int q = tid; q < qlen; q += kThreads) {
           const int e = s_queue[q], l = e >> 1, vert = e & 1;
@@ -388,7 +482,14 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           }
         }
         int cnt = 0;
-        if (act) {
+        if constexpr (QUAD) {
+          // park the candidate; the quads evaluate the queue below
+          if (act) {
+            s_flags[l] = (uint32_t)ffk::pack_flow(fx, fy);
+            cnt = owned(i, j);
+          }
+          enqueue(act, (uint16_t)l);
+        } else if (act) {
           const uint32_t e = evalc(i, j, i * n + fx, j * n + fy);
           cnt = owned(i, j);
           if (e < c0) {
@@ -400,6 +501,24 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
       }
       __syncthreads();
+      if constexpr (QUAD) {
+        const int qlen = (int)s_qlen;
+        for (int base = 0; base < qlen; base += kQuads) {
+          const int q = base + (tid >> 2);
+          if (q < qlen) {
+            const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+            const int32_t fc = (int32_t)s_flags[l];
+            const uint32_t e = evalq(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc));
+            if (qr == 0 && e < s_cost[l]) {
+              s_cost[l] = e;
+              s_flow[l] = fc;
+            }
+          }
+        }
+        __syncthreads();
+        if (tid == 0) s_qlen = 0;
+        __syncthreads();
+      }
     }
   }
 
@@ -417,11 +536,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 // One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
 // four waves per SIMD (two with EV = 2): the register budget then keeps the
 // loads of a patch in flight together instead of one after another.
-template <int LOG2N, int TW, int TH, int kThreads, int EV>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  level_body<LOG2N, TW, TH, kThreads, EV>(a, a.dir[wg / tiles], wg % tiles);
+  level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Float learned features (padded float maps in LevelKDir::Da/Db).
@@ -434,7 +553,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))
 }
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
-template <int LOG2N, int TW, int TH, int kThreads, int EV>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level_batch(
     ffh::LevelKArgs base, ffh::BatchStage st) {
   constexpr int n = 1 << LOG2N;
@@ -462,37 +581,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV 
     d.nn_key = bp.keys[dir];
     d.n_evals = bp.evals + dir;
     d.stream_id = dir;
-    level_body<LOG2N, TW, TH, kThreads, EV>(a, d, local % tiles);
+    level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, d, local % tiles);
     __syncthreads();  // the next item reuses the LDS window
   });
 }
 
 // Tile / workgroup variants of the level kernel (tile, threads, load
-// schedule: see launch_n).  Index kNumVariants of the
+// schedule, window halo: see launch_n).  Index kNumVariants of the
 // per-scale table selects the step-wise schedule instead (one launch per
 // half-sweep or random-search step over all cells, no halo): better where
-// the grid is too small to give every compute unit a tile.
+// the grid is too small to give every compute unit a tile.  A variant with
+// quad evaluations addresses image b with 32-bit offsets; for a larger map
+// its fallback (same tile, a halo at least as wide) runs instead.
 struct Variant {
-  int tw, th;
+  int tw, th, halo, fallback;
 };
-constexpr Variant kVariants[] = {{64, 32}, {32, 16}, {32, 16}, {16, 16}, {32, 32}, {32, 16},
-                                 {16, 16}, {32, 32}, {8, 8},   {16, 16}, {16, 16}};
-constexpr int kNumVariants = 11;
+constexpr int kH = ffh::kLevelHalo;
+constexpr Variant kVariants[] = {{64, 32, kH, 0}, {32, 16, kH, 1}, {32, 16, kH, 2}, {16, 16, kH, 3},
+                                 {32, 32, kH, 4}, {32, 16, kH, 5}, {16, 16, kH, 6}, {32, 32, kH, 7},
+                                 {8, 8, kH, 8},   {16, 16, kH, 9}, {16, 16, kH, 10}, {16, 16, 2, 3},
+                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8}};
+constexpr int kNumVariants = 15;
+static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
-template <int LOG2N, int TW, int TH, int THREADS, int EV>
+template <int LOG2N, int TW, int TH, int THREADS, int EV, int HALO = kH>
 hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
   if (batch) {
     if (batch->total <= 0) return hipSuccess;
     // persistent: enough workgroups to fill the chip, a multiple of 8
     const int grid = ((std::min(batch->total, 2048) + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, EV>), dim3(grid), dim3(THREADS), 0, stream, a,
+    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, EV, HALO>), dim3(grid), dim3(THREADS), 0, stream, a,
                        *batch);
     return hipGetLastError();
   }
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
-  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV, HALO>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
   return hipGetLastError();
 }
 
@@ -533,6 +658,10 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 8: return launch_v<LOG2N, 8, 8, 256, 2>(a, batch, stream);
     case 9: return launch_v<LOG2N, 16, 16, 512, 2>(a, batch, stream);
     case 10: return launch_v<LOG2N, 16, 16, 1024, 1>(a, batch, stream);
+    case 11: return launch_v<LOG2N, 16, 16, 256, 3, 2>(a, batch, stream);
+    case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2>(a, batch, stream);
+    case 13: return launch_v<LOG2N, 16, 16, 256, 3>(a, batch, stream);
+    case 14: return launch_v<LOG2N, 8, 8, 256, 3>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -598,15 +727,32 @@ static int log2_of(int n) {
   return l;
 }
 
+int level_window_halo(int log2n) {
+  const int v = blocked_variant(log2n);
+  return v < 0 ? kLevelHalo : kVariants[v].halo;
+}
+
+bool level_map_fits(int W, int H, int log2n) {
+  const size_t P = (size_t)ffk::desc_pad(1 << log2n);
+  return ((size_t)W + 2 * P) * ((size_t)H + 2 * P) * 16 < ((size_t)1 << 31);
+}
+
+// The table's variant, or its fallback where image b's map is too large
+// for the 32-bit offsets of the quad evaluations.
+static int launch_variant(int log2n, bool map_fits) {
+  const int v = blocked_variant(log2n);
+  return (v >= 0 && !map_fits) ? kVariants[v].fallback : v;
+}
+
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
   const int l2 = log2_of(a.n);
   if (a.fcost) return dispatch_f32(a, l2, stream);
-  return dispatch(a, nullptr, l2, blocked_variant(l2), stream);
+  return dispatch(a, nullptr, l2, launch_variant(l2, level_map_fits(a.W, a.H, l2)), stream);
 }
 
-hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, hipStream_t stream) {
+hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, bool maps_fit, hipStream_t stream) {
   const int l2 = log2_of(base.n);
-  return dispatch(base, &st, l2, blocked_variant(l2), stream);
+  return dispatch(base, &st, l2, launch_variant(l2, maps_fit), stream);
 }
 
 int level_tiles(int Wn, int Hn, int log2n) {
