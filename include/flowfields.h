@@ -215,7 +215,8 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
  *   cost[e] = sum_{v,u=-r..r} sum_{c<16} (f1(clamp(p+n(u,v)))[c] - f2(clamp(p+f+n(u,v)))[c])^2
  * for entry e = (x, y, fx, fy) = pixel p and flow f (int32 [count][4]).
  * f1, f2: float32 [H][W][16]; cost: float32 [count], accumulated in
- * float32 by fused multiply-adds in the order v, u, c. */
+ * float32 as four partial sums s_k over the channels 4k .. 4k+3 (one fused
+ * multiply-add per term, order v, u, c), returned as (s0 + s1) + (s2 + s3). */
 ff_status ff_cost_f32_fwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
                           const int32_t *entries, int32_t count, float *cost, void *stream);
 

@@ -196,7 +196,8 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
 
 
 def cost_f32(Fa, Fb, n: int, r: int, x: int, y: int, fx: int, fy: int) -> float:
-    """Single-precision learned-feature cost (fused multiply-adds, order v, u, c)."""
+    """Single-precision learned-feature cost: four channel-group partial sums
+    (fused multiply-adds, order v, u, c), added as (s0 + s1) + (s2 + s3)."""
     Fa = np.ascontiguousarray(Fa, np.float32)
     Fb = np.ascontiguousarray(Fb, np.float32)
     H, W = Fa.shape[:2]

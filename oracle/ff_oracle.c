@@ -133,24 +133,31 @@ static uint32_t cost_u8(const void *A, const void *B, int W, int H, int n, int r
 
 /* Learned-feature matching error (Sec. 3.5 learned data term, read as the
  * sum of squared differences of 16-channel float features over the
- * subsampled patch of Eq. 3, replicate border): one fused multiply-add per
- * term in the order v, u, c, in single precision. */
+ * subsampled patch of Eq. 3, replicate border), in single precision, R18:
+ * one partial sum per group of four channels (g = 0..3: channels 4g..4g+3),
+ * each accumulated by one fused multiply-add per term in the order v, u, c;
+ * the four partial sums are then added as (s0 + s1) + (s2 + s3). */
 uint32_t or_cost_f32(const float *fa, const float *fb, int W, int H, int n, int r, int x, int y, int fx, int fy)
 {
-    float acc = 0.0f;
-    for (int v = -r; v <= r; ++v)
-        for (int u = -r; u <= r; ++u) {
-            int ax = clampi(x + n * u, 0, W - 1), ay = clampi(y + n * v, 0, H - 1);
-            int bx = clampi(x + fx + n * u, 0, W - 1), by = clampi(y + fy + n * v, 0, H - 1);
-            const float *a = fa + ((size_t)ay * W + ax) * 16;
-            const float *b = fb + ((size_t)by * W + bx) * 16;
-            for (int c = 0; c < 16; ++c) {
-                float d = a[c] - b[c];
-                acc = fmaf(d, d, acc);
+    float part[4];
+    for (int g = 0; g < 4; ++g) {
+        float acc = 0.0f;
+        for (int v = -r; v <= r; ++v)
+            for (int u = -r; u <= r; ++u) {
+                int ax = clampi(x + n * u, 0, W - 1), ay = clampi(y + n * v, 0, H - 1);
+                int bx = clampi(x + fx + n * u, 0, W - 1), by = clampi(y + fy + n * v, 0, H - 1);
+                const float *a = fa + ((size_t)ay * W + ax) * 16;
+                const float *b = fb + ((size_t)by * W + bx) * 16;
+                for (int c = 4 * g; c < 4 * g + 4; ++c) {
+                    float d = a[c] - b[c];
+                    acc = fmaf(d, d, acc);
+                }
             }
-        }
+        part[g] = acc;
+    }
+    float total = (part[0] + part[1]) + (part[2] + part[3]);
     uint32_t bits;
-    memcpy(&bits, &acc, sizeof bits);
+    memcpy(&bits, &total, sizeof bits);
     return bits;
 }
 

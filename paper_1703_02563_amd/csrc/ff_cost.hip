@@ -4,8 +4,10 @@
 // squared-difference data term for learned features, Sec. 3.5; replicate
 // border of Sec. 3.6):
 //   C = sum_{v=-r..r} sum_{u=-r..r} sum_{c<16} (f1(clamp(p+n(u,v)))[c] - f2(clamp(p+f+n(u,v)))[c])^2
-// accumulated in float32 with one fused multiply-add per term, in the order
-// v, u, c (fixed, so that every caller sees the same rounding).
+// accumulated in float32 as four partial sums, one per group of channels
+// 4k .. 4k+3, each with one fused multiply-add per term in the order v, u, c,
+// then added as (s0 + s1) + (s2 + s3) (fixed, so that every caller sees the
+// same rounding).
 //
 // Backward: dL/df1[q] += 2g(f1(q) - f2(t)), dL/df2[t] -= 2g(f1(q) - f2(t))
 // per patch position.  Many entries touch the same pixels, and float
@@ -29,7 +31,7 @@ __global__ __launch_bounds__(256) void k_cost_fwd(ffh::CostArgs a) {
   const int n = a.n, Wm = a.W - 1, Hm = a.H - 1;
   const float4 *f1 = reinterpret_cast<const float4 *>(a.f1);
   const float4 *f2 = reinterpret_cast<const float4 *>(a.f2);
-  float acc = 0.0f;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int v = -R; v <= R; ++v) {
     const size_t qrow = (size_t)clampi(en.y + n * v, Hm) * a.W;
     const size_t trow = (size_t)clampi(en.y + en.w + n * v, Hm) * a.W;
@@ -41,17 +43,17 @@ __global__ __launch_bounds__(256) void k_cost_fwd(ffh::CostArgs a) {
       for (int k = 0; k < 4; ++k) {
         const float4 x = pa[k], y = pb[k];
         float d = x.x - y.x;
-        acc = __fmaf_rn(d, d, acc);
+        acc[k] = __fmaf_rn(d, d, acc[k]);
         d = x.y - y.y;
-        acc = __fmaf_rn(d, d, acc);
+        acc[k] = __fmaf_rn(d, d, acc[k]);
         d = x.z - y.z;
-        acc = __fmaf_rn(d, d, acc);
+        acc[k] = __fmaf_rn(d, d, acc[k]);
         d = x.w - y.w;
-        acc = __fmaf_rn(d, d, acc);
+        acc[k] = __fmaf_rn(d, d, acc[k]);
       }
     }
   }
-  a.cost[e] = acc;
+  a.cost[e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // One thread per (entry, patch position).

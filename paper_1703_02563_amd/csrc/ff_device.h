@@ -113,8 +113,10 @@ __device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const 
 // Matching-error policies of the per-step kernels.  Both return a 32-bit
 // key: the integer SAD of 16-byte descriptors, or the bit pattern of the
 // non-negative float32 sum of squared differences of 16-channel float
-// features (one fused multiply-add per term, order v, u, c), which orders
-// exactly like the float values.
+// features, which orders exactly like the float values.  The float sum is
+// four partial sums, one per group of channels 4k .. 4k+3, each with one
+// fused multiply-add per term in the order v, u, c, added as
+// (s0 + s1) + (s2 + s3).
 struct CostU8 {
   template <int R>
   __device__ static uint32_t eval(const void *Da, const void *Db, int W, int H, int n, int x, int y, int fx,
@@ -135,7 +137,7 @@ struct CostF32 {
                                   int fy) {
     const float4 *fa = static_cast<const float4 *>(Da), *fb = static_cast<const float4 *>(Db);
     const int Wm = W - 1, Hm = H - 1;
-    float acc = 0.0f;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // channels 4k .. 4k+3
 #pragma unroll 1
     for (int v = -R; v <= R; ++v) {
       const size_t ra = (size_t)clampi(y + n * v, Hm) * W, rb = (size_t)clampi(y + fy + n * v, Hm) * W;
@@ -147,17 +149,17 @@ struct CostF32 {
         for (int k = 0; k < 4; ++k) {
           const float4 p = a[k], q = b[k];
           float d = p.x - q.x;
-          acc = __fmaf_rn(d, d, acc);
+          acc[k] = __fmaf_rn(d, d, acc[k]);
           d = p.y - q.y;
-          acc = __fmaf_rn(d, d, acc);
+          acc[k] = __fmaf_rn(d, d, acc[k]);
           d = p.z - q.z;
-          acc = __fmaf_rn(d, d, acc);
+          acc[k] = __fmaf_rn(d, d, acc[k]);
           d = p.w - q.w;
-          acc = __fmaf_rn(d, d, acc);
+          acc[k] = __fmaf_rn(d, d, acc[k]);
         }
       }
     }
-    return __float_as_uint(acc);
+    return __float_as_uint((acc[0] + acc[1]) + (acc[2] + acc[3]));
   }
   template <int R>
   __device__ static void eval2(const void *Da, const void *Db, int W, int H, int n, int x, int y, int f1x, int f1y,

@@ -115,75 +115,41 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
 }
 
 // Float learned-feature cost (Eq. 3 with the squared-difference data term)
-// of cell pixel (ax, ay) and target (bx, by) on padded, phase-ordered float
-// maps (64-byte entries, same indexing as the descriptor maps): float32
-// fused multiply-adds in the order v, u, c; returned as its bit pattern.
-template <int LOG2N>
-__device__ __forceinline__ uint32_t eval_cell_f32(const float4 *__restrict__ A, const float4 *__restrict__ B, int W,
-                                                  int ax, int ay, int bx, int by) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
-  const size_t row = (size_t)n * (W + 2 * P) * 4;
-  const float4 *pa = A + 4 * ffk::desc_index(ax - kR * n, ay - kR * n, LOG2N, W);
-  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
-  float s = 0.0f;
-#pragma unroll 1
-  for (int v = 0; v < K; ++v) {
-    // the 2 x 28 loads of a patch row first (one round trip per row), then
-    // the 112 multiply-adds in their fixed order
-    float4 x[4 * K], y[4 * K];
-#pragma unroll
-    for (int q = 0; q < 4 * K; ++q) {
-      x[q] = pa[q];
-      y[q] = pb[q];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int q = 0; q < 4 * K; ++q) {
-      float e = x[q].x - y[q].x;
-      s = __fmaf_rn(e, e, s);
-      e = x[q].y - y[q].y;
-      s = __fmaf_rn(e, e, s);
-      e = x[q].z - y[q].z;
-      s = __fmaf_rn(e, e, s);
-      e = x[q].w - y[q].w;
-      s = __fmaf_rn(e, e, s);
-    }
-    pa += row;
-    pb += row;
-  }
-  return __float_as_uint(s);
-}
-
-// As eval_cell_f32 with image a's lattice samples from LDS: `pa` points at
-// the cell's 4 float4 in an LDS window of row length DW cells.
+// by a quad of lanes: lane r owns channels 4r .. 4r+3 and sums their terms
+// with one fused multiply-add each in the order v, u, c; the quad then adds
+// the four partial sums as (s0 + s1) + (s2 + s3) (every lane returns the
+// total, as a bit pattern).  Image a's lattice samples come from LDS (`pa`:
+// the cell's 4 float4 in a window of row length DW cells), image b's from
+// its padded, phase-ordered map (64-byte entries): a quad reads one whole
+// entry per load.
 template <int LOG2N, int DW>
-__device__ __forceinline__ uint32_t eval_cell_f32_lds(const float4 *pa, const float4 *__restrict__ B, int W, int bx,
-                                                      int by) {
+__device__ __forceinline__ uint32_t eval_quad_f32(const float4 *pa, const float4 *__restrict__ B, int W, int bx,
+                                                  int by, int r) {
   constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
   const size_t row = (size_t)n * (W + 2 * P) * 4;
-  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) + r;
+  const float4 *ra = pa + (-kR * DW - kR) * 4 + r;
   float s = 0.0f;
-#pragma unroll 1
+#pragma unroll
   for (int v = 0; v < K; ++v) {
-    float4 y[4 * K];
+    float4 y[K];
 #pragma unroll
-    for (int q = 0; q < 4 * K; ++q) y[q] = pb[q];
-    __builtin_amdgcn_sched_barrier(0);
-    const float4 *ra = pa + ((v - kR) * DW - kR) * 4;
+    for (int u = 0; u < K; ++u) y[u] = pb[v * row + 4 * u];
 #pragma unroll
-    for (int q = 0; q < 4 * K; ++q) {
-      const float4 x = ra[q];
-      float e = x.x - y[q].x;
+    for (int u = 0; u < K; ++u) {
+      const float4 x = ra[(v * DW + u) * 4];
+      float e = x.x - y[u].x;
       s = __fmaf_rn(e, e, s);
-      e = x.y - y[q].y;
+      e = x.y - y[u].y;
       s = __fmaf_rn(e, e, s);
-      e = x.z - y[q].z;
+      e = x.z - y[u].z;
       s = __fmaf_rn(e, e, s);
-      e = x.w - y[q].w;
+      e = x.w - y[u].w;
       s = __fmaf_rn(e, e, s);
     }
-    pb += row;
   }
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
   return __float_as_uint(s);
 }
 
@@ -193,9 +159,10 @@ template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   using G = Geo<TW, TH, HALO>;
   constexpr int n = 1 << LOG2N;
-  // EV 3: every evaluation by a quad of lanes (eval_quad); the candidate
-  // flows of a random-search step are then parked in s_flags
-  constexpr bool QUAD = EV == 3;
+  // EV 3 and float features: every evaluation by a quad of lanes
+  // (eval_quad, eval_quad_f32); the candidate flows of a random-search step
+  // are then parked in s_flags
+  constexpr bool QUAD = EV == 3 || F32;
   constexpr int kQuads = kThreads / 4;
   using FlagT = std::conditional_t<QUAD, uint32_t, uint8_t>;
   __shared__ int32_t s_flow[G::LH * G::LW];
@@ -235,23 +202,24 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     }
   }
   __syncthreads();
-  // E_n of grid cell (i, j) and target pixel (bx, by)
+  // E_n of grid cell (i, j) and target pixel (bx, by), one lane per
+  // evaluation (byte descriptors, EV 0-2)
   auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
-    if constexpr (F32) {
-      const float4 *pa = s_daf + 4 * ((j - gj0 + kR) * G::DW + (i - gi0 + kR));
-      return eval_cell_f32_lds<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by);
-    } else {
-      const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-      return eval_cell<LOG2N, G::DW, EV>(pa, Db, W, bx, by);
-    }
+    const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+    return eval_cell<LOG2N, G::DW, (EV < 3 ? EV : 1)>(pa, Db, W, bx, by);
   };
   // the same by a quad of lanes (QUAD only)
   [[maybe_unused]] const __amdgpu_buffer_rsrc_t db_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint8_t *>(d.Db), (short)0,
       (int)((size_t)(H + 2 * ffk::desc_pad(n)) * (W + 2 * ffk::desc_pad(n)) * 16), 0x00020000);
   auto evalq = [&](int i, int j, int bx, int by) -> uint32_t {
-    const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-    return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+    if constexpr (F32) {
+      const float4 *pa = s_daf + 4 * ((j - gj0 + kR) * G::DW + (i - gi0 + kR));
+      return eval_quad_f32<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by, qr);
+    } else {
+      const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+      return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+    }
   };
   // queue append of the lanes with `on` set (one LDS atomic per wave)
   auto enqueue = [&](bool on, uint16_t e) {
@@ -404,7 +372,12 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
             const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
             const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
-            if (qr == 0) atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+            if (qr == 0) {
+              if constexpr (F32)
+                atomicMin(&s_key[l], ((unsigned long long)c << 2) | (unsigned long long)(1 + vert));
+              else
+                atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+            }
           }
         }
       } else {
@@ -414,10 +387,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
           const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
           const uint32_t c = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
-          if constexpr (F32)
-            atomicMin(&s_key[l], ((unsigned long long)c << 2) | (unsigned long long)(1 + vert));
-          else
-            atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+          atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
         }
       }
       __syncthreads();

@@ -41,6 +41,19 @@ def test_cost_forward_matches_f64(H, W, count, n, r):
     assert np.all(np.abs(got - ref) <= COST_RTOL * ref + 1e-6)
 
 
+@pytest.mark.parametrize("H,W,count,n,r", [(48, 64, 400, 1, 3), (37, 53, 300, 2, 3), (20, 30, 101, 1, 1),
+                                          (1, 7, 9, 1, 3), (64, 48, 50, 1, 0)])
+def test_cost_forward_bit_exact_vs_oracle(H, W, count, n, r):
+    """Same fixed summation order as the oracle's single-precision cost:
+    identical bits, entry by entry (borders and out-of-image targets
+    included)."""
+    import oracle
+    f1, f2, ent, _ = _case(3 * H + count, H, W, count, 12)
+    got = cost_f32(cuda(f1), cuda(f2), cuda(ent), n, r).cpu().numpy()
+    ref = np.array([oracle.cost_f32(f1, f2, n, r, *map(int, e)) for e in ent], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
 @pytest.mark.parametrize("H,W,count,n,r", [(48, 64, 300, 1, 3), (37, 53, 200, 2, 3), (120, 160, 2000, 1, 3),
                                           (9, 11, 40, 1, 2)])
 def test_cost_backward_matches_f64(H, W, count, n, r):
