@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
   const int rowb = n * (W + 2 * P) * 16;
   const int u1 = r, u2 = min(r + 4, K - 1);
   const int off = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
-  uint4 b1[K], b2[K];
+  uint4 b1[K], b2[K], a1[K], a2[K];
 #pragma unroll
   for (int v = 0; v < K; ++v) {
     const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u1 * 16, v * rowb, 0);
@@ -101,13 +101,24 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
     b1[v] = make_uint4(x[0], x[1], x[2], x[3]);
     b2[v] = make_uint4(y[0], y[1], y[2], y[3]);
   }
+  // image a's samples from LDS while the global loads are in flight: the
+  // first column's now, the second's once half of the first is summed (so
+  // that fewer than 128 registers hold the whole evaluation)
   const uint4 *ra1 = pa - kR * DW - kR + u1, *ra2 = pa - kR * DW - kR + u2;
+#pragma unroll
+  for (int v = 0; v < K; ++v) a1[v] = ra1[v * DW];
+  __builtin_amdgcn_sched_barrier(0);
   uint32_t s1 = 0, s2 = 0;
 #pragma unroll
-  for (int v = 0; v < K; ++v) {
-    s1 = ffk::sad16(ra1[v * DW], b1[v], s1);
-    s2 = ffk::sad16(ra2[v * DW], b2[v], s2);
-  }
+  for (int v = 0; v < 4; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 0; v < K; ++v) a2[v] = ra2[v * DW];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 4; v < K; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+#pragma unroll
+  for (int v = 0; v < K; ++v) s2 = ffk::sad16(a2[v], b2[v], s2);
   uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
   s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
   s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
@@ -507,7 +518,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 // four waves per SIMD (two with EV = 2): the register budget then keeps the
 // loads of a patch in flight together instead of one after another.
 template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
   level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, a.dir[wg / tiles], wg % tiles);
@@ -524,7 +535,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
 template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, EV == 2 ? 2 : 4))) void k_level_batch(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level_batch(
     ffh::LevelKArgs base, ffh::BatchStage st) {
   constexpr int n = 1 << LOG2N;
   ffk::for_items(st.total, [&](int item) {
