@@ -41,6 +41,7 @@ struct NNArgs {
   NNDir dir[kMaxDirs];
   int ndir;
   int W, H, nc, Wc, M, N;
+  int chunk_tiles;  // reference tiles (32 each) per workgroup; set by launch_nn
 };
 hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
 

@@ -185,7 +185,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
   __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
   __shared__ FlagT s_flags[G::LH * G::LW];             // candidate flags of the current half-sweep
-  __shared__ unsigned int s_cnt, s_qlen;
+  __shared__ unsigned int s_cnt, s_qlen, s_rlen;
 
   const int tid = threadIdx.x, qr = tid & 3;
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
@@ -196,6 +196,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   if (tid == 0) {
     s_cnt = 0;
     s_qlen = 0;
+    s_rlen = 0;
   }
 
   // image-a descriptors on the level lattice around the window
@@ -212,7 +213,9 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       s_daf[k] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
     }
   }
-  __syncthreads();
+  // A continuing run's quads neither evaluate nor count while loading the
+  // state, so one barrier after both loads suffices.
+  if (!QUAD || a.mode != ffh::kLevelContinue) __syncthreads();
   // E_n of grid cell (i, j) and target pixel (bx, by), one lane per
   // evaluation (byte descriptors, EV 0-2)
   auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
@@ -233,10 +236,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     }
   };
   // queue append of the lanes with `on` set (one LDS atomic per wave)
-  auto enqueue = [&](bool on, uint16_t e) {
+  auto enqueue = [&](bool on, uint16_t e, unsigned int &len) {
     const uint64_t b = __ballot(on);
     int q0 = 0;
-    if ((tid & 63) == 0 && b) q0 = (int)atomicAdd(&s_qlen, (unsigned)__popcll(b));
+    if ((tid & 63) == 0 && b) q0 = (int)atomicAdd(&len, (unsigned)__popcll(b));
     q0 = __shfl(q0, 0);
     const int lane = tid & 63;
     if (on) s_queue[q0 + __popcll(b & (lane ? (~0ull >> (64 - lane)) : 0ull))] = e;
@@ -244,6 +247,17 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 
   int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
   auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
+  // random-search candidate of cell (i, j) at step t from its current state
+  [[maybe_unused]] auto rs_candidate = [&](int i, int j, int l, int t, int32_t &fc) {
+    if (s_cost[l] == kUnset) return false;
+    int ox, oy;
+    ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+    const int32_t f0 = s_flow[l];
+    const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
+    const int tx = i * n + fx, ty = j * n + fy;
+    fc = ffk::pack_flow(fx, fy);
+    return (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
+  };
 
   // initial state of the valid window
   {
@@ -284,7 +298,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if constexpr (QUAD) k_eval = eval;
         k_l = (uint16_t)l;
       }
-      if constexpr (QUAD) enqueue(k_eval, k_l);
+      if constexpr (QUAD) enqueue(k_eval, k_l, s_qlen);
       const int tot = __popcll(__ballot(cnt));
       if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
     }
@@ -318,11 +332,12 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
       const int hw = (rr - rl + 1) >> 1, rh = rb - rt;
       // Cells of this colour in the valid window, thread-strided.
-      auto cell = [&](int k, int &i, int &j) {
+      auto cell_of = [&](int c, int k, int &i, int &j) {
         j = rt + (k < hw * rh ? k / hw : 0);
-        i = rl + ((colour + j + rl) & 1) + 2 * (k % max(hw, 1));
+        i = rl + ((c + j + rl) & 1) + 2 * (k % max(hw, 1));
         return k < hw * rh && i < rr;
       };
+      auto cell = [&](int k, int &i, int &j) { return cell_of(colour, k, i, j); };
       // (1) candidate checks (Eq. 2 with the skip rules).  Only evaluations
       // whose value can matter are queued: the vertical source is not
       // evaluated when it repeats the horizontal one or the cell's own flow
@@ -434,12 +449,56 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           s_cost[l] = cost;
           if (!owned(i, j)) cnt = 0;
         }
-        const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2));
+        if constexpr (QUAD) {
+          // after the second half-sweep of a step with a random search:
+          // the cell is final, draw its candidate now
+          if (colour == 0 && t < a.T - 1) {
+            int32_t fc = 0;
+            const bool act = live && rs_candidate(i, j, l, t, fc);
+            if (act) {
+              s_flags[l] = (uint32_t)fc;
+              cnt += owned(i, j);
+            }
+            enqueue(act, (uint16_t)l, s_rlen);
+          }
+        }
+        const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2)) + __popcll(__ballot(cnt >= 3));
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+      }
+      if constexpr (QUAD) {
+        if (colour == 0 && t < a.T - 1) {  // the other colour is final since the first half-sweep
+          for (int base = 0; base < hw * rh; base += kThreads) {
+            int i, j;
+            const bool live = cell_of(1, base + tid, i, j);
+            const int l = (j - gj0) * G::LW + (i - gi0);
+            int32_t fc = 0;
+            const bool act = live && rs_candidate(i, j, l, t, fc);
+            if (act) s_flags[l] = (uint32_t)fc;
+            const int tot = __popcll(__ballot(act && owned(i, j)));
+            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+            enqueue(act, (uint16_t)l, s_rlen);
+          }
+        }
       }
       __syncthreads();
     }
-    if (t < a.T - 1) {  // random search over the whole valid window
+    if (QUAD && t < a.T - 1) {  // the candidates drawn in the second half-sweep, a quad each
+      const int qlen = (int)s_rlen;
+      for (int base = 0; base < qlen; base += kQuads) {
+        const int q = base + (tid >> 2);
+        if (q < qlen) {
+          const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+          const int32_t fc = (int32_t)s_flags[l];
+          const uint32_t e = evalq(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc));
+          if (qr == 0 && e < s_cost[l]) {
+            s_cost[l] = e;
+            s_flow[l] = fc;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_rlen = 0;  // next written after the next step's first half-sweep
+    } else if (t < a.T - 1) {  // random search over the whole valid window
       const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
       const int rw = rr - rl, rh = rb - rt;
       for (int base = 0; base < rw * rh; base += kThreads) {
@@ -463,14 +522,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           }
         }
         int cnt = 0;
-        if constexpr (QUAD) {
-          // park the candidate; the quads evaluate the queue below
-          if (act) {
-            s_flags[l] = (uint32_t)ffk::pack_flow(fx, fy);
-            cnt = owned(i, j);
-          }
-          enqueue(act, (uint16_t)l);
-        } else if (act) {
+        if (act) {
           const uint32_t e = evalc(i, j, i * n + fx, j * n + fy);
           cnt = owned(i, j);
           if (e < c0) {
@@ -482,24 +534,6 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
       }
       __syncthreads();
-      if constexpr (QUAD) {
-        const int qlen = (int)s_qlen;
-        for (int base = 0; base < qlen; base += kQuads) {
-          const int q = base + (tid >> 2);
-          if (q < qlen) {
-            const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
-            const int32_t fc = (int32_t)s_flags[l];
-            const uint32_t e = evalq(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc));
-            if (qr == 0 && e < s_cost[l]) {
-              s_cost[l] = e;
-              s_flow[l] = fc;
-            }
-          }
-        }
-        __syncthreads();
-        if (tid == 0) s_qlen = 0;
-        __syncthreads();
-      }
     }
   }
 

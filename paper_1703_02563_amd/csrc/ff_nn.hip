@@ -32,7 +32,8 @@ namespace {
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kTilesPerChunk = 512;   // <= 2048: the tile index must fit 11 bits
+constexpr int kTilesPerChunk = 512;   // batches; <= kMaxChunkTiles
+constexpr int kMaxChunkTiles = 2048;  // the tile index inside a chunk must fit 11 bits
 constexpr int kQB = 2;                // 32-query blocks per wave (B operand reuse)
 constexpr int kWaves = 4;
 constexpr int kNbPad = (1 << 20) - 1;
@@ -91,13 +92,13 @@ __device__ __forceinline__ long load_i8x8(const uint8_t *p) {
 // Query block `qblk` (32 * kQB queries) against reference chunk `chunk` of
 // one direction.  All threads of the workgroup call it.
 __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W, int nc, int Wc, int qblk,
-                                        int chunk) {
+                                        int chunk, int chunk_tiles) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, kh = lane >> 5;
   const int ntiles = (N + 31) >> 5;
   const int m0 = qblk * (32 * kQB);
-  const int t0 = chunk * kTilesPerChunk;
-  const int t1 = min(t0 + kTilesPerChunk, ntiles);
+  const int t0 = chunk * chunk_tiles;
+  const int t1 = min(t0 + chunk_tiles, ntiles);
   if (t0 + wave >= t1) return;  // wave-uniform: no tile for this wave
   struct {
     int Wc, nc;
@@ -120,30 +121,36 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
 
   const v16i zero = {0};
   // Operands of the two tiles of step t (the second repeats the first at the
-  // odd tail): loads from a clamped index, so they need no branch; padding
-  // references get zero bytes by a select and the padding norm from nb.
+  // odd tail).  The tile index is wave-uniform (scalar registers) and rides
+  // in the buffer loads' scalar offset; references at or beyond N lie outside
+  // the descriptor buffer's range (the loads return zeros, kept as zero
+  // int8 bytes), and their padded norm keeps them below every real one.
+  const __amdgpu_buffer_rsrc_t rdesc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(d.Dr), (short)0, N * 16, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rnorm =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(d.nb), (short)0, ((N + 31) & ~31) * 4, 0x00020000);
+  const int voff_desc = col * 16 + kh * 8, voff_norm = col * 4;
   struct Step {
     long ba, bb;
     int na, nb;
   };
-  auto fetch = [&](int t) {
-    const int tb = (t + kWaves < t1) ? t + kWaves : t;
-    const int ra = t * 32 + col, rb = tb * 32 + col;
+  constexpr long kFlip = (long)0x8080808080808080ull;  // bytes v -> int8 v - 128
+  auto fetch = [&](int t, int tb) {
     Step st;
-    st.ba = load_i8x8(d.Dr + (size_t)min(ra, N - 1) * 16 + kh * 8);
-    st.bb = load_i8x8(d.Dr + (size_t)min(rb, N - 1) * 16 + kh * 8);
-    if (ra >= N) st.ba = 0;
-    if (rb >= N) st.bb = 0;
-    st.na = d.nb[ra];
-    st.nb = d.nb[rb];
+    st.ba = (long)__builtin_amdgcn_raw_buffer_load_b64(rdesc, voff_desc, t * 512, 0) ^ (t * 32 + col < N ? kFlip : 0);
+    st.bb = (long)__builtin_amdgcn_raw_buffer_load_b64(rdesc, voff_desc, tb * 512, 0) ^ (tb * 32 + col < N ? kFlip : 0);
+    st.na = (int)__builtin_amdgcn_raw_buffer_load_b32(rnorm, voff_norm, t * 128, 0);
+    st.nb = (int)__builtin_amdgcn_raw_buffer_load_b32(rnorm, voff_norm, tb * 128, 0);
     return st;
   };
-  Step cur = fetch(t0 + wave);
-  for (int t = t0 + wave; t < t1; t += 2 * kWaves) {
+  const int tw0 = t0 + __builtin_amdgcn_readfirstlane(wave);
+  auto second = [&](int t) { return (t + kWaves < t1) ? t + kWaves : t; };
+  Step cur = fetch(tw0, second(tw0));
+  for (int t = tw0; t < t1; t += 2 * kWaves) {
     // the next step's operands are in flight while this step computes
-    const int tn = t + 2 * kWaves;
-    const Step nxt = fetch(tn < t1 ? tn : t);
-    const int tb = (t + kWaves < t1) ? t + kWaves : t;
+    const int tn = t + 2 * kWaves < t1 ? t + 2 * kWaves : t;
+    const Step nxt = fetch(tn, second(tn));
+    const int tb = second(t);
     const long ba = cur.ba, bb = cur.bb;
     const int nka = opaque_neg((cur.na << 11) | (t - t0));
     const int nkb = opaque_neg((cur.nb << 11) | (tb - t0));
@@ -183,18 +190,18 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
     }
 }
 
-__device__ __forceinline__ int nn_qblocks(int M) { return (M + 32 * kQB - 1) / (32 * kQB); }
-__device__ __forceinline__ int nn_chunks(int N) {
-  return (((N + 31) >> 5) + kTilesPerChunk - 1) / kTilesPerChunk;
+__host__ __device__ __forceinline__ int nn_qblocks(int M) { return (M + 32 * kQB - 1) / (32 * kQB); }
+__host__ __device__ __forceinline__ int nn_chunks(int N, int chunk_tiles = kTilesPerChunk) {
+  return (((N + 31) >> 5) + chunk_tiles - 1) / chunk_tiles;
 }
 
 // One workgroup per (direction, reference chunk, query block) of one pair,
 // query block fastest; XCD-aware order keeps the workgroups of one chunk on
 // one L2.
 __global__ __launch_bounds__(256) void k_nn(ffh::NNArgs a) {
-  const int nqb = nn_qblocks(a.M), nchunk = nn_chunks(a.N);
+  const int nqb = nn_qblocks(a.M), nchunk = nn_chunks(a.N, a.chunk_tiles);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  nn_body(a.dir[wg / (nqb * nchunk)], a.M, a.N, a.W, a.nc, a.Wc, wg % nqb, (wg / nqb) % nchunk);
+  nn_body(a.dir[wg / (nqb * nchunk)], a.M, a.N, a.W, a.nc, a.Wc, wg % nqb, (wg / nqb) % nchunk, a.chunk_tiles);
 }
 
 // ---- batches -----------------------------------------------------------
@@ -251,7 +258,7 @@ __global__ __launch_bounds__(256) void k_nn_batch(ffh::BatchStage st) {
     const int local = item - st.prefix[p];
     const int dir = local / (nqb * nchunk);
     const ffh::NNDir d = {bp.desc1[dir], bp.desc1[dir ^ 1], bp.nb[dir ^ 1], bp.keys[dir]};
-    nn_body(d, M, N, bp.W, nc, Wc, local % nqb, (local / nqb) % nchunk);
+    nn_body(d, M, N, bp.W, nc, Wc, local % nqb, (local / nqb) % nchunk, kTilesPerChunk);
   });
 }
 
@@ -263,8 +270,7 @@ int batch_nn_items(int W, int H, int L) {
   const int nc = 1 << (L - 1);
   const int M = ((W + nc - 1) / nc) * ((H + nc - 1) / nc), N = W * H;
   const int nqb = (M + 32 * kQB - 1) / (32 * kQB);
-  const int nchunk = (((N + 31) >> 5) + kTilesPerChunk - 1) / kTilesPerChunk;
-  return 2 * nqb * nchunk;
+  return 2 * nqb * nn_chunks(N);
 }
 
 static int persistent_grid(int total, int cap) { return ((std::min(std::max(total, 1), cap) + 7) / 8) * 8; }
@@ -283,7 +289,49 @@ hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t count, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_nn(const NNArgs &args, hipStream_t stream) {
+// Workgroups of k_nn the current device holds at once (compute units x
+// resident workgroups per unit), cached per device.
+static int nn_resident_workgroups() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nn, 64 * kWaves, 0) != hipSuccess)
+      return 0;
+    cache[dev] = std::max(cus * per_cu, 1);
+  }
+  return cache[dev];
+}
+
+// Reference chunk length: the number of chunks whose workgroups fill the
+// device in the fewest rounds for the least work per workgroup (a grid of
+// 1.2 rounds would leave most of the second round idle).  Each chunk also
+// costs its reduction and merge, about as much as kChunkOverhead tiles.
+static int nn_chunk_tiles(int ntiles, int per_chunk_wgs) {
+  constexpr int kChunkOverhead = 64;
+  const int cap = nn_resident_workgroups();
+  const int min_chunks = (ntiles + kMaxChunkTiles - 1) / kMaxChunkTiles;
+  if (cap <= 0) return std::max((ntiles + min_chunks - 1) / min_chunks, 1);
+  // at least 32 tiles per chunk (8 per wave), at most 8 rounds' worth
+  const int max_chunks =
+      std::max(min_chunks, std::min(ntiles / 32, min_chunks + 8 * ((cap + per_chunk_wgs - 1) / per_chunk_wgs)));
+  int best = min_chunks;
+  long long best_cost = LLONG_MAX;
+  for (int c = min_chunks; c <= max_chunks; ++c) {
+    const long long rounds = ((long long)c * per_chunk_wgs + cap - 1) / cap;
+    const long long cost = rounds * ((ntiles + c - 1) / c + kChunkOverhead);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return (ntiles + best - 1) / best;
+}
+
+hipError_t launch_nn(const NNArgs &args_in, hipStream_t stream) {
+  NNArgs args = args_in;
   const int Npad = (args.N + 31) & ~31;
   hipLaunchKernelGGL(k_nn_norms, dim3((Npad + 255) / 256, args.ndir), dim3(256), 0, stream, args);
   for (int k = 0; k < args.ndir; ++k) {
@@ -291,8 +339,9 @@ hipError_t launch_nn(const NNArgs &args, hipStream_t stream) {
     if (e != hipSuccess) return e;
   }
   const int ntiles = Npad / 32;
-  const int nqb = (args.M + 32 * kQB - 1) / (32 * kQB);
-  const int nchunk = (ntiles + kTilesPerChunk - 1) / kTilesPerChunk;
+  const int nqb = nn_qblocks(args.M);
+  args.chunk_tiles = nn_chunk_tiles(ntiles, nqb * args.ndir);
+  const int nchunk = nn_chunks(args.N, args.chunk_tiles);
   hipLaunchKernelGGL(k_nn, dim3(nqb * nchunk * args.ndir), dim3(64 * kWaves), 0, stream, args);
   return hipGetLastError();
 }
