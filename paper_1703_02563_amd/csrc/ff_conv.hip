@@ -5,9 +5,9 @@
 // Convolution as an implicit GEMM: 32 output pixels x 32 output channels per
 // wave, K = 9 taps x Cin in chunks of 16 (one v_mfma_f32_32x32x16_bf16 per
 // chunk).  A lane holds 8 consecutive input channels of one tap of one pixel
-// (one 16-byte load, zero outside the image: "same" zero padding) and the
-// matching 8 weights of one output channel.  Layout: activations
-// [B][H][W][C], weights [Cout][9][Cin] (tap = 3 * (dy + 1) + (dx + 1)).
+// (16 bytes, zero outside the image: "same" zero padding) and the matching 8
+// weights of one output channel.  Layout: activations [B][H][W][C], weights
+// [Cout][9][Cin] (tap = 3 * (dy + 1) + (dx + 1)).
 //
 // The data gradient is the same convolution with the weights rotated by 180
 // degrees and transposed ([Cin][9][Cout]).  The weight gradient sums over
@@ -38,9 +38,11 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
   return r;
 }
 
+// Single input channel (the first layer): K = 9 taps padded to 16, lane
+// half kh holds taps 8 * kh .. 8 * kh + 7 of one pixel.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_fwd(ffh::ConvArgs a) {
-  static_assert(CIN == 1 || CIN % 16 == 0, "Cin must be 1 or a multiple of 16");
+  static_assert(CIN == 1, "Cin 1 (wider inputs: k_conv_fwd_tile)");
   static_assert(COUT <= 32, "Cout <= 32");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 31, kh = lane >> 5;
@@ -54,55 +56,23 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ffh::ConvArgs a) {
   const uint16_t *in = a.in;
   const int col = row;  // output channel held by this lane in the B operand
   f32x16 acc = {0};
-  if constexpr (CIN == 1) {
-    // K = 9 taps padded to 16: lane half kh holds taps 8*kh .. 8*kh+7
-    uint16_t av[8], bv[8];
+  uint16_t av[8], bv[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int tap = 8 * kh + e;
-      uint16_t va = 0, vb = 0;
-      if (tap < 9) {
-        const int sx = x + tap % 3 - 1, sy = y + tap / 3 - 1;
-        if (pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
-          va = in[((img * a.H + sy) * a.W + sx)];
-        if (col < COUT) vb = a.w[col * 9 + tap];
-      }
-      av[e] = va;
-      bv[e] = vb;
-    }
-    uint4 ua, ub;
-    __builtin_memcpy(&ua, av, 16);
-    __builtin_memcpy(&ub, bv, 16);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
-  } else {
-    // every operand of the 9 taps is loaded before the first product, so
-    // the wave waits for memory once instead of once per product
-    constexpr int KC = CIN / 16;
-    uint4 ua[9 * KC], ub[9 * KC];
-    int valid = 0;  // bit tap: the tap's pixel lies in the image (else zero padding)
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
+  for (int e = 0; e < 8; ++e) {
+    const int tap = 8 * kh + e;
+    uint16_t va = 0, vb = 0;
+    if (tap < 9) {
       const int sx = x + tap % 3 - 1, sy = y + tap / 3 - 1;
-      valid |= (pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H) << tap;
-      // addresses stay inside the buffers even for lanes whose value is zeroed
-      const int cx = ffk::clampi(sx, a.W - 1), cy = ffk::clampi(sy, a.H - 1);
-      const uint4 *src = reinterpret_cast<const uint4 *>(in + ((img * a.H + cy) * a.W + cx) * CIN);
-      const uint4 *wsrc = reinterpret_cast<const uint4 *>(a.w + ((size_t)min(col, COUT - 1) * 9 + tap) * CIN);
-#pragma unroll
-      for (int cc = 0; cc < KC; ++cc) {
-        ua[tap * KC + cc] = src[cc * 2 + kh];
-        ub[tap * KC + cc] = wsrc[cc * 2 + kh];
-      }
+      if (pv && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H) va = in[((img * a.H + sy) * a.W + sx)];
+      if (col < COUT) vb = a.w[col * 9 + tap];
     }
-    __builtin_amdgcn_sched_barrier(0);
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
-#pragma unroll
-    for (int k = 0; k < 9 * KC; ++k) {
-      const uint4 va = (valid >> (k / KC)) & 1 ? ua[k] : zero4;
-      const uint4 vb = col < COUT ? ub[k] : zero4;
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(va), as_bf16x8(vb), acc, 0, 0, 0);
-    }
+    av[e] = va;
+    bv[e] = vb;
   }
+  uint4 ua, ub;
+  __builtin_memcpy(&ua, av, 16);
+  __builtin_memcpy(&ub, bv, 16);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub), acc, 0, 0, 0);
   if (col >= COUT) return;
   const float bias = a.bias ? a.bias[col] : 0.0f;
   float v[16];
@@ -118,6 +88,77 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ffh::ConvArgs a) {
     if (full || q < P) {
       if (a.out_f32) a.out_f32[q * COUT + col] = v[r];
       if (a.out_bf16) a.out_bf16[q * COUT + col] = f32_to_bf16(v[r]);
+    }
+  }
+}
+
+// Tiled form for Cin >= 16: a workgroup takes kConvRows image rows x 32
+// pixels of one image.  The input tile with a one-pixel border (zeros
+// outside the image: the "same" padding) is staged in LDS once, instead of
+// every tap of every pixel being read from global memory; a pixel occupies
+// Cin * 2 + 16 bytes there, so the 16-byte reads of 32 consecutive pixels hit
+// distinct banks.  Each wave keeps its weight operands in registers and runs
+// every fourth row of the tile.  The products are accumulated in the same
+// order as in k_conv_fwd (taps, then channel chunks), so the results are
+// identical.
+constexpr int kConvRows = 8;
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_conv_fwd_tile(ffh::ConvArgs a) {
+  static_assert(CIN % 16 == 0, "Cin must be a multiple of 16");
+  static_assert(COUT <= 32, "Cout <= 32");
+  constexpr int KC = CIN / 16, TW = 32, TR = kConvRows, LW = TW + 2;
+  constexpr int PX16 = CIN / 8 + 1;  // 16-byte slots per staged pixel (one of padding)
+  __shared__ uint4 s_in[(TR + 2) * LW * PX16];
+  const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TR - 1) / TR;
+  const int img = blockIdx.x / (tiles_x * tiles_y), t = blockIdx.x % (tiles_x * tiles_y);
+  const int x0 = (t % tiles_x) * TW, y0 = (t / tiles_x) * TR;
+  const uint4 zero4 = make_uint4(0, 0, 0, 0);
+  for (int k = threadIdx.x; k < (TR + 2) * LW * (CIN / 8); k += 256) {
+    const int c16 = k % (CIN / 8), px = (k / (CIN / 8)) % LW, ry = k / ((CIN / 8) * LW);
+    const int sx = x0 - 1 + px, sy = y0 - 1 + ry;
+    uint4 v = zero4;
+    if (sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+      v = reinterpret_cast<const uint4 *>(a.in + (((size_t)img * a.H + sy) * a.W + sx) * CIN)[c16];
+    s_in[(ry * LW + px) * PX16 + c16] = v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, kh = lane >> 5, col = row;  // A: pixel x0 + row; B: output channel col
+  uint4 ub[9 * KC];
+  const uint32_t wmask = col < COUT ? 0xFFFFFFFFu : 0u;  // columns beyond Cout multiply by zero
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const uint4 *wsrc = reinterpret_cast<const uint4 *>(a.w + ((size_t)min(col, COUT - 1) * 9 + tap) * CIN);
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) {
+      const uint4 w = wsrc[cc * 2 + kh];
+      ub[tap * KC + cc] = make_uint4(w.x & wmask, w.y & wmask, w.z & wmask, w.w & wmask);
+    }
+  }
+  __syncthreads();
+  const float bias = (a.bias && col < COUT) ? a.bias[col] : 0.0f;
+  for (int rr = wave; rr < TR && y0 + rr < a.H; rr += 4) {
+    f32x16 acc = {0};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const uint4 *src = s_in + ((rr + tap / 3) * LW + row + tap % 3) * PX16;
+#pragma unroll
+      for (int cc = 0; cc < KC; ++cc)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(src[cc * 2 + kh]), as_bf16x8(ub[tap * KC + cc]),
+                                                      acc, 0, 0, 0);
+    }
+    if (col < COUT) {
+      const size_t q0 = ((size_t)img * a.H + y0 + rr) * a.W;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int x = x0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        float v = acc[r] + bias;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        if (x < a.W) {
+          if (a.out_f32) a.out_f32[(q0 + x) * COUT + col] = v;
+          if (a.out_bf16) a.out_bf16[(q0 + x) * COUT + col] = f32_to_bf16(v);
+        }
+      }
     }
   }
 }
@@ -370,10 +411,13 @@ hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t stream) {
   const long long P = (long long)a.B * a.H * a.W;
   const unsigned grid = (unsigned)((P + 127) / 128);
   if (P == 0) return hipSuccess;
+  const long long tiles = (long long)a.B * ((a.W + 31) / 32) * ((a.H + kConvRows - 1) / kConvRows);
+  if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 tgrid((unsigned)tiles);
   if (a.cin == 1 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<1, 32>), dim3(grid), dim3(256), 0, stream, a);
-  else if (a.cin == 32 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<32, 32>), dim3(grid), dim3(256), 0, stream, a);
-  else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_conv_fwd<32, 16>), dim3(grid), dim3(256), 0, stream, a);
-  else if (a.cin == 16 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd<16, 32>), dim3(grid), dim3(256), 0, stream, a);
+  else if (a.cin == 32 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd_tile<32, 32>), tgrid, dim3(256), 0, stream, a);
+  else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_conv_fwd_tile<32, 16>), tgrid, dim3(256), 0, stream, a);
+  else if (a.cin == 16 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd_tile<16, 32>), tgrid, dim3(256), 0, stream, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
