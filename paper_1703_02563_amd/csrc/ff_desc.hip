@@ -20,28 +20,48 @@ namespace {
 
 using ffk::clampi;
 
+// Row sums: a thread takes kRun consecutive pixels of a row and slides the
+// window along them (2h + kRun loads for kRun sums instead of (2h + 1) each).
+constexpr int kRun = 8;
+
 __global__ __launch_bounds__(256) void k_hsum(ffh::DescJobs jobs) {
   const ffh::DescJob &jb = jobs.job[blockIdx.z];
   const int W = jobs.W, H = jobs.H;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
+  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * kRun, y = blockIdx.y;
+  if (x0 >= W || y >= H) return;
   const int h = max(1, jb.n >> 1);
   const uint8_t *row = jb.img + (size_t)y * W;
+  uint16_t *out = jb.hsum + (size_t)y * W;
   uint32_t s = 0;
-  for (int dx = -h; dx <= h; ++dx) s += row[clampi(x + dx, W - 1)];
-  jb.hsum[(size_t)y * W + x] = (uint16_t)s;
+  for (int dx = -h; dx <= h; ++dx) s += row[clampi(x0 + dx, W - 1)];
+  out[x0] = (uint16_t)s;
+  const int x1 = min(x0 + kRun, W);
+  for (int x = x0 + 1; x < x1; ++x) {
+    s += row[clampi(x + h, W - 1)];
+    s -= row[clampi(x - h - 1, W - 1)];
+    out[x] = (uint16_t)s;
+  }
 }
 
+// Column sums of the row sums, divided by the box area: a thread takes kRun
+// consecutive rows of a column and slides the window down them.
 __global__ __launch_bounds__(256) void k_vsum(ffh::DescJobs jobs) {
   const ffh::DescJob &jb = jobs.job[blockIdx.z];
   const int W = jobs.W, H = jobs.H;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y * kRun;
+  if (x >= W || y0 >= H) return;
   const int h = max(1, jb.n >> 1);
   const uint32_t area = (uint32_t)((2 * h + 1) * (2 * h + 1));
+  const uint16_t *col = jb.hsum + x;
   uint32_t s = 0;
-  for (int dy = -h; dy <= h; ++dy) s += jb.hsum[(size_t)clampi(y + dy, H - 1) * W + x];
-  jb.blurred[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
+  for (int dy = -h; dy <= h; ++dy) s += col[(size_t)clampi(y0 + dy, H - 1) * W];
+  jb.blurred[(size_t)y0 * W + x] = (uint8_t)((s + area / 2) / area);
+  const int y1 = min(y0 + kRun, H);
+  for (int y = y0 + 1; y < y1; ++y) {
+    s += col[(size_t)clampi(y + h, H - 1) * W];
+    s -= col[(size_t)clampi(y - h - 1, H - 1) * W];
+    jb.blurred[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
+  }
 }
 
 // The 16 samples of the scale-n descriptor of pixel (x, y) (in the image).
@@ -58,20 +78,52 @@ __device__ __forceinline__ uint4 descriptor_at(const uint8_t *blurred, int W, in
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// One thread per stored entry (padded row yp, column c; coalesced 16-byte
-// stores): the descriptor of the clamped pixel.  Entries that are image
-// pixels also go to the row-major copy when one is requested.
+// One workgroup per stored row yp of one map: the four blurred rows its
+// descriptors sample (y + n(2gy - 3), clamped) are staged in LDS once, then
+// every entry of the padded row (coalesced 16-byte stores) takes its 16
+// samples from there.  Entries that are image pixels also go to the
+// row-major copy when one is requested.  Dynamic LDS: 4 * row_stride(W).
+__host__ __device__ __forceinline__ int desc_row_stride(int W) { return (W + 15) & ~15; }
+
 __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
-  const ffh::DescJob &jb = jobs.job[blockIdx.z];
+  extern __shared__ uint8_t s_rows[];
+  const ffh::DescJob &jb = jobs.job[blockIdx.y];
   const int W = jobs.W, H = jobs.H, n = jb.n, l2 = __builtin_ctz(n);
   const int P = ffk::desc_pad(n), Wp = W + 2 * P, Hp = H + 2 * P;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x, yp = blockIdx.y;
-  if (c >= Wp || yp >= Hp) return;
-  const int xr = ffk::desc_pixel(c, l2, Wp) - P, yr = yp - P;
-  const uint4 d = descriptor_at(jb.blurred, W, H, n, clampi(xr, W - 1), clampi(yr, H - 1));
-  reinterpret_cast<uint4 *>(jb.desc)[(size_t)yp * Wp + c] = d;
-  if (jb.compact && xr >= 0 && xr < W && yr >= 0 && yr < H)
-    reinterpret_cast<uint4 *>(jb.compact)[(size_t)yr * W + xr] = d;
+  const int yp = blockIdx.x, Ws = desc_row_stride(W);
+  if (yp >= Hp) return;  // workgroup-uniform
+  const int yr = yp - P, y = clampi(yr, H - 1);
+  if ((W & 3) == 0) {  // rows start on 4-byte boundaries: dword loads
+    const int wq = W >> 2;
+    for (int k = threadIdx.x; k < 4 * wq; k += blockDim.x) {
+      const int g = k / wq, q = k - g * wq;
+      const uint32_t *row = reinterpret_cast<const uint32_t *>(jb.blurred + (size_t)clampi(y + n * (2 * g - 3), H - 1) * W);
+      reinterpret_cast<uint32_t *>(s_rows + g * Ws)[q] = row[q];
+    }
+  } else {
+    for (int k = threadIdx.x; k < 4 * W; k += blockDim.x) {
+      const int g = k / W, x = k - g * W;
+      s_rows[g * Ws + x] = jb.blurred[(size_t)clampi(y + n * (2 * g - 3), H - 1) * W + x];
+    }
+  }
+  __syncthreads();
+  uint4 *out = reinterpret_cast<uint4 *>(jb.desc) + (size_t)yp * Wp;
+  for (int c = threadIdx.x; c < Wp; c += blockDim.x) {
+    const int xr = ffk::desc_pixel(c, l2, Wp) - P, x = clampi(xr, W - 1);
+    uint32_t w[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint8_t *row = s_rows + g * Ws;
+      uint32_t v = 0;
+#pragma unroll
+      for (int gx = 0; gx < 4; ++gx) v |= (uint32_t)row[clampi(x + n * (2 * gx - 3), W - 1)] << (8 * gx);
+      w[g] = v;
+    }
+    const uint4 d = make_uint4(w[0], w[1], w[2], w[3]);
+    out[c] = d;
+    if (jb.compact && xr >= 0 && xr < W && yr >= 0 && yr < H)
+      reinterpret_cast<uint4 *>(jb.compact)[(size_t)yr * W + xr] = d;
+  }
 }
 
 // ---- batches: items = (pair, image * L + scale, row) ---------------------
@@ -152,13 +204,21 @@ hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream) 
 
 hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
   if (jobs.count <= 0) return hipSuccess;
-  dim3 grid((jobs.W + 255) / 256, jobs.H, jobs.count);
-  hipLaunchKernelGGL(k_hsum, grid, dim3(256), 0, stream, jobs);
-  hipLaunchKernelGGL(k_vsum, grid, dim3(256), 0, stream, jobs);
+  const dim3 ghs((jobs.W + 256 * kRun - 1) / (256 * kRun), jobs.H, jobs.count);
+  hipLaunchKernelGGL(k_hsum, ghs, dim3(256), 0, stream, jobs);
+  const dim3 gvs((jobs.W + 255) / 256, (jobs.H + kRun - 1) / kRun, jobs.count);
+  hipLaunchKernelGGL(k_vsum, gvs, dim3(256), 0, stream, jobs);
   int pmax = 0;
   for (int k = 0; k < jobs.count; ++k) pmax = std::max(pmax, ffk::desc_pad(jobs.job[k].n));
-  const dim3 gpad((jobs.W + 2 * pmax + 255) / 256, jobs.H + 2 * pmax, jobs.count);
-  hipLaunchKernelGGL(k_desc, gpad, dim3(256), 0, stream, jobs);
+  const size_t lds = 4 * (size_t)desc_row_stride(jobs.W);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {  // rows wider than 16 K pixels
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_desc),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 gpad(jobs.H + 2 * pmax, jobs.count);
+  hipLaunchKernelGGL(k_desc, gpad, dim3(256), lds, stream, jobs);
   return hipGetLastError();
 }
 
