@@ -154,14 +154,21 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
     const long ba = cur.ba, bb = cur.bb;
     const int nka = opaque_neg((cur.na << 11) | (t - t0));
     const int nkb = opaque_neg((cur.nb << 11) | (tb - t0));
+    // all four products first: the second pair runs on the matrix core
+    // while the first pair's scores are reduced
+    v16i acc_a[kQB], acc_b[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-      const v16i acc_a = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], ba, zero, 0, 0, 0);
-      const v16i acc_b = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], bb, zero, 0, 0, 0);
+      acc_a[qb] = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], ba, zero, 0, 0, 0);
+      acc_b[qb] = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], bb, zero, 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int sa = acc_a[r] * 4096 + nka;
-        const int sb = acc_b[r] * 4096 + nkb;
+        const int sa = acc_a[qb][r] * 4096 + nka;
+        const int sb = acc_b[qb][r] * 4096 + nkb;
         best[qb][r] = max(best[qb][r], max(sa, sb));
       }
     }
