@@ -199,23 +199,30 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     s_rlen = 0;
   }
 
-  // image-a descriptors on the level lattice around the window
+  // image-a descriptors on the level lattice around the window: every load
+  // of a thread is issued before the first LDS store (one memory round trip)
+  constexpr int NS = F32 ? (4 * G::DH * G::DW + kThreads - 1) / kThreads : (G::DH * G::DW + kThreads - 1) / kThreads;
+  uint4 sv[F32 ? 1 : NS];
+  float4 sf[F32 ? NS : 1];
   if constexpr (!F32) {
     const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
-    for (int k = tid; k < G::DH * G::DW; k += kThreads) {
+    uint4 *v = sv;
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int k = min(it * kThreads + tid, G::DH * G::DW - 1);
       const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
-      s_da[k] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
+      v[it] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
     }
   } else {
     const float4 *Da = reinterpret_cast<const float4 *>(d.Da);
-    for (int k = tid; k < 4 * G::DH * G::DW; k += kThreads) {
+    float4 *v = sf;
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int k = min(it * kThreads + tid, 4 * G::DH * G::DW - 1);
       const int c = k >> 2, vi = gi0 - kR + c % G::DW, vj = gj0 - kR + c / G::DW;
-      s_daf[k] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
+      v[it] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
     }
   }
-  // A continuing run's quads neither evaluate nor count while loading the
-  // state, so one barrier after both loads suffices.
-  if (!QUAD || a.mode != ffh::kLevelContinue) __syncthreads();
   // E_n of grid cell (i, j) and target pixel (bx, by), one lane per
   // evaluation (byte descriptors, EV 0-2)
   auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
@@ -259,46 +266,72 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     return (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
   };
 
-  // initial state of the valid window
+  // initial state of the valid window: the state of every cell of a thread
+  // is loaded first, then stored, evaluated (one lane per evaluation) or
+  // queued (quads)
   {
     const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
     const int rw = rr - rl, rh = rb - rt;
     const int Wc = (Wn + 1) >> 1;
-    for (int base = 0; base < rw * rh; base += kThreads) {
-      const int k = base + tid;
-      int cnt = 0;
-      [[maybe_unused]] bool k_eval = false;
-      [[maybe_unused]] uint16_t k_l = 0;
+    constexpr int NI = (G::LH * G::LW + kThreads - 1) / kThreads;
+    int32_t fv[NI];
+    uint32_t cv[NI];
+    bool ev[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = it * kThreads + tid;
+      fv[it] = 0;
+      cv[it] = kUnset;
+      ev[it] = false;
       if (k < rw * rh) {
         const int i = rl + k % rw, j = rt + k / rw;
-        const int l = (j - gj0) * G::LW + (i - gi0);
-        int32_t f = 0;
-        uint32_t c = kUnset;
-        bool eval = false;
         if (a.mode == ffh::kLevelContinue) {
-          f = d.flow_in[(size_t)j * Wn + i];
-          c = d.cost_in[(size_t)j * Wn + i];
+          fv[it] = d.flow_in[(size_t)j * Wn + i];
+          cv[it] = d.cost_in[(size_t)j * Wn + i];
         } else if (a.mode == ffh::kLevelInit) {
           const uint32_t q = (uint32_t)d.nn_key[(size_t)j * Wn + i];
-          f = ffk::pack_flow((int)(q % (uint32_t)W) - i * n, (int)(q / (uint32_t)W) - j * n);
-          eval = true;
+          fv[it] = ffk::pack_flow((int)(q % (uint32_t)W) - i * n, (int)(q / (uint32_t)W) - j * n);
+          ev[it] = true;
         } else if (!((i | j) & 1)) {
           const int kc = (j >> 1) * Wc + (i >> 1);
-          if (d.ccost[kc] != kUnset) {
-            f = d.cflow[kc];
-            eval = true;
+          const uint32_t cc = d.ccost[kc];
+          const int32_t cf = d.cflow[kc];
+          if (cc != kUnset) {
+            fv[it] = cf;
+            ev[it] = true;
           }
         }
-        s_flow[l] = f;
-        s_cost[l] = c;
-        if (eval) {
-          if constexpr (!QUAD) s_cost[l] = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+      }
+    }
+    // the staged descriptors go to LDS once both groups of loads are issued
+    if constexpr (!F32) {
+#pragma unroll
+      for (int it = 0; it < NS; ++it)
+        if (it * kThreads + tid < G::DH * G::DW) s_da[it * kThreads + tid] = sv[it];
+    } else {
+#pragma unroll
+      for (int it = 0; it < NS; ++it)
+        if (it * kThreads + tid < 4 * G::DH * G::DW) s_daf[it * kThreads + tid] = sf[it];
+    }
+    // one-lane seed evaluations read the staged descriptors, and queueing
+    // needs the counters cleared: a barrier, except for a continuing run of
+    // the quad kernels, which neither evaluates nor queues here
+    if (!QUAD || a.mode != ffh::kLevelContinue) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = it * kThreads + tid;
+      int cnt = 0, l = 0;
+      if (k < rw * rh) {
+        const int i = rl + k % rw, j = rt + k / rw;
+        l = (j - gj0) * G::LW + (i - gi0);
+        s_flow[l] = fv[it];
+        s_cost[l] = cv[it];
+        if (ev[it]) {
+          if constexpr (!QUAD) s_cost[l] = evalc(i, j, i * n + ffk::flow_x(fv[it]), j * n + ffk::flow_y(fv[it]));
           cnt = owned(i, j);
         }
-        if constexpr (QUAD) k_eval = eval;
-        k_l = (uint16_t)l;
       }
-      if constexpr (QUAD) enqueue(k_eval, k_l, s_qlen);
+      if constexpr (QUAD) enqueue(k < rw * rh && ev[it], (uint16_t)l, s_qlen);
       const int tot = __popcll(__ballot(cnt));
       if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
     }
