@@ -536,7 +536,10 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
   // scales, coarse to fine: one persistent launch per run of passes
   for (int lv = L - 1; lv >= 0; --lv) {
     const int n = 1 << lv;
-    fill([&](int W, int H) { return 2 * ffh::level_tiles(ceil_div(W, n), ceil_div(H, n), lv); });
+    bool maps_fit = true;
+    for (int i = 0; i < npairs; ++i) maps_fit = maps_fit && ffh::level_map_fits(pairs[i].W, pairs[i].H, lv);
+    // work items of the kernel that will run (a variant's fallback may tile differently)
+    fill([&](int W, int H) { return 2 * ffh::level_tiles(ceil_div(W, n), ceil_div(H, n), lv, maps_fit); });
     st.n = n;
     st.lv = lv;
     ffh::LevelKArgs k{};
@@ -548,8 +551,6 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.T = T;
     int runs[64][2];
     const int m = level_runs(lv, T, 0, runs);
-    bool maps_fit = true;
-    for (int i = 0; i < npairs; ++i) maps_fit = maps_fit && ffh::level_map_fits(pairs[i].W, pairs[i].H, lv);
     for (int r = 0; r < m; ++r) {
       // runs alternate between the two grid buffers; the last writes gflow/gcost
       st.dst = ((m - 1 - r) & 1) ? 1 : 0;

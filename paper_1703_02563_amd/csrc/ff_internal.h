@@ -154,7 +154,9 @@ hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &tiles, b
 hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream_t stream);
 // items per pair of each stage (host)
 int batch_nn_items(int W, int H, int L);
-int level_tiles(int Wn, int Hn, int log2n);  // tiles of one direction, current variant of that scale
+// tiles of one direction for the kernel that runs at that scale (the current
+// variant, or its fallback when a map does not fit the quad addressing)
+int level_tiles(int Wn, int Hn, int log2n, bool maps_fit);
 
 // Float patch cost of 16-channel float32 feature maps (learned data term).
 struct CostArgs {

@@ -640,7 +640,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 
 // half-sweep or random-search step over all cells, no halo): better where
 // the grid is too small to give every compute unit a tile.  A variant with
 // quad evaluations addresses image b with 32-bit offsets; for a larger map
-// its fallback (same tile, a halo at least as wide) runs instead.
+// its fallback (a halo at least as wide; batches count their work items
+// with level_tiles, which follows the fallback) runs instead.
 struct Variant {
   int tw, th, halo, fallback;
 };
@@ -648,8 +649,8 @@ constexpr int kH = ffh::kLevelHalo;
 constexpr Variant kVariants[] = {{64, 32, kH, 0}, {32, 16, kH, 1}, {32, 16, kH, 2}, {16, 16, kH, 3},
                                  {32, 32, kH, 4}, {32, 16, kH, 5}, {16, 16, kH, 6}, {32, 32, kH, 7},
                                  {8, 8, kH, 8},   {16, 16, kH, 9}, {16, 16, kH, 10}, {16, 16, 2, 3},
-                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8}};
-constexpr int kNumVariants = 15;
+                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8},   {8, 8, 2, 8}};
+constexpr int kNumVariants = 16;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 template <int LOG2N, int TW, int TH, int THREADS, int EV, int HALO = kH>
@@ -710,6 +711,7 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2>(a, batch, stream);
     case 13: return launch_v<LOG2N, 16, 16, 256, 3>(a, batch, stream);
     case 14: return launch_v<LOG2N, 8, 8, 256, 3>(a, batch, stream);
+    case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -803,8 +805,8 @@ hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, bool
   return dispatch(base, &st, l2, launch_variant(l2, maps_fit), stream);
 }
 
-int level_tiles(int Wn, int Hn, int log2n) {
-  const int v = blocked_variant(log2n);
+int level_tiles(int Wn, int Hn, int log2n, bool maps_fit) {
+  const int v = launch_variant(log2n, maps_fit);
   if (v < 0) return 0;
   const Variant t = kVariants[v];
   return ((Wn + t.tw - 1) / t.tw) * ((Hn + t.th - 1) / t.th);

@@ -204,6 +204,29 @@ class FlowFields:
             "n_evals": torch.zeros(2, dtype=torch.int64, device=dev),
         }
 
+    def capture(self, img1: torch.Tensor, img2: torch.Tensor):
+        """Records one call on these input buffers into a HIP graph
+        (torch.cuda.CUDAGraph; a warm-up call runs first).  replay() then
+        re-runs the whole call with one graph launch; the inputs are read
+        from the same buffers at every replay."""
+        s = torch.cuda.Stream(device=self.ws.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self(img1, img2)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self(img1, img2)
+        self.graph = g
+        return g
+
+    def replay(self) -> dict:
+        if getattr(self, "graph", None) is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        return self.out
+
     def __call__(self, img1: torch.Tensor, img2: torch.Tensor) -> dict:
         if tuple(img1.shape) != (self.H, self.W) or tuple(img2.shape) != (self.H, self.W):
             raise ValueError("image shape does not match")

@@ -247,6 +247,29 @@ def test_flow_fields_repeat_is_deterministic():
 
 
 @pytest.mark.parametrize("config", [1, 2])
+def test_flow_fields_graph_replay_repeats_eager_results(config):
+    """One ff_flow_fields call captured into a HIP graph: every replay gives
+    the eager call's outputs (fields, costs, masks, evaluation counts), with
+    the outputs clobbered and eager work on the device between replays."""
+    p = make_pair(config)
+    c = CONFIG_PARAMS[config]
+    H, W = p.img1.shape
+    prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den, eps=c.eps, seed=c.seed)
+    f = ff.FlowFields(W, H, prm)
+    i1, i2 = dev(p.img1), dev(p.img2)
+    eager = {k: host(v).copy() for k, v in f(i1, i2).items()}
+    f.capture(i1, i2)
+    for rep in range(3):
+        for k in ("flow_fwd", "flow_bwd", "cost_fwd", "keep_fwd", "n_evals"):
+            f.out[k].fill_(3)
+        ff.flow_fields(i2, i1, prm)  # eager work of its own between replays
+        torch.cuda.synchronize()
+        got = {k: host(v).copy() for k, v in f.replay().items()}
+        for k in eager:
+            assert np.array_equal(got[k], eager[k]), (rep, k)
+
+
+@pytest.mark.parametrize("config", [1, 2])
 def test_level_kernel_variants_bit_exact(config):
     """Every launch variant of the level kernel gives the same field."""
     p = make_pair(config)
