@@ -18,6 +18,11 @@
 // per cell, straight from global memory.  The descriptor maps are padded
 // with a replicated border of 3n pixels and their rows are in phase order,
 // so every patch read is unclamped and contiguous at every scale.
+//
+// A half-sweep checks every cell's sources and queues the evaluations that
+// can matter, evaluates the queue densely (one lane, or a quad of lanes, per
+// evaluation) and then decodes each cell's best candidate; a random-search
+// step evaluates one queued candidate per cell.
 #include <algorithm>
 #include <type_traits>
 
@@ -184,7 +189,9 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   __shared__ float4 s_daf[F32 ? 4 * G::DH * G::DW : 1];
   __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
   __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
-  __shared__ FlagT s_flags[G::LH * G::LW];             // candidate flags of the current half-sweep
+  // candidate flags of the current half-sweep; with quads also the parked
+  // random-search candidate flows
+  __shared__ FlagT s_flags[G::LH * G::LW];
   __shared__ unsigned int s_cnt, s_qlen, s_rlen;
 
   const int tid = threadIdx.x, qr = tid & 3;
