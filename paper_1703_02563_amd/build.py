@@ -30,10 +30,7 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,6 +39,27 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
     if verbose and errs:
         print("\n".join(errs))
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source to an object in parallel (a temporary folder),
+    then links the shared library."""
+    import concurrent.futures
+    import tempfile
+
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    srcs = sources()
+    with tempfile.TemporaryDirectory(prefix="ff_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in srcs]
+        jobs = max(1, min(len(srcs), os.cpu_count() or 1, 16))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+            futs = [pool.submit(_run, [hipcc, *compile_flags, "-c", src, "-o", obj], verbose)
+                    for src, obj in zip(srcs, objs)]
+            for f in futs:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -107,6 +107,19 @@ struct LevelKArgs {
 // Padded, phase-ordered copy of a float [H][W][16] feature map of scale n.
 hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream);
 hipError_t launch_level(LevelKArgs a, hipStream_t stream);
+// per-scale launchers of the blocked kernels (ff_level_s<log2n>.hip)
+struct BatchStage;
+#define FF_LEVEL_SCALE_DECL(k)                                                                          \
+  hipError_t launch_level_scale##k(const LevelKArgs &a, const BatchStage *batch, int variant, hipStream_t s); \
+  hipError_t launch_level_f32_scale##k(const LevelKArgs &a, hipStream_t s);
+FF_LEVEL_SCALE_DECL(0)
+FF_LEVEL_SCALE_DECL(1)
+FF_LEVEL_SCALE_DECL(2)
+FF_LEVEL_SCALE_DECL(3)
+FF_LEVEL_SCALE_DECL(4)
+FF_LEVEL_SCALE_DECL(5)
+FF_LEVEL_SCALE_DECL(6)
+#undef FF_LEVEL_SCALE_DECL
 int level_window_halo(int log2n);              // halo of the blocked kernel the table selects
 bool level_map_fits(int W, int H, int log2n);  // scale-n map under 2^31 bytes (quad evaluations)
 void level_halo(int t_begin, int t_end, int halo[4]);

@@ -1,0 +1,702 @@
+// Kernels and launchers of the temporally blocked level kernel; included by
+// the per-scale translation units ff_level_s*.hip (each instantiates the
+// kernels of one scale, so that they compile in parallel).
+//
+// Temporally blocked level kernel: a run of propagation steps (Eq. 2) and
+// random-search steps (Sec. 3.1) of one scale in one launch (Sec. 3.2
+// schedule), for patch radius 3.
+//
+// Each workgroup owns a TW x TH tile of the level grid and keeps the flow
+// and cost of the tile plus a halo in LDS.  A half-sweep that reads sources
+// on one side can only update correctly the cells whose source lies inside
+// the currently valid window, so the valid window loses one cell on every
+// side the half-sweep reads from.  The halo of a run equals the number of
+// half-sweeps that read each side, so after the last step exactly the owned
+// tile is valid and is written back.  Cells of the halo are computed
+// redundantly by the neighbouring workgroups; evaluations are counted only
+// for owned cells, so the count equals the unblocked schedule's.
+//
+// The scale-n descriptors of image a are staged in LDS on the level
+// lattice (virtual cell (i+u, j+v) -> pixel clamp((i+u)n, (j+v)n)), which is
+// exactly where E_n reads them.  Image b is read at p + f + n(u, v) with f
+// per cell, straight from global memory.  The descriptor maps are padded
+// with a replicated border of 3n pixels and their rows are in phase order,
+// so every patch read is unclamped and contiguous at every scale.
+//
+// A half-sweep checks every cell's sources and queues the evaluations that
+// can matter, evaluates the queue densely (one lane, or a quad of lanes, per
+// evaluation) and then decodes each cell's best candidate; a random-search
+// step evaluates one queued candidate per cell.
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+using ffk::clampi;
+using ffk::kUnset;
+
+constexpr int kR = 3;
+constexpr int kHalo = ffh::kLevelHalo;
+
+template <int TW, int TH, int HALO = kHalo>
+struct Geo {
+  static constexpr int LW = TW + 2 * HALO, LH = TH + 2 * HALO;  // state window
+  static constexpr int DW = LW + 2 * kR, DH = LH + 2 * kR;        // descriptor window
+  static_assert(2 * LW * LH < 65536, "queue entries are 16-bit: cell * 2 + vertical");
+};
+
+// E_n(p, f) with image-a descriptors from LDS.  `pa` points at the LDS
+// descriptor of the cell itself; (bx, by) = p + f in pixels, inside the
+// image, so the whole patch lies in the padded map of image b: no clamps,
+// and the samples of a patch row are consecutive stored columns (phase
+// order) loaded with immediate offsets.  EV selects the load schedule:
+// 0 rows one after another, 1 rows unrolled (the compiler interleaves),
+// 2 all 49 loads issued before any arithmetic (needs ~200 registers); EV 3
+// evaluates with a quad of lanes instead (eval_quad).
+template <int LOG2N, int DW, int EV>
+__device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int bx, int by) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const int Wp = W + 2 * P;
+  uint32_t s = 0;
+  const uint4 *pb = Db + ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+  if constexpr (EV == 2) {
+    uint4 b[K * K];
+#pragma unroll
+    for (int v = 0; v < K; ++v)
+#pragma unroll
+      for (int u = 0; u < K; ++u) b[v * K + u] = pb[(size_t)v * n * Wp + u];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+#pragma unroll
+      for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], b[v * K + u], s);
+    }
+  } else {
+#pragma unroll EV ? K : 1
+    for (int v = 0; v < K; ++v) {
+      const uint4 *ra = pa + (v - kR) * DW - kR;
+#pragma unroll
+      for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], pb[u], s);
+      pb += (size_t)n * Wp;
+    }
+  }
+  return s;
+}
+
+// E_n(p, f) evaluated by the four lanes of a quad (lanes 4k .. 4k+3 of a
+// wave, all active): lane r takes patch columns u = r and u = r + 4 (none for
+// r = 3) of all seven rows, so one load instruction of a quad covers four
+// consecutive samples (64 contiguous bytes of a patch row) instead of one
+// sample per lane spread over 64 patches.  Image b is read through a buffer
+// resource over its padded map (the row offset rides in the scalar offset);
+// the partial sums are added across the quad, every lane returns the total.
+// Requires a map of less than 2^31 bytes.
+template <int LOG2N, int DW>
+__device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
+                                              int r) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const int rowb = n * (W + 2 * P) * 16;
+  const int u1 = r, u2 = min(r + 4, K - 1);
+  const int off = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
+  uint4 b1[K], b2[K], a1[K], a2[K];
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u1 * 16, v * rowb, 0);
+    const auto y = __builtin_amdgcn_raw_buffer_load_b128(db, off + u2 * 16, v * rowb, 0);
+    b1[v] = make_uint4(x[0], x[1], x[2], x[3]);
+    b2[v] = make_uint4(y[0], y[1], y[2], y[3]);
+  }
+  // image a's samples from LDS while the global loads are in flight: the
+  // first column's now, the second's once half of the first is summed (so
+  // that fewer than 128 registers hold the whole evaluation)
+  const uint4 *ra1 = pa - kR * DW - kR + u1, *ra2 = pa - kR * DW - kR + u2;
+#pragma unroll
+  for (int v = 0; v < K; ++v) a1[v] = ra1[v * DW];
+  __builtin_amdgcn_sched_barrier(0);
+  uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 0; v < K; ++v) a2[v] = ra2[v * DW];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 4; v < K; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+#pragma unroll
+  for (int v = 0; v < K; ++v) s2 = ffk::sad16(a2[v], b2[v], s2);
+  uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  return s;
+}
+
+// Float learned-feature cost (Eq. 3 with the squared-difference data term)
+// by a quad of lanes: lane r owns channels 4r .. 4r+3 and sums their terms
+// with one fused multiply-add each in the order v, u, c; the quad then adds
+// the four partial sums as (s0 + s1) + (s2 + s3) (every lane returns the
+// total, as a bit pattern).  Image a's lattice samples come from LDS (`pa`:
+// the cell's 4 float4 in a window of row length DW cells), image b's from
+// its padded, phase-ordered map (64-byte entries): a quad reads one whole
+// entry per load.
+template <int LOG2N, int DW>
+__device__ __forceinline__ uint32_t eval_quad_f32(const float4 *pa, const float4 *__restrict__ B, int W, int bx,
+                                                  int by, int r) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const size_t row = (size_t)n * (W + 2 * P) * 4;
+  const float4 *pb = B + 4 * ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) + r;
+  const float4 *ra = pa + (-kR * DW - kR) * 4 + r;
+  float s = 0.0f;
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    float4 y[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) y[u] = pb[v * row + 4 * u];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const float4 x = ra[(v * DW + u) * 4];
+      float e = x.x - y[u].x;
+      s = __fmaf_rn(e, e, s);
+      e = x.y - y[u].y;
+      s = __fmaf_rn(e, e, s);
+      e = x.z - y[u].z;
+      s = __fmaf_rn(e, e, s);
+      e = x.w - y[u].w;
+      s = __fmaf_rn(e, e, s);
+    }
+  }
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+  return __float_as_uint(s);
+}
+
+// The run of passes for tile `tile` of one direction `d` (a holds the
+// pair's sizes and the schedule).  All threads of the workgroup call it.
+template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo>
+__device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
+  using G = Geo<TW, TH, HALO>;
+  constexpr int n = 1 << LOG2N;
+  // EV 3 and float features: every evaluation by a quad of lanes
+  // (eval_quad, eval_quad_f32); the candidate flows of a random-search step
+  // are then parked in s_flags
+  constexpr bool QUAD = EV == 3 || F32;
+  constexpr int kQuads = kThreads / 4;
+  using FlagT = std::conditional_t<QUAD, uint32_t, uint8_t>;
+  __shared__ int32_t s_flow[G::LH * G::LW];
+  __shared__ uint32_t s_cost[G::LH * G::LW];
+  // byte descriptors of image a on the level lattice (float features are
+  // read from their padded map instead); 64-bit keys for float costs
+  __shared__ uint4 s_da[F32 ? 1 : G::DH * G::DW];
+  __shared__ float4 s_daf[F32 ? 4 * G::DH * G::DW : 1];
+  __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
+  __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
+  // candidate flags of the current half-sweep; with quads also the parked
+  // random-search candidate flows
+  __shared__ FlagT s_flags[G::LH * G::LW];
+  __shared__ unsigned int s_cnt, s_qlen, s_rlen;
+
+  const int tid = threadIdx.x, qr = tid & 3;
+  const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
+  const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
+  const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
+  const int gi0 = ti0 - HALO, gj0 = tj0 - HALO;  // grid coords of window cell (0, 0)
+  const uint4 *Db = reinterpret_cast<const uint4 *>(d.Db);
+  if (tid == 0) {
+    s_cnt = 0;
+    s_qlen = 0;
+    s_rlen = 0;
+  }
+
+  // image-a descriptors on the level lattice around the window: every load
+  // of a thread is issued before the first LDS store (one memory round trip)
+  constexpr int NS = F32 ? (4 * G::DH * G::DW + kThreads - 1) / kThreads : (G::DH * G::DW + kThreads - 1) / kThreads;
+  uint4 sv[F32 ? 1 : NS];
+  float4 sf[F32 ? NS : 1];
+  if constexpr (!F32) {
+    const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
+    uint4 *v = sv;
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int k = min(it * kThreads + tid, G::DH * G::DW - 1);
+      const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
+      v[it] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
+    }
+  } else {
+    const float4 *Da = reinterpret_cast<const float4 *>(d.Da);
+    float4 *v = sf;
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int k = min(it * kThreads + tid, 4 * G::DH * G::DW - 1);
+      const int c = k >> 2, vi = gi0 - kR + c % G::DW, vj = gj0 - kR + c / G::DW;
+      v[it] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
+    }
+  }
+  // E_n of grid cell (i, j) and target pixel (bx, by), one lane per
+  // evaluation (byte descriptors, EV 0-2)
+  auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
+    const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+    return eval_cell<LOG2N, G::DW, (EV < 3 ? EV : 1)>(pa, Db, W, bx, by);
+  };
+  // the same by a quad of lanes (QUAD only)
+  [[maybe_unused]] const __amdgpu_buffer_rsrc_t db_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(d.Db), (short)0,
+      (int)((size_t)(H + 2 * ffk::desc_pad(n)) * (W + 2 * ffk::desc_pad(n)) * 16), 0x00020000);
+  auto evalq = [&](int i, int j, int bx, int by) -> uint32_t {
+    if constexpr (F32) {
+      const float4 *pa = s_daf + 4 * ((j - gj0 + kR) * G::DW + (i - gi0 + kR));
+      return eval_quad_f32<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by, qr);
+    } else {
+      const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
+      return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+    }
+  };
+  // queue append of the lanes with `on` set (one LDS atomic per wave)
+  auto enqueue = [&](bool on, uint16_t e, unsigned int &len) {
+    const uint64_t b = __ballot(on);
+    int q0 = 0;
+    if ((tid & 63) == 0 && b) q0 = (int)atomicAdd(&len, (unsigned)__popcll(b));
+    q0 = __shfl(q0, 0);
+    const int lane = tid & 63;
+    if (on) s_queue[q0 + __popcll(b & (lane ? (~0ull >> (64 - lane)) : 0ull))] = e;
+  };
+
+  int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
+  auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
+  // random-search candidate of cell (i, j) at step t from its current state
+  [[maybe_unused]] auto rs_candidate = [&](int i, int j, int l, int t, int32_t &fc) {
+    if (s_cost[l] == kUnset) return false;
+    int ox, oy;
+    ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+    const int32_t f0 = s_flow[l];
+    const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
+    const int tx = i * n + fx, ty = j * n + fy;
+    fc = ffk::pack_flow(fx, fy);
+    return (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
+  };
+
+  // initial state of the valid window: the state of every cell of a thread
+  // is loaded first, then stored, evaluated (one lane per evaluation) or
+  // queued (quads)
+  {
+    const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+    const int rw = rr - rl, rh = rb - rt;
+    const int Wc = (Wn + 1) >> 1;
+    constexpr int NI = (G::LH * G::LW + kThreads - 1) / kThreads;
+    int32_t fv[NI];
+    uint32_t cv[NI];
+    bool ev[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = it * kThreads + tid;
+      fv[it] = 0;
+      cv[it] = kUnset;
+      ev[it] = false;
+      if (k < rw * rh) {
+        const int i = rl + k % rw, j = rt + k / rw;
+        if (a.mode == ffh::kLevelContinue) {
+          fv[it] = d.flow_in[(size_t)j * Wn + i];
+          cv[it] = d.cost_in[(size_t)j * Wn + i];
+        } else if (a.mode == ffh::kLevelInit) {
+          const uint32_t q = (uint32_t)d.nn_key[(size_t)j * Wn + i];
+          fv[it] = ffk::pack_flow((int)(q % (uint32_t)W) - i * n, (int)(q / (uint32_t)W) - j * n);
+          ev[it] = true;
+        } else if (!((i | j) & 1)) {
+          const int kc = (j >> 1) * Wc + (i >> 1);
+          const uint32_t cc = d.ccost[kc];
+          const int32_t cf = d.cflow[kc];
+          if (cc != kUnset) {
+            fv[it] = cf;
+            ev[it] = true;
+          }
+        }
+      }
+    }
+    // the staged descriptors go to LDS once both groups of loads are issued
+    if constexpr (!F32) {
+#pragma unroll
+      for (int it = 0; it < NS; ++it)
+        if (it * kThreads + tid < G::DH * G::DW) s_da[it * kThreads + tid] = sv[it];
+    } else {
+#pragma unroll
+      for (int it = 0; it < NS; ++it)
+        if (it * kThreads + tid < 4 * G::DH * G::DW) s_daf[it * kThreads + tid] = sf[it];
+    }
+    // one-lane seed evaluations read the staged descriptors, and queueing
+    // needs the counters cleared: a barrier, except for a continuing run of
+    // the quad kernels, which neither evaluates nor queues here
+    if (!QUAD || a.mode != ffh::kLevelContinue) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = it * kThreads + tid;
+      int cnt = 0, l = 0;
+      if (k < rw * rh) {
+        const int i = rl + k % rw, j = rt + k / rw;
+        l = (j - gj0) * G::LW + (i - gi0);
+        s_flow[l] = fv[it];
+        s_cost[l] = cv[it];
+        if (ev[it]) {
+          if constexpr (!QUAD) s_cost[l] = evalc(i, j, i * n + ffk::flow_x(fv[it]), j * n + ffk::flow_y(fv[it]));
+          cnt = owned(i, j);
+        }
+      }
+      if constexpr (QUAD) enqueue(k < rw * rh && ev[it], (uint16_t)l, s_qlen);
+      const int tot = __popcll(__ballot(cnt));
+      if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+    }
+  }
+  __syncthreads();
+  if constexpr (QUAD) {
+    if (a.mode != ffh::kLevelContinue) {  // the seed evaluations, a quad each
+      const int qlen = (int)s_qlen;
+      for (int base = 0; base < qlen; base += kQuads) {
+        const int q = base + (tid >> 2);
+        if (q < qlen) {
+          const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+          const int32_t f = s_flow[l];
+          const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+          if (qr == 0) s_cost[l] = c;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_qlen = 0;
+      __syncthreads();
+    }
+  }
+
+  for (int t = a.t_begin; t < a.t_end; ++t) {
+    const int dir = t & 3;
+    const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
+    const int vdj = (dir == 0 || dir == 2) ? -1 : 1;
+    for (int colour = 1; colour >= 0; --colour) {
+      if (hdi < 0) --ml; else --mr;
+      if (vdj < 0) --mt; else --mb;
+      const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+      const int hw = (rr - rl + 1) >> 1, rh = rb - rt;
+      // Cells of this colour in the valid window, thread-strided.
+      auto cell_of = [&](int c, int k, int &i, int &j) {
+        j = rt + (k < hw * rh ? k / hw : 0);
+        i = rl + ((c + j + rl) & 1) + 2 * (k % max(hw, 1));
+        return k < hw * rh && i < rr;
+      };
+      auto cell = [&](int k, int &i, int &j) { return cell_of(colour, k, i, j); };
+      // (1) candidate checks (Eq. 2 with the skip rules).  Only evaluations
+      // whose value can matter are queued: the vertical source is not
+      // evaluated when it repeats the horizontal one or the cell's own flow
+      // (its value is then known not to win).  The cell's cost slot holds
+      // the key cost*4 + rank (own 0, horizontal 1, vertical 2; UNSET stays
+      // all ones) and evaluations lower it with an LDS atomic min: the
+      // smallest key is exactly the sequential strict-< choice with ties
+      // kept by the earlier candidate.
+      for (int base = 0; base < hw * rh; base += kThreads) {
+        int i, j;
+        const bool live = cell(base + tid, i, j);
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        bool hv = false, vcomp = false;
+        if (live) {
+          const uint32_t c0 = s_cost[l];
+          const int32_t f0 = s_flow[l];
+          const bool set0 = c0 != kUnset;
+          const int x = i * n, y = j * n;
+          bool vb = false, vsame_h = false, vsame_0 = false;
+          int32_t fh = 0;
+          if (i + hdi >= 0 && i + hdi < Wn && s_cost[l + hdi] != kUnset) {
+            fh = s_flow[l + hdi];
+            const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
+            hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+          }
+          if (j + vdj >= 0 && j + vdj < Hn && s_cost[l + vdj * G::LW] != kUnset) {
+            const int32_t fv = s_flow[l + vdj * G::LW];
+            const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
+            vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
+            vsame_h = hv && fv == fh;
+            vsame_0 = set0 && fv == f0;
+          }
+          vcomp = vb && !vsame_h && !vsame_0;
+          s_flags[l] = (uint8_t)(hv | (vb << 1) | (vsame_h << 2) | (vsame_0 << 3) | (vcomp << 4));
+          if constexpr (F32)
+            s_key[l] = set0 ? (unsigned long long)c0 << 2 : ~0ull;
+          else
+            s_cost[l] = set0 ? c0 << 2 : kUnset;
+        }
+        const uint64_t bh = __ballot(hv), bv = __ballot(vcomp);
+        const int nh = __popcll(bh), nv = __popcll(bv);
+        int q0 = 0;
+        if ((tid & 63) == 0 && nh + nv) q0 = (int)atomicAdd(&s_qlen, (unsigned)(nh + nv));
+        q0 = __shfl(q0, 0);
+        const int lane = tid & 63;
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        if (hv) s_queue[q0 + __popcll(bh & below)] = (uint16_t)(l << 1);
+        if (vcomp) s_queue[q0 + nh + __popcll(bv & below)] = (uint16_t)((l << 1) | 1);
+      }
+      __syncthreads();
+      // (2) the queued evaluations, densely over all lanes
+      if constexpr (QUAD) {
+        const int qlen = (int)s_qlen;
+        for (int base = 0; base < qlen; base += kQuads) {
+          const int q = base + (tid >> 2);
+          if (q < qlen) {
+            const int e = s_queue[q], l = e >> 1, vert = e & 1;
+            const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+            const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
+            const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+            if (qr == 0) {
+              if constexpr (F32)
+                atomicMin(&s_key[l], ((unsigned long long)c << 2) | (unsigned long long)(1 + vert));
+              else
+                atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+            }
+          }
+        }
+      } else {
+        const int qlen = (int)s_qlen;
+        for (int q = tid; q < qlen; q += kThreads) {
+          const int e = s_queue[q], l = e >> 1, vert = e & 1;
+          const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+          const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
+          const uint32_t c = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+          atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_qlen = 0;
+      // (3) new state and evaluation count of every cell
+      for (int base = 0; base < hw * rh; base += kThreads) {
+        int i, j;
+        const bool live = cell(base + tid, i, j);
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        int cnt = 0;
+        if (live) {
+          bool unset;
+          int rank;
+          uint32_t cost;
+          if constexpr (F32) {
+            const unsigned long long key = s_key[l];
+            unset = key == ~0ull;
+            rank = unset ? 0 : (int)(key & 3);
+            cost = unset ? kUnset : (uint32_t)(key >> 2);
+          } else {
+            const uint32_t key = s_cost[l];
+            unset = key == kUnset;
+            rank = unset ? 0 : (int)(key & 3);
+            cost = unset ? kUnset : key >> 2;
+          }
+          const int fl = s_flags[l];
+          const bool hv = fl & 1, vb = fl & 2, vsame_h = fl & 4, vsame_0 = fl & 8;
+          cnt = hv;
+          // the vertical source counts as evaluated unless it equals the
+          // best flow after the horizontal step
+          if (vb) cnt += vsame_h ? (rank == 0) : vsame_0 ? (rank == 1) : 1;
+          if (rank) s_flow[l] = s_flow[rank == 1 ? l + hdi : l + vdj * G::LW];
+          s_cost[l] = cost;
+          if (!owned(i, j)) cnt = 0;
+        }
+        if constexpr (QUAD) {
+          // after the second half-sweep of a step with a random search:
+          // the cell is final, draw its candidate now
+          if (colour == 0 && t < a.T - 1) {
+            int32_t fc = 0;
+            const bool act = live && rs_candidate(i, j, l, t, fc);
+            if (act) {
+              s_flags[l] = (uint32_t)fc;
+              cnt += owned(i, j);
+            }
+            enqueue(act, (uint16_t)l, s_rlen);
+          }
+        }
+        const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2)) + __popcll(__ballot(cnt >= 3));
+        if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+      }
+      if constexpr (QUAD) {
+        if (colour == 0 && t < a.T - 1) {  // the other colour is final since the first half-sweep
+          for (int base = 0; base < hw * rh; base += kThreads) {
+            int i, j;
+            const bool live = cell_of(1, base + tid, i, j);
+            const int l = (j - gj0) * G::LW + (i - gi0);
+            int32_t fc = 0;
+            const bool act = live && rs_candidate(i, j, l, t, fc);
+            if (act) s_flags[l] = (uint32_t)fc;
+            const int tot = __popcll(__ballot(act && owned(i, j)));
+            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+            enqueue(act, (uint16_t)l, s_rlen);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (QUAD && t < a.T - 1) {  // the candidates drawn in the second half-sweep, a quad each
+      const int qlen = (int)s_rlen;
+      for (int base = 0; base < qlen; base += kQuads) {
+        const int q = base + (tid >> 2);
+        if (q < qlen) {
+          const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+          const int32_t fc = (int32_t)s_flags[l];
+          const uint32_t e = evalq(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc));
+          if (qr == 0 && e < s_cost[l]) {
+            s_cost[l] = e;
+            s_flow[l] = fc;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_rlen = 0;  // next written after the next step's first half-sweep
+    } else if (t < a.T - 1) {  // random search over the whole valid window
+      const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
+      const int rw = rr - rl, rh = rb - rt;
+      for (int base = 0; base < rw * rh; base += kThreads) {
+        const int k = base + tid;
+        const bool live = k < rw * rh;
+        const int i = rl + (live ? k % rw : 0), j = rt + (live ? k / rw : 0);
+        const int l = (j - gj0) * G::LW + (i - gi0);
+        bool act = false;
+        int fx = 0, fy = 0;
+        uint32_t c0 = kUnset;
+        if (live) {
+          c0 = s_cost[l];
+          if (c0 != kUnset) {
+            int ox, oy;
+            ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+            const int32_t f0 = s_flow[l];
+            fx = ffk::flow_x(f0) + ox;
+            fy = ffk::flow_y(f0) + oy;
+            const int tx = i * n + fx, ty = j * n + fy;
+            act = (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
+          }
+        }
+        int cnt = 0;
+        if (act) {
+          const uint32_t e = evalc(i, j, i * n + fx, j * n + fy);
+          cnt = owned(i, j);
+          if (e < c0) {
+            s_cost[l] = e;
+            s_flow[l] = ffk::pack_flow(fx, fy);
+          }
+        }
+        const int tot = __popcll(__ballot(cnt));
+        if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
+      }
+      __syncthreads();
+    }
+  }
+
+  // write back the owned tile
+  const int ow = oi1 - ti0, oh = oj1 - tj0;
+  for (int k = tid; k < ow * oh; k += kThreads) {
+    const int i = ti0 + k % ow, j = tj0 + k / ow;
+    const int l = (j - gj0) * G::LW + (i - gi0);
+    d.flow[(size_t)j * Wn + i] = s_flow[l];
+    d.cost[(size_t)j * Wn + i] = s_cost[l];
+  }
+  if (tid == 0 && s_cnt && d.n_evals) atomicAdd(d.n_evals, (unsigned long long)s_cnt);
+}
+
+// One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
+// four waves per SIMD (two with EV = 2): the register budget then keeps the
+// loads of a patch in flight together instead of one after another.
+template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, a.dir[wg / tiles], wg % tiles);
+}
+
+// Float learned features (padded float maps in LevelKDir::Da/Db).
+template <int LOG2N, int TW, int TH, int kThreads>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_level_f32(
+    ffh::LevelKArgs a) {
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  level_body<LOG2N, TW, TH, kThreads, 1, true, ffh::kLevelHaloF32>(a, a.dir[wg / tiles], wg % tiles);
+}
+
+// Persistent launch over the (pair, direction, tile) items of a batch.
+template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level_batch(
+    ffh::LevelKArgs base, ffh::BatchStage st) {
+  constexpr int n = 1 << LOG2N;
+  ffk::for_items(st.total, [&](int item) {
+    const int p = ffk::batch_pair(st.prefix, st.npairs, item);
+    const ffh::BatchPair &bp = st.pairs[p];
+    ffh::LevelKArgs a = base;
+    a.W = bp.W;
+    a.H = bp.H;
+    a.Wn = (bp.W + n - 1) / n;
+    a.Hn = (bp.H + n - 1) / n;
+    a.tiles_x = (a.Wn + TW - 1) / TW;
+    const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+    const int local = item - st.prefix[p];
+    const int dir = local / tiles, lv = st.lv;
+    ffh::LevelKDir d;
+    d.Da = bp.desc[dir][lv];
+    d.Db = bp.desc[dir ^ 1][lv];
+    d.flow = st.dst ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
+    d.cost = st.dst ? bp.scost[lv][dir] : bp.gcost[lv][dir];
+    d.flow_in = st.src ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
+    d.cost_in = st.src ? bp.scost[lv][dir] : bp.gcost[lv][dir];
+    d.cflow = lv + 1 < st.L ? bp.gflow[lv + 1][dir] : nullptr;
+    d.ccost = lv + 1 < st.L ? bp.gcost[lv + 1][dir] : nullptr;
+    d.nn_key = bp.keys[dir];
+    d.n_evals = bp.evals + dir;
+    d.stream_id = dir;
+    level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, d, local % tiles);
+    __syncthreads();  // the next item reuses the LDS window
+  });
+}
+
+template <int LOG2N, int TW, int TH, int THREADS, int EV, int HALO = ffh::kLevelHalo>
+hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
+  if (batch) {
+    if (batch->total <= 0) return hipSuccess;
+    // persistent: enough workgroups to fill the chip, a multiple of 8
+    const int grid = ((std::min(batch->total, 2048) + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_level_batch<LOG2N, TW, TH, THREADS, EV, HALO>), dim3(grid), dim3(THREADS), 0, stream, a,
+                       *batch);
+    return hipGetLastError();
+  }
+  ffh::LevelKArgs b = a;
+  b.tiles_x = (a.Wn + TW - 1) / TW;
+  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV, HALO>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  return hipGetLastError();
+}
+
+template <int LOG2N, int TW, int TH, int THREADS>
+hipError_t launch_f32(const ffh::LevelKArgs &a, hipStream_t stream) {
+  ffh::LevelKArgs b = a;
+  b.tiles_x = (a.Wn + TW - 1) / TW;
+  const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  hipLaunchKernelGGL((k_level_f32<LOG2N, TW, TH, THREADS>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  return hipGetLastError();
+}
+
+// Variant index -> kernel; the tile and halo of every index are listed in
+// kVariants (ff_level.hip), which must match.
+template <int LOG2N>
+hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int variant, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_v<LOG2N, 64, 32, 1024, 0>(a, batch, stream);
+    case 1: return launch_v<LOG2N, 32, 16, 1024, 0>(a, batch, stream);
+    case 2: return launch_v<LOG2N, 32, 16, 256, 1>(a, batch, stream);
+    case 3: return launch_v<LOG2N, 16, 16, 256, 1>(a, batch, stream);
+    case 4: return launch_v<LOG2N, 32, 32, 512, 1>(a, batch, stream);
+    case 5: return launch_v<LOG2N, 32, 16, 256, 2>(a, batch, stream);
+    case 6: return launch_v<LOG2N, 16, 16, 256, 2>(a, batch, stream);
+    case 7: return launch_v<LOG2N, 32, 32, 512, 2>(a, batch, stream);
+    case 8: return launch_v<LOG2N, 8, 8, 256, 2>(a, batch, stream);
+    case 9: return launch_v<LOG2N, 16, 16, 512, 2>(a, batch, stream);
+    case 10: return launch_v<LOG2N, 16, 16, 1024, 1>(a, batch, stream);
+    case 11: return launch_v<LOG2N, 16, 16, 256, 3, 2>(a, batch, stream);
+    case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2>(a, batch, stream);
+    case 13: return launch_v<LOG2N, 16, 16, 256, 3>(a, batch, stream);
+    case 14: return launch_v<LOG2N, 8, 8, 256, 3>(a, batch, stream);
+    case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2>(a, batch, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
+}  // namespace

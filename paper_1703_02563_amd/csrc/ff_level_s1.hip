@@ -1,0 +1,14 @@
+// Level kernels of scale 2^1 (see ff_level_kernels.h).
+#include "ff_level_kernels.h"
+
+namespace ffh {
+
+hipError_t launch_level_scale1(const LevelKArgs &a, const BatchStage *batch, int variant, hipStream_t stream) {
+  return launch_n<1>(a, batch, variant, stream);
+}
+
+hipError_t launch_level_f32_scale1(const LevelKArgs &a, hipStream_t stream) {
+  return launch_f32<1, 16, 16, 256>(a, stream);
+}
+
+}  // namespace ffh
