@@ -101,7 +101,10 @@ size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n);
  * ff_descriptors); desc_ac, desc_bc: descriptor maps of scale nc;
  * nb_scratch: int32 [ceil(W*H/32)*32] scratch;
  * nn_key: uint64 [cells] output, (squared distance << 32) | q;
- * flow, cost: grid of scale nc, outputs. */
+ * flow, cost: grid of scale nc, outputs.  W * H must stay below 2^27 (the
+ * search addresses the descriptors with 32-bit offsets): FF_ERR_ARG
+ * otherwise, as for ff_flow_fields, ff_flow_fields_f32 and the batch calls,
+ * whose workspace-size queries return 0 for such sizes. */
 ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac,
                      const uint8_t *desc_bc, int32_t W, int32_t H, int32_t nc, int32_t radius,
                      int32_t *nb_scratch, uint64_t *nn_key, int16_t *flow, uint32_t *cost,

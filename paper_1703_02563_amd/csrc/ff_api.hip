@@ -19,6 +19,9 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 inline bool is_pow2(int n) { return n >= 1 && n <= 64 && (n & (n - 1)) == 0; }
 inline bool dims_ok(int W, int H) { return W >= 1 && H >= 1 && W <= 32767 && H <= 32767; }
+// The NN seed addresses the level-1 descriptors (16 bytes a pixel) with
+// 32-bit offsets: fewer than 2^27 pixels per image.
+inline bool nn_dims_ok(int W, int H) { return dims_ok(W, H) && (long long)W * H < (1ll << 27); }
 
 ff_status from_hip(hipError_t e) { return e == hipSuccess ? FF_OK : FF_ERR_LAUNCH; }
 
@@ -260,7 +263,7 @@ ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, ui
 ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac, const uint8_t *desc_bc,
                      int32_t W, int32_t H, int32_t nc, int32_t radius, int32_t *nb_scratch, uint64_t *nn_key,
                      int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream) {
-  if (!desc_a1 || !desc_b1 || !desc_ac || !desc_bc || !nb_scratch || !nn_key || !flow || !cost || !dims_ok(W, H) ||
+  if (!desc_a1 || !desc_b1 || !desc_ac || !desc_bc || !nb_scratch || !nn_key || !flow || !cost || !nn_dims_ok(W, H) ||
       !is_pow2(nc) || radius < 0 || radius > 7)
     return FF_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -428,7 +431,7 @@ static bool batch_ok(const ff_pair *pairs, int32_t npairs, const ff_params *p) {
   for (int i = 0; i < npairs; ++i) {
     const ff_pair &q = pairs[i];
     if (!q.img1 || !q.img2 || !q.flow_fwd || !q.flow_bwd || !q.cost_fwd || !q.cost_bwd || !q.keep_fwd ||
-        !dims_ok(q.W, q.H))
+        !nn_dims_ok(q.W, q.H))
       return false;
   }
   return true;
@@ -606,7 +609,7 @@ static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
 }
 
 size_t ff_workspace_bytes_f32(int32_t W, int32_t H, const ff_params *params) {
-  if (!dims_ok(W, H) || !params_ok(params)) return 0;
+  if (!nn_dims_ok(W, H) || !params_ok(params)) return 0;
   return layout_f32(W, H, params).total;
 }
 
@@ -614,7 +617,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
                              const ff_params *params, void *ws, size_t ws_bytes, int16_t *flow_fwd, int16_t *flow_bwd,
                              uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd,
                              uint64_t *n_evals, void *stream) {
-  if (!feat1 || !feat2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !dims_ok(W, H) ||
+  if (!feat1 || !feat2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !nn_dims_ok(W, H) ||
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const int L = params->levels, r = params->radius;
@@ -859,14 +862,14 @@ ff_status ff_set_level_variant(int32_t log2n, int32_t variant) {
 }
 
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params) {
-  if (!dims_ok(W, H) || !params_ok(params)) return 0;
+  if (!nn_dims_ok(W, H) || !params_ok(params)) return 0;
   return layout(W, H, params).total;
 }
 
 ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, int32_t H, const ff_params *params,
                          void *ws, size_t ws_bytes, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd,
                          uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals, void *stream) {
-  if (!img1 || !img2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !dims_ok(W, H) ||
+  if (!img1 || !img2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !nn_dims_ok(W, H) ||
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const Layout lay = layout(W, H, params);

@@ -48,6 +48,10 @@ def test_workspace_bytes_and_validation():
         assert lib.ff_workspace_bytes(64, 64, C.byref(q)) == 0
     assert lib.ff_workspace_bytes(0, 10, C.byref(p)) == 0
     assert lib.ff_workspace_bytes(40000, 10, C.byref(p)) == 0
+    # the NN seed's 32-bit descriptor offsets: fewer than 2^27 pixels
+    assert lib.ff_workspace_bytes(16384, 8191, C.byref(p)) > 0
+    assert lib.ff_workspace_bytes(16384, 8192, C.byref(p)) == 0
+    assert lib.ff_workspace_bytes_f32(16384, 8192, C.byref(p)) == 0
 
 
 def test_bad_arguments_return_before_any_launch():
