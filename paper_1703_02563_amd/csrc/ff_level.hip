@@ -24,8 +24,9 @@ struct Variant {
 constexpr Variant kVariants[] = {{64, 32, kH, 0}, {32, 16, kH, 1}, {32, 16, kH, 2}, {16, 16, kH, 3},
                                  {32, 32, kH, 4}, {32, 16, kH, 5}, {16, 16, kH, 6}, {32, 32, kH, 7},
                                  {8, 8, kH, 8},   {16, 16, kH, 9}, {16, 16, kH, 10}, {16, 16, 2, 3},
-                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8},   {8, 8, 2, 8}};
-constexpr int kNumVariants = 16;
+                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8},   {8, 8, 2, 8},
+                                 {32, 16, 4, 2},  {16, 16, 4, 3}};
+constexpr int kNumVariants = 18;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);

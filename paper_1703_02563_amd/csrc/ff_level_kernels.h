@@ -694,6 +694,8 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 13: return launch_v<LOG2N, 16, 16, 256, 3>(a, batch, stream);
     case 14: return launch_v<LOG2N, 8, 8, 256, 3>(a, batch, stream);
     case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2>(a, batch, stream);
+    case 16: return launch_v<LOG2N, 32, 16, 256, 3, 4>(a, batch, stream);
+    case 17: return launch_v<LOG2N, 16, 16, 256, 3, 4>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
