@@ -53,8 +53,8 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10330.9 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "98882a565e1065ff"
+TRAFFIC_BYTES = 10567.5 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "a6b29771d6326323"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
