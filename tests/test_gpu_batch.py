@@ -123,3 +123,26 @@ def test_batch_with_multi_launch_scales_equals_single_pair_path():
                 assert torch.equal(b.out[k][key], g[key]), (k, key)
     finally:
         ff.set_level_passes(sp, 0)
+
+
+@pytest.mark.parametrize("tables", [{"variants": [16, 17, 13, 14, 16, 3, 3], "passes": [7, 7, 7, 7, 7, 0, 0]},
+                                    {"variants": [13, 14, 17, 16, 14, 3, 3], "passes": [3, 4, 5, 6, 1, 0, 0]}])
+def test_batch_wide_halo_variants_equal_single_pair_path(tables):
+    """Batched launches of the quad variants with halos of 4 and 6, at the
+    longest runs their windows allow (run lengths above that are cut to the
+    halo), equal the single-pair path on the process-wide tables."""
+    c = CONFIG_PARAMS[4]
+    prm = ff.Params(levels=c.levels, iters=c.iters)
+    shapes = [(192, 256), (231, 300), (200, 451), (17, 700)]
+    b = BatchFlowFields(shapes, prm, tables=tables)
+    imgs = []
+    for k, shp in enumerate(shapes):
+        p = make_pair(4, k, shape=shp)
+        i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+        imgs.append((i1, i2))
+        b.set_pair(k, i1, i2)
+    outs = [_host(o) for o in b.run()]
+    for k, (i1, i2) in enumerate(imgs):
+        single = _host(ff.flow_fields(i1, i2, prm))
+        for key in KEYS:
+            assert np.array_equal(outs[k][key], single[key]), (k, key)

@@ -362,7 +362,9 @@ def test_run_length_does_not_change_results(passes):
 
 @pytest.mark.parametrize("table", [([4, 7, 6, 6, 6, 3, 3], [1, 2, 2, 3, 3, 0, 0]),
                                    ([2, 5, 3, 7, 6, 3, 3], [1, 1, 1, 1, 1, 1, 1]),
-                                   ([0, 1, 4, 2, 8, 3, 3], [3, 2, 0, 1, 2, 0, 0])])
+                                   ([0, 1, 4, 2, 8, 3, 3], [3, 2, 0, 1, 2, 0, 0]),
+                                   ([16, 17, 13, 14, 16, 3, 3], [7, 7, 7, 7, 7, 0, 0]),
+                                   ([17, 16, 14, 13, 12, 11, 15], [4, 3, 6, 5, 2, 1, 0])])
 @pytest.mark.parametrize("case", [(2, 0), (5, 16)])
 def test_mixed_variant_and_run_length_tables_bit_exact(table, case):
     """Launch tables mixing variants and run lengths per scale (as the
