@@ -338,6 +338,17 @@ int32_t ff_level_variant_count(void);
 int32_t ff_get_level_variant(int32_t log2n);
 ff_status ff_set_level_variant(int32_t log2n, int32_t variant);
 
+/* Tile of the temporally blocked level kernel that ff_flow_fields_f32 uses
+ * at scale n = 2^log2n, log2n in [0, 6]: variant 0 = 16x16 cells, 1 = 8x8
+ * cells (more workgroups for the small grids of the coarse scales; default
+ * 0 for n <= 2, 1 from n = 4 on).  Process-wide table (host), like the
+ * variant table of the byte-descriptor path; it changes speed only, never
+ * results.  ff_set_level_variant_f32 returns FF_ERR_ARG for log2n or variant
+ * out of range; ff_get_level_variant_f32 returns -1 for log2n out of range. */
+int32_t ff_level_variant_count_f32(void);
+int32_t ff_get_level_variant_f32(int32_t log2n);
+ff_status ff_set_level_variant_f32(int32_t log2n, int32_t variant);
+
 /* Most propagation steps per temporally blocked launch at scale 2^log2n, for
  * the byte-descriptor path (cost_kind 0) or the learned float features
  * (cost_kind 1); 0 = as many as the kernel's halo allows (the default).

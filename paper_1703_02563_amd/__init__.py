@@ -6,9 +6,11 @@ Python binding.
 """
 from .ffi import FlowFieldsError, lib  # noqa: F401
 from .flowfields import (FlowFields, Params, consistency_filter, descriptors, flow_fields,  # noqa: F401
-                         init_nn, level_passes, level_variants, propagate_level, random_search, rs_radius, run_level,
-                         seed_level, set_level_passes, set_level_variants, workspace_bytes)
+                         init_nn, level_passes, level_variants, level_variants_f32, propagate_level, random_search,
+                         rs_radius, run_level, seed_level, set_level_passes, set_level_variants,
+                         set_level_variants_f32, workspace_bytes)
 
 __all__ = ["FlowFieldsError", "lib", "FlowFields", "Params", "consistency_filter", "descriptors", "flow_fields",
-           "init_nn", "level_passes", "level_variants", "set_level_passes", "set_level_variants", "propagate_level",
-           "random_search", "rs_radius", "run_level", "seed_level", "workspace_bytes"]
+           "init_nn", "level_passes", "level_variants", "level_variants_f32", "set_level_passes", "set_level_variants",
+           "set_level_variants_f32", "propagate_level", "random_search", "rs_radius", "run_level", "seed_level",
+           "workspace_bytes"]

@@ -126,7 +126,8 @@ int run_end(int t0, int T, int maxp, int halo = ffh::kLevelHalo) {
 int level_runs(int lv, int T, int fcost, int runs[][2]) {
   int m = 0, t0 = 0;
   while (t0 < T) {
-    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), fcost ? ffh::kLevelHaloF32 : ffh::level_window_halo(lv));
+    const int halo = fcost ? ffh::level_window_halo_f32(lv) : ffh::level_window_halo(lv);
+    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), halo);
     runs[m][0] = t0;
     runs[m][1] = t1;
     ++m;
@@ -853,6 +854,14 @@ int32_t ff_level_launches(int32_t iters, int32_t log2n, int32_t cost_kind) {
 
 ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes) {
   return ffh::set_level_passes(log2n, cost_kind, passes) ? FF_OK : FF_ERR_ARG;
+}
+
+int32_t ff_level_variant_count_f32(void) { return ffh::level_variant_count_f32(); }
+
+int32_t ff_get_level_variant_f32(int32_t log2n) { return ffh::get_level_variant_f32(log2n); }
+
+ff_status ff_set_level_variant_f32(int32_t log2n, int32_t variant) {
+  return ffh::set_level_variant_f32(log2n, variant) ? FF_OK : FF_ERR_ARG;
 }
 
 int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }

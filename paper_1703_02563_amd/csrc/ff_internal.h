@@ -76,7 +76,6 @@ hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
 // follows pass t iff t < T - 1.  halo[] = half-sweeps reading the left,
 // right, top, bottom side over the run (at most kLevelHalo each).
 constexpr int kLevelHalo = 6;
-constexpr int kLevelHaloF32 = 2;  // the float-feature kernels keep a halo of 2: one step per launch
 constexpr int kLevelContinue = 0;  // state from the level grid in global memory
 constexpr int kLevelInit = 1;      // coarsest scale: flows from the NN keys
 constexpr int kLevelSeed = 2;      // seeds from the coarser grid, other cells UNSET
@@ -111,7 +110,7 @@ hipError_t launch_level(LevelKArgs a, hipStream_t stream);
 struct BatchStage;
 #define FF_LEVEL_SCALE_DECL(k)                                                                          \
   hipError_t launch_level_scale##k(const LevelKArgs &a, const BatchStage *batch, int variant, hipStream_t s); \
-  hipError_t launch_level_f32_scale##k(const LevelKArgs &a, hipStream_t s);
+  hipError_t launch_level_f32_scale##k(const LevelKArgs &a, int variant, hipStream_t s);
 FF_LEVEL_SCALE_DECL(0)
 FF_LEVEL_SCALE_DECL(1)
 FF_LEVEL_SCALE_DECL(2)
@@ -121,11 +120,15 @@ FF_LEVEL_SCALE_DECL(5)
 FF_LEVEL_SCALE_DECL(6)
 #undef FF_LEVEL_SCALE_DECL
 int level_window_halo(int log2n);              // halo of the blocked kernel the table selects
+int level_window_halo_f32(int log2n);          // the same for the float-feature kernel
 bool level_map_fits(int W, int H, int log2n);  // scale-n map under 2^31 bytes (quad evaluations)
 void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();
 int get_level_variant(int log2n);
 bool set_level_variant(int log2n, int variant);
+int level_variant_count_f32();
+int get_level_variant_f32(int log2n);
+bool set_level_variant_f32(int log2n, int variant);
 bool level_stepwise(int log2n);  // the table selects the step-wise schedule for this scale
 int get_level_passes(int log2n, int fcost);  // most propagation steps per blocked launch (0: no limit)
 bool set_level_passes(int log2n, int fcost, int passes);

@@ -30,7 +30,7 @@ constexpr int kNumVariants = 18;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);
-using ScaleLaunchF32 = hipError_t (*)(const ffh::LevelKArgs &, hipStream_t);
+using ScaleLaunchF32 = hipError_t (*)(const ffh::LevelKArgs &, int, hipStream_t);
 constexpr ScaleLaunch kScale[7] = {ffh::launch_level_scale0, ffh::launch_level_scale1, ffh::launch_level_scale2,
                                    ffh::launch_level_scale3, ffh::launch_level_scale4, ffh::launch_level_scale5,
                                    ffh::launch_level_scale6};
@@ -45,10 +45,20 @@ hipError_t dispatch(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
   return kScale[log2n](a, batch, variant, stream);
 }
 
-// Float features: 16x16 tiles (image a's samples staged in LDS, 64 bytes each).
+// Window halo of every variant of the float-feature level kernel (image a's
+// samples staged in LDS, 64 bytes each; launch_nf32 in ff_level_kernels.h
+// maps each index to its tile and kernel): 16x16 / 8x8 / 8x8 / 8x8 / 16x16.
+constexpr int kHaloF32[] = {2, 2, 4, 6, 4};
+constexpr int kNumVariantsF32 = 5;
+static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float variant table");
+
+// Per-scale float variant (index log2 n); written by ff_set_level_variant_f32.
+// 8x8 tiles from n = 4 on, where 16x16 tiles leave most compute units idle.
+int g_variant_f32[7] = {0, 0, 1, 1, 1, 1, 1};
+
 hipError_t dispatch_f32(const ffh::LevelKArgs &a, int log2n, hipStream_t stream) {
   if (log2n < 0 || log2n >= 7) return hipErrorInvalidValue;
-  return kScaleF32[log2n](a, stream);
+  return kScaleF32[log2n](a, g_variant_f32[log2n], stream);
 }
 
 // Per-scale variant table (index log2 n); written by ff_set_level_variant.
@@ -86,6 +96,16 @@ static int blocked_variant(int log2n) {
   return v == kNumVariants ? 3 : v;
 }
 
+int level_variant_count_f32() { return kNumVariantsF32; }
+
+int get_level_variant_f32(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant_f32[log2n] : -1; }
+
+bool set_level_variant_f32(int log2n, int variant) {
+  if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= kNumVariantsF32) return false;
+  g_variant_f32[log2n] = variant;
+  return true;
+}
+
 bool set_level_variant(int log2n, int variant) {
   if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= level_variant_count()) return false;
   g_variant[log2n] = variant;
@@ -96,6 +116,11 @@ static int log2_of(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
+}
+
+int level_window_halo_f32(int log2n) {
+  const int v = get_level_variant_f32(log2n);
+  return v < 0 ? 2 : kHaloF32[v];
 }
 
 int level_window_halo(int log2n) {

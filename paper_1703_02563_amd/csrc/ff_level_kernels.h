@@ -605,12 +605,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 
 }
 
 // Float learned features (padded float maps in LevelKDir::Da/Db).
-template <int LOG2N, int TW, int TH, int kThreads>
+template <int LOG2N, int TW, int TH, int kThreads, int HALO>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_level_f32(
     ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  level_body<LOG2N, TW, TH, kThreads, 1, true, ffh::kLevelHaloF32>(a, a.dir[wg / tiles], wg % tiles);
+  level_body<LOG2N, TW, TH, kThreads, 1, true, HALO>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
@@ -664,13 +664,30 @@ hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipS
   return hipGetLastError();
 }
 
-template <int LOG2N, int TW, int TH, int THREADS>
+template <int LOG2N, int TW, int TH, int THREADS, int HALO>
 hipError_t launch_f32(const ffh::LevelKArgs &a, hipStream_t stream) {
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
-  hipLaunchKernelGGL((k_level_f32<LOG2N, TW, TH, THREADS>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  hipLaunchKernelGGL((k_level_f32<LOG2N, TW, TH, THREADS, HALO>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream,
+                     b);
   return hipGetLastError();
+}
+
+// Float-feature variant index -> kernel; kHaloF32 in ff_level.hip lists the
+// window halo of every index, which must match.  16x16 or 8x8 tiles (the
+// latter for the small grids of the coarse scales); a halo of 2 allows one
+// step per launch, 4 two and 6 three.
+template <int LOG2N>
+hipError_t launch_nf32(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_f32<LOG2N, 16, 16, 256, 2>(a, stream);
+    case 1: return launch_f32<LOG2N, 8, 8, 256, 2>(a, stream);
+    case 2: return launch_f32<LOG2N, 8, 8, 256, 4>(a, stream);
+    case 3: return launch_f32<LOG2N, 8, 8, 256, 6>(a, stream);
+    case 4: return launch_f32<LOG2N, 16, 16, 256, 4>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Variant index -> kernel; the tile and halo of every index are listed in

@@ -7,8 +7,8 @@ hipError_t launch_level_scale3(const LevelKArgs &a, const BatchStage *batch, int
   return launch_n<3>(a, batch, variant, stream);
 }
 
-hipError_t launch_level_f32_scale3(const LevelKArgs &a, hipStream_t stream) {
-  return launch_f32<3, 16, 16, 256>(a, stream);
+hipError_t launch_level_f32_scale3(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_nf32<3>(a, variant, stream);
 }
 
 }  // namespace ffh

@@ -7,8 +7,8 @@ hipError_t launch_level_scale5(const LevelKArgs &a, const BatchStage *batch, int
   return launch_n<5>(a, batch, variant, stream);
 }
 
-hipError_t launch_level_f32_scale5(const LevelKArgs &a, hipStream_t stream) {
-  return launch_f32<5, 16, 16, 256>(a, stream);
+hipError_t launch_level_f32_scale5(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_nf32<5>(a, variant, stream);
 }
 
 }  // namespace ffh

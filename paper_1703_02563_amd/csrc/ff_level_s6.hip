@@ -7,8 +7,8 @@ hipError_t launch_level_scale6(const LevelKArgs &a, const BatchStage *batch, int
   return launch_n<6>(a, batch, variant, stream);
 }
 
-hipError_t launch_level_f32_scale6(const LevelKArgs &a, hipStream_t stream) {
-  return launch_f32<6, 16, 16, 256>(a, stream);
+hipError_t launch_level_f32_scale6(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_nf32<6>(a, variant, stream);
 }
 
 }  // namespace ffh

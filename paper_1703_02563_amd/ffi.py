@@ -76,6 +76,9 @@ _SIGS = {
     "ff_level_variant_count": (C.c_int32, []),
     "ff_get_level_variant": (C.c_int32, [_I32]),
     "ff_set_level_variant": (C.c_int, [_I32, _I32]),
+    "ff_level_variant_count_f32": (C.c_int32, []),
+    "ff_get_level_variant_f32": (C.c_int32, [_I32]),
+    "ff_set_level_variant_f32": (C.c_int, [_I32, _I32]),
     "ff_get_level_passes": (C.c_int32, [_I32, _I32]),
     "ff_set_level_passes": (C.c_int, [_I32, _I32, _I32]),
     "ff_level_launches": (C.c_int32, [_I32, _I32, _I32]),

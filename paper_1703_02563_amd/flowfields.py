@@ -168,6 +168,18 @@ def set_level_variants(table) -> None:
         check(lib().ff_set_level_variant(k, int(v)), "ff_set_level_variant")
 
 
+def level_variants_f32() -> list:
+    """Current float-feature level-kernel variant per scale (index log2 n)."""
+    return [int(lib().ff_get_level_variant_f32(k)) for k in range(7)]
+
+
+def set_level_variants_f32(table) -> None:
+    """Sets the float-feature level-kernel variant of every scale (0: 16x16
+    tiles, 1: 8x8 tiles)."""
+    for k, v in enumerate(table):
+        check(lib().ff_set_level_variant_f32(k, int(v)), "ff_set_level_variant_f32")
+
+
 def level_passes(cost_kind: int = 0) -> list:
     """Most propagation steps per blocked launch, per scale (0 = no limit)."""
     return [int(lib().ff_get_level_passes(l2, cost_kind)) for l2 in range(7)]

@@ -90,6 +90,18 @@ def test_descriptor_map_bytes():
     assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0
 
 
+def test_float_level_variant_table_validation():
+    lib = ff.lib()
+    assert lib.ff_level_variant_count_f32() == 5
+    assert ff.level_variants_f32() == [0, 0, 1, 1, 1, 1, 1]
+    assert lib.ff_get_level_variant_f32(7) == -1 and lib.ff_get_level_variant_f32(-1) == -1
+    assert lib.ff_set_level_variant_f32(0, 5) == ffi.FF_ERR_ARG
+    assert lib.ff_set_level_variant_f32(0, -1) == ffi.FF_ERR_ARG
+    assert lib.ff_set_level_variant_f32(7, 0) == ffi.FF_ERR_ARG
+    assert lib.ff_set_level_variant_f32(3, 0) == ffi.FF_OK and lib.ff_get_level_variant_f32(3) == 0
+    assert lib.ff_set_level_variant_f32(3, 1) == ffi.FF_OK
+
+
 def test_level_passes_table_validation():
     lib = ff.lib()
     assert lib.ff_get_level_passes(0, 0) == 0 and lib.ff_get_level_passes(7, 0) == -1

@@ -217,10 +217,15 @@ def test_quantize_matches_oracle():
     assert np.array_equal(q, oracle.quantize_u8(f))
 
 
+@pytest.mark.parametrize("tiles", [None, 0, 1, 2, 3, 4])
 @pytest.mark.parametrize("shape,L,T,passes", [((40, 56), 3, 4, 0), ((33, 1), 2, 3, 0), ((1, 1), 1, 1, 0),
                                               ((120, 160), 3, 4, 0), ((61, 95), 4, 5, 0), ((61, 95), 4, 5, 1),
-                                              ((120, 160), 3, 4, 2)])
-def test_learned_flow_fields_bit_exact(shape, L, T, passes):
+                                              ((120, 160), 3, 4, 2), ((150, 211), 5, 4, 0)])
+def test_learned_flow_fields_bit_exact(shape, L, T, passes, tiles):
+    """Float-feature fields equal the oracle for the default variant table
+    and with every scale on one variant (16x16 or 8x8 tiles, windows with a
+    halo of 2, 4 or 6: with run length 0 the wider windows run two or three
+    steps per launch)."""
     H, W = shape
     pad = 10
     canvas = feature_canvas(11 + H, H + 2 * pad, W + 2 * pad)
@@ -229,14 +234,17 @@ def test_learned_flow_fields_bit_exact(shape, L, T, passes):
     m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
     prm = ff.Params(levels=L, iters=T)
     o = oracle.flow_fields_f32(m1, m2, L, T, nthreads=NT)
-    saved = ff.level_passes(1)
+    saved, saved_v = ff.level_passes(1), ff.level_variants_f32()
     try:
         ff.set_level_passes([passes] * 7, 1)
+        if tiles is not None:
+            ff.set_level_variants_f32([tiles] * 7)
         g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2],
                                prm)
         torch.cuda.synchronize()
     finally:
         ff.set_level_passes(saved, 1)
+        ff.set_level_variants_f32(saved_v)
     for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
         assert np.array_equal(g[k].cpu().numpy(), o[k]), k
     for k in ("cost_fwd", "cost_bwd"):
