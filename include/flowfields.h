@@ -260,14 +260,16 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
 
 /* out[p][co] = bias[co] + sum_{tap, ci} w[co][tap][ci] * in[p + d(tap)][ci],
  * then max(0, .) if relu; written as float32 and/or bf16 (either nullable,
- * not both); bias nullable. */
+ * not both); bias nullable.  in must be 16-byte aligned when cin >= 16
+ * (FF_ERR_ARG otherwise). */
 ff_status ff_conv3x3_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
                          const uint16_t *w, const float *bias, int32_t relu, float *out_f32, uint16_t *out_bf16,
                          void *stream);
 
 /* Gradient with respect to the input of a (cin -> cout) layer: the same
  * convolution of gout ([B][H][W][cout] bf16) with the weights rotated by 180
- * degrees and transposed (written to wflip_scratch, cin*9*cout bf16). */
+ * degrees and transposed (written to wflip_scratch, cin*9*cout bf16); gout
+ * 16-byte aligned (FF_ERR_ARG otherwise). */
 ff_status ff_conv3x3_bwd_data(const uint16_t *gout, int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout,
                               const uint16_t *w, uint16_t *wflip_scratch, float *gin_f32, uint16_t *gin_bf16,
                               void *stream);

@@ -746,6 +746,7 @@ ff_status ff_conv3x3_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, in
                          const uint16_t *w, const float *bias, int32_t relu, float *out_f32, uint16_t *out_bf16,
                          void *stream) {
   if (!in || !w || (!out_f32 && !out_bf16) || !conv_shape_ok(B, H, W, cin, cout)) return FF_ERR_ARG;
+  if (cin >= 16 && !aligned16(in)) return FF_ERR_ARG;  // 16-byte loads of input channel chunks
   ffh::ConvArgs a{};
   a.in = in;
   a.w = w;

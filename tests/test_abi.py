@@ -72,6 +72,8 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter(fake, fake, fake, None, 5, 5, 1.0, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_init_nn(fake, fake, fake, fake, 5, 5, 6, 3, fake, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+    # misaligned convolution input (16-byte loads of channel chunks)
+    assert lib.ff_conv3x3_fwd(C.c_void_p(0x1008), 1, 4, 4, 32, 32, fake, None, 0, None, fake, None) == ffi.FF_ERR_ARG
 
 
 def test_python_binding_rejects_host_tensors():
