@@ -52,12 +52,12 @@ def lib():
         L.or_rs_radius.argtypes = [i, i, i]
         L.or_rs_radius.restype = i
         L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
-        L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
+        L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
         L.or_cost_f32.restype = C.c_uint32
         L.or_quantize_u8.argtypes = [P, C.c_int64, P]
-        L.or_flow_fields_f32.argtypes = [P, P, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
+        L.or_flow_fields_f32.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields_f32.restype = i
         _lib = L
     return _lib
@@ -177,7 +177,11 @@ def consistency(fa, ca, fb, cb, eps: float = 1.0):
 
 
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
-                eps: float = 1.0, seed: int = 12345, nthreads: int = 1) -> dict:
+                eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
+                fine_iters: int = 0) -> dict:
+    """The whole schedule on one pair.  plus_iters > 0: Flow Fields+ (P steps
+    at R^+ = Rp_num / R_den before the `iters` steps at R); fine_iters > 0:
+    the finest scale runs only that many steps at R (Flow Fields+ Fast)."""
     img1, img2 = _u8(img1), _u8(img2)
     H, W = img1.shape
     out = {
@@ -186,8 +190,8 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
         "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
     }
     ne = np.zeros(2, np.uint64)
-    rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, float(eps), seed,
-                              nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
+    rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters, Rp_num,
+                              fine_iters, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
                               _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -213,7 +217,8 @@ def quantize_u8(f) -> np.ndarray:
 
 
 def flow_fields_f32(F1, F2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
-                    eps: float = 1.0, seed: int = 12345, nthreads: int = 1) -> dict:
+                    eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
+                    fine_iters: int = 0) -> dict:
     """The multi-scale schedule on learned float features F1[l], F2[l]
     (float32 [H][W][16] per scale 2^l); costs come back as float32."""
     F1 = [np.ascontiguousarray(f, np.float32) for f in F1]
@@ -228,7 +233,7 @@ def flow_fields_f32(F1, F2, levels: int, iters: int, radius: int = 3, R_num: int
     }
     ne = np.zeros(2, np.uint64)
     rc = lib().or_flow_fields_f32(C.cast(arr1, C.c_void_p), C.cast(arr2, C.c_void_p), W, H, levels, iters, radius,
-                                  R_num, R_den, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]),
+                                  R_num, R_den, plus_iters, Rp_num, fine_iters, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]),
                                   _p(out["cost_fwd"]), _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]),
                                   _p(ne))
     if rc != 0:

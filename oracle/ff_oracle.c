@@ -42,7 +42,9 @@
  *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14).
  *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
- *               random-search steps between them, forward and backward.
+ *               random-search steps between them, forward and backward;
+ *               optionally the Flow Fields+ steps (Sec. 3.3: P steps at
+ *               R^+ first) and the Fast finest scale (Sec. 3.4).
  *
  * Layouts: images uint8 [H][W]; descriptors uint8 [H][W][16]; a level grid
  * of scale n has ceil(W/n) x ceil(H/n) cells, cell (i, j) <-> pixel
@@ -415,11 +417,40 @@ void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, co
 /* R_n = floor(R * n) with R = R_num / R_den (R6). */
 int or_rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
 
-/* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b. */
+/* Steps of one scale.  The original schedule (Sec. 3.2): T propagation
+ * steps, a random search at R_n after each but the last.  Flow Fields+
+ * (Sec. 3.3): first P steps whose random searches use R_n^+ = R^+ n, then T
+ * steps at R_n; random searches sit only between two steps of the same
+ * group (P - 1 and T - 1 of them), and the step index t, which sets the
+ * direction t mod 4 and keys the generator, runs on over both groups.
+ * Flow Fields+ Fast (Sec. 3.4): the finest scale runs only Tfine steps at
+ * R_n (no R^+ group) when Tfine > 0. */
+typedef struct {
+    int P, T;      /* steps at R_n^+, then at R_n */
+    int Rn, Rnp;   /* R_n and R_n^+ */
+} or_scale_steps;
+
+static or_scale_steps scale_steps(int level, int T, int R_num, int R_den, int P, int Rp_num, int Tfine)
+{
+    int n = 1 << level;
+    or_scale_steps st;
+    st.P = P;
+    st.T = T;
+    if (level == 0 && Tfine > 0) {
+        st.P = 0;
+        st.T = Tfine;
+    }
+    st.Rn = or_rs_radius(n, R_num, R_den);
+    st.Rnp = or_rs_radius(n, Rp_num, R_den);
+    return st;
+}
+
+/* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, with the
+ * per-scale steps of scale_steps. */
 static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
                                const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
-                               uint64_t seed, int stream, int nthreads, int16_t *flow_out, uint32_t *cost_out,
-                               uint64_t *n_evals)
+                               int P, int Rp_num, int Tfine, uint64_t seed, int stream, int nthreads,
+                               int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
 {
     int nc = 1 << (L - 1);
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
@@ -441,12 +472,13 @@ static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *N
             seed_level_g(E, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
             cur ^= 1;
         }
-        int Rn = or_rs_radius(n, R_num, R_den);
-        for (int t = 0; t < T; ++t) {
+        or_scale_steps st = scale_steps(level, T, R_num, R_den, P, Rp_num, Tfine);
+        for (int t = 0; t < st.P + st.T; ++t) {
             propagate_g(E, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
-            if (t < T - 1)
-                random_search_g(E, Da[level], Db[level], W, H, n, r, Rn, seed, stream, level, t, fl[cur],
-                                co[cur], n_evals, nthreads);
+            int last_of_group = t == st.P - 1 || t == st.P + st.T - 1;
+            if (!last_of_group)
+                random_search_g(E, Da[level], Db[level], W, H, n, r, t < st.P ? st.Rnp : st.Rn, seed, stream,
+                                level, t, fl[cur], co[cur], n_evals, nthreads);
         }
     }
     memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells0);
@@ -461,12 +493,12 @@ static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *N
  * field (img2 -> img1, stream 1) and both consistency masks.
  * n_evals[0], n_evals[1]: number of E_n evaluations of each direction. */
 int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r,
-                   int R_num, int R_den, double eps, uint64_t seed, int nthreads,
+                   int R_num, int R_den, int P, int Rp_num, int Tfine, double eps, uint64_t seed, int nthreads,
                    int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                    uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
-        R_num < 0 || R_den < 1)
+        R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64)
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *blur = (uint8_t *)malloc(np);
@@ -482,9 +514,9 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
     }
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(cost_u8, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
-                       R_num, R_den, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+                       R_num, R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
     flow_one_direction(cost_u8, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
-                       R_num, R_den, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+                       R_num, R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
@@ -498,12 +530,12 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
  * matching error is or_cost_f32 (costs are returned as float bit patterns).
  */
 int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, int H, int L, int T, int r,
-                       int R_num, int R_den, double eps, uint64_t seed, int nthreads, int16_t *flow_fwd,
-                       int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd,
-                       uint8_t *keep_bwd, uint64_t *n_evals)
+                       int R_num, int R_den, int P, int Rp_num, int Tfine, double eps, uint64_t seed,
+                       int nthreads, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                       uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
-        R_num < 0 || R_den < 1)
+        R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64)
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *q1 = (uint8_t *)malloc(np * 16), *q2 = (uint8_t *)malloc(np * 16);
@@ -511,9 +543,9 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
     or_quantize_u8(F2[0], (int64_t)np * 16, q2);
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(cost_f32, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
-                       R_den, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+                       R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
     flow_one_direction(cost_f32, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
-                       R_den, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+                       R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     free(q1);

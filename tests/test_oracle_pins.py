@@ -446,3 +446,94 @@ def test_evaluation_count_bound():
         bound += cells * (2 * T + T - 1) + cells  # + one seed evaluation per cell at most
     assert max(o["n_evals"]) <= bound
     assert min(o["n_evals"]) > 0
+
+
+# ---------------------------------------------------------------- Flow Fields+ schedules (Sec. 3.3, 3.4)
+
+def _scale_steps_by_hand(level, T, P, Tfine):
+    """(steps at R^+, steps at R) of one scale, restated from Sec. 3.3 and
+    3.4: P steps at R^+ then T at R; the Fast finest scale only Tfine at R."""
+    if level == 0 and Tfine > 0:
+        return 0, Tfine
+    return P, T
+
+
+@pytest.mark.parametrize("P,Rp,Tfine", [(4, 2, 0), (4, 2, 4), (2, 3, 0), (3, 2, 1)])
+def test_flow_fields_plus_is_the_step_sequence_of_the_paper(P, Rp, Tfine):
+    """The oracle's Flow Fields+ driver equals the composition of its
+    separately pinned steps in the order Sec. 3.3 gives: P propagation steps
+    with random searches at R_n^+ = R^+ n between them, then T steps with
+    random searches at R_n between them (none between the two groups), the
+    step index running on across both (directions t mod 4); Fast (Sec. 3.4):
+    only Tfine steps at R on the finest scale."""
+    p = make_pair(1)
+    L, T, seed = 3, 4, 777
+    o = oracle.flow_fields(p.img1, p.img2, L, T, seed=seed, nthreads=4, plus_iters=P, Rp_num=Rp,
+                           fine_iters=Tfine)
+    Da, Db = oracle.descriptors_all(p.img1, L), oracle.descriptors_all(p.img2, L)
+    nc = 1 << (L - 1)
+    idx, _ = oracle.nn(Da[0], Db[0], nc, nthreads=4)
+    flow, cost, ne = oracle.init_coarse(idx, Da[L - 1], Db[L - 1], nc)
+    for level in range(L - 1, -1, -1):
+        n = 1 << level
+        if level < L - 1:
+            flow, cost, k = oracle.seed_level(flow, cost, Da[level], Db[level], n)
+            ne += k
+        Pl, Tl = _scale_steps_by_hand(level, T, P, Tfine)
+        for t in range(Pl + Tl):
+            flow, cost, k = oracle.propagate(Da[level], Db[level], n, t, flow, cost, nthreads=4)
+            ne += k
+            if t != Pl - 1 and t != Pl + Tl - 1:
+                Rn = n * Rp if t < Pl else n  # R = 1, R^+ = Rp
+                flow, cost, k = oracle.random_search(Da[level], Db[level], n, Rn, seed, 0, level, t, flow, cost,
+                                                     nthreads=4)
+                ne += k
+    assert np.array_equal(o["flow_fwd"], flow)
+    assert np.array_equal(o["cost_fwd"], cost)
+    assert o["n_evals"][0] == ne
+
+
+def test_fast_with_all_steps_at_the_finest_scale_is_the_original_schedule():
+    """Without an R^+ group, Fast with Tfine = T is the original schedule."""
+    p = make_pair(1)
+    a = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4)
+    b = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4, fine_iters=4)
+    for k in ("flow_fwd", "flow_bwd", "cost_fwd", "cost_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(a[k], b[k])
+    assert a["n_evals"] == b["n_evals"]
+
+
+@pytest.mark.parametrize("t", [(6, -4), (-11, 3)])
+def test_flow_fields_plus_recovers_an_integer_translation(t):
+    img1, img2 = translated_crops(71, 56, 72, t[0], t[1])
+    o = oracle.flow_fields(img1, img2, 3, 8, nthreads=2, plus_iters=4, Rp_num=2)
+    H, W = img1.shape
+    m = 7
+    ys, xs = np.mgrid[0:H, 0:W]
+    inner = (xs >= m) & (xs < W - m) & (ys >= m) & (ys < H - m)
+    inner &= (xs + t[0] >= m) & (xs + t[0] < W - m) & (ys + t[1] >= m) & (ys + t[1] < H - m)
+    f = o["flow_fwd"]
+    assert np.all(f[inner][:, 0] == t[0]) and np.all(f[inner][:, 1] == t[1])
+    assert np.all(o["cost_fwd"][inner] == 0)
+
+
+def test_flow_fields_plus_evaluation_count_bound():
+    """At most 2 evaluations per cell and step, 1 per random search (P - 1
+    + T - 1 of them) and 1 seed evaluation per cell and scale."""
+    p = make_pair(1)
+    L, T, P = 3, 8, 4
+    o = oracle.flow_fields(p.img1, p.img2, L, T, nthreads=4, plus_iters=P, Rp_num=2)
+    H, W = p.img1.shape
+    bound = 0
+    for lv in range(L):
+        n = 1 << lv
+        cells = (-(-W // n)) * (-(-H // n))
+        bound += cells * (2 * (P + T) + (P - 1) + (T - 1)) + cells
+    assert 0 < min(o["n_evals"]) and max(o["n_evals"]) <= bound
+
+
+def test_flow_fields_plus_rejects_bad_schedules():
+    img, _ = random_images(3, 20, 20)
+    for kw in ({"plus_iters": -1}, {"fine_iters": -2}, {"plus_iters": 60, "Rp_num": 2}, {"Rp_num": -1}):
+        with pytest.raises(ValueError):
+            oracle.flow_fields(img, img, 2, 8, **kw)
