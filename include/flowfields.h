@@ -59,6 +59,17 @@ typedef struct {
     int32_t R_den;   /*   integer offset bound is R_n = floor(R_num * n / R_den) */
     float eps;       /* consistency threshold: keep iff |F(p) + F_b(p + F(p))| < eps */
     uint64_t seed;   /* key of the counter-based random-search generator */
+    /* Flow Fields+ (Sec. 3.3): plus_iters = P > 0 runs, on every scale, P
+     * propagation steps whose random searches use R_n^+ = floor(Rp_num * n /
+     * R_den) before the T steps at R_n; random searches sit only between two
+     * steps of the same group, and the step index t (direction t mod 4,
+     * generator counter) runs on over both groups.  P = 0: the original
+     * schedule.  Flow Fields+ Fast (Sec. 3.4): fine_iters > 0 makes the finest
+     * scale run only fine_iters steps at R_n.  Limits: P + T <= 64,
+     * fine_iters <= 64, Rp_num in [0, 2^20]. */
+    int32_t plus_iters;
+    int32_t Rp_num;
+    int32_t fine_iters;
 } ff_params;
 
 /* Library version (host). */

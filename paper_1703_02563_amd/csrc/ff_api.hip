@@ -27,10 +27,33 @@ ff_status from_hip(hipError_t e) { return e == hipSuccess ? FF_OK : FF_ERR_LAUNC
 
 bool params_ok(const ff_params *p) {
   return p && p->levels >= 1 && p->levels <= kMaxLevels && p->iters >= 1 && p->iters <= 64 && p->radius >= 0 &&
-         p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20;
+         p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20 &&
+         p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
+         p->fine_iters >= 0 && p->fine_iters <= 64;
 }
 
 int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
+
+// Steps of scale lv: P steps whose random searches use R_n^+, then T at R_n
+// (Flow Fields+, Sec. 3.3; P = 0 is the original schedule of Sec. 3.2), or
+// only fine_iters steps at R_n on the finest scale (Flow Fields+ Fast, Sec.
+// 3.4).  A random search follows step t unless t ends its group.
+struct ScaleSteps {
+  int P, T, Rn, Rnp;
+  int total() const { return P + T; }
+  bool rs_after(int t) const { return t != P - 1 && t != P + T - 1; }
+  int radius(int t) const { return t < P ? Rnp : Rn; }
+};
+
+ScaleSteps scale_steps(const ff_params *p, int lv) {
+  const int n = 1 << lv;
+  ScaleSteps st{p->plus_iters, p->iters, rs_radius(n, p->R_num, p->R_den), rs_radius(n, p->Rp_num, p->R_den)};
+  if (lv == 0 && p->fine_iters > 0) {
+    st.P = 0;
+    st.T = p->fine_iters;
+  }
+  return st;
+}
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
@@ -147,14 +170,18 @@ int level_runs(int lv, int T, int fcost, int runs[][2]) {
 // launch writes flow/cost.
 hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_params *p, int first_mode,
                              hipStream_t s, int32_t *const *sflow = nullptr, uint32_t *const *scost = nullptr) {
-  const int n = 1 << lv, T = p->iters;
+  const int n = 1 << lv;
+  const ScaleSteps sst = scale_steps(p, lv);
+  const int T = sst.total();
   k.W = W;
   k.H = H;
   k.n = n;
   k.Wn = ceil_div(W, n);
   k.Hn = ceil_div(H, n);
   k.level = lv;
-  k.Rn = rs_radius(n, p->R_num, p->R_den);
+  k.Rn = sst.Rn;
+  k.Rnp = sst.Rnp;
+  k.P = sst.P;
   k.seed = p->seed;
   k.T = T;
   int runs[64][2];
@@ -214,15 +241,17 @@ hipError_t run_level_steps(ffh::LevelArgs a, int W, int H, int lv, int L, const 
   a.Wn = ceil_div(W, n);
   a.Hn = ceil_div(H, n);
   a.level = lv;
-  a.Rn = rs_radius(n, p->R_num, p->R_den);
+  const ScaleSteps st = scale_steps(p, lv);
+  a.Rn = st.Rn;
   a.radius = p->radius;
   a.seed = p->seed;
   hipError_t e = (lv == L - 1) ? ffh::launch_init_coarse(a, s) : ffh::launch_seed_level(a, s);
   if (e != hipSuccess) return e;
-  for (int t = 0; t < p->iters; ++t) {
+  for (int t = 0; t < st.total(); ++t) {
     a.pass = t;
     if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return e;
-    if (t < p->iters - 1 && (e = ffh::launch_random_search(a, s)) != hipSuccess) return e;
+    a.Rn = st.radius(t);
+    if (st.rs_after(t) && (e = ffh::launch_random_search(a, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -347,7 +376,8 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
     return FF_ERR_ARG;
   if (!scratch || scratch_bytes < ff_run_level_scratch_bytes(W, H, level)) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  const int n = 1 << level, r = params->radius, T = params->iters;
+  const int n = 1 << level, r = params->radius;
+  const ScaleSteps st = scale_steps(params, level);
   if (r == 3) {
     ffh::LevelKArgs k{};
     k.ndir = 1;
@@ -368,7 +398,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
   ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, r, flow, cost, n_evals);
   a.level = level;
   a.seed = params->seed;
-  a.Rn = rs_radius(n, params->R_num, params->R_den);
+  a.Rn = st.Rn;
   a.dir[0].stream_id = stream_id;
   a.dir[0].nn_key = nn_key;
   a.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
@@ -376,10 +406,11 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
   hipError_t e = hipSuccess;
   if (mode == 1) return FF_ERR_UNSUPPORTED;  // the per-step path seeds through ff_init_nn
   if (mode == 2) e = ffh::launch_seed_level(a, s);
-  for (int t = 0; t < T && e == hipSuccess; ++t) {
+  for (int t = 0; t < st.total() && e == hipSuccess; ++t) {
     a.pass = t;
     e = ffh::launch_propagate(a, s);
-    if (e == hipSuccess && t < T - 1) e = ffh::launch_random_search(a, s);
+    a.Rn = st.radius(t);
+    if (e == hipSuccess && st.rs_after(t)) e = ffh::launch_random_search(a, s);
   }
   return from_hip(e);
 }
@@ -509,7 +540,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
   if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
   if (params->radius != 3) return FF_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  const int L = params->levels, T = params->iters, nc = 1 << (L - 1);
+  const int L = params->levels, nc = 1 << (L - 1);
   ffh::BatchStage st{};
   st.pairs = static_cast<const ffh::BatchPair *>(table);
   st.npairs = npairs;
@@ -550,11 +581,14 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.ndir = 2;
     k.n = n;
     k.level = lv;
-    k.Rn = rs_radius(n, params->R_num, params->R_den);
+    const ScaleSteps sst = scale_steps(params, lv);
+    k.Rn = sst.Rn;
+    k.Rnp = sst.Rnp;
+    k.P = sst.P;
     k.seed = params->seed;
-    k.T = T;
+    k.T = sst.total();
     int runs[64][2];
-    const int m = level_runs(lv, T, 0, runs);
+    const int m = level_runs(lv, k.T, 0, runs);
     for (int r = 0; r < m; ++r) {
       // runs alternate between the two grid buffers; the last writes gflow/gcost
       st.dst = ((m - 1 - r) & 1) ? 1 : 0;

@@ -73,7 +73,8 @@ hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
 
 // Temporally blocked run of propagation / random-search steps of one scale
 // (patch radius 3).  Passes [t_begin, t_end) of T; a random-search step
-// follows pass t iff t < T - 1.  halo[] = half-sweeps reading the left,
+// follows pass t iff t is neither P - 1 nor T - 1, with radius Rnp for t < P
+// and Rn after (Flow Fields+ groups).  halo[] = half-sweeps reading the left,
 // right, top, bottom side over the run (at most kLevelHalo each).
 constexpr int kLevelHalo = 6;
 constexpr int kLevelContinue = 0;  // state from the level grid in global memory
@@ -96,8 +97,9 @@ struct LevelKArgs {
   LevelKDir dir[kMaxDirs];
   int ndir;
   int W, H, n, Wn, Hn, level, Rn;
+  int Rnp, P;  // the first P steps' random searches use Rnp (Flow Fields+); 0: none
   uint64_t seed;
-  int t_begin, t_end, T;
+  int t_begin, t_end, T;  // T: steps of the scale; no random search after steps P - 1 and T - 1
   int mode;
   int fcost;    // 0: byte descriptor maps; 1: padded float feature maps (64-byte entries)
   int tiles_x;  // set by launch_level

@@ -267,11 +267,14 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 
   int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
   auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
+  // a random search follows step t unless t ends its group (the R^+ steps
+  // of Flow Fields+ end at P - 1, the scale at T - 1)
+  auto rs_after = [&](int t) { return t != a.P - 1 && t != a.T - 1; };
   // random-search candidate of cell (i, j) at step t from its current state
   [[maybe_unused]] auto rs_candidate = [&](int i, int j, int l, int t, int32_t &fc) {
     if (s_cost[l] == kUnset) return false;
     int ox, oy;
-    ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+    ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, t < a.P ? a.Rnp : a.Rn, ox, oy);
     const int32_t f0 = s_flow[l];
     const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
     const int tx = i * n + fx, ty = j * n + fy;
@@ -498,7 +501,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if constexpr (QUAD) {
           // after the second half-sweep of a step with a random search:
           // the cell is final, draw its candidate now
-          if (colour == 0 && t < a.T - 1) {
+          if (colour == 0 && rs_after(t)) {
             int32_t fc = 0;
             const bool act = live && rs_candidate(i, j, l, t, fc);
             if (act) {
@@ -512,7 +515,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
       }
       if constexpr (QUAD) {
-        if (colour == 0 && t < a.T - 1) {  // the other colour is final since the first half-sweep
+        if (colour == 0 && rs_after(t)) {  // the other colour is final since the first half-sweep
           for (int base = 0; base < hw * rh; base += kThreads) {
             int i, j;
             const bool live = cell_of(1, base + tid, i, j);
@@ -528,7 +531,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       }
       __syncthreads();
     }
-    if (QUAD && t < a.T - 1) {  // the candidates drawn in the second half-sweep, a quad each
+    if (QUAD && rs_after(t)) {  // the candidates drawn in the second half-sweep, a quad each
       const int qlen = (int)s_rlen;
       for (int base = 0; base < qlen; base += kQuads) {
         const int q = base + (tid >> 2);
@@ -544,7 +547,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       }
       __syncthreads();
       if (tid == 0) s_rlen = 0;  // next written after the next step's first half-sweep
-    } else if (t < a.T - 1) {  // random search over the whole valid window
+    } else if (rs_after(t)) {  // random search over the whole valid window
       const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
       const int rw = rr - rl, rh = rb - rt;
       for (int base = 0; base < rw * rh; base += kThreads) {
@@ -559,7 +562,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           c0 = s_cost[l];
           if (c0 != kUnset) {
             int ox, oy;
-            ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, a.Rn, ox, oy);
+            ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, t < a.P ? a.Rnp : a.Rn, ox, oy);
             const int32_t f0 = s_flow[l];
             fx = ffk::flow_x(f0) + ox;
             fy = ffk::flow_y(f0) + oy;

@@ -32,6 +32,9 @@ class FFParams(C.Structure):
         ("R_den", C.c_int32),
         ("eps", C.c_float),
         ("seed", C.c_uint64),
+        ("plus_iters", C.c_int32),
+        ("Rp_num", C.c_int32),
+        ("fine_iters", C.c_int32),
     ]
 
 

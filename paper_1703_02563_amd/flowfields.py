@@ -29,9 +29,13 @@ class Params:
     R_den: int = 1
     eps: float = 1.0
     seed: int = 12345
+    plus_iters: int = 0  # Flow Fields+: steps at R+ = Rp_num / R_den before the `iters` steps at R
+    Rp_num: int = 0
+    fine_iters: int = 0  # Flow Fields+ Fast: steps at R on the finest scale (0: as the other scales)
 
     def to_c(self) -> FFParams:
-        return FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed)
+        return FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
+                        self.plus_iters, self.Rp_num, self.fine_iters)
 
 
 def _stream():

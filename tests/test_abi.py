@@ -72,6 +72,13 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter(fake, fake, fake, None, 5, 5, 1.0, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_init_nn(fake, fake, fake, fake, 5, 5, 6, 3, fake, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+    # bad Flow Fields+ schedules
+    for kw in ({"plus_iters": -1}, {"plus_iters": 60, "iters": 6}, {"Rp_num": -2}, {"fine_iters": 65},
+               {"fine_iters": -1}, {"Rp_num": (1 << 20) + 1}):
+        q = ff.Params(**kw).to_c()
+        assert lib.ff_workspace_bytes(64, 64, C.byref(q)) == 0, kw
+        assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(q), fake, 1 << 30, fake, fake, fake, fake, fake, None,
+                                  None, None) == ffi.FF_ERR_ARG, kw
     # misaligned convolution input (16-byte loads of channel chunks)
     assert lib.ff_conv3x3_fwd(C.c_void_p(0x1008), 1, 4, 4, 32, 32, fake, None, 0, None, fake, None) == ffi.FF_ERR_ARG
 

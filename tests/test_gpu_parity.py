@@ -202,7 +202,8 @@ def test_consistency_bit_exact():
 
 def _compare_full(img1, img2, params: ff.Params):
     o = oracle.flow_fields(img1, img2, params.levels, params.iters, params.radius, params.R_num, params.R_den,
-                           params.eps, params.seed, nthreads=NT)
+                           params.eps, params.seed, nthreads=NT, plus_iters=params.plus_iters, Rp_num=params.Rp_num,
+                           fine_iters=params.fine_iters)
     g = ff.flow_fields(dev(img1), dev(img2), params)
     for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
         assert np.array_equal(host(g[k]), o[k]), k

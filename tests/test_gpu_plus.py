@@ -1,0 +1,124 @@
+"""Flow Fields+ (Sec. 3.3) and Flow Fields+ Fast (Sec. 3.4) schedules on
+every GPU path, bit for bit against the oracle, whose schedule is pinned
+against the composition of its pinned steps: P steps with random searches at
+R^+ first, then T at R, random searches only inside a group, the step index
+running on over both groups; Fast: only the given number of steps at R on the
+finest scale."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1703_02563_amd as ff
+from ffgen import CONFIG_PARAMS, batch_shapes, make_pair, random_images
+from paper_1703_02563_amd.batch import BatchFlowFields
+from test_gpu_parity import _compare_full, as_u32, dev, host
+from test_learned_oracle import feature_canvas, feature_pyramid
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+KEYS = ("flow_fwd", "flow_bwd", "cost_fwd", "cost_bwd", "keep_fwd", "keep_bwd", "n_evals")
+
+# (plus_iters, Rp_num, iters, fine_iters): the paper's 4 x R+ then 8 x R, its
+# Fast form, and short schedules with odd group ends
+SCHEDULES = [(4, 2, 8, 0), (4, 2, 8, 4), (1, 3, 2, 0), (3, 2, 1, 2), (2, 4, 3, 1)]
+
+
+def _params(config, sched, **kw):
+    c = CONFIG_PARAMS[config]
+    P, Rp, T, Tf = sched
+    return ff.Params(levels=c.levels, iters=T, R_num=c.R_num, R_den=c.R_den, eps=c.eps, seed=c.seed,
+                     plus_iters=P, Rp_num=Rp * c.R_num, fine_iters=Tf, **kw)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("config", [1, 2])
+def test_plus_schedules_bit_exact(config, sched):
+    p = make_pair(config)
+    print(f"plus schedule {sched} config {config}", flush=True)
+    _compare_full(p.img1, p.img2, _params(config, sched))
+
+
+@pytest.mark.parametrize("shape,L,R", [((1, 1), 1, (1, 1)), ((23, 1), 3, (1, 1)), ((31, 45), 3, (3, 2)),
+                                       ((66, 97), 4, (2, 1))])
+@pytest.mark.parametrize("sched", SCHEDULES[:3])
+def test_plus_small_shapes(shape, L, R, sched):
+    ia, ib = random_images(610 + L, *shape)
+    P, Rp, T, Tf = sched
+    _compare_full(ia, ib, ff.Params(levels=L, iters=T, R_num=R[0], R_den=R[1], plus_iters=P, Rp_num=Rp * R[0],
+                                    fine_iters=Tf))
+
+
+def test_plus_other_patch_radius():
+    """Radius other than 3: the per-step path (one launch per step)."""
+    ia, ib = random_images(710, 40, 56)
+    for r in (1, 2):
+        _compare_full(ia, ib, ff.Params(levels=2, iters=3, radius=r, plus_iters=2, Rp_num=2, fine_iters=2))
+
+
+def test_plus_every_level_variant():
+    """Each blocked variant and the step-wise schedule, with run lengths that
+    end inside and at the border of the R^+ group."""
+    p = make_pair(1)
+    prm = _params(1, SCHEDULES[0])
+    o = oracle.flow_fields(p.img1, p.img2, prm.levels, prm.iters, prm.radius, prm.R_num, prm.R_den, prm.eps,
+                           prm.seed, nthreads=NT, plus_iters=prm.plus_iters, Rp_num=prm.Rp_num)
+    sv, sp = ff.level_variants(), ff.level_passes(0)
+    try:
+        for passes in (0, 3):
+            ff.set_level_passes([passes] * 7, 0)
+            for v in range(int(ff.lib().ff_level_variant_count())):
+                ff.set_level_variants([v] * 7)
+                g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+                for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
+                    assert np.array_equal(host(g[k]), o[k]), (passes, v, k)
+                assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"]), (passes, v)
+                assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], (passes, v)
+    finally:
+        ff.set_level_variants(sv)
+        ff.set_level_passes(sp, 0)
+
+
+def test_plus_batch_equals_single_pair_path():
+    c = CONFIG_PARAMS[4]
+    prm = ff.Params(levels=c.levels, iters=8, plus_iters=4, Rp_num=2, fine_iters=4)
+    shapes = batch_shapes()[:5]
+    b = BatchFlowFields(shapes, prm)
+    imgs = []
+    for k, shp in enumerate(shapes):
+        p = make_pair(4, k, shape=shp)
+        i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+        imgs.append((p, i1, i2))
+        b.set_pair(k, i1, i2)
+    b.run()
+    torch.cuda.synchronize()
+    for k, (p, i1, i2) in enumerate(imgs):
+        g = ff.flow_fields(i1, i2, prm)
+        for key in KEYS:
+            assert torch.equal(b.out[k][key], g[key]), (k, key)
+    p, i1, i2 = imgs[0]
+    o = oracle.flow_fields(p.img1, p.img2, prm.levels, prm.iters, nthreads=NT, plus_iters=4, Rp_num=2, fine_iters=4)
+    assert np.array_equal(b.out[0]["flow_fwd"].cpu().numpy(), o["flow_fwd"])
+    assert tuple(int(v) for v in b.out[0]["n_evals"].cpu()) == o["n_evals"]
+
+
+@pytest.mark.parametrize("sched", [(4, 2, 8, 0), (2, 3, 3, 2)])
+def test_plus_learned_features_bit_exact(sched):
+    from paper_1703_02563_amd import learned as Lm
+    H, W, pad, L = 61, 95, 10, 3
+    canvas = feature_canvas(31, H + 2 * pad, W + 2 * pad)
+    F1 = canvas[pad:pad + H, pad:pad + W].copy()
+    F2 = canvas[pad - 2:pad - 2 + H, pad + 3:pad + 3 + W].copy() + feature_canvas(32, H, W) * 0.05
+    m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
+    P, Rp, T, Tf = sched
+    prm = ff.Params(levels=L, iters=T, plus_iters=P, Rp_num=Rp, fine_iters=Tf)
+    o = oracle.flow_fields_f32(m1, m2, L, T, nthreads=NT, plus_iters=P, Rp_num=Rp, fine_iters=Tf)
+    g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2], prm)
+    torch.cuda.synchronize()
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(g[k].cpu().numpy(), o[k]), k
+    for k in ("cost_fwd", "cost_bwd"):
+        assert np.array_equal(g[k].cpu().numpy().view(np.uint32), o[k]), k
+    assert tuple(int(v) for v in g["n_evals"].cpu()) == o["n_evals"]
