@@ -53,8 +53,8 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10567.5 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "a6b29771d6326323"
+TRAFFIC_BYTES = 10568.0 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "b458bbf36e3bcd21"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
@@ -153,6 +153,38 @@ def batched_throughput(ff, torch, reps):
     mpix = sum(h * w for h, w in shapes) / 1e6
     return {"pairs": len(shapes), "mpix": round(mpix, 3), "ms_per_batch": round(dt * 1e3, 3),
             "mpix_per_s": round(mpix / dt, 2), "graph": True}
+
+
+def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
+    """Flow Fields+ (Sec. 3.3: 4 steps at R+ = 2R, then 8 at R on every scale)
+    and Flow Fields+ Fast (Sec. 3.4: only 4 steps at R on the finest scale) on
+    the same pair and launch tables: Mpix/s and quality."""
+    import dataclasses
+
+    from ffgen import epe_stats
+    res = {}
+    for name, kw in (("plus", dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num)),
+                     ("plus_fast", dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num, fine_iters=4))):
+        prm = dataclasses.replace(params, **kw)
+        H, W = img1.shape
+        runner = ff.FlowFields(W, H, prm, device=img1.device)
+        for _ in range(3):
+            runner(img1, img2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            runner(img1, img2)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        out = runner.out
+        q = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=out["keep_fwd"].cpu().numpy())
+        res[name] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
+                     "steps": f"{prm.plus_iters} x R+ then {prm.iters} x R"
+                              + (f", finest {prm.fine_iters} x R" if prm.fine_iters else ""),
+                     "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
+                     "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
+                     "kept_epe": round(q["kept_epe"], 4)}
+    return res
 
 
 def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
@@ -297,6 +329,10 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {nbytes} bytes")
 
+    log("bench: Flow Fields+ schedules")
+    schedules = schedule_leg(ff, torch, img1, img2, params, pair)
+    log(f"bench: schedules {schedules}")
+
     batched = None
     if not args.no_batch:
         log("bench: batched 64-pair workload (graph replay)")
@@ -328,7 +364,8 @@ def main():
                    "W": W, "H": H, "levels": c.levels, "iters": c.iters, "R": f"{c.R_num}/{c.R_den}",
                    "n_evals": n_evals, "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                    "epe10": round(q["epe10"], 4), "kept_density": round(q["kept_density"], 4),
-                   "kept_epe": round(q["kept_epe"], 4), "batched": batched, "learned": learned},
+                   "kept_epe": round(q["kept_epe"], 4), "schedules": schedules, "batched": batched,
+                   "learned": learned},
         "roofline": roof,
         "cpu_baseline": base,
     }
