@@ -52,6 +52,7 @@ def lib():
         L.or_rs_radius.argtypes = [i, i, i]
         L.or_rs_radius.restype = i
         L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
+        L.or_consistency2.argtypes = [P, P, P, P, P, P, i, i, dbl, P]
         L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
@@ -173,6 +174,15 @@ def consistency(fa, ca, fb, cb, eps: float = 1.0):
     keep = np.empty((H, W), np.uint8)
     args = [np.ascontiguousarray(a) for a in (fa, ca, fb, cb)]
     lib().or_consistency(*[_p(a) for a in args], W, H, float(eps), _p(keep))
+    return keep
+
+
+def consistency2(fa, ca, fb1, cb1, fb2, cb2, eps: float = 1.0):
+    """Keep mask of field a against two backward fields (Sec. 3.7)."""
+    H, W = ca.shape
+    keep = np.empty((H, W), np.uint8)
+    args = [np.ascontiguousarray(a) for a in (fa, ca, fb1, cb1, fb2, cb2)]
+    lib().or_consistency2(*[_p(a) for a in args], W, H, float(eps), _p(keep))
     return keep
 
 

@@ -39,7 +39,8 @@
  *               mix(seed ^ mix(counter)), mapped to a range by Lemire's
  *               multiply-shift (ACM TOMACS 2019).
  *   consistency forward-backward check (Sec. 3.7): keep p iff
- *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14).
+ *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14);
+ *               consistency2 the same against two backward fields.
  *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
  *               random-search steps between them, forward and backward;
@@ -411,6 +412,35 @@ void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, co
             if (cb[kq] == OR_UNSET) continue;
             int64_t dx = fa[2 * k] + fb[2 * kq], dy = fa[2 * k + 1] + fb[2 * kq + 1];
             keep[k] = (double)(dx * dx + dy * dy) < eps * eps;
+        }
+}
+
+/* Consistency against two backward fields (Sec. 3.7): keep pixel p of
+ * field a iff it passes the check of or_consistency against field b1 and
+ * against field b2 (fields with different generator seeds and possibly
+ * different patch radii); deleted if it fails either. */
+void or_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,
+                     const int16_t *fb2, const uint32_t *cb2, int W, int H, double eps, uint8_t *keep)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t k = (size_t)y * W + x;
+            keep[k] = 0;
+            if (ca[k] == OR_UNSET) continue;
+            int qx = x + fa[2 * k], qy = y + fa[2 * k + 1];
+            size_t kq = (size_t)qy * W + qx;
+            int ok = 1;
+            const int16_t *fb[2] = {fb1, fb2};
+            const uint32_t *cb[2] = {cb1, cb2};
+            for (int j = 0; j < 2 && ok; ++j) {
+                if (cb[j][kq] == OR_UNSET) {
+                    ok = 0;
+                    break;
+                }
+                int64_t dx = fa[2 * k] + fb[j][2 * kq], dy = fa[2 * k + 1] + fb[j][2 * kq + 1];
+                ok = (double)(dx * dx + dy * dy) < eps * eps;
+            }
+            keep[k] = (uint8_t)ok;
         }
 }
 

@@ -537,3 +537,50 @@ def test_flow_fields_plus_rejects_bad_schedules():
     for kw in ({"plus_iters": -1}, {"fine_iters": -2}, {"plus_iters": 60, "Rp_num": 2}, {"Rp_num": -1}):
         with pytest.raises(ValueError):
             oracle.flow_fields(img, img, 2, 8, **kw)
+
+
+# ---------------------------------------------------------------- two backward fields (Sec. 3.7)
+
+def test_consistency2_closed_form():
+    """Constructed fields: a pixel consistent with only one backward field is
+    deleted; UNSET targets in either field delete; both consistent keeps."""
+    H, W = 3, 4
+    fa = np.zeros((H, W, 2), np.int16)
+    ca = np.zeros((H, W), np.uint32)
+    fa[0, 0] = (1, 0)   # -> (1, 0): b1 returns (-1, 0), b2 returns (-1, 1): |(0, 1)| = 1, not < 1
+    fa[1, 1] = (2, 1)   # -> (3, 2): both return (-2, -1)
+    fa[2, 0] = (0, -2)  # -> (0, 0): b2 UNSET there
+    ca[0, 1] = oracle.UNSET
+    fb1 = np.zeros((H, W, 2), np.int16)
+    fb2 = np.zeros((H, W, 2), np.int16)
+    cb1 = np.zeros((H, W), np.uint32)
+    cb2 = np.zeros((H, W), np.uint32)
+    fb1[0, 1] = (-1, 0)
+    fb2[0, 1] = (-1, 1)
+    fb1[2, 3] = fb2[2, 3] = (-2, -1)
+    fb1[0, 0] = (0, 2)
+    cb2[0, 0] = oracle.UNSET
+    keep = oracle.consistency2(fa, ca, fb1, cb1, fb2, cb2, 1.0)
+    assert keep[1, 1] == 1  # consistent with both
+    assert keep[0, 0] == 0  # consistent with b1 only (residual (0, 1) against b2)
+    assert keep[2, 0] == 0  # its target (0, 0) is UNSET in b2
+    assert keep[0, 1] == 0  # UNSET in a
+    assert keep[1, 0] == 1 and keep[2, 2] == 1  # zero flows meeting zero flows
+    assert keep[2, 3] == 0  # zero flow meeting (-2, -1) in both
+    keep15 = oracle.consistency2(fa, ca, fb1, cb1, fb2, cb2, 1.5)
+    assert keep15[0, 0] == 1  # |(0, 1)| < 1.5
+
+
+@pytest.mark.parametrize("eps", [0.5, 1.0, 2.5])
+def test_consistency2_is_both_single_checks(eps):
+    """Deleted iff inconsistent with one of the two backward fields: the
+    mask equals the AND of the two single checks (each pinned above)."""
+    p = make_pair(1)
+    o1 = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4)
+    o2 = oracle.flow_fields(p.img2, p.img1, 3, 4, radius=2, seed=999, nthreads=4)
+    k = oracle.consistency2(o1["flow_fwd"], o1["cost_fwd"], o1["flow_bwd"], o1["cost_bwd"], o2["flow_fwd"],
+                            o2["cost_fwd"], eps)
+    k1 = oracle.consistency(o1["flow_fwd"], o1["cost_fwd"], o1["flow_bwd"], o1["cost_bwd"], eps)
+    k2 = oracle.consistency(o1["flow_fwd"], o1["cost_fwd"], o2["flow_fwd"], o2["cost_fwd"], eps)
+    assert np.array_equal(k, k1 & k2)
+    assert k.sum() < k1.sum()  # the second field deletes some pixels the first check kept
