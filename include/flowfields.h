@@ -163,6 +163,16 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                 const uint32_t *cost_b, int32_t W, int32_t H, float eps, uint8_t *keep_a,
                                 uint8_t *keep_b, void *stream);
 
+/* Consistency against two backward fields (Sec. 3.7): keep_a[p] = 1 iff p
+ * passes the ff_consistency_filter test against field b1 and against field
+ * b2 (backward fields made with different generator seeds, and possibly
+ * different patch radii: for instance the forward field of a second
+ * ff_flow_fields call on the swapped images).  Same layouts and errors as
+ * ff_consistency_filter. */
+ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b1,
+                                 const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
+                                 int32_t H, float eps, uint8_t *keep_a, void *stream);
+
 /* All steps of one scale (Sec. 3.2): T propagation steps with T-1
  * random-search steps between them (RS stream `stream_id`, level index
  * `level`, n = 2^level), starting from

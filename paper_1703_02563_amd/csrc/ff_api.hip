@@ -361,6 +361,16 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                           (hipStream_t)stream));
 }
 
+ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b1,
+                                 const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
+                                 int32_t H, float eps, uint8_t *keep_a, void *stream) {
+  if (!flow_a || !cost_a || !flow_b1 || !cost_b1 || !flow_b2 || !cost_b2 || !keep_a || !dims_ok(W, H) ||
+      !(eps >= 0.0f))
+    return FF_ERR_ARG;
+  return from_hip(ffh::launch_consistency2(flow_a, cost_a, flow_b1, cost_b1, flow_b2, cost_b2, W, H, eps, keep_a,
+                                           (hipStream_t)stream));
+}
+
 size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level) {
   if (!dims_ok(W, H) || level < 0 || level >= kMaxLevels) return 0;
   return (size_t)ceil_div(W, 1 << level) * ceil_div(H, 1 << level) * 2 * sizeof(uint32_t);

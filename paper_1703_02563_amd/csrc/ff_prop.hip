@@ -11,7 +11,8 @@
 //    horizontal source, vertical source; strictly lower cost wins.
 //  * k_random_search: one random-search step (Sec. 3.1) with integer
 //    offsets from the counter-based generator.
-//  * k_consistency: forward-backward check (Sec. 3.7).
+//  * k_consistency: forward-backward check (Sec. 3.7); k_consistency2 the
+//    same against two backward fields.
 //
 // One lane per cell; both directions of a pair run in one launch
 // (blockIdx.z).  Each kernel counts the patch-cost evaluations it performs
@@ -212,6 +213,29 @@ __global__ __launch_bounds__(256) void k_consistency(const int32_t *fa, const ui
   keep[k] = out;
 }
 
+// Against two backward fields (Sec. 3.7): kept iff the check above passes
+// for both (their generator seeds, and possibly patch radii, differ).
+__global__ __launch_bounds__(256) void k_consistency2(const int32_t *fa, const uint32_t *ca, const int32_t *fb1,
+                                                      const uint32_t *cb1, const int32_t *fb2, const uint32_t *cb2,
+                                                      int W, int H, double eps2, uint8_t *keep) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const size_t k = (size_t)y * W + x;
+  uint8_t out = 0;
+  if (ca[k] != kUnset) {
+    const int32_t f = fa[k];
+    const int qx = x + ffk::flow_x(f), qy = y + ffk::flow_y(f);
+    const size_t kq = (size_t)qy * W + qx;
+    if (qx >= 0 && qx < W && qy >= 0 && qy < H && cb1[kq] != kUnset && cb2[kq] != kUnset) {
+      const int32_t g1 = fb1[kq], g2 = fb2[kq];
+      const int64_t dx1 = ffk::flow_x(f) + ffk::flow_x(g1), dy1 = ffk::flow_y(f) + ffk::flow_y(g1);
+      const int64_t dx2 = ffk::flow_x(f) + ffk::flow_x(g2), dy2 = ffk::flow_y(f) + ffk::flow_y(g2);
+      out = (double)(dx1 * dx1 + dy1 * dy1) < eps2 && (double)(dx2 * dx2 + dy2 * dy2) < eps2;
+    }
+  }
+  keep[k] = out;
+}
+
 // Batches: items = (pair, direction, row); direction 1 writes the backward
 // mask when the pair has one.
 __global__ __launch_bounds__(256) void k_consistency_batch(ffh::BatchStage st, double eps2) {
@@ -306,6 +330,17 @@ hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream
   if (rows.total <= 0) return hipSuccess;
   const dim3 grid(((std::min(rows.total, 4096) + 7) / 8) * 8);
   hipLaunchKernelGGL(k_consistency_batch, grid, dim3(256), 0, stream, rows, (double)eps * (double)eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,
+                               const int16_t *fb2, const uint32_t *cb2, int W, int H, float eps, uint8_t *keep,
+                               hipStream_t stream) {
+  dim3 grid((W + 255) / 256, H);
+  const double eps2 = (double)eps * (double)eps;
+  hipLaunchKernelGGL(k_consistency2, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
+                     reinterpret_cast<const int32_t *>(fb1), cb1, reinterpret_cast<const int32_t *>(fb2), cb2, W, H,
+                     eps2, keep);
   return hipGetLastError();
 }
 

@@ -161,6 +161,37 @@ def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: b
     return keep_a, keep_b
 
 
+def consistency_filter2(flow_a, cost_a, flow_b1, cost_b1, flow_b2, cost_b2, eps: float = 1.0):
+    """Keep mask of field a against two backward fields (Sec. 3.7)."""
+    H, W = cost_a.shape
+    for t in (cost_b1, cost_b2):
+        if tuple(t.shape) != (H, W):
+            raise ValueError("consistency_filter2: the three fields must have the same size")
+    keep = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device)
+    check(lib().ff_consistency_filter2(_ptr(flow_a, torch.int16), _ptr(cost_a, torch.int32),
+                                       _ptr(flow_b1, torch.int16), _ptr(cost_b1, torch.int32),
+                                       _ptr(flow_b2, torch.int16), _ptr(cost_b2, torch.int32), W, H, eps, _ptr(keep),
+                                       _stream()), "ff_consistency_filter2")
+    return keep
+
+
+def flow_fields_two_backward(img1, img2, params: Params, seed2: int | None = None, radius2: int | None = None):
+    """Flow Fields with the check against two backward fields (Sec. 3.7).
+    The second backward field is the forward field of a second run on the
+    swapped images with generator seed `seed2` (default seed + 1) and patch
+    radius `radius2` (default the same radius); keep_fwd becomes the mask
+    against both backward fields (keep_bwd stays the single check of the
+    first backward field).  Adds flow_bwd2 and cost_bwd2 to the result."""
+    out = flow_fields(img1, img2, params)
+    p2 = dataclasses.replace(params, seed=params.seed + 1 if seed2 is None else seed2,
+                             radius=params.radius if radius2 is None else radius2)
+    o2 = flow_fields(img2, img1, p2)
+    out["keep_fwd"] = consistency_filter2(out["flow_fwd"], out["cost_fwd"], out["flow_bwd"], out["cost_bwd"],
+                                          o2["flow_fwd"], o2["cost_fwd"], params.eps)
+    out["flow_bwd2"], out["cost_bwd2"] = o2["flow_fwd"], o2["cost_fwd"]
+    return out
+
+
 def level_variants() -> list:
     """Current level-kernel variant per scale (index log2 n)."""
     return [int(lib().ff_get_level_variant(k)) for k in range(7)]

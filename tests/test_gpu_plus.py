@@ -3,7 +3,7 @@ every GPU path, bit for bit against the oracle, whose schedule is pinned
 against the composition of its pinned steps: P steps with random searches at
 R^+ first, then T at R, random searches only inside a group, the step index
 running on over both groups; Fast: only the given number of steps at R on the
-finest scale."""
+finest scale.  Also the check against two backward fields (Sec. 3.7)."""
 import os
 
 import numpy as np
@@ -122,3 +122,23 @@ def test_plus_learned_features_bit_exact(sched):
     for k in ("cost_fwd", "cost_bwd"):
         assert np.array_equal(g[k].cpu().numpy().view(np.uint32), o[k]), k
     assert tuple(int(v) for v in g["n_evals"].cpu()) == o["n_evals"]
+
+
+@pytest.mark.parametrize("config,radius2", [(1, 2), (1, 3), (2, 2)])
+def test_two_backward_check_bit_exact(config, radius2):
+    """flow_fields_two_backward = oracle fields of both runs (the second on
+    the swapped images with seed 999 and patch radius radius2) and the
+    oracle's mask against both backward fields."""
+    p = make_pair(config)
+    c = CONFIG_PARAMS[config]
+    prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den, eps=c.eps, seed=c.seed)
+    g = ff.flow_fields_two_backward(dev(p.img1), dev(p.img2), prm, seed2=999, radius2=radius2)
+    o1 = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, 3, c.R_num, c.R_den, c.eps, c.seed, nthreads=NT)
+    o2 = oracle.flow_fields(p.img2, p.img1, c.levels, c.iters, radius2, c.R_num, c.R_den, c.eps, 999, nthreads=NT)
+    keep = oracle.consistency2(o1["flow_fwd"], o1["cost_fwd"], o1["flow_bwd"], o1["cost_bwd"], o2["flow_fwd"],
+                               o2["cost_fwd"], c.eps)
+    assert np.array_equal(host(g["flow_bwd2"]), o2["flow_fwd"])
+    assert np.array_equal(as_u32(g["cost_bwd2"]), o2["cost_fwd"])
+    assert np.array_equal(host(g["keep_fwd"]), keep)
+    assert np.array_equal(host(g["keep_bwd"]), o1["keep_bwd"])
+    assert host(g["keep_fwd"]).sum() <= o1["keep_fwd"].sum()
