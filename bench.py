@@ -156,8 +156,9 @@ def batched_throughput(ff, torch, reps):
 
 
 def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
-    """Flow Fields+ (Sec. 3.3: 4 steps at R+ = 2R, then 8 at R on every scale)
-    and Flow Fields+ Fast (Sec. 3.4: only 4 steps at R on the finest scale) on
+    """Flow Fields+ (Sec. 3.3: 4 steps at R+ = 2R, then 8 at R on every scale),
+    Flow Fields+ Fast (Sec. 3.4: only 4 steps at R on the finest scale) and
+    the original schedule checked against two backward fields (Sec. 3.7) on
     the same pair and launch tables: Mpix/s and quality."""
     import dataclasses
 
@@ -184,6 +185,22 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
                      "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
                      "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
                      "kept_epe": round(q["kept_epe"], 4)}
+    # the original schedule with the check against two backward fields (Sec. 3.7; second field: seed + 1,
+    # patch radius 2)
+    run2 = lambda: ff.flow_fields_two_backward(img1, img2, params, radius2=2)  # noqa: E731
+    for _ in range(3):
+        run2()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = run2()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    q = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=out["keep_fwd"].cpu().numpy())
+    H, W = img1.shape
+    res["two_backward"] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
+                           "second_backward": "seed + 1, patch radius 2", "kept_density": round(q["kept_density"], 4),
+                           "kept_epe": round(q["kept_epe"], 4)}
     return res
 
 
