@@ -53,6 +53,7 @@ def lib():
         L.or_rs_radius.restype = i
         L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
         L.or_consistency2.argtypes = [P, P, P, P, P, P, i, i, dbl, P]
+        L.or_sparsify.argtypes = [P, P, P, P, i, i, i, i, P]
         L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
@@ -184,6 +185,18 @@ def consistency2(fa, ca, fb1, cb1, fb2, cb2, eps: float = 1.0):
     args = [np.ascontiguousarray(a) for a in (fa, ca, fb1, cb1, fb2, cb2)]
     lib().or_consistency2(*[_p(a) for a in args], W, H, float(eps), _p(keep))
     return keep
+
+
+def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:
+    """Selected pixel index (y * W + x, or -1) of every q x q region (Sec. 3.8)."""
+    H, W = keep.shape
+    sel = np.empty((-(-H // q), -(-W // q)), np.int32)
+    fa = np.ascontiguousarray(fa, np.int16)
+    keep = np.ascontiguousarray(keep, np.uint8)
+    fb1 = np.ascontiguousarray(fb1, np.int16)
+    fb2 = None if fb2 is None else np.ascontiguousarray(fb2, np.int16)
+    lib().or_sparsify(_p(fa), _p(keep), _p(fb1), None if fb2 is None else _p(fb2), W, H, q, e, _p(sel))
+    return sel
 
 
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,

@@ -41,6 +41,7 @@
  *   consistency forward-backward check (Sec. 3.7): keep p iff
  *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14);
  *               consistency2 the same against two backward fields.
+ *   sparsify    one sample per q x q region (Sec. 3.8).
  *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
  *               random-search steps between them, forward and backward;
@@ -441,6 +442,45 @@ void or_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, 
                 ok = (double)(dx * dx + dy * dy) < eps * eps;
             }
             keep[k] = (uint8_t)ok;
+        }
+}
+
+/* Sparsification (Sec. 3.8): in every q x q region of the filtered field a
+ * (regions anchored at (0, 0), ragged at the right and bottom) that still
+ * holds at least e kept samples, select the kept sample whose consistency
+ * errors |F_a(p) + F_b1(p + F_a(p))| (+ the same against b2 when b2 is
+ * given) sum to the least, in double precision; ties go to the smallest
+ * row-major pixel index.  sel[region] = y * W + x of the selection, or -1.
+ * A kept sample whose target leaves the image is not a candidate. */
+void or_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t *fb1, const int16_t *fb2, int W, int H,
+                 int q, int e, int32_t *sel)
+{
+    int Wq = (W + q - 1) / q, Hq = (H + q - 1) / q;
+    for (int ry = 0; ry < Hq; ++ry)
+        for (int rx = 0; rx < Wq; ++rx) {
+            int count = 0;
+            int32_t best = -1;
+            double best_err = 0.0;
+            for (int y = ry * q; y < ry * q + q && y < H; ++y)
+                for (int x = rx * q; x < rx * q + q && x < W; ++x) {
+                    size_t k = (size_t)y * W + x;
+                    if (!keep[k]) continue;
+                    ++count;
+                    int tx = x + fa[2 * k], ty = y + fa[2 * k + 1];
+                    if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
+                    size_t kt = (size_t)ty * W + tx;
+                    double dx = fa[2 * k] + fb1[2 * kt], dy = fa[2 * k + 1] + fb1[2 * kt + 1];
+                    double err = sqrt(dx * dx + dy * dy);
+                    if (fb2) {
+                        double ex = fa[2 * k] + fb2[2 * kt], ey = fa[2 * k + 1] + fb2[2 * kt + 1];
+                        err += sqrt(ex * ex + ey * ey);
+                    }
+                    if (best < 0 || err < best_err) {  /* row-major scan: ties keep the earlier */
+                        best = (int32_t)k;
+                        best_err = err;
+                    }
+                }
+            sel[(size_t)ry * Wq + rx] = count >= e ? best : -1;
         }
 }
 

@@ -584,3 +584,77 @@ def test_consistency2_is_both_single_checks(eps):
     k2 = oracle.consistency(o1["flow_fwd"], o1["cost_fwd"], o2["flow_fwd"], o2["cost_fwd"], eps)
     assert np.array_equal(k, k1 & k2)
     assert k.sum() < k1.sum()  # the second field deletes some pixels the first check kept
+
+
+# ---------------------------------------------------------------- q x q sparsification (Sec. 3.8)
+
+def _sparsify_numpy(fa, keep, fb1, fb2, q, e):
+    """Brute force restated with NumPy: per region, the kept in-image
+    candidates ordered by (summed error, pixel index)."""
+    H, W = keep.shape
+    ys, xs = np.mgrid[0:H, 0:W]
+    tx, ty = xs + fa[..., 0], ys + fa[..., 1]
+    inside = (tx >= 0) & (tx < W) & (ty >= 0) & (ty < H)
+    txc, tyc = np.clip(tx, 0, W - 1), np.clip(ty, 0, H - 1)
+    err = np.zeros((H, W))
+    for fb in [fb1] + ([fb2] if fb2 is not None else []):
+        d = fa.astype(np.float64) + fb[tyc, txc].astype(np.float64)
+        err = err + np.sqrt(d[..., 0] ** 2 + d[..., 1] ** 2)
+    out = np.full((-(-H // q), -(-W // q)), -1, np.int32)
+    for ry in range(out.shape[0]):
+        for rx in range(out.shape[1]):
+            sl = (slice(ry * q, ry * q + q), slice(rx * q, rx * q + q))
+            k, cand = keep[sl].astype(bool), keep[sl].astype(bool) & inside[sl]
+            if k.sum() < e or not cand.any():
+                continue
+            idx = (ys[sl] * W + xs[sl])[cand]
+            order = np.lexsort((idx, err[sl][cand]))
+            out[ry, rx] = idx[order[0]]
+    return out
+
+
+@pytest.mark.parametrize("q,e,two", [(3, 1, True), (3, 4, True), (4, 2, False), (2, 1, True), (5, 7, False)])
+def test_sparsify_equals_numpy_brute_force(q, e, two):
+    rng = np.random.default_rng(q * 10 + e)
+    H, W = 23, 31
+    fa = rng.integers(-3, 4, size=(H, W, 2)).astype(np.int16)
+    fb1 = rng.integers(-3, 4, size=(H, W, 2)).astype(np.int16)
+    fb2 = rng.integers(-3, 4, size=(H, W, 2)).astype(np.int16) if two else None
+    keep = (rng.random((H, W)) < 0.6).astype(np.uint8)
+    got = oracle.sparsify(fa, keep, fb1, fb2, q, e)
+    assert np.array_equal(got, _sparsify_numpy(fa, keep, fb1, fb2, q, e))
+
+
+def test_sparsify_hand_worked_region():
+    """One 3x3 region: three kept samples with errors 1, sqrt(2), 1 against a
+    single backward field: the earlier of the two at error 1 wins; with
+    e = 4 the region is dropped; nothing kept gives -1."""
+    fa = np.zeros((3, 3, 2), np.int16)
+    fb = np.zeros((3, 3, 2), np.int16)
+    keep = np.zeros((3, 3), np.uint8)
+    keep[0, 2] = keep[1, 1] = keep[2, 0] = 1
+    fb[0, 2] = (1, 0)   # error 1 at index 2
+    fb[1, 1] = (1, 1)   # error sqrt(2) at index 4
+    fb[2, 0] = (0, -1)  # error 1 at index 6
+    assert oracle.sparsify(fa, keep, fb, None, 3, 1)[0, 0] == 2
+    assert oracle.sparsify(fa, keep, fb, None, 3, 3)[0, 0] == 2
+    assert oracle.sparsify(fa, keep, fb, None, 3, 4)[0, 0] == -1
+    assert oracle.sparsify(fa, np.zeros_like(keep), fb, None, 3, 0)[0, 0] == -1
+    fb2 = np.zeros_like(fb)
+    fb2[0, 2] = (2, 0)  # index 2 now sums 3, index 6 sums 1 + 0
+    assert oracle.sparsify(fa, keep, fb, fb2, 3, 1)[0, 0] == 6
+
+
+def test_sparsify_on_a_field_selects_kept_samples_of_least_error():
+    p = make_pair(1)
+    o = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4)
+    H, W = p.img1.shape
+    sel = oracle.sparsify(o["flow_fwd"], o["keep_fwd"], o["flow_bwd"], None, 3, 2)
+    assert (sel >= 0).sum() > 0.5 * sel.size
+    for ry, rx in zip(*np.nonzero(sel >= 0)):
+        k = int(sel[ry, rx])
+        y, x = divmod(k, W)
+        assert y // 3 == ry and x // 3 == rx and o["keep_fwd"][y, x] == 1
+        # kept samples passed the check: |F + F_b|^2 < 1, so the error is 0 (integer flows)
+        f = o["flow_fwd"][y, x].astype(int)
+        assert np.all(f + o["flow_bwd"][y + f[1], x + f[0]] == 0)
