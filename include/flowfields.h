@@ -173,6 +173,17 @@ ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, 
                                  const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
                                  int32_t H, float eps, uint8_t *keep_a, void *stream);
 
+/* Sparsification (Sec. 3.8): for every q x q region of the filtered field
+ * a (regions anchored at (0, 0), ragged at the right and bottom; sel is
+ * int32 [ceil(H/q)][ceil(W/q)]), sel = y * W + x of the kept sample
+ * (keep_a != 0) whose consistency errors |F_a(p) + F_b1(p + F_a(p))| (+ the
+ * same against flow_b2, nullable) sum to the least in double precision, ties
+ * to the smallest pixel index; -1 if the region holds fewer than e kept
+ * samples or none whose target lies in the image.  q in [1, 64], e >= 0
+ * (FF_ERR_ARG otherwise). */
+ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_t *flow_b1, const int16_t *flow_b2,
+                      int32_t W, int32_t H, int32_t q, int32_t e, int32_t *sel, void *stream);
+
 /* All steps of one scale (Sec. 3.2): T propagation steps with T-1
  * random-search steps between them (RS stream `stream_id`, level index
  * `level`, n = 2^level), starting from

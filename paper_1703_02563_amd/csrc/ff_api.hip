@@ -371,6 +371,12 @@ ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, 
                                            (hipStream_t)stream));
 }
 
+ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_t *flow_b1, const int16_t *flow_b2,
+                      int32_t W, int32_t H, int32_t q, int32_t e, int32_t *sel, void *stream) {
+  if (!flow_a || !keep_a || !flow_b1 || !sel || !dims_ok(W, H) || q < 1 || q > 64 || e < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_sparsify(flow_a, keep_a, flow_b1, flow_b2, W, H, q, e, sel, (hipStream_t)stream));
+}
+
 size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level) {
   if (!dims_ok(W, H) || level < 0 || level >= kMaxLevels) return 0;
   return (size_t)ceil_div(W, 1 << level) * ceil_div(H, 1 << level) * 2 * sizeof(uint32_t);

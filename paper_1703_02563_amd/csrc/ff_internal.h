@@ -221,6 +221,8 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, 
 hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream);
 
 // Consistency of field a against field b (full resolution).
+hipError_t launch_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t *fb1, const int16_t *fb2, int W,
+                           int H, int q, int e, int32_t *sel, hipStream_t stream);
 hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,
                                const int16_t *fb2, const uint32_t *cb2, int W, int H, float eps, uint8_t *keep,
                                hipStream_t stream);

@@ -12,7 +12,8 @@
 //  * k_random_search: one random-search step (Sec. 3.1) with integer
 //    offsets from the counter-based generator.
 //  * k_consistency: forward-backward check (Sec. 3.7); k_consistency2 the
-//    same against two backward fields.
+//    same against two backward fields; k_sparsify: one sample per q x q
+//    region (Sec. 3.8).
 //
 // One lane per cell; both directions of a pair run in one launch
 // (blockIdx.z).  Each kernel counts the patch-cost evaluations it performs
@@ -236,6 +237,43 @@ __global__ __launch_bounds__(256) void k_consistency2(const int32_t *fa, const u
   keep[k] = out;
 }
 
+// Sparsification (Sec. 3.8): one lane per q x q region; among the region's
+// kept samples whose target lies in the image, the least summed consistency
+// error |F_a + F_b1| (+ |F_a + F_b2|) in double precision, ties to the
+// smallest pixel index (row-major scan, strict <); -1 if fewer than e kept.
+__global__ __launch_bounds__(256) void k_sparsify(const int32_t *fa, const uint8_t *keep, const int32_t *fb1,
+                                                  const int32_t *fb2, int W, int H, int q, int e, int32_t *sel) {
+  const int Wq = (W + q - 1) / q, Hq = (H + q - 1) / q;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (long long)Wq * Hq) return;
+  const int rx = (int)(r % Wq), ry = (int)(r / Wq);
+  int count = 0, best = -1;
+  double best_err = 0.0;
+  for (int y = ry * q; y < min(ry * q + q, H); ++y)
+    for (int x = rx * q; x < min(rx * q + q, W); ++x) {
+      const size_t k = (size_t)y * W + x;
+      if (!keep[k]) continue;
+      ++count;
+      const int32_t f = fa[k];
+      const int tx = x + ffk::flow_x(f), ty = y + ffk::flow_y(f);
+      if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
+      const size_t kt = (size_t)ty * W + tx;
+      const int32_t g1 = fb1[kt];
+      const double dx = ffk::flow_x(f) + ffk::flow_x(g1), dy = ffk::flow_y(f) + ffk::flow_y(g1);
+      double err = sqrt(dx * dx + dy * dy);
+      if (fb2) {
+        const int32_t g2 = fb2[kt];
+        const double ex = ffk::flow_x(f) + ffk::flow_x(g2), ey = ffk::flow_y(f) + ffk::flow_y(g2);
+        err += sqrt(ex * ex + ey * ey);
+      }
+      if (best < 0 || err < best_err) {
+        best = (int)k;
+        best_err = err;
+      }
+    }
+  sel[r] = count >= e ? best : -1;
+}
+
 // Batches: items = (pair, direction, row); direction 1 writes the backward
 // mask when the pair has one.
 __global__ __launch_bounds__(256) void k_consistency_batch(ffh::BatchStage st, double eps2) {
@@ -330,6 +368,15 @@ hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream
   if (rows.total <= 0) return hipSuccess;
   const dim3 grid(((std::min(rows.total, 4096) + 7) / 8) * 8);
   hipLaunchKernelGGL(k_consistency_batch, grid, dim3(256), 0, stream, rows, (double)eps * (double)eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t *fb1, const int16_t *fb2, int W,
+                           int H, int q, int e, int32_t *sel, hipStream_t stream) {
+  const long long regions = (long long)((W + q - 1) / q) * ((H + q - 1) / q);
+  hipLaunchKernelGGL(k_sparsify, dim3((unsigned)((regions + 255) / 256)), dim3(256), 0, stream,
+                     reinterpret_cast<const int32_t *>(fa), keep, reinterpret_cast<const int32_t *>(fb1),
+                     reinterpret_cast<const int32_t *>(fb2), W, H, q, e, sel);
   return hipGetLastError();
 }
 

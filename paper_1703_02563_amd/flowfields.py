@@ -175,6 +175,16 @@ def consistency_filter2(flow_a, cost_a, flow_b1, cost_b1, flow_b2, cost_b2, eps:
     return keep
 
 
+def sparsify(flow_a, keep_a, flow_b1, flow_b2=None, q: int = 3, e: int = 1) -> torch.Tensor:
+    """One sample per q x q region (Sec. 3.8): int32 [ceil(H/q)][ceil(W/q)]
+    pixel indices y * W + x of the selections, -1 where none."""
+    H, W = keep_a.shape
+    sel = torch.empty((-(-H // q), -(-W // q)), dtype=torch.int32, device=keep_a.device)
+    check(lib().ff_sparsify(_ptr(flow_a, torch.int16), _ptr(keep_a, torch.uint8), _ptr(flow_b1, torch.int16),
+                            _ptr(flow_b2, torch.int16), W, H, q, e, _ptr(sel), _stream()), "ff_sparsify")
+    return sel
+
+
 def flow_fields_two_backward(img1, img2, params: Params, seed2: int | None = None, radius2: int | None = None):
     """Flow Fields with the check against two backward fields (Sec. 3.7).
     The second backward field is the forward field of a second run on the

@@ -74,6 +74,10 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_init_nn(fake, fake, fake, fake, 5, 5, 6, 3, fake, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter2(fake, fake, fake, fake, None, fake, 5, 5, 1.0, fake, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter2(fake, fake, fake, fake, fake, fake, 5, 5, -1.0, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_sparsify(fake, fake, fake, None, 5, 5, 0, 1, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_sparsify(fake, fake, fake, None, 5, 5, 65, 1, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_sparsify(fake, fake, fake, None, 5, 5, 3, -1, fake, None) == ffi.FF_ERR_ARG
+    assert lib.ff_sparsify(fake, fake, None, None, 5, 5, 3, 1, fake, None) == ffi.FF_ERR_ARG
     # bad Flow Fields+ schedules
     for kw in ({"plus_iters": -1}, {"plus_iters": 60, "iters": 6}, {"Rp_num": -2}, {"fine_iters": 65},
                {"fine_iters": -1}, {"Rp_num": (1 << 20) + 1}):

@@ -3,7 +3,8 @@ every GPU path, bit for bit against the oracle, whose schedule is pinned
 against the composition of its pinned steps: P steps with random searches at
 R^+ first, then T at R, random searches only inside a group, the step index
 running on over both groups; Fast: only the given number of steps at R on the
-finest scale.  Also the check against two backward fields (Sec. 3.7)."""
+finest scale.  Also the check against two backward fields (Sec. 3.7) and
+the q x q sparsification (Sec. 3.8)."""
 import os
 
 import numpy as np
@@ -142,3 +143,34 @@ def test_two_backward_check_bit_exact(config, radius2):
     assert np.array_equal(host(g["keep_fwd"]), keep)
     assert np.array_equal(host(g["keep_bwd"]), o1["keep_bwd"])
     assert host(g["keep_fwd"]).sum() <= o1["keep_fwd"].sum()
+
+
+@pytest.mark.parametrize("q,e,two", [(3, 1, True), (3, 5, False), (4, 2, True), (1, 1, False), (64, 3, True),
+                                     (7, 0, False)])
+def test_sparsify_bit_exact_on_random_fields(q, e, two):
+    """Random fields (targets partly outside the image, many equal errors):
+    selections, ties and dropped regions equal the oracle's."""
+    rng = np.random.default_rng(q * 100 + e)
+    H, W = 97, 131
+    fa = rng.integers(-5, 6, size=(H, W, 2)).astype(np.int16)
+    fb1 = rng.integers(-5, 6, size=(H, W, 2)).astype(np.int16)
+    fb2 = rng.integers(-5, 6, size=(H, W, 2)).astype(np.int16) if two else None
+    keep = (rng.random((H, W)) < 0.5).astype(np.uint8)
+    got = ff.sparsify(dev(fa), dev(keep), dev(fb1), None if fb2 is None else dev(fb2), q, e)
+    assert np.array_equal(host(got), oracle.sparsify(fa, keep, fb1, fb2, q, e))
+
+
+def test_sparsify_bit_exact_on_oracle_fields():
+    """The 1024x436 pair's fields from the oracle (both backward fields):
+    the GPU selection equals the oracle's."""
+    p = make_pair(2)
+    c = CONFIG_PARAMS[2]
+    o1 = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
+    o2 = oracle.flow_fields(p.img2, p.img1, c.levels, c.iters, radius=2, seed=c.seed + 1, nthreads=NT)
+    keep = oracle.consistency2(o1["flow_fwd"], o1["cost_fwd"], o1["flow_bwd"], o1["cost_bwd"], o2["flow_fwd"],
+                               o2["cost_fwd"], c.eps)
+    for q, e in ((3, 1), (3, 3), (4, 4)):
+        got = ff.sparsify(dev(o1["flow_fwd"]), dev(keep), dev(o1["flow_bwd"]), dev(o2["flow_fwd"]), q, e)
+        exp = oracle.sparsify(o1["flow_fwd"], keep, o1["flow_bwd"], o2["flow_fwd"], q, e)
+        assert np.array_equal(host(got), exp), (q, e)
+        assert (exp >= 0).sum() > 0
