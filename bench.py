@@ -54,7 +54,7 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
 TRAFFIC_BYTES = 10568.0 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "b458bbf36e3bcd21"
+TRAFFIC_SOURCES_SHA = "2a0872497478728d"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-pair measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-descriptor measurement")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the Flow Fields+ / Fast / two-backward-field measurements")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--val-pairs", type=int, default=4, help="held-out pairs of the EPE judge")
     ap.add_argument("--train-pairs", type=int, default=16)
@@ -346,9 +348,11 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {nbytes} bytes")
 
-    log("bench: Flow Fields+ schedules")
-    schedules = schedule_leg(ff, torch, img1, img2, params, pair)
-    log(f"bench: schedules {schedules}")
+    schedules = None
+    if not args.no_schedules:
+        log("bench: Flow Fields+ schedules")
+        schedules = schedule_leg(ff, torch, img1, img2, params, pair)
+        log(f"bench: schedules {schedules}")
 
     batched = None
     if not args.no_batch:
