@@ -8,9 +8,9 @@ the learned-descriptor form and its gradient live in ``oracle.float_cost``
 (NumPy, float64).
 """
 from .core import (UNSET, build, lib, blur, descriptor, descriptors_all, cost, nn, init_coarse, seed_level,
-                   propagate, random_search, rs_offset, rs_radius, consistency, consistency2, sparsify, flow_fields,
-                   mix64, cost_f32, quantize_u8, flow_fields_f32)
+                   propagate, random_search, rs_offset, rs_radius, consistency, consistency2, region_filter,
+                   sparsify, flow_fields, mix64, cost_f32, quantize_u8, flow_fields_f32)
 
 __all__ = ["UNSET", "build", "lib", "blur", "descriptor", "descriptors_all", "cost", "nn", "init_coarse",
-           "seed_level", "propagate", "random_search", "rs_offset", "rs_radius", "consistency", "consistency2", "sparsify",
-           "flow_fields", "mix64", "cost_f32", "quantize_u8", "flow_fields_f32"]
+           "seed_level", "propagate", "random_search", "rs_offset", "rs_radius", "consistency", "consistency2",
+           "region_filter", "sparsify", "flow_fields", "mix64", "cost_f32", "quantize_u8", "flow_fields_f32"]

@@ -54,6 +54,7 @@ def lib():
         L.or_consistency.argtypes = [P, P, P, P, i, i, dbl, P]
         L.or_consistency2.argtypes = [P, P, P, P, P, P, i, i, dbl, P]
         L.or_sparsify.argtypes = [P, P, P, P, i, i, i, i, P]
+        L.or_region_filter.argtypes = [P, P, P, i, i, i, P]
         L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
@@ -185,6 +186,17 @@ def consistency2(fa, ca, fb1, cb1, fb2, cb2, eps: float = 1.0):
     args = [np.ascontiguousarray(a) for a in (fa, ca, fb1, cb1, fb2, cb2)]
     lib().or_consistency2(*[_p(a) for a in args], W, H, float(eps), _p(keep))
     return keep
+
+
+def region_filter(flow, cost, keep, s: int) -> np.ndarray:
+    """Keep mask without the small regions next to removed outliers (Sec. 3.7)."""
+    H, W = keep.shape
+    out = np.empty((H, W), np.uint8)
+    flow = np.ascontiguousarray(flow, np.int16)
+    cost = np.ascontiguousarray(cost, np.uint32)
+    keep = np.ascontiguousarray(keep, np.uint8)
+    lib().or_region_filter(_p(flow), _p(cost), _p(keep), W, H, s, _p(out))
+    return out
 
 
 def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:

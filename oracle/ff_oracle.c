@@ -41,6 +41,7 @@
  *   consistency forward-backward check (Sec. 3.7): keep p iff
  *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14);
  *               consistency2 the same against two backward fields.
+ *   region_filter  deletes small regions next to removed outliers (Sec. 3.7).
  *   sparsify    one sample per q x q region (Sec. 3.8).
  *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
@@ -443,6 +444,59 @@ void or_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, 
             }
             keep[k] = (uint8_t)ok;
         }
+}
+
+/* Region filter (Sec. 3.7, after the consistency check): the kept pixels
+ * form regions, two 4-neighbours belonging to the same region iff their
+ * flows differ by less than 3 px (|F(p) - F(q)|^2 < 9, exact).  A region of
+ * fewer than s pixels is deleted if one of its pixels could take in, by the
+ * same rule, a 4-neighbour that the consistency check removed (set, cost not
+ * UNSET, but not kept).  keep_out = keep_in minus the deleted regions.
+ * Breadth-first search over each region in turn. */
+static int region_link(const int16_t *f, size_t a, size_t b)
+{
+    int dx = f[2 * a] - f[2 * b], dy = f[2 * a + 1] - f[2 * b + 1];
+    return dx * dx + dy * dy < 9;
+}
+
+void or_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int W, int H, int s,
+                      uint8_t *keep_out)
+{
+    size_t N = (size_t)W * H;
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * N);
+    size_t *queue = (size_t *)malloc(sizeof(size_t) * N);
+    for (size_t k = 0; k < N; ++k) comp[k] = -1;
+    memcpy(keep_out, keep_in, N);
+    const int ddx[4] = {1, -1, 0, 0}, ddy[4] = {0, 0, 1, -1};
+    for (size_t k0 = 0; k0 < N; ++k0) {
+        if (!keep_in[k0] || comp[k0] >= 0) continue;
+        size_t head = 0, tail = 0;
+        queue[tail++] = k0;
+        comp[k0] = (int32_t)k0;
+        int touches = 0;
+        while (head < tail) {
+            size_t k = queue[head++];
+            int x = (int)(k % W), y = (int)(k / W);
+            for (int d = 0; d < 4; ++d) {
+                int nx = x + ddx[d], ny = y + ddy[d];
+                if (nx < 0 || nx >= W || ny < 0 || ny >= H) continue;
+                size_t kn = (size_t)ny * W + nx;
+                if (!region_link(flow, k, kn)) continue;
+                if (keep_in[kn]) {
+                    if (comp[kn] < 0) {
+                        comp[kn] = (int32_t)k0;
+                        queue[tail++] = kn;
+                    }
+                } else if (cost[kn] != OR_UNSET) {
+                    touches = 1;  /* a removed outlier the region could take in */
+                }
+            }
+        }
+        if (tail < (size_t)s && touches)
+            for (size_t i = 0; i < tail; ++i) keep_out[queue[i]] = 0;
+    }
+    free(comp);
+    free(queue);
 }
 
 /* Sparsification (Sec. 3.8): in every q x q region of the filtered field a

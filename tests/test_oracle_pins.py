@@ -658,3 +658,105 @@ def test_sparsify_on_a_field_selects_kept_samples_of_least_error():
         # kept samples passed the check: |F + F_b|^2 < 1, so the error is 0 (integer flows)
         f = o["flow_fwd"][y, x].astype(int)
         assert np.all(f + o["flow_bwd"][y + f[1], x + f[0]] == 0)
+
+
+# ---------------------------------------------------------------- region filter (Sec. 3.7)
+
+def _region_filter_union_find(flow, cost, keep, s):
+    """Independent restatement: union-find over the kept pixels' linked
+    4-neighbour pairs, then the size and removed-outlier tests per region."""
+    H, W = keep.shape
+    parent = list(range(H * W))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    f = flow.astype(np.int64)
+
+    def linked(a, b):
+        d = f[a // W, a % W] - f[b // W, b % W]
+        return int(d[0] ** 2 + d[1] ** 2) < 9
+
+    for y in range(H):
+        for x in range(W):
+            a = y * W + x
+            for b in ([a + 1] if x + 1 < W else []) + ([a + W] if y + 1 < H else []):
+                if keep[y, x] and keep.flat[b] and linked(a, b):
+                    parent[find(a)] = find(b)
+    size, touch = {}, {}
+    for y in range(H):
+        for x in range(W):
+            if not keep[y, x]:
+                continue
+            a = y * W + x
+            r = find(a)
+            size[r] = size.get(r, 0) + 1
+            for nx, ny in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1)):
+                if 0 <= nx < W and 0 <= ny < H and not keep[ny, nx] and cost[ny, nx] != UNSET and \
+                        linked(a, ny * W + nx):
+                    touch[r] = True
+    out = keep.copy()
+    for y in range(H):
+        for x in range(W):
+            if keep[y, x]:
+                r = find(y * W + x)
+                if size[r] < s and touch.get(r, False):
+                    out[y, x] = 0
+    return out
+
+
+@pytest.mark.parametrize("seed,s", [(1, 5), (2, 12), (3, 40), (4, 1)])
+def test_region_filter_equals_union_find(seed, s):
+    rng = np.random.default_rng(seed)
+    H, W = 19, 27
+    flow = rng.integers(-4, 5, size=(H, W, 2)).astype(np.int16)
+    flow[: H // 2] = rng.integers(-1, 2, size=(H // 2, W, 2))  # smooth part: large regions
+    cost = rng.integers(0, 100, size=(H, W)).astype(np.uint32)
+    cost[rng.random((H, W)) < 0.05] = UNSET
+    keep = ((rng.random((H, W)) < 0.7) & (cost != UNSET)).astype(np.uint8)
+    got = oracle.region_filter(flow, cost, keep, s)
+    assert np.array_equal(got, _region_filter_union_find(flow, cost, keep, s))
+
+
+def test_region_filter_constant_flow_is_connected_components():
+    """With one flow everywhere every 4-neighbour pair links: the regions are
+    the 4-connected components of the mask (scipy.ndimage.label), and a
+    component is deleted iff it is smaller than s and borders a removed
+    (set, not kept) pixel."""
+    rng = np.random.default_rng(7)
+    H, W = 30, 40
+    keep = (rng.random((H, W)) < 0.55).astype(np.uint8)
+    flow = np.zeros((H, W, 2), np.int16)
+    cost = np.zeros((H, W), np.uint32)
+    cost[::3, ::4] = UNSET
+    s = 6
+    lab, n = ndi.label(keep)
+    removed = (keep == 0) & (cost != UNSET)
+    grown = ndi.binary_dilation(removed, structure=ndi.generate_binary_structure(2, 1))
+    expect = keep.copy()
+    for c in range(1, n + 1):
+        m = lab == c
+        if m.sum() < s and (m & grown).any():
+            expect[m] = 0
+    assert np.array_equal(oracle.region_filter(flow, cost, keep, s), expect)
+
+
+def test_region_filter_hand_worked():
+    """A 2-pixel region next to a removed outlier of similar flow is deleted;
+    next to one of dissimilar flow (difference 3 px) it stays; s = 2 keeps it."""
+    flow = np.zeros((1, 4, 2), np.int16)
+    cost = np.zeros((1, 4), np.uint32)
+    keep = np.array([[1, 1, 0, 1]], np.uint8)
+    flow[0, 2] = (2, 2)  # removed outlier, |diff| = sqrt(8) < 3 from (0, 0)
+    flow[0, 3] = (7, 0)  # lone kept pixel, dissimilar to the outlier ((2, 2): 29, (3, 0): 16)
+    out = oracle.region_filter(flow, cost, keep, 3)
+    assert out.tolist() == [[0, 0, 0, 1]]
+    flow[0, 2] = (3, 0)  # now |diff| = 3: not below 3 px
+    assert oracle.region_filter(flow, cost, keep, 3).tolist() == [[1, 1, 0, 1]]
+    flow[0, 2] = (2, 2)
+    assert oracle.region_filter(flow, cost, keep, 2).tolist() == [[1, 1, 0, 1]]
+    cost[0, 2] = UNSET  # an UNSET pixel is no removed outlier
+    assert oracle.region_filter(flow, cost, keep, 3).tolist() == [[1, 1, 0, 1]]
