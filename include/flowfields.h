@@ -173,6 +173,20 @@ ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, 
                                  const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
                                  int32_t H, float eps, uint8_t *keep_a, void *stream);
 
+/* Region filter (Sec. 3.7, after the consistency check): the kept pixels
+ * (keep_in != 0) form regions, two 4-neighbours belonging to the same region
+ * iff their flows differ by less than 3 px (|F(p) - F(q)|^2 < 9, exact); a
+ * region of fewer than s pixels is deleted if one of its pixels has a
+ * 4-neighbour the check removed (cost not 0xFFFFFFFF, keep_in == 0) whose
+ * flow differs from its own by less than 3 px.  keep_out [H][W] (not
+ * keep_in) = keep_in minus the deleted regions.  Full-resolution flow
+ * [H][W][2], cost [H][W].  scratch: device, at least
+ * ff_region_filter_scratch_bytes(W, H) bytes (FF_ERR_WORKSPACE otherwise),
+ * 4-byte aligned, contents on return unspecified; s >= 0. */
+size_t ff_region_filter_scratch_bytes(int32_t W, int32_t H);
+ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W, int32_t H,
+                           int32_t s, void *scratch, size_t scratch_bytes, uint8_t *keep_out, void *stream);
+
 /* Sparsification (Sec. 3.8): for every q x q region of the filtered field
  * a (regions anchored at (0, 0), ragged at the right and bottom; sel is
  * int32 [ceil(H/q)][ceil(W/q)]), sel = y * W + x of the kept sample

@@ -9,10 +9,10 @@ from .flowfields import (FlowFields, Params, consistency_filter, consistency_fil
                          flow_fields, flow_fields_two_backward,
                          init_nn, level_passes, level_variants, level_variants_f32, propagate_level, random_search,
                          rs_radius, run_level, seed_level, set_level_passes, set_level_variants,
-                         set_level_variants_f32, sparsify, workspace_bytes)
+                         set_level_variants_f32, region_filter, sparsify, workspace_bytes)
 
 __all__ = ["FlowFieldsError", "lib", "FlowFields", "Params", "consistency_filter", "consistency_filter2",
            "descriptors", "flow_fields", "flow_fields_two_backward",
            "init_nn", "level_passes", "level_variants", "level_variants_f32", "set_level_passes", "set_level_variants",
            "set_level_variants_f32", "propagate_level", "random_search", "rs_radius", "run_level", "seed_level",
-           "sparsify", "workspace_bytes"]
+           "region_filter", "sparsify", "workspace_bytes"]

@@ -371,6 +371,17 @@ ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, 
                                            (hipStream_t)stream));
 }
 
+size_t ff_region_filter_scratch_bytes(int32_t W, int32_t H) {
+  return dims_ok(W, H) ? ffh::region_filter_scratch_bytes(W, H) : 0;
+}
+
+ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W, int32_t H,
+                           int32_t s, void *scratch, size_t scratch_bytes, uint8_t *keep_out, void *stream) {
+  if (!flow || !cost || !keep_in || !keep_out || !dims_ok(W, H) || s < 0 || keep_in == keep_out) return FF_ERR_ARG;
+  if (!scratch || scratch_bytes < ffh::region_filter_scratch_bytes(W, H)) return FF_ERR_WORKSPACE;
+  return from_hip(ffh::launch_region_filter(flow, cost, keep_in, W, H, s, scratch, keep_out, (hipStream_t)stream));
+}
+
 ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_t *flow_b1, const int16_t *flow_b2,
                       int32_t W, int32_t H, int32_t q, int32_t e, int32_t *sel, void *stream) {
   if (!flow_a || !keep_a || !flow_b1 || !sel || !dims_ok(W, H) || q < 1 || q > 64 || e < 0) return FF_ERR_ARG;

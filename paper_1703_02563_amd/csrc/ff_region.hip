@@ -1,0 +1,131 @@
+// Region filter (Sec. 3.7, after the consistency check): regions of kept
+// pixels, two 4-neighbours belonging to one region iff their flows differ by
+// less than 3 px; a region of fewer than s pixels is deleted if one of its
+// pixels could take in, by the same rule, a removed outlier (a set pixel the
+// check did not keep).
+//
+// Regions are found by union-find in a scratch array of parents with
+// parent[x] <= x at all times: a union hooks the larger of two roots under
+// the smaller with a compare-and-swap, so every root ends as the smallest
+// pixel index of its region, whatever the order of the unions.  A find
+// follows strictly decreasing indices and stops; a failed swap returns a
+// smaller parent, so the larger of the two roots decreases on every retry
+// and a union ends after at most N retries.  Parents are read with
+// device-scope atomic loads (no stale copies in a compute unit's cache).
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace {
+
+using ffk::kUnset;
+
+__device__ __forceinline__ int rf_load(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int rf_find(const int32_t *parent, int x) {
+  for (;;) {
+    const int p = rf_load(parent + x);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+__device__ __forceinline__ bool rf_linked(int32_t fa, int32_t fb) {
+  const int dx = ffk::flow_x(fa) - ffk::flow_x(fb), dy = ffk::flow_y(fa) - ffk::flow_y(fb);
+  return dx * dx + dy * dy < 9;
+}
+
+__global__ __launch_bounds__(256) void k_rf_init(int32_t *parent, int32_t *size, uint32_t *flag, int W, int H) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int k = y * W + x;
+  parent[k] = k;
+  size[k] = 0;
+  flag[k] = 0;
+}
+
+__device__ __forceinline__ void rf_union(int32_t *parent, int a, int b) {
+  int ra = rf_find(parent, a), rb = rf_find(parent, b);
+  while (ra != rb) {
+    if (ra > rb) {
+      const int t = ra;
+      ra = rb;
+      rb = t;
+    }
+    const int old = atomicCAS(parent + rb, rb, ra);  // hook rb under ra if rb is still a root
+    if (old == rb) return;
+    rb = rf_find(parent, old);  // old < rb
+    ra = rf_find(parent, ra);
+  }
+}
+
+// Unions of every kept pixel with its right and lower neighbours.
+__global__ __launch_bounds__(256) void k_rf_union(const int32_t *flow, const uint8_t *keep, int32_t *parent, int W,
+                                                  int H) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int k = y * W + x;
+  if (!keep[k]) return;
+  const int32_t f = flow[k];
+  if (x + 1 < W && keep[k + 1] && rf_linked(f, flow[k + 1])) rf_union(parent, k, k + 1);
+  if (y + 1 < H && keep[k + W] && rf_linked(f, flow[k + W])) rf_union(parent, k, k + W);
+}
+
+// Region sizes, and whether a region borders a removed outlier it could take in.
+__global__ __launch_bounds__(256) void k_rf_measure(const int32_t *flow, const uint32_t *cost, const uint8_t *keep,
+                                                    const int32_t *parent, int32_t *size, uint32_t *flag, int W,
+                                                    int H) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int k = y * W + x;
+  if (!keep[k]) return;
+  const int r = rf_find(parent, k);
+  atomicAdd(size + r, 1);
+  const int32_t f = flow[k];
+  const int nx[4] = {x + 1, x - 1, x, x}, ny[4] = {y, y, y + 1, y - 1};
+  bool touches = false;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (nx[d] < 0 || nx[d] >= W || ny[d] < 0 || ny[d] >= H) continue;
+    const int kn = ny[d] * W + nx[d];
+    touches |= !keep[kn] && cost[kn] != kUnset && rf_linked(f, flow[kn]);
+  }
+  if (touches) atomicOr(flag + r, 1u);
+}
+
+__global__ __launch_bounds__(256) void k_rf_apply(const uint8_t *keep, const int32_t *parent, const int32_t *size,
+                                                  const uint32_t *flag, int W, int H, int s, uint8_t *keep_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int k = y * W + x;
+  uint8_t out = 0;
+  if (keep[k]) {
+    const int r = rf_find(parent, k);
+    out = !(size[r] < s && flag[r] != 0);
+  }
+  keep_out[k] = out;
+}
+
+}  // namespace
+
+namespace ffh {
+
+size_t region_filter_scratch_bytes(int W, int H) { return (size_t)W * H * 3 * sizeof(int32_t); }
+
+hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep, int W, int H, int s,
+                                void *scratch, uint8_t *keep_out, hipStream_t stream) {
+  const size_t N = (size_t)W * H;
+  int32_t *parent = static_cast<int32_t *>(scratch);
+  int32_t *size = parent + N;
+  uint32_t *flag = reinterpret_cast<uint32_t *>(size + N);
+  const int32_t *f = reinterpret_cast<const int32_t *>(flow);
+  const dim3 grid((W + 255) / 256, H), block(256);
+  hipLaunchKernelGGL(k_rf_init, grid, block, 0, stream, parent, size, flag, W, H);
+  hipLaunchKernelGGL(k_rf_union, grid, block, 0, stream, f, keep, parent, W, H);
+  hipLaunchKernelGGL(k_rf_measure, grid, block, 0, stream, f, cost, keep, parent, size, flag, W, H);
+  hipLaunchKernelGGL(k_rf_apply, grid, block, 0, stream, keep, parent, size, flag, W, H, s, keep_out);
+  return hipGetLastError();
+}
+
+}  // namespace ffh

@@ -56,6 +56,8 @@ _SIGS = {
     "ff_consistency_filter": (C.c_int, [_P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_consistency_filter2": (C.c_int, [_P, _P, _P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P]),
     "ff_sparsify": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P]),
+    "ff_region_filter_scratch_bytes": (C.c_size_t, [_I32, _I32]),
+    "ff_region_filter": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, C.c_size_t, _P, _P]),
     "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
     "ff_run_level": (C.c_int, [_P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P, _P, _P,
                                C.c_size_t, _P, _P]),

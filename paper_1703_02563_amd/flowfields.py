@@ -175,6 +175,18 @@ def consistency_filter2(flow_a, cost_a, flow_b1, cost_b1, flow_b2, cost_b2, eps:
     return keep
 
 
+def region_filter(flow, cost, keep, s: int) -> torch.Tensor:
+    """Keep mask without the regions of fewer than s pixels that border a
+    removed outlier of similar flow (Sec. 3.7)."""
+    H, W = keep.shape
+    out = torch.empty((H, W), dtype=torch.uint8, device=keep.device)
+    nbytes = int(lib().ff_region_filter_scratch_bytes(W, H))
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=keep.device)
+    check(lib().ff_region_filter(_ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(keep, torch.uint8), W, H, s,
+                                 _ptr(scratch), nbytes, _ptr(out), _stream()), "ff_region_filter")
+    return out
+
+
 def sparsify(flow_a, keep_a, flow_b1, flow_b2=None, q: int = 3, e: int = 1) -> torch.Tensor:
     """One sample per q x q region (Sec. 3.8): int32 [ceil(H/q)][ceil(W/q)]
     pixel indices y * W + x of the selections, -1 where none."""

@@ -3,8 +3,8 @@ every GPU path, bit for bit against the oracle, whose schedule is pinned
 against the composition of its pinned steps: P steps with random searches at
 R^+ first, then T at R, random searches only inside a group, the step index
 running on over both groups; Fast: only the given number of steps at R on the
-finest scale.  Also the check against two backward fields (Sec. 3.7) and
-the q x q sparsification (Sec. 3.8)."""
+finest scale.  Also the check against two backward fields and the region
+filter (Sec. 3.7) and the q x q sparsification (Sec. 3.8)."""
 import os
 
 import numpy as np
@@ -174,3 +174,50 @@ def test_sparsify_bit_exact_on_oracle_fields():
         exp = oracle.sparsify(o1["flow_fwd"], keep, o1["flow_bwd"], o2["flow_fwd"], q, e)
         assert np.array_equal(host(got), exp), (q, e)
         assert (exp >= 0).sum() > 0
+
+
+def _random_filter_inputs(seed, H, W):
+    rng = np.random.default_rng(seed)
+    flow = rng.integers(-4, 5, size=(H, W, 2)).astype(np.int16)
+    flow[: H // 2] = rng.integers(-1, 2, size=(H // 2, W, 2))  # smooth half: large regions
+    cost = rng.integers(0, 1000, size=(H, W)).astype(np.uint32)
+    cost[rng.random((H, W)) < 0.05] = oracle.UNSET
+    keep = ((rng.random((H, W)) < 0.7) & (cost != oracle.UNSET)).astype(np.uint8)
+    return flow, cost, keep
+
+
+@pytest.mark.parametrize("seed,shape,s", [(1, (97, 131), 5), (2, (97, 131), 40), (3, (1, 300), 3), (4, (300, 1), 7),
+                                          (5, (1, 1), 2), (6, (64, 64), 0), (7, (211, 157), 100)])
+def test_region_filter_bit_exact_on_random_fields(seed, shape, s):
+    flow, cost, keep = _random_filter_inputs(seed, *shape)
+    got = ff.region_filter(dev(flow), dev(cost.view(np.int32)), dev(keep), s)
+    assert np.array_equal(host(got), oracle.region_filter(flow, cost, keep, s))
+
+
+def test_region_filter_serpentine_region():
+    """One region winding through the whole image (long chains of unions)
+    plus single-pixel islands next to removed outliers."""
+    H, W = 64, 96
+    keep = np.zeros((H, W), np.uint8)
+    keep[::2] = 1
+    for y in range(1, H, 2):
+        keep[y, W - 1 if (y // 2) % 2 == 0 else 0] = 1  # connect rows alternately at the ends
+    flow = np.zeros((H, W, 2), np.int16)
+    cost = np.zeros((H, W), np.uint32)
+    rng = np.random.default_rng(9)
+    for y, x in zip(rng.integers(1, H - 1, 40) | 1, rng.integers(2, W - 2, 40)):
+        keep[y, x] = 1  # islands inside the gaps; they touch the serpentine, so they join it
+    for s in (10, H * W):
+        got = ff.region_filter(dev(flow), dev(cost.view(np.int32)), dev(keep), s)
+        assert np.array_equal(host(got), oracle.region_filter(flow, cost, keep, s)), s
+
+
+def test_region_filter_bit_exact_on_oracle_fields():
+    p = make_pair(2)
+    c = CONFIG_PARAMS[2]
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
+    for s in (4, 50):
+        exp = oracle.region_filter(o["flow_fwd"], o["cost_fwd"], o["keep_fwd"], s)
+        got = ff.region_filter(dev(o["flow_fwd"]), dev(o["cost_fwd"].view(np.int32)), dev(o["keep_fwd"]), s)
+        assert np.array_equal(host(got), exp), s
+        assert exp.sum() < o["keep_fwd"].sum()
