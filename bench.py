@@ -162,6 +162,8 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     the same pair and launch tables: Mpix/s and quality."""
     import dataclasses
 
+    import numpy as np
+
     from ffgen import epe_stats
     res = {}
     for name, kw in (("plus", dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num)),
@@ -201,6 +203,27 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     res["two_backward"] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
                            "second_backward": "seed + 1, patch radius 2", "kept_density": round(q["kept_density"], 4),
                            "kept_epe": round(q["kept_epe"], 4)}
+    # then the region filter (Sec. 3.7, s = 50) and the 3 x 3 sparsification (Sec. 3.8, e = 2) on that field
+    def filters():
+        kf = ff.region_filter(out["flow_fwd"], out["cost_fwd"], out["keep_fwd"], 50)
+        return kf, ff.sparsify(out["flow_fwd"], kf, out["flow_bwd"], out["flow_bwd2"], 3, 2)
+    for _ in range(3):
+        filters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        kf, sel = filters()
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - t0) / reps * 1e3
+    qf = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=kf.cpu().numpy())
+    idx = sel.cpu().numpy().ravel()
+    idx = idx[idx >= 0]
+    ys, xs = idx // W, idx % W
+    f = out["flow_fwd"].cpu().numpy()[ys, xs].astype(np.float64)
+    sparse_epe = float(np.mean(np.hypot(*(f - pair.flow_gt[ys, xs]).T))) if len(idx) else None
+    res["filtered"] = {"ms_region_filter_and_sparsify": round(fms, 4), "region_s": 50, "sparsify_q_e": [3, 2],
+                       "kept_density": round(qf["kept_density"], 4), "kept_epe": round(qf["kept_epe"], 4),
+                       "samples": int(len(idx)), "sample_epe": None if sparse_epe is None else round(sparse_epe, 4)}
     return res
 
 

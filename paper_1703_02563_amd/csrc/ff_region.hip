@@ -10,8 +10,12 @@
 // pixel index of its region, whatever the order of the unions.  A find
 // follows strictly decreasing indices and stops; a failed swap returns a
 // smaller parent, so the larger of the two roots decreases on every retry
-// and a union ends after at most N retries.  Parents are read with
-// device-scope atomic loads (no stale copies in a compute unit's cache).
+// and a union ends after at most N retries.  Finds halve their paths (a
+// parent is lowered with atomicMin to its own parent, an ancestor, so the
+// order invariant holds), and once all unions are done every pixel's parent
+// is set to its root, so the later passes find roots in one step.  Parents
+// are read with device-scope atomic loads (no stale copies in a compute
+// unit's cache).
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -31,6 +35,17 @@ __device__ __forceinline__ int rf_find(const int32_t *parent, int x) {
   }
 }
 
+// The same with path halving: x's parent is lowered to its grandparent.
+__device__ __forceinline__ int rf_find_halve(int32_t *parent, int x) {
+  for (;;) {
+    const int p = rf_load(parent + x);
+    if (p == x) return x;
+    const int g = rf_load(parent + p);
+    if (g != p) atomicMin(parent + x, g);
+    x = p;
+  }
+}
+
 __device__ __forceinline__ bool rf_linked(int32_t fa, int32_t fb) {
   const int dx = ffk::flow_x(fa) - ffk::flow_x(fb), dy = ffk::flow_y(fa) - ffk::flow_y(fb);
   return dx * dx + dy * dy < 9;
@@ -46,7 +61,7 @@ __global__ __launch_bounds__(256) void k_rf_init(int32_t *parent, int32_t *size,
 }
 
 __device__ __forceinline__ void rf_union(int32_t *parent, int a, int b) {
-  int ra = rf_find(parent, a), rb = rf_find(parent, b);
+  int ra = rf_find_halve(parent, a), rb = rf_find_halve(parent, b);
   while (ra != rb) {
     if (ra > rb) {
       const int t = ra;
@@ -55,9 +70,18 @@ __device__ __forceinline__ void rf_union(int32_t *parent, int a, int b) {
     }
     const int old = atomicCAS(parent + rb, rb, ra);  // hook rb under ra if rb is still a root
     if (old == rb) return;
-    rb = rf_find(parent, old);  // old < rb
-    ra = rf_find(parent, ra);
+    rb = rf_find_halve(parent, old);  // old < rb
+    ra = rf_find_halve(parent, ra);
   }
+}
+
+// After the unions: every pixel's parent becomes its root.
+__global__ __launch_bounds__(256) void k_rf_flatten(int32_t *parent, int W, int H) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const int k = y * W + x;
+  const int r = rf_find(parent, k);
+  if (r != k) atomicMin(parent + k, r);
 }
 
 // Unions of every kept pixel with its right and lower neighbours.
@@ -72,26 +96,43 @@ __global__ __launch_bounds__(256) void k_rf_union(const int32_t *flow, const uin
   if (y + 1 < H && keep[k + W] && rf_linked(f, flow[k + W])) rf_union(parent, k, k + W);
 }
 
-// Region sizes, and whether a region borders a removed outlier it could take in.
+// Region sizes, and whether a region borders a removed outlier it could
+// take in.  The atomics are aggregated per wave (neighbouring pixels mostly
+// share a root): the first pending lane's root is served with one atomic
+// for all lanes of that root, until every lane is served (at most 64 rounds,
+// the same for all lanes of the wave).
 __global__ __launch_bounds__(256) void k_rf_measure(const int32_t *flow, const uint32_t *cost, const uint8_t *keep,
                                                     const int32_t *parent, int32_t *size, uint32_t *flag, int W,
                                                     int H) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
   const int k = y * W + x;
-  if (!keep[k]) return;
-  const int r = rf_find(parent, k);
-  atomicAdd(size + r, 1);
-  const int32_t f = flow[k];
-  const int nx[4] = {x + 1, x - 1, x, x}, ny[4] = {y, y, y + 1, y - 1};
+  const bool on = x < W && y < H && keep[k] != 0;
+  int r = -1;
   bool touches = false;
+  if (on) {
+    r = rf_find(parent, k);
+    const int32_t f = flow[k];
+    const int nx[4] = {x + 1, x - 1, x, x}, ny[4] = {y, y, y + 1, y - 1};
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    if (nx[d] < 0 || nx[d] >= W || ny[d] < 0 || ny[d] >= H) continue;
-    const int kn = ny[d] * W + nx[d];
-    touches |= !keep[kn] && cost[kn] != kUnset && rf_linked(f, flow[kn]);
+    for (int d = 0; d < 4; ++d) {
+      if (nx[d] < 0 || nx[d] >= W || ny[d] < 0 || ny[d] >= H) continue;
+      const int kn = ny[d] * W + nx[d];
+      touches |= !keep[kn] && cost[kn] != kUnset && rf_linked(f, flow[kn]);
+    }
   }
-  if (touches) atomicOr(flag + r, 1u);
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(on);
+  while (pending) {
+    const int leader = __ffsll(pending) - 1;
+    const int rl = __shfl(r, leader);
+    const unsigned long long same = __ballot(on && r == rl) & pending;
+    const unsigned long long hit = __ballot(on && r == rl && touches) & pending;
+    if (lane == leader) {
+      atomicAdd(size + rl, (int)__popcll(same));
+      if (hit) atomicOr(flag + rl, 1u);
+    }
+    pending &= ~same;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rf_apply(const uint8_t *keep, const int32_t *parent, const int32_t *size,
@@ -123,6 +164,7 @@ hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const
   const dim3 grid((W + 255) / 256, H), block(256);
   hipLaunchKernelGGL(k_rf_init, grid, block, 0, stream, parent, size, flag, W, H);
   hipLaunchKernelGGL(k_rf_union, grid, block, 0, stream, f, keep, parent, W, H);
+  hipLaunchKernelGGL(k_rf_flatten, grid, block, 0, stream, parent, W, H);
   hipLaunchKernelGGL(k_rf_measure, grid, block, 0, stream, f, cost, keep, parent, size, flag, W, H);
   hipLaunchKernelGGL(k_rf_apply, grid, block, 0, stream, keep, parent, size, flag, W, H, s, keep_out);
   return hipGetLastError();
