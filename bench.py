@@ -53,8 +53,8 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10568.0 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "2a0872497478728d"
+TRAFFIC_BYTES = 10568.1 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "c1c65354e256ed3d"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
@@ -218,12 +218,12 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     qf = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=kf.cpu().numpy())
     idx = sel.cpu().numpy().ravel()
     idx = idx[idx >= 0]
-    ys, xs = idx // W, idx % W
-    f = out["flow_fwd"].cpu().numpy()[ys, xs].astype(np.float64)
-    sparse_epe = float(np.mean(np.hypot(*(f - pair.flow_gt[ys, xs]).T))) if len(idx) else None
+    picked = np.zeros((H, W), np.uint8)
+    picked.flat[idx] = 1
+    qs = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=picked)  # non-occluded samples
     res["filtered"] = {"ms_region_filter_and_sparsify": round(fms, 4), "region_s": 50, "sparsify_q_e": [3, 2],
                        "kept_density": round(qf["kept_density"], 4), "kept_epe": round(qf["kept_epe"], 4),
-                       "samples": int(len(idx)), "sample_epe": None if sparse_epe is None else round(sparse_epe, 4)}
+                       "samples": int(len(idx)), "sample_epe": round(qs["kept_epe"], 4)}
     return res
 
 
