@@ -51,11 +51,21 @@ __device__ __forceinline__ bool rf_linked(int32_t fa, int32_t fb) {
   return dx * dx + dy * dy < 9;
 }
 
-__global__ __launch_bounds__(256) void k_rf_init(int32_t *parent, int32_t *size, uint32_t *flag, int W, int H) {
+// Parents start as the start of each pixel's linked run within its wave
+// (64 consecutive pixels of one row, found with a ballot: no atomics), the
+// run start itself and unkept pixels as their own parent; parent <= index.
+__global__ __launch_bounds__(256) void k_rf_init(const int32_t *flow, const uint8_t *keep, int32_t *parent,
+                                                 int32_t *size, uint32_t *flag, int W, int H) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
+  const int lane = threadIdx.x & 63;
   const int k = y * W + x;
-  parent[k] = k;
+  const bool in = x < W && y < H;
+  const bool hl = in && lane > 0 && keep[k] && keep[k - 1] && rf_linked(flow[k], flow[k - 1]);
+  const unsigned long long starts = __ballot(!hl);  // lane 0 always starts a run
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const int start = 63 - __clzll(starts & upto);
+  if (!in) return;
+  parent[k] = k - (lane - start);
   size[k] = 0;
   flag[k] = 0;
 }
@@ -75,6 +85,26 @@ __device__ __forceinline__ void rf_union(int32_t *parent, int a, int b) {
   }
 }
 
+// Unions of the links the initial runs do not hold: a horizontal link into
+// the previous wave's pixels, and a vertical link unless the left
+// neighbour's vertical link already implies it (both rows' runs go on).
+__global__ __launch_bounds__(256) void k_rf_union(const int32_t *flow, const uint8_t *keep, int32_t *parent, int W,
+                                                  int H) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int k = y * W + x;
+  const bool on = x < W && y < H && keep[k] != 0;
+  int32_t f = 0;
+  if (on) f = flow[k];
+  const bool hl = on && x > 0 && keep[k - 1] && rf_linked(f, flow[k - 1]);
+  const bool below = on && y + 1 < H && keep[k + W] != 0;
+  const bool vl = below && rf_linked(f, flow[k + W]);
+  const bool hlb = below && x > 0 && keep[k + W - 1] && rf_linked(flow[k + W], flow[k + W - 1]);
+  const bool vl_left = __shfl_up(vl, 1);
+  if (hl && lane == 0) rf_union(parent, k, k - 1);
+  if (vl && !(lane > 0 && hl && hlb && vl_left)) rf_union(parent, k, k + W);
+}
+
 // After the unions: every pixel's parent becomes its root.
 __global__ __launch_bounds__(256) void k_rf_flatten(int32_t *parent, int W, int H) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
@@ -82,18 +112,6 @@ __global__ __launch_bounds__(256) void k_rf_flatten(int32_t *parent, int W, int 
   const int k = y * W + x;
   const int r = rf_find(parent, k);
   if (r != k) atomicMin(parent + k, r);
-}
-
-// Unions of every kept pixel with its right and lower neighbours.
-__global__ __launch_bounds__(256) void k_rf_union(const int32_t *flow, const uint8_t *keep, int32_t *parent, int W,
-                                                  int H) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= W || y >= H) return;
-  const int k = y * W + x;
-  if (!keep[k]) return;
-  const int32_t f = flow[k];
-  if (x + 1 < W && keep[k + 1] && rf_linked(f, flow[k + 1])) rf_union(parent, k, k + 1);
-  if (y + 1 < H && keep[k + W] && rf_linked(f, flow[k + W])) rf_union(parent, k, k + W);
 }
 
 // Region sizes, and whether a region borders a removed outlier it could
@@ -162,7 +180,7 @@ hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const
   uint32_t *flag = reinterpret_cast<uint32_t *>(size + N);
   const int32_t *f = reinterpret_cast<const int32_t *>(flow);
   const dim3 grid((W + 255) / 256, H), block(256);
-  hipLaunchKernelGGL(k_rf_init, grid, block, 0, stream, parent, size, flag, W, H);
+  hipLaunchKernelGGL(k_rf_init, grid, block, 0, stream, f, keep, parent, size, flag, W, H);
   hipLaunchKernelGGL(k_rf_union, grid, block, 0, stream, f, keep, parent, W, H);
   hipLaunchKernelGGL(k_rf_flatten, grid, block, 0, stream, parent, W, H);
   hipLaunchKernelGGL(k_rf_measure, grid, block, 0, stream, f, cost, keep, parent, size, flag, W, H);
