@@ -182,7 +182,8 @@ ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, 
  * keep_in) = keep_in minus the deleted regions.  Full-resolution flow
  * [H][W][2], cost [H][W].  scratch: device, at least
  * ff_region_filter_scratch_bytes(W, H) bytes (FF_ERR_WORKSPACE otherwise),
- * 4-byte aligned, contents on return unspecified; s >= 0. */
+ * 4-byte aligned (FF_ERR_ARG otherwise), contents on return unspecified;
+ * s >= 0. */
 size_t ff_region_filter_scratch_bytes(int32_t W, int32_t H);
 ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W, int32_t H,
                            int32_t s, void *scratch, size_t scratch_bytes, uint8_t *keep_out, void *stream);

@@ -379,6 +379,7 @@ ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint
                            int32_t s, void *scratch, size_t scratch_bytes, uint8_t *keep_out, void *stream) {
   if (!flow || !cost || !keep_in || !keep_out || !dims_ok(W, H) || s < 0 || keep_in == keep_out) return FF_ERR_ARG;
   if (!scratch || scratch_bytes < ffh::region_filter_scratch_bytes(W, H)) return FF_ERR_WORKSPACE;
+  if ((uintptr_t)scratch & 3) return FF_ERR_ARG;  // 32-bit atomics on the parents and counters
   return from_hip(ffh::launch_region_filter(flow, cost, keep_in, W, H, s, scratch, keep_out, (hipStream_t)stream));
 }
 

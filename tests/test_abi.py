@@ -84,6 +84,8 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_region_filter(fake, fake, fake, 10, 5, 3, fake, 600, fake, None) == ffi.FF_ERR_ARG  # in place
     assert lib.ff_region_filter(fake, fake, fake, 10, 5, 3, fake, 599, C.c_void_p(0x2000), None) == \
         ffi.FF_ERR_WORKSPACE
+    assert lib.ff_region_filter(fake, fake, fake, 10, 5, 3, C.c_void_p(0x3002), 600, C.c_void_p(0x2000), None) == \
+        ffi.FF_ERR_ARG  # misaligned scratch
     # bad Flow Fields+ schedules
     for kw in ({"plus_iters": -1}, {"plus_iters": 60, "iters": 6}, {"Rp_num": -2}, {"fine_iters": 65},
                {"fine_iters": -1}, {"Rp_num": (1 << 20) + 1}):
