@@ -221,3 +221,24 @@ def test_region_filter_bit_exact_on_oracle_fields():
         got = ff.region_filter(dev(o["flow_fwd"]), dev(o["cost_fwd"].view(np.int32)), dev(o["keep_fwd"]), s)
         assert np.array_equal(host(got), exp), s
         assert exp.sum() < o["keep_fwd"].sum()
+
+
+@pytest.mark.parametrize("sched", [SCHEDULES[0], SCHEDULES[1]])
+def test_plus_graph_replay_repeats_eager_results(sched):
+    """A HIP-graph capture of a Flow Fields+ call replays the eager results,
+    with eager work of its own between the replays."""
+    p = make_pair(1)
+    prm = _params(1, sched)
+    H, W = p.img1.shape
+    f = ff.FlowFields(W, H, prm)
+    i1, i2 = dev(p.img1), dev(p.img2)
+    eager = {k: host(v).copy() for k, v in f(i1, i2).items()}
+    f.capture(i1, i2)
+    for rep in range(3):
+        for k in ("flow_fwd", "cost_fwd", "keep_fwd", "n_evals"):
+            f.out[k].fill_(5)
+        ff.flow_fields(i2, i1, prm)
+        torch.cuda.synchronize()
+        got = {k: host(v).copy() for k, v in f.replay().items()}
+        for k in eager:
+            assert np.array_equal(got[k], eager[k]), (rep, k)

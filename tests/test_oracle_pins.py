@@ -760,3 +760,21 @@ def test_region_filter_hand_worked():
     assert oracle.region_filter(flow, cost, keep, 2).tolist() == [[1, 1, 0, 1]]
     cost[0, 2] = UNSET  # an UNSET pixel is no removed outlier
     assert oracle.region_filter(flow, cost, keep, 3).tolist() == [[1, 1, 0, 1]]
+
+
+def test_outlier_chain_masks_only_shrink():
+    """Consistency against one, then two backward fields, then the region
+    filter: each step keeps a subset of the previous mask; the sparse
+    samples are kept pixels, one per region at most."""
+    p = make_pair(1)
+    o1 = oracle.flow_fields(p.img1, p.img2, 3, 4, nthreads=4)
+    o2 = oracle.flow_fields(p.img2, p.img1, 3, 4, radius=2, seed=4321, nthreads=4)
+    k1 = o1["keep_fwd"]
+    k2 = oracle.consistency2(o1["flow_fwd"], o1["cost_fwd"], o1["flow_bwd"], o1["cost_bwd"], o2["flow_fwd"],
+                             o2["cost_fwd"])
+    k3 = oracle.region_filter(o1["flow_fwd"], o1["cost_fwd"], k2, 30)
+    assert np.all(k2 <= k1) and np.all(k3 <= k2) and k3.sum() > 0
+    sel = oracle.sparsify(o1["flow_fwd"], k3, o1["flow_bwd"], o2["flow_fwd"], 3, 1)
+    picked = sel[sel >= 0]
+    assert len(np.unique(picked)) == len(picked)
+    assert np.all(k3.ravel()[picked] == 1)
