@@ -15,7 +15,7 @@ import oracle
 import paper_1703_02563_amd as ff
 from ffgen import CONFIG_PARAMS, batch_shapes, make_pair, random_images
 from paper_1703_02563_amd.batch import BatchFlowFields
-from test_gpu_parity import _compare_full, as_u32, dev, host
+from test_gpu_parity import _compare_full, _random_level_state, as_u32, counter, dev, host, to_lib
 from test_learned_oracle import feature_canvas, feature_pyramid
 
 pytestmark = pytest.mark.gpu
@@ -242,3 +242,35 @@ def test_plus_graph_replay_repeats_eager_results(sched):
         got = {k: host(v).copy() for k, v in f.replay().items()}
         for k in eager:
             assert np.array_equal(got[k], eager[k]), (rep, k)
+
+
+@pytest.mark.parametrize("level,sched", [(0, (4, 2, 8, 0)), (0, (4, 2, 8, 4)), (1, (3, 2, 2, 1)), (2, (2, 3, 3, 0))])
+def test_run_level_plus_schedules_bit_exact(level, sched):
+    """ff_run_level from a consistent state under a Flow Fields+ / Fast
+    schedule equals the oracle's steps in the order Sec. 3.3 gives (Fast:
+    fine_iters steps at R when the scale is the finest)."""
+    P, Rp, T, Tf = sched
+    H, W = 61, 83
+    n = 1 << level
+    prm = ff.Params(levels=level + 1, iters=T, plus_iters=P, Rp_num=Rp, fine_iters=Tf)
+    ia, ib = random_images(870 + level, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    flow, cost = _random_level_state(5 + level, H, W, n)
+    for j, i in zip(*np.nonzero(cost != oracle.UNSET)):
+        cost[j, i] = oracle.cost(Da, Db, n, 3, i * n, j * n, int(flow[j, i, 0]), int(flow[j, i, 1]))
+    Pl, Tl = (0, Tf) if level == 0 and Tf > 0 else (P, T)
+    ef, ec, ne = flow, cost, 0
+    for t in range(Pl + Tl):
+        ef, ec, k = oracle.propagate(Da, Db, n, t, ef, ec, nthreads=NT)
+        ne += k
+        if t != Pl - 1 and t != Pl + Tl - 1:
+            Rn = oracle.rs_radius(n, Rp, 1) if t < Pl else oracle.rs_radius(n, 1, 1)
+            ef, ec, k = oracle.random_search(Da, Db, n, Rn, prm.seed, 0, level, t, ef, ec, nthreads=NT)
+            ne += k
+    gf, gc = dev(flow), dev(cost.view(np.int32))
+    cnt = counter()
+    ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, prm, 0, 0, gf, gc, n_evals=cnt)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ne
