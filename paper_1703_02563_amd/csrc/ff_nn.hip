@@ -38,10 +38,12 @@ constexpr int kQB = 2;                // 32-query blocks per wave (B operand reu
 constexpr int kWaves = 4;
 constexpr int kNbPad = (1 << 20) - 1;
 
+// Also clears the direction's NN keys (M <= N cells) for k_nn's atomicMin.
 __global__ __launch_bounds__(256) void k_nn_norms(ffh::NNArgs a) {
   const ffh::NNDir d = a.dir[blockIdx.y];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int Npad = (a.N + 31) & ~31;
+  if (idx < a.M) d.keys[idx] = ~0ull;
   if (idx >= Npad) return;
   int s = kNbPad;
   if (idx < a.N) {
@@ -340,11 +342,8 @@ static int nn_chunk_tiles(int ntiles, int per_chunk_wgs) {
 hipError_t launch_nn(const NNArgs &args_in, hipStream_t stream) {
   NNArgs args = args_in;
   const int Npad = (args.N + 31) & ~31;
+  // norms of the references; the same launch clears the keys (M <= N <= Npad)
   hipLaunchKernelGGL(k_nn_norms, dim3((Npad + 255) / 256, args.ndir), dim3(256), 0, stream, args);
-  for (int k = 0; k < args.ndir; ++k) {
-    hipError_t e = launch_fill_u64(args.dir[k].keys, ~0ull, args.M, stream);
-    if (e != hipSuccess) return e;
-  }
   const int ntiles = Npad / 32;
   const int nqb = nn_qblocks(args.M);
   args.chunk_tiles = nn_chunk_tiles(ntiles, nqb * args.ndir);

@@ -193,11 +193,17 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
   ffk::wave_count_add(d.n_evals, cnt);
 }
 
-__global__ __launch_bounds__(256) void k_consistency(const int32_t *fa, const uint32_t *ca, const int32_t *fb,
-                                                     const uint32_t *cb, int W, int H, double eps2,
-                                                     uint8_t *keep) {
+// blockIdx.z = 1 runs the check with the roles of the two fields swapped
+// (the mask of field b), in the same launch.
+__global__ __launch_bounds__(256) void k_consistency(const int32_t *fa0, const uint32_t *ca0, const int32_t *fb0,
+                                                     const uint32_t *cb0, int W, int H, double eps2,
+                                                     uint8_t *keep_a, uint8_t *keep_b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= W || y >= H) return;
+  const bool swap = blockIdx.z == 1;
+  const int32_t *fa = swap ? fb0 : fa0, *fb = swap ? fa0 : fb0;
+  const uint32_t *ca = swap ? cb0 : ca0, *cb = swap ? ca0 : cb0;
+  uint8_t *keep = swap ? keep_b : keep_a;
   const size_t k = (size_t)y * W + x;
   uint8_t out = 0;
   if (ca[k] != kUnset) {
@@ -393,13 +399,10 @@ hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int1
 
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W,
                               int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream) {
-  dim3 grid((W + 255) / 256, H);
+  dim3 grid((W + 255) / 256, H, keep_b ? 2 : 1);
   const double eps2 = (double)eps * (double)eps;
   hipLaunchKernelGGL(k_consistency, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
-                     reinterpret_cast<const int32_t *>(fb), cb, W, H, eps2, keep_a);
-  if (keep_b)
-    hipLaunchKernelGGL(k_consistency, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fb), cb,
-                       reinterpret_cast<const int32_t *>(fa), ca, W, H, eps2, keep_b);
+                     reinterpret_cast<const int32_t *>(fb), cb, W, H, eps2, keep_a, keep_b);
   return hipGetLastError();
 }
 
