@@ -53,7 +53,7 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10568.1 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
+TRAFFIC_BYTES = 10568.0 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
 TRAFFIC_SOURCES_SHA = "c1c65354e256ed3d"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
