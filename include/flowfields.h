@@ -423,7 +423,10 @@ size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);
  * params: host pointer.  ws: device workspace of ff_workspace_bytes bytes.
  * flow_fwd/flow_bwd: [H][W][2]; cost_fwd/cost_bwd: [H][W];
  * keep_fwd/keep_bwd: [H][W] (keep_bwd nullable);
- * n_evals: nullable uint64 [2], evaluations per direction (overwritten). */
+ * n_evals: nullable uint64 [2], evaluations per direction (overwritten).
+ * Forward field only: flow_bwd, cost_bwd, keep_fwd and keep_bwd all NULL
+ * (no backward field, no masks; n_evals[1] = 0); only some of them NULL is
+ * FF_ERR_ARG. */
 ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, int32_t H,
                          const ff_params *params, void *ws, size_t ws_bytes, int16_t *flow_fwd,
                          int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd,

@@ -941,9 +941,12 @@ size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params) {
 ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, int32_t H, const ff_params *params,
                          void *ws, size_t ws_bytes, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd,
                          uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals, void *stream) {
-  if (!img1 || !img2 || !ws || !flow_fwd || !flow_bwd || !cost_fwd || !cost_bwd || !keep_fwd || !nn_dims_ok(W, H) ||
-      !params_ok(params) || !(params->eps >= 0.0f))
+  // forward field only: every backward output and both masks NULL
+  const bool fwd_only = !flow_bwd && !cost_bwd && !keep_fwd && !keep_bwd;
+  if (!img1 || !img2 || !ws || !flow_fwd || !cost_fwd || (!fwd_only && (!flow_bwd || !cost_bwd || !keep_fwd)) ||
+      !nn_dims_ok(W, H) || !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
+  const int nd = fwd_only ? 1 : 2;  // directions computed
   const Layout lay = layout(W, H, params);
   if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
@@ -995,14 +998,14 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   uint64_t *keys = reinterpret_cast<uint64_t *>(base + lay.keys);
   int32_t *nb = reinterpret_cast<int32_t *>(base + lay.nb);
   ffh::NNArgs nn{};
-  nn.ndir = 2;
+  nn.ndir = nd;
   nn.W = W;
   nn.H = H;
   nn.nc = nc;
   nn.Wc = ceil_div(W, nc);
   nn.M = (int)lay.M;
   nn.N = (int)lay.N;
-  for (int dr = 0; dr < 2; ++dr)
+  for (int dr = 0; dr < nd; ++dr)
     nn.dir[dr] = {desc1[dr], desc1[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
 
@@ -1012,13 +1015,13 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     uint32_t *scost[kMaxLevels][2];
     carve_second_grids(base, lay.sgrids, W, H, L, sflow, scost);
     ffh::LevelKArgs k{};
-    k.ndir = 2;
-    for (int dr = 0; dr < 2; ++dr) {
+    k.ndir = nd;
+    for (int dr = 0; dr < nd; ++dr) {
       k.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
       k.dir[dr].stream_id = dr;
     }
     for (int lv = L - 1; lv >= 0; --lv) {
-      for (int dr = 0; dr < 2; ++dr) {
+      for (int dr = 0; dr < nd; ++dr) {
         k.dir[dr].Da = desc[dr][lv];
         k.dir[dr].Db = desc[dr ^ 1][lv];
         k.dir[dr].flow = gflow[lv][dr];
@@ -1029,8 +1032,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       }
       if (ffh::level_stepwise(lv)) {
         ffh::LevelArgs a{};
-        a.ndir = 2;
-        for (int dr = 0; dr < 2; ++dr) {
+        a.ndir = nd;
+        for (int dr = 0; dr < nd; ++dr) {
           const ffh::LevelKDir &kd = k.dir[dr];
           a.dir[dr] = {kd.Da, kd.Db, kd.flow, kd.cost, kd.cflow, kd.ccost, kd.nn_key, desc1[dr], kd.n_evals, dr};
         }
@@ -1041,22 +1044,23 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       if ((e = run_level_blocked(k, W, H, lv, params, mode, s, sflow[lv], scost[lv])) != hipSuccess)
         return FF_ERR_LAUNCH;
     }
+    if (fwd_only) return FF_OK;
     return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                             keep_bwd, s));
   }
 
   ffh::LevelArgs a{};
-  a.ndir = 2;
+  a.ndir = nd;
   a.W = W;
   a.H = H;
   a.radius = r;
   a.seed = params->seed;
-  for (int dr = 0; dr < 2; ++dr) {
+  for (int dr = 0; dr < nd; ++dr) {
     a.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
     a.dir[dr].stream_id = dr;
   }
   for (int lv = L - 1; lv >= 0; --lv) {
-    for (int dr = 0; dr < 2; ++dr) {
+    for (int dr = 0; dr < nd; ++dr) {
       a.dir[dr].Da = desc[dr][lv];
       a.dir[dr].Db = desc[dr ^ 1][lv];
       a.dir[dr].flow = gflow[lv][dr];
@@ -1068,6 +1072,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     }
     if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
+  if (fwd_only) return FF_OK;
   return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                           keep_bwd, s));
 }

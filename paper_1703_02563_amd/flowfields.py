@@ -207,7 +207,7 @@ def flow_fields_two_backward(img1, img2, params: Params, seed2: int | None = Non
     out = flow_fields(img1, img2, params)
     p2 = dataclasses.replace(params, seed=params.seed + 1 if seed2 is None else seed2,
                              radius=params.radius if radius2 is None else radius2)
-    o2 = flow_fields(img2, img1, p2)
+    o2 = flow_fields(img2, img1, p2, backward=False)
     out["keep_fwd"] = consistency_filter2(out["flow_fwd"], out["cost_fwd"], out["flow_bwd"], out["cost_bwd"],
                                           o2["flow_fwd"], o2["cost_fwd"], params.eps)
     out["flow_bwd2"], out["cost_bwd2"] = o2["flow_fwd"], o2["cost_fwd"]
@@ -255,8 +255,10 @@ def workspace_bytes(W: int, H: int, params: Params) -> int:
 class FlowFields:
     """Reusable buffers for repeated ff_flow_fields calls on one frame size."""
 
-    def __init__(self, W: int, H: int, params: Params, device="cuda"):
-        self.W, self.H, self.params = W, H, params
+    def __init__(self, W: int, H: int, params: Params, device="cuda", backward: bool = True):
+        """backward=False: the forward field only (flow_fwd, cost_fwd,
+        n_evals[0]); no backward field and no consistency masks."""
+        self.W, self.H, self.params, self.backward = W, H, params, backward
         self._cp = params.to_c()
         nbytes = int(lib().ff_workspace_bytes(W, H, self._cp))
         if nbytes == 0:
@@ -272,6 +274,9 @@ class FlowFields:
             "keep_bwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
             "n_evals": torch.zeros(2, dtype=torch.int64, device=dev),
         }
+        if not backward:
+            for k in ("flow_bwd", "cost_bwd", "keep_fwd", "keep_bwd"):
+                del self.out[k]
 
     def capture(self, img1: torch.Tensor, img2: torch.Tensor):
         """Records one call on these input buffers into a HIP graph
@@ -301,15 +306,17 @@ class FlowFields:
             raise ValueError("image shape does not match")
         o = self.out
         check(lib().ff_flow_fields(_ptr(img1, torch.uint8, "img1"), _ptr(img2, torch.uint8, "img2"), self.W, self.H,
-                                   self._cp, _ptr(self.ws), self.ws.numel(), _ptr(o["flow_fwd"]), _ptr(o["flow_bwd"]),
-                                   _ptr(o["cost_fwd"]), _ptr(o["cost_bwd"]), _ptr(o["keep_fwd"]),
-                                   _ptr(o["keep_bwd"]), _ptr(o["n_evals"]), _stream()), "ff_flow_fields")
+                                   self._cp, _ptr(self.ws), self.ws.numel(), _ptr(o["flow_fwd"]),
+                                   _ptr(o.get("flow_bwd")), _ptr(o["cost_fwd"]), _ptr(o.get("cost_bwd")),
+                                   _ptr(o.get("keep_fwd")), _ptr(o.get("keep_bwd")), _ptr(o["n_evals"]), _stream()),
+              "ff_flow_fields")
         return o
 
 
-def flow_fields(img1: torch.Tensor, img2: torch.Tensor, params: Params | None = None) -> dict:
-    """Forward and backward Flow Fields of one pair plus consistency masks."""
+def flow_fields(img1: torch.Tensor, img2: torch.Tensor, params: Params | None = None, backward: bool = True) -> dict:
+    """Forward and backward Flow Fields of one pair plus consistency masks
+    (backward=False: the forward field only)."""
     params = params or Params()
     H, W = img1.shape
-    ff = FlowFields(W, H, params, device=img1.device)
+    ff = FlowFields(W, H, params, device=img1.device, backward=backward)
     return {k: v for k, v in ff(img1, img2).items()}

@@ -61,6 +61,11 @@ def test_bad_arguments_return_before_any_launch():
     # NULL image
     assert lib.ff_flow_fields(None, fake, 64, 64, C.byref(p), fake, 1 << 30, fake, fake, fake, fake, fake, None,
                               None, None) == ffi.FF_ERR_ARG
+    # backward outputs only partly NULL (all NULL is the forward-only mode)
+    assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 1 << 30, fake, None, fake, fake, fake, None,
+                              None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 1 << 30, fake, None, fake, None, fake, None,
+                              None, None) == ffi.FF_ERR_ARG
     # too small a workspace
     assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 16, fake, fake, fake, fake, fake, None, None,
                               None) == ffi.FF_ERR_WORKSPACE

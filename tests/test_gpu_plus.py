@@ -274,3 +274,25 @@ def test_run_level_plus_schedules_bit_exact(level, sched):
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
+
+
+@pytest.mark.parametrize("radius,stepwise", [(3, False), (3, True), (2, False)])
+def test_forward_only_equals_the_forward_part(radius, stepwise):
+    """ff_flow_fields with every backward output NULL gives the full call's
+    forward field, cost and evaluation count (blocked, step-wise and
+    per-step radius paths)."""
+    p = make_pair(1)
+    c = CONFIG_PARAMS[1]
+    prm = ff.Params(levels=c.levels, iters=c.iters, radius=radius, seed=c.seed)
+    sv = ff.level_variants()
+    try:
+        if stepwise:
+            ff.set_level_variants([int(ff.lib().ff_level_variant_count()) - 1] * 7)
+        full = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+        fwd = ff.flow_fields(dev(p.img1), dev(p.img2), prm, backward=False)
+    finally:
+        ff.set_level_variants(sv)
+    assert set(fwd) == {"flow_fwd", "cost_fwd", "n_evals"}
+    assert torch.equal(fwd["flow_fwd"], full["flow_fwd"]) and torch.equal(fwd["cost_fwd"], full["cost_fwd"])
+    ne = host(fwd["n_evals"])
+    assert int(ne[0]) == int(host(full["n_evals"])[0]) and int(ne[1]) == 0
