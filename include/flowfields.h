@@ -188,6 +188,20 @@ size_t ff_region_filter_scratch_bytes(int32_t W, int32_t H);
 ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W, int32_t H,
                            int32_t s, void *scratch, size_t scratch_bytes, uint8_t *keep_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the region
+ * filter of ff_region_filter with no scratch argument.  Its scratch is a
+ * static device array of the library, 24 MiB per GPU the library runs on,
+ * held until the process ends; the call itself allocates nothing.  W * H
+ * must not exceed ff_region_filter_noalloc_max_pixels() (2,097,152 pixels):
+ * larger images return FF_ERR_WORKSPACE before anything is enqueued; other
+ * argument errors as ff_region_filter.  Results equal ff_region_filter's.
+ * All calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (two streams, two threads) race and must be serialised by the caller. */
+size_t ff_region_filter_noalloc_max_pixels(void);
+ff_status ff_region_filter_noalloc(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W,
+                                   int32_t H, int32_t s, uint8_t *keep_out, void *stream);
+
 /* Sparsification (Sec. 3.8): for every q x q region of the filtered field
  * a (regions anchored at (0, 0), ragged at the right and bottom; sel is
  * int32 [ceil(H/q)][ceil(W/q)]), sel = y * W + x of the kept sample

@@ -383,6 +383,15 @@ ff_status ff_region_filter(const int16_t *flow, const uint32_t *cost, const uint
   return from_hip(ffh::launch_region_filter(flow, cost, keep_in, W, H, s, scratch, keep_out, (hipStream_t)stream));
 }
 
+size_t ff_region_filter_noalloc_max_pixels(void) { return ffh::region_filter_noalloc_max_pixels(); }
+
+ff_status ff_region_filter_noalloc(const int16_t *flow, const uint32_t *cost, const uint8_t *keep_in, int32_t W,
+                                   int32_t H, int32_t s, uint8_t *keep_out, void *stream) {
+  if (!flow || !cost || !keep_in || !keep_out || !dims_ok(W, H) || s < 0 || keep_in == keep_out) return FF_ERR_ARG;
+  if ((size_t)W * H > ffh::region_filter_noalloc_max_pixels()) return FF_ERR_WORKSPACE;
+  return from_hip(ffh::launch_region_filter_noalloc(flow, cost, keep_in, W, H, s, keep_out, (hipStream_t)stream));
+}
+
 ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_t *flow_b1, const int16_t *flow_b2,
                       int32_t W, int32_t H, int32_t q, int32_t e, int32_t *sel, void *stream) {
   if (!flow_a || !keep_a || !flow_b1 || !sel || !dims_ok(W, H) || q < 1 || q > 64 || e < 0) return FF_ERR_ARG;

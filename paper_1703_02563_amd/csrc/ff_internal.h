@@ -223,7 +223,12 @@ hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t
 // Consistency of field a against field b (full resolution).
 size_t region_filter_scratch_bytes(int W, int H);
 hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep, int W, int H, int s,
-                                void *scratch, uint8_t *keep_out, hipStream_t stream);
+                                void *work, uint8_t *keep_out, hipStream_t stream);
+// The same with the library's static per-device scratch (W * H at most
+// region_filter_noalloc_max_pixels()).
+size_t region_filter_noalloc_max_pixels();
+hipError_t launch_region_filter_noalloc(const int16_t *flow, const uint32_t *cost, const uint8_t *keep, int W, int H,
+                                        int s, uint8_t *keep_out, hipStream_t stream);
 hipError_t launch_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t *fb1, const int16_t *fb2, int W,
                            int H, int q, int e, int32_t *sel, hipStream_t stream);
 hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,

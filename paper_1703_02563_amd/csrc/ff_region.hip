@@ -16,6 +16,8 @@
 // is set to its root, so the later passes find roots in one step.  Parents
 // are read with device-scope atomic loads (no stale copies in a compute
 // unit's cache).
+#include <mutex>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -173,9 +175,9 @@ namespace ffh {
 size_t region_filter_scratch_bytes(int W, int H) { return (size_t)W * H * 3 * sizeof(int32_t); }
 
 hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const uint8_t *keep, int W, int H, int s,
-                                void *scratch, uint8_t *keep_out, hipStream_t stream) {
+                                void *work, uint8_t *keep_out, hipStream_t stream) {
   const size_t N = (size_t)W * H;
-  int32_t *parent = static_cast<int32_t *>(scratch);
+  int32_t *parent = static_cast<int32_t *>(work);
   int32_t *size = parent + N;
   uint32_t *flag = reinterpret_cast<uint32_t *>(size + N);
   const int32_t *f = reinterpret_cast<const int32_t *>(flow);
@@ -186,6 +188,52 @@ hipError_t launch_region_filter(const int16_t *flow, const uint32_t *cost, const
   hipLaunchKernelGGL(k_rf_measure, grid, block, 0, stream, f, cost, keep, parent, size, flag, W, H);
   hipLaunchKernelGGL(k_rf_apply, grid, block, 0, stream, keep, parent, size, flag, W, H, s, keep_out);
   return hipGetLastError();
+}
+
+}  // namespace ffh
+
+// ---- the region filter without caller-provided scratch ----------------------
+// Parents, sizes and flags of up to kNoAllocMaxPixels pixels live in a
+// static device array.  Its name in host code is only a host-side stand-in:
+// the device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is handed
+// to the kernels.  Every call on one device shares its copy (k_rf_init
+// rewrites all of it that a call reads: parents, sizes and flags), so calls
+// that overlap on one device race.
+
+namespace {
+
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 21;  // 2,097,152 pixels (1920 x 1080 fits): 24 MiB
+static __device__ __align__(256) int32_t scratch[3 * kNoAllocMaxPixels];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (nullptr on error).
+void *noalloc_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+namespace ffh {
+
+size_t region_filter_noalloc_max_pixels() { return kNoAllocMaxPixels; }
+
+hipError_t launch_region_filter_noalloc(const int16_t *flow, const uint32_t *cost, const uint8_t *keep, int W, int H,
+                                        int s, uint8_t *keep_out, hipStream_t stream) {
+  void *work = noalloc_scratch();
+  if (!work) return hipErrorInvalidDevicePointer;
+  return launch_region_filter(flow, cost, keep, W, H, s, work, keep_out, stream);
 }
 
 }  // namespace ffh

@@ -58,6 +58,8 @@ _SIGS = {
     "ff_sparsify": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P]),
     "ff_region_filter_scratch_bytes": (C.c_size_t, [_I32, _I32]),
     "ff_region_filter": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, C.c_size_t, _P, _P]),
+    "ff_region_filter_noalloc_max_pixels": (C.c_size_t, []),
+    "ff_region_filter_noalloc": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
     "ff_run_level": (C.c_int, [_P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P, _P, _P,
                                C.c_size_t, _P, _P]),

@@ -154,3 +154,18 @@ def test_level_launches_follow_the_run_length_table():
     finally:
         lib.ff_set_level_passes(1, 0, old)
     assert lib.ff_level_launches(0, 1, 0) == -1 and lib.ff_level_launches(6, 9, 0) == -1
+
+
+def test_noalloc_region_filter_validation():
+    """Sizes beyond the static scratch array and bad arguments return before
+    anything is enqueued."""
+    lib = ffi.lib()
+    fake = C.c_void_p(0x1000)
+    out = C.c_void_p(0x2000)
+    maxpx = int(lib.ff_region_filter_noalloc_max_pixels())
+    assert maxpx == 1 << 21
+    assert lib.ff_region_filter_noalloc(fake, fake, fake, 2049, 1024, 3, out, None) == ffi.FF_ERR_WORKSPACE
+    assert lib.ff_region_filter_noalloc(fake, fake, fake, 10, 5, -1, out, None) == ffi.FF_ERR_ARG
+    assert lib.ff_region_filter_noalloc(fake, fake, fake, 10, 5, 3, fake, None) == ffi.FF_ERR_ARG  # in place
+    assert lib.ff_region_filter_noalloc(None, fake, fake, 10, 5, 3, out, None) == ffi.FF_ERR_ARG
+    assert lib.ff_region_filter_noalloc(fake, fake, fake, 0, 5, 3, out, None) == ffi.FF_ERR_ARG
