@@ -189,6 +189,38 @@ def test_init_coarse_flow_is_target_minus_pixel():
             assert 0 <= i * nc + flow[j, i, 0] < 27 and 0 <= j * nc + flow[j, i, 1] < 21
 
 
+@pytest.mark.parametrize("nc", [4, 8])
+def test_init_coarse_cost_is_the_scale_nc_cost(nc):
+    """The seed cost is E_nc (Eq. 4 ranks the candidates with the cost of
+    the coarsest scale): on cells whose pixel and target are 6 nc inside
+    the image it equals the 13 x 13 weighted sum over the scale-nc blurred
+    images, which is not the sum over the level-1 blurred images."""
+    H, W, pad, t = 14 * nc + 16, 16 * nc + 20, 12, (3, -2)
+    big, _ = random_images(70 + nc, H + 2 * pad, W + 2 * pad)
+    ia = big[pad:pad + H, pad:pad + W].copy()
+    ib = big[pad - t[1]:pad - t[1] + H, pad - t[0]:pad - t[0] + W].copy()
+    ib = np.clip(ib.astype(int) + np.random.default_rng(nc).integers(-6, 7, ib.shape), 0, 255).astype(np.uint8)
+    B1a, B1b = oracle.blur(ia, 1), oracle.blur(ib, 1)
+    Bca, Bcb = oracle.blur(ia, nc), oracle.blur(ib, nc)
+    Da1, Db1 = oracle.descriptor(B1a, 1), oracle.descriptor(B1b, 1)
+    Dac, Dbc = oracle.descriptor(Bca, nc), oracle.descriptor(Bcb, nc)
+    idx, _ = oracle.nn(Da1, Db1, nc, nthreads=2)
+    flow, cost, _ = oracle.init_coarse(idx, Dac, Dbc, nc)
+    Hc, Wc = idx.shape
+    lo = 6 * nc
+    checked = differs = 0
+    for j in range(Hc):
+        for i in range(Wc):
+            p = (i * nc, j * nc)
+            q = (p[0] + int(flow[j, i, 0]), p[1] + int(flow[j, i, 1]))
+            if not all(lo <= v < hi - lo for v, hi in ((p[0], W), (p[1], H), (q[0], W), (q[1], H))):
+                continue
+            checked += 1
+            assert cost[j, i] == _weighted_13x13(Bca, Bcb, nc, p, q), (i, j)
+            differs += cost[j, i] != _weighted_13x13(B1a, B1b, 1, p, q)
+    assert checked >= 4 and differs == checked
+
+
 # ---------------------------------------------------------------- level seeding (Sec. 3.2)
 
 def test_seed_level_keeps_shared_pixels_and_unsets_others():
@@ -244,6 +276,59 @@ def test_propagation_spreads_into_its_quadrant(d):
     # flow it has just taken and is skipped
     assert ne == 5
     assert np.all(flow2 == 0)
+
+
+def _tie_case(b_values):
+    """A 24 x 24 level-1 case in which image b's descriptors are constant per
+    vertical band (b_values: band of x < 12, band of x >= 12), so E_1 of a
+    target depends only on the band its patch falls in."""
+    ia, _ = random_images(77, 24, 24)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = np.empty_like(Da)
+    Db[:, :12] = b_values[0]
+    Db[:, 12:] = b_values[1]
+    return Da, Db
+
+
+def _step_from(Da, Db, cell_state):
+    """Propagation step 0 (sources: left and top) from a grid in which only
+    the given cells are set; returns the flow of cell (11, 10) (odd, first
+    half-sweep) and the step's evaluation count."""
+    flow = np.zeros((24, 24, 2), np.int16)
+    cost = np.full((24, 24), UNSET, np.uint32)
+    for (i, j), f in cell_state.items():
+        flow[j, i] = f
+        cost[j, i] = oracle.cost(Da, Db, 1, 3, i, j, f[0], f[1])
+    f2, c2, ne = oracle.propagate(Da, Db, 1, 0, flow, cost)
+    return tuple(int(v) for v in f2[10, 11]), int(c2[10, 11]), ne
+
+
+def test_propagation_ties_prefer_horizontal_then_keep_own():
+    """Sec. 4.4 remarks that propagation prefers the horizontal source when
+    matching errors are identical; a candidate replaces the held flow only
+    if strictly better (Eq. 2).  Cell (11, 10) reads its left source
+    (10, 10) and its top source (11, 9); both targets lie in the same
+    band of image b (equal errors) or in different bands (strict order)."""
+    fh, fv = (-8, 2), (-9, -4)  # both targets of cell (11, 10) in the band x < 12
+    Da, Db = _tie_case((100, 100))
+    # an UNSET cell with two equal candidates takes the horizontal one
+    got, c, _ = _step_from(Da, Db, {(10, 10): fh, (11, 9): fv})
+    assert got == fh and c == oracle.cost(Da, Db, 1, 3, 11, 10, *fh)
+    # a held flow of equal error stays (neither candidate is strictly lower)
+    got, _, _ = _step_from(Da, Db, {(10, 10): fh, (11, 9): fv, (11, 10): (-5, 1)})
+    assert got == (-5, 1)
+    # strict differences decide, whichever source holds the better flow:
+    # image b's band x >= 12 (the target of fr) matches worse, then better
+    fr = (4, 3)
+    for bands in ((100, 250), (250, 100)):
+        Da, Db = _tie_case(bands)
+        e_r = oracle.cost(Da, Db, 1, 3, 11, 10, *fr)
+        e_h = oracle.cost(Da, Db, 1, 3, 11, 10, *fh)
+        assert e_r != e_h
+        best = fr if e_r < e_h else fh
+        for h, v in ((fr, fh), (fh, fr)):  # the better flow on the horizontal, then the vertical source
+            got, c, _ = _step_from(Da, Db, {(10, 10): h, (11, 9): v})
+            assert got == best and c == min(e_r, e_h), (bands, h, v)
 
 
 def test_propagation_is_monotone_and_consistent():
