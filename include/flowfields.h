@@ -300,8 +300,8 @@ size_t ff_workspace_bytes_f32(int32_t W, int32_t H, const ff_params *params);
 /* The multi-scale Flow Fields schedule (Sec. 3.2) on learned features
  * instead of the byte descriptors: feat1[l], feat2[l] (host arrays of
  * `levels` device pointers) are float32 [H][W][16] feature maps of scale
- * 2^l.  The NN seed runs on the level-1 maps quantised to bytes (as
- * ff_quantize_u8) on int8 matrix cores; every other matching error is the
+ * 2^l.  The NN seed runs on the level-1 maps of both images quantised to
+ * bytes with one shared range (as ff_quantize_pair_u8) on int8 matrix cores; every other matching error is the
  * float32 squared-difference patch cost of ff_cost_f32_fwd.  Costs are
  * returned as the bit patterns of the float32 values (UNSET = 0xFFFFFFFF);
  * the rest as ff_flow_fields. */
@@ -387,8 +387,17 @@ size_t ff_quantize_scratch_bytes(void);
 
 /* Learned features to bytes for the matrix-core NN seed: with lo, hi the
  * minimum and maximum over all `count` values, q = clamp(rint((f - lo) *
- * (255 / (hi - lo))), 0, 255) in float32 (q = 0 if hi == lo). */
+ * (255 / (hi - lo))), 0, 255) in float32 (q = 0 if hi == lo).
+ * scratch: float, ff_quantize_scratch_bytes() bytes. */
 ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream);
+
+/* The same for the two images of a pair with ONE range: lo, hi over the
+ * 2 * count values of f1 and f2 together, both quantised with it, so equal
+ * feature values become equal bytes in both images and the byte-space
+ * nearest neighbour of the seed (Sec. 3.1) compares descriptors on one
+ * scale.  q1, q2: [count] outputs. */
+ff_status ff_quantize_pair_u8(const float *f1, const float *f2, int64_t count, float *scratch, uint8_t *q1,
+                              uint8_t *q2, void *stream);
 
 /* Launch configuration (tile size, workgroup size, load unrolling) of the
  * temporally blocked level kernel that ff_flow_fields uses for patch radius 3

@@ -60,6 +60,7 @@ def lib():
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
         L.or_cost_f32.restype = C.c_uint32
         L.or_quantize_u8.argtypes = [P, C.c_int64, P]
+        L.or_quantize_pair_u8.argtypes = [P, P, C.c_int64, P, P]
         L.or_flow_fields_f32.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields_f32.restype = i
         _lib = L
@@ -249,6 +250,16 @@ def quantize_u8(f) -> np.ndarray:
     q = np.empty(f.shape, np.uint8)
     lib().or_quantize_u8(_p(f), f.size, _p(q))
     return q
+
+
+def quantize_pair_u8(f1, f2):
+    """Both maps quantised to bytes with the range of their union."""
+    f1 = np.ascontiguousarray(f1, np.float32)
+    f2 = np.ascontiguousarray(f2, np.float32)
+    assert f1.shape == f2.shape
+    q1, q2 = np.empty(f1.shape, np.uint8), np.empty(f2.shape, np.uint8)
+    lib().or_quantize_pair_u8(_p(f1), _p(f2), f1.size, _p(q1), _p(q2))
+    return q1, q2
 
 
 def flow_fields_f32(F1, F2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,

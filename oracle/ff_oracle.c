@@ -174,18 +174,41 @@ static uint32_t cost_f32(const void *A, const void *B, int W, int H, int n, int 
 /* Learned features to bytes for the NN seed: with lo, hi the range of all
  * values, q = clamp(rint((f - lo) * (255 / (hi - lo))), 0, 255) in single
  * precision. */
-void or_quantize_u8(const float *f, int64_t count, uint8_t *q)
+static void quantize_range(const float *f, int64_t count, float lo, float hi, uint8_t *q)
 {
-    float lo = INFINITY, hi = -INFINITY;
-    for (int64_t i = 0; i < count; ++i) {
-        lo = fminf(lo, f[i]);
-        hi = fmaxf(hi, f[i]);
-    }
     float s = hi > lo ? 255.0f / (hi - lo) : 0.0f;
     for (int64_t i = 0; i < count; ++i) {
         float t = rintf((f[i] - lo) * s);
         q[i] = (uint8_t)fminf(fmaxf(t, 0.0f), 255.0f);
     }
+}
+
+static void value_range(const float *f, int64_t count, float *lo, float *hi)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        *lo = fminf(*lo, f[i]);
+        *hi = fmaxf(*hi, f[i]);
+    }
+}
+
+void or_quantize_u8(const float *f, int64_t count, uint8_t *q)
+{
+    float lo = INFINITY, hi = -INFINITY;
+    value_range(f, count, &lo, &hi);
+    quantize_range(f, count, lo, hi, q);
+}
+
+/* Both images' level-1 features with ONE range (lo, hi over both maps), so
+ * that equal feature values become equal bytes in both images and the
+ * byte-space nearest neighbour is taken on one scale (Sec. 3.1: the seed is
+ * the nearest neighbour in feature space). */
+void or_quantize_pair_u8(const float *f1, const float *f2, int64_t count, uint8_t *q1, uint8_t *q2)
+{
+    float lo = INFINITY, hi = -INFINITY;
+    value_range(f1, count, &lo, &hi);
+    value_range(f2, count, &lo, &hi);
+    quantize_range(f1, count, lo, hi, q1);
+    quantize_range(f2, count, lo, hi, q2);
 }
 
 /* Exact nearest neighbour (stands in for the kd-tree candidate set of
@@ -663,8 +686,7 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *q1 = (uint8_t *)malloc(np * 16), *q2 = (uint8_t *)malloc(np * 16);
-    or_quantize_u8(F1[0], (int64_t)np * 16, q1);
-    or_quantize_u8(F2[0], (int64_t)np * 16, q2);
+    or_quantize_pair_u8(F1[0], F2[0], (int64_t)np * 16, q1, q2);
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(cost_f32, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
                        R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);

@@ -656,7 +656,7 @@ static LayoutF32 layout_f32(int W, int H, const ff_params *p) {
   l.M = (size_t)ceil_div(W, nc) * ceil_div(H, nc);
   size_t off = 0;
   l.q = off; off = align256(off + 2 * l.N * 16);
-  l.qscratch = off; off = align256(off + 2 * ff_quantize_scratch_bytes());
+  l.qscratch = off; off = align256(off + ffh::quantize_scratch_bytes());
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
   l.grids = off;
@@ -701,13 +701,12 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
   char *base = static_cast<char *>(ws);
   hipError_t e;
   // bytes of the level-1 features for the matrix-core NN seed
+  // (one range over both images: equal feature values become equal bytes)
   uint8_t *q[2];
-  for (int im = 0; im < 2; ++im) {
-    q[im] = reinterpret_cast<uint8_t *>(base + lay.q) + (size_t)im * lay.N * 16;
-    float *qs = reinterpret_cast<float *>(base + lay.qscratch + im * ff_quantize_scratch_bytes());
-    if ((e = ffh::launch_quantize(im ? feat2[0] : feat1[0], (long long)lay.N * 16, qs, q[im], s)) != hipSuccess)
-      return FF_ERR_LAUNCH;
-  }
+  for (int im = 0; im < 2; ++im) q[im] = reinterpret_cast<uint8_t *>(base + lay.q) + (size_t)im * lay.N * 16;
+  if ((e = ffh::launch_quantize_pair(feat1[0], feat2[0], (long long)lay.N * 16,
+                                     reinterpret_cast<float *>(base + lay.qscratch), q[0], q[1], s)) != hipSuccess)
+    return FF_ERR_LAUNCH;
   uint64_t *evals = n_evals ? n_evals : reinterpret_cast<uint64_t *>(base + lay.evals);
   if ((e = ffh::launch_fill_u64(evals, 0, 2, s)) != hipSuccess) return FF_ERR_LAUNCH;
   int32_t *gflow[kMaxLevels][2];
@@ -907,11 +906,17 @@ ff_status ff_triplet_hinge(const float *cost, int32_t m, float margin, float sca
   return from_hip(ffh::launch_triplet_hinge(cost, m, margin, scale, weight, grad_cost, loss, (hipStream_t)stream));
 }
 
-size_t ff_quantize_scratch_bytes(void) { return (1024 + 1) * 2 * sizeof(float); }
+size_t ff_quantize_scratch_bytes(void) { return ffh::quantize_scratch_bytes(); }
 
 ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t *q, void *stream) {
   if (!f || !scratch || !q || count < 0) return FF_ERR_ARG;
   return from_hip(ffh::launch_quantize(f, count, scratch, q, (hipStream_t)stream));
+}
+
+ff_status ff_quantize_pair_u8(const float *f1, const float *f2, int64_t count, float *scratch, uint8_t *q1,
+                              uint8_t *q2, void *stream) {
+  if (!f1 || !f2 || !scratch || !q1 || !q2 || count < 0) return FF_ERR_ARG;
+  return from_hip(ffh::launch_quantize_pair(f1, f2, count, scratch, q1, q2, (hipStream_t)stream));
 }
 
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }

@@ -500,4 +500,20 @@ hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t
   return hipGetLastError();
 }
 
+// Two maps with the range of their union: partials of map 1, then of map 2,
+// one final reduction over both, both quantised with that range.
+hipError_t launch_quantize_pair(const float *f1, const float *f2, long long count, float *part, uint8_t *q1,
+                                uint8_t *q2, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_minmax_partial, dim3(kQuantParts), dim3(256), 0, stream, f1, count, part);
+  hipLaunchKernelGGL(k_minmax_partial, dim3(kQuantParts), dim3(256), 0, stream, f2, count, part + 2 * kQuantParts);
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, stream, part, 2 * kQuantParts);
+  const float *range = part + 4 * kQuantParts;
+  hipLaunchKernelGGL(k_quantize, dim3(blocks_of(count)), dim3(256), 0, stream, f1, count, range, q1);
+  hipLaunchKernelGGL(k_quantize, dim3(blocks_of(count)), dim3(256), 0, stream, f2, count, range, q2);
+  return hipGetLastError();
+}
+
+size_t quantize_scratch_bytes() { return (size_t)(2 * kQuantParts + 1) * 2 * sizeof(float); }
+
 }  // namespace ffh

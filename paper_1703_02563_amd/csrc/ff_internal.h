@@ -219,6 +219,9 @@ hipError_t launch_l2norm16_bwd(const float *y, const float *inv_norm, const floa
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int count, float lr, float b1, float b2,
                        float eps, int step, uint16_t *p_bf16, hipStream_t stream);
 hipError_t launch_quantize(const float *f, long long count, float *part, uint8_t *q, hipStream_t stream);
+hipError_t launch_quantize_pair(const float *f1, const float *f2, long long count, float *part, uint8_t *q1,
+                                uint8_t *q2, hipStream_t stream);
+size_t quantize_scratch_bytes();  // float scratch of launch_quantize and launch_quantize_pair
 
 // Consistency of field a against field b (full resolution).
 size_t region_filter_scratch_bytes(int W, int H);

@@ -79,6 +79,7 @@ _SIGS = {
     "ff_l2norm16_bwd": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "ff_quantize_scratch_bytes": (C.c_size_t, []),
     "ff_quantize_u8": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "ff_quantize_pair_u8": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P]),
     "ff_workspace_bytes_f32": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
     "ff_flow_fields_f32": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P,
                                      _P, _P, _P]),

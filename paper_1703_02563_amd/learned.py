@@ -362,3 +362,16 @@ def quantize_u8(f: torch.Tensor) -> torch.Tensor:
     check(lib().ff_quantize_u8(_ptr(f, torch.float32), f.numel(), _ptr(scratch), _ptr(q), _stream()),
           "ff_quantize_u8")
     return q
+
+
+def quantize_pair_u8(f1: torch.Tensor, f2: torch.Tensor):
+    """Both maps to bytes with the range of their union (ff_quantize_pair_u8)."""
+    f1, f2 = f1.contiguous(), f2.contiguous()
+    if f1.shape != f2.shape:
+        raise ValueError("quantize_pair_u8: maps of the same shape")
+    q1 = torch.empty(f1.shape, dtype=torch.uint8, device=f1.device)
+    q2 = torch.empty(f2.shape, dtype=torch.uint8, device=f2.device)
+    scratch = torch.empty(int(lib().ff_quantize_scratch_bytes()) // 4, dtype=torch.float32, device=f1.device)
+    check(lib().ff_quantize_pair_u8(_ptr(f1, torch.float32), _ptr(f2, torch.float32), f1.numel(), _ptr(scratch),
+                                    _ptr(q1), _ptr(q2), _stream()), "ff_quantize_pair_u8")
+    return q1, q2

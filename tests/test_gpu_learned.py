@@ -322,3 +322,38 @@ def test_triplet_hinge_kernel_and_gradient_match_autograd():
     (torch.relu(margin + (cp - cn) / 49.0).sum() * weight).backward()
     assert torch.allclose(g1, a1.grad, rtol=1e-5, atol=1e-6)
     assert torch.allclose(g2, a2.grad, rtol=1e-5, atol=1e-6)
+
+
+def test_quantize_pair_matches_oracle():
+    f1 = feature_canvas(3, 40, 60)
+    f2 = feature_canvas(4, 40, 60) * 2.5 - 1.0
+    q1, q2 = Lm.quantize_pair_u8(torch.from_numpy(f1).cuda(), torch.from_numpy(f2).cuda())
+    e1, e2 = oracle.quantize_pair_u8(f1, f2)
+    assert np.array_equal(q1.cpu().numpy(), e1) and np.array_equal(q2.cpu().numpy(), e2)
+
+
+@pytest.mark.parametrize("shape,L,T", [((120, 160), 3, 4), ((150, 211), 5, 4)])
+def test_learned_level_kernel_costs_within_float64_bound(shape, L, T):
+    """Independently of the summation order the kernels and the oracle
+    share: every set cell's stored float32 cost lies within 784 * 2^-24
+    (relative) of the float64 patch cost of its flow (non-negative terms:
+    the float32 sum of 784 terms is within 784 u of the exact sum)."""
+    from oracle.float_cost import cost_f64
+    H, W = shape
+    pad = 10
+    canvas = feature_canvas(31 + H, H + 2 * pad, W + 2 * pad)
+    F1 = canvas[pad:pad + H, pad:pad + W].copy()
+    F2 = canvas[pad - 3:pad - 3 + H, pad + 2:pad + 2 + W].copy() + feature_canvas(32, H, W) * 0.05
+    m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
+    g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2],
+                           ff.Params(levels=L, iters=T))
+    torch.cuda.synchronize()
+    for fa, fb, fk, ck in ((F1, F2, "flow_fwd", "cost_fwd"), (F2, F1, "flow_bwd", "cost_bwd")):
+        flow = g[fk].cpu().numpy()
+        bits_ = g[ck].cpu().numpy().view(np.uint32)
+        ys, xs = np.nonzero(bits_ != oracle.UNSET)
+        assert len(ys) == H * W
+        ent = np.stack([xs, ys, flow[ys, xs, 0], flow[ys, xs, 1]], 1)
+        ref = cost_f64(fa, fb, ent, 1, 3)
+        got = bits_[ys, xs].view(np.float32).astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 784 * 2.0 ** -24 * ref + 1e-30), float(np.max(np.abs(got - ref) / ref))

@@ -433,3 +433,43 @@ def test_run_level_multi_launch_bit_exact(mode, passes):
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
+
+
+def _tie_state(bands, cells):
+    """The constructed tie cases of the oracle pins: image b's descriptors
+    constant per vertical band, a few set cells with consistent costs."""
+    ia, _ = random_images(77, 24, 24)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = np.empty_like(Da)
+    Db[:, :12] = bands[0]
+    Db[:, 12:] = bands[1]
+    flow = np.zeros((24, 24, 2), np.int16)
+    cost = np.full((24, 24), oracle.UNSET, np.uint32)
+    for (i, j), f in cells.items():
+        flow[j, i] = f
+        cost[j, i] = oracle.cost(Da, Db, 1, 3, i, j, f[0], f[1])
+    return Da, Db, flow, cost
+
+
+@pytest.mark.parametrize("blocked", [False, True])
+def test_propagation_ties_bit_exact(blocked):
+    """Equal errors of the horizontal and vertical source (the horizontal
+    one wins), a held flow of equal error (kept) and strict differences
+    either way, through the per-step kernel and the blocked kernel."""
+    fh, fv, fr = (-8, 2), (-9, -4), (4, 3)
+    cases = [((100, 100), {(10, 10): fh, (11, 9): fv}),
+             ((100, 100), {(10, 10): fh, (11, 9): fv, (11, 10): (-5, 1)}),
+             ((100, 250), {(10, 10): fr, (11, 9): fh}), ((100, 250), {(10, 10): fh, (11, 9): fr}),
+             ((250, 100), {(10, 10): fr, (11, 9): fh}), ((250, 100), {(10, 10): fh, (11, 9): fr})]
+    prm = ff.Params(levels=1, iters=1)
+    for bands, cells in cases:
+        Da, Db, flow, cost = _tie_state(bands, cells)
+        ef, ec, ne = oracle.propagate(Da, Db, 1, 0, flow, cost)
+        gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
+        if blocked:
+            ff.run_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 0, prm, 0, 0, gf, gc, n_evals=cnt)
+        else:
+            ff.propagate_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 1, 0, gf, gc, n_evals=cnt)
+        assert np.array_equal(host(gf), ef), cells
+        assert np.array_equal(as_u32(gc), ec), cells
+        assert int(host(cnt)[0]) == ne

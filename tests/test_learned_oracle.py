@@ -84,3 +84,52 @@ def test_translated_features_exact_recovery(t):
     f = o["flow_fwd"]
     assert np.all(f[inner][:, 0] == t[0]) and np.all(f[inner][:, 1] == t[1])
     assert np.all(o["cost_fwd"][inner].view(np.float32) == 0.0)
+
+
+def test_quantize_pair_shares_one_range():
+    """Both maps are quantised with the range of their union: the closed form
+    per element, equal values give equal bytes in both maps."""
+    f1 = feature_canvas(6, 20, 30)
+    f2 = feature_canvas(7, 20, 30) * 3.0 + 1.0
+    q1, q2 = oracle.quantize_pair_u8(f1, f2)
+    lo = float(min(f1.min(), f2.min()))
+    hi = float(max(f1.max(), f2.max()))
+    for f, q in ((f1, q1), (f2, q2)):
+        exact = (f.astype(np.float64) - lo) * 255.0 / (hi - lo)
+        assert np.all(np.abs(q - exact) <= 0.5 + 1e-3)
+    assert q1.min() > 0 or q2.min() == 0
+    both = np.concatenate([f1.ravel(), f2.ravel()])
+    qb = np.concatenate([q1.ravel(), q2.ravel()])
+    assert qb[np.argmin(both)] == 0 and qb[np.argmax(both)] == 255
+
+
+def test_quantized_nn_recovers_a_shift_under_a_different_value_range():
+    """Image 2's features are image 1's shifted by t, except for a strip of
+    content entering at the border with values far outside image 1's range.
+    One shared range maps equal features to equal bytes, so the byte-space
+    nearest neighbour of every grid cell whose match lies inside image 2 is
+    its shifted pixel (Sec. 3.1 seed: the nearest neighbour in feature
+    space).  Separate ranges per image break that (the check that this pin
+    can fail)."""
+    H, W, pad, t = 40, 56, 8, (5, -3)
+    canvas = feature_canvas(21, H + 2 * pad, W + 2 * pad)
+    F1 = canvas[pad:pad + H, pad:pad + W].copy()
+    F2 = canvas[pad - t[1]:pad - t[1] + H, pad - t[0]:pad - t[0] + W].copy()
+    F2[:, W - 4:] = F2[:, W - 4:] * 4.0 + 6.0  # entering content with another value range
+    nc = 4
+    q1, q2 = oracle.quantize_pair_u8(F1, F2)
+    idx, dist = oracle.nn(q1, q2, nc)
+    sep1, sep2 = oracle.quantize_u8(F1), oracle.quantize_u8(F2)
+    idx_sep, _ = oracle.nn(sep1, sep2, nc)
+    Hc, Wc = idx.shape
+    checked = wrong_sep = 0
+    for j in range(Hc):
+        for i in range(Wc):
+            x, y = i * nc + t[0], j * nc + t[1]
+            if not (0 <= x < W - 4 and 0 <= y < H):
+                continue
+            checked += 1
+            assert idx[j, i] == y * W + x and dist[j, i] == 0, (i, j)
+            wrong_sep += idx_sep[j, i] != y * W + x
+    assert checked > 80
+    assert wrong_sep > checked // 2
