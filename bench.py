@@ -26,20 +26,82 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pair, c, threads, min_seconds=10.0, max_runs=20):
-    """The oracle on the host cores: the whole pair, repeated until about
-    min_seconds of work (a bounded sample of the timed workload)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_pair_seconds(pair, c, threads, min_seconds, max_runs=20):
+    """Seconds per whole pair of the oracle on `threads` host threads,
+    repeated until about min_seconds of work (at least one run)."""
     import oracle
     runs, t0 = 0, time.perf_counter()
     while runs < max_runs and (runs == 0 or time.perf_counter() - t0 < min_seconds):
         oracle.flow_fields(pair.img1, pair.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed,
                            nthreads=threads)
         runs += 1
-    dt = time.perf_counter() - t0
+    return (time.perf_counter() - t0) / runs, runs
+
+
+def cpu_baseline(pair, c, threads):
+    """The oracle on the host cores: the whole 1024x436 pair (descriptors,
+    fwd+bwd fields, consistency) on `threads` threads for about 10 s, and
+    one run on a single thread."""
     H, W = pair.img1.shape
-    return {"value": runs * W * H / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{runs} runs of one full {W}x{H} pair (descriptors, fwd+bwd fields, consistency), "
-                      f"{dt:.2f} s in total"}
+    s_nt, runs_nt = oracle_pair_seconds(pair, c, threads, 10.0)
+    s_1t, _ = oracle_pair_seconds(pair, c, 1, 0.0, max_runs=1)
+    return {"value": round(W * H / s_nt / 1e6, 4), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"{runs_nt} runs of one full {W}x{H} pair (descriptors, fwd+bwd fields, consistency) on "
+                      f"{threads} threads, {s_nt * runs_nt:.2f} s in total; one run on 1 thread",
+            "ms_per_pair": round(s_nt * 1e3, 1),
+            "single_thread": {"value": round(W * H / s_1t / 1e6, 5), "ms_per_pair": round(s_1t * 1e3, 1)},
+            "host_logical_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def config_legs(ff, torch, threads, tuned, reps=20):
+    """The other single-pair workloads, GPU beside the oracle: 160x120
+    (3 scales x 4 steps) and 1242x375 radial expansion (5 scales x 6 steps,
+    R = 3/2); GPU ms per pair with HIP events, oracle ms on `threads` host
+    threads (and one thread for the small pair)."""
+    import dataclasses
+
+    from ffgen import CONFIG_PARAMS, make_pair
+    out = {}
+    for cfg in (1, 3):
+        p, c = make_pair(cfg), CONFIG_PARAMS[cfg]
+        H, W = p.img1.shape
+        prm = ff.Params(levels=c.levels, iters=c.iters, radius=c.radius, R_num=c.R_num, R_den=c.R_den, eps=c.eps,
+                        seed=c.seed)
+        if tuned is not None and (W, H) == (1024, 436):
+            prm = dataclasses.replace(prm, tuning=tuned)
+        i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+        runner = ff.FlowFields(W, H, prm, device=i1.device)
+        for _ in range(3):
+            runner(i1, i2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            runner(i1, i2)
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / reps
+        s_nt, _ = oracle_pair_seconds(p, c, threads, 2.0)
+        leg = {"W": W, "H": H, "levels": c.levels, "iters": c.iters, "R": f"{c.R_num}/{c.R_den}",
+               "gpu_ms_per_pair": round(gms, 4), "gpu_mpix_per_s": round(W * H / gms / 1e3, 2),
+               "oracle_ms_per_pair": round(s_nt * 1e3, 1), "oracle_threads": threads,
+               "n_evals": [int(v) for v in runner.out["n_evals"].cpu()]}
+        if cfg == 1:
+            s_1t, _ = oracle_pair_seconds(p, c, 1, 1.0)
+            leg["oracle_1thread_ms_per_pair"] = round(s_1t * 1e3, 1)
+        out[f"{W}x{H}"] = leg
+    return out
 
 
 # Integer-VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
@@ -71,9 +133,12 @@ def level_sources_sha():
 
 
 def roofline_level0(ff, torch, img1, img2, params, reps):
-    """Times the scale-1 level kernel (one direction, one launch of
-    ff_run_level from the scale-2 seeds) with HIP events on the current
-    stream; algorithmic work = patch evaluations x 196 v_sad_u8 lane-ops."""
+    """Times the scale-1 level kernel (one direction, one ff_run_level call
+    from the scale-2 seeds) with HIP events on the current stream.
+    Algorithmic work = the evaluations the launches compute for the cells
+    they own (the work counters of ff_run_level; evaluations that a
+    consistent state makes unnecessary and recomputed halo cells are not
+    counted) x 196 v_sad_u8 lane-ops."""
     H, W = img1.shape
     L = params.levels
     Da = [ff.descriptors(img1, 1 << lv)[1] for lv in range(L)]
@@ -95,34 +160,41 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     fl0 = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
     co0 = torch.empty((H, W), dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    work = torch.zeros(2, dtype=torch.int64, device=dev)
+    scratch = torch.empty(int(ff.lib().ff_run_level_scratch_bytes(W, H, 0)), dtype=torch.uint8, device=dev)
 
-    def launch(counter=None):
+    def launch(counter=None, wk=None):
         ff.run_level(Da[0], Db[0], 0, params, 0, 2, fl0, co0, coarse_flow=prev[0], coarse_cost=prev[1],
-                     n_evals=counter)
+                     n_evals=counter, n_work=wk, scratch=scratch)
 
     for _ in range(3):
         launch()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     torch.cuda.synchronize()
-    for a, b in ev:
+    for a, b in ev:  # timed without the counters
         a.record()
-        launch(cnt)
+        launch()
         b.record()
     torch.cuda.synchronize()
+    launch(cnt, work)  # the same call once more, counted (the counts do not vary between calls)
+    torch.cuda.synchronize()
     # one ff_run_level call = `launches` launches of the scale-1 level kernel
-    launches = int(ff.lib().ff_level_launches(params.iters, 0, 0))
+    launches = ff.level_launches(params, 0)
     ms = sum(a.elapsed_time(b) for a, b in ev) / reps / launches
-    evals = int(cnt.item()) / reps / launches
-    achieved = evals * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
+    evals = int(cnt.item()) / launches
+    w_owned, w_all = (int(v) / launches for v in work.cpu())
+    achieved = w_owned * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
+    tun = params.tuning or ff.default_tuning()
     traffic = None
-    if level_sources_sha() == TRAFFIC_SOURCES_SHA and ff.level_variants()[0] == TRAFFIC_VARIANT \
-            and ff.level_passes(0)[0] == TRAFFIC_PASSES:
+    if level_sources_sha() == TRAFFIC_SOURCES_SHA and tun.variant[0] == TRAFFIC_VARIANT \
+            and tun.passes[0] == TRAFFIC_PASSES:
         traffic = round(TRAFFIC_BYTES)
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
             "kernel": f"k_level<0,*> (scale 1, forward; ff_run_level = {launches} launches, averages per launch)",
             "avg_launch_ms": round(ms, 5), "evals_per_launch": evals,
-            "algorithmic_ops_per_launch": evals * SAD_OPS_PER_EVAL}
+            "computed_owned_per_launch": w_owned, "computed_all_per_launch": w_all,
+            "algorithmic_ops_per_launch": w_owned * SAD_OPS_PER_EVAL}
 
 
 def batched_throughput(ff, torch, reps):
@@ -134,10 +206,12 @@ def batched_throughput(ff, torch, reps):
     shapes = batch_shapes()
     prm = ff.Params(levels=c.levels, iters=c.iters, radius=c.radius, R_num=c.R_num, R_den=c.R_den, eps=c.eps,
                     seed=c.seed)
+    import dataclasses
+
     from paper_1703_02563_amd import autotune
     tables = autotune.load_batch(len(shapes), prm)
-    log(f"bench: batch launch tables {tables if tables else '(process-wide)'}")
-    b = BatchFlowFields(shapes, prm, tables=tables)
+    log(f"bench: batch launch tables {tables if tables else '(built-in)'}")
+    b = BatchFlowFields(shapes, dataclasses.replace(prm, tuning=tables))
     for k, shp in enumerate(shapes):
         p = make_pair(4, k, shape=shp)
         b.set_pair(k, torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda())
@@ -311,6 +385,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-descriptor measurement")
     ap.add_argument("--no-schedules", action="store_true",
                     help="skip the Flow Fields+ / Fast / two-backward-field measurements")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 160x120 and 1242x375 pairs (GPU beside the oracle)")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--val-pairs", type=int, default=4, help="held-out pairs of the EPE judge")
     ap.add_argument("--train-pairs", type=int, default=16)
@@ -339,9 +415,14 @@ def main():
     dev = torch.device("cuda:0")
     img1 = torch.from_numpy(pair.img1).to(dev)
     img2 = torch.from_numpy(pair.img2).to(dev)
+    import dataclasses
+
     from paper_1703_02563_amd import autotune
     tuned = autotune.load(W, H, params)
-    log(f"bench: level-kernel variants {ff.level_variants()}, passes per launch {ff.level_passes(0)} "
+    if tuned is not None:
+        params = dataclasses.replace(params, tuning=tuned)
+    tun = params.tuning or ff.default_tuning()
+    log(f"bench: level-kernel variants {tun.variant}, passes per launch {tun.passes} "
         f"({'tuned' if tuned else 'defaults'}; "
         f"cache {autotune.DEFAULT_CACHE}, key {autotune._key(W, H, params)})")
     runner = ff.FlowFields(W, H, params, device=dev)
@@ -393,10 +474,16 @@ def main():
     roof = roofline_level0(ff, torch, img1, img2, params, reps=20)
     log(f"bench: roofline {roof}")
 
+    threads = max(1, min(16, os.cpu_count() or 1))
+    legs = None
+    if not args.no_configs:
+        log("bench: other single-pair workloads, GPU beside the oracle")
+        legs = config_legs(ff, torch, threads, tuned)
+        log(f"bench: configs {legs}")
+
     base = None
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        log(f"bench: CPU oracle baseline on {threads} threads")
+        log(f"bench: CPU oracle baseline on {threads} threads and on 1 thread")
         base = cpu_baseline(pair, c, threads)
 
     rec = {
@@ -409,7 +496,7 @@ def main():
                    "n_evals": n_evals, "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                    "epe10": round(q["epe10"], 4), "kept_density": round(q["kept_density"], 4),
                    "kept_epe": round(q["kept_epe"], 4), "schedules": schedules, "batched": batched,
-                   "learned": learned},
+                   "learned": learned, "other_pairs": legs},
         "roofline": roof,
         "cpu_baseline": base,
     }

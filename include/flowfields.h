@@ -27,8 +27,10 @@
  *    FF_ERR_ARG / FF_ERR_WORKSPACE before anything is enqueued.  A failed
  *    launch returns FF_ERR_LAUNCH.  Faults inside kernels surface at the
  *    caller's next synchronisation of `stream`.
- *  * Calls are re-entrant; calls on different streams may overlap when they
- *    write disjoint buffers.
+ *  * Calls are re-entrant and keep no mutable global state (launch tables
+ *    come with each call, ff_tuning); calls on different streams or threads
+ *    may overlap when they write disjoint buffers.  The one exception is
+ *    ff_region_filter_noalloc (one static scratch array per GPU).
  */
 #ifndef FLOWFIELDS_H
 #define FLOWFIELDS_H
@@ -50,6 +52,23 @@ typedef enum {
 
 #define FF_UNSET_COST 0xFFFFFFFFu
 
+/* Launch tables of the temporally blocked level kernels (speed only: results
+ * never depend on them), indexed by scale log2 n = 0..6.  variant: kernel
+ * variant of the byte-descriptor path, in [0, ff_level_variant_count()) (the
+ * last index selects the step-wise schedule: one launch per step over all
+ * cells); passes: most propagation steps per blocked launch, 0 = as many as
+ * the variant's halo allows, in [0, 64]; variant_f32 / passes_f32: the same
+ * for the learned float features (variant_f32 in
+ * [0, ff_level_variant_count_f32())).  Host memory, read during the call
+ * only; the library keeps no mutable table, so calls with different tables
+ * may run concurrently. */
+typedef struct {
+    int32_t variant[7];
+    int32_t passes[7];
+    int32_t variant_f32[7];
+    int32_t passes_f32[7];
+} ff_tuning;
+
 /* Schedule of one Flow Field computation (Sec. 3.1, 3.2; parameters Sec. 4.1). */
 typedef struct {
     int32_t levels;  /* L: scales n = 2^(L-1), ..., 2, 1 (the paper's k = L-1) */
@@ -70,7 +89,13 @@ typedef struct {
     int32_t plus_iters;
     int32_t Rp_num;
     int32_t fine_iters;
+    /* host, nullable: launch tables of this call (NULL: the built-in table,
+     * see ff_default_tuning); an entry out of range is FF_ERR_ARG. */
+    const ff_tuning *tuning;
 } ff_params;
+
+/* The built-in launch tables (host): written to *out. */
+void ff_default_tuning(ff_tuning *out);
 
 /* Library version (host). */
 int ff_version(void);
@@ -227,11 +252,16 @@ ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_
  * ff_propagate_level and ff_random_search calls (same fields, same
  * evaluation count); radius 3 runs in temporally blocked launches that keep
  * the state on chip and skip evaluations whose value the consistent state
- * already fixes.  desc_a/desc_b: descriptor maps of scale n; params: host. */
+ * already fixes.  desc_a/desc_b: descriptor maps of scale n; params: host
+ * (params->tuning selects the launches).  n_work: nullable device uint64
+ * [2] counters of the evaluations the kernels actually compute (added to):
+ * [0] those of cells the launch owns, [1] all of them, the recomputed halo
+ * cells of the blocked launches included; n_evals counts the evaluations of
+ * the schedule itself, of which a consistent state makes some unnecessary. */
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
-                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, void *stream);
+                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream);
 
 /* Scratch bytes of ff_run_level (host): a second grid of scale 2^level
  * (flow and cost), which the launches of a scale alternate with flow/cost
@@ -399,41 +429,18 @@ ff_status ff_quantize_u8(const float *f, int64_t count, float *scratch, uint8_t 
 ff_status ff_quantize_pair_u8(const float *f1, const float *f2, int64_t count, float *scratch, uint8_t *q1,
                               uint8_t *q2, void *stream);
 
-/* Launch configuration (tile size, workgroup size, load unrolling) of the
- * temporally blocked level kernel that ff_flow_fields uses for patch radius 3
- * at scale n = 2^log2n, log2n in [0, 6].  A process-wide table (host),
- * written by the autotuner; it changes speed only, never results.  Setting
- * it while another thread runs ff_flow_fields is a race.
- * ff_set_level_variant returns FF_ERR_ARG for log2n or variant out of range;
- * ff_get_level_variant returns -1 for log2n out of range. */
+/* Number of variants in the launch tables (host): byte-descriptor level
+ * kernels plus the step-wise schedule (the last index), and float-feature
+ * level kernels (0: 16x16 cells with a halo of 2, 1: 8x8 / 2, 2: 8x8 / 4,
+ * 3: 8x8 / 6, 4: 16x16 / 4). */
 int32_t ff_level_variant_count(void);
-int32_t ff_get_level_variant(int32_t log2n);
-ff_status ff_set_level_variant(int32_t log2n, int32_t variant);
-
-/* Tile of the temporally blocked level kernel that ff_flow_fields_f32 uses
- * at scale n = 2^log2n, log2n in [0, 6]: variant 0 = 16x16 cells, 1 = 8x8
- * cells (more workgroups for the small grids of the coarse scales; default
- * 0 for n <= 2, 1 from n = 4 on).  Process-wide table (host), like the
- * variant table of the byte-descriptor path; it changes speed only, never
- * results.  ff_set_level_variant_f32 returns FF_ERR_ARG for log2n or variant
- * out of range; ff_get_level_variant_f32 returns -1 for log2n out of range. */
 int32_t ff_level_variant_count_f32(void);
-int32_t ff_get_level_variant_f32(int32_t log2n);
-ff_status ff_set_level_variant_f32(int32_t log2n, int32_t variant);
 
-/* Most propagation steps per temporally blocked launch at scale 2^log2n, for
- * the byte-descriptor path (cost_kind 0) or the learned float features
- * (cost_kind 1); 0 = as many as the kernel's halo allows (the default).
- * Shorter runs recompute less halo but need more launches; results never
- * change.  Process-wide table (host), like the variant table.  The setter
- * returns FF_ERR_ARG for log2n outside [0, 6], cost_kind not 0/1 or passes
- * outside [0, 64]; the getter -1. */
-int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind);
-ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes);
-
-/* Number of blocked launches the current tables give one scale 2^log2n of
- * a schedule with `iters` propagation steps (host); -1 if out of range. */
-int32_t ff_level_launches(int32_t iters, int32_t log2n, int32_t cost_kind);
+/* Number of blocked launches the tables give one scale 2^log2n of a
+ * schedule with `iters` propagation steps, for the byte descriptors
+ * (cost_kind 0) or the float features (1); tuning NULL = the built-in table
+ * (host); -1 if out of range. */
+int32_t ff_level_launches(const ff_tuning *tuning, int32_t iters, int32_t log2n, int32_t cost_kind);
 
 /* Bytes of device workspace ff_flow_fields needs for a W x H pair (host). */
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params);

@@ -51,13 +51,11 @@ def _lib():
 class BatchFlowFields:
     """Buffers and launches for a fixed list of frame shapes [(H, W), ...]."""
 
-    def __init__(self, shapes, params: Params, device="cuda", tables=None):
-        """tables: optional {"variants": [...], "passes": [...]} level-kernel
-        launch tables applied around every launch of this batch (graph
-        capture included); None keeps the process-wide tables."""
+    def __init__(self, shapes, params: Params, device="cuda"):
+        """params.tuning: the level-kernel launch tables of this batch's
+        calls (None: the built-in tables)."""
         self.shapes = [(int(h), int(w)) for h, w in shapes]
         self.params = params
-        self.tables = tables
         self._cp = params.to_c()
         dev = torch.device(device)
         self.device = dev
@@ -102,21 +100,9 @@ class BatchFlowFields:
         self.img2[k].copy_(img2)
 
     def run(self):
-        from .flowfields import level_passes, level_variants, set_level_passes, set_level_variants
-        saved = None
-        if self.tables is not None:
-            saved = (level_variants(), level_passes(0))
-            set_level_variants(self.tables["variants"])
-            if "passes" in self.tables:
-                set_level_passes(self.tables["passes"], 0)
-        try:
-            check(_lib().ff_flow_fields_batched(self.pairs, len(self.shapes), self._cp,
-                                                C.c_void_p(self.table.data_ptr()), C.c_void_p(self.ws.data_ptr()),
-                                                self.ws.numel(), _stream()), "ff_flow_fields_batched")
-        finally:
-            if saved is not None:
-                set_level_variants(saved[0])
-                set_level_passes(saved[1], 0)
+        check(_lib().ff_flow_fields_batched(self.pairs, len(self.shapes), self._cp,
+                                            C.c_void_p(self.table.data_ptr()), C.c_void_p(self.ws.data_ptr()),
+                                            self.ws.numel(), _stream()), "ff_flow_fields_batched")
         return self.out
 
     def capture(self):

@@ -25,11 +25,24 @@ inline bool nn_dims_ok(int W, int H) { return dims_ok(W, H) && (long long)W * H 
 
 ff_status from_hip(hipError_t e) { return e == hipSuccess ? FF_OK : FF_ERR_LAUNCH; }
 
+// The call's launch tables (ff_tuning and ffh::Tuning have the same fields).
+ffh::Tuning tuning_of(const ff_tuning *t) {
+  if (!t) return ffh::default_tuning();
+  ffh::Tuning u;
+  for (int k = 0; k < ffh::kTuneScales; ++k) {
+    u.variant[k] = t->variant[k];
+    u.passes[k] = t->passes[k];
+    u.variant_f32[k] = t->variant_f32[k];
+    u.passes_f32[k] = t->passes_f32[k];
+  }
+  return u;
+}
+
 bool params_ok(const ff_params *p) {
   return p && p->levels >= 1 && p->levels <= kMaxLevels && p->iters >= 1 && p->iters <= 64 && p->radius >= 0 &&
          p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20 &&
          p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
-         p->fine_iters >= 0 && p->fine_iters <= 64;
+         p->fine_iters >= 0 && p->fine_iters <= 64 && ffh::tuning_ok(tuning_of(p->tuning));
 }
 
 int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
@@ -146,11 +159,12 @@ int run_end(int t0, int T, int maxp, int halo = ffh::kLevelHalo) {
 }
 
 // Runs of passes of one scale: [t0, t1) pairs; the number of launches.
-int level_runs(int lv, int T, int fcost, int runs[][2]) {
+int level_runs(const ffh::Tuning &tun, int lv, int T, int fcost, int runs[][2]) {
   int m = 0, t0 = 0;
+  const int halo = fcost ? ffh::level_window_halo_f32(tun.variant_f32[lv]) : ffh::level_window_halo(tun.variant[lv]);
+  const int maxp = fcost ? tun.passes_f32[lv] : tun.passes[lv];
   while (t0 < T) {
-    const int halo = fcost ? ffh::level_window_halo_f32(lv) : ffh::level_window_halo(lv);
-    const int t1 = run_end(t0, T, ffh::get_level_passes(lv, fcost), halo);
+    const int t1 = run_end(t0, T, maxp, halo);
     runs[m][0] = t0;
     runs[m][1] = t1;
     ++m;
@@ -184,8 +198,10 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   k.P = sst.P;
   k.seed = p->seed;
   k.T = T;
+  const ffh::Tuning tun = tuning_of(p->tuning);
+  k.variant = k.fcost ? tun.variant_f32[lv] : tun.variant[lv];
   int runs[64][2];
-  const int m = level_runs(lv, T, k.fcost, runs);
+  const int m = level_runs(tun, lv, T, k.fcost, runs);
   const bool two = m > 1 || first_mode == ffh::kLevelContinue;
   if (two && (!sflow || !scost)) return hipErrorInvalidValue;
   int32_t *main_f[ffh::kMaxDirs];
@@ -406,7 +422,7 @@ size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level) {
 ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
-                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, void *stream) {
+                       void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream) {
   if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !params_ok(params) || level < 0 ||
       level >= kMaxLevels || stream_id < 0 || stream_id > 0xFF || mode < 0 || mode > 2 || (mode == 1 && !nn_key) ||
       (mode == 2 && (!coarse_flow || !coarse_cost)))
@@ -426,6 +442,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
     k.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
     k.dir[0].ccost = coarse_cost;
     k.dir[0].n_evals = reinterpret_cast<unsigned long long *>(n_evals);
+    k.dir[0].n_work = reinterpret_cast<unsigned long long *>(n_work);
     k.dir[0].stream_id = stream_id;
     const int first = mode == 1 ? ffh::kLevelInit : (mode == 2 ? ffh::kLevelSeed : ffh::kLevelContinue);
     int32_t *sf[1] = {static_cast<int32_t *>(scratch)};
@@ -440,6 +457,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
   a.dir[0].nn_key = nn_key;
   a.dir[0].cflow = reinterpret_cast<const int32_t *>(coarse_flow);
   a.dir[0].ccost = coarse_cost;
+  a.dir[0].n_work = reinterpret_cast<unsigned long long *>(n_work);
   hipError_t e = hipSuccess;
   if (mode == 1) return FF_ERR_UNSUPPORTED;  // the per-step path seeds through ff_init_nn
   if (mode == 2) e = ffh::launch_seed_level(a, s);
@@ -606,12 +624,15 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
   }
   if ((e = ffh::launch_batch_nn(norms, keysf, nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
   // scales, coarse to fine: one persistent launch per run of passes
+  const ffh::Tuning tun = tuning_of(params->tuning);
   for (int lv = L - 1; lv >= 0; --lv) {
     const int n = 1 << lv;
     bool maps_fit = true;
     for (int i = 0; i < npairs; ++i) maps_fit = maps_fit && ffh::level_map_fits(pairs[i].W, pairs[i].H, lv);
     // work items of the kernel that will run (a variant's fallback may tile differently)
-    fill([&](int W, int H) { return 2 * ffh::level_tiles(ceil_div(W, n), ceil_div(H, n), lv, maps_fit); });
+    fill([&](int W, int H) {
+      return 2 * ffh::level_tiles(ceil_div(W, n), ceil_div(H, n), tun.variant[lv], maps_fit);
+    });
     st.n = n;
     st.lv = lv;
     ffh::LevelKArgs k{};
@@ -624,8 +645,9 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
     k.P = sst.P;
     k.seed = params->seed;
     k.T = sst.total();
+    k.variant = tun.variant[lv];
     int runs[64][2];
-    const int m = level_runs(lv, k.T, 0, runs);
+    const int m = level_runs(tun, lv, k.T, 0, runs);
     for (int r = 0; r < m; ++r) {
       // runs alternate between the two grid buffers; the last writes gflow/gcost
       st.dst = ((m - 1 - r) & 1) ? 1 : 0;
@@ -921,30 +943,26 @@ ff_status ff_quantize_pair_u8(const float *f1, const float *f2, int64_t count, f
 
 int32_t ff_level_variant_count(void) { return ffh::level_variant_count(); }
 
-int32_t ff_get_level_passes(int32_t log2n, int32_t cost_kind) { return ffh::get_level_passes(log2n, cost_kind); }
-
-int32_t ff_level_launches(int32_t iters, int32_t log2n, int32_t cost_kind) {
-  if (iters < 1 || iters > 64 || ffh::get_level_passes(log2n, cost_kind) < 0) return -1;
-  int runs[64][2];
-  return level_runs(log2n, iters, cost_kind, runs);
-}
-
-ff_status ff_set_level_passes(int32_t log2n, int32_t cost_kind, int32_t passes) {
-  return ffh::set_level_passes(log2n, cost_kind, passes) ? FF_OK : FF_ERR_ARG;
-}
-
 int32_t ff_level_variant_count_f32(void) { return ffh::level_variant_count_f32(); }
 
-int32_t ff_get_level_variant_f32(int32_t log2n) { return ffh::get_level_variant_f32(log2n); }
-
-ff_status ff_set_level_variant_f32(int32_t log2n, int32_t variant) {
-  return ffh::set_level_variant_f32(log2n, variant) ? FF_OK : FF_ERR_ARG;
+void ff_default_tuning(ff_tuning *out) {
+  if (!out) return;
+  const ffh::Tuning &t = ffh::default_tuning();
+  for (int k = 0; k < ffh::kTuneScales; ++k) {
+    out->variant[k] = t.variant[k];
+    out->passes[k] = t.passes[k];
+    out->variant_f32[k] = t.variant_f32[k];
+    out->passes_f32[k] = t.passes_f32[k];
+  }
 }
 
-int32_t ff_get_level_variant(int32_t log2n) { return ffh::get_level_variant(log2n); }
-
-ff_status ff_set_level_variant(int32_t log2n, int32_t variant) {
-  return ffh::set_level_variant(log2n, variant) ? FF_OK : FF_ERR_ARG;
+int32_t ff_level_launches(const ff_tuning *tuning, int32_t iters, int32_t log2n, int32_t cost_kind) {
+  const ffh::Tuning tun = tuning_of(tuning);
+  if (iters < 1 || iters > 64 || log2n < 0 || log2n >= ffh::kTuneScales || (cost_kind != 0 && cost_kind != 1) ||
+      !ffh::tuning_ok(tun))
+    return -1;
+  int runs[64][2];
+  return level_runs(tun, log2n, iters, cost_kind, runs);
 }
 
 size_t ff_workspace_bytes(int32_t W, int32_t H, const ff_params *params) {
@@ -1044,12 +1062,13 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         k.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
         k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
-      if (ffh::level_stepwise(lv)) {
+      if (ffh::level_stepwise(tuning_of(params->tuning).variant[lv])) {
         ffh::LevelArgs a{};
         a.ndir = nd;
         for (int dr = 0; dr < nd; ++dr) {
           const ffh::LevelKDir &kd = k.dir[dr];
-          a.dir[dr] = {kd.Da, kd.Db, kd.flow, kd.cost, kd.cflow, kd.ccost, kd.nn_key, desc1[dr], kd.n_evals, dr};
+          a.dir[dr] = {kd.Da, kd.Db, kd.flow, kd.cost, kd.cflow, kd.ccost, kd.nn_key, desc1[dr], kd.n_evals,
+                       nullptr, dr};
         }
         if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
         continue;

@@ -232,4 +232,17 @@ __device__ __forceinline__ void wave_count_add(unsigned long long *counter, int 
   if ((threadIdx.x & 63) == 0 && total) atomicAdd(counter, (unsigned long long)total);
 }
 
+// Adds a per-lane count of the whole wave to both entries of a [2] counter
+// pair (nullable), one atomic per entry and wave.
+__device__ __forceinline__ void wave_count_add2(unsigned long long *counter2, int cnt) {
+  if (counter2 == nullptr) return;
+  const unsigned long long b1 = __ballot(cnt >= 1);
+  const unsigned long long b2 = __ballot(cnt >= 2);
+  const int total = __popcll(b1) + __popcll(b2);
+  if ((threadIdx.x & 63) == 0 && total) {
+    atomicAdd(counter2, (unsigned long long)total);
+    atomicAdd(counter2 + 1, (unsigned long long)total);
+  }
+}
+
 }  // namespace ffk

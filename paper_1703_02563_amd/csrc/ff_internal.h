@@ -45,6 +45,21 @@ struct NNArgs {
 };
 hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
 
+// Launch tables of the temporally blocked level kernels, per scale log2 n
+// (the C ABI's ff_tuning): kernel variant and most propagation steps per
+// launch (0: as many as the window's halo allows), for the byte descriptors
+// and for the learned float features.  Passed with every call; the library
+// keeps only the immutable default.
+constexpr int kTuneScales = 7;
+struct Tuning {
+  int variant[kTuneScales];
+  int passes[kTuneScales];
+  int variant_f32[kTuneScales];
+  int passes_f32[kTuneScales];
+};
+const Tuning &default_tuning();
+bool tuning_ok(const Tuning &t);
+
 // Per-direction state of a level grid.
 struct LevelDir {
   const void *Da;      // scale-n descriptors (or float features) of the source image
@@ -56,6 +71,7 @@ struct LevelDir {
   const uint64_t *nn_key; // coarsest init only
   const uint8_t *Dq1;     // level-1 descriptors of the source image (coarsest init only)
   unsigned long long *n_evals;
+  unsigned long long *n_work;  // nullable [2]: evaluations computed (all of them count in both entries here)
   int stream_id;
 };
 struct LevelArgs {
@@ -91,6 +107,11 @@ struct LevelKDir {
   const uint32_t *ccost;
   const uint64_t *nn_key;
   unsigned long long *n_evals;
+  // nullable [2]: [0] evaluations computed for owned cells, [1] all
+  // evaluations computed, halo recomputation included (n_evals counts the
+  // unblocked schedule's evaluations, some of which a consistent state makes
+  // unnecessary)
+  unsigned long long *n_work;
   int stream_id;
 };
 struct LevelKArgs {
@@ -102,6 +123,7 @@ struct LevelKArgs {
   int t_begin, t_end, T;  // T: steps of the scale; no random search after steps P - 1 and T - 1
   int mode;
   int fcost;    // 0: byte descriptor maps; 1: padded float feature maps (64-byte entries)
+  int variant;  // the launch table's variant of this scale (byte or float table by fcost)
   int tiles_x;  // set by launch_level
   int halo[4];
 };
@@ -121,19 +143,13 @@ FF_LEVEL_SCALE_DECL(4)
 FF_LEVEL_SCALE_DECL(5)
 FF_LEVEL_SCALE_DECL(6)
 #undef FF_LEVEL_SCALE_DECL
-int level_window_halo(int log2n);              // halo of the blocked kernel the table selects
-int level_window_halo_f32(int log2n);          // the same for the float-feature kernel
+int level_window_halo(int variant);              // window halo of a byte-descriptor variant
+int level_window_halo_f32(int variant);          // the same for a float-feature variant
 bool level_map_fits(int W, int H, int log2n);  // scale-n map under 2^31 bytes (quad evaluations)
 void level_halo(int t_begin, int t_end, int halo[4]);
-int level_variant_count();
-int get_level_variant(int log2n);
-bool set_level_variant(int log2n, int variant);
+int level_variant_count();      // byte-descriptor variants + the step-wise schedule
 int level_variant_count_f32();
-int get_level_variant_f32(int log2n);
-bool set_level_variant_f32(int log2n, int variant);
-bool level_stepwise(int log2n);  // the table selects the step-wise schedule for this scale
-int get_level_passes(int log2n, int fcost);  // most propagation steps per blocked launch (0: no limit)
-bool set_level_passes(int log2n, int fcost, int passes);
+bool level_stepwise(int variant);  // the variant index that selects the step-wise schedule
 
 // ---- batches of pairs of different sizes (one launch per stage) ----------
 constexpr int kMaxBatch = 256;
@@ -174,7 +190,7 @@ hipError_t launch_batch_consistency(const BatchStage &rows, float eps, hipStream
 int batch_nn_items(int W, int H, int L);
 // tiles of one direction for the kernel that runs at that scale (the current
 // variant, or its fallback when a map does not fit the quad addressing)
-int level_tiles(int Wn, int Hn, int log2n, bool maps_fit);
+int level_tiles(int Wn, int Hn, int variant, bool maps_fit);
 
 // Float patch cost of 16-channel float32 feature maps (learned data term).
 struct CostArgs {

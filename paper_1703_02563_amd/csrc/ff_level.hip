@@ -52,65 +52,41 @@ constexpr int kHaloF32[] = {2, 2, 4, 6, 4};
 constexpr int kNumVariantsF32 = 5;
 static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float variant table");
 
-// Per-scale float variant (index log2 n); written by ff_set_level_variant_f32.
-// 8x8 tiles from n = 4 on, where 16x16 tiles leave most compute units idle.
-int g_variant_f32[7] = {0, 0, 1, 1, 1, 1, 1};
-
-hipError_t dispatch_f32(const ffh::LevelKArgs &a, int log2n, hipStream_t stream) {
-  if (log2n < 0 || log2n >= 7) return hipErrorInvalidValue;
-  return kScaleF32[log2n](a, g_variant_f32[log2n], stream);
-}
-
-// Per-scale variant table (index log2 n); written by ff_set_level_variant.
-int g_variant[7] = {2, 2, 3, 3, 3, 3, 3};
-// Most propagation steps per launch, per cost kind and scale (0: as many as
-// the halo allows).  Shorter runs recompute less halo at the price of more
-// launches; the float features' evaluations are expensive enough that one
-// step per launch is fastest at every scale (measured at 1024x436).
-int g_passes[2][7] = {{0, 0, 0, 0, 0, 0, 0}, {1, 1, 1, 1, 1, 1, 1}};
+// The built-in launch tables.  Byte descriptors: one-lane 32x16 tiles at
+// n = 1, 2 and 16x16 tiles from n = 4 on, as many steps per launch as the
+// halo allows.  Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
+// on (16x16 tiles leave most compute units idle there), one step per launch
+// (the float evaluations are expensive enough that this is fastest at every
+// scale, measured at 1024x436).
+constexpr ffh::Tuning kDefaultTuning = {{2, 2, 3, 3, 3, 3, 3},
+                                        {0, 0, 0, 0, 0, 0, 0},
+                                        {0, 0, 1, 1, 1, 1, 1},
+                                        {1, 1, 1, 1, 1, 1, 1}};
 
 }  // namespace
 
 namespace ffh {
 
+const Tuning &default_tuning() { return kDefaultTuning; }
+
 int level_variant_count() { return kNumVariants + 1; }  // + the step-wise schedule
 
-int get_level_variant(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant[log2n] : -1; }
+int level_variant_count_f32() { return kNumVariantsF32; }
 
-bool level_stepwise(int log2n) { return get_level_variant(log2n) == kNumVariants; }
+bool level_stepwise(int variant) { return variant == kNumVariants; }
 
-int get_level_passes(int log2n, int fcost) {
-  return (log2n >= 0 && log2n < 7 && (fcost == 0 || fcost == 1)) ? g_passes[fcost][log2n] : -1;
-}
-
-bool set_level_passes(int log2n, int fcost, int passes) {
-  if (log2n < 0 || log2n >= 7 || (fcost != 0 && fcost != 1) || passes < 0 || passes > 64) return false;
-  g_passes[fcost][log2n] = passes;
+bool tuning_ok(const Tuning &t) {
+  for (int k = 0; k < kTuneScales; ++k) {
+    if (t.variant[k] < 0 || t.variant[k] >= level_variant_count()) return false;
+    if (t.variant_f32[k] < 0 || t.variant_f32[k] >= kNumVariantsF32) return false;
+    if (t.passes[k] < 0 || t.passes[k] > 64 || t.passes_f32[k] < 0 || t.passes_f32[k] > 64) return false;
+  }
   return true;
 }
 
 // Blocked kernel variant used where the table asks for the step-wise
 // schedule but the caller only has the blocked form (batches, ff_run_level).
-static int blocked_variant(int log2n) {
-  const int v = get_level_variant(log2n);
-  return v == kNumVariants ? 3 : v;
-}
-
-int level_variant_count_f32() { return kNumVariantsF32; }
-
-int get_level_variant_f32(int log2n) { return (log2n >= 0 && log2n < 7) ? g_variant_f32[log2n] : -1; }
-
-bool set_level_variant_f32(int log2n, int variant) {
-  if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= kNumVariantsF32) return false;
-  g_variant_f32[log2n] = variant;
-  return true;
-}
-
-bool set_level_variant(int log2n, int variant) {
-  if (log2n < 0 || log2n >= 7 || variant < 0 || variant >= level_variant_count()) return false;
-  g_variant[log2n] = variant;
-  return true;
-}
+static int blocked_variant(int variant) { return variant == kNumVariants ? 3 : variant; }
 
 static int log2_of(int n) {
   int l = 0;
@@ -118,14 +94,13 @@ static int log2_of(int n) {
   return l;
 }
 
-int level_window_halo_f32(int log2n) {
-  const int v = get_level_variant_f32(log2n);
-  return v < 0 ? 2 : kHaloF32[v];
+int level_window_halo_f32(int variant) {
+  return (variant >= 0 && variant < kNumVariantsF32) ? kHaloF32[variant] : 2;
 }
 
-int level_window_halo(int log2n) {
-  const int v = blocked_variant(log2n);
-  return v < 0 ? kLevelHalo : kVariants[v].halo;
+int level_window_halo(int variant) {
+  const int v = blocked_variant(variant);
+  return (v >= 0 && v < kNumVariants) ? kVariants[v].halo : kLevelHalo;
 }
 
 bool level_map_fits(int W, int H, int log2n) {
@@ -135,25 +110,28 @@ bool level_map_fits(int W, int H, int log2n) {
 
 // The table's variant, or its fallback where image b's map is too large
 // for the 32-bit offsets of the quad evaluations.
-static int launch_variant(int log2n, bool map_fits) {
-  const int v = blocked_variant(log2n);
+static int launch_variant(int variant, bool map_fits) {
+  const int v = blocked_variant(variant);
   return (v >= 0 && !map_fits) ? kVariants[v].fallback : v;
 }
 
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
   const int l2 = log2_of(a.n);
-  if (a.fcost) return dispatch_f32(a, l2, stream);
-  return dispatch(a, nullptr, l2, launch_variant(l2, level_map_fits(a.W, a.H, l2)), stream);
+  if (a.fcost) {
+    if (l2 < 0 || l2 >= 7) return hipErrorInvalidValue;
+    return kScaleF32[l2](a, a.variant, stream);
+  }
+  return dispatch(a, nullptr, l2, launch_variant(a.variant, level_map_fits(a.W, a.H, l2)), stream);
 }
 
 hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, bool maps_fit, hipStream_t stream) {
   const int l2 = log2_of(base.n);
-  return dispatch(base, &st, l2, launch_variant(l2, maps_fit), stream);
+  return dispatch(base, &st, l2, launch_variant(base.variant, maps_fit), stream);
 }
 
-int level_tiles(int Wn, int Hn, int log2n, bool maps_fit) {
-  const int v = launch_variant(log2n, maps_fit);
-  if (v < 0) return 0;
+int level_tiles(int Wn, int Hn, int variant, bool maps_fit) {
+  const int v = launch_variant(variant, maps_fit);
+  if (v < 0 || v >= kNumVariants) return 0;
   const Variant t = kVariants[v];
   return ((Wn + t.tw - 1) / t.tw) * ((Hn + t.th - 1) / t.th);
 }

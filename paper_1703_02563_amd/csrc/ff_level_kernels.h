@@ -199,6 +199,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   // random-search candidate flows
   __shared__ FlagT s_flags[G::LH * G::LW];
   __shared__ unsigned int s_cnt, s_qlen, s_rlen;
+  __shared__ unsigned int s_work[2];  // evaluations computed: owned cells, all cells
 
   const int tid = threadIdx.x, qr = tid & 3;
   const int W = a.W, H = a.H, Wn = a.Wn, Hn = a.Hn;
@@ -210,6 +211,8 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     s_cnt = 0;
     s_qlen = 0;
     s_rlen = 0;
+    s_work[0] = 0;
+    s_work[1] = 0;
   }
 
   // image-a descriptors on the level lattice around the window: every load
@@ -253,6 +256,16 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     } else {
       const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
       return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+    }
+  };
+  // evaluations computed (the work counters; a no-op without them), called
+  // by every lane of a wave
+  auto count_work = [&](bool did, bool own) {
+    if (d.n_work == nullptr) return;
+    const int all = __popcll(__ballot(did)), mine = __popcll(__ballot(did && own));
+    if ((tid & 63) == 0 && all) {
+      atomicAdd(&s_work[0], (unsigned)mine);
+      atomicAdd(&s_work[1], (unsigned)all);
     }
   };
   // queue append of the lanes with `on` set (one LDS atomic per wave)
@@ -347,6 +360,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           cnt = owned(i, j);
         }
       }
+      if constexpr (!QUAD) count_work(k < rw * rh && ev[it], cnt != 0);
       if constexpr (QUAD) enqueue(k < rw * rh && ev[it], (uint16_t)l, s_qlen);
       const int tot = __popcll(__ballot(cnt));
       if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
@@ -358,12 +372,15 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       const int qlen = (int)s_qlen;
       for (int base = 0; base < qlen; base += kQuads) {
         const int q = base + (tid >> 2);
+        bool own = false;
         if (q < qlen) {
           const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
           const int32_t f = s_flow[l];
           const uint32_t c = evalq(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
           if (qr == 0) s_cost[l] = c;
+          own = owned(i, j);
         }
+        count_work(q < qlen && qr == 0, own);
       }
       __syncthreads();
       if (tid == 0) s_qlen = 0;
@@ -442,6 +459,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         const int qlen = (int)s_qlen;
         for (int base = 0; base < qlen; base += kQuads) {
           const int q = base + (tid >> 2);
+          bool own = false;
           if (q < qlen) {
             const int e = s_queue[q], l = e >> 1, vert = e & 1;
             const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
@@ -453,16 +471,24 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
               else
                 atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
             }
+            own = owned(i, j);
           }
+          count_work(q < qlen && qr == 0, own);
         }
       } else {
         const int qlen = (int)s_qlen;
-        for (int q = tid; q < qlen; q += kThreads) {
-          const int e = s_queue[q], l = e >> 1, vert = e & 1;
-          const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
-          const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
-          const uint32_t c = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
-          atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+        for (int base = 0; base < qlen; base += kThreads) {
+          const int q = base + tid;
+          bool own = false;
+          if (q < qlen) {
+            const int e = s_queue[q], l = e >> 1, vert = e & 1;
+            const int i = gi0 + l % G::LW, j = gj0 + l / G::LW;
+            const int32_t f = s_flow[vert ? l + vdj * G::LW : l + hdi];
+            const uint32_t c = evalc(i, j, i * n + ffk::flow_x(f), j * n + ffk::flow_y(f));
+            atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + vert));
+            own = owned(i, j);
+          }
+          count_work(q < qlen, own);
         }
       }
       __syncthreads();
@@ -535,6 +561,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       const int qlen = (int)s_rlen;
       for (int base = 0; base < qlen; base += kQuads) {
         const int q = base + (tid >> 2);
+        bool own = false;
         if (q < qlen) {
           const int l = s_queue[q], i = gi0 + l % G::LW, j = gj0 + l / G::LW;
           const int32_t fc = (int32_t)s_flags[l];
@@ -543,7 +570,9 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             s_cost[l] = e;
             s_flow[l] = fc;
           }
+          own = owned(i, j);
         }
+        count_work(q < qlen && qr == 0, own);
       }
       __syncthreads();
       if (tid == 0) s_rlen = 0;  // next written after the next step's first half-sweep
@@ -579,6 +608,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             s_flow[l] = ffk::pack_flow(fx, fy);
           }
         }
+        count_work(act, cnt != 0);
         const int tot = __popcll(__ballot(cnt));
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
       }
@@ -595,6 +625,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     d.cost[(size_t)j * Wn + i] = s_cost[l];
   }
   if (tid == 0 && s_cnt && d.n_evals) atomicAdd(d.n_evals, (unsigned long long)s_cnt);
+  if (tid == 0 && d.n_work && s_work[1]) {
+    atomicAdd(d.n_work, (unsigned long long)s_work[0]);
+    atomicAdd(d.n_work + 1, (unsigned long long)s_work[1]);
+  }
 }
 
 // One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
@@ -644,6 +678,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 
     d.ccost = lv + 1 < st.L ? bp.gcost[lv + 1][dir] : nullptr;
     d.nn_key = bp.keys[dir];
     d.n_evals = bp.evals + dir;
+    d.n_work = nullptr;
     d.stream_id = dir;
     level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, d, local % tiles);
     __syncthreads();  // the next item reuses the LDS window

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
     cnt = 1;
   }
   ffk::wave_count_add(d.n_evals, cnt);
+  ffk::wave_count_add2(d.n_work, cnt);
 }
 
 template <int R, class Cost>
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
     d.cost[m] = c;
   }
   ffk::wave_count_add(d.n_evals, cnt);
+  ffk::wave_count_add2(d.n_work, cnt);
 }
 
 // Half-sweep of colour `colour` ((i + j) & 1 == colour) of propagation step
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int i = 2 * kx + ((colour + j) & 1);
   const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n;
-  int cnt = 0;
+  int cnt = 0, work = 0;
   if (i < Wn && j < Hn) {
     const int dir = a.pass & 3;
     const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
     // the horizontal source replaced f0, which is rare)
     const bool vcomp = vb && !(hv && fv == fh) && !(set0 && fv == f0);
     uint32_t eh = 0, ev = 0;
+    work = (int)hv + (int)vcomp;
     if (hv || vcomp)
       Cost::template eval2<R>(d.Da, d.Db, W, H, n,
                           x, y, ffk::flow_x(fh), ffk::flow_y(fh), hv, ffk::flow_x(fv), ffk::flow_y(fv), vcomp,
@@ -151,10 +154,12 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
         e = eh;
       else if (vcomp)
         e = ev;
-      else  // fv == f0 after the horizontal source replaced it; the stored
-            // cost of a caller-made state need not equal E(p, f0)
+      else {  // fv == f0 after the horizontal source replaced it; the stored
+              // cost of a caller-made state need not equal E(p, f0)
         e = Cost::template eval<R>(d.Da, d.Db, W, H,
                                n, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
+        work += 1;
+      }
       if (e < bc) { bc = e; bf = fv; }
     }
     if (bc != c0 || bf != f0) {
@@ -163,6 +168,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
     }
   }
   ffk::wave_count_add(d.n_evals, cnt);
+  ffk::wave_count_add2(d.n_work, work);
 }
 
 template <int R, class Cost>
@@ -191,6 +197,7 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
     }
   }
   ffk::wave_count_add(d.n_evals, cnt);
+  ffk::wave_count_add2(d.n_work, cnt);
 }
 
 // blockIdx.z = 1 runs the check with the roles of the two fields swapped

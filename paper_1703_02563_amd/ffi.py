@@ -22,6 +22,16 @@ class FlowFieldsError(RuntimeError):
         super().__init__(f"{what}: {status_str(status)} ({status})" if what else status_str(status))
 
 
+class FFTuning(C.Structure):
+    """Mirror of ff_tuning (launch tables per scale log2 n = 0..6)."""
+    _fields_ = [
+        ("variant", C.c_int32 * 7),
+        ("passes", C.c_int32 * 7),
+        ("variant_f32", C.c_int32 * 7),
+        ("passes_f32", C.c_int32 * 7),
+    ]
+
+
 class FFParams(C.Structure):
     """Mirror of ff_params."""
     _fields_ = [
@@ -35,6 +45,7 @@ class FFParams(C.Structure):
         ("plus_iters", C.c_int32),
         ("Rp_num", C.c_int32),
         ("fine_iters", C.c_int32),
+        ("tuning", C.POINTER(FFTuning)),
     ]
 
 
@@ -62,7 +73,7 @@ _SIGS = {
     "ff_region_filter_noalloc": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
     "ff_run_level": (C.c_int, [_P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P, _P, _P,
-                               C.c_size_t, _P, _P]),
+                               C.c_size_t, _P, _P, _P]),
     "ff_run_level_scratch_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_cost_f32_fwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "ff_cost_f32_bwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),
@@ -84,14 +95,9 @@ _SIGS = {
     "ff_flow_fields_f32": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P,
                                      _P, _P, _P]),
     "ff_level_variant_count": (C.c_int32, []),
-    "ff_get_level_variant": (C.c_int32, [_I32]),
-    "ff_set_level_variant": (C.c_int, [_I32, _I32]),
     "ff_level_variant_count_f32": (C.c_int32, []),
-    "ff_get_level_variant_f32": (C.c_int32, [_I32]),
-    "ff_set_level_variant_f32": (C.c_int, [_I32, _I32]),
-    "ff_get_level_passes": (C.c_int32, [_I32, _I32]),
-    "ff_set_level_passes": (C.c_int, [_I32, _I32, _I32]),
-    "ff_level_launches": (C.c_int32, [_I32, _I32, _I32]),
+    "ff_default_tuning": (None, [C.POINTER(FFTuning)]),
+    "ff_level_launches": (C.c_int32, [C.POINTER(FFTuning), _I32, _I32, _I32]),
     "ff_flow_fields": (C.c_int, [_P, _P, _I32, _I32, C.POINTER(FFParams), _P, C.c_size_t, _P, _P, _P, _P, _P, _P,
                                  _P, _P]),
 }

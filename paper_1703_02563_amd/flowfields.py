@@ -9,14 +9,44 @@ uint32 bit pattern (0xFFFFFFFF, i.e. -1, marks an UNSET cell).
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 
 import torch
 
 from . import ffi
-from .ffi import FFParams, check, lib
+from .ffi import FFParams, FFTuning, check, lib
 
 UNSET_I32 = -1  # 0xFFFFFFFF viewed as int32
+
+
+@dataclasses.dataclass
+class Tuning:
+    """Launch tables of the level kernels per scale log2 n = 0..6 (see
+    ff_tuning): speed only, results never depend on them."""
+    variant: list
+    passes: list
+    variant_f32: list
+    passes_f32: list
+
+    def to_c(self) -> FFTuning:
+        t = FFTuning()
+        for name in ("variant", "passes", "variant_f32", "passes_f32"):
+            vals = [int(v) for v in getattr(self, name)]
+            if len(vals) != 7:
+                raise ValueError(f"Tuning.{name}: 7 entries (log2 n = 0..6)")
+            getattr(t, name)[:] = vals
+        return t
+
+    def replace(self, **kw) -> "Tuning":
+        return dataclasses.replace(self, **{k: list(v) for k, v in kw.items()})
+
+
+def default_tuning() -> Tuning:
+    """The library's built-in launch tables (ff_default_tuning)."""
+    t = FFTuning()
+    lib().ff_default_tuning(ctypes.byref(t))
+    return Tuning(list(t.variant), list(t.passes), list(t.variant_f32), list(t.passes_f32))
 
 
 @dataclasses.dataclass
@@ -32,10 +62,15 @@ class Params:
     plus_iters: int = 0  # Flow Fields+: steps at R+ = Rp_num / R_den before the `iters` steps at R
     Rp_num: int = 0
     fine_iters: int = 0  # Flow Fields+ Fast: steps at R on the finest scale (0: as the other scales)
+    tuning: Tuning | None = None  # launch tables of the calls (None: the built-in tables)
 
     def to_c(self) -> FFParams:
-        return FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
-                        self.plus_iters, self.Rp_num, self.fine_iters)
+        p = FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
+                     self.plus_iters, self.Rp_num, self.fine_iters, None)
+        if self.tuning is not None:
+            p._tuning = self.tuning.to_c()  # kept alive with the struct that points at it
+            p.tuning = ctypes.pointer(p._tuning)
+        return p
 
 
 def _stream():
@@ -61,10 +96,6 @@ def _ptr(t: torch.Tensor | None, dtype=None, what: str = "tensor"):
 
 def cells(W: int, H: int, n: int):
     return -(-W // n), -(-H // n)
-
-
-def rs_radius(n: int, R_num: int, R_den: int) -> int:
-    return (R_num * n) // R_den
 
 
 def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False):
@@ -140,15 +171,27 @@ def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, le
 
 
 def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: int, flow, cost, nn_key=None,
-              coarse_flow=None, coarse_cost=None, n_evals=None):
-    """All steps of one scale, in place on (flow, cost); see ff_run_level."""
+              coarse_flow=None, coarse_cost=None, n_evals=None, n_work=None, scratch=None):
+    """All steps of one scale, in place on (flow, cost); see ff_run_level.
+    n_work: optional int64 [2] device counters of the evaluations computed
+    (owned cells, all cells); scratch: optional reusable second grid."""
     W, H = _map_dims(desc_a, desc_b, 1 << level)
     nbytes = int(lib().ff_run_level_scratch_bytes(W, H, level))
-    scratch = torch.empty(nbytes, dtype=torch.uint8, device=desc_a.device)
+    if scratch is None:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=desc_a.device)
+    elif scratch.numel() * scratch.element_size() < nbytes:
+        raise ValueError("run_level: scratch too small")
     check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, level, params.to_c(),
                              stream_id, mode, _ptr(nn_key, torch.int64), _ptr(coarse_flow, torch.int16),
                              _ptr(coarse_cost, torch.int32), _ptr(flow, torch.int16), _ptr(cost, torch.int32),
-                             _ptr(scratch), nbytes, _ptr(n_evals, torch.int64), _stream()), "ff_run_level")
+                             _ptr(scratch), nbytes, _ptr(n_evals, torch.int64), _ptr(n_work, torch.int64),
+                             _stream()), "ff_run_level")
+
+
+def level_launches(params: Params, level: int, cost_kind: int = 0) -> int:
+    """Blocked launches the call's tables give one scale (ff_level_launches)."""
+    t = params.tuning.to_c() if params.tuning is not None else None
+    return int(lib().ff_level_launches(ctypes.byref(t) if t is not None else None, params.iters, level, cost_kind))
 
 
 def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: bool = True):
@@ -212,39 +255,6 @@ def flow_fields_two_backward(img1, img2, params: Params, seed2: int | None = Non
                                           o2["flow_fwd"], o2["cost_fwd"], params.eps)
     out["flow_bwd2"], out["cost_bwd2"] = o2["flow_fwd"], o2["cost_fwd"]
     return out
-
-
-def level_variants() -> list:
-    """Current level-kernel variant per scale (index log2 n)."""
-    return [int(lib().ff_get_level_variant(k)) for k in range(7)]
-
-
-def set_level_variants(table) -> None:
-    """Sets the level-kernel variant of every scale (index log2 n)."""
-    for k, v in enumerate(table):
-        check(lib().ff_set_level_variant(k, int(v)), "ff_set_level_variant")
-
-
-def level_variants_f32() -> list:
-    """Current float-feature level-kernel variant per scale (index log2 n)."""
-    return [int(lib().ff_get_level_variant_f32(k)) for k in range(7)]
-
-
-def set_level_variants_f32(table) -> None:
-    """Sets the float-feature level-kernel variant of every scale (0: 16x16
-    tiles, 1: 8x8 tiles)."""
-    for k, v in enumerate(table):
-        check(lib().ff_set_level_variant_f32(k, int(v)), "ff_set_level_variant_f32")
-
-
-def level_passes(cost_kind: int = 0) -> list:
-    """Most propagation steps per blocked launch, per scale (0 = no limit)."""
-    return [int(lib().ff_get_level_passes(l2, cost_kind)) for l2 in range(7)]
-
-
-def set_level_passes(table, cost_kind: int = 0) -> None:
-    for l2, p in enumerate(table):
-        check(lib().ff_set_level_passes(l2, cost_kind, int(p)), "ff_set_level_passes")
 
 
 def workspace_bytes(W: int, H: int, params: Params) -> int:

@@ -118,42 +118,37 @@ def test_descriptor_map_bytes():
     assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0
 
 
-def test_float_level_variant_table_validation():
+def test_default_tuning_and_validation():
+    """The built-in launch tables, and tables out of range rejected before
+    anything is enqueued."""
     lib = ff.lib()
     assert lib.ff_level_variant_count_f32() == 5
-    assert ff.level_variants_f32() == [0, 0, 1, 1, 1, 1, 1]
-    assert lib.ff_get_level_variant_f32(7) == -1 and lib.ff_get_level_variant_f32(-1) == -1
-    assert lib.ff_set_level_variant_f32(0, 5) == ffi.FF_ERR_ARG
-    assert lib.ff_set_level_variant_f32(0, -1) == ffi.FF_ERR_ARG
-    assert lib.ff_set_level_variant_f32(7, 0) == ffi.FF_ERR_ARG
-    assert lib.ff_set_level_variant_f32(3, 0) == ffi.FF_OK and lib.ff_get_level_variant_f32(3) == 0
-    assert lib.ff_set_level_variant_f32(3, 1) == ffi.FF_OK
-
-
-def test_level_passes_table_validation():
-    lib = ff.lib()
-    assert lib.ff_get_level_passes(0, 0) == 0 and lib.ff_get_level_passes(7, 0) == -1
-    assert lib.ff_get_level_passes(0, 2) == -1
-    assert lib.ff_set_level_passes(0, 0, 65) == ffi.FF_ERR_ARG
-    assert lib.ff_set_level_passes(-1, 0, 1) == ffi.FF_ERR_ARG
-    assert lib.ff_set_level_passes(0, 3, 1) == ffi.FF_ERR_ARG
-    old = lib.ff_get_level_passes(2, 1)
-    assert lib.ff_set_level_passes(2, 1, 3) == ffi.FF_OK and lib.ff_get_level_passes(2, 1) == 3
-    assert lib.ff_set_level_passes(2, 1, old) == ffi.FF_OK
+    t = ff.default_tuning()
+    assert t.variant_f32 == [0, 0, 1, 1, 1, 1, 1] and t.passes_f32 == [1] * 7
+    assert all(0 <= v < lib.ff_level_variant_count() for v in t.variant) and t.passes == [0] * 7
+    fake = C.c_void_p(0x1000)
+    for bad in (dict(variant=[lib.ff_level_variant_count()] * 7), dict(variant=[-1] * 7), dict(passes=[65] * 7),
+                dict(passes_f32=[-1] * 7), dict(variant_f32=[5] * 7)):
+        q = ff.Params(tuning=t.replace(**bad)).to_c()
+        assert lib.ff_workspace_bytes(64, 64, C.byref(q)) == 0, bad
+        assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(q), fake, 1 << 30, fake, fake, fake, fake, fake, None,
+                                  None, None) == ffi.FF_ERR_ARG, bad
+    ok = ff.Params(tuning=t.replace(variant=[3] * 7, passes=[2] * 7)).to_c()
+    assert lib.ff_workspace_bytes(64, 64, C.byref(ok)) > 0
 
 
 def test_level_launches_follow_the_run_length_table():
     """Launches per scale: the halo of the blocked kernel holds 6 steps
-    (3 per side pair), the run-length table caps a run."""
+    (3 per side pair), the run-length table caps a run; tables per call."""
     lib = ff.lib()
-    old = lib.ff_get_level_passes(1, 0)
-    try:
-        for passes, T, expect in [(0, 6, 1), (0, 9, 2), (1, 6, 6), (2, 6, 3), (3, 6, 2), (4, 7, 2), (0, 1, 1)]:
-            assert lib.ff_set_level_passes(1, 0, passes) == ffi.FF_OK
-            assert lib.ff_level_launches(T, 1, 0) == expect, (passes, T)
-    finally:
-        lib.ff_set_level_passes(1, 0, old)
-    assert lib.ff_level_launches(0, 1, 0) == -1 and lib.ff_level_launches(6, 9, 0) == -1
+    t = ff.default_tuning()
+    for passes, T, expect in [(0, 6, 1), (0, 9, 2), (1, 6, 6), (2, 6, 3), (3, 6, 2), (4, 7, 2), (0, 1, 1)]:
+        tc = t.replace(passes=[passes] * 7).to_c()
+        assert lib.ff_level_launches(C.byref(tc), T, 1, 0) == expect, (passes, T)
+        assert ff.level_launches(ff.Params(iters=T, tuning=t.replace(passes=[passes] * 7)), 1) == expect
+    assert lib.ff_level_launches(None, 6, 1, 0) == 1  # the built-in table
+    assert lib.ff_level_launches(None, 0, 1, 0) == -1 and lib.ff_level_launches(None, 6, 9, 0) == -1
+    assert lib.ff_level_launches(None, 6, 1, 2) == -1
 
 
 def test_noalloc_region_filter_validation():

@@ -10,6 +10,7 @@ import torch
 
 import oracle
 import paper_1703_02563_amd as ff
+from tuning_util import with_tuning
 from ffgen import CONFIG_PARAMS, batch_shapes, make_pair, random_images
 from paper_1703_02563_amd.batch import BatchFlowFields
 
@@ -104,25 +105,20 @@ def test_batch_with_multi_launch_scales_equals_single_pair_path():
     path alternates its grid buffers like the single-pair path."""
     from paper_1703_02563_amd.batch import BatchFlowFields
     c = CONFIG_PARAMS[4]
-    prm = ff.Params(levels=c.levels, iters=c.iters)
+    prm = with_tuning(ff.Params(levels=c.levels, iters=c.iters), passes=[1, 2, 1, 3, 2, 0, 0])
     shapes = [(192, 256), (231, 300), (200, 451)]
-    sp = ff.level_passes(0)
-    try:
-        ff.set_level_passes([1, 2, 1, 3, 2, 0, 0], 0)
-        b = BatchFlowFields(shapes, prm)
-        imgs = []
-        for k, shp in enumerate(shapes):
-            p = make_pair(4, k, shape=shp)
-            i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
-            imgs.append((i1, i2))
-            b.set_pair(k, i1, i2)
-        b.run()
-        for k, (i1, i2) in enumerate(imgs):
-            g = ff.flow_fields(i1, i2, prm)
-            for key in ("flow_fwd", "flow_bwd", "keep_fwd"):
-                assert torch.equal(b.out[k][key], g[key]), (k, key)
-    finally:
-        ff.set_level_passes(sp, 0)
+    b = BatchFlowFields(shapes, prm)
+    imgs = []
+    for k, shp in enumerate(shapes):
+        p = make_pair(4, k, shape=shp)
+        i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
+        imgs.append((i1, i2))
+        b.set_pair(k, i1, i2)
+    b.run()
+    for k, (i1, i2) in enumerate(imgs):
+        g = ff.flow_fields(i1, i2, prm)
+        for key in ("flow_fwd", "flow_bwd", "keep_fwd"):
+            assert torch.equal(b.out[k][key], g[key]), (k, key)
 
 
 @pytest.mark.parametrize("tables", [{"variants": [16, 17, 13, 14, 16, 3, 3], "passes": [7, 7, 7, 7, 7, 0, 0]},
@@ -130,11 +126,11 @@ def test_batch_with_multi_launch_scales_equals_single_pair_path():
 def test_batch_wide_halo_variants_equal_single_pair_path(tables):
     """Batched launches of the quad variants with halos of 4 and 6, at the
     longest runs their windows allow (run lengths above that are cut to the
-    halo), equal the single-pair path on the process-wide tables."""
+    halo), equal the single-pair path on the built-in tables."""
     c = CONFIG_PARAMS[4]
     prm = ff.Params(levels=c.levels, iters=c.iters)
     shapes = [(192, 256), (231, 300), (200, 451), (17, 700)]
-    b = BatchFlowFields(shapes, prm, tables=tables)
+    b = BatchFlowFields(shapes, with_tuning(prm, variant=tables["variants"], passes=tables["passes"]))
     imgs = []
     for k, shp in enumerate(shapes):
         p = make_pair(4, k, shape=shp)

@@ -13,6 +13,7 @@ import torch.nn.functional as F
 
 import oracle
 import paper_1703_02563_amd as ff
+from tuning_util import with_tuning
 from descnet_ref import LAYERS, bf16, forward, torch_weight
 from paper_1703_02563_amd import learned as Lm
 from test_learned_oracle import feature_canvas, feature_pyramid
@@ -232,19 +233,11 @@ def test_learned_flow_fields_bit_exact(shape, L, T, passes, tiles):
     F1 = canvas[pad:pad + H, pad:pad + W].copy()
     F2 = canvas[pad - 3:pad - 3 + H, pad + 2:pad + 2 + W].copy() + feature_canvas(12, H, W) * 0.05
     m1, m2 = feature_pyramid(F1, L), feature_pyramid(F2, L)
-    prm = ff.Params(levels=L, iters=T)
+    prm = with_tuning(ff.Params(levels=L, iters=T), passes_f32=[passes] * 7,
+                      **({} if tiles is None else {"variant_f32": [tiles] * 7}))
     o = oracle.flow_fields_f32(m1, m2, L, T, nthreads=NT)
-    saved, saved_v = ff.level_passes(1), ff.level_variants_f32()
-    try:
-        ff.set_level_passes([passes] * 7, 1)
-        if tiles is not None:
-            ff.set_level_variants_f32([tiles] * 7)
-        g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2],
-                               prm)
-        torch.cuda.synchronize()
-    finally:
-        ff.set_level_passes(saved, 1)
-        ff.set_level_variants_f32(saved_v)
+    g = Lm.flow_fields_f32([torch.from_numpy(a).cuda() for a in m1], [torch.from_numpy(a).cuda() for a in m2], prm)
+    torch.cuda.synchronize()
     for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
         assert np.array_equal(g[k].cpu().numpy(), o[k]), k
     for k in ("cost_fwd", "cost_bwd"):

@@ -13,6 +13,7 @@ import torch
 
 import oracle
 import paper_1703_02563_amd as ff
+from tuning_util import with_tuning
 from ffgen import CONFIG_PARAMS, FF_SEED, make_pair, random_images
 
 pytestmark = pytest.mark.gpu
@@ -278,17 +279,12 @@ def test_level_kernel_variants_bit_exact(config):
     prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den)
     o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed,
                            nthreads=NT)
-    saved = ff.level_variants()
-    try:
-        for v in range(int(ff.lib().ff_level_variant_count())):
-            ff.set_level_variants([v] * 7)
-            g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
-            for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
-                assert np.array_equal(host(g[k]), o[k]), (v, k)
-            assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"]), v
-            assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], v
-    finally:
-        ff.set_level_variants(saved)
+    for v in range(int(ff.lib().ff_level_variant_count())):
+        g = ff.flow_fields(dev(p.img1), dev(p.img2), with_tuning(prm, variant=[v] * 7))
+        for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
+            assert np.array_equal(host(g[k]), o[k]), (v, k)
+        assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"]), v
+        assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], v
 
 
 @pytest.mark.parametrize("shape,level,T,R", [((61, 83), 0, 6, (1, 1)), ((61, 83), 1, 4, (3, 2)),
@@ -349,16 +345,11 @@ def test_run_length_does_not_change_results(passes):
     c = CONFIG_PARAMS[1]
     prm = ff.Params(levels=c.levels, iters=c.iters)
     o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
-    saved = ff.level_passes(0)
-    try:
-        ff.set_level_passes([passes] * 7, 0)
-        g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
-        for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
-            assert np.array_equal(host(g[k]), o[k]), k
-        assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"])
-        assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
-    finally:
-        ff.set_level_passes(saved, 0)
+    g = ff.flow_fields(dev(p.img1), dev(p.img2), with_tuning(prm, passes=[passes] * 7))
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(host(g[k]), o[k]), k
+    assert np.array_equal(as_u32(g["cost_fwd"]), o["cost_fwd"])
+    assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
 
 
 @pytest.mark.parametrize("table", [([4, 7, 6, 6, 6, 3, 3], [1, 2, 2, 3, 3, 0, 0]),
@@ -376,19 +367,13 @@ def test_mixed_variant_and_run_length_tables_bit_exact(table, case):
     c = CONFIG_PARAMS[2]
     prm = ff.Params(levels=c.levels, iters=c.iters)
     o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, nthreads=NT)
-    sv, sp = ff.level_variants(), ff.level_passes(0)
-    try:
-        ff.set_level_variants(table[0])
-        ff.set_level_passes(table[1], 0)
-        for _ in range(2):
-            g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
-            for key in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
-                assert np.array_equal(host(g[key]), o[key]), key
-            assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"])
-            assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
-    finally:
-        ff.set_level_variants(sv)
-        ff.set_level_passes(sp, 0)
+    prm = with_tuning(prm, variant=table[0], passes=table[1])
+    for _ in range(2):
+        g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+        for key in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+            assert np.array_equal(host(g[key]), o[key]), key
+        assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"])
+        assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"]
 
 
 @pytest.mark.parametrize("mode", [0, 2])
@@ -421,15 +406,10 @@ def test_run_level_multi_launch_bit_exact(mode, passes):
         if t < T - 1:
             ef, ec, k = oracle.random_search(Da, Db, n, 1, prm.seed, 0, level, t, ef, ec, nthreads=NT)
             ne += k
-    sp = ff.level_passes(0)
-    try:
-        ff.set_level_passes([passes] * 7, 0)
-        cnt = counter()
-        ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, prm, 0, mode, gf, gc,
-                     coarse_flow=None if cflow is None else dev(cflow),
-                     coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
-    finally:
-        ff.set_level_passes(sp, 0)
+    cnt = counter()
+    ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, with_tuning(prm, passes=[passes] * 7), 0, mode, gf,
+                 gc, coarse_flow=None if cflow is None else dev(cflow),
+                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
@@ -473,3 +453,42 @@ def test_propagation_ties_bit_exact(blocked):
         assert np.array_equal(host(gf), ef), cells
         assert np.array_equal(as_u32(gc), ec), cells
         assert int(host(cnt)[0]) == ne
+
+
+def test_two_streams_with_different_tables_run_concurrently():
+    """Launch tables travel with each call: two threads enqueue calls with
+    different tables on two streams at once, and both results are the
+    oracle's."""
+    import threading
+    p = make_pair(1)
+    c = CONFIG_PARAMS[1]
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed, nthreads=NT)
+    base = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den)
+    prms = [with_tuning(base, variant=[16, 17, 14, 15, 15, 3, 3], passes=[2, 2, 3, 2, 2, 0, 0]),
+            with_tuning(base, variant=[2, 5, 3, 7, 6, 3, 3], passes=[1, 1, 1, 1, 1, 1, 1])]
+    i1, i2 = dev(p.img1), dev(p.img2)
+    runners = [ff.FlowFields(160, 120, prm) for prm in prms]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                for _ in range(20):
+                    runners[k](i1, i2)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors
+    for r in runners:
+        for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+            assert np.array_equal(host(r.out[k]), o[k]), k
+        assert np.array_equal(as_u32(r.out["cost_fwd"]), o["cost_fwd"])
+        assert tuple(int(x) for x in host(r.out["n_evals"])) == o["n_evals"]

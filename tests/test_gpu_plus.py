@@ -13,6 +13,7 @@ import torch
 
 import oracle
 import paper_1703_02563_amd as ff
+from tuning_util import with_tuning
 from ffgen import CONFIG_PARAMS, batch_shapes, make_pair, random_images
 from paper_1703_02563_amd.batch import BatchFlowFields
 from test_gpu_parity import _compare_full, _random_level_state, as_u32, counter, dev, host, to_lib
@@ -66,20 +67,14 @@ def test_plus_every_level_variant():
     prm = _params(1, SCHEDULES[0])
     o = oracle.flow_fields(p.img1, p.img2, prm.levels, prm.iters, prm.radius, prm.R_num, prm.R_den, prm.eps,
                            prm.seed, nthreads=NT, plus_iters=prm.plus_iters, Rp_num=prm.Rp_num)
-    sv, sp = ff.level_variants(), ff.level_passes(0)
-    try:
-        for passes in (0, 3):
-            ff.set_level_passes([passes] * 7, 0)
-            for v in range(int(ff.lib().ff_level_variant_count())):
-                ff.set_level_variants([v] * 7)
-                g = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
-                for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
-                    assert np.array_equal(host(g[k]), o[k]), (passes, v, k)
-                assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"]), (passes, v)
-                assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], (passes, v)
-    finally:
-        ff.set_level_variants(sv)
-        ff.set_level_passes(sp, 0)
+    for passes in (0, 3):
+        for v in range(int(ff.lib().ff_level_variant_count())):
+            pv = with_tuning(prm, variant=[v] * 7, passes=[passes] * 7)
+            g = ff.flow_fields(dev(p.img1), dev(p.img2), pv)
+            for k in ("flow_fwd", "flow_bwd", "keep_fwd"):
+                assert np.array_equal(host(g[k]), o[k]), (passes, v, k)
+            assert np.array_equal(as_u32(g["cost_bwd"]), o["cost_bwd"]), (passes, v)
+            assert tuple(int(x) for x in host(g["n_evals"])) == o["n_evals"], (passes, v)
 
 
 def test_plus_batch_equals_single_pair_path():
@@ -284,14 +279,10 @@ def test_forward_only_equals_the_forward_part(radius, stepwise):
     p = make_pair(1)
     c = CONFIG_PARAMS[1]
     prm = ff.Params(levels=c.levels, iters=c.iters, radius=radius, seed=c.seed)
-    sv = ff.level_variants()
-    try:
-        if stepwise:
-            ff.set_level_variants([int(ff.lib().ff_level_variant_count()) - 1] * 7)
-        full = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
-        fwd = ff.flow_fields(dev(p.img1), dev(p.img2), prm, backward=False)
-    finally:
-        ff.set_level_variants(sv)
+    if stepwise:
+        prm = with_tuning(prm, variant=[int(ff.lib().ff_level_variant_count()) - 1] * 7)
+    full = ff.flow_fields(dev(p.img1), dev(p.img2), prm)
+    fwd = ff.flow_fields(dev(p.img1), dev(p.img2), prm, backward=False)
     assert set(fwd) == {"flow_fwd", "cost_fwd", "n_evals"}
     assert torch.equal(fwd["flow_fwd"], full["flow_fwd"]) and torch.equal(fwd["cost_fwd"], full["cost_fwd"])
     ne = host(fwd["n_evals"])
