@@ -35,3 +35,25 @@ def forward(x, ws, bs, round_bf16=False, delta=None):
     if delta is not None:
         h = l2norm(h, delta)
     return h.permute(0, 2, 3, 1)
+
+
+def reference_chain(x, ws, bs, probe):
+    """The network's forward in float64 with the kernels' rounding points
+    (bf16 activations after the first two layers) and its exact float64
+    backward (no gradient rounding): per layer the activations a_k, outputs
+    y_k, and the weight, bias and upstream gradients."""
+    a, ys = [x], []
+    for k, (cin, cout, relu) in enumerate(LAYERS):
+        y = F.conv2d(a[-1], torch_weight(ws[k]), bs[k], padding=1)
+        ys.append(y)
+        if relu:
+            a.append(bf16(torch.relu(y)))
+    g = probe
+    gw, gb, gy = [None] * 3, [None] * 3, [None] * 3
+    for k in (2, 1, 0):
+        gy[k] = g
+        gw[k] = torch.nn.grad.conv2d_weight(a[k], torch_weight(ws[k]).shape, g, padding=1)
+        gb[k] = g.sum((0, 2, 3))
+        if k:
+            g = torch.nn.grad.conv2d_input(a[k].shape, torch_weight(ws[k]), g, padding=1) * (ys[k - 1] > 0)
+    return a, ys, gw, gb, gy

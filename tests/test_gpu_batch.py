@@ -1,6 +1,5 @@
-"""Batched Flow Fields: every pair of a batch equals its single-pair result,
-which the other GPU tests pin to the oracle; a few pairs are compared with
-the oracle directly.  Results do not depend on batch order, and graph
+"""Batched Flow Fields: every pair of a batch equals its single-pair result
+and, for all 64 pairs of the batched workload, the oracle's.  Results do not depend on batch order, and graph
 replays repeat the eager results."""
 import os
 
@@ -69,7 +68,22 @@ def test_config4_batch_equals_single_pair_path():
         single = _host(ff.flow_fields(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), prm))
         for key in KEYS:
             assert np.array_equal(outs[k][key], single[key]), (k, key)
-    for k in (0, 17):  # and straight against the oracle
+
+
+@pytest.fixture(scope="module")
+def config4_outputs():
+    """The 64-pair batch of the batched workload, run once for the oracle
+    comparisons below."""
+    b, pairs, prm, _ = _config4_batch(64)
+    return [_host(o) for o in b.run()], pairs, prm
+
+
+@pytest.mark.parametrize("group", range(8))
+def test_config4_batch_matches_oracle(config4_outputs, group):
+    """Every pair of the 64-pair batch (sizes 256-1280 x 192-512) against the
+    oracle, eight pairs per test."""
+    outs, pairs, prm = config4_outputs
+    for k in range(8 * group, 8 * group + 8):
         _check_oracle(pairs[k].img1, pairs[k].img2, outs[k], prm)
 
 

@@ -492,3 +492,31 @@ def test_two_streams_with_different_tables_run_concurrently():
             assert np.array_equal(host(r.out[k]), o[k]), k
         assert np.array_equal(as_u32(r.out["cost_fwd"]), o["cost_fwd"])
         assert tuple(int(x) for x in host(r.out["n_evals"])) == o["n_evals"]
+
+
+@pytest.mark.parametrize("radius", [3, 2])
+def test_run_level_work_counters(radius):
+    """ff_run_level's counters of computed evaluations: never above the
+    schedule's count, owned cells <= all cells, and for the per-step
+    kernels (no halo) the two are equal; the blocked kernels compute
+    most of the schedule's evaluations (a consistent state fixes only the
+    repeated vertical sources)."""
+    H, W, T = 130, 200, 5
+    prm = ff.Params(levels=1, iters=T, radius=radius)
+    ia, ib = random_images(77, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
+    Db = oracle.descriptor(oracle.blur(ib, 1), 1)
+    cflow, ccost = _random_level_state(6, H, W, 2)
+    gf = torch.empty((H, W, 2), dtype=torch.int16, device="cuda")
+    gc = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    cnt = counter()
+    work = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ff.run_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 0, prm, 0, 2, gf, gc, coarse_flow=dev(cflow),
+                 coarse_cost=dev(ccost.view(np.int32)), n_evals=cnt, n_work=work)
+    ne = int(host(cnt)[0])
+    owned, every = (int(v) for v in host(work))
+    assert 0 < owned <= ne and owned <= every
+    if radius != 3:
+        assert owned == every
+    else:
+        assert every > owned and owned > 0.8 * ne
