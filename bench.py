@@ -141,8 +141,10 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     counted) x 196 v_sad_u8 lane-ops."""
     H, W = img1.shape
     L = params.levels
-    Da = [ff.descriptors(img1, 1 << lv)[1] for lv in range(L)]
-    Db = [ff.descriptors(img2, 1 << lv)[1] for lv in range(L)]
+    ma = [ff.descriptors(img1, 1 << lv, wform=True) for lv in range(L)]
+    mb = [ff.descriptors(img2, 1 << lv, wform=True) for lv in range(L)]
+    Da, Wa = [m[1] for m in ma], [m[2] for m in ma]
+    Db, Wb = [m[1] for m in mb], [m[2] for m in mb]
     Da1 = ff.descriptors(img1, 1, rowmajor=True)[2]
     Db1 = ff.descriptors(img2, 1, rowmajor=True)[2]
     _, _, key = ff.init_nn(Da1, Db1, Da[L - 1], Db[L - 1], 1 << (L - 1))
@@ -153,9 +155,10 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
         fl = torch.empty((Hn, Wn, 2), dtype=torch.int16, device=dev)
         co = torch.empty((Hn, Wn), dtype=torch.int32, device=dev)
         if prev is None:
-            ff.run_level(Da[lv], Db[lv], lv, params, 0, 1, fl, co, nn_key=key)
+            ff.run_level(Da[lv], Db[lv], lv, params, 0, 1, fl, co, nn_key=key, wform_a=Wa[lv], wform_b=Wb[lv])
         else:
-            ff.run_level(Da[lv], Db[lv], lv, params, 0, 2, fl, co, coarse_flow=prev[0], coarse_cost=prev[1])
+            ff.run_level(Da[lv], Db[lv], lv, params, 0, 2, fl, co, coarse_flow=prev[0], coarse_cost=prev[1],
+                         wform_a=Wa[lv], wform_b=Wb[lv])
         prev = (fl, co)
     fl0 = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
     co0 = torch.empty((H, W), dtype=torch.int32, device=dev)
@@ -165,7 +168,7 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
 
     def launch(counter=None, wk=None):
         ff.run_level(Da[0], Db[0], 0, params, 0, 2, fl0, co0, coarse_flow=prev[0], coarse_cost=prev[1],
-                     n_evals=counter, n_work=wk, scratch=scratch)
+                     n_evals=counter, n_work=wk, scratch=scratch, wform_a=Wa[0], wform_b=Wb[0])
 
     for _ in range(3):
         launch()

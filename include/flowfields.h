@@ -111,7 +111,9 @@ const char *ff_status_str(ff_status s);
  * img: [H][W]; blurred: [H][W] output; hsum: [H][W] uint16 scratch;
  * desc: the descriptor MAP of scale n (output, ff_descriptor_map_bytes);
  * desc_rowmajor (nullable): the same descriptors as plain [H][W][16] (the
- * input of ff_init_nn's nearest-neighbour search).
+ * input of ff_init_nn's nearest-neighbour search); wform (nullable): the
+ * weight-class row map of scale n (output, ff_wform_map_bytes), which the
+ * level kernels with weight-class evaluations read.
  * Descriptor map layout (every entry point that takes a "descriptor map"
  * expects it): P = 3n, Wp = W + 2P; Hp = H + 2P rows of Wp 16-byte entries;
  * entry (y + P, col(x + P)) holds desc[clamp(y)][clamp(x)] for x in
@@ -121,11 +123,25 @@ const char *ff_status_str(ff_status s);
  * are adjacent and a radius-3 patch around any in-image pixel needs no
  * clamping.  n <= 64. */
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum,
-                         uint8_t *blurred, uint8_t *desc, uint8_t *desc_rowmajor, void *stream);
+                         uint8_t *blurred, uint8_t *desc, uint8_t *desc_rowmajor, uint8_t *wform, void *stream);
 
 /* Bytes of a descriptor map of scale n (host): (W + 6n) * (H + 6n) * 16;
  * 0 for invalid sizes. */
 size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n);
+
+/* Weight-class row map of scale n (the cost of Eq. 3 written on the
+ * blurred image I^n): W * (H + 6n) entries of 16 bytes, entry (y + 3n) * W +
+ * x for y in [-3n, H + 3n) holding the 13 samples I^n(clamp(x + n a),
+ * clamp(y)), a = -6..6, grouped by how often the subsampled patch of a
+ * radius-3 cost counts them: bytes 0-3 a = -6, -5, 5, 6 (once); bytes 4-7
+ * a = -4, -3, 3, 4 (twice); bytes 8-11 a = -2, -1, 1, 2 (three times); byte
+ * 12 a = 0 (four times); bytes 13-15 zero.  For a pixel and a target both
+ * at least 3n inside the image, E_n = sum over b = -6..6 of w(b) times the
+ * weighted byte SADs of rows y + n b, w = 1,1,2,2,3,3,4,3,3,2,2,1,1: each
+ * descriptor byte is one blurred sample, so the 784 byte differences are
+ * 169 samples with multiplicities w(a) w(b).  Bytes (host); 0 for invalid
+ * sizes. */
+size_t ff_wform_map_bytes(int32_t W, int32_t H, int32_t n);
 
 /* Initial flow of the coarsest scale nc (Sec. 3.1 initialisation, Eq. 1;
  * Sec. 3.2 Eq. 4 with a single candidate): for every cell p of the grid of
@@ -252,13 +268,17 @@ ff_status ff_sparsify(const int16_t *flow_a, const uint8_t *keep_a, const int16_
  * ff_propagate_level and ff_random_search calls (same fields, same
  * evaluation count); radius 3 runs in temporally blocked launches that keep
  * the state on chip and skip evaluations whose value the consistent state
- * already fixes.  desc_a/desc_b: descriptor maps of scale n; params: host
+ * already fixes.  desc_a/desc_b: descriptor maps of scale n; wform_a/wform_b
+ * (nullable, both or neither): weight-class row maps of scale n, which the
+ * weight-class variants of the launch table need (without them those
+ * variants run their descriptor-quad twins); params: host
  * (params->tuning selects the launches).  n_work: nullable device uint64
  * [2] counters of the evaluations the kernels actually compute (added to):
  * [0] those of cells the launch owns, [1] all of them, the recomputed halo
  * cells of the blocked launches included; n_evals counts the evaluations of
  * the schedule itself, of which a consistent state makes some unnecessary. */
-ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
+ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8_t *wform_a, const uint8_t *wform_b,
+                       int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
                        void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream);

@@ -70,7 +70,7 @@ ScaleSteps scale_steps(const ff_params *p, int lv) {
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc[2][kMaxLevels], desc1, nb, keys, grids, sgrids, evals, total;
+  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, nb, keys, grids, sgrids, evals, total;
   size_t N, Npad, M;
   int L;
 };
@@ -95,6 +95,11 @@ Layout layout(int W, int H, const ff_params *p) {
     for (int lv = 0; lv < l.L; ++lv) {
       l.desc[im][lv] = off;
       off = align256(off + desc_map_bytes(W, H, 1 << lv));
+    }
+  for (int im = 0; im < 2; ++im)
+    for (int lv = 0; lv < l.L; ++lv) {
+      l.wform[im][lv] = off;
+      off = align256(off + ffk::wform_bytes(W, H, 1 << lv));
     }
   l.desc1 = off; off = align256(off + 2 * l.N * 16);
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
@@ -294,15 +299,20 @@ size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n) {
   return desc_map_bytes(W, H, n);
 }
 
+size_t ff_wform_map_bytes(int32_t W, int32_t H, int32_t n) {
+  if (!dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1))) return 0;
+  return ffk::wform_bytes(W, H, n);
+}
+
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum, uint8_t *blurred,
-                         uint8_t *desc, uint8_t *desc_rowmajor, void *stream) {
+                         uint8_t *desc, uint8_t *desc_rowmajor, uint8_t *wform, void *stream) {
   if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1)))
     return FF_ERR_ARG;
   ffh::DescJobs jobs{};
   jobs.W = W;
   jobs.H = H;
   jobs.count = 1;
-  jobs.job[0] = {img, hsum, blurred, desc, desc_rowmajor, n};
+  jobs.job[0] = {img, hsum, blurred, desc, desc_rowmajor, wform, n};
   return from_hip(ffh::launch_descriptors(jobs, (hipStream_t)stream));
 }
 
@@ -419,7 +429,8 @@ size_t ff_run_level_scratch_bytes(int32_t W, int32_t H, int32_t level) {
   return (size_t)ceil_div(W, 1 << level) * ceil_div(H, 1 << level) * 2 * sizeof(uint32_t);
 }
 
-ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t level,
+ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8_t *wform_a, const uint8_t *wform_b,
+                       int32_t W, int32_t H, int32_t level,
                        const ff_params *params, int32_t stream_id, int32_t mode, const uint64_t *nn_key,
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
                        void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream) {
@@ -436,6 +447,8 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, 
     k.ndir = 1;
     k.dir[0].Da = desc_a;
     k.dir[0].Db = desc_b;
+    k.dir[0].Wa = wform_a;
+    k.dir[0].Wb = wform_b;
     k.dir[0].flow = reinterpret_cast<int32_t *>(flow);
     k.dir[0].cost = cost;
     k.dir[0].nn_key = nn_key;
@@ -560,6 +573,7 @@ ff_status ff_batch_table(const ff_pair *pairs, int32_t npairs, const ff_params *
         t.hsum[im][lv] = reinterpret_cast<uint16_t *>(b + lay.hsum) + z * lay.N;
         t.blur[im][lv] = reinterpret_cast<uint8_t *>(b + lay.blur) + z * lay.N;
         t.desc[im][lv] = reinterpret_cast<uint8_t *>(b + lay.desc[im][lv]);
+        t.wform[im][lv] = reinterpret_cast<uint8_t *>(b + lay.wform[im][lv]);
       }
       t.desc1[im] = reinterpret_cast<uint8_t *>(b + lay.desc1) + (size_t)im * lay.N * 16;
       t.nb[im] = reinterpret_cast<int32_t *>(b + lay.nb) + (size_t)im * lay.Npad;
@@ -999,7 +1013,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       desc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.desc[im][lv]);
       jobs.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
                      reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, desc[im][lv],
-                     lv == 0 ? desc1[im] : nullptr, 1 << lv};
+                     lv == 0 ? desc1[im] : nullptr, reinterpret_cast<uint8_t *>(base + lay.wform[im][lv]), 1 << lv};
     }
   }
   hipError_t e = ffh::launch_descriptors(jobs, s);
@@ -1056,6 +1070,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       for (int dr = 0; dr < nd; ++dr) {
         k.dir[dr].Da = desc[dr][lv];
         k.dir[dr].Db = desc[dr ^ 1][lv];
+        k.dir[dr].Wa = reinterpret_cast<const uint8_t *>(base + lay.wform[dr][lv]);
+        k.dir[dr].Wb = reinterpret_cast<const uint8_t *>(base + lay.wform[dr ^ 1][lv]);
         k.dir[dr].flow = gflow[lv][dr];
         k.dir[dr].cost = gcost[lv][dr];
         k.dir[dr].nn_key = keys + (size_t)dr * lay.M;

@@ -78,11 +78,20 @@ __device__ __forceinline__ uint4 descriptor_at(const uint8_t *blurred, int W, in
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Weight-class row entry (wform_index) of pixel x of blurred row `row`.
+__device__ __forceinline__ uint4 wform_entry(const uint8_t *row, int W, int n, int x) {
+  auto at = [&](int a) { return (uint32_t)row[clampi(x + n * a, W - 1)]; };
+  return make_uint4(at(-6) | at(-5) << 8 | at(5) << 16 | at(6) << 24, at(-4) | at(-3) << 8 | at(3) << 16 | at(4) << 24,
+                    at(-2) | at(-1) << 8 | at(1) << 16 | at(2) << 24, at(0));
+}
+
 // One workgroup per stored row yp of one map: the four blurred rows its
 // descriptors sample (y + n(2gy - 3), clamped) are staged in LDS once, then
 // every entry of the padded row (coalesced 16-byte stores) takes its 16
 // samples from there.  Entries that are image pixels also go to the
-// row-major copy when one is requested.  Dynamic LDS: 4 * row_stride(W).
+// row-major copy when one is requested.  The weight-class row map has the
+// same rows (y + 3n); its row yp is written from a fifth staged row, the
+// blurred row y itself.  Dynamic LDS: 5 * row_stride(W).
 __host__ __device__ __forceinline__ int desc_row_stride(int W) { return (W + 15) & ~15; }
 
 __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
@@ -93,20 +102,27 @@ __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
   const int yp = blockIdx.x, Ws = desc_row_stride(W);
   if (yp >= Hp) return;  // workgroup-uniform
   const int yr = yp - P, y = clampi(yr, H - 1);
+  // staged rows g = 0..3: y + n(2g - 3); g = 4: y itself (weight-class map)
+  const int nrows = jb.wform ? 5 : 4;
+  auto src_row = [&](int g) { return g < 4 ? clampi(y + n * (2 * g - 3), H - 1) : y; };
   if ((W & 3) == 0) {  // rows start on 4-byte boundaries: dword loads
     const int wq = W >> 2;
-    for (int k = threadIdx.x; k < 4 * wq; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nrows * wq; k += blockDim.x) {
       const int g = k / wq, q = k - g * wq;
-      const uint32_t *row = reinterpret_cast<const uint32_t *>(jb.blurred + (size_t)clampi(y + n * (2 * g - 3), H - 1) * W);
+      const uint32_t *row = reinterpret_cast<const uint32_t *>(jb.blurred + (size_t)src_row(g) * W);
       reinterpret_cast<uint32_t *>(s_rows + g * Ws)[q] = row[q];
     }
   } else {
-    for (int k = threadIdx.x; k < 4 * W; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nrows * W; k += blockDim.x) {
       const int g = k / W, x = k - g * W;
-      s_rows[g * Ws + x] = jb.blurred[(size_t)clampi(y + n * (2 * g - 3), H - 1) * W + x];
+      s_rows[g * Ws + x] = jb.blurred[(size_t)src_row(g) * W + x];
     }
   }
   __syncthreads();
+  if (jb.wform) {
+    uint4 *wout = reinterpret_cast<uint4 *>(jb.wform) + (size_t)yp * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) wout[x] = wform_entry(s_rows + 4 * Ws, W, n, x);
+  }
   uint4 *out = reinterpret_cast<uint4 *>(jb.desc) + (size_t)yp * Wp;
   for (int c = threadIdx.x; c < Wp; c += blockDim.x) {
     const int xr = ffk::desc_pixel(c, l2, Wp) - P, x = clampi(xr, W - 1);
@@ -186,6 +202,16 @@ __global__ __launch_bounds__(256) void k_desc_batch(ffh::BatchStage st) {
       for (int yp = yp0; yp < yp1; ++yp) map[(size_t)yp * Wp + c] = d;
       if (r.lv == 0 && xr >= 0 && xr < W) reinterpret_cast<uint4 *>(r.bp->desc1[r.im])[(size_t)r.y * W + xr] = d;
     }
+    // weight-class rows: the same stored rows (y + 3n), the first and last
+    // image rows replicated into the border rows
+    uint4 *wmap = reinterpret_cast<uint4 *>(r.bp->wform[r.im][r.lv]);
+    if (wmap) {
+      const uint8_t *brow = b + (size_t)r.y * W;
+      for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        const uint4 e = wform_entry(brow, W, n, x);
+        for (int yp = yp0; yp < yp1; ++yp) wmap[(size_t)yp * W + x] = e;
+      }
+    }
   });
 }
 
@@ -210,7 +236,7 @@ hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
   hipLaunchKernelGGL(k_vsum, gvs, dim3(256), 0, stream, jobs);
   int pmax = 0;
   for (int k = 0; k < jobs.count; ++k) pmax = std::max(pmax, ffk::desc_pad(jobs.job[k].n));
-  const size_t lds = 4 * (size_t)desc_row_stride(jobs.W);
+  const size_t lds = 5 * (size_t)desc_row_stride(jobs.W);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {  // rows wider than 16 K pixels
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_desc),

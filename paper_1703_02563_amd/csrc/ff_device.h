@@ -60,6 +60,26 @@ __device__ __forceinline__ size_t desc_index(int x, int y, int log2n, int W) {
   return (size_t)(y + P) * Wp + desc_col(x + P, log2n, Wp);
 }
 
+// Weight-class row map of a scale-n blurred image I^n: one 16-byte entry per
+// pixel (x, y) for y in [-3n, H + 3n) (rows clamped), entry index
+// (y + 3n) * W + x.  The entry holds the 13 samples I^n(clamp(x + n a), y),
+// a = -6..6, grouped by the multiplicity w(a) = 1,1,2,2,3,3,4,3,3,2,2,1,1 with
+// which a sample enters the subsampled patch cost: dword 0 the samples of
+// weight 1 (a = -6, -5, 5, 6), dword 1 weight 2 (a = -4, -3, 3, 4), dword 2
+// weight 3 (a = -2, -1, 1, 2), dword 3 weight 4 (a = 0, then three zero
+// bytes).  For a pixel p and a target q both at least 3n inside the image,
+// E_n(p, q - p) = sum over row offsets b = -6..6 of w(b) * (1 s1 + 2 s2 +
+// 3 s3 + 4 s4), s_k = the byte SAD of dword k of the entries of rows
+// y + n b of the two maps (each descriptor byte is one blurred sample, so the
+// 784 byte differences of Eq. 3 are the 169 samples counted w(a) w(b) times).
+constexpr int kWformPad = 3;
+__host__ __device__ __forceinline__ size_t wform_index(int x, int y, int n, int W) {
+  return (size_t)(y + kWformPad * n) * W + x;
+}
+__host__ __device__ __forceinline__ size_t wform_bytes(int W, int H, int n) {
+  return (size_t)W * (H + 2 * kWformPad * n) * 16;
+}
+
 __device__ __forceinline__ int flow_x(int32_t f) { return (int)(int16_t)(f & 0xFFFF); }
 __device__ __forceinline__ int flow_y(int32_t f) { return f >> 16; }
 __device__ __forceinline__ int32_t pack_flow(int fx, int fy) {

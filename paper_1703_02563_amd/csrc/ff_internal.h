@@ -18,6 +18,7 @@ struct DescJob {
   uint8_t *blurred;
   uint8_t *desc;     // padded, phase-ordered map (see desc_index)
   uint8_t *compact;  // nullable: row-major [H][W][16] copy (the NN seed's input)
+  uint8_t *wform;    // nullable: weight-class row map (see wform_index)
   int n;
 };
 struct DescJobs {
@@ -99,6 +100,8 @@ constexpr int kLevelSeed = 2;      // seeds from the coarser grid, other cells U
 struct LevelKDir {
   const uint8_t *Da;
   const uint8_t *Db;
+  const uint8_t *Wa;  // weight-class row maps of the two images (nullable: the
+  const uint8_t *Wb;  //   variants that use them fall back to descriptor quads)
   int32_t *flow;            // written: the owned cells after the run
   uint32_t *cost;
   const int32_t *flow_in;   // read by a continuing run (never the buffer it writes:
@@ -146,6 +149,7 @@ FF_LEVEL_SCALE_DECL(6)
 int level_window_halo(int variant);              // window halo of a byte-descriptor variant
 int level_window_halo_f32(int variant);          // the same for a float-feature variant
 bool level_map_fits(int W, int H, int log2n);  // scale-n map under 2^31 bytes (quad evaluations)
+bool level_uses_wform(int variant);  // the variant evaluates interior cells on weight-class row maps
 void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();      // byte-descriptor variants + the step-wise schedule
 int level_variant_count_f32();
@@ -163,6 +167,7 @@ struct BatchPair {
   uint16_t *hsum[2][kMaxScales];
   uint8_t *blur[2][kMaxScales];
   uint8_t *desc[2][kMaxScales];  // padded maps
+  uint8_t *wform[2][kMaxScales]; // weight-class row maps
   uint8_t *desc1[2];             // row-major scale-1 descriptors (NN seed)
   int32_t *nb[2];
   uint64_t *keys[2];

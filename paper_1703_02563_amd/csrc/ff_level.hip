@@ -17,16 +17,21 @@ constexpr int kH = ffh::kLevelHalo;
 // the grid is too small to give every compute unit a tile.  A variant with
 // quad evaluations addresses image b with 32-bit offsets; for a larger map
 // its fallback (a halo at least as wide; batches count their work items
-// with level_tiles, which follows the fallback) runs instead.
+// with level_tiles, which follows the fallback) runs instead.  Variants 18-23
+// evaluate interior cells on the weight-class row maps; without those maps
+// (a caller that passes none) their descriptor-quad twin (`nowf`, same tile
+// and halo) runs.
 struct Variant {
-  int tw, th, halo, fallback;
+  int tw, th, halo, fallback, nowf;
 };
-constexpr Variant kVariants[] = {{64, 32, kH, 0}, {32, 16, kH, 1}, {32, 16, kH, 2}, {16, 16, kH, 3},
-                                 {32, 32, kH, 4}, {32, 16, kH, 5}, {16, 16, kH, 6}, {32, 32, kH, 7},
-                                 {8, 8, kH, 8},   {16, 16, kH, 9}, {16, 16, kH, 10}, {16, 16, 2, 3},
-                                 {32, 16, 2, 2},  {16, 16, kH, 3}, {8, 8, kH, 8},   {8, 8, 2, 8},
-                                 {32, 16, 4, 2},  {16, 16, 4, 3}};
-constexpr int kNumVariants = 18;
+constexpr Variant kVariants[] = {
+    {64, 32, kH, 0, 0},   {32, 16, kH, 1, 1},   {32, 16, kH, 2, 2},   {16, 16, kH, 3, 3},   {32, 32, kH, 4, 4},
+    {32, 16, kH, 5, 5},   {16, 16, kH, 6, 6},   {32, 32, kH, 7, 7},   {8, 8, kH, 8, 8},     {16, 16, kH, 9, 9},
+    {16, 16, kH, 10, 10}, {16, 16, 2, 3, 11},   {32, 16, 2, 2, 12},   {16, 16, kH, 3, 13},  {8, 8, kH, 8, 14},
+    {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},   {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},
+    {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15}};
+constexpr int kNumVariants = 24;
+constexpr int kFirstWform = 18;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);
@@ -108,11 +113,23 @@ bool level_map_fits(int W, int H, int log2n) {
   return ((size_t)W + 2 * P) * ((size_t)H + 2 * P) * 16 < ((size_t)1 << 31);
 }
 
+bool level_uses_wform(int variant) { return variant >= kFirstWform && variant < kNumVariants; }
+
 // The table's variant, or its fallback where image b's map is too large
-// for the 32-bit offsets of the quad evaluations.
-static int launch_variant(int variant, bool map_fits) {
-  const int v = blocked_variant(variant);
-  return (v >= 0 && !map_fits) ? kVariants[v].fallback : v;
+// for the 32-bit offsets of the quad evaluations, or its descriptor-quad
+// twin where the weight-class maps are missing.
+static int launch_variant(int variant, bool map_fits, bool has_wform) {
+  int v = blocked_variant(variant);
+  if (v < 0 || v >= kNumVariants) return v;
+  if (!map_fits) return kVariants[v].fallback;
+  if (!has_wform) v = kVariants[v].nowf;
+  return v;
+}
+
+static bool dirs_have_wform(const LevelKArgs &a) {
+  for (int d = 0; d < a.ndir; ++d)
+    if (!a.dir[d].Wa || !a.dir[d].Wb) return false;
+  return true;
 }
 
 hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
@@ -121,16 +138,17 @@ hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
     if (l2 < 0 || l2 >= 7) return hipErrorInvalidValue;
     return kScaleF32[l2](a, a.variant, stream);
   }
-  return dispatch(a, nullptr, l2, launch_variant(a.variant, level_map_fits(a.W, a.H, l2)), stream);
+  return dispatch(a, nullptr, l2, launch_variant(a.variant, level_map_fits(a.W, a.H, l2), dirs_have_wform(a)),
+                  stream);
 }
 
 hipError_t launch_batch_level(const LevelKArgs &base, const BatchStage &st, bool maps_fit, hipStream_t stream) {
   const int l2 = log2_of(base.n);
-  return dispatch(base, &st, l2, launch_variant(base.variant, maps_fit), stream);
+  return dispatch(base, &st, l2, launch_variant(base.variant, maps_fit, true), stream);
 }
 
 int level_tiles(int Wn, int Hn, int variant, bool maps_fit) {
-  const int v = launch_variant(variant, maps_fit);
+  const int v = launch_variant(variant, maps_fit, true);
   if (v < 0 || v >= kNumVariants) return 0;
   const Variant t = kVariants[v];
   return ((Wn + t.tw - 1) / t.tw) * ((Hn + t.th - 1) / t.th);

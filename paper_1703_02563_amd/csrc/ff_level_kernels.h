@@ -136,6 +136,67 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
   return s;
 }
 
+// The same with image a's patch also read from its padded map (a quad per
+// evaluation; the cells the weight-class evaluation does not cover).
+template <int LOG2N>
+__device__ __forceinline__ uint32_t eval_quad_gg(__amdgpu_buffer_rsrc_t da, __amdgpu_buffer_rsrc_t db, int W, int ax,
+                                                 int ay, int bx, int by, int r) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  const int rowb = n * (W + 2 * P) * 16;
+  const int u1 = r, u2 = min(r + 4, K - 1);
+  const int offa = (int)ffk::desc_index(ax - kR * n, ay - kR * n, LOG2N, W) * 16;
+  const int offb = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
+  uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    const auto a1 = __builtin_amdgcn_raw_buffer_load_b128(da, offa + u1 * 16, v * rowb, 0);
+    const auto a2 = __builtin_amdgcn_raw_buffer_load_b128(da, offa + u2 * 16, v * rowb, 0);
+    const auto b1 = __builtin_amdgcn_raw_buffer_load_b128(db, offb + u1 * 16, v * rowb, 0);
+    const auto b2 = __builtin_amdgcn_raw_buffer_load_b128(db, offb + u2 * 16, v * rowb, 0);
+    s1 = ffk::sad16(make_uint4(a1[0], a1[1], a1[2], a1[3]), make_uint4(b1[0], b1[1], b1[2], b1[3]), s1);
+    s2 = ffk::sad16(make_uint4(a2[0], a2[1], a2[2], a2[3]), make_uint4(b2[0], b2[1], b2[2], b2[3]), s2);
+  }
+  uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  return s;
+}
+
+// E_n(p, f) by one lane from the weight-class row maps (wform_index), for a
+// cell p and a target (bx, by) both at least 3n inside the image: the 13
+// rows y + n b (b = -6..6) of image a come from LDS (`pa`: the cell's entry
+// of row b = -6 in a window of row length LW), those of image b from its
+// map (one 16-byte load per row, the row step in the scalar offset); four
+// byte SADs per row go to the accumulator of its (row weight, column
+// weight) class, and E = sum_{l,k} l k T[l][k].
+template <int LOG2N, int LW>
+__device__ __forceinline__ uint32_t eval_wform(const uint4 *pa, __amdgpu_buffer_rsrc_t wb, int W, int bx, int by) {
+  constexpr int n = 1 << LOG2N, K = 13;
+  constexpr int kRowClass[K] = {0, 0, 1, 1, 2, 2, 3, 2, 2, 1, 1, 0, 0};  // w(b) - 1
+  const int rowb = n * W * 16;
+  const int off = (int)ffk::wform_index(bx, by - 6 * n, n, W) * 16;
+  uint4 B[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(wb, off, b * rowb, 0);
+    B[b] = make_uint4(x[0], x[1], x[2], x[3]);
+  }
+  uint32_t T[4][4] = {};
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const uint4 A = pa[b * LW];
+    const int l = kRowClass[b];
+    T[l][0] = __builtin_amdgcn_sad_u8(A.x, B[b].x, T[l][0]);
+    T[l][1] = __builtin_amdgcn_sad_u8(A.y, B[b].y, T[l][1]);
+    T[l][2] = __builtin_amdgcn_sad_u8(A.z, B[b].z, T[l][2]);
+    T[l][3] = __builtin_amdgcn_sad_u8(A.w, B[b].w, T[l][3]);
+  }
+  uint32_t R[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) R[l] = T[l][0] + 2 * T[l][1] + 3 * T[l][2] + 4 * T[l][3];
+  return R[0] + 2 * R[1] + 3 * R[2] + 4 * R[3];
+}
+
 // Float learned-feature cost (Eq. 3 with the squared-difference data term)
 // by a quad of lanes: lane r owns channels 4r .. 4r+3 and sums their terms
 // with one fused multiply-add each in the order v, u, c; the quad then adds
@@ -183,22 +244,30 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   constexpr int n = 1 << LOG2N;
   // EV 3 and float features: every evaluation by a quad of lanes
   // (eval_quad, eval_quad_f32); the candidate flows of a random-search step
-  // are then parked in s_flags
-  constexpr bool QUAD = EV == 3 || F32;
+  // are then parked in s_flags.  EV 4: evaluations whose cell and target lie
+  // 3n inside the image by one lane each on the weight-class row maps
+  // (eval_wform, image a's rows staged in LDS), the others by a quad
+  // reading both descriptor maps (eval_quad_gg); such queues fill from the
+  // front (weight-class) and from the back (descriptor quads).
+  constexpr bool WF = EV == 4;
+  constexpr bool QUAD = EV == 3 || F32 || WF;
+  constexpr int QCAP = G::LH * G::LW + G::LH;
   constexpr int kQuads = kThreads / 4;
   using FlagT = std::conditional_t<QUAD, uint32_t, uint8_t>;
   __shared__ int32_t s_flow[G::LH * G::LW];
   __shared__ uint32_t s_cost[G::LH * G::LW];
   // byte descriptors of image a on the level lattice (float features are
   // read from their padded map instead); 64-bit keys for float costs
-  __shared__ uint4 s_da[F32 ? 1 : G::DH * G::DW];
+  __shared__ uint4 s_da[(F32 || WF) ? 1 : G::DH * G::DW];
+  // weight-class row entries of image a: window rows gj0 - 6 ... gj0 + LH + 5
+  __shared__ uint4 s_wa[WF ? (G::LH + 12) * G::LW : 1];
   __shared__ float4 s_daf[F32 ? 4 * G::DH * G::DW : 1];
   __shared__ unsigned long long s_key[F32 ? G::LH * G::LW : 1];
-  __shared__ uint16_t s_queue[G::LH * G::LW + G::LH];  // queued evaluations: cell * 2 + vertical
+  __shared__ uint16_t s_queue[QCAP];  // queued evaluations: cell * 2 + vertical
   // candidate flags of the current half-sweep; with quads also the parked
   // random-search candidate flows
   __shared__ FlagT s_flags[G::LH * G::LW];
-  __shared__ unsigned int s_cnt, s_qlen, s_rlen;
+  __shared__ unsigned int s_cnt, s_qlen, s_rlen, s_blen, s_rblen;
   __shared__ unsigned int s_work[2];  // evaluations computed: owned cells, all cells
 
   const int tid = threadIdx.x, qr = tid & 3;
@@ -206,21 +275,33 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   const int ti0 = (tile % a.tiles_x) * TW, tj0 = (tile / a.tiles_x) * TH;
   const int oi1 = min(ti0 + TW, Wn), oj1 = min(tj0 + TH, Hn);
   const int gi0 = ti0 - HALO, gj0 = tj0 - HALO;  // grid coords of window cell (0, 0)
+  auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
   const uint4 *Db = reinterpret_cast<const uint4 *>(d.Db);
   if (tid == 0) {
     s_cnt = 0;
     s_qlen = 0;
     s_rlen = 0;
+    s_blen = 0;
+    s_rblen = 0;
     s_work[0] = 0;
     s_work[1] = 0;
   }
 
   // image-a descriptors on the level lattice around the window: every load
   // of a thread is issued before the first LDS store (one memory round trip)
-  constexpr int NS = F32 ? (4 * G::DH * G::DW + kThreads - 1) / kThreads : (G::DH * G::DW + kThreads - 1) / kThreads;
+  constexpr int NSTAGE = F32 ? 4 * G::DH * G::DW : (WF ? (G::LH + 12) * G::LW : G::DH * G::DW);
+  constexpr int NS = (NSTAGE + kThreads - 1) / kThreads;
   uint4 sv[F32 ? 1 : NS];
   float4 sf[F32 ? NS : 1];
-  if constexpr (!F32) {
+  if constexpr (WF) {
+    const uint4 *Wa = reinterpret_cast<const uint4 *>(d.Wa);
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int k = min(it * kThreads + tid, NSTAGE - 1);
+      const int vi = gi0 + k % G::LW, vj = gj0 - 6 + k / G::LW;
+      sv[it] = Wa[ffk::wform_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), n, W)];
+    }
+  } else if constexpr (!F32) {
     const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
     uint4 *v = sv;
 #pragma unroll
@@ -268,6 +349,71 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       atomicAdd(&s_work[1], (unsigned)all);
     }
   };
+  // the weight-class path: interior test, one-lane and all-global quad evaluations
+  [[maybe_unused]] const __amdgpu_buffer_rsrc_t wb_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(d.Wb), (short)0, WF ? (int)ffk::wform_bytes(W, H, n) : 0, 0x00020000);
+  [[maybe_unused]] const __amdgpu_buffer_rsrc_t da_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(d.Da), (short)0,
+      WF ? (int)((size_t)(H + 2 * ffk::desc_pad(n)) * (W + 2 * ffk::desc_pad(n)) * 16) : 0, 0x00020000);
+  [[maybe_unused]] auto inner = [&](int i, int j, int bx, int by) {
+    const int lo = 3 * n;
+    return i * n >= lo && i * n <= W - 1 - lo && j * n >= lo && j * n <= H - 1 - lo && bx >= lo && bx <= W - 1 - lo &&
+           by >= lo && by <= H - 1 - lo;
+  };
+  [[maybe_unused]] auto evalw = [&](int i, int j, int bx, int by) -> uint32_t {
+    return eval_wform<LOG2N, G::LW>(s_wa + (j - gj0) * G::LW + (i - gi0), wb_rsrc, W, bx, by);
+  };
+  [[maybe_unused]] auto evalg = [&](int i, int j, int bx, int by) -> uint32_t {
+    return eval_quad_gg<LOG2N>(da_rsrc, db_rsrc, W, i * n, j * n, bx, by, qr);
+  };
+  // append of the lanes with `on` set, at the front (inn) or the back (!inn)
+  // of the queue: one LDS atomic per wave and end
+  [[maybe_unused]] auto enqueue2 = [&](bool on, bool inn, uint16_t e, unsigned int &flen, unsigned int &blen) {
+    const uint64_t bi = __ballot(on && inn), bb = __ballot(on && !inn);
+    int q0 = 0, q1 = 0;
+    if ((tid & 63) == 0) {
+      if (bi) q0 = (int)atomicAdd(&flen, (unsigned)__popcll(bi));
+      if (bb) q1 = (int)atomicAdd(&blen, (unsigned)__popcll(bb));
+    }
+    q0 = __shfl(q0, 0);
+    q1 = __shfl(q1, 0);
+    const int lane = tid & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (on && inn) s_queue[q0 + __popcll(bi & below)] = e;
+    if (on && !inn) s_queue[QCAP - 1 - (q1 + __popcll(bb & below))] = e;
+  };
+  // evaluations of a front/back queue pair: the front entries one lane each
+  // (weight-class), the back entries a quad each.  decode(e, l, i, j, bx, by)
+  // gives an entry's window cell l, grid cell (i, j) and target pixel;
+  // done(e, l, cost) is called once per entry, on the evaluating lane (the
+  // quad's lane 0)
+  [[maybe_unused]] auto run_queues = [&](int flen, int blen, auto decode, auto done) {
+    for (int base = 0; base < flen; base += kThreads) {
+      const int q = base + tid;
+      bool own = false;
+      if (q < flen) {
+        const int e = s_queue[q];
+        int l, i, j, bx, by;
+        decode(e, l, i, j, bx, by);
+        done(e, l, evalw(i, j, bx, by));
+        own = owned(i, j);
+      }
+      count_work(q < flen, own);
+    }
+    for (int base = 0; base < blen; base += kQuads) {
+      const int q = base + (tid >> 2);
+      bool own = false;
+      if (q < blen) {
+        const int e = s_queue[QCAP - 1 - q];
+        int l, i, j, bx, by;
+        decode(e, l, i, j, bx, by);
+        const uint32_t c = evalg(i, j, bx, by);
+        if (qr == 0) done(e, l, c);
+        own = owned(i, j);
+      }
+      count_work(q < blen && qr == 0, own);
+    }
+  };
   // queue append of the lanes with `on` set (one LDS atomic per wave)
   auto enqueue = [&](bool on, uint16_t e, unsigned int &len) {
     const uint64_t b = __ballot(on);
@@ -279,7 +425,6 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   };
 
   int ml = a.halo[0], mr = a.halo[1], mt = a.halo[2], mb = a.halo[3];
-  auto owned = [&](int i, int j) { return i >= ti0 && i < oi1 && j >= tj0 && j < oj1; };
   // a random search follows step t unless t ends its group (the R^+ steps
   // of Flow Fields+ end at P - 1, the scale at T - 1)
   auto rs_after = [&](int t) { return t != a.P - 1 && t != a.T - 1; };
@@ -333,7 +478,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       }
     }
     // the staged descriptors go to LDS once both groups of loads are issued
-    if constexpr (!F32) {
+    if constexpr (WF) {
+#pragma unroll
+      for (int it = 0; it < NS; ++it)
+        if (it * kThreads + tid < NSTAGE) s_wa[it * kThreads + tid] = sv[it];
+    } else if constexpr (!F32) {
 #pragma unroll
       for (int it = 0; it < NS; ++it)
         if (it * kThreads + tid < G::DH * G::DW) s_da[it * kThreads + tid] = sv[it];
@@ -350,6 +499,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     for (int it = 0; it < NI; ++it) {
       const int k = it * kThreads + tid;
       int cnt = 0, l = 0;
+      bool inn = false;
       if (k < rw * rh) {
         const int i = rl + k % rw, j = rt + k / rw;
         l = (j - gj0) * G::LW + (i - gi0);
@@ -357,17 +507,38 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         s_cost[l] = cv[it];
         if (ev[it]) {
           if constexpr (!QUAD) s_cost[l] = evalc(i, j, i * n + ffk::flow_x(fv[it]), j * n + ffk::flow_y(fv[it]));
+          if constexpr (WF) inn = inner(i, j, i * n + ffk::flow_x(fv[it]), j * n + ffk::flow_y(fv[it]));
           cnt = owned(i, j);
         }
       }
       if constexpr (!QUAD) count_work(k < rw * rh && ev[it], cnt != 0);
-      if constexpr (QUAD) enqueue(k < rw * rh && ev[it], (uint16_t)l, s_qlen);
+      if constexpr (WF)
+        enqueue2(k < rw * rh && ev[it], inn, (uint16_t)l, s_qlen, s_blen);
+      else if constexpr (QUAD)
+        enqueue(k < rw * rh && ev[it], (uint16_t)l, s_qlen);
       const int tot = __popcll(__ballot(cnt));
       if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
     }
   }
   __syncthreads();
-  if constexpr (QUAD) {
+  if constexpr (WF) {
+    if (a.mode != ffh::kLevelContinue) {  // the seed evaluations
+      run_queues(
+          (int)s_qlen, (int)s_blen,
+          [&](int e, int &l, int &i, int &j, int &bx, int &by) {
+            l = e;
+            i = gi0 + l % G::LW;
+            j = gj0 + l / G::LW;
+            const int32_t f = s_flow[l];
+            bx = i * n + ffk::flow_x(f);
+            by = j * n + ffk::flow_y(f);
+          },
+          [&](int, int l, uint32_t c) { s_cost[l] = c; });
+      __syncthreads();
+      if (tid == 0) s_qlen = s_blen = 0;
+      __syncthreads();
+    }
+  } else if constexpr (QUAD) {
     if (a.mode != ffh::kLevelContinue) {  // the seed evaluations, a quad each
       const int qlen = (int)s_qlen;
       for (int base = 0; base < qlen; base += kQuads) {
@@ -417,6 +588,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         const bool live = cell(base + tid, i, j);
         const int l = (j - gj0) * G::LW + (i - gi0);
         bool hv = false, vcomp = false;
+        [[maybe_unused]] bool hin = false, vin = false;  // weight-class path: cell and target inside
         if (live) {
           const uint32_t c0 = s_cost[l];
           const int32_t f0 = s_flow[l];
@@ -428,6 +600,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             fh = s_flow[l + hdi];
             const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
             hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+            if constexpr (WF) hin = inner(i, j, tx, ty);
           }
           if (j + vdj >= 0 && j + vdj < Hn && s_cost[l + vdj * G::LW] != kUnset) {
             const int32_t fv = s_flow[l + vdj * G::LW];
@@ -435,6 +608,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
             vsame_h = hv && fv == fh;
             vsame_0 = set0 && fv == f0;
+            if constexpr (WF) vin = inner(i, j, tx, ty);
           }
           vcomp = vb && !vsame_h && !vsame_0;
           s_flags[l] = (uint8_t)(hv | (vb << 1) | (vsame_h << 2) | (vsame_0 << 3) | (vcomp << 4));
@@ -443,19 +617,50 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           else
             s_cost[l] = set0 ? c0 << 2 : kUnset;
         }
-        const uint64_t bh = __ballot(hv), bv = __ballot(vcomp);
-        const int nh = __popcll(bh), nv = __popcll(bv);
-        int q0 = 0;
-        if ((tid & 63) == 0 && nh + nv) q0 = (int)atomicAdd(&s_qlen, (unsigned)(nh + nv));
-        q0 = __shfl(q0, 0);
-        const int lane = tid & 63;
-        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-        if (hv) s_queue[q0 + __popcll(bh & below)] = (uint16_t)(l << 1);
-        if (vcomp) s_queue[q0 + nh + __popcll(bv & below)] = (uint16_t)((l << 1) | 1);
+        if constexpr (WF) {  // weight-class entries at the front, descriptor quads at the back
+          const uint64_t bhi = __ballot(hv && hin), bvi = __ballot(vcomp && vin);
+          const uint64_t bhb = __ballot(hv && !hin), bvb = __ballot(vcomp && !vin);
+          const int nhi = __popcll(bhi), nvi = __popcll(bvi), nhb = __popcll(bhb), nvb = __popcll(bvb);
+          int q0 = 0, q1 = 0;
+          if ((tid & 63) == 0) {
+            if (nhi + nvi) q0 = (int)atomicAdd(&s_qlen, (unsigned)(nhi + nvi));
+            if (nhb + nvb) q1 = (int)atomicAdd(&s_blen, (unsigned)(nhb + nvb));
+          }
+          q0 = __shfl(q0, 0);
+          q1 = __shfl(q1, 0);
+          const int lane = tid & 63;
+          const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+          if (hv && hin) s_queue[q0 + __popcll(bhi & below)] = (uint16_t)(l << 1);
+          if (vcomp && vin) s_queue[q0 + nhi + __popcll(bvi & below)] = (uint16_t)((l << 1) | 1);
+          if (hv && !hin) s_queue[QCAP - 1 - (q1 + __popcll(bhb & below))] = (uint16_t)(l << 1);
+          if (vcomp && !vin) s_queue[QCAP - 1 - (q1 + nhb + __popcll(bvb & below))] = (uint16_t)((l << 1) | 1);
+        } else {
+          const uint64_t bh = __ballot(hv), bv = __ballot(vcomp);
+          const int nh = __popcll(bh), nv = __popcll(bv);
+          int q0 = 0;
+          if ((tid & 63) == 0 && nh + nv) q0 = (int)atomicAdd(&s_qlen, (unsigned)(nh + nv));
+          q0 = __shfl(q0, 0);
+          const int lane = tid & 63;
+          const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+          if (hv) s_queue[q0 + __popcll(bh & below)] = (uint16_t)(l << 1);
+          if (vcomp) s_queue[q0 + nh + __popcll(bv & below)] = (uint16_t)((l << 1) | 1);
+        }
       }
       __syncthreads();
       // (2) the queued evaluations, densely over all lanes
-      if constexpr (QUAD) {
+      if constexpr (WF) {
+        run_queues(
+            (int)s_qlen, (int)s_blen,
+            [&](int e, int &l, int &i, int &j, int &bx, int &by) {
+              l = e >> 1;
+              i = gi0 + l % G::LW;
+              j = gj0 + l / G::LW;
+              const int32_t f = s_flow[(e & 1) ? l + vdj * G::LW : l + hdi];
+              bx = i * n + ffk::flow_x(f);
+              by = j * n + ffk::flow_y(f);
+            },
+            [&](int e, int l, uint32_t c) { atomicMin(&s_cost[l], (c << 2) | (uint32_t)(1 + (e & 1))); });
+      } else if constexpr (QUAD) {
         const int qlen = (int)s_qlen;
         for (int base = 0; base < qlen; base += kQuads) {
           const int q = base + (tid >> 2);
@@ -492,7 +697,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         }
       }
       __syncthreads();
-      if (tid == 0) s_qlen = 0;
+      if (tid == 0) s_qlen = s_blen = 0;
       // (3) new state and evaluation count of every cell
       for (int base = 0; base < hw * rh; base += kThreads) {
         int i, j;
@@ -534,7 +739,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
               s_flags[l] = (uint32_t)fc;
               cnt += owned(i, j);
             }
-            enqueue(act, (uint16_t)l, s_rlen);
+            if constexpr (WF)
+              enqueue2(act, act && inner(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc)), (uint16_t)l, s_rlen,
+                       s_rblen);
+            else
+              enqueue(act, (uint16_t)l, s_rlen);
           }
         }
         const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2)) + __popcll(__ballot(cnt >= 3));
@@ -551,13 +760,36 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             if (act) s_flags[l] = (uint32_t)fc;
             const int tot = __popcll(__ballot(act && owned(i, j)));
             if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
-            enqueue(act, (uint16_t)l, s_rlen);
+            if constexpr (WF)
+              enqueue2(act, act && inner(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc)), (uint16_t)l, s_rlen,
+                       s_rblen);
+            else
+              enqueue(act, (uint16_t)l, s_rlen);
           }
         }
       }
       __syncthreads();
     }
-    if (QUAD && rs_after(t)) {  // the candidates drawn in the second half-sweep, a quad each
+    if (WF && rs_after(t)) {  // the candidates drawn in the second half-sweep
+      run_queues(
+          (int)s_rlen, (int)s_rblen,
+          [&](int e, int &l, int &i, int &j, int &bx, int &by) {
+            l = e;
+            i = gi0 + l % G::LW;
+            j = gj0 + l / G::LW;
+            const int32_t fc = (int32_t)s_flags[l];
+            bx = i * n + ffk::flow_x(fc);
+            by = j * n + ffk::flow_y(fc);
+          },
+          [&](int, int l, uint32_t c) {
+            if (c < s_cost[l]) {
+              s_cost[l] = c;
+              s_flow[l] = (int32_t)s_flags[l];
+            }
+          });
+      __syncthreads();
+      if (tid == 0) s_rlen = s_rblen = 0;  // next written after the next step's first half-sweep
+    } else if (QUAD && rs_after(t)) {  // the candidates drawn in the second half-sweep, a quad each
       const int qlen = (int)s_rlen;
       for (int base = 0; base < qlen; base += kQuads) {
         const int q = base + (tid >> 2);
@@ -635,7 +867,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 // four waves per SIMD (two with EV = 2): the register budget then keeps the
 // loads of a patch in flight together instead of one after another.
 template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV >= 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
   level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, a.dir[wg / tiles], wg % tiles);
@@ -652,7 +884,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))
 
 // Persistent launch over the (pair, direction, tile) items of a batch.
 template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level_batch(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV >= 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level_batch(
     ffh::LevelKArgs base, ffh::BatchStage st) {
   constexpr int n = 1 << LOG2N;
   ffk::for_items(st.total, [&](int item) {
@@ -670,6 +902,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV == 
     ffh::LevelKDir d;
     d.Da = bp.desc[dir][lv];
     d.Db = bp.desc[dir ^ 1][lv];
+    d.Wa = bp.wform[dir][lv];
+    d.Wb = bp.wform[dir ^ 1][lv];
     d.flow = st.dst ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
     d.cost = st.dst ? bp.scost[lv][dir] : bp.gcost[lv][dir];
     d.flow_in = st.src ? bp.sflow[lv][dir] : bp.gflow[lv][dir];
@@ -751,6 +985,12 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2>(a, batch, stream);
     case 16: return launch_v<LOG2N, 32, 16, 256, 3, 4>(a, batch, stream);
     case 17: return launch_v<LOG2N, 16, 16, 256, 3, 4>(a, batch, stream);
+    case 18: return launch_v<LOG2N, 32, 16, 256, 4, 4>(a, batch, stream);
+    case 19: return launch_v<LOG2N, 16, 16, 256, 4, 4>(a, batch, stream);
+    case 20: return launch_v<LOG2N, 32, 16, 256, 4, 2>(a, batch, stream);
+    case 21: return launch_v<LOG2N, 16, 16, 256, 4, 2>(a, batch, stream);
+    case 22: return launch_v<LOG2N, 8, 8, 256, 4, 6>(a, batch, stream);
+    case 23: return launch_v<LOG2N, 8, 8, 256, 4, 2>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }

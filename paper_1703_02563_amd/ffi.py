@@ -57,8 +57,9 @@ _I32 = C.c_int32
 _SIGS = {
     "ff_version": (C.c_int, []),
     "ff_status_str": (C.c_char_p, [C.c_int]),
-    "ff_descriptors": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P]),
+    "ff_descriptors": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "ff_descriptor_map_bytes": (C.c_size_t, [_I32, _I32, _I32]),
+    "ff_wform_map_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_init_nn": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "ff_seed_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_propagate_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
@@ -72,8 +73,8 @@ _SIGS = {
     "ff_region_filter_noalloc_max_pixels": (C.c_size_t, []),
     "ff_region_filter_noalloc": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "ff_workspace_bytes": (C.c_size_t, [_I32, _I32, C.POINTER(FFParams)]),
-    "ff_run_level": (C.c_int, [_P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P, _P, _P,
-                               C.c_size_t, _P, _P, _P]),
+    "ff_run_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P,
+                               _P, _P, C.c_size_t, _P, _P, _P]),
     "ff_run_level_scratch_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_cost_f32_fwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "ff_cost_f32_bwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),

@@ -98,22 +98,31 @@ def cells(W: int, H: int, n: int):
     return -(-W // n), -(-H // n)
 
 
-def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False):
+def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False, wform: bool = False):
     """Scale-space image and the descriptor map of scale n: uint8
     [H + 6n, W + 6n, 16], a replicated border of 3n pixels, the pixels of a
     row in phase order (x mod n, then x // n); the layout every entry point
     taking a descriptor map expects (see ff_descriptors).  rowmajor=True also
-    returns the plain [H, W, 16] descriptors (the NN seed's input)."""
+    returns the plain [H, W, 16] descriptors (the NN seed's input);
+    wform=True also returns the weight-class row map uint8 [H + 6n, W, 16]
+    (ff_wform_map_bytes).  Returns (blurred, desc[, plain][, wform])."""
     H, W = img.shape
     P = 3 * n
     hsum = torch.empty((H, W), dtype=torch.int16, device=img.device)
     blurred = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     desc = torch.empty((H + 2 * P, W + 2 * P, 16), dtype=torch.uint8, device=img.device)
     plain = torch.empty((H, W, 16), dtype=torch.uint8, device=img.device) if rowmajor else None
+    wf = torch.empty((H + 2 * P, W, 16), dtype=torch.uint8, device=img.device) if wform else None
     assert desc.numel() == int(lib().ff_descriptor_map_bytes(W, H, n))
+    assert wf is None or wf.numel() == int(lib().ff_wform_map_bytes(W, H, n))
     check(lib().ff_descriptors(_ptr(img, torch.uint8, "img"), W, H, n, _ptr(hsum), _ptr(blurred), _ptr(desc),
-                               _ptr(plain), _stream()), "ff_descriptors")
-    return (blurred, desc, plain) if rowmajor else (blurred, desc)
+                               _ptr(plain), _ptr(wf), _stream()), "ff_descriptors")
+    out = (blurred, desc)
+    if rowmajor:
+        out += (plain,)
+    if wform:
+        out += (wf,)
+    return out
 
 
 def _map_dims(desc_a, desc_b, n: int):
@@ -171,17 +180,22 @@ def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, le
 
 
 def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: int, flow, cost, nn_key=None,
-              coarse_flow=None, coarse_cost=None, n_evals=None, n_work=None, scratch=None):
+              coarse_flow=None, coarse_cost=None, n_evals=None, n_work=None, scratch=None, wform_a=None, wform_b=None):
     """All steps of one scale, in place on (flow, cost); see ff_run_level.
     n_work: optional int64 [2] device counters of the evaluations computed
-    (owned cells, all cells); scratch: optional reusable second grid."""
+    (owned cells, all cells); scratch: optional reusable second grid;
+    wform_a/wform_b: the weight-class row maps of scale 2^level (both or
+    neither)."""
     W, H = _map_dims(desc_a, desc_b, 1 << level)
+    if (wform_a is None) != (wform_b is None):
+        raise ValueError("run_level: both weight-class maps or neither")
     nbytes = int(lib().ff_run_level_scratch_bytes(W, H, level))
     if scratch is None:
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=desc_a.device)
     elif scratch.numel() * scratch.element_size() < nbytes:
         raise ValueError("run_level: scratch too small")
-    check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, level, params.to_c(),
+    check(lib().ff_run_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), _ptr(wform_a, torch.uint8),
+                             _ptr(wform_b, torch.uint8), W, H, level, params.to_c(),
                              stream_id, mode, _ptr(nn_key, torch.int64), _ptr(coarse_flow, torch.int16),
                              _ptr(coarse_cost, torch.int32), _ptr(flow, torch.int16), _ptr(cost, torch.int32),
                              _ptr(scratch), nbytes, _ptr(n_evals, torch.int64), _ptr(n_work, torch.int64),

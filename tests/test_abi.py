@@ -70,9 +70,9 @@ def test_bad_arguments_return_before_any_launch():
     assert lib.ff_flow_fields(fake, fake, 64, 64, C.byref(p), fake, 16, fake, fake, fake, fake, fake, None, None,
                               None) == ffi.FF_ERR_WORKSPACE
     # bad sizes / scales / passes
-    assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
-    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
-    assert lib.ff_descriptors(fake, 5, 5, 128, fake, fake, fake, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 128, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_propagate_level(fake, fake, 5, 5, 1, 3, -1, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_consistency_filter(fake, fake, fake, None, 5, 5, 1.0, fake, None, None) == ffi.FF_ERR_ARG

@@ -56,6 +56,22 @@ def to_lib(D, n):
     return out
 
 
+def wform_lib(B, n):
+    """Blurred image [H][W] -> weight-class row map [H + 6n][W][16] as
+    documented for ff_wform_map_bytes (numpy, from the oracle's blur)."""
+    H, W = B.shape
+    rows = B[np.clip(np.arange(-3 * n, H + 3 * n), 0, H - 1)]
+    x = np.arange(W)
+
+    def col(a):
+        return rows[:, np.clip(x + n * a, 0, W - 1)]
+
+    out = np.zeros((H + 6 * n, W, 16), np.uint8)
+    for k, a in enumerate((-6, -5, 5, 6, -4, -3, 3, 4, -2, -1, 1, 2, 0)):
+        out[..., k] = col(a)
+    return out
+
+
 def from_lib(M, n):
     """Descriptor map -> row-major [H][W][16] (drops the border)."""
     P = 3 * n
@@ -71,10 +87,11 @@ SHAPES = [(37, 53), (1, 1), (1, 40), (33, 1), (120, 160), (9, 300)]
 @pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
 def test_descriptors_bit_exact(shape, n):
     img, _ = random_images(100 + n, *shape, kind="uniform")
-    blurred, desc, plain = ff.descriptors(dev(img), n, rowmajor=True)
+    blurred, desc, plain, wform = ff.descriptors(dev(img), n, rowmajor=True, wform=True)
     eb = oracle.blur(img, n)
     ed = oracle.descriptor(eb, n)
     assert np.array_equal(host(blurred), eb)
+    assert np.array_equal(host(wform), wform_lib(eb, n))
     assert np.array_equal(host(plain), ed)
     assert np.array_equal(from_lib(host(desc), n), ed)
     assert np.array_equal(host(desc), to_lib(ed, n))  # the replicated border as well
@@ -291,14 +308,21 @@ def test_level_kernel_variants_bit_exact(config):
                                              ((130, 200), 2, 6, (1, 1)), ((45, 70), 0, 9, (2, 1)),
                                              ((33, 1), 0, 3, (1, 1)), ((200, 260), 0, 6, (1, 1))])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_run_level_bit_exact(shape, level, T, R, mode):
-    """ff_run_level equals the oracle's step sequence for that scale."""
+@pytest.mark.parametrize("variant", [None, 18, 20, 23])
+def test_run_level_bit_exact(shape, level, T, R, mode, variant):
+    """ff_run_level equals the oracle's step sequence for that scale (the
+    built-in table, and weight-class variants given their row maps)."""
     H, W = shape
     n = 1 << level
     prm = ff.Params(levels=level + 1, iters=T, R_num=R[0], R_den=R[1])
     ia, ib = random_images(800 + level * 10 + mode, H, W)
-    Da = oracle.descriptor(oracle.blur(ia, n), n)
-    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    Ba, Bb = oracle.blur(ia, n), oracle.blur(ib, n)
+    Da = oracle.descriptor(Ba, n)
+    Db = oracle.descriptor(Bb, n)
+    wf = {}
+    if variant is not None:
+        prm = with_tuning(prm, variant=[variant] * 7)
+        wf = dict(wform_a=dev(wform_lib(Ba, n)), wform_b=dev(wform_lib(Bb, n)))
     Wn, Hn = -(-W // n), -(-H // n)
     key = cflow = ccost = None
     if mode == 0:
@@ -332,7 +356,7 @@ def test_run_level_bit_exact(shape, level, T, R, mode):
     cnt = counter()
     ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, prm, 0, mode, gf, gc, nn_key=key,
                  coarse_flow=None if cflow is None else dev(cflow),
-                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
+                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt, **wf)
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
@@ -356,7 +380,9 @@ def test_run_length_does_not_change_results(passes):
                                    ([2, 5, 3, 7, 6, 3, 3], [1, 1, 1, 1, 1, 1, 1]),
                                    ([0, 1, 4, 2, 8, 3, 3], [3, 2, 0, 1, 2, 0, 0]),
                                    ([16, 17, 13, 14, 16, 3, 3], [7, 7, 7, 7, 7, 0, 0]),
-                                   ([17, 16, 14, 13, 12, 11, 15], [4, 3, 6, 5, 2, 1, 0])])
+                                   ([17, 16, 14, 13, 12, 11, 15], [4, 3, 6, 5, 2, 1, 0]),
+                                   ([18, 19, 22, 23, 23, 3, 3], [2, 2, 3, 2, 2, 0, 0]),
+                                   ([20, 21, 18, 22, 24, 23, 19], [1, 1, 2, 3, 0, 1, 2])])
 @pytest.mark.parametrize("case", [(2, 0), (5, 16)])
 def test_mixed_variant_and_run_length_tables_bit_exact(table, case):
     """Launch tables mixing variants and run lengths per scale (as the
@@ -378,15 +404,21 @@ def test_mixed_variant_and_run_length_tables_bit_exact(table, case):
 
 @pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("passes", [1, 2])
-def test_run_level_multi_launch_bit_exact(mode, passes):
+@pytest.mark.parametrize("variant", [None, 18])
+def test_run_level_multi_launch_bit_exact(mode, passes, variant):
     """ff_run_level split into several launches (odd and even counts, a
     continuing first run included) equals the oracle's step sequence."""
     H, W, level, T = 130, 200, 0, 5
     n = 1
     prm = ff.Params(levels=1, iters=T)
     ia, ib = random_images(950 + mode + passes, H, W)
-    Da = oracle.descriptor(oracle.blur(ia, n), n)
-    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    Ba, Bb = oracle.blur(ia, n), oracle.blur(ib, n)
+    Da = oracle.descriptor(Ba, n)
+    Db = oracle.descriptor(Bb, n)
+    wf = {}
+    if variant is not None:
+        prm = with_tuning(prm, variant=[variant] * 7)
+        wf = dict(wform_a=dev(wform_lib(Ba, n)), wform_b=dev(wform_lib(Bb, n)))
     if mode == 0:
         flow, cost = _random_level_state(5, H, W, n)
         for j, i in zip(*np.nonzero(cost != oracle.UNSET)):
@@ -409,44 +441,54 @@ def test_run_level_multi_launch_bit_exact(mode, passes):
     cnt = counter()
     ff.run_level(dev(to_lib(Da, n)), dev(to_lib(Db, n)), level, with_tuning(prm, passes=[passes] * 7), 0, mode, gf,
                  gc, coarse_flow=None if cflow is None else dev(cflow),
-                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt)
+                 coarse_cost=None if ccost is None else dev(ccost.view(np.int32)), n_evals=cnt, **wf)
     assert np.array_equal(host(gf), ef)
     assert np.array_equal(as_u32(gc), ec)
     assert int(host(cnt)[0]) == ne
 
 
 def _tie_state(bands, cells):
-    """The constructed tie cases of the oracle pins: image b's descriptors
-    constant per vertical band, a few set cells with consistent costs."""
-    ia, _ = random_images(77, 24, 24)
-    Da = oracle.descriptor(oracle.blur(ia, 1), 1)
-    Db = np.empty_like(Da)
-    Db[:, :12] = bands[0]
-    Db[:, 12:] = bands[1]
-    flow = np.zeros((24, 24, 2), np.int16)
-    cost = np.full((24, 24), oracle.UNSET, np.uint32)
+    """Tie cases like those of the oracle pins, on a 48 x 24 pair: image b is
+    a blurred image constant on the bands x < 24 and x >= 24 (its patch costs
+    depend only on the band a target's patch and descriptors reach); a few
+    set cells with consistent costs."""
+    ia, _ = random_images(77, 24, 48)
+    Ba = oracle.blur(ia, 1)
+    Bb = np.empty((24, 48), np.uint8)
+    Bb[:, :24] = bands[0]
+    Bb[:, 24:] = bands[1]
+    Da, Db = oracle.descriptor(Ba, 1), oracle.descriptor(Bb, 1)
+    flow = np.zeros((24, 48, 2), np.int16)
+    cost = np.full((24, 48), oracle.UNSET, np.uint32)
     for (i, j), f in cells.items():
         flow[j, i] = f
         cost[j, i] = oracle.cost(Da, Db, 1, 3, i, j, f[0], f[1])
-    return Da, Db, flow, cost
+    return Ba, Bb, Da, Db, flow, cost
 
 
-@pytest.mark.parametrize("blocked", [False, True])
+@pytest.mark.parametrize("blocked", [False, True, "wform"])
 def test_propagation_ties_bit_exact(blocked):
     """Equal errors of the horizontal and vertical source (the horizontal
     one wins), a held flow of equal error (kept) and strict differences
-    either way, through the per-step kernel and the blocked kernel."""
-    fh, fv, fr = (-8, 2), (-9, -4), (4, 3)
-    cases = [((100, 100), {(10, 10): fh, (11, 9): fv}),
-             ((100, 100), {(10, 10): fh, (11, 9): fv, (11, 10): (-5, 1)}),
-             ((100, 250), {(10, 10): fr, (11, 9): fh}), ((100, 250), {(10, 10): fh, (11, 9): fr}),
-             ((250, 100), {(10, 10): fr, (11, 9): fh}), ((250, 100), {(10, 10): fh, (11, 9): fr})]
+    either way, for cell (23, 10) (left source (22, 10), top (23, 9)),
+    through the per-step kernel, the blocked descriptor kernel and the
+    weight-class kernel (every cell and target here 3 px inside)."""
+    fh, fv, fr = (-8, 2), (-9, -4), (8, 3)  # targets (15, 12), (14, 6) in the left band, (31, 13) in the right
+    cases = [((100, 100), {(22, 10): fh, (23, 9): fv}),
+             ((100, 100), {(22, 10): fh, (23, 9): fv, (23, 10): (-7, 1)}),
+             ((100, 250), {(22, 10): fr, (23, 9): fh}), ((100, 250), {(22, 10): fh, (23, 9): fr}),
+             ((250, 100), {(22, 10): fr, (23, 9): fh}), ((250, 100), {(22, 10): fh, (23, 9): fr})]
     prm = ff.Params(levels=1, iters=1)
     for bands, cells in cases:
-        Da, Db, flow, cost = _tie_state(bands, cells)
+        Ba, Bb, Da, Db, flow, cost = _tie_state(bands, cells)
         ef, ec, ne = oracle.propagate(Da, Db, 1, 0, flow, cost)
+        if bands[0] == bands[1] and len(cells) == 2:
+            assert tuple(ef[10, 23]) == fh  # the pinned rule on this case
         gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
-        if blocked:
+        if blocked == "wform":
+            ff.run_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 0, with_tuning(prm, variant=[18] * 7), 0, 0, gf, gc,
+                         n_evals=cnt, wform_a=dev(wform_lib(Ba, 1)), wform_b=dev(wform_lib(Bb, 1)))
+        elif blocked:
             ff.run_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 0, prm, 0, 0, gf, gc, n_evals=cnt)
         else:
             ff.propagate_level(dev(to_lib(Da, 1)), dev(to_lib(Db, 1)), 1, 0, gf, gc, n_evals=cnt)

@@ -106,6 +106,48 @@ def test_cost_interior_weighted_identity(n):
         assert e == _weighted_13x13(Ba, Bb, n, p, q)
 
 
+def _weighted_13x13_clamped(Ba, Bb, n, p, q):
+    """The 13 x 13 weighted sum with the blurred samples read through the
+    image border (replicate): the descriptors' own clamp."""
+    H, W = Ba.shape
+    s = 0
+    for b in range(-6, 7):
+        ya, yb = min(max(p[1] + n * b, 0), H - 1), min(max(q[1] + n * b, 0), H - 1)
+        for a in range(-6, 7):
+            xa, xb = min(max(p[0] + n * a, 0), W - 1), min(max(q[0] + n * a, 0), W - 1)
+            s += W13[a + 6] * W13[b + 6] * abs(int(Ba[ya, xa]) - int(Bb[yb, xb]))
+    return s
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_cost_weighted_identity_holds_3n_inside(n):
+    """The weighted identity with clamped blurred samples holds exactly when
+    the pixel and the target are at least 3n inside the image (every patch
+    position is then in the image, so the patch clamp does nothing and only
+    the descriptors' own clamp remains), and fails just outside."""
+    H, W = 30 + 8 * n, 34 + 8 * n
+    ia, ib = random_images(5 * n, H, W)
+    Ba, Bb = oracle.blur(ia, n), oracle.blur(ib, n)
+    Da, Db = oracle.descriptor(Ba, n), oracle.descriptor(Bb, n)
+    rng = np.random.default_rng(n)
+    lo = 3 * n
+
+    def pick(L):  # biased to the edge of the interior
+        return int((lo, L - 1 - lo, rng.integers(lo, L - lo), lo + 1)[rng.integers(0, 4)])
+
+    for _ in range(120):
+        p, q = (pick(W), pick(H)), (pick(W), pick(H))
+        e = oracle.cost(Da, Db, n, 3, p[0], p[1], q[0] - p[0], q[1] - p[1])
+        assert e == _weighted_13x13_clamped(Ba, Bb, n, p, q), (p, q)
+    outside = 0
+    for _ in range(40):
+        p = (lo - 1, int(rng.integers(lo, H - lo)))
+        q = (int(rng.integers(lo, W - lo)), int(rng.integers(lo, H - lo)))
+        outside += oracle.cost(Da, Db, n, 3, p[0], p[1], q[0] - p[0], q[1] - p[1]) != \
+            _weighted_13x13_clamped(Ba, Bb, n, p, q)
+    assert outside > 30
+
+
 def test_cost_border_is_edge_replication():
     n, r = 2, 3
     ia, ib = random_images(9, 20, 26)
