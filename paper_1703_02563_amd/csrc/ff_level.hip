@@ -29,8 +29,9 @@ constexpr Variant kVariants[] = {
     {32, 16, kH, 5, 5},   {16, 16, kH, 6, 6},   {32, 32, kH, 7, 7},   {8, 8, kH, 8, 8},     {16, 16, kH, 9, 9},
     {16, 16, kH, 10, 10}, {16, 16, 2, 3, 11},   {32, 16, 2, 2, 12},   {16, 16, kH, 3, 13},  {8, 8, kH, 8, 14},
     {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},   {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},
-    {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15}};
-constexpr int kNumVariants = 24;
+    {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},
+    {64, 32, 4, 0, 16}};
+constexpr int kNumVariants = 26;
 constexpr int kFirstWform = 18;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 

@@ -991,6 +991,8 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 21: return launch_v<LOG2N, 16, 16, 256, 4, 2>(a, batch, stream);
     case 22: return launch_v<LOG2N, 8, 8, 256, 4, 6>(a, batch, stream);
     case 23: return launch_v<LOG2N, 8, 8, 256, 4, 2>(a, batch, stream);
+    case 24: return launch_v<LOG2N, 32, 16, 512, 4, 4>(a, batch, stream);
+    case 25: return launch_v<LOG2N, 64, 32, 1024, 4, 4>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
