@@ -57,6 +57,13 @@ def lib():
         L.or_region_filter.argtypes = [P, P, P, i, i, i, P]
         L.or_flow_fields.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
         L.or_flow_fields.restype = i
+        L.or_flow_fields_sub.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P, P]
+        L.or_flow_fields_sub.restype = i
+        L.or_cost_sub.argtypes = [P, P, i, i, i, i, i, i, i, i, i]
+        L.or_cost_sub.restype = C.c_uint32
+        L.or_propagate_sub.argtypes = [P, P, i, i, i, i, i, i, P, P, P, i]
+        L.or_random_search_sub.argtypes = [P, P, i, i, i, i, i, i, u64, i, i, i, P, P, P, i]
+        L.or_consistency_sub.argtypes = [P, P, P, P, i, i, i, dbl, P]
         L.or_cost_f32.argtypes = [P, P, i, i, i, i, i, i, i, i]
         L.or_cost_f32.restype = C.c_uint32
         L.or_quantize_u8.argtypes = [P, C.c_int64, P]
@@ -214,10 +221,12 @@ def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:
 
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
                 eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
-                fine_iters: int = 0) -> dict:
+                fine_iters: int = 0, subpixel: int = 0) -> dict:
     """The whole schedule on one pair.  plus_iters > 0: Flow Fields+ (P steps
     at R^+ = Rp_num / R_den before the `iters` steps at R); fine_iters > 0:
-    the finest scale runs only that many steps at R (Flow Fields+ Fast)."""
+    the finest scale runs only that many steps at R (Flow Fields+ Fast);
+    subpixel = s > 0: flows in units of 1/2^s pixel, bilinear targets, costs
+    of cost_sub (scaled by 4^s)."""
     img1, img2 = _u8(img1), _u8(img2)
     H, W = img1.shape
     out = {
@@ -226,13 +235,54 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
         "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
     }
     ne = np.zeros(2, np.uint64)
-    rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters, Rp_num,
-                              fine_iters, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
-                              _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
+    if subpixel:
+        rc = lib().or_flow_fields_sub(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters,
+                                      Rp_num, fine_iters, subpixel, float(eps), seed, nthreads, _p(out["flow_fwd"]),
+                                      _p(out["flow_bwd"]), _p(out["cost_fwd"]), _p(out["cost_bwd"]),
+                                      _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
+    else:
+        rc = lib().or_flow_fields(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters, Rp_num,
+                                  fine_iters, float(eps), seed, nthreads, _p(out["flow_fwd"]), _p(out["flow_bwd"]),
+                                  _p(out["cost_fwd"]), _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]),
+                                  _p(ne))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     out["n_evals"] = (int(ne[0]), int(ne[1]))
     return out
+
+
+def cost_sub(Da, Db, n: int, r: int, x: int, y: int, fx: int, fy: int, s: int) -> int:
+    """Subpixel matching error (flow in units of 1/2^s pixel), scaled by 4^s."""
+    H, W = Da.shape[:2]
+    return int(lib().or_cost_sub(_p(Da), _p(Db), W, H, n, r, x, y, fx, fy, s))
+
+
+def propagate_sub(Da, Db, n: int, s: int, pass_: int, flow, cost_, r: int = 3, nthreads: int = 1):
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_propagate_sub(_p(Da), _p(Db), W, H, n, r, s, pass_, _p(flow), _p(cost_), _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def random_search_sub(Da, Db, n: int, s: int, Rn: int, seed: int, stream: int, level: int, pass_: int, flow, cost_,
+                      r: int = 3, nthreads: int = 1):
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_random_search_sub(_p(Da), _p(Db), W, H, n, r, s, Rn, seed, stream, level, pass_, _p(flow), _p(cost_),
+                               _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def consistency_sub(fa, ca, fb, cb, s: int, eps: float = 1.0):
+    H, W = ca.shape
+    keep = np.empty((H, W), np.uint8)
+    args = [np.ascontiguousarray(a) for a in (fa, ca, fb, cb)]
+    lib().or_consistency_sub(*[_p(a) for a in args], W, H, s, float(eps), _p(keep))
+    return keep
 
 
 def cost_f32(Fa, Fb, n: int, r: int, x: int, y: int, fx: int, fy: int) -> float:

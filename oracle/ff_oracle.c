@@ -43,6 +43,10 @@
  *               consistency2 the same against two backward fields.
  *   region_filter  deletes small regions next to removed outliers (Sec. 3.7).
  *   sparsify    one sample per q x q region (Sec. 3.8).
+ *   cost_sub    the subpixel form (Sec. 3.1: random-search offsets with
+ *               subpixel accuracy, colours by bilinear interpolation): flows
+ *               in units of 1/2^s pixel, image b's descriptors bilinearly
+ *               interpolated at the target, costs scaled by 4^s (exact).
  *   flow_fields the whole multi-scale schedule (Sec. 3.1, 3.2): L levels
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
  *               random-search steps between them, forward and backward;
@@ -129,10 +133,12 @@ uint32_t or_cost(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int 
  * singles order exactly like their bit patterns), so one schedule serves
  * both data terms.  0xFFFFFFFF (UNSET) is above every such value. */
 typedef uint32_t (*or_cost_fn)(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx,
-                               int fy);
+                               int fy, int s);
 
-static uint32_t cost_u8(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy)
+static uint32_t cost_u8(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy,
+                        int s)
 {
+    (void)s;
     return or_cost((const uint8_t *)A, (const uint8_t *)B, W, H, n, r, x, y, fx, fy);
 }
 
@@ -166,9 +172,63 @@ uint32_t or_cost_f32(const float *fa, const float *fb, int W, int H, int n, int 
     return bits;
 }
 
-static uint32_t cost_f32(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy)
+static uint32_t cost_f32(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy,
+                         int s)
 {
+    (void)s;
     return or_cost_f32((const float *)A, (const float *)B, W, H, n, r, x, y, fx, fy);
+}
+
+/* Matching error of a subpixel flow (Sec. 3.1: random-search offsets with
+ * subpixel accuracy; the colours of the target patch by bilinear
+ * interpolation).  Flows are in units of 1/2^s pixel, S = 2^s: the target
+ * t = p + f / S lies in the cell of the integer pixels (tx0, ty0) ..
+ * (tx0 + 1, ty0 + 1) with fractions ax, ay in [0, S); the descriptors of
+ * image b at every patch position t + n(u, v) are the bilinear mix of those
+ * four pixels' descriptors (each read through the border, as or_cost does)
+ * with weights (S - ax)(S - ay), ax (S - ay), (S - ax) ay, ax ay, which sum
+ * to S^2.  The error is sum |S^2 a - sum_k w_k b_k| over the patch positions
+ * and channels: the cost of Eq. 3 on the interpolated descriptors times
+ * S^2, an exact integer (for an integer flow, S^2 times or_cost).  The
+ * target must lie in the image (0 <= t <= W - 1, 0 <= t_y <= H - 1). */
+uint32_t or_cost_sub(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int x, int y, int fx, int fy,
+                     int s)
+{
+    int S = 1 << s;
+    int tx = x * S + fx, ty = y * S + fy;
+    int tx0 = tx / S, ty0 = ty / S, ax = tx - tx0 * S, ay = ty - ty0 * S;
+    int w[4] = {(S - ax) * (S - ay), ax * (S - ay), (S - ax) * ay, ax * ay};
+    int cx[4] = {tx0, tx0 + 1, tx0, tx0 + 1}, cy[4] = {ty0, ty0, ty0 + 1, ty0 + 1};
+    uint32_t sum = 0;
+    for (int v = -r; v <= r; ++v)
+        for (int u = -r; u <= r; ++u) {
+            int ax_ = clampi(x + n * u, 0, W - 1), ay_ = clampi(y + n * v, 0, H - 1);
+            const uint8_t *a = Da + ((size_t)ay_ * W + ax_) * 16;
+            const uint8_t *b[4];
+            for (int k = 0; k < 4; ++k) {
+                int bx = clampi(cx[k] + n * u, 0, W - 1), by = clampi(cy[k] + n * v, 0, H - 1);
+                b[k] = Db + ((size_t)by * W + bx) * 16;
+            }
+            for (int c = 0; c < 16; ++c) {
+                int mix = 0;
+                for (int k = 0; k < 4; ++k) mix += w[k] * b[k][c];
+                sum += (uint32_t)abs(S * S * (int)a[c] - mix);
+            }
+        }
+    return sum;
+}
+
+static uint32_t cost_u8_sub(const void *A, const void *B, int W, int H, int n, int r, int x, int y, int fx, int fy,
+                            int s)
+{
+    return or_cost_sub((const uint8_t *)A, (const uint8_t *)B, W, H, n, r, x, y, fx, fy, s);
+}
+
+/* Target p + f / 2^s of a flow lies in the image. */
+static int target_in(int W, int H, int x, int y, int fx, int fy, int s)
+{
+    int tx = x * (1 << s) + fx, ty = y * (1 << s) + fy;
+    return tx >= 0 && tx <= (W - 1) * (1 << s) && ty >= 0 && ty <= (H - 1) * (1 << s);
 }
 
 /* Learned features to bytes for the NN seed: with lo, hi the range of all
@@ -245,17 +305,18 @@ void or_nn(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc,
 
 /* Initial flow of the coarsest scale (Eq. 1 / Eq. 4 with one candidate):
  * F(p) = q - p, cost = E_nc(p, F(p)). */
-static void init_coarse_g(or_cost_fn E, const int32_t *best_idx, const void *Da, const void *Db, int W, int H,
-                          int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, const void *Da, const void *Db, int W,
+                          int H, int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     for (int j = 0; j < Hc; ++j)
         for (int i = 0; i < Wc; ++i) {
             int k = j * Wc + i, x = i * nc, y = j * nc;
             int qx = best_idx[k] % W, qy = best_idx[k] / W;
-            flow[2 * k] = (int16_t)(qx - x);
-            flow[2 * k + 1] = (int16_t)(qy - y);
-            cost[k] = E(Da, Db, W, H, nc, r, x, y, qx - x, qy - y);
+            int fx = (qx - x) * (1 << s), fy = (qy - y) * (1 << s);  /* integer seed, in 1/2^s pixel */
+            flow[2 * k] = (int16_t)fx;
+            flow[2 * k + 1] = (int16_t)fy;
+            cost[k] = E(Da, Db, W, H, nc, r, x, y, fx, fy, s);
             *n_evals += 1;
         }
 }
@@ -263,7 +324,7 @@ static void init_coarse_g(or_cost_fn E, const int32_t *best_idx, const void *Da,
 void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
                     int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    init_coarse_g(cost_u8, best_idx, Da, Db, W, H, nc, r, flow, cost, n_evals);
+    init_coarse_g(cost_u8, 0, best_idx, Da, Db, W, H, nc, r, flow, cost, n_evals);
 }
 
 /* Hand-over from scale 2n to scale n (Sec. 3.2): cell (i, j) with i and j
@@ -271,8 +332,8 @@ void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *D
  * its flow as a seed (flows are kept in full-resolution pixel units); its
  * cost is re-evaluated with E_n.  All other cells start UNSET and receive a
  * value in the first propagation step. */
-static void seed_level_g(or_cost_fn E, const int16_t *cflow, const uint32_t *ccost, const void *Da, const void *Db,
-                         int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+static void seed_level_g(or_cost_fn E, int s, const int16_t *cflow, const uint32_t *ccost, const void *Da,
+                         const void *Db, int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), Wc = ceil_div(W, 2 * n);
     for (int j = 0; j < Hn; ++j)
@@ -287,7 +348,7 @@ static void seed_level_g(or_cost_fn E, const int16_t *cflow, const uint32_t *cco
             int fx = cflow[2 * kc], fy = cflow[2 * kc + 1];
             flow[2 * k] = (int16_t)fx;
             flow[2 * k + 1] = (int16_t)fy;
-            cost[k] = E(Da, Db, W, H, n, r, i * n, j * n, fx, fy);
+            cost[k] = E(Da, Db, W, H, n, r, i * n, j * n, fx, fy, s);
             *n_evals += 1;
         }
 }
@@ -295,7 +356,7 @@ static void seed_level_g(or_cost_fn E, const int16_t *cflow, const uint32_t *cco
 void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db,
                    int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    seed_level_g(cost_u8, cflow, ccost, Da, Db, W, H, n, r, flow, cost, n_evals);
+    seed_level_g(cost_u8, 0, cflow, ccost, Da, Db, W, H, n, r, flow, cost, n_evals);
 }
 
 /* Source cells of propagation direction d (Eq. 2 for d = 0; the other three
@@ -313,7 +374,7 @@ static void prop_sources(int d, int *hdi, int *vdj)
  * cells, by E_n with strict improvement.  Run as two half-sweeps: first all
  * cells with (i+j) odd, then all with (i+j) even; a cell only reads cells of
  * the other colour, so the result does not depend on the visiting order. */
-static void propagate_g(or_cost_fn E, const void *Da, const void *Db, int W, int H, int n, int r, int pass,
+static void propagate_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r, int pass,
                         int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
@@ -330,15 +391,15 @@ static void propagate_g(or_cost_fn E, const void *Da, const void *Db, int W, int
                 int k = j * Wn + i, x = i * n, y = j * n;
                 uint32_t bc = cost[k];
                 int bfx = flow[2 * k], bfy = flow[2 * k + 1];
-                for (int s = 0; s < 2; ++s) {
-                    int si = s == 0 ? i + hdi : i, sj = s == 0 ? j : j + vdj;
+                for (int src = 0; src < 2; ++src) {  /* horizontal, then vertical source */
+                    int si = src == 0 ? i + hdi : i, sj = src == 0 ? j : j + vdj;
                     if (si < 0 || si >= Wn || sj < 0 || sj >= Hn) continue;
                     int ks = sj * Wn + si;
                     if (cost[ks] == OR_UNSET) continue;
                     int fx = flow[2 * ks], fy = flow[2 * ks + 1];
                     if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
-                    if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
-                    uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy);
+                    if (!target_in(W, H, x, y, fx, fy, s)) continue;
+                    uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
                     cnt += 1;
                     if (e < bc) { bc = e; bfx = fx; bfy = fy; }
                 }
@@ -353,7 +414,7 @@ static void propagate_g(or_cost_fn E, const void *Da, const void *Db, int W, int
 void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
                   int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
-    propagate_g(cost_u8, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
+    propagate_g(cost_u8, 0, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
 }
 
 /* SplitMix64 output mixer (Steele, Lea, Flood 2014). */
@@ -385,8 +446,8 @@ void or_rs_offset(uint64_t seed, int stream, int level, int pass, int j, int i, 
 /* One random-search step (Sec. 3.1): every set cell tries its flow plus a
  * random offset and keeps it if E_n strictly decreases.  Offset (0, 0) and
  * targets outside the image are skipped. */
-static void random_search_g(or_cost_fn E, const void *Da, const void *Db, int W, int H, int n, int r, int Rn,
-                            uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
+static void random_search_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r,
+                            int Rn, uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
                             uint64_t *n_evals, int nthreads)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n);
@@ -399,11 +460,12 @@ static void random_search_g(or_cost_fn E, const void *Da, const void *Db, int W,
         for (int i = 0; i < Wn; ++i) {
             int k = j * Wn + i, x = i * n, y = j * n, ox, oy;
             if (cost[k] == OR_UNSET) continue;
-            or_rs_offset(seed, stream, level, pass, j, i, Rn, &ox, &oy);
+            /* offsets uniform on [-Rn, Rn]^2 in units of 1/2^s pixel */
+            or_rs_offset(seed, stream, level, pass, j, i, Rn * (1 << s), &ox, &oy);
             if (ox == 0 && oy == 0) continue;
             int fx = flow[2 * k] + ox, fy = flow[2 * k + 1] + oy;
-            if (x + fx < 0 || x + fx >= W || y + fy < 0 || y + fy >= H) continue;
-            uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy);
+            if (!target_in(W, H, x, y, fx, fy, s)) continue;
+            uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
             cnt += 1;
             if (e < cost[k]) {
                 cost[k] = e;
@@ -418,26 +480,36 @@ void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n,
                       uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
                       uint64_t *n_evals, int nthreads)
 {
-    random_search_g(cost_u8, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals, nthreads);
+    random_search_g(cost_u8, 0, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals, nthreads);
 }
 
 /* Forward-backward consistency (Sec. 3.7): keep pixel p of field a iff it is
  * set, its target q = p + F_a(p) is set in field b and
- * |F_a(p) + F_b(q)|^2 < eps^2 (integer flows, exact). */
-void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
-                    int W, int H, double eps, uint8_t *keep)
+ * |F_a(p) + F_b(q)| < eps (exact integer test).  Flows in units of 1/2^s
+ * pixel: q is the pixel nearest to the target (halves rounded up) and the
+ * test is |F_a(p) + F_b(q)|^2 < (eps 2^s)^2 in those units. */
+static void consistency_g(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W,
+                          int H, int s, double eps, uint8_t *keep)
 {
+    int S = 1 << s;
+    double lim = eps * S;
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             size_t k = (size_t)y * W + x;
             keep[k] = 0;
             if (ca[k] == OR_UNSET) continue;
-            int qx = x + fa[2 * k], qy = y + fa[2 * k + 1];
+            int qx = (x * S + fa[2 * k] + S / 2) / S, qy = (y * S + fa[2 * k + 1] + S / 2) / S;
             size_t kq = (size_t)qy * W + qx;
             if (cb[kq] == OR_UNSET) continue;
             int64_t dx = fa[2 * k] + fb[2 * kq], dy = fa[2 * k + 1] + fb[2 * kq + 1];
-            keep[k] = (double)(dx * dx + dy * dy) < eps * eps;
+            keep[k] = (double)(dx * dx + dy * dy) < lim * lim;
         }
+}
+
+void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
+                    int W, int H, double eps, uint8_t *keep)
+{
+    consistency_g(fa, ca, fb, cb, W, H, 0, eps, keep);
 }
 
 /* Consistency against two backward fields (Sec. 3.7): keep pixel p of
@@ -594,7 +666,7 @@ static or_scale_steps scale_steps(int level, int T, int R_num, int R_den, int P,
 
 /* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, with the
  * per-scale steps of scale_steps. */
-static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
+static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
                                const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
                                int P, int Rp_num, int Tfine, uint64_t seed, int stream, int nthreads,
                                int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
@@ -612,19 +684,20 @@ static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *N
     }
     or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
     int cur = 0;
-    init_coarse_g(E, idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
+    init_coarse_g(E, s, idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
     for (int level = L - 1; level >= 0; --level) {
         int n = 1 << level;
         if (level < L - 1) {
-            seed_level_g(E, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
+            seed_level_g(E, s, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1],
+                         n_evals);
             cur ^= 1;
         }
         or_scale_steps st = scale_steps(level, T, R_num, R_den, P, Rp_num, Tfine);
         for (int t = 0; t < st.P + st.T; ++t) {
-            propagate_g(E, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
+            propagate_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
             int last_of_group = t == st.P - 1 || t == st.P + st.T - 1;
             if (!last_of_group)
-                random_search_g(E, Da[level], Db[level], W, H, n, r, t < st.P ? st.Rnp : st.Rn, seed, stream,
+                random_search_g(E, s, Da[level], Db[level], W, H, n, r, t < st.P ? st.Rnp : st.Rn, seed, stream,
                                 level, t, fl[cur], co[cur], n_evals, nthreads);
         }
     }
@@ -638,14 +711,17 @@ static void flow_one_direction(or_cost_fn E, const uint8_t *Nq, const uint8_t *N
 /* The whole hot path for one image pair: scale-space descriptors of both
  * images at every level, forward field (img1 -> img2, stream 0), backward
  * field (img2 -> img1, stream 1) and both consistency masks.
- * n_evals[0], n_evals[1]: number of E_n evaluations of each direction. */
-int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r,
-                   int R_num, int R_den, int P, int Rp_num, int Tfine, double eps, uint64_t seed, int nthreads,
-                   int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
-                   uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+ * n_evals[0], n_evals[1]: number of E_n evaluations of each direction.
+ * s > 0: the subpixel form (flows, random-search offsets and the
+ * consistency threshold in units of 1/2^s pixel, costs of or_cost_sub). */
+static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
+                         int R_den, int P, int Rp_num, int Tfine, int s, double eps, uint64_t seed, int nthreads,
+                         int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                         uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
-        R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64)
+        R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64 || s < 0 || s > 3 ||
+        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))))
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *blur = (uint8_t *)malloc(np);
@@ -659,16 +735,58 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
         or_blur(img2, W, H, n, blur);
         or_descriptor(blur, W, H, n, D2[l]);
     }
+    or_cost_fn E = s > 0 ? cost_u8_sub : cost_u8;
     n_evals[0] = n_evals[1] = 0;
-    flow_one_direction(cost_u8, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
+    flow_one_direction(E, s, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
                        R_num, R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
-    flow_one_direction(cost_u8, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
+    flow_one_direction(E, s, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
                        R_num, R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
-    or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
-    if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
+    consistency_g(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, s, eps, keep_fwd);
+    if (keep_bwd) consistency_g(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, s, eps, keep_bwd);
     for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
     free(blur);
     return 0;
+}
+
+int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r,
+                   int R_num, int R_den, int P, int Rp_num, int Tfine, double eps, uint64_t seed, int nthreads,
+                   int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                   uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+{
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, eps, seed, nthreads, flow_fwd,
+                         flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+}
+
+/* The subpixel form of or_flow_fields (flows in units of 1/2^s pixel). */
+int or_flow_fields_sub(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
+                       int R_den, int P, int Rp_num, int Tfine, int s, double eps, uint64_t seed, int nthreads,
+                       int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                       uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+{
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, eps, seed, nthreads, flow_fwd,
+                         flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+}
+
+/* One propagation step and one random-search step of the subpixel form
+ * (flows in units of 1/2^s pixel; Rn in pixels). */
+void or_propagate_sub(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int s, int pass,
+                      int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
+{
+    propagate_g(cost_u8_sub, s, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
+}
+
+void or_random_search_sub(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int s, int Rn,
+                          uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
+                          uint64_t *n_evals, int nthreads)
+{
+    random_search_g(cost_u8_sub, s, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals,
+                    nthreads);
+}
+
+void or_consistency_sub(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W, int H,
+                        int s, double eps, uint8_t *keep)
+{
+    consistency_g(fa, ca, fb, cb, W, H, s, eps, keep);
 }
 
 /* The same multi-scale schedule on learned float features: F1[l], F2[l] are
@@ -688,9 +806,9 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
     uint8_t *q1 = (uint8_t *)malloc(np * 16), *q2 = (uint8_t *)malloc(np * 16);
     or_quantize_pair_u8(F1[0], F2[0], (int64_t)np * 16, q1, q2);
     n_evals[0] = n_evals[1] = 0;
-    flow_one_direction(cost_f32, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
+    flow_one_direction(cost_f32, 0, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
                        R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
-    flow_one_direction(cost_f32, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
+    flow_one_direction(cost_f32, 0, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
                        R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
