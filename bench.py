@@ -264,6 +264,25 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
                      "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
                      "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
                      "kept_epe": round(q["kept_epe"], 4)}
+    # subpixel random search (Sec. 3.1): flows in 1/8 px, bilinear targets (per-step kernels)
+    import numpy as _np
+    prm = dataclasses.replace(params, subpixel=3)
+    H, W = img1.shape
+    runner = ff.FlowFields(W, H, prm, device=img1.device)
+    runner(img1, img2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        runner(img1, img2)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    out = runner.out
+    q = epe_stats(out["flow_fwd"].cpu().numpy().astype(_np.float64) / 8.0, pair.flow_gt, pair.occ,
+                  keep=out["keep_fwd"].cpu().numpy())
+    res["subpixel"] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
+                       "flow_unit": "1/8 px", "n_evals": [int(v) for v in out["n_evals"].cpu()],
+                       "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
+                       "kept_density": round(q["kept_density"], 4), "kept_epe": round(q["kept_epe"], 4)}
     # the original schedule with the check against two backward fields (Sec. 3.7; second field: seed + 1,
     # patch radius 2)
     run2 = lambda: ff.flow_fields_two_backward(img1, img2, params, radius2=2)  # noqa: E731

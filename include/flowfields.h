@@ -89,6 +89,16 @@ typedef struct {
     int32_t plus_iters;
     int32_t Rp_num;
     int32_t fine_iters;
+    /* Subpixel random search (Sec. 3.1: offsets with subpixel accuracy, the
+     * target patch's colours by bilinear interpolation): 0 = integer flows;
+     * 3 = every flow, random-search offset (uniform on [-R_n, R_n]^2 in
+     * steps of 1/8 px) and the consistency threshold in units of 1/8 pixel,
+     * image b's descriptors bilinearly interpolated at the target with
+     * weights in 1/64, costs 64 times Eq. 3 (exact integers).  Requires
+     * W, H <= 4095 (int16 flows); other values FF_ERR_ARG.  Runs on the
+     * per-step kernels; ff_flow_fields_batched and ff_flow_fields_f32
+     * return FF_ERR_UNSUPPORTED for it. */
+    int32_t subpixel;
     /* host, nullable: launch tables of this call (NULL: the built-in table,
      * see ff_default_tuning); an entry out of range is FF_ERR_ARG. */
     const ff_tuning *tuning;
@@ -203,6 +213,14 @@ ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t
 ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
                                 const uint32_t *cost_b, int32_t W, int32_t H, float eps, uint8_t *keep_a,
                                 uint8_t *keep_b, void *stream);
+
+/* ff_consistency_filter for flows in units of 1/2^subpixel pixel
+ * (subpixel in [0, 3]): q is the pixel nearest to p + F_a(p) (halves
+ * rounded up) and the test is |F_a(p) + F_b(q)|^2 < (eps 2^subpixel)^2 in
+ * those units; subpixel = 0 is ff_consistency_filter. */
+ff_status ff_consistency_filter_sub(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                    const uint32_t *cost_b, int32_t W, int32_t H, int32_t subpixel, float eps,
+                                    uint8_t *keep_a, uint8_t *keep_b, void *stream);
 
 /* Consistency against two backward fields (Sec. 3.7): keep_a[p] = 1 iff p
  * passes the ff_consistency_filter test against field b1 and against field

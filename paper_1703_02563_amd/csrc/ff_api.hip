@@ -42,7 +42,13 @@ bool params_ok(const ff_params *p) {
   return p && p->levels >= 1 && p->levels <= kMaxLevels && p->iters >= 1 && p->iters <= 64 && p->radius >= 0 &&
          p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20 &&
          p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
-         p->fine_iters >= 0 && p->fine_iters <= 64 && ffh::tuning_ok(tuning_of(p->tuning));
+         p->fine_iters >= 0 && p->fine_iters <= 64 && (p->subpixel == 0 || p->subpixel == 3) &&
+         ffh::tuning_ok(tuning_of(p->tuning));
+}
+
+// Subpixel flows (1/8 px in int16) reach at most 4095 px.
+bool sub_dims_ok(const ff_params *p, int W, int H) {
+  return p->subpixel == 0 || (W <= (32767 >> p->subpixel) && H <= (32767 >> p->subpixel));
 }
 
 int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
@@ -387,6 +393,16 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
                                           (hipStream_t)stream));
 }
 
+ff_status ff_consistency_filter_sub(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                    const uint32_t *cost_b, int32_t W, int32_t H, int32_t subpixel, float eps,
+                                    uint8_t *keep_a, uint8_t *keep_b, void *stream) {
+  if (!flow_a || !cost_a || !flow_b || !cost_b || !keep_a || !dims_ok(W, H) || !(eps >= 0.0f) || subpixel < 0 ||
+      subpixel > 3)
+    return FF_ERR_ARG;
+  return from_hip(ffh::launch_consistency(flow_a, cost_a, flow_b, cost_b, W, H, eps, keep_a, keep_b,
+                                          (hipStream_t)stream, subpixel));
+}
+
 ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b1,
                                  const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
                                  int32_t H, float eps, uint8_t *keep_a, void *stream) {
@@ -440,9 +456,10 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
     return FF_ERR_ARG;
   if (!scratch || scratch_bytes < ff_run_level_scratch_bytes(W, H, level)) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
+  if (!sub_dims_ok(params, W, H)) return FF_ERR_ARG;
   const int n = 1 << level, r = params->radius;
   const ScaleSteps st = scale_steps(params, level);
-  if (r == 3) {
+  if (r == 3 && params->subpixel == 0) {
     ffh::LevelKArgs k{};
     k.ndir = 1;
     k.dir[0].Da = desc_a;
@@ -463,6 +480,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
     return from_hip(run_level_blocked(k, W, H, level, params, first, s, sf, sc));
   }
   ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, r, flow, cost, n_evals);
+  a.fcost = params->subpixel ? 2 : 0;
   a.level = level;
   a.seed = params->seed;
   a.Rn = st.Rn;
@@ -607,7 +625,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
                                  void *ws, size_t ws_bytes, void *stream) {
   if (!batch_ok(pairs, npairs, params) || !table || !ws || !(params->eps >= 0.0f)) return FF_ERR_ARG;
   if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
-  if (params->radius != 3) return FF_ERR_UNSUPPORTED;
+  if (params->radius != 3 || params->subpixel) return FF_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const int L = params->levels, nc = 1 << (L - 1);
   ffh::BatchStage st{};
@@ -729,6 +747,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const int L = params->levels, r = params->radius;
+  if (params->subpixel) return FF_ERR_UNSUPPORTED;
   for (int lv = 0; lv < L; ++lv)
     if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
   const LayoutF32 lay = layout_f32(W, H, params);
@@ -990,8 +1009,9 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   // forward field only: every backward output and both masks NULL
   const bool fwd_only = !flow_bwd && !cost_bwd && !keep_fwd && !keep_bwd;
   if (!img1 || !img2 || !ws || !flow_fwd || !cost_fwd || (!fwd_only && (!flow_bwd || !cost_bwd || !keep_fwd)) ||
-      !nn_dims_ok(W, H) || !params_ok(params) || !(params->eps >= 0.0f))
+      !nn_dims_ok(W, H) || !params_ok(params) || !(params->eps >= 0.0f) || !sub_dims_ok(params, W, H))
     return FF_ERR_ARG;
+  const int sb = params->subpixel;  // flows in 1/2^sb px
   const int nd = fwd_only ? 1 : 2;  // directions computed
   const Layout lay = layout(W, H, params);
   if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
@@ -1055,7 +1075,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     nn.dir[dr] = {desc1[dr], desc1[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
 
-  if (r == 3) {
+  if (r == 3 && sb == 0) {
     // temporally blocked level kernels: one launch per run of passes
     int32_t *sflow[kMaxLevels][2];
     uint32_t *scost[kMaxLevels][2];
@@ -1100,6 +1120,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
 
   ffh::LevelArgs a{};
   a.ndir = nd;
+  a.fcost = sb ? 2 : 0;
   a.W = W;
   a.H = H;
   a.radius = r;
@@ -1123,7 +1144,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   }
   if (fwd_only) return FF_OK;
   return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
-                                          keep_bwd, s));
+                                          keep_bwd, s, sb));
 }
 
 }  // extern "C"

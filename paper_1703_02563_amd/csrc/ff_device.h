@@ -138,6 +138,7 @@ __device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const 
 // fused multiply-add per term in the order v, u, c, added as
 // (s0 + s1) + (s2 + s3).
 struct CostU8 {
+  static constexpr int kSub = 0;  // flows in whole pixels
   template <int R>
   __device__ static uint32_t eval(const void *Da, const void *Db, int W, int H, int n, int x, int y, int fx,
                                   int fy) {
@@ -152,6 +153,7 @@ struct CostU8 {
 };
 
 struct CostF32 {
+  static constexpr int kSub = 0;
   template <int R>
   __device__ static uint32_t eval(const void *Da, const void *Db, int W, int H, int n, int x, int y, int fx,
                                   int fy) {
@@ -188,6 +190,77 @@ struct CostF32 {
     c2 = en2 ? eval<R>(Da, Db, W, H, n, x, y, f2x, f2y) : 0u;
   }
 };
+
+// Four channels of the subpixel cost: |64 a - sum_k w_k b_k| per byte,
+// summed into acc.  The bytes go to 16-bit lanes (even and odd bytes); a
+// weighted sum of four bytes with weights summing to 64 stays below 2^14 in
+// its lane, so the lanes of one 32-bit multiply-add never carry into each
+// other, and v_sad_u16 adds both lanes' absolute differences.
+__device__ __forceinline__ uint32_t sad_bilinear4(uint32_t a, uint32_t b00, uint32_t b10, uint32_t b01, uint32_t b11,
+                                                  uint32_t w00, uint32_t w10, uint32_t w01, uint32_t w11,
+                                                  uint32_t acc) {
+  constexpr uint32_t m = 0x00FF00FFu;
+  const uint32_t ae = (a & m) << 6, ao = ((a >> 8) & m) << 6;
+  const uint32_t me = (b00 & m) * w00 + (b10 & m) * w10 + (b01 & m) * w01 + (b11 & m) * w11;
+  const uint32_t mo = ((b00 >> 8) & m) * w00 + ((b10 >> 8) & m) * w10 + ((b01 >> 8) & m) * w01 +
+                      ((b11 >> 8) & m) * w11;
+  acc = __builtin_amdgcn_sad_u16(ae, me, acc);
+  return __builtin_amdgcn_sad_u16(ao, mo, acc);
+}
+
+// Subpixel matching error (random-search offsets with subpixel accuracy,
+// the target patch's colours by bilinear interpolation): flows in 1/8
+// pixel; the target t = p + f / 8 lies between pixels (tx0, ty0) and
+// (tx0 + 1, ty0 + 1) with fractions ax, ay; image b's descriptors at every
+// patch position t + n(u, v) are the bilinear mix of the four pixels'
+// descriptors (each read through the border) with weights (8 - ax)(8 - ay),
+// ax (8 - ay), (8 - ax) ay, ax ay; E = sum |64 a - mix| over patch positions
+// and channels (Eq. 3 times 64, exact).  A corner of weight 0 is read at
+// the other corner's column or row (its value does not matter).
+struct CostU8Sub {
+  static constexpr int kSub = 3;
+  template <int R>
+  __device__ static uint32_t eval(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
+                                  int fy) {
+    const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
+    const int tx = x * 8 + fx, ty = y * 8 + fy;  // inside the image: non-negative
+    const int tx0 = tx >> 3, ty0 = ty >> 3, ax = tx & 7, ay = ty & 7;
+    const int tx1 = tx0 + (ax != 0), ty1 = ty0 + (ay != 0);
+    const uint32_t w00 = (8 - ax) * (8 - ay), w10 = ax * (8 - ay), w01 = (8 - ax) * ay, w11 = ax * ay;
+    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    uint32_t sum = 0;
+#pragma unroll 1
+    for (int v = -R; v <= R; ++v) {
+      const uint4 *ra = Da + (size_t)(clampi(y + n * v, Hm) + P) * Wp;
+      const uint4 *r0 = Db + (size_t)(clampi(ty0 + n * v, Hm) + P) * Wp;
+      const uint4 *r1 = Db + (size_t)(clampi(ty1 + n * v, Hm) + P) * Wp;
+#pragma unroll 1
+      for (int u = -R; u <= R; ++u) {
+        const uint4 a = ra[desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
+        const int c0 = desc_col(clampi(tx0 + n * u, Wm) + P, l2, Wp), c1 = desc_col(clampi(tx1 + n * u, Wm) + P, l2, Wp);
+        const uint4 b00 = r0[c0], b10 = r0[c1], b01 = r1[c0], b11 = r1[c1];
+        sum = sad_bilinear4(a.x, b00.x, b10.x, b01.x, b11.x, w00, w10, w01, w11, sum);
+        sum = sad_bilinear4(a.y, b00.y, b10.y, b01.y, b11.y, w00, w10, w01, w11, sum);
+        sum = sad_bilinear4(a.z, b00.z, b10.z, b01.z, b11.z, w00, w10, w01, w11, sum);
+        sum = sad_bilinear4(a.w, b00.w, b10.w, b01.w, b11.w, w00, w10, w01, w11, sum);
+      }
+    }
+    return sum;
+  }
+  template <int R>
+  __device__ static void eval2(const void *Da, const void *Db, int W, int H, int n, int x, int y, int f1x, int f1y,
+                               bool en1, int f2x, int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
+    c1 = en1 ? eval<R>(Da, Db, W, H, n, x, y, f1x, f1y) : 0u;
+    c2 = en2 ? eval<R>(Da, Db, W, H, n, x, y, f2x, f2y) : 0u;
+  }
+};
+
+// Target p + f / 2^SB of a flow (in units of 1/2^SB pixel) inside the image.
+template <int SB>
+__device__ __forceinline__ bool target_in(int W, int H, int x, int y, int fx, int fy) {
+  const int tx = x * (1 << SB) + fx, ty = y * (1 << SB) + fy;
+  return tx >= 0 && tx <= (W - 1) * (1 << SB) && ty >= 0 && ty <= (H - 1) * (1 << SB);
+}
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

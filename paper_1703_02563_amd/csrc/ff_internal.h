@@ -78,7 +78,7 @@ struct LevelDir {
 struct LevelArgs {
   LevelDir dir[kMaxDirs];
   int ndir;
-  int fcost;  // 0: byte descriptors, SAD; 1: float32 16-channel features, SSD
+  int fcost;  // 0: byte descriptors, SAD; 1: float32 16-channel features, SSD; 2: byte descriptors, 1/8-px flows
   int W, H, n, Wn, Hn, radius;
   int Rn, level, pass;
   uint64_t seed;
@@ -258,7 +258,9 @@ hipError_t launch_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t
 hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,
                                const int16_t *fb2, const uint32_t *cb2, int W, int H, float eps, uint8_t *keep,
                                hipStream_t stream);
+// sb: flows in units of 1/2^sb pixel (0: whole pixels)
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
-                              int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream);
+                              int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream,
+                              int sb = 0);
 
 }  // namespace ffh

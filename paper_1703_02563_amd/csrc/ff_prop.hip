@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
         na += e * e;
       }
     const_cast<uint64_t *>(d.nn_key)[m] = ((uint64_t)(uint32_t)(dd + na) << 32) | q;
-    const int fx = (int)(q % (uint32_t)a.W) - x, fy = (int)(q / (uint32_t)a.W) - y;
+    // the seed is an integer flow, stored in the cost's flow unit
+    const int fx = ((int)(q % (uint32_t)a.W) - x) * (1 << Cost::kSub), fy = ((int)(q / (uint32_t)a.W) - y) * (1 << Cost::kSub);
     d.flow[m] = ffk::pack_flow(fx, fy);
     d.cost[m] = Cost::template eval<R>(d.Da, d.Db,
                                    a.W, a.H, a.n, x, y, fx, fy);
@@ -114,8 +115,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
       const int ks = j * Wn + hi;
       if (d.cost[ks] != kUnset) {
         fh = d.flow[ks];
-        const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
-        hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
+        hv = !(set0 && fh == f0) && ffk::target_in<Cost::kSub>(W, H, x, y, ffk::flow_x(fh), ffk::flow_y(fh));
       }
     }
     // vertical source: validity except the "held flow" rule, which depends
@@ -127,8 +127,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
       const int ks = vj * Wn + i;
       if (d.cost[ks] != kUnset) {
         fv = d.flow[ks];
-        const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
-        vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
+        vb = ffk::target_in<Cost::kSub>(W, H, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
       }
     }
     // E(p, fv) need not be computed in the shared pass when fv equals fh
@@ -182,11 +181,12 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
     const uint32_t c0 = d.cost[k];
     if (c0 != kUnset) {
       int ox, oy;
-      ffk::rs_offset(a.seed, d.stream_id, a.level, a.pass, j, i, a.Rn, ox, oy);
+      // offsets uniform on [-Rn, Rn]^2 in the cost's flow unit
+      ffk::rs_offset(a.seed, d.stream_id, a.level, a.pass, j, i, a.Rn * (1 << Cost::kSub), ox, oy);
       const int32_t f0 = d.flow[k];
       const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
       const int x = i * a.n, y = j * a.n;
-      if ((ox | oy) != 0 && x + fx >= 0 && x + fx < a.W && y + fy >= 0 && y + fy < a.H) {
+      if ((ox | oy) != 0 && ffk::target_in<Cost::kSub>(a.W, a.H, x, y, fx, fy)) {
         const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.n, x, y, fx, fy);
         cnt = 1;
         if (e < c0) {
@@ -202,8 +202,10 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
 
 // blockIdx.z = 1 runs the check with the roles of the two fields swapped
 // (the mask of field b), in the same launch.
+// Flows in units of 1/2^sb pixel: q is the pixel nearest to the target
+// (halves rounded up); eps2 is the squared threshold in those units.
 __global__ __launch_bounds__(256) void k_consistency(const int32_t *fa0, const uint32_t *ca0, const int32_t *fb0,
-                                                     const uint32_t *cb0, int W, int H, double eps2,
+                                                     const uint32_t *cb0, int W, int H, int sb, double eps2,
                                                      uint8_t *keep_a, uint8_t *keep_b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= W || y >= H) return;
@@ -215,7 +217,9 @@ __global__ __launch_bounds__(256) void k_consistency(const int32_t *fa0, const u
   uint8_t out = 0;
   if (ca[k] != kUnset) {
     const int32_t f = fa[k];
-    const int qx = x + ffk::flow_x(f), qy = y + ffk::flow_y(f);
+    const int half = (1 << sb) >> 1;
+    const int tx = (x << sb) + ffk::flow_x(f) + half, ty = (y << sb) + ffk::flow_y(f) + half;
+    const int qx = tx >= 0 ? tx >> sb : -1, qy = ty >= 0 ? ty >> sb : -1;
     const size_t kq = (size_t)qy * W + qx;
     // fields made by the method never point outside; caller-made ones may
     if (qx >= 0 && qx < W && qy >= 0 && qy < H && cb[kq] != kUnset) {
@@ -330,8 +334,10 @@ __global__ __launch_bounds__(256) void k_consistency_batch(ffh::BatchStage st, d
     default: return hipErrorInvalidValue;                                       \
   }
 #define FF_RADIUS_SWITCH(A_, CALL)                                              \
-  if ((A_).fcost) {                                                             \
+  if ((A_).fcost == 1) {                                                        \
     FF_RADIUS_SWITCH_C((A_).radius, CALL, ffk::CostF32)                         \
+  } else if ((A_).fcost == 2) {                                                 \
+    FF_RADIUS_SWITCH_C((A_).radius, CALL, ffk::CostU8Sub)                       \
   } else {                                                                      \
     FF_RADIUS_SWITCH_C((A_).radius, CALL, ffk::CostU8)                          \
   }
@@ -405,11 +411,11 @@ hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int1
 }
 
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W,
-                              int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream) {
+                              int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream, int sb) {
   dim3 grid((W + 255) / 256, H, keep_b ? 2 : 1);
-  const double eps2 = (double)eps * (double)eps;
+  const double lim = (double)eps * (double)(1 << sb);
   hipLaunchKernelGGL(k_consistency, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
-                     reinterpret_cast<const int32_t *>(fb), cb, W, H, eps2, keep_a, keep_b);
+                     reinterpret_cast<const int32_t *>(fb), cb, W, H, sb, lim * lim, keep_a, keep_b);
   return hipGetLastError();
 }
 

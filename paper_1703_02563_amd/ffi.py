@@ -45,6 +45,7 @@ class FFParams(C.Structure):
         ("plus_iters", C.c_int32),
         ("Rp_num", C.c_int32),
         ("fine_iters", C.c_int32),
+        ("subpixel", C.c_int32),
         ("tuning", C.POINTER(FFTuning)),
     ]
 
@@ -67,6 +68,7 @@ _SIGS = {
                                    _P, _P]),
     "ff_consistency_filter": (C.c_int, [_P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_consistency_filter2": (C.c_int, [_P, _P, _P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P]),
+    "ff_consistency_filter_sub": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_sparsify": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P]),
     "ff_region_filter_scratch_bytes": (C.c_size_t, [_I32, _I32]),
     "ff_region_filter": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _P, C.c_size_t, _P, _P]),

@@ -62,11 +62,12 @@ class Params:
     plus_iters: int = 0  # Flow Fields+: steps at R+ = Rp_num / R_den before the `iters` steps at R
     Rp_num: int = 0
     fine_iters: int = 0  # Flow Fields+ Fast: steps at R on the finest scale (0: as the other scales)
+    subpixel: int = 0  # 3: flows, random-search offsets and the threshold in 1/8 px, bilinear targets
     tuning: Tuning | None = None  # launch tables of the calls (None: the built-in tables)
 
     def to_c(self) -> FFParams:
         p = FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
-                     self.plus_iters, self.Rp_num, self.fine_iters, None)
+                     self.plus_iters, self.Rp_num, self.fine_iters, self.subpixel, None)
         if self.tuning is not None:
             p._tuning = self.tuning.to_c()  # kept alive with the struct that points at it
             p.tuning = ctypes.pointer(p._tuning)
@@ -215,6 +216,17 @@ def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: b
     check(lib().ff_consistency_filter(_ptr(flow_a, torch.int16), _ptr(cost_a, torch.int32), _ptr(flow_b, torch.int16),
                                       _ptr(cost_b, torch.int32), W, H, eps, _ptr(keep_a), _ptr(keep_b), _stream()),
           "ff_consistency_filter")
+    return keep_a, keep_b
+
+
+def consistency_filter_sub(flow_a, cost_a, flow_b, cost_b, subpixel: int, eps: float = 1.0, both: bool = True):
+    """Consistency of fields with flows in units of 1/2^subpixel pixel."""
+    H, W = cost_a.shape
+    keep_a = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device)
+    keep_b = torch.empty((H, W), dtype=torch.uint8, device=cost_a.device) if both else None
+    check(lib().ff_consistency_filter_sub(_ptr(flow_a, torch.int16), _ptr(cost_a, torch.int32),
+                                          _ptr(flow_b, torch.int16), _ptr(cost_b, torch.int32), W, H, subpixel, eps,
+                                          _ptr(keep_a), _ptr(keep_b), _stream()), "ff_consistency_filter_sub")
     return keep_a, keep_b
 
 

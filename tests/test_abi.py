@@ -164,3 +164,19 @@ def test_noalloc_region_filter_validation():
     assert lib.ff_region_filter_noalloc(fake, fake, fake, 10, 5, 3, fake, None) == ffi.FF_ERR_ARG  # in place
     assert lib.ff_region_filter_noalloc(None, fake, fake, 10, 5, 3, out, None) == ffi.FF_ERR_ARG
     assert lib.ff_region_filter_noalloc(fake, fake, fake, 0, 5, 3, out, None) == ffi.FF_ERR_ARG
+
+
+def test_subpixel_arguments():
+    """The subpixel form accepts 0 or 3 bits and frames up to 4095 px; the
+    batch and learned-feature calls do not support it."""
+    lib = ffi.lib()
+    fake = C.c_void_p(0x1000)
+    for bad in (1, 2, 4, -1):
+        q = ff.Params(subpixel=bad).to_c()
+        assert lib.ff_workspace_bytes(64, 64, C.byref(q)) == 0, bad
+    q = ff.Params(subpixel=3).to_c()
+    assert lib.ff_workspace_bytes(64, 64, C.byref(q)) > 0
+    assert lib.ff_flow_fields(fake, fake, 4096, 8, C.byref(q), fake, 1 << 40, fake, fake, fake, fake, fake, None,
+                              None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_consistency_filter_sub(fake, fake, fake, fake, 8, 8, 4, C.c_float(1.0), fake, None, None) == \
+        ffi.FF_ERR_ARG
