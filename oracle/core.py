@@ -43,6 +43,12 @@ def lib():
         L.or_cost.restype = C.c_uint32
         L.or_nn.argtypes = [P, P, i, i, i, P, P, i]
         L.or_init_coarse.argtypes = [P, P, P, i, i, i, i, P, P, P]
+        L.or_nn_topl.argtypes = [P, P, i, i, i, i, P, P, i]
+        L.or_init_coarse_l.argtypes = [P, i, P, P, i, i, i, i, P, P, P]
+        L.or_propagate_raster.argtypes = [P, P, i, i, i, i, i, P, P, P]
+        L.or_flow_fields_x.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P,
+                                       P]
+        L.or_flow_fields_x.restype = i
         L.or_seed_level.argtypes = [P, P, P, P, i, i, i, i, P, P, P]
         L.or_propagate.argtypes = [P, P, i, i, i, i, i, P, P, P, i]
         L.or_random_search.argtypes = [P, P, i, i, i, i, i, u64, i, i, i, P, P, P, i]
@@ -121,6 +127,31 @@ def nn(Da1, Db1, nc: int, nthreads: int = 1):
     return idx, dist
 
 
+def nn_topl(Da1, Db1, nc: int, l: int, nthreads: int = 1):
+    """The l nearest pixels of every coarsest-grid cell, ranked by (distance,
+    index): idx [Hc][Wc][l] (-1 past the image's pixel count), dist alike."""
+    H, W = Da1.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    idx = np.empty((Hc, Wc, l), np.int32)
+    dist = np.empty((Hc, Wc, l), np.int64)
+    lib().or_nn_topl(_p(Da1), _p(Db1), W, H, nc, l, _p(idx), _p(dist), nthreads)
+    return idx, dist
+
+
+def init_coarse_l(cand, Da, Db, nc: int, r: int = 3):
+    """Seeds from l ranked candidates per cell (cand [Hc][Wc][l]): the lowest
+    E_nc, the earlier rank on equal cost; returns (flow, cost, n_evals)."""
+    H, W = Da.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    cand = np.ascontiguousarray(cand, np.int32)
+    l = cand.shape[-1]
+    flow = np.empty((Hc, Wc, 2), np.int16)
+    cost_ = np.empty((Hc, Wc), np.uint32)
+    ne = np.zeros(1, np.uint64)
+    lib().or_init_coarse_l(_p(cand), l, _p(Da), _p(Db), W, H, nc, r, _p(flow), _p(cost_), _p(ne))
+    return flow, cost_, int(ne[0])
+
+
 def init_coarse(idx, Da, Db, nc: int, r: int = 3):
     H, W = Da.shape[:2]
     Wc, Hc = cells(W, H, nc)
@@ -151,6 +182,16 @@ def propagate(Da, Db, n: int, pass_: int, flow, cost_, r: int = 3, nthreads: int
     cost_ = np.array(cost_, np.uint32, order="C", copy=True)
     ne = np.zeros(1, np.uint64)
     lib().or_propagate(_p(Da), _p(Db), W, H, n, r, pass_, _p(flow), _p(cost_), _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def propagate_raster(Da, Db, n: int, pass_: int, flow, cost_, r: int = 3):
+    """Serial-order propagation step on copies; returns (flow, cost, n_evals)."""
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_propagate_raster(_p(Da), _p(Db), W, H, n, r, pass_, _p(flow), _p(cost_), _p(ne))
     return flow, cost_, int(ne[0])
 
 
@@ -221,12 +262,13 @@ def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:
 
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
                 eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
-                fine_iters: int = 0, subpixel: int = 0) -> dict:
+                fine_iters: int = 0, subpixel: int = 0, nn_l: int = 1, raster: bool = False) -> dict:
     """The whole schedule on one pair.  plus_iters > 0: Flow Fields+ (P steps
     at R^+ = Rp_num / R_den before the `iters` steps at R); fine_iters > 0:
     the finest scale runs only that many steps at R (Flow Fields+ Fast);
     subpixel = s > 0: flows in units of 1/2^s pixel, bilinear targets, costs
-    of cost_sub (scaled by 4^s)."""
+    of cost_sub (scaled by 4^s); nn_l > 1: seeds reranked among the nn_l
+    nearest pixels (Eq. 4); raster: serial-order propagation steps."""
     img1, img2 = _u8(img1), _u8(img2)
     H, W = img1.shape
     out = {
@@ -235,7 +277,12 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
         "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
     }
     ne = np.zeros(2, np.uint64)
-    if subpixel:
+    if nn_l != 1 or raster:
+        rc = lib().or_flow_fields_x(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters,
+                                    Rp_num, fine_iters, subpixel, nn_l, int(bool(raster)), float(eps), seed, nthreads,
+                                    _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
+                                    _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
+    elif subpixel:
         rc = lib().or_flow_fields_sub(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters,
                                       Rp_num, fine_iters, subpixel, float(eps), seed, nthreads, _p(out["flow_fwd"]),
                                       _p(out["flow_bwd"]), _p(out["cost_fwd"]), _p(out["cost_bwd"]),

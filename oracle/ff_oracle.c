@@ -22,8 +22,11 @@
  *               pixels of the other image under squared L2 of the level-1
  *               descriptors (stands in for the kd-tree of Sec. 3.1 with leaf
  *               size 1, R4); ties go to the smallest linear index.
- *   init        initial flow F = q - p (Eq. 1 / Eq. 4 with |L| = 1) and its
- *               cost at the coarsest scale.
+ *   nn_topl     the l nearest pixels in the same order (the candidate set L
+ *               of Sec. 3.1 read as the l nearest neighbours, R28).
+ *   init        initial flow F = q - p (Eq. 1 / Eq. 4) and its cost at the
+ *               coarsest scale: the candidate of lowest E_nc, the earlier
+ *               rank on equal cost (|L| = 1: the nearest neighbour).
  *   seed_level  coarse-to-fine hand-over (Sec. 3.2): grid pixels shared with
  *               the coarser grid keep its flow (same full-resolution pixel)
  *               and re-evaluate the cost; all others start UNSET.
@@ -32,6 +35,8 @@
  *               as two checkerboard half-sweeps (R1), odd (i+j) first (R11);
  *               candidate order own, horizontal, vertical, strict "<" (R3);
  *               candidates whose target leaves the image are rejected (R9).
+ *   propagate_raster  the same step in the serial order of Sec. 3.1 (a cell
+ *               after its two source cells), R29.
  *   random_search  one random-search step (Sec. 3.1) with integer offsets
  *               uniform on [-R_n, R_n]^2, R_n = floor(R * n) (R5, R6), drawn
  *               from a counter-based generator: SplitMix64's output mixer
@@ -303,28 +308,85 @@ void or_nn(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc,
     }
 }
 
-/* Initial flow of the coarsest scale (Eq. 1 / Eq. 4 with one candidate):
- * F(p) = q - p, cost = E_nc(p, F(p)). */
-static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, const void *Da, const void *Db, int W,
+/* The l nearest neighbours (the candidate set L of Sec. 3.1, a kd-tree leaf
+ * of size l, read as the l nearest pixels): for every cell of the grid of
+ * scale nc, the l pixels q of image b with the smallest (squared L2 distance
+ * of the level-1 descriptors, q.y*W + q.x), in that order; idx[k*l + c],
+ * dist[k*l + c] is candidate c of cell k, idx -1 (dist INT64_MAX) where the
+ * image has fewer than l pixels.  l = 1 is or_nn. */
+void or_nn_topl(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, int l,
+                int32_t *idx, int64_t *dist, int nthreads)
+{
+    int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
+    int64_t N = (int64_t)W * H;
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (int k = 0; k < Wc * Hc; ++k) {
+        int i = k % Wc, j = k / Wc;
+        const uint8_t *a = Da1 + ((size_t)(j * nc) * W + (size_t)(i * nc)) * 16;
+        int32_t *bi = idx + (size_t)k * l;
+        int64_t *bd = dist + (size_t)k * l;
+        for (int c = 0; c < l; ++c) { bi[c] = -1; bd[c] = INT64_MAX; }
+        for (int64_t q = 0; q < N; ++q) {
+            const uint8_t *b = Db1 + (size_t)q * 16;
+            int64_t d = 0;
+            for (int c = 0; c < 16; ++c) {
+                int64_t e = (int64_t)a[c] - (int64_t)b[c];
+                d += e * e;
+            }
+            /* q grows, so an equal distance ranks after every listed entry */
+            if (d >= bd[l - 1]) continue;
+            int pos = l - 1;
+            while (pos > 0 && bd[pos - 1] > d) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = d;
+            bi[pos] = (int32_t)q;
+        }
+    }
+}
+
+/* Initial flow of the coarsest scale (Eq. 1; Eq. 4 at scale nc): of the l
+ * candidates q of a cell p (idx[k*l + c], in rank order, -1 = none), the one
+ * with the lowest E_nc(p, q - p), the earlier rank on equal cost; every
+ * candidate costs one evaluation.  F(p) = q - p. */
+static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, int l, const void *Da, const void *Db, int W,
                           int H, int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     for (int j = 0; j < Hc; ++j)
         for (int i = 0; i < Wc; ++i) {
             int k = j * Wc + i, x = i * nc, y = j * nc;
-            int qx = best_idx[k] % W, qy = best_idx[k] / W;
-            int fx = (qx - x) * (1 << s), fy = (qy - y) * (1 << s);  /* integer seed, in 1/2^s pixel */
-            flow[2 * k] = (int16_t)fx;
-            flow[2 * k + 1] = (int16_t)fy;
-            cost[k] = E(Da, Db, W, H, nc, r, x, y, fx, fy, s);
-            *n_evals += 1;
+            uint32_t bc = OR_UNSET;
+            int bfx = 0, bfy = 0, have = 0;
+            for (int c = 0; c < l; ++c) {
+                int32_t q = best_idx[(size_t)k * l + c];
+                if (q < 0) continue;
+                int fx = (q % W - x) * (1 << s), fy = (q / W - y) * (1 << s);  /* integer seed, in 1/2^s pixel */
+                uint32_t e = E(Da, Db, W, H, nc, r, x, y, fx, fy, s);
+                *n_evals += 1;
+                if (!have || e < bc) { bc = e; bfx = fx; bfy = fy; have = 1; }
+            }
+            flow[2 * k] = (int16_t)bfx;
+            flow[2 * k + 1] = (int16_t)bfy;
+            cost[k] = bc;
         }
 }
 
 void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
                     int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    init_coarse_g(cost_u8, 0, best_idx, Da, Db, W, H, nc, r, flow, cost, n_evals);
+    init_coarse_g(cost_u8, 0, best_idx, 1, Da, Db, W, H, nc, r, flow, cost, n_evals);
+}
+
+void or_init_coarse_l(const int32_t *cand_idx, int l, const uint8_t *Da, const uint8_t *Db, int W, int H,
+                      int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    init_coarse_g(cost_u8, 0, cand_idx, l, Da, Db, W, H, nc, r, flow, cost, n_evals);
 }
 
 /* Hand-over from scale 2n to scale n (Sec. 3.2): cell (i, j) with i and j
@@ -415,6 +477,53 @@ void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int
                   int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
     propagate_g(cost_u8, 0, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
+}
+
+/* One propagation step (Eq. 2) in the serial order the paper asks for: a
+ * cell is updated only after its horizontal and vertical source cells, so a
+ * flow can travel any distance within the step's quadrant.  Direction d's
+ * sources sit at (i + hdi, j) and (i, j + vdj); the scan takes the rows
+ * starting from the side of the vertical source and, within a row, the
+ * cells starting from the side of the horizontal source (d = 0: ordinary
+ * raster order).  The per-cell update is that
+ * of the checkerboard step (own, horizontal, vertical; strictly lower wins;
+ * UNSET, held and out-of-image candidates skipped), reading the sources'
+ * values of this step. */
+static void propagate_raster_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r,
+                               int pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
+    prop_sources(pass & 3, &hdi, &vdj);
+    for (int jj = 0; jj < Hn; ++jj) {
+        int j = vdj < 0 ? jj : Hn - 1 - jj;
+        for (int ii = 0; ii < Wn; ++ii) {
+            int i = hdi < 0 ? ii : Wn - 1 - ii;
+            int k = j * Wn + i, x = i * n, y = j * n;
+            uint32_t bc = cost[k];
+            int bfx = flow[2 * k], bfy = flow[2 * k + 1];
+            for (int src = 0; src < 2; ++src) {  /* horizontal, then vertical source */
+                int si = src == 0 ? i + hdi : i, sj = src == 0 ? j : j + vdj;
+                if (si < 0 || si >= Wn || sj < 0 || sj >= Hn) continue;
+                int ks = sj * Wn + si;
+                if (cost[ks] == OR_UNSET) continue;
+                int fx = flow[2 * ks], fy = flow[2 * ks + 1];
+                if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
+                if (!target_in(W, H, x, y, fx, fy, s)) continue;
+                uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
+                *n_evals += 1;
+                if (e < bc) { bc = e; bfx = fx; bfy = fy; }
+            }
+            cost[k] = bc;
+            flow[2 * k] = (int16_t)bfx;
+            flow[2 * k + 1] = (int16_t)bfy;
+        }
+    }
+}
+
+void or_propagate_raster(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
+                         int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    propagate_raster_g(cost_u8, 0, Da, Db, W, H, n, r, pass, flow, cost, n_evals);
 }
 
 /* SplitMix64 output mixer (Steele, Lea, Flood 2014). */
@@ -665,26 +774,30 @@ static or_scale_steps scale_steps(int level, int T, int R_num, int R_den, int P,
 }
 
 /* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, with the
- * per-scale steps of scale_steps. */
+ * per-scale steps of scale_steps; nn_l candidates per seed (Eq. 4), raster:
+ * serial-order propagation steps instead of checkerboard ones. */
 static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
                                const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
-                               int P, int Rp_num, int Tfine, uint64_t seed, int stream, int nthreads,
-                               int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
+                               int P, int Rp_num, int Tfine, int nn_l, int raster, uint64_t seed, int stream,
+                               int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
 {
     int nc = 1 << (L - 1);
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     size_t cells0 = (size_t)W * H;
-    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)Wc * Hc);
-    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)Wc * Hc);
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)Wc * Hc * nn_l);
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)Wc * Hc * nn_l);
     int16_t *fl[2];
     uint32_t *co[2];
     for (int b = 0; b < 2; ++b) {
         fl[b] = (int16_t *)malloc(sizeof(int16_t) * 2 * cells0);
         co[b] = (uint32_t *)malloc(sizeof(uint32_t) * cells0);
     }
-    or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
+    if (nn_l == 1)
+        or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
+    else
+        or_nn_topl(Nq, Nr, W, H, nc, nn_l, idx, dist, nthreads);
     int cur = 0;
-    init_coarse_g(E, s, idx, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
+    init_coarse_g(E, s, idx, nn_l, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
     for (int level = L - 1; level >= 0; --level) {
         int n = 1 << level;
         if (level < L - 1) {
@@ -694,7 +807,10 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
         }
         or_scale_steps st = scale_steps(level, T, R_num, R_den, P, Rp_num, Tfine);
         for (int t = 0; t < st.P + st.T; ++t) {
-            propagate_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
+            if (raster)
+                propagate_raster_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals);
+            else
+                propagate_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
             int last_of_group = t == st.P - 1 || t == st.P + st.T - 1;
             if (!last_of_group)
                 random_search_g(E, s, Da[level], Db[level], W, H, n, r, t < st.P ? st.Rnp : st.Rn, seed, stream,
@@ -713,15 +829,18 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
  * field (img2 -> img1, stream 1) and both consistency masks.
  * n_evals[0], n_evals[1]: number of E_n evaluations of each direction.
  * s > 0: the subpixel form (flows, random-search offsets and the
- * consistency threshold in units of 1/2^s pixel, costs of or_cost_sub). */
+ * consistency threshold in units of 1/2^s pixel, costs of or_cost_sub).
+ * nn_l in [1, 16]: seeds reranked among the nn_l nearest pixels (Eq. 4);
+ * raster != 0: propagation steps in serial order (propagate_raster_g). */
 static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
-                         int R_den, int P, int Rp_num, int Tfine, int s, double eps, uint64_t seed, int nthreads,
+                         int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, double eps,
+                         uint64_t seed, int nthreads,
                          int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                          uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
         R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64 || s < 0 || s > 3 ||
-        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))))
+        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))) || nn_l < 1 || nn_l > 16)
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *blur = (uint8_t *)malloc(np);
@@ -738,9 +857,11 @@ static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H,
     or_cost_fn E = s > 0 ? cost_u8_sub : cost_u8;
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(E, s, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, seed, 0, nthreads, flow_fwd, cost_fwd,
+                       &n_evals[0]);
     flow_one_direction(E, s, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, seed, 1, nthreads, flow_bwd, cost_bwd,
+                       &n_evals[1]);
     consistency_g(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, s, eps, keep_fwd);
     if (keep_bwd) consistency_g(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, s, eps, keep_bwd);
     for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
@@ -753,8 +874,19 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
                    int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                    uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, eps, seed, nthreads, flow_fwd,
-                         flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, 1, 0, eps, seed, nthreads,
+                         flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+}
+
+/* or_flow_fields with every option: subpixel form s, nn_l seed candidates,
+ * serial-order (raster) propagation. */
+int or_flow_fields_x(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
+                     int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, double eps, uint64_t seed,
+                     int nthreads, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
+                     uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+{
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, nn_l, raster, eps, seed,
+                         nthreads, flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* The subpixel form of or_flow_fields (flows in units of 1/2^s pixel). */
@@ -763,8 +895,8 @@ int or_flow_fields_sub(const uint8_t *img1, const uint8_t *img2, int W, int H, i
                        int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                        uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, eps, seed, nthreads, flow_fwd,
-                         flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, 1, 0, eps, seed, nthreads,
+                         flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* One propagation step and one random-search step of the subpixel form
@@ -807,9 +939,9 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
     or_quantize_pair_u8(F1[0], F2[0], (int64_t)np * 16, q1, q2);
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(cost_f32, 0, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+                       R_den, P, Rp_num, Tfine, 1, 0, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
     flow_one_direction(cost_f32, 0, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+                       R_den, P, Rp_num, Tfine, 1, 0, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     free(q1);
