@@ -102,6 +102,21 @@ typedef struct {
     /* host, nullable: launch tables of this call (NULL: the built-in table,
      * see ff_default_tuning); an entry out of range is FF_ERR_ARG. */
     const ff_tuning *tuning;
+    /* Seed candidates (Sec. 3.1: the l entries of a kd-tree leaf, ranked by
+     * matching error, Eq. 1 / Eq. 4; l = 8 in Sec. 4.1): 0 or 1 = the exact
+     * nearest neighbour alone; 2..8 = the nn_l nearest pixels by (squared
+     * descriptor distance, linear index), of which the one with the lowest
+     * E_nc wins (the earlier rank on equal cost); every candidate counts one
+     * evaluation.  Other values FF_ERR_ARG. */
+    int32_t nn_l;
+    /* Propagation order (Sec. 3.1: a cell after its left and upper
+     * neighbours): 0 = two checkerboard half-sweeps per step; 1 = the serial
+     * order of each step's direction, computed exactly by anti-diagonal
+     * wavefronts (ff_propagate_raster; integer costs; a long chain of
+     * dependent launches, far slower than the checkerboard).  Other values
+     * FF_ERR_ARG.  ff_flow_fields_batched and ff_flow_fields_f32 return
+     * FF_ERR_UNSUPPORTED for nn_l > 1 or raster = 1. */
+    int32_t raster;
 } ff_params;
 
 /* The built-in launch tables (host): written to *out. */
@@ -172,6 +187,34 @@ ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8
                      int32_t *nb_scratch, uint64_t *nn_key, int16_t *flow, uint32_t *cost,
                      uint64_t *n_evals, void *stream);
 
+/* Scratch bytes of ff_nn_topl and ff_init_nn_l for a grid of scale nc
+ * (host; 0 for invalid sizes). */
+size_t ff_nn_topl_scratch_bytes(int32_t W, int32_t H, int32_t nc);
+
+/* The l nearest pixels of image b of every cell p of the grid of scale nc
+ * (the candidate set of Sec. 3.1, a kd-tree leaf of size l, read as the l
+ * nearest neighbours): ranked by (squared L2 distance of the level-1
+ * descriptors, q.y*W + q.x).  cand: uint64 [cells][l] output, entry
+ * (distance << 32) | q, ~0 where the image has fewer than l pixels.
+ * Computed exactly: a bound from the exact NN's neighbourhood, a matrix-core
+ * pass that collects every pixel within it, a selection, and a full scan for
+ * a cell whose collection overflows.  desc_a1, desc_b1: as for ff_init_nn;
+ * nb_scratch: as for ff_init_nn; scratch: device, ff_nn_topl_scratch_bytes
+ * (FF_ERR_WORKSPACE if smaller); 1 <= l <= 8. */
+ff_status ff_nn_topl(const uint8_t *desc_a1, const uint8_t *desc_b1, int32_t W, int32_t H, int32_t nc, int32_t l,
+                     int32_t *nb_scratch, void *scratch, size_t scratch_bytes, uint64_t *cand, void *stream);
+
+/* ff_init_nn with nn_l candidates per cell (Eq. 1 / Eq. 4): the seed of
+ * cell p is the candidate q of ff_nn_topl with the lowest E_nc(p, q - p),
+ * the earlier rank on equal cost; n_evals grows by the number of
+ * candidates.  nn_key receives the winner in ff_init_nn's format.  nn_l 0
+ * or 1: ff_init_nn (scratch unused); 2..8: scratch of
+ * ff_nn_topl_scratch_bytes bytes. */
+ff_status ff_init_nn_l(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac,
+                       const uint8_t *desc_bc, int32_t W, int32_t H, int32_t nc, int32_t radius, int32_t nn_l,
+                       int32_t *nb_scratch, void *scratch, size_t scratch_bytes, uint64_t *nn_key,
+                       int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
+
 /* Coarse-to-fine hand-over from scale 2n to scale n (Sec. 3.2): cells with
  * both grid indices even are the same pixel as a coarse cell and take its
  * flow as a seed, with the cost re-evaluated at scale n; all other cells
@@ -193,6 +236,18 @@ ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost,
 ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
                              int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
                              void *stream);
+
+/* One propagation step (Sec. 3.1, Eq. 2) at scale n in the serial order of
+ * direction d = pass mod 4: rows taken from the side of the vertical source
+ * cell, the cells of a row from the side of the horizontal source cell
+ * (d = 0: raster order), each cell updated as in ff_propagate_level but
+ * after its two source cells, whose values of this step it reads.  Same
+ * result as that serial scan; the GPU sweeps anti-diagonals of 32 x 32-cell
+ * tiles, one launch per tile anti-diagonal (ceil(Wn/32) + ceil(Hn/32) - 1
+ * launches).  Arguments as for ff_propagate_level. */
+ff_status ff_propagate_raster(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                              int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
+                              void *stream);
 
 /* One random-search step (Sec. 3.1) at scale n: every set cell tries
  * F + o with o uniform on [-Rn, Rn]^2 and keeps it if E_n is strictly

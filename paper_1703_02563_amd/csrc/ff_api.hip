@@ -42,9 +42,12 @@ bool params_ok(const ff_params *p) {
   return p && p->levels >= 1 && p->levels <= kMaxLevels && p->iters >= 1 && p->iters <= 64 && p->radius >= 0 &&
          p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20 &&
          p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
-         p->fine_iters >= 0 && p->fine_iters <= 64 && (p->subpixel == 0 || p->subpixel == 3) &&
-         ffh::tuning_ok(tuning_of(p->tuning));
+         p->fine_iters >= 0 && p->fine_iters <= 64 && (p->subpixel == 0 || p->subpixel == 3) && p->nn_l >= 0 &&
+         p->nn_l <= ffh::kTopLMax && (p->raster == 0 || p->raster == 1) && ffh::tuning_ok(tuning_of(p->tuning));
 }
+
+// Seed candidates of the call (0 and 1: the exact NN alone).
+int nn_l_of(const ff_params *p) { return p->nn_l > 1 ? p->nn_l : 1; }
 
 // Subpixel flows (1/8 px in int16) reach at most 4095 px.
 bool sub_dims_ok(const ff_params *p, int W, int H) {
@@ -76,7 +79,8 @@ ScaleSteps scale_steps(const ff_params *p, int lv) {
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, nb, keys, grids, sgrids, evals, total;
+  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, nb, keys, topl, cand, grids, sgrids, evals,
+      total;
   size_t N, Npad, M;
   int L;
 };
@@ -110,6 +114,11 @@ Layout layout(int W, int H, const ff_params *p) {
   l.desc1 = off; off = align256(off + 2 * l.N * 16);
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
+  // seed rerank: bound, collection and ranked candidates of both directions
+  l.topl = off;
+  if (p->nn_l > 1) off = align256(off + 2 * ffh::topl_scratch_bytes((int)l.M));
+  l.cand = off;
+  if (p->nn_l > 1) off = align256(off + 2 * l.M * p->nn_l * sizeof(uint64_t));
   l.grids = off;
   for (int lv = 1; lv < l.L; ++lv) {
     const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
@@ -276,7 +285,8 @@ hipError_t run_level_steps(ffh::LevelArgs a, int W, int H, int lv, int L, const 
   if (e != hipSuccess) return e;
   for (int t = 0; t < st.total(); ++t) {
     a.pass = t;
-    if ((e = ffh::launch_propagate(a, s)) != hipSuccess) return e;
+    e = p->raster ? ffh::launch_propagate_raster(a, s) : ffh::launch_propagate(a, s);
+    if (e != hipSuccess) return e;
     a.Rn = st.radius(t);
     if (st.rs_after(t) && (e = ffh::launch_random_search(a, s)) != hipSuccess) return e;
   }
@@ -346,6 +356,85 @@ ff_status ff_init_nn(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8
   return from_hip(ffh::launch_init_coarse(a, s));
 }
 
+size_t ff_nn_topl_scratch_bytes(int32_t W, int32_t H, int32_t nc) {
+  if (!nn_dims_ok(W, H) || !is_pow2(nc) || nc > (1 << (kMaxLevels - 1))) return 0;
+  const size_t M = (size_t)ceil_div(W, nc) * ceil_div(H, nc);
+  return align256(M * sizeof(uint64_t)) + ffh::topl_scratch_bytes((int)M) +
+         align256(M * ffh::kTopLMax * sizeof(uint64_t));
+}
+
+// The NN keys, then the l ranked candidates of every cell (scratch: keys,
+// the top-l pass's parts, and -- when cand is NULL -- the candidates).
+static hipError_t nn_topl_run(const uint8_t *desc_a1, const uint8_t *desc_b1, int W, int H, int nc, int l,
+                              int32_t *nb_scratch, char *scratch, uint64_t *keys, uint64_t *cand, hipStream_t s) {
+  ffh::NNArgs nn{};
+  nn.ndir = 1;
+  nn.W = W;
+  nn.H = H;
+  nn.nc = nc;
+  nn.Wc = ceil_div(W, nc);
+  nn.M = nn.Wc * ceil_div(H, nc);
+  nn.N = W * H;
+  nn.dir[0] = {desc_a1, desc_b1, nb_scratch, keys};
+  hipError_t e = ffh::launch_nn(nn, s);
+  if (e != hipSuccess) return e;
+  ffh::TopLArgs tl{};
+  tl.ndir = 1;
+  tl.l = l;
+  tl.W = W;
+  tl.H = H;
+  tl.nc = nc;
+  tl.Wc = nn.Wc;
+  tl.M = nn.M;
+  tl.N = nn.N;
+  ffh::TopLDir &d = tl.dir[0];
+  d.Dq = desc_a1;
+  d.Dr = desc_b1;
+  d.nb = nb_scratch;
+  d.nn_key = keys;
+  ffh::topl_carve(scratch + align256((size_t)nn.M * sizeof(uint64_t)), nn.M, d);
+  d.cand = cand;
+  return ffh::launch_topl(tl, s);
+}
+
+ff_status ff_nn_topl(const uint8_t *desc_a1, const uint8_t *desc_b1, int32_t W, int32_t H, int32_t nc, int32_t l,
+                     int32_t *nb_scratch, void *scratch, size_t scratch_bytes, uint64_t *cand, void *stream) {
+  if (!desc_a1 || !desc_b1 || !nb_scratch || !cand || !nn_dims_ok(W, H) || !is_pow2(nc) ||
+      nc > (1 << (kMaxLevels - 1)) || l < 1 || l > ffh::kTopLMax)
+    return FF_ERR_ARG;
+  if (!scratch || scratch_bytes < ff_nn_topl_scratch_bytes(W, H, nc)) return FF_ERR_WORKSPACE;
+  char *sp = static_cast<char *>(scratch);
+  return from_hip(nn_topl_run(desc_a1, desc_b1, W, H, nc, l, nb_scratch, sp, reinterpret_cast<uint64_t *>(sp), cand,
+                              (hipStream_t)stream));
+}
+
+ff_status ff_init_nn_l(const uint8_t *desc_a1, const uint8_t *desc_b1, const uint8_t *desc_ac, const uint8_t *desc_bc,
+                       int32_t W, int32_t H, int32_t nc, int32_t radius, int32_t nn_l, int32_t *nb_scratch,
+                       void *scratch, size_t scratch_bytes, uint64_t *nn_key, int16_t *flow, uint32_t *cost,
+                       uint64_t *n_evals, void *stream) {
+  if (nn_l < 0 || nn_l > ffh::kTopLMax) return FF_ERR_ARG;
+  if (nn_l <= 1)
+    return ff_init_nn(desc_a1, desc_b1, desc_ac, desc_bc, W, H, nc, radius, nb_scratch, nn_key, flow, cost, n_evals,
+                      stream);
+  if (!desc_a1 || !desc_b1 || !desc_ac || !desc_bc || !nb_scratch || !nn_key || !flow || !cost || !nn_dims_ok(W, H) ||
+      !is_pow2(nc) || nc > (1 << (kMaxLevels - 1)) || radius < 0 || radius > 7)
+    return FF_ERR_ARG;
+  if (!scratch || scratch_bytes < ff_nn_topl_scratch_bytes(W, H, nc)) return FF_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *sp = static_cast<char *>(scratch);
+  const int M = ceil_div(W, nc) * ceil_div(H, nc);
+  uint64_t *cand =
+      reinterpret_cast<uint64_t *>(sp + align256((size_t)M * sizeof(uint64_t)) + ffh::topl_scratch_bytes(M));
+  hipError_t e = nn_topl_run(desc_a1, desc_b1, W, H, nc, nn_l, nb_scratch, sp, nn_key, cand, s);
+  if (e != hipSuccess) return FF_ERR_LAUNCH;
+  ffh::LevelArgs a = one_dir_args(desc_ac, desc_bc, W, H, nc, radius, flow, cost, n_evals);
+  a.dir[0].nn_key = nn_key;
+  a.dir[0].Dq1 = desc_a1;
+  const uint64_t *cands[1] = {cand};
+  if ((e = ffh::launch_rerank(a, cands, nn_l, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  return from_hip(ffh::launch_init_coarse(a, s));
+}
+
 ff_status ff_seed_level(const int16_t *coarse_flow, const uint32_t *coarse_cost, const uint8_t *desc_a,
                         const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t radius, int16_t *flow,
                         uint32_t *cost, uint64_t *n_evals, void *stream) {
@@ -367,6 +456,17 @@ ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32
   ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, flow, cost, n_evals);
   a.pass = pass;
   return from_hip(ffh::launch_propagate(a, (hipStream_t)stream));
+}
+
+ff_status ff_propagate_raster(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
+                              int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
+                              void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !is_pow2(n) || radius < 0 || radius > 7 ||
+      pass < 0 || pass > 0xFFFF)
+    return FF_ERR_ARG;
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, flow, cost, n_evals);
+  a.pass = pass;
+  return from_hip(ffh::launch_propagate_raster(a, (hipStream_t)stream));
 }
 
 ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
@@ -459,7 +559,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
   if (!sub_dims_ok(params, W, H)) return FF_ERR_ARG;
   const int n = 1 << level, r = params->radius;
   const ScaleSteps st = scale_steps(params, level);
-  if (r == 3 && params->subpixel == 0) {
+  if (r == 3 && params->subpixel == 0 && !params->raster) {
     ffh::LevelKArgs k{};
     k.ndir = 1;
     k.dir[0].Da = desc_a;
@@ -494,7 +594,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
   if (mode == 2) e = ffh::launch_seed_level(a, s);
   for (int t = 0; t < st.total() && e == hipSuccess; ++t) {
     a.pass = t;
-    e = ffh::launch_propagate(a, s);
+    e = params->raster ? ffh::launch_propagate_raster(a, s) : ffh::launch_propagate(a, s);
     a.Rn = st.radius(t);
     if (e == hipSuccess && st.rs_after(t)) e = ffh::launch_random_search(a, s);
   }
@@ -625,7 +725,7 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
                                  void *ws, size_t ws_bytes, void *stream) {
   if (!batch_ok(pairs, npairs, params) || !table || !ws || !(params->eps >= 0.0f)) return FF_ERR_ARG;
   if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
-  if (params->radius != 3 || params->subpixel) return FF_ERR_UNSUPPORTED;
+  if (params->radius != 3 || params->subpixel || params->nn_l > 1 || params->raster) return FF_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const int L = params->levels, nc = 1 << (L - 1);
   ffh::BatchStage st{};
@@ -747,7 +847,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const int L = params->levels, r = params->radius;
-  if (params->subpixel) return FF_ERR_UNSUPPORTED;
+  if (params->subpixel || params->nn_l > 1 || params->raster) return FF_ERR_UNSUPPORTED;
   for (int lv = 0; lv < L; ++lv)
     if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
   const LayoutF32 lay = layout_f32(W, H, params);
@@ -1074,8 +1174,49 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   for (int dr = 0; dr < nd; ++dr)
     nn.dir[dr] = {desc1[dr], desc1[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  if (params->nn_l > 1) {
+    // seed rerank among the nn_l nearest pixels (Eq. 1, Eq. 4)
+    ffh::TopLArgs tl{};
+    tl.ndir = nd;
+    tl.l = params->nn_l;
+    tl.W = W;
+    tl.H = H;
+    tl.nc = nc;
+    tl.Wc = nn.Wc;
+    tl.M = nn.M;
+    tl.N = nn.N;
+    const uint64_t *cand[2];
+    for (int dr = 0; dr < nd; ++dr) {
+      ffh::TopLDir &d = tl.dir[dr];
+      d.Dq = desc1[dr];
+      d.Dr = desc1[dr ^ 1];
+      d.nb = nb + (size_t)dr * lay.Npad;
+      d.nn_key = keys + (size_t)dr * lay.M;
+      ffh::topl_carve(base + lay.topl + (size_t)dr * ffh::topl_scratch_bytes((int)lay.M), (int)lay.M, d);
+      d.cand = reinterpret_cast<uint64_t *>(base + lay.cand) + (size_t)dr * lay.M * params->nn_l;
+      cand[dr] = d.cand;
+    }
+    if ((e = ffh::launch_topl(tl, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    ffh::LevelArgs ra{};
+    ra.ndir = nd;
+    ra.fcost = sb ? 2 : 0;
+    ra.W = W;
+    ra.H = H;
+    ra.n = nc;
+    ra.Wn = ceil_div(W, nc);
+    ra.Hn = ceil_div(H, nc);
+    ra.radius = r;
+    for (int dr = 0; dr < nd; ++dr) {
+      ra.dir[dr].Da = desc[dr][L - 1];
+      ra.dir[dr].Db = desc[dr ^ 1][L - 1];
+      ra.dir[dr].Dq1 = desc1[dr];
+      ra.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+      ra.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
+    }
+    if ((e = ffh::launch_rerank(ra, cand, params->nn_l, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  }
 
-  if (r == 3 && sb == 0) {
+  if (r == 3 && sb == 0 && !params->raster) {
     // temporally blocked level kernels: one launch per run of passes
     int32_t *sflow[kMaxLevels][2];
     uint32_t *scost[kMaxLevels][2];

@@ -150,6 +150,25 @@ struct CostU8 {
     patch_cost2<R>(static_cast<const uint4 *>(Da), static_cast<const uint4 *>(Db), W, H, n, x, y, f1x, f1y, en1, f2x,
                    f2y, en2, c1, c2);
   }
+  // The terms of patch positions k = g, g + G, ... (k = (v + R)(2R + 1) +
+  // u + R): integers, so the G parts of one evaluation add up to eval's
+  // value in any order.
+  template <int R>
+  __device__ static uint32_t eval_part(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
+                                       int fy, int g, int G) {
+    const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
+    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    constexpr int D = 2 * R + 1;
+    uint32_t s = 0;
+    for (int k = g; k < D * D; k += G) {
+      const int v = k / D - R, u = k % D - R;
+      const uint4 a = Da[(size_t)(clampi(y + n * v, Hm) + P) * Wp + desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
+      const uint4 b =
+          Db[(size_t)(clampi(y + fy + n * v, Hm) + P) * Wp + desc_col(clampi(x + fx + n * u, Wm) + P, l2, Wp)];
+      s = sad16(a, b, s);
+    }
+    return s;
+  }
 };
 
 struct CostF32 {
@@ -253,6 +272,32 @@ struct CostU8Sub {
     c1 = en1 ? eval<R>(Da, Db, W, H, n, x, y, f1x, f1y) : 0u;
     c2 = en2 ? eval<R>(Da, Db, W, H, n, x, y, f2x, f2y) : 0u;
   }
+  // The terms of patch positions k = g, g + G, ... (see CostU8::eval_part).
+  template <int R>
+  __device__ static uint32_t eval_part(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
+                                       int fy, int g, int G) {
+    const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
+    const int tx = x * 8 + fx, ty = y * 8 + fy;
+    const int tx0 = tx >> 3, ty0 = ty >> 3, ax = tx & 7, ay = ty & 7;
+    const int tx1 = tx0 + (ax != 0), ty1 = ty0 + (ay != 0);
+    const uint32_t w00 = (8 - ax) * (8 - ay), w10 = ax * (8 - ay), w01 = (8 - ax) * ay, w11 = ax * ay;
+    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    constexpr int D = 2 * R + 1;
+    uint32_t sum = 0;
+    for (int k = g; k < D * D; k += G) {
+      const int v = k / D - R, u = k % D - R;
+      const uint4 a = Da[(size_t)(clampi(y + n * v, Hm) + P) * Wp + desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
+      const uint4 *r0 = Db + (size_t)(clampi(ty0 + n * v, Hm) + P) * Wp;
+      const uint4 *r1 = Db + (size_t)(clampi(ty1 + n * v, Hm) + P) * Wp;
+      const int c0 = desc_col(clampi(tx0 + n * u, Wm) + P, l2, Wp), c1 = desc_col(clampi(tx1 + n * u, Wm) + P, l2, Wp);
+      const uint4 b00 = r0[c0], b10 = r0[c1], b01 = r1[c0], b11 = r1[c1];
+      sum = sad_bilinear4(a.x, b00.x, b10.x, b01.x, b11.x, w00, w10, w01, w11, sum);
+      sum = sad_bilinear4(a.y, b00.y, b10.y, b01.y, b11.y, w00, w10, w01, w11, sum);
+      sum = sad_bilinear4(a.z, b00.z, b10.z, b01.z, b11.z, w00, w10, w01, w11, sum);
+      sum = sad_bilinear4(a.w, b00.w, b10.w, b01.w, b11.w, w00, w10, w01, w11, sum);
+    }
+    return sum;
+  }
 };
 
 // Target p + f / 2^SB of a flow (in units of 1/2^SB pixel) inside the image.
@@ -335,6 +380,28 @@ __device__ __forceinline__ void wave_count_add2(unsigned long long *counter2, in
   if ((threadIdx.x & 63) == 0 && total) {
     atomicAdd(counter2, (unsigned long long)total);
     atomicAdd(counter2 + 1, (unsigned long long)total);
+  }
+}
+
+// Adds a per-lane count of any size of the whole wave to a global counter
+// (nullable) with one atomic per wave.
+__device__ __forceinline__ void wave_sum_add(unsigned long long *counter, int cnt) {
+  if (counter == nullptr) return;
+  int v = cnt;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(counter, (unsigned long long)v);
+}
+
+// The same for both entries of a [2] counter pair (nullable).
+__device__ __forceinline__ void wave_sum_add2(unsigned long long *counter2, int cnt) {
+  if (counter2 == nullptr) return;
+  int v = cnt;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0 && v) {
+    atomicAdd(counter2, (unsigned long long)v);
+    atomicAdd(counter2 + 1, (unsigned long long)v);
   }
 }
 

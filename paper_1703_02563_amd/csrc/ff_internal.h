@@ -46,6 +46,33 @@ struct NNArgs {
 };
 hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
 
+// The l nearest references of every query (2 <= l <= kTopLMax), after
+// launch_nn: a bound from the exact NN's neighbourhood, a matrix-core pass
+// that collects every reference within the bound, a selection, and a full
+// scan for a query whose collection overflowed (see ff_nn.hip).
+constexpr int kTopLMax = 8;
+constexpr int kTopLCap = 64;  // collected references per query before the full scan
+struct TopLDir {
+  const uint8_t *Dq;       // level-1 row-major descriptors of the query image
+  const uint8_t *Dr;       // the same of the reference image
+  const int32_t *nb;       // reference norms of launch_nn
+  const uint64_t *nn_key;  // launch_nn's keys (NN of each query)
+  uint64_t *tau;           // [M] scratch: bound key
+  int32_t *thr;            // [M] scratch: score threshold of the bound
+  uint32_t *cnt;           // [M] scratch: references collected
+  uint64_t *buf;           // [M][kTopLCap] scratch
+  uint64_t *cand;          // [M][l] output: (squared distance << 32) | q, ranked; ~0 past N
+};
+struct TopLArgs {
+  TopLDir dir[kMaxDirs];
+  int ndir, l;
+  int W, H, nc, Wc, M, N;
+  int chunk_tiles;  // set by launch_topl
+};
+size_t topl_scratch_bytes(int M);  // tau, thr, cnt and buf of one direction (256-byte aligned parts)
+void topl_carve(void *scratch, int M, TopLDir &d);
+hipError_t launch_topl(const TopLArgs &args, hipStream_t stream);
+
 // Launch tables of the temporally blocked level kernels, per scale log2 n
 // (the C ABI's ff_tuning): kernel variant and most propagation steps per
 // launch (0: as many as the window's halo allows), for the byte descriptors
@@ -87,6 +114,15 @@ hipError_t launch_init_coarse(const LevelArgs &a, hipStream_t stream);
 hipError_t launch_seed_level(const LevelArgs &a, hipStream_t stream);
 hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream);  // both half-sweeps
 hipError_t launch_random_search(const LevelArgs &a, hipStream_t stream);
+// Seed rerank (Eq. 1, Eq. 4) at the coarsest scale: per cell the candidate
+// of cand[dir] ([cells][l], launch_topl's output) with the lowest E_nc, the
+// earlier rank on equal cost, written to nn_key in launch_nn's format for
+// the initialisation; counts every candidate but the winner (the
+// initialisation evaluates the winner again).
+hipError_t launch_rerank(const LevelArgs &a, const uint64_t *const *cand, int l, hipStream_t stream);
+// One propagation step in serial order (anti-diagonal wavefronts over tiles;
+// integer costs only).
+hipError_t launch_propagate_raster(const LevelArgs &a, hipStream_t stream);
 
 // Temporally blocked run of propagation / random-search steps of one scale
 // (patch radius 3).  Passes [t_begin, t_end) of T; a random-search step

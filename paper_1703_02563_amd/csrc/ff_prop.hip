@@ -200,6 +200,165 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
   ffk::wave_count_add2(d.n_work, cnt);
 }
 
+
+// Seed rerank (Eq. 1, Eq. 4): of the l ranked candidates of cell m, the one
+// with the lowest E_nc, the earlier rank on equal cost; written to nn_key in
+// launch_nn's relative form for the initialisation.  Counts the candidates
+// but the winner (the initialisation evaluates the winner again).
+struct CandPtrs {
+  const uint64_t *cand[ffh::kMaxDirs];
+};
+
+template <int R, class Cost>
+__global__ __launch_bounds__(256) void k_rerank(ffh::LevelArgs a, CandPtrs c, int l) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = 0;
+  if (m < a.Wn * a.Hn) {
+    const int i = m % a.Wn, j = m / a.Wn;
+    const int x = i * a.n, y = j * a.n;
+    const uint4 qa = reinterpret_cast<const uint4 *>(d.Dq1)[(size_t)y * a.W + x];
+    const uint32_t w[4] = {qa.x, qa.y, qa.z, qa.w};
+    int na = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int e = (int)((w[k] >> (8 * b)) & 0xFF) - 128;
+        na += e * e;
+      }
+    const uint64_t *cm = c.cand[blockIdx.z] + (size_t)m * l;
+    uint64_t bk = ~0ull;
+    uint32_t bc = 0;
+    for (int k = 0; k < l; ++k) {
+      const uint64_t key = cm[k];
+      if (key == ~0ull) continue;
+      const uint32_t q = (uint32_t)key;
+      const int fx = ((int)(q % (uint32_t)a.W) - x) * (1 << Cost::kSub);
+      const int fy = ((int)(q / (uint32_t)a.W) - y) * (1 << Cost::kSub);
+      const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.n, x, y, fx, fy);
+      ++cnt;
+      if (bk == ~0ull || e < bc) {
+        bc = e;
+        bk = key;
+      }
+    }
+    if (bk != ~0ull)
+      const_cast<uint64_t *>(d.nn_key)[m] =
+          ((uint64_t)(uint32_t)((int)(bk >> 32) - na + (1 << 20)) << 32) | (uint32_t)bk;
+  }
+  ffk::wave_sum_add(d.n_evals, cnt > 0 ? cnt - 1 : 0);
+  ffk::wave_sum_add2(d.n_work, cnt);
+}
+
+// One propagation step in the serial order of its direction (Sec. 3.1: a
+// cell after its horizontal and vertical source cells).  A cell depends only
+// on its two sources, so the cells of one anti-diagonal of the scan can be
+// updated together once the previous anti-diagonal is final: the grid is cut
+// into kRasterTile^2 tiles, one launch handles the tiles of one tile
+// anti-diagonal, and inside a tile a workgroup sweeps the cell
+// anti-diagonals through LDS.  The tile's row and column before it (in scan
+// order) come from tiles of earlier launches.  Per cell 16 lanes: 8 sum the
+// horizontal candidate's patch terms and 8 the vertical one's; the leader
+// lane applies the update of k_prop_half in serial order.
+constexpr int kRasterTile = 32;
+constexpr int kRasterLanes = 8;
+
+template <int R, class Cost>
+__global__ __launch_bounds__(512) void k_prop_raster(ffh::LevelArgs a, int diag, int nty) {
+  constexpr int S = kRasterTile, G = kRasterLanes, S1 = S + 1;
+  __shared__ int32_t sf[S1 * S1];
+  __shared__ uint32_t sc[S1 * S1];
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n;
+  const int dir = a.pass & 3;
+  const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
+  const int vdj = (dir == 0 || dir == 2) ? -1 : 1;
+  // tile (ta, tb) in scan coordinates; scan cell (sa, sb) is grid cell
+  // (sa, sb) mirrored along the axes whose source lies on the high side
+  const int ta = max(0, diag - (nty - 1)) + (int)blockIdx.x, tb = diag - ta;
+  const int a0 = ta * S, b0 = tb * S;
+  const int tw = min(S, Wn - a0), th = min(S, Hn - b0);
+  auto grid_index = [&](int sa, int sb) {
+    const int i = hdi < 0 ? sa : Wn - 1 - sa, j = vdj < 0 ? sb : Hn - 1 - sb;
+    return j * Wn + i;
+  };
+  for (int e = threadIdx.x; e < (th + 1) * (tw + 1); e += blockDim.x) {
+    const int lb = e / (tw + 1) - 1, la = e % (tw + 1) - 1;  // -1: the row / column before the tile
+    const int sa = a0 + la, sb = b0 + lb;
+    int32_t f = 0;
+    uint32_t c = kUnset;  // outside the grid: no source
+    if (sa >= 0 && sb >= 0) {
+      const int k = grid_index(sa, sb);
+      f = d.flow[k];
+      c = d.cost[k];
+    }
+    sf[(lb + 1) * S1 + la + 1] = f;
+    sc[(lb + 1) * S1 + la + 1] = c;
+  }
+  __syncthreads();
+  const int slot = threadIdx.x / (2 * G), cand = (threadIdx.x / G) & 1, g = threadIdx.x % G;
+  int cnt = 0, work = 0;
+  for (int dd = 0; dd <= tw + th - 2; ++dd) {
+    const int amin = max(0, dd - (th - 1)), amax = min(dd, tw - 1);
+    const int la = amin + slot, lb = dd - la;
+    if (la <= amax) {  // uniform over the cell's 16 lanes
+      const int o = (lb + 1) * S1 + la + 1;
+      const int32_t f0 = sf[o], fh = sf[o - 1], fv = sf[o - S1];
+      const uint32_t c0 = sc[o], ch = sc[o - 1], cv = sc[o - S1];
+      const int sa = a0 + la, sb = b0 + lb;
+      const int x = (hdi < 0 ? sa : Wn - 1 - sa) * n, y = (vdj < 0 ? sb : Hn - 1 - sb) * n;
+      const bool set0 = c0 != kUnset;
+      const bool hv = ch != kUnset && !(set0 && fh == f0) &&
+                      ffk::target_in<Cost::kSub>(W, H, x, y, ffk::flow_x(fh), ffk::flow_y(fh));
+      const bool vb = cv != kUnset && ffk::target_in<Cost::kSub>(W, H, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
+      // E(p, fv) is computed unless it is E(p, fh); whether it is used
+      // depends on the horizontal outcome (the held-flow rule)
+      const bool vcomp = vb && !(hv && fv == fh);
+      const int32_t fc = cand == 0 ? fh : fv;
+      uint32_t part = 0;
+      if (cand == 0 ? hv : vcomp)
+        part = Cost::template eval_part<R>(d.Da, d.Db, W, H, n, x, y, ffk::flow_x(fc), ffk::flow_y(fc), g, G);
+      part += __shfl_xor(part, 1);
+      part += __shfl_xor(part, 2);
+      part += __shfl_xor(part, 4);
+      const uint32_t other = __shfl_xor(part, G);
+      if (cand == 0 && g == 0) {
+        const uint32_t eh = part, ev = other;
+        uint32_t bc = c0;
+        int32_t bf = f0;
+        if (hv) {
+          ++cnt;
+          if (eh < bc) {
+            bc = eh;
+            bf = fh;
+          }
+        }
+        if (vb && (bc == kUnset || fv != bf)) {
+          ++cnt;
+          const uint32_t e = (hv && fv == fh) ? eh : ev;
+          if (e < bc) {
+            bc = e;
+            bf = fv;
+          }
+        }
+        work += (int)hv + (int)vcomp;
+        sf[o] = bf;
+        sc[o] = bc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < th * tw; e += blockDim.x) {
+    const int lb = e / tw, la = e % tw;
+    const int k = grid_index(a0 + la, b0 + lb);
+    d.flow[k] = sf[(lb + 1) * S1 + la + 1];
+    d.cost[k] = sc[(lb + 1) * S1 + la + 1];
+  }
+  ffk::wave_sum_add(d.n_evals, cnt);
+  ffk::wave_sum_add2(d.n_work, work);
+}
+
 // blockIdx.z = 1 runs the check with the roles of the two fields swapped
 // (the mask of field b), in the same launch.
 // Flows in units of 1/2^sb pixel: q is the pixel nearest to the target
@@ -370,6 +529,36 @@ hipError_t launch_propagate(const LevelArgs &a, hipStream_t stream) {
   for (int colour = 1; colour >= 0; --colour) {
 #define CALL(R, C) hipLaunchKernelGGL((k_prop_half<R, C>), grid, dim3(256), 0, stream, a, colour)
     FF_RADIUS_SWITCH(a, CALL)
+#undef CALL
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rerank(const LevelArgs &a, const uint64_t *const *cand, int l, hipStream_t stream) {
+  if (l < 1 || l > kTopLMax) return hipErrorInvalidValue;
+  CandPtrs c{};
+  for (int dr = 0; dr < a.ndir; ++dr) c.cand[dr] = cand[dr];
+  const int cells = a.Wn * a.Hn;
+  dim3 grid((cells + 255) / 256, 1, a.ndir);
+#define CALL(R, C) hipLaunchKernelGGL((k_rerank<R, C>), grid, dim3(256), 0, stream, a, c, l)
+  FF_RADIUS_SWITCH(a, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate_raster(const LevelArgs &a, hipStream_t stream) {
+  const int ntx = (a.Wn + kRasterTile - 1) / kRasterTile, nty = (a.Hn + kRasterTile - 1) / kRasterTile;
+  for (int diag = 0; diag < ntx + nty - 1; ++diag) {
+    const int lo = std::max(0, diag - (nty - 1)), hi = std::min(diag, ntx - 1);
+    dim3 grid(hi - lo + 1, 1, a.ndir);
+#define CALL(R, C) hipLaunchKernelGGL((k_prop_raster<R, C>), grid, dim3(2 * kRasterTile * kRasterLanes), 0, stream, a, diag, nty)
+    if (a.fcost == 2) {
+      FF_RADIUS_SWITCH_C(a.radius, CALL, ffk::CostU8Sub)
+    } else if (a.fcost == 0) {
+      FF_RADIUS_SWITCH_C(a.radius, CALL, ffk::CostU8)
+    } else {
+      return hipErrorInvalidValue;  // integer costs only
+    }
 #undef CALL
   }
   return hipGetLastError();

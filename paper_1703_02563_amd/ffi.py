@@ -47,6 +47,8 @@ class FFParams(C.Structure):
         ("fine_iters", C.c_int32),
         ("subpixel", C.c_int32),
         ("tuning", C.POINTER(FFTuning)),
+        ("nn_l", C.c_int32),
+        ("raster", C.c_int32),
     ]
 
 
@@ -62,6 +64,11 @@ _SIGS = {
     "ff_descriptor_map_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_wform_map_bytes": (C.c_size_t, [_I32, _I32, _I32]),
     "ff_init_nn": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
+    "ff_nn_topl_scratch_bytes": (C.c_size_t, [_I32, _I32, _I32]),
+    "ff_nn_topl": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _P, C.c_size_t, _P, _P]),
+    "ff_init_nn_l": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, C.c_size_t, _P, _P, _P, _P,
+                               _P]),
+    "ff_propagate_raster": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_seed_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_propagate_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_random_search": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, C.c_uint64, _I32, _I32, _I32, _P, _P,

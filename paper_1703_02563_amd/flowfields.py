@@ -64,10 +64,13 @@ class Params:
     fine_iters: int = 0  # Flow Fields+ Fast: steps at R on the finest scale (0: as the other scales)
     subpixel: int = 0  # 3: flows, random-search offsets and the threshold in 1/8 px, bilinear targets
     tuning: Tuning | None = None  # launch tables of the calls (None: the built-in tables)
+    nn_l: int = 1  # seed candidates: the nn_l nearest pixels, reranked by patch cost (Eq. 1 / Eq. 4)
+    raster: bool = False  # propagation steps in serial order (anti-diagonal wavefronts)
 
     def to_c(self) -> FFParams:
         p = FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
-                     self.plus_iters, self.Rp_num, self.fine_iters, self.subpixel, None)
+                     self.plus_iters, self.Rp_num, self.fine_iters, self.subpixel, None, self.nn_l,
+                     int(bool(self.raster)))
         if self.tuning is not None:
             p._tuning = self.tuning.to_c()  # kept alive with the struct that points at it
             p.tuning = ctypes.pointer(p._tuning)
@@ -152,6 +155,46 @@ def init_nn(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, radius: int = 3, n_eval
     return flow, cost, key
 
 
+def nn_topl(desc_a1, desc_b1, nc: int, l: int):
+    """The l nearest pixels of every coarsest-grid cell (ff_nn_topl): int64
+    [Hc, Wc, l] entries (squared distance << 32) | q, ranked; -1 past the
+    image's pixel count."""
+    H, W = desc_a1.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    dev = desc_a1.device
+    if tuple(desc_b1.shape) != (H, W, 16):
+        raise ValueError("nn_topl: level-1 descriptors [H, W, 16] of two images of one size")
+    nb = torch.empty(((W * H + 31) // 32) * 32, dtype=torch.int32, device=dev)
+    nbytes = int(lib().ff_nn_topl_scratch_bytes(W, H, nc))
+    scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    cand = torch.empty((Hc, Wc, l), dtype=torch.int64, device=dev)
+    check(lib().ff_nn_topl(_ptr(desc_a1, torch.uint8), _ptr(desc_b1, torch.uint8), W, H, nc, l, _ptr(nb),
+                           _ptr(scratch), nbytes, _ptr(cand), _stream()), "ff_nn_topl")
+    return cand
+
+
+def init_nn_l(desc_a1, desc_b1, desc_ac, desc_bc, nc: int, nn_l: int, radius: int = 3,
+              n_evals: torch.Tensor | None = None):
+    """Seed of the coarsest grid from the nn_l nearest pixels (ff_init_nn_l);
+    returns (flow, cost, nn_key)."""
+    H, W = desc_a1.shape[:2]
+    Wc, Hc = cells(W, H, nc)
+    dev = desc_a1.device
+    if _map_dims(desc_ac, desc_bc, nc) != (W, H) or tuple(desc_b1.shape) != (H, W, 16):
+        raise ValueError("init_nn_l: level-1 descriptors [H, W, 16] and scale-nc maps of the same image size")
+    nb = torch.empty(((W * H + 31) // 32) * 32, dtype=torch.int32, device=dev)
+    nbytes = int(lib().ff_nn_topl_scratch_bytes(W, H, nc))
+    scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    key = torch.empty((Hc, Wc), dtype=torch.int64, device=dev)
+    flow = torch.empty((Hc, Wc, 2), dtype=torch.int16, device=dev)
+    cost = torch.empty((Hc, Wc), dtype=torch.int32, device=dev)
+    check(lib().ff_init_nn_l(_ptr(desc_a1, torch.uint8), _ptr(desc_b1, torch.uint8), _ptr(desc_ac, torch.uint8),
+                             _ptr(desc_bc, torch.uint8), W, H, nc, radius, nn_l, _ptr(nb), _ptr(scratch), nbytes,
+                             _ptr(key), _ptr(flow), _ptr(cost), _ptr(n_evals, torch.int64), _stream()),
+          "ff_init_nn_l")
+    return flow, cost, key
+
+
 def seed_level(cflow, ccost, desc_a, desc_b, n: int, radius: int = 3, n_evals=None):
     W, H = _map_dims(desc_a, desc_b, n)
     Wn, Hn = cells(W, H, n)
@@ -169,6 +212,14 @@ def propagate_level(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int 
     check(lib().ff_propagate_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, pass_,
                                    _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
                                    _stream()), "ff_propagate_level")
+
+
+def propagate_raster(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int = 3, n_evals=None):
+    """One propagation step in serial order, in place on (flow, cost)."""
+    W, H = _map_dims(desc_a, desc_b, n)
+    check(lib().ff_propagate_raster(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, pass_,
+                                    _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
+                                    _stream()), "ff_propagate_raster")
 
 
 def random_search(desc_a, desc_b, n: int, Rn: int, seed: int, stream_id: int, level: int, pass_: int, flow, cost,

@@ -1,0 +1,200 @@
+"""Seed rerank among the l nearest pixels (Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 4)
+and serial-order propagation (Sec. 3.1, Eq. 2) on the GPU, bit for bit
+against the oracle: the ranked candidate lists (including images whose ties
+overflow the collection and take the full-scan path, and images with fewer
+pixels than candidates), the reranked seeds with their evaluation counts,
+single serial steps in all four directions on grids of several tiles with
+ragged edges, and whole fields with either option or both, in the integer
+and the subpixel form; at 1024x436 the candidate lists of every cell and
+the whole fields of both options."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1703_02563_amd as ff
+from ffgen import CONFIG_PARAMS, make_pair, random_images
+from test_gpu_parity import _random_level_state, as_u32, counter, dev, host, to_lib
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+BIG = np.iinfo(np.int64).max
+
+
+def _expected_cand(idx, dist):
+    """The library's entries (distance << 32) | q, -1 for missing ranks."""
+    e = (dist.astype(np.uint64) << np.uint64(32)) | idx.astype(np.uint32).astype(np.uint64)
+    e[idx < 0] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    return e.view(np.int64)
+
+
+def _images(kind, seed, H, W):
+    rng = np.random.default_rng(seed)
+    if kind == "levels":  # two grey levels: large groups of equal descriptors
+        a = (rng.integers(0, 2, size=(H, W)) * 200).astype(np.uint8)
+        b = (rng.integers(0, 2, size=(H, W)) * 200).astype(np.uint8)
+        return a, b
+    if kind == "flat":
+        return np.full((H, W), 90, np.uint8), np.full((H, W), 90, np.uint8)
+    return random_images(seed, H, W, kind=kind)
+
+
+def _overflowed(scratch, M):
+    """Cells whose collection exceeded the list capacity (the full-scan
+    path): the counters sit after the NN keys, the bounds and the
+    thresholds, each part 256-byte aligned."""
+    al = lambda b: (b + 255) // 256 * 256
+    off = al(M * 8) + al(M * 8) + al(M * 4)
+    cnt = host(scratch[off:off + 4 * M]).view(np.uint32)
+    return int(np.count_nonzero(cnt > 64))
+
+
+@pytest.mark.parametrize("kind,shape,nc,l", [("box", (37, 29), 4, 8), ("uniform", (40, 64), 4, 8),
+                                             ("levels", (33, 47), 2, 8), ("flat", (20, 30), 2, 8),
+                                             ("box", (130, 257), 8, 5), ("box", (2, 3), 1, 8),
+                                             ("uniform", (1, 1), 1, 2), ("box", (7, 200), 16, 8)])
+def test_topl_candidates_bit_exact(kind, shape, nc, l):
+    H, W = shape
+    ia, ib = _images(kind, 900 + H + nc, H, W)
+    Da, Db = oracle.descriptor(oracle.blur(ia, 1), 1), oracle.descriptor(oracle.blur(ib, 1), 1)
+    idx, dist = oracle.nn_topl(Da, Db, nc, l, nthreads=NT)
+    cand = ff.nn_topl(dev(Da), dev(Db), nc, l)
+    assert np.array_equal(host(cand), _expected_cand(idx, dist))
+
+
+def test_topl_overflow_takes_the_full_scan():
+    """Uncorrelated noise: the neighbourhood of the exact NN gives a loose
+    bound, far more than the list capacity of pixels pass it, and the
+    full scan must still return the exact ranking."""
+    H, W, nc, l = 48, 64, 4, 8
+    ia, ib = random_images(17, H, W, kind="uniform")
+    Da, Db = oracle.descriptor(oracle.blur(ia, 1), 1), oracle.descriptor(oracle.blur(ib, 1), 1)
+    M = -(-W // nc) * -(-H // nc)
+    nbytes = int(ff.lib().ff_nn_topl_scratch_bytes(W, H, nc))
+    scratch = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    nb = torch.empty(((W * H + 31) // 32) * 32, dtype=torch.int32, device="cuda")
+    cand = torch.empty((-(-H // nc), -(-W // nc), l), dtype=torch.int64, device="cuda")
+    from paper_1703_02563_amd.flowfields import _ptr, _stream, check
+    gA, gB = dev(Da), dev(Db)  # kept alive over the call
+    check(ff.lib().ff_nn_topl(_ptr(gA), _ptr(gB), W, H, nc, l, _ptr(nb), _ptr(scratch), nbytes, _ptr(cand),
+                              _stream()), "ff_nn_topl")
+    idx, dist = oracle.nn_topl(Da, Db, nc, l, nthreads=NT)
+    assert np.array_equal(host(cand), _expected_cand(idx, dist))
+    assert _overflowed(scratch, M) > 0
+
+
+@pytest.mark.parametrize("shape,nc,l", [((40, 60), 4, 8), ((61, 95), 8, 3), ((3, 5), 2, 8), ((130, 257), 4, 8)])
+def test_init_nn_l_bit_exact(shape, nc, l):
+    H, W = shape
+    ia, ib = random_images(77 * nc + H, H, W)
+    L = nc.bit_length()
+    Da, Db = oracle.descriptors_all(ia, L), oracle.descriptors_all(ib, L)
+    cand, _ = oracle.nn_topl(Da[0], Db[0], nc, l, nthreads=NT)
+    eflow, ecost, ene = oracle.init_coarse_l(cand, Da[L - 1], Db[L - 1], nc)
+    cnt = counter()
+    flow, cost, key = ff.init_nn_l(dev(Da[0]), dev(Db[0]), dev(to_lib(Da[L - 1], nc)), dev(to_lib(Db[L - 1], nc)),
+                                   nc, l, n_evals=cnt)
+    assert np.array_equal(host(flow), eflow)
+    assert np.array_equal(as_u32(cost), ecost)
+    assert int(host(cnt)[0]) == ene
+    # the key names the winner, with its squared distance
+    k = host(key).view(np.uint64)
+    q = (k & 0xFFFFFFFF).astype(np.int64)
+    ys, xs = np.mgrid[0:eflow.shape[0], 0:eflow.shape[1]] * nc
+    assert np.array_equal(q % W - xs, eflow[..., 0]) and np.array_equal(q // W - ys, eflow[..., 1])
+    d = ((Da[0][ys, xs].astype(np.int64) - Db[0].reshape(-1, 16)[q].astype(np.int64)) ** 2).sum(-1)
+    assert np.array_equal((k >> 32).astype(np.int64), d)
+
+
+@pytest.mark.parametrize("shape,n", [((45, 70), 1), ((100, 70), 1), ((61, 83), 2), ((64, 96), 4), ((1, 31), 1),
+                                     ((29, 1), 1), ((33, 33), 1), ((200, 150), 1)])
+@pytest.mark.parametrize("pass_", [0, 1, 2, 3])
+def test_propagate_raster_bit_exact(shape, n, pass_):
+    H, W = shape
+    ia, ib = random_images(1400 + n + pass_ + H, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    flow, cost = _random_level_state(pass_ + 3, H, W, n)
+    ef, ec, ene = oracle.propagate_raster(Da, Db, n, pass_, flow, cost)
+    gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
+    ff.propagate_raster(dev(to_lib(Da, n)), dev(to_lib(Db, n)), n, pass_, gf, gc, n_evals=cnt)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ene
+
+
+@pytest.mark.parametrize("radius", [1, 2, 4])
+def test_propagate_raster_other_radii(radius):
+    H, W, n = 70, 90, 1
+    ia, ib = random_images(1500 + radius, H, W)
+    Da = oracle.descriptor(oracle.blur(ia, n), n)
+    Db = oracle.descriptor(oracle.blur(ib, n), n)
+    flow, cost = _random_level_state(radius, H, W, n)
+    ef, ec, ene = oracle.propagate_raster(Da, Db, n, 0, flow, cost, r=radius)
+    gf, gc, cnt = dev(flow), dev(cost.view(np.int32)), counter()
+    ff.propagate_raster(dev(to_lib(Da, n)), dev(to_lib(Db, n)), n, 0, gf, gc, radius=radius, n_evals=cnt)
+    assert np.array_equal(host(gf), ef)
+    assert np.array_equal(as_u32(gc), ec)
+    assert int(host(cnt)[0]) == ene
+
+
+def _compare(g, o):
+    for k in ("flow_fwd", "flow_bwd", "keep_fwd", "keep_bwd"):
+        assert np.array_equal(host(g[k]), o[k]), k
+    for k in ("cost_fwd", "cost_bwd"):
+        assert np.array_equal(as_u32(g[k]), o[k]), k
+    assert tuple(int(v) for v in host(g["n_evals"])) == o["n_evals"]
+
+
+@pytest.mark.parametrize("nn_l,raster,sub", [(8, False, 0), (1, True, 0), (8, True, 0), (4, False, 3),
+                                             (1, True, 3)])
+@pytest.mark.parametrize("shape,L,T", [((96, 128), 3, 4), ((61, 95), 3, 3), ((33, 1), 2, 3), ((1, 1), 1, 1)])
+def test_fields_with_options_bit_exact(nn_l, raster, sub, shape, L, T):
+    H, W = shape
+    ia, ib = random_images(1600 + H + W, H, W)
+    prm = ff.Params(levels=L, iters=T, nn_l=nn_l, raster=raster, subpixel=sub)
+    o = oracle.flow_fields(ia, ib, L, T, nthreads=NT, nn_l=nn_l, raster=raster, subpixel=sub)
+    _compare(ff.flow_fields(dev(ia), dev(ib), prm), o)
+
+
+def test_options_config1_bit_exact():
+    p = make_pair(1)
+    c = CONFIG_PARAMS[1]
+    for nn_l, raster in ((8, False), (8, True)):
+        prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den, nn_l=nn_l, raster=raster)
+        o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed,
+                               nthreads=NT, nn_l=nn_l, raster=raster)
+        _compare(ff.flow_fields(dev(p.img1), dev(p.img2), prm), o)
+
+
+def test_unsupported_forms_are_rejected():
+    H, W = 40, 50
+    ia, ib = random_images(3, H, W)
+    for field, value in (("nn_l", 9), ("raster", 2), ("nn_l", -1)):
+        cp = ff.Params(levels=2, iters=2).to_c()
+        setattr(cp, field, value)
+        assert int(ff.lib().ff_workspace_bytes(W, H, cp)) == 0
+    with pytest.raises(ff.FlowFieldsError):
+        ff.flow_fields(dev(ia), dev(ib), ff.Params(levels=2, iters=2, nn_l=9))
+
+
+def test_topl_candidates_full_size():
+    """1024x436, nc = 16: every cell's ranked list of 8."""
+    p = make_pair(2)
+    Da, Db = oracle.descriptor(oracle.blur(p.img1, 1), 1), oracle.descriptor(oracle.blur(p.img2, 1), 1)
+    idx, dist = oracle.nn_topl(Da, Db, 16, 8, nthreads=NT)
+    cand = ff.nn_topl(dev(Da), dev(Db), 16, 8)
+    assert np.array_equal(host(cand), _expected_cand(idx, dist))
+
+
+def test_options_full_size_bit_exact():
+    """1024x436 (5 scales, 6 steps) with the rerank of 8 candidates and
+    serial-order propagation: whole fields, masks and counts."""
+    p = make_pair(2)
+    c = CONFIG_PARAMS[2]
+    prm = ff.Params(levels=c.levels, iters=c.iters, R_num=c.R_num, R_den=c.R_den, nn_l=8, raster=True)
+    o = oracle.flow_fields(p.img1, p.img2, c.levels, c.iters, c.radius, c.R_num, c.R_den, c.eps, c.seed,
+                           nthreads=NT, nn_l=8, raster=True)
+    _compare(ff.flow_fields(dev(p.img1), dev(p.img2), prm), o)
