@@ -196,9 +196,9 @@ size_t ff_nn_topl_scratch_bytes(int32_t W, int32_t H, int32_t nc);
  * nearest neighbours): ranked by (squared L2 distance of the level-1
  * descriptors, q.y*W + q.x).  cand: uint64 [cells][l] output, entry
  * (distance << 32) | q, ~0 where the image has fewer than l pixels.
- * Computed exactly: a bound from the exact NN's neighbourhood, a matrix-core
- * pass that collects every pixel within it, a selection, and a full scan for
- * a cell whose collection overflows.  desc_a1, desc_b1: as for ff_init_nn;
+ * Computed exactly as l passes of ff_init_nn's matrix-core search, pass k
+ * leaving out every pixel whose (distance, index) is at most pass k-1's
+ * result.  desc_a1, desc_b1: as for ff_init_nn;
  * nb_scratch: as for ff_init_nn; scratch: device, ff_nn_topl_scratch_bytes
  * (FF_ERR_WORKSPACE if smaller); 1 <= l <= 8. */
 ff_status ff_nn_topl(const uint8_t *desc_a1, const uint8_t *desc_b1, int32_t W, int32_t H, int32_t nc, int32_t l,

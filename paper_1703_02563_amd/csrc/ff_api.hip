@@ -392,7 +392,7 @@ static hipError_t nn_topl_run(const uint8_t *desc_a1, const uint8_t *desc_b1, in
   d.Dr = desc_b1;
   d.nb = nb_scratch;
   d.nn_key = keys;
-  ffh::topl_carve(scratch + align256((size_t)nn.M * sizeof(uint64_t)), nn.M, d);
+  d.keys = reinterpret_cast<uint64_t *>(scratch + align256((size_t)nn.M * sizeof(uint64_t)));
   d.cand = cand;
   return ffh::launch_topl(tl, s);
 }
@@ -1192,7 +1192,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       d.Dr = desc1[dr ^ 1];
       d.nb = nb + (size_t)dr * lay.Npad;
       d.nn_key = keys + (size_t)dr * lay.M;
-      ffh::topl_carve(base + lay.topl + (size_t)dr * ffh::topl_scratch_bytes((int)lay.M), (int)lay.M, d);
+      d.keys = reinterpret_cast<uint64_t *>(base + lay.topl + (size_t)dr * ffh::topl_scratch_bytes((int)lay.M));
       d.cand = reinterpret_cast<uint64_t *>(base + lay.cand) + (size_t)dr * lay.M * params->nn_l;
       cand[dr] = d.cand;
     }

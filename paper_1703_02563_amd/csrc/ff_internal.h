@@ -46,31 +46,27 @@ struct NNArgs {
 };
 hipError_t launch_nn(const NNArgs &args, hipStream_t stream);
 
-// The l nearest references of every query (2 <= l <= kTopLMax), after
-// launch_nn: a bound from the exact NN's neighbourhood, a matrix-core pass
-// that collects every reference within the bound, a selection, and a full
-// scan for a query whose collection overflowed (see ff_nn.hip).
+// The l nearest references of every query (1 <= l <= kTopLMax), after
+// launch_nn: l - 1 more passes of the NN kernel, pass k leaving out the
+// references up to pass k-1's key (see ff_nn.hip).
 constexpr int kTopLMax = 8;
-constexpr int kTopLCap = 64;  // collected references per query before the full scan
 struct TopLDir {
   const uint8_t *Dq;       // level-1 row-major descriptors of the query image
   const uint8_t *Dr;       // the same of the reference image
   const int32_t *nb;       // reference norms of launch_nn
-  const uint64_t *nn_key;  // launch_nn's keys (NN of each query)
-  uint64_t *tau;           // [M] scratch: bound key
-  int32_t *thr;            // [M] scratch: score threshold of the bound
-  uint32_t *cnt;           // [M] scratch: references collected
-  uint64_t *buf;           // [M][kTopLCap] scratch
+  const uint64_t *nn_key;  // launch_nn's keys (pass 0)
+  uint64_t *keys;          // [kTopLMax - 1][M] scratch: keys of passes 1 ..
   uint64_t *cand;          // [M][l] output: (squared distance << 32) | q, ranked; ~0 past N
 };
 struct TopLArgs {
   TopLDir dir[kMaxDirs];
   int ndir, l;
   int W, H, nc, Wc, M, N;
-  int chunk_tiles;  // set by launch_topl
 };
-size_t topl_scratch_bytes(int M);  // tau, thr, cnt and buf of one direction (256-byte aligned parts)
-void topl_carve(void *scratch, int M, TopLDir &d);
+struct TopLPrev {
+  const uint64_t *key[kMaxDirs];
+};
+size_t topl_scratch_bytes(int M);  // the keys of passes 1 .. kTopLMax - 1 of one direction
 hipError_t launch_topl(const TopLArgs &args, hipStream_t stream);
 
 // Launch tables of the temporally blocked level kernels, per scale log2 n

@@ -92,9 +92,13 @@ __device__ __forceinline__ long load_i8x8(const uint8_t *p) {
 }
 
 // Query block `qblk` (32 * kQB queries) against reference chunk `chunk` of
-// one direction.  All threads of the workgroup call it.
+// one direction.  All threads of the workgroup call it.  kExcl: the next
+// nearest reference instead of the nearest -- every reference whose key
+// (distance, index) is at most the query's key in prev (the previous
+// pass's result) is left out; prev[m] = ~0 leaves out all.
+template <bool kExcl = false>
 __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W, int nc, int Wc, int qblk,
-                                        int chunk, int chunk_tiles) {
+                                        int chunk, int chunk_tiles, const uint64_t *prev = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, kh = lane >> 5;
   const int ntiles = (N + 31) >> 5;
@@ -120,6 +124,33 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
   for (int qb = 0; qb < kQB; ++qb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) best[qb][r] = INT_MIN;
+  // Exclusion as a score bound per (query row, lane): a reference of this
+  // lane (column col, chunk tile tl, index (t0 + tl) * 32 + col) has a key
+  // at most (dd*, q*) iff 2048 dd + tl <= K = 2048 dd* + floor((q* - col) /
+  // 32) - t0 (the tile term clamped to [-1, 2047]), i.e. iff its score
+  // -(2048 dd + tl) >= -K; it is kept iff the score is below thr = -K.
+  int thr[kQB][16];
+  if constexpr (kExcl) {
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + qb * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        int t = INT_MAX;  // padding rows: nothing left out (they write nothing)
+        if (m < M) {
+          const uint64_t pk = prev[m];
+          if (pk == ~0ull) {
+            t = INT_MIN;  // nothing left to find
+          } else {
+            const int dd = (int)(uint32_t)(pk >> 32) - (1 << 20);
+            int tl = ((int)(uint32_t)pk - col) >> 5;  // floor: the shift is arithmetic
+            tl = tl - t0 < -1 ? -1 : (tl - t0 > 2047 ? 2047 : tl - t0);
+            t = (int)-(2048ll * dd + tl);  // 2048 dd + tl <= 2^31 - 1
+          }
+        }
+        thr[qb][r] = t;
+      }
+  }
 
   const v16i zero = {0};
   // Operands of the two tiles of step t (the second repeats the first at the
@@ -169,8 +200,12 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
     for (int qb = 0; qb < kQB; ++qb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int sa = acc_a[qb][r] * 4096 + nka;
-        const int sb = acc_b[qb][r] * 4096 + nkb;
+        int sa = acc_a[qb][r] * 4096 + nka;
+        int sb = acc_b[qb][r] * 4096 + nkb;
+        if constexpr (kExcl) {
+          sa = sa < thr[qb][r] ? sa : INT_MIN;
+          sb = sb < thr[qb][r] ? sb : INT_MIN;
+        }
         best[qb][r] = max(best[qb][r], max(sa, sb));
       }
     }
@@ -188,6 +223,9 @@ __device__ __forceinline__ void nn_body(const ffh::NNDir &d, int M, int N, int W
       const int tl = key & 2047;       // tile inside the chunk
       const uint32_t ref = (uint32_t)((t0 + tl) * 32 + col);
       unsigned long long v = ((unsigned long long)(uint32_t)(dd + (1 << 20)) << 32) | ref;
+      if constexpr (kExcl) {
+        if (best[qb][r] == INT_MIN) v = ~0ull;  // every reference of the lane left out
+      }
 #pragma unroll
       for (int off = 16; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(v, off);
@@ -274,20 +312,18 @@ __global__ __launch_bounds__(256) void k_nn_batch(ffh::BatchStage st) {
 
 // ---- the l nearest references (seed rerank, Eq. 1 / Eq. 4) -------------
 //
-// The l smallest keys (distance, index) of a query are found in four steps:
-//  1. k_topl_bound: exact distances to a few references near the query's
-//     exact NN q* (the 5 x 5 pixels around q* and q* + 1 .. q* + 7) give a
-//     bound tau: the l-th smallest key of any l distinct references is at
-//     least the l-th smallest key of all references, so every wanted
-//     reference has a key <= tau.
-//  2. k_topl_collect: k_nn's matrix-core pass, but every score is compared
-//     with the bound's score threshold; the rare references that pass
-//     (distance <= tau's) are checked against tau exactly and appended to
-//     the query's list.
-//  3. k_topl_select: the l smallest keys of each list, ranked.
-//  4. k_topl_full: a query whose list exceeded kTopLCap scans all references.
-// Keys inside the pass have launch_nn's relative form ((dist - |a|^2 + 2^20)
-// << 32) | q; the output carries the squared distance itself.
+// The k-th nearest reference of a query (k = 1 .. l - 1; k = 0 is k_nn's
+// result) is the nearest one among those whose key (distance, index) is
+// larger than the (k-1)-th's: pass k is k_nn with that exclusion, so l
+// passes give the l smallest keys, ranked, with the ties of k_nn.
+
+__global__ __launch_bounds__(256) void k_nn_excl(ffh::NNArgs a, ffh::TopLPrev prev) {
+  const int nqb = nn_qblocks(a.M), nchunk = nn_chunks(a.N, a.chunk_tiles);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  const int dir = wg / (nqb * nchunk);
+  nn_body<true>(a.dir[dir], a.M, a.N, a.W, a.nc, a.Wc, wg % nqb, (wg / nqb) % nchunk, a.chunk_tiles,
+                prev.key[dir]);
+}
 
 __device__ __forceinline__ int query_norm(const uint8_t *Dq, int W, int nc, int Wc, int m) {
   const int i = m % Wc, j = m / Wc;
@@ -304,241 +340,20 @@ __device__ __forceinline__ int query_norm(const uint8_t *Dq, int W, int nc, int 
   return s;
 }
 
-__device__ __forceinline__ int sq_dist16(const uint4 a, const uint4 b) {
-  const uint32_t wa[4] = {a.x, a.y, a.z, a.w}, wb[4] = {b.x, b.y, b.z, b.w};
-  int s = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int e = (int)((wa[k] >> (8 * c)) & 0xFF) - (int)((wb[k] >> (8 * c)) & 0xFF);
-      s += e * e;
-    }
-  return s;
-}
-
-__device__ __forceinline__ uint64_t rel_key(int dist, int na, uint32_t q) {
-  return ((uint64_t)(uint32_t)(dist - na + (1 << 20)) << 32) | q;
-}
-
-__device__ __forceinline__ uint64_t abs_key(uint64_t rel, int na) {
-  if (rel == ~0ull) return rel;
-  return ((uint64_t)(uint32_t)((int)(rel >> 32) - (1 << 20) + na) << 32) | (uint32_t)rel;
-}
-
-// Sorted insertion into an ascending list of kTopLMax keys held in
-// registers (the largest falls off).
-__device__ __forceinline__ void list_insert(uint64_t (&list)[ffh::kTopLMax], uint64_t x) {
-#pragma unroll
-  for (int t = 0; t < ffh::kTopLMax; ++t) {
-    const uint64_t lo = list[t] < x ? list[t] : x;
-    x = list[t] < x ? x : list[t];
-    list[t] = lo;
-  }
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint64_t o = __shfl_xor(v, off);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_topl_bound(ffh::TopLArgs a) {
+// Ranked candidates with the squared distance itself: cand[m * l + k] =
+// (dist << 32) | q of pass k, ~0 for a pass that found no reference of the
+// image (padding references, index >= N, or none left).
+__global__ __launch_bounds__(256) void k_topl_assemble(ffh::TopLArgs a) {
   const ffh::TopLDir d = a.dir[blockIdx.y];
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
   const int na = query_norm(d.Dq, a.W, a.nc, a.Wc, m);
-  const int i = m % a.Wc, j = m / a.Wc;
-  const uint4 qa = reinterpret_cast<const uint4 *>(d.Dq)[(size_t)(j * a.nc) * a.W + (size_t)(i * a.nc)];
-  const uint4 *Dr = reinterpret_cast<const uint4 *>(d.Dr);
-  const uint32_t q0 = (uint32_t)d.nn_key[m];
-  const int qx = (int)(q0 % (uint32_t)a.W), qy = (int)(q0 / (uint32_t)a.W);
-  uint64_t list[ffh::kTopLMax];
-#pragma unroll
-  for (int t = 0; t < ffh::kTopLMax; ++t) list[t] = ~0ull;
-  auto consider = [&](uint32_t q) {
-    const uint64_t key = rel_key(sq_dist16(qa, Dr[q]), na, q);
-    bool dup = false;
-#pragma unroll
-    for (int t = 0; t < ffh::kTopLMax; ++t) dup |= list[t] == key;
-    if (!dup) list_insert(list, key);
-  };
-  for (int dy = -2; dy <= 2; ++dy)
-    for (int dx = -2; dx <= 2; ++dx) {
-      const int x = qx + dx, y = qy + dy;
-      if (x >= 0 && x < a.W && y >= 0 && y < a.H) consider((uint32_t)(y * a.W + x));
-    }
-  for (int k = 1; k < ffh::kTopLMax; ++k)
-    if ((int64_t)q0 + k < (int64_t)a.N) consider(q0 + (uint32_t)k);
-  uint64_t tau = ~0ull;
-#pragma unroll
-  for (int t = 0; t < ffh::kTopLMax; ++t)
-    if (t == a.l - 1) tau = list[t];
-  // score s = -(2048 (dist - |a|^2) + tile) passes iff dist <= tau's distance
-  // is implied by s >= 2048 (|a|^2 - dist_tau) - 2047 (tile < 2048)
-  d.tau[m] = tau;
-  d.thr[m] = tau == ~0ull ? INT_MIN + 1 : 2048 * ((1 << 20) - (int)(tau >> 32)) - 2047;
-  d.cnt[m] = 0;
-}
-
-// k_nn's pass for query block `qblk` and reference chunk `chunk`, collecting
-// the references within each query's bound.
-__device__ __forceinline__ void collect_body(const ffh::TopLDir &d, int M, int N, int W, int nc, int Wc, int qblk,
-                                             int chunk, int chunk_tiles) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 31, kh = lane >> 5;
-  const int ntiles = (N + 31) >> 5;
-  const int m0 = qblk * (32 * kQB);
-  const int t0 = chunk * chunk_tiles;
-  const int t1 = min(t0 + chunk_tiles, ntiles);
-  if (t0 + wave >= t1) return;  // wave-uniform
-
-  long aop[kQB];
-  int thr[kQB][16];
-#pragma unroll
-  for (int qb = 0; qb < kQB; ++qb) {
-    const int m = min(m0 + qb * 32 + col, M - 1);
-    const int i = m % Wc, j = m / Wc;
-    const size_t pix = (size_t)(j * nc) * W + (size_t)(i * nc);
-    aop[qb] = load_i8x8(d.Dq + pix * 16 + kh * 8);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int mr = m0 + qb * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-      thr[qb][r] = mr < M ? d.thr[mr] : INT_MAX;  // padding rows never pass
-    }
-  }
-  const v16i zero = {0};
-  const __amdgpu_buffer_rsrc_t rdesc =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(d.Dr), (short)0, N * 16, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rnorm =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(d.nb), (short)0, ((N + 31) & ~31) * 4, 0x00020000);
-  const int voff_desc = col * 16 + kh * 8, voff_norm = col * 4;
-  constexpr long kFlip = (long)0x8080808080808080ull;
-  struct Step {
-    long ba, bb;
-    int na, nb;
-  };
-  auto fetch = [&](int t, int tb) {
-    Step st;
-    st.ba = (long)__builtin_amdgcn_raw_buffer_load_b64(rdesc, voff_desc, t * 512, 0) ^ (t * 32 + col < N ? kFlip : 0);
-    st.bb = (long)__builtin_amdgcn_raw_buffer_load_b64(rdesc, voff_desc, tb * 512, 0) ^ (tb * 32 + col < N ? kFlip : 0);
-    st.na = (int)__builtin_amdgcn_raw_buffer_load_b32(rnorm, voff_norm, t * 128, 0);
-    st.nb = (int)__builtin_amdgcn_raw_buffer_load_b32(rnorm, voff_norm, tb * 128, 0);
-    return st;
-  };
-  // appends the reference of score s (tile tl of the chunk) if its key is
-  // within the query's bound
-  auto append = [&](int mr, int s) {
-    const int key = -s;
-    const int dd = key >> 11, tl = key & 2047;
-    const uint32_t ref = (uint32_t)((t0 + tl) * 32 + col);
-    if ((int)ref >= N) return;
-    const uint64_t k64 = ((uint64_t)(uint32_t)(dd + (1 << 20)) << 32) | ref;
-    if (k64 > d.tau[mr]) return;
-    const uint32_t pos = atomicAdd(d.cnt + mr, 1u);
-    if (pos < (uint32_t)ffh::kTopLCap) d.buf[(size_t)mr * ffh::kTopLCap + pos] = k64;
-  };
-  const int tw0 = t0 + __builtin_amdgcn_readfirstlane(wave);
-  auto second = [&](int t) { return (t + kWaves < t1) ? t + kWaves : t; };
-  Step cur = fetch(tw0, second(tw0));
-  for (int t = tw0; t < t1; t += 2 * kWaves) {
-    const int tn = t + 2 * kWaves < t1 ? t + 2 * kWaves : t;
-    const Step nxt = fetch(tn, second(tn));
-    const int tb = second(t);
-    const int nka = opaque_neg((cur.na << 11) | (t - t0));
-    const int nkb = opaque_neg((cur.nb << 11) | (tb - t0));
-    v16i acc_a[kQB], acc_b[kQB];
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
-      acc_a[qb] = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], cur.ba, zero, 0, 0, 0);
-      acc_b[qb] = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[qb], cur.bb, zero, 0, 0, 0);
-    }
-    bool hit = false;
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        hit |= max(acc_a[qb][r] * 4096 + nka, acc_b[qb][r] * 4096 + nkb) >= thr[qb][r];
-    if (__any(hit)) {
-#pragma unroll
-      for (int qb = 0; qb < kQB; ++qb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int mr = m0 + qb * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-          const int sa = acc_a[qb][r] * 4096 + nka, sb = acc_b[qb][r] * 4096 + nkb;
-          if (sa >= thr[qb][r]) append(mr, sa);
-          if (tb != t && sb >= thr[qb][r]) append(mr, sb);  // the odd tail repeats tile t
-        }
-    }
-    cur = nxt;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_topl_collect(ffh::TopLArgs a) {
-  const int nqb = nn_qblocks(a.M), nchunk = nn_chunks(a.N, a.chunk_tiles);
-  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  collect_body(a.dir[wg / (nqb * nchunk)], a.M, a.N, a.W, a.nc, a.Wc, wg % nqb, (wg / nqb) % nchunk,
-               a.chunk_tiles);
-}
-
-// One wave per query: the l smallest collected keys, ranked.
-__global__ __launch_bounds__(256) void k_topl_select(ffh::TopLArgs a) {
-  const ffh::TopLDir d = a.dir[blockIdx.y];
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (m >= a.M) return;  // wave-uniform
-  const uint32_t c = d.cnt[m];
-  if (c > (uint32_t)ffh::kTopLCap) return;  // k_topl_full
-  const int na = query_norm(d.Dq, a.W, a.nc, a.Wc, m);
-  uint64_t v = (uint32_t)lane < c ? d.buf[(size_t)m * ffh::kTopLCap + lane] : ~0ull;
   for (int k = 0; k < a.l; ++k) {
-    const uint64_t mn = wave_min_u64(v);
-    if (v == mn) v = ~0ull;  // keys are distinct (one per reference)
-    if (lane == 0) d.cand[(size_t)m * a.l + k] = abs_key(mn, na);
-  }
-}
-
-// One workgroup per query whose collection overflowed: every thread keeps
-// the smallest keys of its share of the references, then wave 0 merges.
-__global__ __launch_bounds__(256) void k_topl_full(ffh::TopLArgs a) {
-  const ffh::TopLDir d = a.dir[blockIdx.y];
-  const int m = blockIdx.x;
-  if (d.cnt[m] <= (uint32_t)ffh::kTopLCap) return;  // block-uniform
-  __shared__ uint64_t lists[256 * ffh::kTopLMax];
-  const int na = query_norm(d.Dq, a.W, a.nc, a.Wc, m);
-  const int i = m % a.Wc, j = m / a.Wc;
-  const uint4 qa = reinterpret_cast<const uint4 *>(d.Dq)[(size_t)(j * a.nc) * a.W + (size_t)(i * a.nc)];
-  const uint4 *Dr = reinterpret_cast<const uint4 *>(d.Dr);
-  const uint64_t tau = d.tau[m];
-  uint64_t list[ffh::kTopLMax];
-#pragma unroll
-  for (int t = 0; t < ffh::kTopLMax; ++t) list[t] = ~0ull;
-  for (int q = threadIdx.x; q < a.N; q += blockDim.x) {
-    const uint64_t key = rel_key(sq_dist16(qa, Dr[q]), na, (uint32_t)q);
-    if (key <= tau && key < list[ffh::kTopLMax - 1]) list_insert(list, key);
-  }
-#pragma unroll
-  for (int t = 0; t < ffh::kTopLMax; ++t) lists[threadIdx.x * ffh::kTopLMax + t] = list[t];
-  __syncthreads();
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
-  for (int k = 0; k < a.l; ++k) {
-    // this lane's smallest key among the lists of threads lane + 64 u
-    uint64_t mine = ~0ull;
-    int slot = -1;
-    for (int u = 0; u < 4; ++u)
-      for (int t = 0; t < ffh::kTopLMax; ++t) {
-        const int e = (lane + 64 * u) * ffh::kTopLMax + t;
-        if (lists[e] < mine) {
-          mine = lists[e];
-          slot = e;
-        }
-      }
-    const uint64_t mn = wave_min_u64(mine);
-    if (mn != ~0ull && mine == mn) lists[slot] = ~0ull;
-    if (lane == 0) d.cand[(size_t)m * a.l + k] = abs_key(mn, na);
+    const uint64_t rel = k == 0 ? d.nn_key[m] : d.keys[(size_t)(k - 1) * a.M + m];
+    uint64_t out = ~0ull;
+    if (rel != ~0ull && (int64_t)(uint32_t)rel < (int64_t)a.N)
+      out = ((uint64_t)(uint32_t)((int)(uint32_t)(rel >> 32) - (1 << 20) + na) << 32) | (uint32_t)rel;
+    d.cand[(size_t)m * a.l + k] = out;
   }
 }
 
@@ -625,33 +440,37 @@ hipError_t launch_nn(const NNArgs &args_in, hipStream_t stream) {
 
 
 size_t topl_scratch_bytes(int M) {
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return al((size_t)M * 8) + al((size_t)M * 4) + al((size_t)M * 4) + al((size_t)M * kTopLCap * 8);
-}
-
-void topl_carve(void *scratch, int M, TopLDir &d) {
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  char *p = static_cast<char *>(scratch);
-  d.tau = reinterpret_cast<uint64_t *>(p);
-  p += al((size_t)M * 8);
-  d.thr = reinterpret_cast<int32_t *>(p);
-  p += al((size_t)M * 4);
-  d.cnt = reinterpret_cast<uint32_t *>(p);
-  p += al((size_t)M * 4);
-  d.buf = reinterpret_cast<uint64_t *>(p);
+  return (((size_t)(kTopLMax - 1) * M * sizeof(uint64_t)) + 255) & ~(size_t)255;
 }
 
 hipError_t launch_topl(const TopLArgs &args_in, hipStream_t stream) {
   TopLArgs a = args_in;
   if (a.l < 1 || a.l > kTopLMax || a.M < 1 || a.N < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_topl_bound, dim3((a.M + 255) / 256, a.ndir), dim3(256), 0, stream, a);
+  NNArgs nn{};
+  nn.ndir = a.ndir;
+  nn.W = a.W;
+  nn.H = a.H;
+  nn.nc = a.nc;
+  nn.Wc = a.Wc;
+  nn.M = a.M;
+  nn.N = a.N;
   const int ntiles = (a.N + 31) / 32;
   const int nqb = nn_qblocks(a.M);
-  a.chunk_tiles = nn_chunk_tiles(ntiles, nqb * a.ndir);
-  const int nchunk = nn_chunks(a.N, a.chunk_tiles);
-  hipLaunchKernelGGL(k_topl_collect, dim3(nqb * nchunk * a.ndir), dim3(64 * kWaves), 0, stream, a);
-  hipLaunchKernelGGL(k_topl_select, dim3((a.M + 3) / 4, a.ndir), dim3(256), 0, stream, a);
-  hipLaunchKernelGGL(k_topl_full, dim3(a.M, a.ndir), dim3(256), 0, stream, a);
+  nn.chunk_tiles = nn_chunk_tiles(ntiles, nqb * a.ndir);
+  const int nchunk = nn_chunks(a.N, nn.chunk_tiles);
+  for (int k = 1; k < a.l; ++k) {
+    TopLPrev prev{};
+    for (int dr = 0; dr < a.ndir; ++dr) {
+      const TopLDir &d = a.dir[dr];
+      uint64_t *keys = d.keys + (size_t)(k - 1) * a.M;
+      nn.dir[dr] = {d.Dq, d.Dr, const_cast<int32_t *>(d.nb), keys};
+      prev.key[dr] = k == 1 ? d.nn_key : keys - a.M;
+      hipError_t e = launch_fill_u64(keys, ~0ull, a.M, stream);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_nn_excl, dim3(nqb * nchunk * a.ndir), dim3(64 * kWaves), 0, stream, nn, prev);
+  }
+  hipLaunchKernelGGL(k_topl_assemble, dim3((a.M + 255) / 256, a.ndir), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -41,16 +41,6 @@ def _images(kind, seed, H, W):
     return random_images(seed, H, W, kind=kind)
 
 
-def _overflowed(scratch, M):
-    """Cells whose collection exceeded the list capacity (the full-scan
-    path): the counters sit after the NN keys, the bounds and the
-    thresholds, each part 256-byte aligned."""
-    al = lambda b: (b + 255) // 256 * 256
-    off = al(M * 8) + al(M * 8) + al(M * 4)
-    cnt = host(scratch[off:off + 4 * M]).view(np.uint32)
-    return int(np.count_nonzero(cnt > 64))
-
-
 @pytest.mark.parametrize("kind,shape,nc,l", [("box", (37, 29), 4, 8), ("uniform", (40, 64), 4, 8),
                                              ("levels", (33, 47), 2, 8), ("flat", (20, 30), 2, 8),
                                              ("box", (130, 257), 8, 5), ("box", (2, 3), 1, 8),
@@ -64,25 +54,20 @@ def test_topl_candidates_bit_exact(kind, shape, nc, l):
     assert np.array_equal(host(cand), _expected_cand(idx, dist))
 
 
-def test_topl_overflow_takes_the_full_scan():
-    """Uncorrelated noise: the neighbourhood of the exact NN gives a loose
-    bound, far more than the list capacity of pixels pass it, and the
-    full scan must still return the exact ranking."""
-    H, W, nc, l = 48, 64, 4, 8
-    ia, ib = random_images(17, H, W, kind="uniform")
-    Da, Db = oracle.descriptor(oracle.blur(ia, 1), 1), oracle.descriptor(oracle.blur(ib, 1), 1)
-    M = -(-W // nc) * -(-H // nc)
-    nbytes = int(ff.lib().ff_nn_topl_scratch_bytes(W, H, nc))
-    scratch = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
-    nb = torch.empty(((W * H + 31) // 32) * 32, dtype=torch.int32, device="cuda")
-    cand = torch.empty((-(-H // nc), -(-W // nc), l), dtype=torch.int64, device="cuda")
-    from paper_1703_02563_amd.flowfields import _ptr, _stream, check
-    gA, gB = dev(Da), dev(Db)  # kept alive over the call
-    check(ff.lib().ff_nn_topl(_ptr(gA), _ptr(gB), W, H, nc, l, _ptr(nb), _ptr(scratch), nbytes, _ptr(cand),
-                              _stream()), "ff_nn_topl")
-    idx, dist = oracle.nn_topl(Da, Db, nc, l, nthreads=NT)
-    assert np.array_equal(host(cand), _expected_cand(idx, dist))
-    assert _overflowed(scratch, M) > 0
+def test_topl_ties_across_lanes_and_tiles():
+    """A periodic image (period 7 x 5 px) matched against itself: every
+    interior cell has exact copies at distance 0 all over the frame, so
+    the ranking is decided by the index among references that sit in
+    different lanes and tiles of the search."""
+    rng = np.random.default_rng(8)
+    pat = rng.integers(0, 256, size=(5, 7)).astype(np.uint8)
+    img = np.tile(pat, (30, 40))[:137, :263].copy()
+    D = oracle.descriptor(oracle.blur(img, 1), 1)
+    for nc, l in ((4, 8), (8, 6)):
+        idx, dist = oracle.nn_topl(D, D, nc, l, nthreads=NT)
+        assert np.count_nonzero(dist[..., -1] == 0) > 100  # many cells with l exact copies
+        cand = ff.nn_topl(dev(D), dev(D), nc, l)
+        assert np.array_equal(host(cand), _expected_cand(idx, dist))
 
 
 @pytest.mark.parametrize("shape,nc,l", [((40, 60), 4, 8), ((61, 95), 8, 3), ((3, 5), 2, 8), ((130, 257), 4, 8)])
