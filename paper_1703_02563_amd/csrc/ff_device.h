@@ -151,16 +151,20 @@ struct CostU8 {
                    f2y, en2, c1, c2);
   }
   // The terms of patch positions k = g, g + G, ... (k = (v + R)(2R + 1) +
-  // u + R): integers, so the G parts of one evaluation add up to eval's
-  // value in any order.
-  template <int R>
+  // u + R) for lane g of G: integers, so the G parts of one evaluation add
+  // up to eval's value in any order.
+  template <int R, int G>
   __device__ static uint32_t eval_part(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
-                                       int fy, int g, int G) {
+                                       int fy, int g) {
     const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
     const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
     constexpr int D = 2 * R + 1;
     uint32_t s = 0;
-    for (int k = g; k < D * D; k += G) {
+    // unrolled: all of the lane's loads are in flight together
+#pragma unroll
+    for (int it = 0; it < (D * D + G - 1) / G; ++it) {
+      const int k = g + it * G;
+      if (k >= D * D) break;
       const int v = k / D - R, u = k % D - R;
       const uint4 a = Da[(size_t)(clampi(y + n * v, Hm) + P) * Wp + desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
       const uint4 b =
@@ -273,9 +277,9 @@ struct CostU8Sub {
     c2 = en2 ? eval<R>(Da, Db, W, H, n, x, y, f2x, f2y) : 0u;
   }
   // The terms of patch positions k = g, g + G, ... (see CostU8::eval_part).
-  template <int R>
+  template <int R, int G>
   __device__ static uint32_t eval_part(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
-                                       int fy, int g, int G) {
+                                       int fy, int g) {
     const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
     const int tx = x * 8 + fx, ty = y * 8 + fy;
     const int tx0 = tx >> 3, ty0 = ty >> 3, ax = tx & 7, ay = ty & 7;
@@ -284,7 +288,10 @@ struct CostU8Sub {
     const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
     constexpr int D = 2 * R + 1;
     uint32_t sum = 0;
-    for (int k = g; k < D * D; k += G) {
+#pragma unroll
+    for (int it = 0; it < (D * D + G - 1) / G; ++it) {
+      const int k = g + it * G;
+      if (k >= D * D) break;
       const int v = k / D - R, u = k % D - R;
       const uint4 a = Da[(size_t)(clampi(y + n * v, Hm) + P) * Wp + desc_col(clampi(x + n * u, Wm) + P, l2, Wp)];
       const uint4 *r0 = Db + (size_t)(clampi(ty0 + n * v, Hm) + P) * Wp;

@@ -265,7 +265,8 @@ constexpr int kRasterTile = 32;
 constexpr int kRasterLanes = 8;
 
 template <int R, class Cost>
-__global__ __launch_bounds__(512) void k_prop_raster(ffh::LevelArgs a, int diag, int nty) {
+__global__ __launch_bounds__(2 * kRasterTile * kRasterLanes) void k_prop_raster(ffh::LevelArgs a, int diag,
+                                                                                  int nty) {
   constexpr int S = kRasterTile, G = kRasterLanes, S1 = S + 1;
   __shared__ int32_t sf[S1 * S1];
   __shared__ uint32_t sc[S1 * S1];
@@ -299,10 +300,10 @@ __global__ __launch_bounds__(512) void k_prop_raster(ffh::LevelArgs a, int diag,
   __syncthreads();
   const int slot = threadIdx.x / (2 * G), cand = (threadIdx.x / G) & 1, g = threadIdx.x % G;
   int cnt = 0, work = 0;
-  for (int dd = 0; dd <= tw + th - 2; ++dd) {
+  for (int dd = 0; dd <= tw + th - 2; ++dd) {  // cell anti-diagonals of the tile
     const int amin = max(0, dd - (th - 1)), amax = min(dd, tw - 1);
     const int la = amin + slot, lb = dd - la;
-    if (la <= amax) {  // uniform over the cell's 16 lanes
+    if (la <= amax) {  // uniform over the cell's 2G lanes
       const int o = (lb + 1) * S1 + la + 1;
       const int32_t f0 = sf[o], fh = sf[o - 1], fv = sf[o - S1];
       const uint32_t c0 = sc[o], ch = sc[o - 1], cv = sc[o - S1];
@@ -318,10 +319,9 @@ __global__ __launch_bounds__(512) void k_prop_raster(ffh::LevelArgs a, int diag,
       const int32_t fc = cand == 0 ? fh : fv;
       uint32_t part = 0;
       if (cand == 0 ? hv : vcomp)
-        part = Cost::template eval_part<R>(d.Da, d.Db, W, H, n, x, y, ffk::flow_x(fc), ffk::flow_y(fc), g, G);
-      part += __shfl_xor(part, 1);
-      part += __shfl_xor(part, 2);
-      part += __shfl_xor(part, 4);
+        part = Cost::template eval_part<R, G>(d.Da, d.Db, W, H, n, x, y, ffk::flow_x(fc), ffk::flow_y(fc), g);
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off);
       const uint32_t other = __shfl_xor(part, G);
       if (cand == 0 && g == 0) {
         const uint32_t eh = part, ev = other;
