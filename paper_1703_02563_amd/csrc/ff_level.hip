@@ -30,9 +30,9 @@ constexpr Variant kVariants[] = {
     {16, 16, kH, 10, 10}, {16, 16, 2, 3, 11},   {32, 16, 2, 2, 12},   {16, 16, kH, 3, 13},  {8, 8, kH, 8, 14},
     {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},   {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},
     {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},
-    {64, 32, 4, 0, 16}};
-constexpr int kNumVariants = 26;
-constexpr int kFirstWform = 18;
+    {64, 32, 4, 0, 16},   {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},     {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},
+    {16, 16, kH, 10, 30}};
+constexpr int kNumVariants = 31;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);
@@ -114,7 +114,9 @@ bool level_map_fits(int W, int H, int log2n) {
   return ((size_t)W + 2 * P) * ((size_t)H + 2 * P) * 16 < ((size_t)1 << 31);
 }
 
-bool level_uses_wform(int variant) { return variant >= kFirstWform && variant < kNumVariants; }
+bool level_uses_wform(int variant) {
+  return variant >= 0 && variant < kNumVariants && kVariants[variant].nowf != variant;
+}
 
 // The table's variant, or its fallback where image b's map is too large
 // for the 32-bit offsets of the quad evaluations, or its descriptor-quad

@@ -993,6 +993,11 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 23: return launch_v<LOG2N, 8, 8, 256, 4, 2>(a, batch, stream);
     case 24: return launch_v<LOG2N, 32, 16, 512, 4, 4>(a, batch, stream);
     case 25: return launch_v<LOG2N, 64, 32, 1024, 4, 4>(a, batch, stream);
+    case 26: return launch_v<LOG2N, 8, 8, 1024, 3>(a, batch, stream);
+    case 27: return launch_v<LOG2N, 8, 8, 1024, 3, 4>(a, batch, stream);
+    case 28: return launch_v<LOG2N, 8, 8, 1024, 4>(a, batch, stream);
+    case 29: return launch_v<LOG2N, 8, 8, 1024, 4, 4>(a, batch, stream);
+    case 30: return launch_v<LOG2N, 16, 16, 1024, 3>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
