@@ -46,8 +46,10 @@ def lib():
         L.or_nn_topl.argtypes = [P, P, i, i, i, i, P, P, i]
         L.or_init_coarse_l.argtypes = [P, i, P, P, i, i, i, i, P, P, P]
         L.or_propagate_raster.argtypes = [P, P, i, i, i, i, i, P, P, P]
-        L.or_flow_fields_x.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P, P,
-                                       P]
+        L.or_flow_fields_x.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P,
+                                       P, P]
+        L.or_nn_topl_step.argtypes = [P, P, i, i, i, i, i, P, P, i]
+        L.or_consistency_grid.argtypes = [P, P, P, P, i, i, i, dbl, P]
         L.or_flow_fields_x.restype = i
         L.or_seed_level.argtypes = [P, P, P, P, i, i, i, i, P, P, P]
         L.or_propagate.argtypes = [P, P, i, i, i, i, i, P, P, P, i]
@@ -127,14 +129,15 @@ def nn(Da1, Db1, nc: int, nthreads: int = 1):
     return idx, dist
 
 
-def nn_topl(Da1, Db1, nc: int, l: int, nthreads: int = 1):
+def nn_topl(Da1, Db1, nc: int, l: int, nthreads: int = 1, rstep: int = 1):
     """The l nearest pixels of every coarsest-grid cell, ranked by (distance,
-    index): idx [Hc][Wc][l] (-1 past the image's pixel count), dist alike."""
+    index): idx [Hc][Wc][l] (-1 past the image's pixel count), dist alike;
+    rstep = 2: among the pixels with even x and y only."""
     H, W = Da1.shape[:2]
     Wc, Hc = cells(W, H, nc)
     idx = np.empty((Hc, Wc, l), np.int32)
     dist = np.empty((Hc, Wc, l), np.int64)
-    lib().or_nn_topl(_p(Da1), _p(Db1), W, H, nc, l, _p(idx), _p(dist), nthreads)
+    lib().or_nn_topl_step(_p(Da1), _p(Db1), W, H, nc, l, rstep, _p(idx), _p(dist), nthreads)
     return idx, dist
 
 
@@ -228,6 +231,16 @@ def consistency(fa, ca, fb, cb, eps: float = 1.0):
     return keep
 
 
+def consistency_grid(fa, ca, fb, cb, W: int, H: int, n: int, eps: float = 1.0):
+    """Keep mask of a field on the grid of scale n (one match per n x n
+    region) against the backward field on the same grid."""
+    Wn, Hn = cells(W, H, n)
+    keep = np.empty((Hn, Wn), np.uint8)
+    args = [np.ascontiguousarray(a) for a in (fa, ca, fb, cb)]
+    lib().or_consistency_grid(*[_p(a) for a in args], W, H, n, float(eps), _p(keep))
+    return keep
+
+
 def consistency2(fa, ca, fb1, cb1, fb2, cb2, eps: float = 1.0):
     """Keep mask of field a against two backward fields (Sec. 3.7)."""
     H, W = ca.shape
@@ -262,24 +275,29 @@ def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:
 
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
                 eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
-                fine_iters: int = 0, subpixel: int = 0, nn_l: int = 1, raster: bool = False) -> dict:
+                fine_iters: int = 0, subpixel: int = 0, nn_l: int = 1, raster: bool = False,
+                fast_x2: bool = False) -> dict:
     """The whole schedule on one pair.  plus_iters > 0: Flow Fields+ (P steps
     at R^+ = Rp_num / R_den before the `iters` steps at R); fine_iters > 0:
     the finest scale runs only that many steps at R (Flow Fields+ Fast);
     subpixel = s > 0: flows in units of 1/2^s pixel, bilinear targets, costs
     of cost_sub (scaled by 4^s); nn_l > 1: seeds reranked among the nn_l
-    nearest pixels (Eq. 4); raster: serial-order propagation steps."""
+    nearest pixels (Eq. 4); raster: serial-order propagation steps; fast_x2:
+    Flow Fields+ Fast x2 (finest scale skipped, seeds among the even pixels,
+    fields and masks on the grid of scale 2, fine_iters steps there)."""
     img1, img2 = _u8(img1), _u8(img2)
     H, W = img1.shape
+    Ho, Wo = (-(-H // 2), -(-W // 2)) if fast_x2 else (H, W)
     out = {
-        "flow_fwd": np.empty((H, W, 2), np.int16), "flow_bwd": np.empty((H, W, 2), np.int16),
-        "cost_fwd": np.empty((H, W), np.uint32), "cost_bwd": np.empty((H, W), np.uint32),
-        "keep_fwd": np.empty((H, W), np.uint8), "keep_bwd": np.empty((H, W), np.uint8),
+        "flow_fwd": np.empty((Ho, Wo, 2), np.int16), "flow_bwd": np.empty((Ho, Wo, 2), np.int16),
+        "cost_fwd": np.empty((Ho, Wo), np.uint32), "cost_bwd": np.empty((Ho, Wo), np.uint32),
+        "keep_fwd": np.empty((Ho, Wo), np.uint8), "keep_bwd": np.empty((Ho, Wo), np.uint8),
     }
     ne = np.zeros(2, np.uint64)
-    if nn_l != 1 or raster:
+    if nn_l != 1 or raster or fast_x2:
         rc = lib().or_flow_fields_x(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters,
-                                    Rp_num, fine_iters, subpixel, nn_l, int(bool(raster)), float(eps), seed, nthreads,
+                                    Rp_num, fine_iters, subpixel, nn_l, int(bool(raster)), int(bool(fast_x2)),
+                                    float(eps), seed, nthreads,
                                     _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
                                     _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
     elif subpixel:

@@ -23,7 +23,8 @@
  *               descriptors (stands in for the kd-tree of Sec. 3.1 with leaf
  *               size 1, R4); ties go to the smallest linear index.
  *   nn_topl     the l nearest pixels in the same order (the candidate set L
- *               of Sec. 3.1 read as the l nearest neighbours, R28).
+ *               of Sec. 3.1 read as the l nearest neighbours, R28); with a
+ *               reference step of 2, the even pixels only (Fast x2, R30).
  *   init        initial flow F = q - p (Eq. 1 / Eq. 4) and its cost at the
  *               coarsest scale: the candidate of lowest E_nc, the earlier
  *               rank on equal cost (|L| = 1: the nearest neighbour).
@@ -45,7 +46,9 @@
  *               multiply-shift (ACM TOMACS 2019).
  *   consistency forward-backward check (Sec. 3.7): keep p iff
  *               |F(p) + F_b(p + F(p))| < eps, evaluated exactly (R14);
- *               consistency2 the same against two backward fields.
+ *               consistency2 the same against two backward fields;
+ *               consistency_grid the check of fields on the grid of scale
+ *               n (one match per n x n region, Fast x2, R30).
  *   region_filter  deletes small regions next to removed outliers (Sec. 3.7).
  *   sparsify    one sample per q x q region (Sec. 3.8).
  *   cost_sub    the subpixel form (Sec. 3.1: random-search offsets with
@@ -56,7 +59,8 @@
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
  *               random-search steps between them, forward and backward;
  *               optionally the Flow Fields+ steps (Sec. 3.3: P steps at
- *               R^+ first) and the Fast finest scale (Sec. 3.4).
+ *               R^+ first), the Fast finest scale (Sec. 3.4) and Fast x2
+ *               (finest scale skipped, R30).
  *
  * Layouts: images uint8 [H][W]; descriptors uint8 [H][W][16]; a level grid
  * of scale n has ceil(W/n) x ceil(H/n) cells, cell (i, j) <-> pixel
@@ -313,12 +317,13 @@ void or_nn(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc,
  * scale nc, the l pixels q of image b with the smallest (squared L2 distance
  * of the level-1 descriptors, q.y*W + q.x), in that order; idx[k*l + c],
  * dist[k*l + c] is candidate c of cell k, idx -1 (dist INT64_MAX) where the
- * image has fewer than l pixels.  l = 1 is or_nn. */
-void or_nn_topl(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, int l,
-                int32_t *idx, int64_t *dist, int nthreads)
+ * image has fewer than l pixels.  l = 1 is or_nn.  rstep = 2: only the
+ * pixels with even x and y are candidates (Flow Fields+ Fast x2, Sec. 3.4:
+ * one pixel of every 2x2 region enters the tree). */
+void or_nn_topl_step(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, int l, int rstep,
+                     int32_t *idx, int64_t *dist, int nthreads)
 {
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
-    int64_t N = (int64_t)W * H;
     (void)nthreads;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
@@ -329,25 +334,33 @@ void or_nn_topl(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, in
         int32_t *bi = idx + (size_t)k * l;
         int64_t *bd = dist + (size_t)k * l;
         for (int c = 0; c < l; ++c) { bi[c] = -1; bd[c] = INT64_MAX; }
-        for (int64_t q = 0; q < N; ++q) {
-            const uint8_t *b = Db1 + (size_t)q * 16;
-            int64_t d = 0;
-            for (int c = 0; c < 16; ++c) {
-                int64_t e = (int64_t)a[c] - (int64_t)b[c];
-                d += e * e;
+        for (int qy = 0; qy < H; qy += rstep)
+            for (int qx = 0; qx < W; qx += rstep) {
+                int32_t q = qy * W + qx;
+                const uint8_t *b = Db1 + (size_t)q * 16;
+                int64_t d = 0;
+                for (int c = 0; c < 16; ++c) {
+                    int64_t e = (int64_t)a[c] - (int64_t)b[c];
+                    d += e * e;
+                }
+                /* q grows, so an equal distance ranks after every listed entry */
+                if (d >= bd[l - 1]) continue;
+                int pos = l - 1;
+                while (pos > 0 && bd[pos - 1] > d) {
+                    bd[pos] = bd[pos - 1];
+                    bi[pos] = bi[pos - 1];
+                    --pos;
+                }
+                bd[pos] = d;
+                bi[pos] = q;
             }
-            /* q grows, so an equal distance ranks after every listed entry */
-            if (d >= bd[l - 1]) continue;
-            int pos = l - 1;
-            while (pos > 0 && bd[pos - 1] > d) {
-                bd[pos] = bd[pos - 1];
-                bi[pos] = bi[pos - 1];
-                --pos;
-            }
-            bd[pos] = d;
-            bi[pos] = (int32_t)q;
-        }
     }
+}
+
+void or_nn_topl(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, int l,
+                int32_t *idx, int64_t *dist, int nthreads)
+{
+    or_nn_topl_step(Da1, Db1, W, H, nc, l, 1, idx, dist, nthreads);
 }
 
 /* Initial flow of the coarsest scale (Eq. 1; Eq. 4 at scale nc): of the l
@@ -621,6 +634,30 @@ void or_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, co
     consistency_g(fa, ca, fb, cb, W, H, 0, eps, keep);
 }
 
+/* The check on fields of the grid of scale n (Flow Fields+ Fast x2, Sec.
+ * 3.4: one match per n x n region): cell (i, j) is pixel p = (i n, j n); the
+ * backward match used for its target t = p + F_a is the one of the region
+ * holding t, cell (floor(t.x / n), floor(t.y / n)); keep iff both are set
+ * and |F_a + F_b|^2 < eps^2 (exact integers, compared in double).  n = 1
+ * is or_consistency. */
+void or_consistency_grid(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb, int W,
+                         int H, int n, double eps, uint8_t *keep)
+{
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n);
+    for (int j = 0; j < Hn; ++j)
+        for (int i = 0; i < Wn; ++i) {
+            size_t k = (size_t)j * Wn + i;
+            keep[k] = 0;
+            if (ca[k] == OR_UNSET) continue;
+            int tx = i * n + fa[2 * k], ty = j * n + fa[2 * k + 1];
+            if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
+            size_t kq = (size_t)(ty / n) * Wn + (size_t)(tx / n);
+            if (cb[kq] == OR_UNSET) continue;
+            int64_t dx = fa[2 * k] + fb[2 * kq], dy = fa[2 * k + 1] + fb[2 * kq + 1];
+            keep[k] = (double)(dx * dx + dy * dy) < eps * eps;
+        }
+}
+
 /* Consistency against two backward fields (Sec. 3.7): keep pixel p of
  * field a iff it passes the check of or_consistency against field b1 and
  * against field b2 (fields with different generator seeds and possibly
@@ -751,20 +788,20 @@ int or_rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n
  * steps at R_n; random searches sit only between two steps of the same
  * group (P - 1 and T - 1 of them), and the step index t, which sets the
  * direction t mod 4 and keys the generator, runs on over both groups.
- * Flow Fields+ Fast (Sec. 3.4): the finest scale runs only Tfine steps at
- * R_n (no R^+ group) when Tfine > 0. */
+ * Flow Fields+ Fast (Sec. 3.4): the finest scale run (level lmin) runs only
+ * Tfine steps at R_n (no R^+ group) when Tfine > 0. */
 typedef struct {
     int P, T;      /* steps at R_n^+, then at R_n */
     int Rn, Rnp;   /* R_n and R_n^+ */
 } or_scale_steps;
 
-static or_scale_steps scale_steps(int level, int T, int R_num, int R_den, int P, int Rp_num, int Tfine)
+static or_scale_steps scale_steps(int level, int lmin, int T, int R_num, int R_den, int P, int Rp_num, int Tfine)
 {
     int n = 1 << level;
     or_scale_steps st;
     st.P = P;
     st.T = T;
-    if (level == 0 && Tfine > 0) {
+    if (level == lmin && Tfine > 0) {
         st.P = 0;
         st.T = Tfine;
     }
@@ -775,11 +812,13 @@ static or_scale_steps scale_steps(int level, int T, int R_num, int R_den, int P,
 
 /* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, with the
  * per-scale steps of scale_steps; nn_l candidates per seed (Eq. 4), raster:
- * serial-order propagation steps instead of checkerboard ones. */
+ * serial-order propagation steps instead of checkerboard ones; lmin = 1:
+ * the finest scale is not run and the result is the grid of scale 2, the
+ * seeds taken from the even pixels only (Flow Fields+ Fast x2, Sec. 3.4). */
 static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
                                const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
-                               int P, int Rp_num, int Tfine, int nn_l, int raster, uint64_t seed, int stream,
-                               int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
+                               int P, int Rp_num, int Tfine, int nn_l, int raster, int lmin, uint64_t seed,
+                               int stream, int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
 {
     int nc = 1 << (L - 1);
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
@@ -792,20 +831,20 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
         fl[b] = (int16_t *)malloc(sizeof(int16_t) * 2 * cells0);
         co[b] = (uint32_t *)malloc(sizeof(uint32_t) * cells0);
     }
-    if (nn_l == 1)
+    if (nn_l == 1 && lmin == 0)
         or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
     else
-        or_nn_topl(Nq, Nr, W, H, nc, nn_l, idx, dist, nthreads);
+        or_nn_topl_step(Nq, Nr, W, H, nc, nn_l, lmin ? 2 : 1, idx, dist, nthreads);
     int cur = 0;
     init_coarse_g(E, s, idx, nn_l, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
-    for (int level = L - 1; level >= 0; --level) {
+    for (int level = L - 1; level >= lmin; --level) {
         int n = 1 << level;
         if (level < L - 1) {
             seed_level_g(E, s, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1],
                          n_evals);
             cur ^= 1;
         }
-        or_scale_steps st = scale_steps(level, T, R_num, R_den, P, Rp_num, Tfine);
+        or_scale_steps st = scale_steps(level, lmin, T, R_num, R_den, P, Rp_num, Tfine);
         for (int t = 0; t < st.P + st.T; ++t) {
             if (raster)
                 propagate_raster_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals);
@@ -817,8 +856,9 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
                                 level, t, fl[cur], co[cur], n_evals, nthreads);
         }
     }
-    memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells0);
-    memcpy(cost_out, co[cur], sizeof(uint32_t) * cells0);
+    size_t cells_out = (size_t)ceil_div(W, 1 << lmin) * ceil_div(H, 1 << lmin);
+    memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells_out);
+    memcpy(cost_out, co[cur], sizeof(uint32_t) * cells_out);
     for (int b = 0; b < 2; ++b) { free(fl[b]); free(co[b]); }
     free(idx);
     free(dist);
@@ -831,16 +871,18 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
  * s > 0: the subpixel form (flows, random-search offsets and the
  * consistency threshold in units of 1/2^s pixel, costs of or_cost_sub).
  * nn_l in [1, 16]: seeds reranked among the nn_l nearest pixels (Eq. 4);
- * raster != 0: propagation steps in serial order (propagate_raster_g). */
+ * raster != 0: propagation steps in serial order (propagate_raster_g);
+ * fast_x2 != 0: Flow Fields+ Fast x2 (Sec. 3.4), the fields and masks are
+ * grids of scale 2 ([ceil(H/2)][ceil(W/2)]) checked by or_consistency_grid. */
 static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
-                         int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, double eps,
-                         uint64_t seed, int nthreads,
+                         int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2,
+                         double eps, uint64_t seed, int nthreads,
                          int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                          uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
         R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64 || s < 0 || s > 3 ||
-        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))) || nn_l < 1 || nn_l > 16)
+        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))) || nn_l < 1 || nn_l > 16 || (fast_x2 && (L < 2 || s > 0)))
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *blur = (uint8_t *)malloc(np);
@@ -856,14 +898,20 @@ static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H,
     }
     or_cost_fn E = s > 0 ? cost_u8_sub : cost_u8;
     n_evals[0] = n_evals[1] = 0;
+    int lmin = fast_x2 ? 1 : 0;
     flow_one_direction(E, s, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, seed, 0, nthreads, flow_fwd, cost_fwd,
+                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, lmin, seed, 0, nthreads, flow_fwd, cost_fwd,
                        &n_evals[0]);
     flow_one_direction(E, s, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, seed, 1, nthreads, flow_bwd, cost_bwd,
+                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, lmin, seed, 1, nthreads, flow_bwd, cost_bwd,
                        &n_evals[1]);
-    consistency_g(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, s, eps, keep_fwd);
-    if (keep_bwd) consistency_g(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, s, eps, keep_bwd);
+    if (fast_x2) {
+        or_consistency_grid(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, 2, eps, keep_fwd);
+        if (keep_bwd) or_consistency_grid(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, 2, eps, keep_bwd);
+    } else {
+        consistency_g(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, s, eps, keep_fwd);
+        if (keep_bwd) consistency_g(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, s, eps, keep_bwd);
+    }
     for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
     free(blur);
     return 0;
@@ -874,19 +922,20 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
                    int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                    uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, 1, 0, eps, seed, nthreads,
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, 1, 0, 0, eps, seed, nthreads,
                          flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* or_flow_fields with every option: subpixel form s, nn_l seed candidates,
- * serial-order (raster) propagation. */
+ * serial-order (raster) propagation, Flow Fields+ Fast x2 (fast_x2; outputs
+ * on the grid of scale 2). */
 int or_flow_fields_x(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
-                     int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, double eps, uint64_t seed,
-                     int nthreads, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
-                     uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+                     int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2, double eps,
+                     uint64_t seed, int nthreads, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd,
+                     uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, nn_l, raster, eps, seed,
-                         nthreads, flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, nn_l, raster, fast_x2, eps,
+                         seed, nthreads, flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* The subpixel form of or_flow_fields (flows in units of 1/2^s pixel). */
@@ -895,7 +944,7 @@ int or_flow_fields_sub(const uint8_t *img1, const uint8_t *img2, int W, int H, i
                        int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                        uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, 1, 0, eps, seed, nthreads,
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, 1, 0, 0, eps, seed, nthreads,
                          flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
@@ -939,9 +988,9 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
     or_quantize_pair_u8(F1[0], F2[0], (int64_t)np * 16, q1, q2);
     n_evals[0] = n_evals[1] = 0;
     flow_one_direction(cost_f32, 0, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, 1, 0, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
+                       R_den, P, Rp_num, Tfine, 1, 0, 0, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
     flow_one_direction(cost_f32, 0, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, 1, 0, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+                       R_den, P, Rp_num, Tfine, 1, 0, 0, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     free(q1);
