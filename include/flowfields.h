@@ -117,6 +117,16 @@ typedef struct {
      * FF_ERR_ARG.  ff_flow_fields_batched and ff_flow_fields_f32 return
      * FF_ERR_UNSUPPORTED for nn_l > 1 or raster = 1. */
     int32_t raster;
+    /* Flow Fields+ Fast x2 (Sec. 3.4): 1 = the finest scale is not run; the
+     * scale-2 grid is the last one (its step count is fine_iters when that
+     * is > 0), the NN seed searches only the pixels with even x and y (one
+     * pixel of every 2x2 region), and ff_flow_fields returns fields, costs
+     * and masks on the grid of scale 2 ([ceil(H/2)][ceil(W/2)] cells, cell
+     * (i, j) = pixel (2i, 2j), flows in pixels), checked with
+     * ff_consistency_filter_grid.  Needs levels >= 2 and subpixel = 0
+     * (FF_ERR_ARG otherwise); the batched and learned calls return
+     * FF_ERR_UNSUPPORTED. */
+    int32_t fast_x2;
 } ff_params;
 
 /* The built-in launch tables (host): written to *out. */
@@ -276,6 +286,17 @@ ff_status ff_consistency_filter(const int16_t *flow_a, const uint32_t *cost_a, c
 ff_status ff_consistency_filter_sub(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
                                     const uint32_t *cost_b, int32_t W, int32_t H, int32_t subpixel, float eps,
                                     uint8_t *keep_a, uint8_t *keep_b, void *stream);
+
+/* The check of fields on the grid of scale n (one match per n x n region,
+ * Flow Fields+ Fast x2, Sec. 3.4): cell (i, j) is pixel p = (i n, j n); its
+ * target t = p + F_a is checked against the match of the region holding t,
+ * cell (floor(t.x / n), floor(t.y / n)) of field b: kept iff both are set
+ * and |F_a + F_b|^2 < eps^2.  Fields, costs and masks: [ceil(H/n)][ceil(W/n)]
+ * (W, H: the image size); keep_b nullable (the mask of field b against
+ * field a).  n = 1 is ff_consistency_filter. */
+ff_status ff_consistency_filter_grid(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                     const uint32_t *cost_b, int32_t W, int32_t H, int32_t n, float eps,
+                                     uint8_t *keep_a, uint8_t *keep_b, void *stream);
 
 /* Consistency against two backward fields (Sec. 3.7): keep_a[p] = 1 iff p
  * passes the ff_consistency_filter test against field b1 and against field

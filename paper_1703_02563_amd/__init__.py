@@ -6,13 +6,13 @@ Python binding.
 """
 from .ffi import FlowFieldsError, lib  # noqa: F401
 from .flowfields import (FlowFields, Params, Tuning, consistency_filter, consistency_filter2,  # noqa: F401
-                         consistency_filter_sub,
+                         consistency_filter_sub, consistency_filter_grid,
                          default_tuning, descriptors, flow_fields, flow_fields_two_backward, init_nn,
                          level_launches, propagate_level, random_search, run_level, seed_level, region_filter,
                          sparsify, workspace_bytes, nn_topl, init_nn_l, propagate_raster)
 
 __all__ = ["FlowFieldsError", "lib", "FlowFields", "Params", "Tuning", "consistency_filter", "consistency_filter2",
-           "consistency_filter_sub",
+           "consistency_filter_sub", "consistency_filter_grid",
            "default_tuning", "descriptors", "flow_fields", "flow_fields_two_backward", "init_nn", "level_launches",
            "propagate_level", "random_search", "run_level", "seed_level", "region_filter", "sparsify",
            "workspace_bytes", "nn_topl", "init_nn_l", "propagate_raster"]

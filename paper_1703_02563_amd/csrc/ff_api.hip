@@ -43,7 +43,8 @@ bool params_ok(const ff_params *p) {
          p->radius <= 7 && p->R_num >= 0 && p->R_den >= 1 && p->R_num <= 1 << 20 && p->R_den <= 1 << 20 &&
          p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
          p->fine_iters >= 0 && p->fine_iters <= 64 && (p->subpixel == 0 || p->subpixel == 3) && p->nn_l >= 0 &&
-         p->nn_l <= ffh::kTopLMax && (p->raster == 0 || p->raster == 1) && ffh::tuning_ok(tuning_of(p->tuning));
+         p->nn_l <= ffh::kTopLMax && (p->raster == 0 || p->raster == 1) && (p->fast_x2 == 0 || p->fast_x2 == 1) &&
+         (!p->fast_x2 || (p->levels >= 2 && p->subpixel == 0)) && ffh::tuning_ok(tuning_of(p->tuning));
 }
 
 // Seed candidates of the call (0 and 1: the exact NN alone).
@@ -70,7 +71,7 @@ struct ScaleSteps {
 ScaleSteps scale_steps(const ff_params *p, int lv) {
   const int n = 1 << lv;
   ScaleSteps st{p->plus_iters, p->iters, rs_radius(n, p->R_num, p->R_den), rs_radius(n, p->Rp_num, p->R_den)};
-  if (lv == 0 && p->fine_iters > 0) {
+  if (lv == (p->fast_x2 ? 1 : 0) && p->fine_iters > 0) {  // the finest scale run
     st.P = 0;
     st.T = p->fine_iters;
   }
@@ -79,8 +80,8 @@ ScaleSteps scale_steps(const ff_params *p, int lv) {
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, nb, keys, topl, cand, grids, sgrids, evals,
-      total;
+  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, desc1e, nb, keys, topl, cand, grids, sgrids,
+      evals, total;
   size_t N, Npad, M;
   int L;
 };
@@ -112,6 +113,9 @@ Layout layout(int W, int H, const ff_params *p) {
       off = align256(off + ffk::wform_bytes(W, H, 1 << lv));
     }
   l.desc1 = off; off = align256(off + 2 * l.N * 16);
+  // Fast x2: the NN's references, the even pixels of both images
+  l.desc1e = off;
+  if (p->fast_x2) off = align256(off + 2 * (size_t)ceil_div(W, 2) * ceil_div(H, 2) * 16);
   l.nb = off; off = align256(off + 2 * l.Npad * sizeof(int32_t));
   l.keys = off; off = align256(off + 2 * l.M * sizeof(uint64_t));
   // seed rerank: bound, collection and ranked candidates of both directions
@@ -503,6 +507,15 @@ ff_status ff_consistency_filter_sub(const int16_t *flow_a, const uint32_t *cost_
                                           (hipStream_t)stream, subpixel));
 }
 
+ff_status ff_consistency_filter_grid(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b,
+                                     const uint32_t *cost_b, int32_t W, int32_t H, int32_t n, float eps,
+                                     uint8_t *keep_a, uint8_t *keep_b, void *stream) {
+  if (!flow_a || !cost_a || !flow_b || !cost_b || !keep_a || !dims_ok(W, H) || !is_pow2(n) || !(eps >= 0.0f))
+    return FF_ERR_ARG;
+  return from_hip(ffh::launch_consistency_grid(flow_a, cost_a, flow_b, cost_b, W, H, n, eps, keep_a, keep_b,
+                                               (hipStream_t)stream));
+}
+
 ff_status ff_consistency_filter2(const int16_t *flow_a, const uint32_t *cost_a, const int16_t *flow_b1,
                                  const uint32_t *cost_b1, const int16_t *flow_b2, const uint32_t *cost_b2, int32_t W,
                                  int32_t H, float eps, uint8_t *keep_a, void *stream) {
@@ -725,7 +738,8 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
                                  void *ws, size_t ws_bytes, void *stream) {
   if (!batch_ok(pairs, npairs, params) || !table || !ws || !(params->eps >= 0.0f)) return FF_ERR_ARG;
   if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
-  if (params->radius != 3 || params->subpixel || params->nn_l > 1 || params->raster) return FF_ERR_UNSUPPORTED;
+  if (params->radius != 3 || params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2)
+    return FF_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const int L = params->levels, nc = 1 << (L - 1);
   ffh::BatchStage st{};
@@ -847,7 +861,7 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const int L = params->levels, r = params->radius;
-  if (params->subpixel || params->nn_l > 1 || params->raster) return FF_ERR_UNSUPPORTED;
+  if (params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2) return FF_ERR_UNSUPPORTED;
   for (int lv = 0; lv < L; ++lv)
     if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
   const LayoutF32 lay = layout_f32(W, H, params);
@@ -1117,6 +1131,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   if (ws_bytes < lay.total) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int L = params->levels, r = params->radius;
+  const int lmin = params->fast_x2 ? 1 : 0;  // finest scale run (Fast x2: scale 2)
   char *base = static_cast<char *>(ws);
   const uint8_t *img[2] = {img1, img2};
 
@@ -1131,9 +1146,11 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     for (int lv = 0; lv < L; ++lv) {
       const int z = im * L + lv;
       desc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.desc[im][lv]);
+      // scales below lmin only give the NN its level-1 descriptors
       jobs.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
-                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, desc[im][lv],
-                     lv == 0 ? desc1[im] : nullptr, reinterpret_cast<uint8_t *>(base + lay.wform[im][lv]), 1 << lv};
+                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N,
+                     lv < lmin ? nullptr : desc[im][lv], lv == 0 ? desc1[im] : nullptr,
+                     lv < lmin ? nullptr : reinterpret_cast<uint8_t *>(base + lay.wform[im][lv]), 1 << lv};
     }
   }
   hipError_t e = ffh::launch_descriptors(jobs, s);
@@ -1142,13 +1159,9 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   uint64_t *evals = n_evals ? n_evals : reinterpret_cast<uint64_t *>(base + lay.evals);
   if ((e = ffh::launch_fill_u64(evals, 0, 2, s)) != hipSuccess) return FF_ERR_LAUNCH;
 
-  // level grids: scale 1 lives in the caller's outputs
+  // level grids: the finest scale run lives in the caller's outputs
   int32_t *gflow[kMaxLevels][2];
   uint32_t *gcost[kMaxLevels][2];
-  gflow[0][0] = reinterpret_cast<int32_t *>(flow_fwd);
-  gflow[0][1] = reinterpret_cast<int32_t *>(flow_bwd);
-  gcost[0][0] = cost_fwd;
-  gcost[0][1] = cost_bwd;
   size_t off = lay.grids;
   for (int lv = 1; lv < L; ++lv) {
     const size_t cells = (size_t)ceil_div(W, 1 << lv) * ceil_div(H, 1 << lv);
@@ -1158,6 +1171,10 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     }
     off = align256(off + 2 * cells * 2 * sizeof(uint32_t));
   }
+  gflow[lmin][0] = reinterpret_cast<int32_t *>(flow_fwd);
+  gflow[lmin][1] = reinterpret_cast<int32_t *>(flow_bwd);
+  gcost[lmin][0] = cost_fwd;
+  gcost[lmin][1] = cost_bwd;
 
   // exact NN seeds of the coarsest grid, both directions
   const int nc = 1 << (L - 1);
@@ -1171,9 +1188,22 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   nn.Wc = ceil_div(W, nc);
   nn.M = (int)lay.M;
   nn.N = (int)lay.N;
+  // references: every pixel, or (Fast x2) the pixels with even x and y
+  const uint8_t *refs[2] = {desc1[0], desc1[1]};
+  if (params->fast_x2) {
+    nn.N = ceil_div(W, 2) * ceil_div(H, 2);
+    for (int im = 0; im < 2; ++im) {
+      uint8_t *ev = reinterpret_cast<uint8_t *>(base + lay.desc1e) + (size_t)im * nn.N * 16;
+      if ((e = ffh::launch_gather_even(desc1[im], ev, W, H, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      refs[im] = ev;
+    }
+  }
   for (int dr = 0; dr < nd; ++dr)
-    nn.dir[dr] = {desc1[dr], desc1[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
+    nn.dir[dr] = {desc1[dr], refs[dr ^ 1], nb + (size_t)dr * lay.Npad, keys + (size_t)dr * lay.M};
   if ((e = ffh::launch_nn(nn, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  if (params->fast_x2 && params->nn_l <= 1)
+    for (int dr = 0; dr < nd; ++dr)
+      if ((e = ffh::launch_remap_even(keys + (size_t)dr * lay.M, nn.M, W, s)) != hipSuccess) return FF_ERR_LAUNCH;
   if (params->nn_l > 1) {
     // seed rerank among the nn_l nearest pixels (Eq. 1, Eq. 4)
     ffh::TopLArgs tl{};
@@ -1185,11 +1215,12 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     tl.Wc = nn.Wc;
     tl.M = nn.M;
     tl.N = nn.N;
+    tl.even_refs = params->fast_x2;
     const uint64_t *cand[2];
     for (int dr = 0; dr < nd; ++dr) {
       ffh::TopLDir &d = tl.dir[dr];
       d.Dq = desc1[dr];
-      d.Dr = desc1[dr ^ 1];
+      d.Dr = refs[dr ^ 1];
       d.nb = nb + (size_t)dr * lay.Npad;
       d.nn_key = keys + (size_t)dr * lay.M;
       d.keys = reinterpret_cast<uint64_t *>(base + lay.topl + (size_t)dr * ffh::topl_scratch_bytes((int)lay.M));
@@ -1227,7 +1258,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       k.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
       k.dir[dr].stream_id = dr;
     }
-    for (int lv = L - 1; lv >= 0; --lv) {
+    for (int lv = L - 1; lv >= lmin; --lv) {
       for (int dr = 0; dr < nd; ++dr) {
         k.dir[dr].Da = desc[dr][lv];
         k.dir[dr].Db = desc[dr ^ 1][lv];
@@ -1255,6 +1286,9 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         return FF_ERR_LAUNCH;
     }
     if (fwd_only) return FF_OK;
+    if (params->fast_x2)
+      return from_hip(ffh::launch_consistency_grid(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, 2, params->eps,
+                                                   keep_fwd, keep_bwd, s));
     return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                             keep_bwd, s));
   }
@@ -1270,7 +1304,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     a.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
     a.dir[dr].stream_id = dr;
   }
-  for (int lv = L - 1; lv >= 0; --lv) {
+  for (int lv = L - 1; lv >= lmin; --lv) {
     for (int dr = 0; dr < nd; ++dr) {
       a.dir[dr].Da = desc[dr][lv];
       a.dir[dr].Db = desc[dr ^ 1][lv];
@@ -1284,6 +1318,9 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
   if (fwd_only) return FF_OK;
+  if (params->fast_x2)
+    return from_hip(ffh::launch_consistency_grid(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, 2, params->eps,
+                                                 keep_fwd, keep_bwd, s));
   return from_hip(ffh::launch_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, params->eps, keep_fwd,
                                           keep_bwd, s, sb));
 }

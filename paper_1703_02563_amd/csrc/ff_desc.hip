@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
       w[g] = v;
     }
     const uint4 d = make_uint4(w[0], w[1], w[2], w[3]);
-    out[c] = d;
+    if (jb.desc) out[c] = d;
     if (jb.compact && xr >= 0 && xr < W && yr >= 0 && yr < H)
       reinterpret_cast<uint4 *>(jb.compact)[(size_t)yr * W + xr] = d;
   }

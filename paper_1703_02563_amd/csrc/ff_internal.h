@@ -16,7 +16,7 @@ struct DescJob {
   const uint8_t *img;
   uint16_t *hsum;
   uint8_t *blurred;
-  uint8_t *desc;     // padded, phase-ordered map (see desc_index)
+  uint8_t *desc;     // padded, phase-ordered map (see desc_index); nullable: only the copies below
   uint8_t *compact;  // nullable: row-major [H][W][16] copy (the NN seed's input)
   uint8_t *wform;    // nullable: weight-class row map (see wform_index)
   int n;
@@ -62,11 +62,17 @@ struct TopLArgs {
   TopLDir dir[kMaxDirs];
   int ndir, l;
   int W, H, nc, Wc, M, N;
+  int even_refs;  // 1: the references are the even-pixel subset (launch_gather_even)
 };
 struct TopLPrev {
   const uint64_t *key[kMaxDirs];
 };
 size_t topl_scratch_bytes(int M);  // the keys of passes 1 .. kTopLMax - 1 of one direction
+// Flow Fields+ Fast x2: the level-1 descriptors of the pixels with even x
+// and y ([ceil(H/2)][ceil(W/2)][16], the NN's references), and the NN keys
+// over that subset turned into keys naming image pixels.
+hipError_t launch_gather_even(const uint8_t *desc1, uint8_t *out, int W, int H, hipStream_t stream);
+hipError_t launch_remap_even(uint64_t *keys, int M, int W, hipStream_t stream);
 hipError_t launch_topl(const TopLArgs &args, hipStream_t stream);
 
 // Launch tables of the temporally blocked level kernels, per scale log2 n
@@ -290,6 +296,10 @@ hipError_t launch_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t
 hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int16_t *fb1, const uint32_t *cb1,
                                const int16_t *fb2, const uint32_t *cb2, int W, int H, float eps, uint8_t *keep,
                                hipStream_t stream);
+// Fields on the grid of scale n, one match per n x n region (Fast x2).
+hipError_t launch_consistency_grid(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
+                                  int W, int H, int n, float eps, uint8_t *keep_a, uint8_t *keep_b,
+                                  hipStream_t stream);
 // sb: flows in units of 1/2^sb pixel (0: whole pixels)
 hipError_t launch_consistency(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
                               int W, int H, float eps, uint8_t *keep_a, uint8_t *keep_b, hipStream_t stream,

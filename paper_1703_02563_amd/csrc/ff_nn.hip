@@ -340,6 +340,28 @@ __device__ __forceinline__ int query_norm(const uint8_t *Dq, int W, int nc, int 
   return s;
 }
 
+// Reference index of the even-pixel subset (Flow Fields+ Fast x2: pixel
+// (2a, 2b) is entry b * W2 + a) -> pixel index of the image.
+__device__ __forceinline__ uint32_t even_pixel(uint32_t q, int W2, int W) {
+  return (q / (uint32_t)W2) * 2u * (uint32_t)W + (q % (uint32_t)W2) * 2u;
+}
+
+// Level-1 descriptors of the pixels with even x and y, row-major [H2][W2].
+__global__ __launch_bounds__(256) void k_gather_even(const uint4 *src, uint4 *dst, int W, int H) {
+  const int W2 = (W + 1) >> 1, H2 = (H + 1) >> 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= W2 * H2) return;
+  dst[k] = src[(size_t)(k / W2) * 2 * W + (k % W2) * 2];
+}
+
+// NN keys over the even-pixel subset -> keys naming image pixels.
+__global__ __launch_bounds__(256) void k_remap_even(uint64_t *keys, int M, int W) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const uint64_t k = keys[m];
+  if (k != ~0ull) keys[m] = (k & 0xFFFFFFFF00000000ull) | even_pixel((uint32_t)k, (W + 1) >> 1, W);
+}
+
 // Ranked candidates with the squared distance itself: cand[m * l + k] =
 // (dist << 32) | q of pass k, ~0 for a pass that found no reference of the
 // image (padding references, index >= N, or none left).
@@ -351,8 +373,10 @@ __global__ __launch_bounds__(256) void k_topl_assemble(ffh::TopLArgs a) {
   for (int k = 0; k < a.l; ++k) {
     const uint64_t rel = k == 0 ? d.nn_key[m] : d.keys[(size_t)(k - 1) * a.M + m];
     uint64_t out = ~0ull;
-    if (rel != ~0ull && (int64_t)(uint32_t)rel < (int64_t)a.N)
-      out = ((uint64_t)(uint32_t)((int)(uint32_t)(rel >> 32) - (1 << 20) + na) << 32) | (uint32_t)rel;
+    if (rel != ~0ull && (int64_t)(uint32_t)rel < (int64_t)a.N) {
+      const uint32_t q = a.even_refs ? even_pixel((uint32_t)rel, (a.W + 1) >> 1, a.W) : (uint32_t)rel;
+      out = ((uint64_t)(uint32_t)((int)(uint32_t)(rel >> 32) - (1 << 20) + na) << 32) | q;
+    }
     d.cand[(size_t)m * a.l + k] = out;
   }
 }
@@ -438,6 +462,18 @@ hipError_t launch_nn(const NNArgs &args_in, hipStream_t stream) {
   return hipGetLastError();
 }
 
+
+hipError_t launch_gather_even(const uint8_t *desc1, uint8_t *out, int W, int H, hipStream_t stream) {
+  const int n2 = ((W + 1) >> 1) * ((H + 1) >> 1);
+  hipLaunchKernelGGL(k_gather_even, dim3((n2 + 255) / 256), dim3(256), 0, stream,
+                     reinterpret_cast<const uint4 *>(desc1), reinterpret_cast<uint4 *>(out), W, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_remap_even(uint64_t *keys, int M, int W, hipStream_t stream) {
+  hipLaunchKernelGGL(k_remap_even, dim3((M + 255) / 256), dim3(256), 0, stream, keys, M, W);
+  return hipGetLastError();
+}
 
 size_t topl_scratch_bytes(int M) {
   return (((size_t)(kTopLMax - 1) * M * sizeof(uint64_t)) + 255) & ~(size_t)255;

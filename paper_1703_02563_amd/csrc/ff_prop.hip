@@ -390,6 +390,37 @@ __global__ __launch_bounds__(256) void k_consistency(const int32_t *fa0, const u
   keep[k] = out;
 }
 
+// The check on fields of the grid of scale n (one match per n x n region,
+// Flow Fields+ Fast x2): cell (i, j) is pixel (i n, j n); the backward match
+// of its target t is that of the region holding t, cell (t.x / n, t.y / n).
+// blockIdx.z = 1: roles swapped (the mask of field b).
+__global__ __launch_bounds__(256) void k_consistency_grid(const int32_t *fa0, const uint32_t *ca0,
+                                                          const int32_t *fb0, const uint32_t *cb0, int W, int H,
+                                                          int n, double eps2, uint8_t *keep_a, uint8_t *keep_b) {
+  const int Wn = (W + n - 1) / n, Hn = (H + n - 1) / n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= Wn || j >= Hn) return;
+  const bool swap = blockIdx.z == 1;
+  const int32_t *fa = swap ? fb0 : fa0, *fb = swap ? fa0 : fb0;
+  const uint32_t *ca = swap ? cb0 : ca0, *cb = swap ? ca0 : cb0;
+  uint8_t *keep = swap ? keep_b : keep_a;
+  const size_t k = (size_t)j * Wn + i;
+  uint8_t out = 0;
+  if (ca[k] != kUnset) {
+    const int32_t f = fa[k];
+    const int tx = i * n + ffk::flow_x(f), ty = j * n + ffk::flow_y(f);
+    if (tx >= 0 && tx < W && ty >= 0 && ty < H) {
+      const size_t kq = (size_t)(ty / n) * Wn + (size_t)(tx / n);
+      if (cb[kq] != kUnset) {
+        const int32_t g = fb[kq];
+        const int64_t dx = ffk::flow_x(f) + ffk::flow_x(g), dy = ffk::flow_y(f) + ffk::flow_y(g);
+        out = (double)(dx * dx + dy * dy) < eps2;
+      }
+    }
+  }
+  keep[k] = out;
+}
+
 // Against two backward fields (Sec. 3.7): kept iff the check above passes
 // for both (their generator seeds, and possibly patch radii, differ).
 __global__ __launch_bounds__(256) void k_consistency2(const int32_t *fa, const uint32_t *ca, const int32_t *fb1,
@@ -596,6 +627,16 @@ hipError_t launch_consistency2(const int16_t *fa, const uint32_t *ca, const int1
   hipLaunchKernelGGL(k_consistency2, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
                      reinterpret_cast<const int32_t *>(fb1), cb1, reinterpret_cast<const int32_t *>(fb2), cb2, W, H,
                      eps2, keep);
+  return hipGetLastError();
+}
+
+hipError_t launch_consistency_grid(const int16_t *fa, const uint32_t *ca, const int16_t *fb, const uint32_t *cb,
+                                  int W, int H, int n, float eps, uint8_t *keep_a, uint8_t *keep_b,
+                                  hipStream_t stream) {
+  const int Wn = (W + n - 1) / n, Hn = (H + n - 1) / n;
+  dim3 grid((Wn + 255) / 256, Hn, keep_b ? 2 : 1);
+  hipLaunchKernelGGL(k_consistency_grid, grid, dim3(256), 0, stream, reinterpret_cast<const int32_t *>(fa), ca,
+                     reinterpret_cast<const int32_t *>(fb), cb, W, H, n, (double)eps * (double)eps, keep_a, keep_b);
   return hipGetLastError();
 }
 

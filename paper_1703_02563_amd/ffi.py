@@ -49,6 +49,7 @@ class FFParams(C.Structure):
         ("tuning", C.POINTER(FFTuning)),
         ("nn_l", C.c_int32),
         ("raster", C.c_int32),
+        ("fast_x2", C.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ _SIGS = {
                                    _P, _P]),
     "ff_consistency_filter": (C.c_int, [_P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_consistency_filter2": (C.c_int, [_P, _P, _P, _P, _P, _P, _I32, _I32, C.c_float, _P, _P]),
+    "ff_consistency_filter_grid": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_consistency_filter_sub": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.c_float, _P, _P, _P]),
     "ff_sparsify": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P]),
     "ff_region_filter_scratch_bytes": (C.c_size_t, [_I32, _I32]),

@@ -66,11 +66,12 @@ class Params:
     tuning: Tuning | None = None  # launch tables of the calls (None: the built-in tables)
     nn_l: int = 1  # seed candidates: the nn_l nearest pixels, reranked by patch cost (Eq. 1 / Eq. 4)
     raster: bool = False  # propagation steps in serial order (anti-diagonal wavefronts)
+    fast_x2: bool = False  # Flow Fields+ Fast x2: no finest scale, outputs on the grid of scale 2
 
     def to_c(self) -> FFParams:
         p = FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
                      self.plus_iters, self.Rp_num, self.fine_iters, self.subpixel, None, self.nn_l,
-                     int(bool(self.raster)))
+                     int(bool(self.raster)), int(bool(self.fast_x2)))
         if self.tuning is not None:
             p._tuning = self.tuning.to_c()  # kept alive with the struct that points at it
             p.tuning = ctypes.pointer(p._tuning)
@@ -270,6 +271,19 @@ def consistency_filter(flow_a, cost_a, flow_b, cost_b, eps: float = 1.0, both: b
     return keep_a, keep_b
 
 
+def consistency_filter_grid(flow_a, cost_a, flow_b, cost_b, W: int, H: int, n: int, eps: float = 1.0,
+                            both: bool = True):
+    """Consistency of fields on the grid of scale n (one match per n x n
+    region) of a W x H image."""
+    Hn, Wn = cost_a.shape
+    keep_a = torch.empty((Hn, Wn), dtype=torch.uint8, device=cost_a.device)
+    keep_b = torch.empty((Hn, Wn), dtype=torch.uint8, device=cost_a.device) if both else None
+    check(lib().ff_consistency_filter_grid(_ptr(flow_a, torch.int16), _ptr(cost_a, torch.int32),
+                                           _ptr(flow_b, torch.int16), _ptr(cost_b, torch.int32), W, H, n, eps,
+                                           _ptr(keep_a), _ptr(keep_b), _stream()), "ff_consistency_filter_grid")
+    return keep_a, keep_b
+
+
 def consistency_filter_sub(flow_a, cost_a, flow_b, cost_b, subpixel: int, eps: float = 1.0, both: bool = True):
     """Consistency of fields with flows in units of 1/2^subpixel pixel."""
     H, W = cost_a.shape
@@ -352,13 +366,14 @@ class FlowFields:
             raise ffi.FlowFieldsError(ffi.FF_ERR_ARG, "ff_workspace_bytes")
         dev = torch.device(device)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        Ho, Wo = ((H + 1) // 2, (W + 1) // 2) if params.fast_x2 else (H, W)  # Fast x2: grid of scale 2
         self.out = {
-            "flow_fwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
-            "flow_bwd": torch.empty((H, W, 2), dtype=torch.int16, device=dev),
-            "cost_fwd": torch.empty((H, W), dtype=torch.int32, device=dev),
-            "cost_bwd": torch.empty((H, W), dtype=torch.int32, device=dev),
-            "keep_fwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
-            "keep_bwd": torch.empty((H, W), dtype=torch.uint8, device=dev),
+            "flow_fwd": torch.empty((Ho, Wo, 2), dtype=torch.int16, device=dev),
+            "flow_bwd": torch.empty((Ho, Wo, 2), dtype=torch.int16, device=dev),
+            "cost_fwd": torch.empty((Ho, Wo), dtype=torch.int32, device=dev),
+            "cost_bwd": torch.empty((Ho, Wo), dtype=torch.int32, device=dev),
+            "keep_fwd": torch.empty((Ho, Wo), dtype=torch.uint8, device=dev),
+            "keep_bwd": torch.empty((Ho, Wo), dtype=torch.uint8, device=dev),
             "n_evals": torch.zeros(2, dtype=torch.int64, device=dev),
         }
         if not backward:
