@@ -234,33 +234,45 @@ def batched_throughput(ff, torch, reps):
 
 def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     """Flow Fields+ (Sec. 3.3: 4 steps at R+ = 2R, then 8 at R on every scale),
-    Flow Fields+ Fast (Sec. 3.4: only 4 steps at R on the finest scale) and
-    the original schedule checked against two backward fields (Sec. 3.7) on
-    the same pair and launch tables: Mpix/s and quality."""
+    Flow Fields+ Fast (Sec. 3.4: only 4 steps at R on the finest scale), Fast
+    x2 (no finest scale), the rerank of 8 seed candidates (Eq. 4), the serial
+    propagation order, the subpixel form and the original schedule checked
+    against two backward fields (Sec. 3.7) on the same pair and launch
+    tables: Mpix/s and quality."""
     import dataclasses
 
     import numpy as np
 
     from ffgen import epe_stats
     res = {}
-    for name, kw in (("plus", dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num)),
-                     ("plus_fast", dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num, fine_iters=4))):
+    plus = dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num)
+    for name, kw, n_reps in (("plus", plus, reps), ("plus_fast", dict(plus, fine_iters=4), reps),
+                             # Sec. 3.4: no finest scale, 4 x R on scale 2, one match per 2x2 region
+                             ("plus_fast_x2", dict(plus, fine_iters=4, fast_x2=True), reps),
+                             # Eq. 4 with the paper's leaf size l = 8 (Sec. 4.1)
+                             ("nn_l8", dict(nn_l=8), 5),
+                             # serial propagation order (Sec. 3.1), exact by anti-diagonal wavefronts
+                             ("raster", dict(raster=True), 2)):
         prm = dataclasses.replace(params, **kw)
         H, W = img1.shape
         runner = ff.FlowFields(W, H, prm, device=img1.device)
-        for _ in range(3):
+        for _ in range(1 if prm.raster else 3):
             runner(img1, img2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(reps):
+        for _ in range(n_reps):
             runner(img1, img2)
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / reps * 1e3
+        ms = (time.perf_counter() - t0) / n_reps * 1e3
         out = runner.out
-        q = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt, pair.occ, keep=out["keep_fwd"].cpu().numpy())
+        # Fast x2's fields sit on the grid of scale 2: judged at its cells' pixels
+        g = 2 if prm.fast_x2 else 1
+        q = epe_stats(out["flow_fwd"].cpu().numpy(), pair.flow_gt[::g, ::g], pair.occ[::g, ::g],
+                      keep=out["keep_fwd"].cpu().numpy())
         res[name] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
                      "steps": f"{prm.plus_iters} x R+ then {prm.iters} x R"
-                              + (f", finest {prm.fine_iters} x R" if prm.fine_iters else ""),
+                              + (f", finest {prm.fine_iters} x R" if prm.fine_iters else "")
+                              + (", finest scale skipped, grid of scale 2" if prm.fast_x2 else ""),
                      "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
                      "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
                      "kept_epe": round(q["kept_epe"], 4)}
