@@ -46,8 +46,14 @@ def lib():
         L.or_nn_topl.argtypes = [P, P, i, i, i, i, P, P, i]
         L.or_init_coarse_l.argtypes = [P, i, P, P, i, i, i, i, P, P, P]
         L.or_propagate_raster.argtypes = [P, P, i, i, i, i, i, P, P, P]
-        L.or_flow_fields_x.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P, P,
-                                       P, P]
+        L.or_flow_fields_x.argtypes = [P, P, i, i, i, i, i, i, i, i, i, i, i, i, i, i, i, dbl, u64, i, P, P, P, P,
+                                       P, P, P]
+        L.or_make_stages.argtypes = [i, i, i, P, P]
+        L.or_make_stages.restype = i
+        L.or_rescore.argtypes = [P, P, i, i, i, i, i, P, P, P]
+        L.or_seed_level_m.argtypes = [P, P, P, P, i, i, i, i, i, P, P, P]
+        L.or_propagate_m.argtypes = [P, P, i, i, i, i, i, i, P, P, P, i]
+        L.or_random_search_m.argtypes = [P, P, i, i, i, i, i, i, u64, i, i, i, P, P, P, i]
         L.or_nn_topl_step.argtypes = [P, P, i, i, i, i, i, P, P, i]
         L.or_consistency_grid.argtypes = [P, P, P, P, i, i, i, dbl, P]
         L.or_flow_fields_x.restype = i
@@ -198,6 +204,59 @@ def propagate_raster(Da, Db, n: int, pass_: int, flow, cost_, r: int = 3):
     return flow, cost_, int(ne[0])
 
 
+def stages(levels: int, fast_x2: bool = False, subscales: bool = False):
+    """(grid scale n, patch scale m) of every stage of the schedule, coarse
+    to fine."""
+    n = np.zeros(16, np.int32)
+    m = np.zeros(16, np.int32)
+    k = lib().or_make_stages(levels, int(bool(fast_x2)), int(bool(subscales)), _p(n), _p(m))
+    return [(int(a), int(b)) for a, b in zip(n[:k], m[:k])]
+
+
+def rescore(Da, Db, n: int, m: int, flow, cost_, r: int = 3):
+    """Same grid, new patch scale: every set cell's cost at patch scale m;
+    returns (cost, n_evals)."""
+    H, W = Da.shape[:2]
+    flow = np.ascontiguousarray(flow, np.int16)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_rescore(_p(Da), _p(Db), W, H, n, m, r, _p(flow), _p(cost_), _p(ne))
+    return cost_, int(ne[0])
+
+
+def seed_level_m(cflow, ccost, Da, Db, n: int, m: int, r: int = 3):
+    """Hand-over to the grid of scale n with costs at patch scale m."""
+    H, W = Da.shape[:2]
+    Wn, Hn = cells(W, H, n)
+    flow = np.empty((Hn, Wn, 2), np.int16)
+    cost_ = np.empty((Hn, Wn), np.uint32)
+    ne = np.zeros(1, np.uint64)
+    cflow = np.ascontiguousarray(cflow, np.int16)
+    ccost = np.ascontiguousarray(ccost, np.uint32)
+    lib().or_seed_level_m(_p(cflow), _p(ccost), _p(Da), _p(Db), W, H, n, m, r, _p(flow), _p(cost_), _p(ne))
+    return flow, cost_, int(ne[0])
+
+
+def propagate_m(Da, Db, n: int, m: int, pass_: int, flow, cost_, r: int = 3, nthreads: int = 1):
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_propagate_m(_p(Da), _p(Db), W, H, n, m, r, pass_, _p(flow), _p(cost_), _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
+def random_search_m(Da, Db, n: int, m: int, Rn: int, seed: int, stream: int, gen: int, pass_: int, flow, cost_,
+                    r: int = 3, nthreads: int = 1):
+    H, W = Da.shape[:2]
+    flow = np.array(flow, np.int16, order="C", copy=True)
+    cost_ = np.array(cost_, np.uint32, order="C", copy=True)
+    ne = np.zeros(1, np.uint64)
+    lib().or_random_search_m(_p(Da), _p(Db), W, H, n, m, r, Rn, seed, stream, gen, pass_, _p(flow), _p(cost_),
+                             _p(ne), nthreads)
+    return flow, cost_, int(ne[0])
+
+
 def rs_radius(n: int, R_num: int, R_den: int) -> int:
     return int(lib().or_rs_radius(n, R_num, R_den))
 
@@ -276,7 +335,7 @@ def sparsify(fa, keep, fb1, fb2=None, q: int = 3, e: int = 1) -> np.ndarray:
 def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int = 1, R_den: int = 1,
                 eps: float = 1.0, seed: int = 12345, nthreads: int = 1, plus_iters: int = 0, Rp_num: int = 0,
                 fine_iters: int = 0, subpixel: int = 0, nn_l: int = 1, raster: bool = False,
-                fast_x2: bool = False) -> dict:
+                fast_x2: bool = False, subscales: bool = False) -> dict:
     """The whole schedule on one pair.  plus_iters > 0: Flow Fields+ (P steps
     at R^+ = Rp_num / R_den before the `iters` steps at R); fine_iters > 0:
     the finest scale runs only that many steps at R (Flow Fields+ Fast);
@@ -284,7 +343,8 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
     of cost_sub (scaled by 4^s); nn_l > 1: seeds reranked among the nn_l
     nearest pixels (Eq. 4); raster: serial-order propagation steps; fast_x2:
     Flow Fields+ Fast x2 (finest scale skipped, seeds among the even pixels,
-    fields and masks on the grid of scale 2, fine_iters steps there)."""
+    fields and masks on the grid of scale 2, fine_iters steps there);
+    subscales: the sub-scale stages of Sec. 3.3 (see stages())."""
     img1, img2 = _u8(img1), _u8(img2)
     H, W = img1.shape
     Ho, Wo = (-(-H // 2), -(-W // 2)) if fast_x2 else (H, W)
@@ -294,10 +354,10 @@ def flow_fields(img1, img2, levels: int, iters: int, radius: int = 3, R_num: int
         "keep_fwd": np.empty((Ho, Wo), np.uint8), "keep_bwd": np.empty((Ho, Wo), np.uint8),
     }
     ne = np.zeros(2, np.uint64)
-    if nn_l != 1 or raster or fast_x2:
+    if nn_l != 1 or raster or fast_x2 or subscales:
         rc = lib().or_flow_fields_x(_p(img1), _p(img2), W, H, levels, iters, radius, R_num, R_den, plus_iters,
                                     Rp_num, fine_iters, subpixel, nn_l, int(bool(raster)), int(bool(fast_x2)),
-                                    float(eps), seed, nthreads,
+                                    int(bool(subscales)), float(eps), seed, nthreads,
                                     _p(out["flow_fwd"]), _p(out["flow_bwd"]), _p(out["cost_fwd"]),
                                     _p(out["cost_bwd"]), _p(out["keep_fwd"]), _p(out["keep_bwd"]), _p(ne))
     elif subpixel:

@@ -59,8 +59,10 @@
  *               n = 2^(L-1) .. 1, T propagation steps per level with T-1
  *               random-search steps between them, forward and backward;
  *               optionally the Flow Fields+ steps (Sec. 3.3: P steps at
- *               R^+ first), the Fast finest scale (Sec. 3.4) and Fast x2
- *               (finest scale skipped, R30).
+ *               R^+ first), the Fast finest scale (Sec. 3.4), Fast x2
+ *               (finest scale skipped, R30) and sub-scales (Sec. 3.3, R31:
+ *               patch scales 3n/2 on the grid of scale n; rescore moves a
+ *               grid to another patch scale).
  *
  * Layouts: images uint8 [H][W]; descriptors uint8 [H][W][16]; a level grid
  * of scale n has ceil(W/n) x ceil(H/n) cells, cell (i, j) <-> pixel
@@ -368,7 +370,7 @@ void or_nn_topl(const uint8_t *Da1, const uint8_t *Db1, int W, int H, int nc, in
  * with the lowest E_nc(p, q - p), the earlier rank on equal cost; every
  * candidate costs one evaluation.  F(p) = q - p. */
 static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, int l, const void *Da, const void *Db, int W,
-                          int H, int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+                          int H, int nc, int m, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     for (int j = 0; j < Hc; ++j)
@@ -380,7 +382,7 @@ static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, int l, c
                 int32_t q = best_idx[(size_t)k * l + c];
                 if (q < 0) continue;
                 int fx = (q % W - x) * (1 << s), fy = (q / W - y) * (1 << s);  /* integer seed, in 1/2^s pixel */
-                uint32_t e = E(Da, Db, W, H, nc, r, x, y, fx, fy, s);
+                uint32_t e = E(Da, Db, W, H, m, r, x, y, fx, fy, s);
                 *n_evals += 1;
                 if (!have || e < bc) { bc = e; bfx = fx; bfy = fy; have = 1; }
             }
@@ -393,13 +395,13 @@ static void init_coarse_g(or_cost_fn E, int s, const int32_t *best_idx, int l, c
 void or_init_coarse(const int32_t *best_idx, const uint8_t *Da, const uint8_t *Db, int W, int H,
                     int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    init_coarse_g(cost_u8, 0, best_idx, 1, Da, Db, W, H, nc, r, flow, cost, n_evals);
+    init_coarse_g(cost_u8, 0, best_idx, 1, Da, Db, W, H, nc, nc, r, flow, cost, n_evals);
 }
 
 void or_init_coarse_l(const int32_t *cand_idx, int l, const uint8_t *Da, const uint8_t *Db, int W, int H,
                       int nc, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    init_coarse_g(cost_u8, 0, cand_idx, l, Da, Db, W, H, nc, r, flow, cost, n_evals);
+    init_coarse_g(cost_u8, 0, cand_idx, l, Da, Db, W, H, nc, nc, r, flow, cost, n_evals);
 }
 
 /* Hand-over from scale 2n to scale n (Sec. 3.2): cell (i, j) with i and j
@@ -408,7 +410,8 @@ void or_init_coarse_l(const int32_t *cand_idx, int l, const uint8_t *Da, const u
  * cost is re-evaluated with E_n.  All other cells start UNSET and receive a
  * value in the first propagation step. */
 static void seed_level_g(or_cost_fn E, int s, const int16_t *cflow, const uint32_t *ccost, const void *Da,
-                         const void *Db, int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+                         const void *Db, int W, int H, int n, int m, int r, int16_t *flow, uint32_t *cost,
+                         uint64_t *n_evals)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), Wc = ceil_div(W, 2 * n);
     for (int j = 0; j < Hn; ++j)
@@ -423,7 +426,7 @@ static void seed_level_g(or_cost_fn E, int s, const int16_t *cflow, const uint32
             int fx = cflow[2 * kc], fy = cflow[2 * kc + 1];
             flow[2 * k] = (int16_t)fx;
             flow[2 * k + 1] = (int16_t)fy;
-            cost[k] = E(Da, Db, W, H, n, r, i * n, j * n, fx, fy, s);
+            cost[k] = E(Da, Db, W, H, m, r, i * n, j * n, fx, fy, s);
             *n_evals += 1;
         }
 }
@@ -431,7 +434,7 @@ static void seed_level_g(or_cost_fn E, int s, const int16_t *cflow, const uint32
 void or_seed_level(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db,
                    int W, int H, int n, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    seed_level_g(cost_u8, 0, cflow, ccost, Da, Db, W, H, n, r, flow, cost, n_evals);
+    seed_level_g(cost_u8, 0, cflow, ccost, Da, Db, W, H, n, n, r, flow, cost, n_evals);
 }
 
 /* Source cells of propagation direction d (Eq. 2 for d = 0; the other three
@@ -449,8 +452,8 @@ static void prop_sources(int d, int *hdi, int *vdj)
  * cells, by E_n with strict improvement.  Run as two half-sweeps: first all
  * cells with (i+j) odd, then all with (i+j) even; a cell only reads cells of
  * the other colour, so the result does not depend on the visiting order. */
-static void propagate_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r, int pass,
-                        int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
+static void propagate_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int m, int r,
+                        int pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
     prop_sources(pass & 3, &hdi, &vdj);
@@ -474,7 +477,7 @@ static void propagate_g(or_cost_fn E, int s, const void *Da, const void *Db, int
                     int fx = flow[2 * ks], fy = flow[2 * ks + 1];
                     if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
                     if (!target_in(W, H, x, y, fx, fy, s)) continue;
-                    uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
+                    uint32_t e = E(Da, Db, W, H, m, r, x, y, fx, fy, s);
                     cnt += 1;
                     if (e < bc) { bc = e; bfx = fx; bfy = fy; }
                 }
@@ -489,7 +492,7 @@ static void propagate_g(or_cost_fn E, int s, const void *Da, const void *Db, int
 void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
                   int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
-    propagate_g(cost_u8, 0, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
+    propagate_g(cost_u8, 0, Da, Db, W, H, n, n, r, pass, flow, cost, n_evals, nthreads);
 }
 
 /* One propagation step (Eq. 2) in the serial order the paper asks for: a
@@ -502,8 +505,8 @@ void or_propagate(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int
  * of the checkerboard step (own, horizontal, vertical; strictly lower wins;
  * UNSET, held and out-of-image candidates skipped), reading the sources'
  * values of this step. */
-static void propagate_raster_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r,
-                               int pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+static void propagate_raster_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int m,
+                               int r, int pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
     int Wn = ceil_div(W, n), Hn = ceil_div(H, n), hdi, vdj;
     prop_sources(pass & 3, &hdi, &vdj);
@@ -522,7 +525,7 @@ static void propagate_raster_g(or_cost_fn E, int s, const void *Da, const void *
                 int fx = flow[2 * ks], fy = flow[2 * ks + 1];
                 if (bc != OR_UNSET && fx == bfx && fy == bfy) continue;
                 if (!target_in(W, H, x, y, fx, fy, s)) continue;
-                uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
+                uint32_t e = E(Da, Db, W, H, m, r, x, y, fx, fy, s);
                 *n_evals += 1;
                 if (e < bc) { bc = e; bfx = fx; bfy = fy; }
             }
@@ -536,7 +539,7 @@ static void propagate_raster_g(or_cost_fn E, int s, const void *Da, const void *
 void or_propagate_raster(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int pass,
                          int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    propagate_raster_g(cost_u8, 0, Da, Db, W, H, n, r, pass, flow, cost, n_evals);
+    propagate_raster_g(cost_u8, 0, Da, Db, W, H, n, n, r, pass, flow, cost, n_evals);
 }
 
 /* SplitMix64 output mixer (Steele, Lea, Flood 2014). */
@@ -568,7 +571,7 @@ void or_rs_offset(uint64_t seed, int stream, int level, int pass, int j, int i, 
 /* One random-search step (Sec. 3.1): every set cell tries its flow plus a
  * random offset and keeps it if E_n strictly decreases.  Offset (0, 0) and
  * targets outside the image are skipped. */
-static void random_search_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int r,
+static void random_search_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int m, int r,
                             int Rn, uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
                             uint64_t *n_evals, int nthreads)
 {
@@ -587,7 +590,7 @@ static void random_search_g(or_cost_fn E, int s, const void *Da, const void *Db,
             if (ox == 0 && oy == 0) continue;
             int fx = flow[2 * k] + ox, fy = flow[2 * k + 1] + oy;
             if (!target_in(W, H, x, y, fx, fy, s)) continue;
-            uint32_t e = E(Da, Db, W, H, n, r, x, y, fx, fy, s);
+            uint32_t e = E(Da, Db, W, H, m, r, x, y, fx, fy, s);
             cnt += 1;
             if (e < cost[k]) {
                 cost[k] = e;
@@ -602,7 +605,7 @@ void or_random_search(const uint8_t *Da, const uint8_t *Db, int W, int H, int n,
                       uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
                       uint64_t *n_evals, int nthreads)
 {
-    random_search_g(cost_u8, 0, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals, nthreads);
+    random_search_g(cost_u8, 0, Da, Db, W, H, n, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals, nthreads);
 }
 
 /* Forward-backward consistency (Sec. 3.7): keep pixel p of field a iff it is
@@ -782,45 +785,118 @@ void or_sparsify(const int16_t *fa, const uint8_t *keep, const int16_t *fb1, con
 /* R_n = floor(R * n) with R = R_num / R_den (R6). */
 int or_rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
 
-/* Steps of one scale.  The original schedule (Sec. 3.2): T propagation
- * steps, a random search at R_n after each but the last.  Flow Fields+
- * (Sec. 3.3): first P steps whose random searches use R_n^+ = R^+ n, then T
- * steps at R_n; random searches sit only between two steps of the same
+/* The scales of the schedule, coarse to fine (Sec. 3.2): stage k has the
+ * grid scale n (the cells p = (i n, j n) that propagate and search) and the
+ * patch scale m (patch spacing, blur and random-search distance).  Without
+ * sub-scales m = n for n = 2^(L-1), ..., 2^lmin.  With sub-scales (Sec.
+ * 3.3, table of scales and sub-scales, R31) every scale n >= 2 below the
+ * coarsest is preceded, on the same grid, by the sub-scale m = 3n/2: for
+ * L = 4 the stages are (8,8) (4,6) (4,4) (2,3) (2,2) (1,1).  gen is the
+ * generator's level field: log2 n, plus 16 on a sub-scale stage. */
+typedef struct {
+    int n, m, gen;
+} or_stage;
+
+int or_make_stages(int L, int lmin, int sub, int *stage_n, int *stage_m)
+{
+    int k = 0;
+    for (int level = L - 1; level >= lmin; --level) {
+        int n = 1 << level;
+        if (sub && level < L - 1 && n >= 2) {
+            stage_n[k] = n;
+            stage_m[k] = 3 * n / 2;
+            ++k;
+        }
+        stage_n[k] = n;
+        stage_m[k] = n;
+        ++k;
+    }
+    return k;
+}
+
+/* Steps of one stage.  The original schedule (Sec. 3.2): T propagation
+ * steps, a random search at R_m after each but the last.  Flow Fields+
+ * (Sec. 3.3): first P steps whose random searches use R_m^+ = R^+ m, then T
+ * steps at R_m; random searches sit only between two steps of the same
  * group (P - 1 and T - 1 of them), and the step index t, which sets the
  * direction t mod 4 and keys the generator, runs on over both groups.
- * Flow Fields+ Fast (Sec. 3.4): the finest scale run (level lmin) runs only
- * Tfine steps at R_n (no R^+ group) when Tfine > 0. */
+ * Flow Fields+ Fast (Sec. 3.4): the finest stage run runs only Tfine steps
+ * at R_m (no R^+ group) when Tfine > 0. */
 typedef struct {
-    int P, T;      /* steps at R_n^+, then at R_n */
-    int Rn, Rnp;   /* R_n and R_n^+ */
+    int P, T;      /* steps at R_m^+, then at R_m */
+    int Rn, Rnp;   /* R_m and R_m^+ */
 } or_scale_steps;
 
-static or_scale_steps scale_steps(int level, int lmin, int T, int R_num, int R_den, int P, int Rp_num, int Tfine)
+static or_scale_steps scale_steps(int m, int finest, int T, int R_num, int R_den, int P, int Rp_num, int Tfine)
 {
-    int n = 1 << level;
     or_scale_steps st;
     st.P = P;
     st.T = T;
-    if (level == lmin && Tfine > 0) {
+    if (finest && Tfine > 0) {
         st.P = 0;
         st.T = Tfine;
     }
-    st.Rn = or_rs_radius(n, R_num, R_den);
-    st.Rnp = or_rs_radius(n, Rp_num, R_den);
+    st.Rn = or_rs_radius(m, R_num, R_den);
+    st.Rnp = or_rs_radius(m, Rp_num, R_den);
     return st;
 }
 
-/* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, with the
- * per-scale steps of scale_steps; nn_l candidates per seed (Eq. 4), raster:
- * serial-order propagation steps instead of checkerboard ones; lmin = 1:
- * the finest scale is not run and the result is the grid of scale 2, the
- * seeds taken from the even pixels only (Flow Fields+ Fast x2, Sec. 3.4). */
-static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
-                               const void *const *Db, int W, int H, int L, int T, int r, int R_num, int R_den,
-                               int P, int Rp_num, int Tfine, int nn_l, int raster, int lmin, uint64_t seed,
-                               int stream, int nthreads, int16_t *flow_out, uint32_t *cost_out, uint64_t *n_evals)
+/* Patch-scale change on one grid (the step from a sub-scale m = 3n/2 to the
+ * scale n, Sec. 3.3): every set cell keeps its flow and evaluates its cost
+ * at the new patch scale m. */
+static void rescore_g(or_cost_fn E, int s, const void *Da, const void *Db, int W, int H, int n, int m, int r,
+                      int16_t *flow, uint32_t *cost, uint64_t *n_evals)
 {
-    int nc = 1 << (L - 1);
+    int Wn = ceil_div(W, n), Hn = ceil_div(H, n);
+    for (int j = 0; j < Hn; ++j)
+        for (int i = 0; i < Wn; ++i) {
+            int k = j * Wn + i;
+            if (cost[k] == OR_UNSET) continue;
+            cost[k] = E(Da, Db, W, H, m, r, i * n, j * n, flow[2 * k], flow[2 * k + 1], s);
+            *n_evals += 1;
+        }
+}
+
+void or_rescore(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int m, int r, int16_t *flow,
+                uint32_t *cost, uint64_t *n_evals)
+{
+    rescore_g(cost_u8, 0, Da, Db, W, H, n, m, r, flow, cost, n_evals);
+}
+
+/* The steps with a patch scale m apart from the grid scale n (a sub-scale
+ * stage); Da, Db: features of patch scale m. */
+void or_seed_level_m(const int16_t *cflow, const uint32_t *ccost, const uint8_t *Da, const uint8_t *Db, int W, int H,
+                     int n, int m, int r, int16_t *flow, uint32_t *cost, uint64_t *n_evals)
+{
+    seed_level_g(cost_u8, 0, cflow, ccost, Da, Db, W, H, n, m, r, flow, cost, n_evals);
+}
+
+void or_propagate_m(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int m, int r, int pass, int16_t *flow,
+                    uint32_t *cost, uint64_t *n_evals, int nthreads)
+{
+    propagate_g(cost_u8, 0, Da, Db, W, H, n, m, r, pass, flow, cost, n_evals, nthreads);
+}
+
+void or_random_search_m(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int m, int r, int Rn,
+                        uint64_t seed, int stream, int gen, int pass, int16_t *flow, uint32_t *cost,
+                        uint64_t *n_evals, int nthreads)
+{
+    random_search_g(cost_u8, 0, Da, Db, W, H, n, m, r, Rn, seed, stream, gen, pass, flow, cost, n_evals, nthreads);
+}
+
+/* One direction of the multi-scale Flow Field (Sec. 3.2), a -> b, over the
+ * stages of or_make_stages: Da[k], Db[k] are the features of patch scale
+ * stage_m[k]; nn_l candidates per seed (Eq. 4); raster: serial-order
+ * propagation steps instead of checkerboard ones; rstep = 2: the seeds are
+ * taken from the even pixels only (Flow Fields+ Fast x2, Sec. 3.4).  The
+ * result is the grid of the last stage. */
+static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uint8_t *Nr, const void *const *Da,
+                               const void *const *Db, int W, int H, int nst, const int *stage_n, const int *stage_m,
+                               int T, int r, int R_num, int R_den, int P, int Rp_num, int Tfine, int nn_l, int raster,
+                               int rstep, uint64_t seed, int stream, int nthreads, int16_t *flow_out,
+                               uint32_t *cost_out, uint64_t *n_evals)
+{
+    int nc = stage_n[0];
     int Wc = ceil_div(W, nc), Hc = ceil_div(H, nc);
     size_t cells0 = (size_t)W * H;
     int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)Wc * Hc * nn_l);
@@ -831,32 +907,37 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
         fl[b] = (int16_t *)malloc(sizeof(int16_t) * 2 * cells0);
         co[b] = (uint32_t *)malloc(sizeof(uint32_t) * cells0);
     }
-    if (nn_l == 1 && lmin == 0)
+    if (nn_l == 1 && rstep == 1)
         or_nn(Nq, Nr, W, H, nc, idx, dist, nthreads);
     else
-        or_nn_topl_step(Nq, Nr, W, H, nc, nn_l, lmin ? 2 : 1, idx, dist, nthreads);
+        or_nn_topl_step(Nq, Nr, W, H, nc, nn_l, rstep, idx, dist, nthreads);
     int cur = 0;
-    init_coarse_g(E, s, idx, nn_l, Da[L - 1], Db[L - 1], W, H, nc, r, fl[cur], co[cur], n_evals);
-    for (int level = L - 1; level >= lmin; --level) {
-        int n = 1 << level;
-        if (level < L - 1) {
-            seed_level_g(E, s, fl[cur], co[cur], Da[level], Db[level], W, H, n, r, fl[cur ^ 1], co[cur ^ 1],
-                         n_evals);
+    init_coarse_g(E, s, idx, nn_l, Da[0], Db[0], W, H, nc, stage_m[0], r, fl[cur], co[cur], n_evals);
+    for (int k = 0; k < nst; ++k) {
+        int n = stage_n[k], m = stage_m[k];
+        int level = 0;
+        while ((1 << level) < n) ++level;
+        int gen = level + (m != n ? 16 : 0);
+        if (k > 0 && n == stage_n[k - 1]) {
+            rescore_g(E, s, Da[k], Db[k], W, H, n, m, r, fl[cur], co[cur], n_evals);
+        } else if (k > 0) {
+            seed_level_g(E, s, fl[cur], co[cur], Da[k], Db[k], W, H, n, m, r, fl[cur ^ 1], co[cur ^ 1], n_evals);
             cur ^= 1;
         }
-        or_scale_steps st = scale_steps(level, lmin, T, R_num, R_den, P, Rp_num, Tfine);
+        or_scale_steps st = scale_steps(m, k == nst - 1, T, R_num, R_den, P, Rp_num, Tfine);
         for (int t = 0; t < st.P + st.T; ++t) {
             if (raster)
-                propagate_raster_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals);
+                propagate_raster_g(E, s, Da[k], Db[k], W, H, n, m, r, t, fl[cur], co[cur], n_evals);
             else
-                propagate_g(E, s, Da[level], Db[level], W, H, n, r, t, fl[cur], co[cur], n_evals, nthreads);
+                propagate_g(E, s, Da[k], Db[k], W, H, n, m, r, t, fl[cur], co[cur], n_evals, nthreads);
             int last_of_group = t == st.P - 1 || t == st.P + st.T - 1;
             if (!last_of_group)
-                random_search_g(E, s, Da[level], Db[level], W, H, n, r, t < st.P ? st.Rnp : st.Rn, seed, stream,
-                                level, t, fl[cur], co[cur], n_evals, nthreads);
+                random_search_g(E, s, Da[k], Db[k], W, H, n, m, r, t < st.P ? st.Rnp : st.Rn, seed, stream, gen, t,
+                                fl[cur], co[cur], n_evals, nthreads);
         }
     }
-    size_t cells_out = (size_t)ceil_div(W, 1 << lmin) * ceil_div(H, 1 << lmin);
+    int nl = stage_n[nst - 1];
+    size_t cells_out = (size_t)ceil_div(W, nl) * ceil_div(H, nl);
     memcpy(flow_out, fl[cur], sizeof(int16_t) * 2 * cells_out);
     memcpy(cost_out, co[cur], sizeof(uint32_t) * cells_out);
     for (int b = 0; b < 2; ++b) { free(fl[b]); free(co[b]); }
@@ -875,36 +956,40 @@ static void flow_one_direction(or_cost_fn E, int s, const uint8_t *Nq, const uin
  * fast_x2 != 0: Flow Fields+ Fast x2 (Sec. 3.4), the fields and masks are
  * grids of scale 2 ([ceil(H/2)][ceil(W/2)]) checked by or_consistency_grid. */
 static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
-                         int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2,
+                         int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2, int sub,
                          double eps, uint64_t seed, int nthreads,
                          int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                          uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
     if (W < 1 || H < 1 || W > 32767 || H > 32767 || L < 1 || L > 7 || T < 1 || r < 0 || r > 7 ||
         R_num < 0 || R_den < 1 || P < 0 || Rp_num < 0 || Tfine < 0 || P + T > 64 || Tfine > 64 || s < 0 || s > 3 ||
-        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))) || nn_l < 1 || nn_l > 16 || (fast_x2 && (L < 2 || s > 0)))
+        (s > 0 && (W > (32767 >> s) || H > (32767 >> s))) || nn_l < 1 || nn_l > 16 || (fast_x2 && (L < 2 || s > 0)) ||
+        (sub && fast_x2))
         return 1;
     size_t np = (size_t)W * H;
     uint8_t *blur = (uint8_t *)malloc(np);
-    uint8_t *D1[7], *D2[7];
-    for (int l = 0; l < L; ++l) {
-        int n = 1 << l;
-        D1[l] = (uint8_t *)malloc(np * 16);
-        D2[l] = (uint8_t *)malloc(np * 16);
-        or_blur(img1, W, H, n, blur);
-        or_descriptor(blur, W, H, n, D1[l]);
-        or_blur(img2, W, H, n, blur);
-        or_descriptor(blur, W, H, n, D2[l]);
+    int stage_n[16], stage_m[16];
+    int nst = or_make_stages(L, fast_x2 ? 1 : 0, sub, stage_n, stage_m);
+    /* features of every stage's patch scale (level-1 ones for the NN seed) */
+    uint8_t *D1[16], *D2[16], *N1 = (uint8_t *)malloc(np * 16), *N2 = (uint8_t *)malloc(np * 16);
+    for (int k = 0; k <= nst; ++k) {
+        int m = k < nst ? stage_m[k] : 1;
+        uint8_t *a = k < nst ? (D1[k] = (uint8_t *)malloc(np * 16)) : N1;
+        uint8_t *b = k < nst ? (D2[k] = (uint8_t *)malloc(np * 16)) : N2;
+        or_blur(img1, W, H, m, blur);
+        or_descriptor(blur, W, H, m, a);
+        or_blur(img2, W, H, m, blur);
+        or_descriptor(blur, W, H, m, b);
     }
     or_cost_fn E = s > 0 ? cost_u8_sub : cost_u8;
     n_evals[0] = n_evals[1] = 0;
-    int lmin = fast_x2 ? 1 : 0;
-    flow_one_direction(E, s, D1[0], D2[0], (const void *const *)D1, (const void *const *)D2, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, lmin, seed, 0, nthreads, flow_fwd, cost_fwd,
-                       &n_evals[0]);
-    flow_one_direction(E, s, D2[0], D1[0], (const void *const *)D2, (const void *const *)D1, W, H, L, T, r,
-                       R_num, R_den, P, Rp_num, Tfine, nn_l, raster, lmin, seed, 1, nthreads, flow_bwd, cost_bwd,
-                       &n_evals[1]);
+    int rstep = fast_x2 ? 2 : 1;
+    flow_one_direction(E, s, N1, N2, (const void *const *)D1, (const void *const *)D2, W, H, nst, stage_n, stage_m,
+                       T, r, R_num, R_den, P, Rp_num, Tfine, nn_l, raster, rstep, seed, 0, nthreads, flow_fwd,
+                       cost_fwd, &n_evals[0]);
+    flow_one_direction(E, s, N2, N1, (const void *const *)D2, (const void *const *)D1, W, H, nst, stage_n, stage_m,
+                       T, r, R_num, R_den, P, Rp_num, Tfine, nn_l, raster, rstep, seed, 1, nthreads, flow_bwd,
+                       cost_bwd, &n_evals[1]);
     if (fast_x2) {
         or_consistency_grid(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, 2, eps, keep_fwd);
         if (keep_bwd) or_consistency_grid(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, 2, eps, keep_bwd);
@@ -912,7 +997,9 @@ static int flow_fields_g(const uint8_t *img1, const uint8_t *img2, int W, int H,
         consistency_g(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, s, eps, keep_fwd);
         if (keep_bwd) consistency_g(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, s, eps, keep_bwd);
     }
-    for (int l = 0; l < L; ++l) { free(D1[l]); free(D2[l]); }
+    for (int k = 0; k < nst; ++k) { free(D1[k]); free(D2[k]); }
+    free(N1);
+    free(N2);
     free(blur);
     return 0;
 }
@@ -922,20 +1009,20 @@ int or_flow_fields(const uint8_t *img1, const uint8_t *img2, int W, int H, int L
                    int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                    uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, 1, 0, 0, eps, seed, nthreads,
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, 0, 1, 0, 0, 0, eps, seed, nthreads,
                          flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* or_flow_fields with every option: subpixel form s, nn_l seed candidates,
  * serial-order (raster) propagation, Flow Fields+ Fast x2 (fast_x2; outputs
- * on the grid of scale 2). */
+ * on the grid of scale 2), sub-scales (sub; Sec. 3.3). */
 int or_flow_fields_x(const uint8_t *img1, const uint8_t *img2, int W, int H, int L, int T, int r, int R_num,
-                     int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2, double eps,
-                     uint64_t seed, int nthreads, int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd,
-                     uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
+                     int R_den, int P, int Rp_num, int Tfine, int s, int nn_l, int raster, int fast_x2, int sub,
+                     double eps, uint64_t seed, int nthreads, int16_t *flow_fwd, int16_t *flow_bwd,
+                     uint32_t *cost_fwd, uint32_t *cost_bwd, uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, nn_l, raster, fast_x2, eps,
-                         seed, nthreads, flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, nn_l, raster, fast_x2, sub,
+                         eps, seed, nthreads, flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
 /* The subpixel form of or_flow_fields (flows in units of 1/2^s pixel). */
@@ -944,7 +1031,7 @@ int or_flow_fields_sub(const uint8_t *img1, const uint8_t *img2, int W, int H, i
                        int16_t *flow_fwd, int16_t *flow_bwd, uint32_t *cost_fwd, uint32_t *cost_bwd,
                        uint8_t *keep_fwd, uint8_t *keep_bwd, uint64_t *n_evals)
 {
-    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, 1, 0, 0, eps, seed, nthreads,
+    return flow_fields_g(img1, img2, W, H, L, T, r, R_num, R_den, P, Rp_num, Tfine, s, 1, 0, 0, 0, eps, seed, nthreads,
                          flow_fwd, flow_bwd, cost_fwd, cost_bwd, keep_fwd, keep_bwd, n_evals);
 }
 
@@ -953,14 +1040,14 @@ int or_flow_fields_sub(const uint8_t *img1, const uint8_t *img2, int W, int H, i
 void or_propagate_sub(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int s, int pass,
                       int16_t *flow, uint32_t *cost, uint64_t *n_evals, int nthreads)
 {
-    propagate_g(cost_u8_sub, s, Da, Db, W, H, n, r, pass, flow, cost, n_evals, nthreads);
+    propagate_g(cost_u8_sub, s, Da, Db, W, H, n, n, r, pass, flow, cost, n_evals, nthreads);
 }
 
 void or_random_search_sub(const uint8_t *Da, const uint8_t *Db, int W, int H, int n, int r, int s, int Rn,
                           uint64_t seed, int stream, int level, int pass, int16_t *flow, uint32_t *cost,
                           uint64_t *n_evals, int nthreads)
 {
-    random_search_g(cost_u8_sub, s, Da, Db, W, H, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals,
+    random_search_g(cost_u8_sub, s, Da, Db, W, H, n, n, r, Rn, seed, stream, level, pass, flow, cost, n_evals,
                     nthreads);
 }
 
@@ -987,10 +1074,19 @@ int or_flow_fields_f32(const float *const *F1, const float *const *F2, int W, in
     uint8_t *q1 = (uint8_t *)malloc(np * 16), *q2 = (uint8_t *)malloc(np * 16);
     or_quantize_pair_u8(F1[0], F2[0], (int64_t)np * 16, q1, q2);
     n_evals[0] = n_evals[1] = 0;
-    flow_one_direction(cost_f32, 0, q1, q2, (const void *const *)F1, (const void *const *)F2, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, 1, 0, 0, seed, 0, nthreads, flow_fwd, cost_fwd, &n_evals[0]);
-    flow_one_direction(cost_f32, 0, q2, q1, (const void *const *)F2, (const void *const *)F1, W, H, L, T, r, R_num,
-                       R_den, P, Rp_num, Tfine, 1, 0, 0, seed, 1, nthreads, flow_bwd, cost_bwd, &n_evals[1]);
+    int stage_n[16], stage_m[16];
+    int nst = or_make_stages(L, 0, 0, stage_n, stage_m);
+    const float *S1[16], *S2[16];  /* stage k is scale 2^(L-1-k) */
+    for (int k = 0; k < nst; ++k) {
+        S1[k] = F1[L - 1 - k];
+        S2[k] = F2[L - 1 - k];
+    }
+    flow_one_direction(cost_f32, 0, q1, q2, (const void *const *)S1, (const void *const *)S2, W, H, nst, stage_n,
+                       stage_m, T, r, R_num, R_den, P, Rp_num, Tfine, 1, 0, 1, seed, 0, nthreads, flow_fwd, cost_fwd,
+                       &n_evals[0]);
+    flow_one_direction(cost_f32, 0, q2, q1, (const void *const *)S2, (const void *const *)S1, W, H, nst, stage_n,
+                       stage_m, T, r, R_num, R_den, P, Rp_num, Tfine, 1, 0, 1, seed, 1, nthreads, flow_bwd, cost_bwd,
+                       &n_evals[1]);
     or_consistency(flow_fwd, cost_fwd, flow_bwd, cost_bwd, W, H, eps, keep_fwd);
     if (keep_bwd) or_consistency(flow_bwd, cost_bwd, flow_fwd, cost_fwd, W, H, eps, keep_bwd);
     free(q1);

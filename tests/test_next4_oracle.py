@@ -250,7 +250,7 @@ def test_default_options_reproduce_the_plain_schedule():
     ne = np.zeros(2, np.uint64)
     p = oracle.core._p
     rc = ext.or_flow_fields_x(p(np.ascontiguousarray(a)), p(np.ascontiguousarray(b)), W, H, 3, 4, 3, 1, 1, 0, 0, 0,
-                              0, 1, 0, 0, 1.0, 12345, 1, p(outs["flow_fwd"]), p(outs["flow_bwd"]), p(outs["cost_fwd"]),
+                              0, 1, 0, 0, 0, 1.0, 12345, 1, p(outs["flow_fwd"]), p(outs["flow_bwd"]), p(outs["cost_fwd"]),
                               p(outs["cost_bwd"]), p(outs["keep_fwd"]), p(outs["keep_bwd"]), p(ne))
     assert rc == 0
     for k, v in outs.items():
