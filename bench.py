@@ -247,6 +247,8 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     res = {}
     plus = dict(iters=8, plus_iters=4, Rp_num=2 * params.R_num)
     for name, kw, n_reps in (("plus", plus, reps), ("plus_fast", dict(plus, fine_iters=4), reps),
+                             # Sec. 3.3: a stage of patch scale 3n/2 before every scale below the coarsest
+                             ("plus_subscales", dict(plus, subscales=True), 5),
                              # Sec. 3.4: no finest scale, 4 x R on scale 2, one match per 2x2 region
                              ("plus_fast_x2", dict(plus, fine_iters=4, fast_x2=True), reps),
                              # Eq. 4 with the paper's leaf size l = 8 (Sec. 4.1)
@@ -272,7 +274,8 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
         res[name] = {"mpix_per_s": round(W * H / ms / 1e3, 2), "ms_per_pair": round(ms, 4),
                      "steps": f"{prm.plus_iters} x R+ then {prm.iters} x R"
                               + (f", finest {prm.fine_iters} x R" if prm.fine_iters else "")
-                              + (", finest scale skipped, grid of scale 2" if prm.fast_x2 else ""),
+                              + (", finest scale skipped, grid of scale 2" if prm.fast_x2 else "")
+                              + (", sub-scales 3n/2" if prm.subscales else ""),
                      "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
                      "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
                      "kept_epe": round(q["kept_epe"], 4)}

@@ -127,6 +127,17 @@ typedef struct {
      * (FF_ERR_ARG otherwise); the batched and learned calls return
      * FF_ERR_UNSUPPORTED. */
     int32_t fast_x2;
+    /* Sub-scales (Sec. 3.3, table of scales and sub-scales): 1 = every scale
+     * n >= 2 below the coarsest is preceded by a stage on the same grid
+     * whose patch spacing, blur and random-search distances follow the
+     * sub-scale m = 3n/2 (for L = 4: (8,8) (4,6) (4,4) (2,3) (2,2) (1,1));
+     * the step to the next stage on one grid keeps the flows and evaluates
+     * the costs at the new patch scale (ff_rescore_level); every stage runs
+     * the plus_iters / iters steps (fine_iters on the last one); the
+     * generator's level field is log2 n, plus 16 on a sub-scale stage.  Runs
+     * on the per-step kernels.  Not with fast_x2 (FF_ERR_ARG); ff_run_level,
+     * the batched and the learned calls return FF_ERR_UNSUPPORTED. */
+    int32_t subscales;
 } ff_params;
 
 /* The built-in launch tables (host): written to *out. */
@@ -156,7 +167,8 @@ const char *ff_status_str(ff_status s);
  * pixels are grouped by phase, col(c) = (c mod n)*floor(Wp/n) +
  * min(c mod n, Wp mod n) + floor(c/n): the samples x + n*u of a patch row
  * are adjacent and a radius-3 patch around any in-image pixel needs no
- * clamping.  n <= 64. */
+ * clamping.  A scale that is not a power of two (a sub-scale, Sec. 3.3)
+ * keeps the pixels of a row in image order, col(c) = c.  1 <= n <= 64. */
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum,
                          uint8_t *blurred, uint8_t *desc, uint8_t *desc_rowmajor, uint8_t *wform, void *stream);
 
@@ -258,6 +270,15 @@ ff_status ff_propagate_level(const uint8_t *desc_a, const uint8_t *desc_b, int32
 ff_status ff_propagate_raster(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
                               int32_t radius, int32_t pass, int16_t *flow, uint32_t *cost, uint64_t *n_evals,
                               void *stream);
+
+/* Patch-scale change on one grid (Sec. 3.3 sub-scales): every set cell
+ * (i, j) of the grid of scale n keeps its flow and gets the cost of the
+ * patch of scale m, E_m(p, F) with p = (i n, j n) (patch samples p + m(u, v),
+ * features of scale m); n_evals grows by the number of set cells.  desc_a,
+ * desc_b: descriptor maps of scale m (ff_descriptors with n = m); flow:
+ * input; cost: in/out.  n a power of two, 1 <= m <= 64. */
+ff_status ff_rescore_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t m,
+                           int32_t radius, const int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream);
 
 /* One random-search step (Sec. 3.1) at scale n: every set cell tries
  * F + o with o uniform on [-Rn, Rn]^2 and keeps it if E_n is strictly

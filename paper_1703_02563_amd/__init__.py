@@ -9,10 +9,10 @@ from .flowfields import (FlowFields, Params, Tuning, consistency_filter, consist
                          consistency_filter_sub, consistency_filter_grid,
                          default_tuning, descriptors, flow_fields, flow_fields_two_backward, init_nn,
                          level_launches, propagate_level, random_search, run_level, seed_level, region_filter,
-                         sparsify, workspace_bytes, nn_topl, init_nn_l, propagate_raster)
+                         sparsify, workspace_bytes, nn_topl, init_nn_l, propagate_raster, rescore_level)
 
 __all__ = ["FlowFieldsError", "lib", "FlowFields", "Params", "Tuning", "consistency_filter", "consistency_filter2",
            "consistency_filter_sub", "consistency_filter_grid",
            "default_tuning", "descriptors", "flow_fields", "flow_fields_two_backward", "init_nn", "level_launches",
            "propagate_level", "random_search", "run_level", "seed_level", "region_filter", "sparsify",
-           "workspace_bytes", "nn_topl", "init_nn_l", "propagate_raster"]
+           "workspace_bytes", "nn_topl", "init_nn_l", "propagate_raster", "rescore_level"]

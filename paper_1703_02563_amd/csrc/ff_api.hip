@@ -44,7 +44,8 @@ bool params_ok(const ff_params *p) {
          p->plus_iters >= 0 && p->plus_iters + p->iters <= 64 && p->Rp_num >= 0 && p->Rp_num <= 1 << 20 &&
          p->fine_iters >= 0 && p->fine_iters <= 64 && (p->subpixel == 0 || p->subpixel == 3) && p->nn_l >= 0 &&
          p->nn_l <= ffh::kTopLMax && (p->raster == 0 || p->raster == 1) && (p->fast_x2 == 0 || p->fast_x2 == 1) &&
-         (!p->fast_x2 || (p->levels >= 2 && p->subpixel == 0)) && ffh::tuning_ok(tuning_of(p->tuning));
+         (!p->fast_x2 || (p->levels >= 2 && p->subpixel == 0)) && (p->subscales == 0 || p->subscales == 1) &&
+         !(p->subscales && p->fast_x2) && ffh::tuning_ok(tuning_of(p->tuning));
 }
 
 // Seed candidates of the call (0 and 1: the exact NN alone).
@@ -56,6 +57,24 @@ bool sub_dims_ok(const ff_params *p, int W, int H) {
 }
 
 int rs_radius(int n, int R_num, int R_den) { return (int)(((int64_t)R_num * n) / R_den); }
+
+// The sub-scale stage before scale n = 2^lv (Sec. 3.3): patch scale 3n/2.
+int subscale_of(int lv) { return 3 << (lv - 1); }
+
+// Stages of the sub-scale schedule, coarse to fine: (grid scale n, patch
+// scale m); every scale n >= 2 below the coarsest is preceded by (n, 3n/2).
+int subscale_stages(int L, int *stage_lv, int *stage_m) {
+  int k = 0;
+  for (int lv = L - 1; lv >= 0; --lv) {
+    if (lv < L - 1 && lv >= 1) {
+      stage_lv[k] = lv;
+      stage_m[k++] = subscale_of(lv);
+    }
+    stage_lv[k] = lv;
+    stage_m[k++] = 1 << lv;
+  }
+  return k;
+}
 
 // Steps of scale lv: P steps whose random searches use R_n^+, then T at R_n
 // (Flow Fields+, Sec. 3.3; P = 0 is the original schedule of Sec. 3.2), or
@@ -80,8 +99,8 @@ ScaleSteps scale_steps(const ff_params *p, int lv) {
 
 // Device workspace of ff_flow_fields, carved in this order.
 struct Layout {
-  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], desc1, desc1e, nb, keys, topl, cand, grids, sgrids,
-      evals, total;
+  size_t hsum, blur, desc[2][kMaxLevels], wform[2][kMaxLevels], sdesc[2][kMaxLevels], desc1, desc1e, nb, keys, topl,
+      cand, grids, sgrids, evals, total;
   size_t N, Npad, M;
   int L;
 };
@@ -111,6 +130,12 @@ Layout layout(int W, int H, const ff_params *p) {
     for (int lv = 0; lv < l.L; ++lv) {
       l.wform[im][lv] = off;
       off = align256(off + ffk::wform_bytes(W, H, 1 << lv));
+    }
+  // sub-scales: the maps of patch scale 3n/2 for the scales n = 2^lv, 1 <= lv <= L - 2
+  for (int im = 0; im < 2; ++im)
+    for (int lv = 1; lv + 1 < l.L; ++lv) {
+      l.sdesc[im][lv] = off;
+      if (p->subscales) off = align256(off + desc_map_bytes(W, H, subscale_of(lv)));
     }
   l.desc1 = off; off = align256(off + 2 * l.N * 16);
   // Fast x2: the NN's references, the even pixels of both images
@@ -297,6 +322,42 @@ hipError_t run_level_steps(ffh::LevelArgs a, int W, int H, int lv, int L, const 
   return hipSuccess;
 }
 
+// One stage of the sub-scale schedule with one launch per step: grid scale
+// 2^lv, patch scale m (a.dir[].Da/Db: the features of scale m); entry 0:
+// the coarsest stage's NN initialisation, 1: the same grid at a new patch
+// scale (costs re-evaluated), 2: the hand-over from the coarser grid.  The
+// generator's level field is lv, plus 16 on a sub-scale stage.
+hipError_t run_stage(ffh::LevelArgs a, int W, int H, int lv, int m, int entry, bool finest, const ff_params *p,
+                     hipStream_t s) {
+  const int n = 1 << lv;
+  a.W = W;
+  a.H = H;
+  a.n = n;
+  a.ns = m;
+  a.Wn = ceil_div(W, n);
+  a.Hn = ceil_div(H, n);
+  a.level = lv + (m != n ? 16 : 0);
+  a.radius = p->radius;
+  a.seed = p->seed;
+  ScaleSteps st{p->plus_iters, p->iters, rs_radius(m, p->R_num, p->R_den), rs_radius(m, p->Rp_num, p->R_den)};
+  if (finest && p->fine_iters > 0) {
+    st.P = 0;
+    st.T = p->fine_iters;
+  }
+  hipError_t e = entry == 0   ? ffh::launch_init_coarse(a, s)
+                 : entry == 1 ? ffh::launch_rescore(a, s)
+                              : ffh::launch_seed_level(a, s);
+  if (e != hipSuccess) return e;
+  for (int t = 0; t < st.total(); ++t) {
+    a.pass = t;
+    a.Rn = st.radius(t);
+    e = p->raster ? ffh::launch_propagate_raster(a, s) : ffh::launch_propagate(a, s);
+    if (e != hipSuccess) return e;
+    if (st.rs_after(t) && (e = ffh::launch_random_search(a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -315,19 +376,18 @@ const char *ff_status_str(ff_status s) {
 }
 
 size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n) {
-  if (!dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1))) return 0;
+  if (!dims_ok(W, H) || n < 1 || n > 64) return 0;
   return desc_map_bytes(W, H, n);
 }
 
 size_t ff_wform_map_bytes(int32_t W, int32_t H, int32_t n) {
-  if (!dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1))) return 0;
+  if (!dims_ok(W, H) || n < 1 || n > 64) return 0;
   return ffk::wform_bytes(W, H, n);
 }
 
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum, uint8_t *blurred,
                          uint8_t *desc, uint8_t *desc_rowmajor, uint8_t *wform, void *stream) {
-  if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || !is_pow2(n) || n > (1 << (kMaxLevels - 1)))
-    return FF_ERR_ARG;
+  if (!img || !hsum || !blurred || !desc || !dims_ok(W, H) || n < 1 || n > 64) return FF_ERR_ARG;
   ffh::DescJobs jobs{};
   jobs.W = W;
   jobs.H = H;
@@ -473,6 +533,16 @@ ff_status ff_propagate_raster(const uint8_t *desc_a, const uint8_t *desc_b, int3
   return from_hip(ffh::launch_propagate_raster(a, (hipStream_t)stream));
 }
 
+ff_status ff_rescore_level(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n, int32_t m,
+                           int32_t radius, const int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !is_pow2(n) || m < 1 || m > 64 || radius < 0 ||
+      radius > 7)
+    return FF_ERR_ARG;
+  ffh::LevelArgs a = one_dir_args(desc_a, desc_b, W, H, n, radius, const_cast<int16_t *>(flow), cost, n_evals);
+  a.ns = m;
+  return from_hip(ffh::launch_rescore(a, (hipStream_t)stream));
+}
+
 ff_status ff_random_search(const uint8_t *desc_a, const uint8_t *desc_b, int32_t W, int32_t H, int32_t n,
                            int32_t radius, int32_t Rn, uint64_t seed, int32_t stream_id, int32_t level, int32_t pass,
                            int16_t *flow, uint32_t *cost, uint64_t *n_evals, void *stream) {
@@ -570,6 +640,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
   if (!scratch || scratch_bytes < ff_run_level_scratch_bytes(W, H, level)) return FF_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (!sub_dims_ok(params, W, H)) return FF_ERR_ARG;
+  if (params->subscales) return FF_ERR_UNSUPPORTED;  // a stage is not a scale: ff_flow_fields runs them
   const int n = 1 << level, r = params->radius;
   const ScaleSteps st = scale_steps(params, level);
   if (r == 3 && params->subpixel == 0 && !params->raster) {
@@ -738,7 +809,8 @@ ff_status ff_flow_fields_batched(const ff_pair *pairs, int32_t npairs, const ff_
                                  void *ws, size_t ws_bytes, void *stream) {
   if (!batch_ok(pairs, npairs, params) || !table || !ws || !(params->eps >= 0.0f)) return FF_ERR_ARG;
   if (ws_bytes < ff_batch_workspace_bytes(pairs, npairs, params)) return FF_ERR_WORKSPACE;
-  if (params->radius != 3 || params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2)
+  if (params->radius != 3 || params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2 ||
+      params->subscales)
     return FF_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const int L = params->levels, nc = 1 << (L - 1);
@@ -861,7 +933,8 @@ ff_status ff_flow_fields_f32(const float *const *feat1, const float *const *feat
       !params_ok(params) || !(params->eps >= 0.0f))
     return FF_ERR_ARG;
   const int L = params->levels, r = params->radius;
-  if (params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2) return FF_ERR_UNSUPPORTED;
+  if (params->subpixel || params->nn_l > 1 || params->raster || params->fast_x2 || params->subscales)
+    return FF_ERR_UNSUPPORTED;
   for (int lv = 0; lv < L; ++lv)
     if (!feat1[lv] || !feat2[lv]) return FF_ERR_ARG;
   const LayoutF32 lay = layout_f32(W, H, params);
@@ -1155,6 +1228,23 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   }
   hipError_t e = ffh::launch_descriptors(jobs, s);
   if (e != hipSuccess) return FF_ERR_LAUNCH;
+  // sub-scales: the maps of patch scale 3n/2 (after the jobs above on the
+  // same stream, so their row-sum and blur scratch can be reused)
+  uint8_t *sdesc[2][kMaxLevels] = {};
+  if (params->subscales && L > 2) {
+    ffh::DescJobs sj{};
+    sj.W = W;
+    sj.H = H;
+    for (int im = 0; im < 2; ++im)
+      for (int lv = 1; lv + 1 < L; ++lv) {
+        const int z = sj.count++;
+        sdesc[im][lv] = reinterpret_cast<uint8_t *>(base + lay.sdesc[im][lv]);
+        sj.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
+                     reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N, sdesc[im][lv], nullptr, nullptr,
+                     subscale_of(lv)};
+      }
+    if ((e = ffh::launch_descriptors(sj, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  }
 
   uint64_t *evals = n_evals ? n_evals : reinterpret_cast<uint64_t *>(base + lay.evals);
   if ((e = ffh::launch_fill_u64(evals, 0, 2, s)) != hipSuccess) return FF_ERR_LAUNCH;
@@ -1247,7 +1337,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     if ((e = ffh::launch_rerank(ra, cand, params->nn_l, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
 
-  if (r == 3 && sb == 0 && !params->raster) {
+  if (r == 3 && sb == 0 && !params->raster && !params->subscales) {
     // temporally blocked level kernels: one launch per run of passes
     int32_t *sflow[kMaxLevels][2];
     uint32_t *scost[kMaxLevels][2];
@@ -1304,18 +1394,39 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     a.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
     a.dir[dr].stream_id = dr;
   }
-  for (int lv = L - 1; lv >= lmin; --lv) {
-    for (int dr = 0; dr < nd; ++dr) {
-      a.dir[dr].Da = desc[dr][lv];
-      a.dir[dr].Db = desc[dr ^ 1][lv];
-      a.dir[dr].flow = gflow[lv][dr];
-      a.dir[dr].cost = gcost[lv][dr];
-      a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
-      a.dir[dr].Dq1 = desc1[dr];
-      a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
-      a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+  if (params->subscales) {
+    // stages (n, 3n/2), (n, n) for every scale below the coarsest but the finest
+    int stage_lv[2 * kMaxLevels], stage_m[2 * kMaxLevels];
+    const int nst = subscale_stages(L, stage_lv, stage_m);
+    for (int k = 0; k < nst; ++k) {
+      const int lv = stage_lv[k], m = stage_m[k];
+      for (int dr = 0; dr < nd; ++dr) {
+        a.dir[dr].Da = m == (1 << lv) ? desc[dr][lv] : sdesc[dr][lv];
+        a.dir[dr].Db = m == (1 << lv) ? desc[dr ^ 1][lv] : sdesc[dr ^ 1][lv];
+        a.dir[dr].flow = gflow[lv][dr];
+        a.dir[dr].cost = gcost[lv][dr];
+        a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+        a.dir[dr].Dq1 = desc1[dr];
+        a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+        a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+      }
+      const int entry = k == 0 ? 0 : (stage_lv[k - 1] == lv ? 1 : 2);
+      if ((e = run_stage(a, W, H, lv, m, entry, k == nst - 1, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
     }
-    if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
+  } else {
+    for (int lv = L - 1; lv >= lmin; --lv) {
+      for (int dr = 0; dr < nd; ++dr) {
+        a.dir[dr].Da = desc[dr][lv];
+        a.dir[dr].Db = desc[dr ^ 1][lv];
+        a.dir[dr].flow = gflow[lv][dr];
+        a.dir[dr].cost = gcost[lv][dr];
+        a.dir[dr].nn_key = keys + (size_t)dr * lay.M;
+        a.dir[dr].Dq1 = desc1[dr];
+        a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
+        a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
+      }
+      if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
+    }
   }
   if (fwd_only) return FF_OK;
   if (params->fast_x2)

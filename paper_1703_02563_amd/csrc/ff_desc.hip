@@ -97,7 +97,7 @@ __host__ __device__ __forceinline__ int desc_row_stride(int W) { return (W + 15)
 __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
   extern __shared__ uint8_t s_rows[];
   const ffh::DescJob &jb = jobs.job[blockIdx.y];
-  const int W = jobs.W, H = jobs.H, n = jb.n, l2 = __builtin_ctz(n);
+  const int W = jobs.W, H = jobs.H, n = jb.n, l2 = ffk::map_log2(n);
   const int P = ffk::desc_pad(n), Wp = W + 2 * P, Hp = H + 2 * P;
   const int yp = blockIdx.x, Ws = desc_row_stride(W);
   if (yp >= Hp) return;  // workgroup-uniform

@@ -45,6 +45,15 @@ constexpr int kDescPad = 3;
 
 __host__ __device__ __forceinline__ int desc_pad(int n) { return kDescPad * n; }
 
+// Layout exponent of the map of scale n: log2 n for a power of two; 0 (the
+// pixels of a row in image order) for a sub-scale that is not one.
+__host__ __device__ __forceinline__ int map_log2(int n) {
+  int l = 0;
+  if ((n & (n - 1)) == 0)
+    while ((1 << l) < n) ++l;
+  return l;
+}
+
 // Inverse of desc_col: the pixel stored at column c.
 __device__ __forceinline__ int desc_pixel(int c, int log2n, int W) {
   const int q = W >> log2n, m = W & ((1 << log2n) - 1);
@@ -90,7 +99,7 @@ __device__ __forceinline__ int32_t pack_flow(int fx, int fy) {
 template <int R>
 __device__ __forceinline__ uint32_t patch_cost(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db,
                                                int W, int H, int n, int x, int y, int fx, int fy) {
-  const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+  const int Wm = W - 1, Hm = H - 1, l2 = map_log2(n), P = desc_pad(n), Wp = W + 2 * P;
   uint32_t s = 0;
 #pragma unroll 1
   for (int v = -R; v <= R; ++v) {
@@ -112,7 +121,7 @@ template <int R>
 __device__ __forceinline__ void patch_cost2(const uint4 *__restrict__ Da, const uint4 *__restrict__ Db, int W,
                                             int H, int n, int x, int y, int f1x, int f1y, bool en1, int f2x,
                                             int f2y, bool en2, uint32_t &c1, uint32_t &c2) {
-  const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+  const int Wm = W - 1, Hm = H - 1, l2 = map_log2(n), P = desc_pad(n), Wp = W + 2 * P;
   uint32_t s1 = 0, s2 = 0;
 #pragma unroll 1
   for (int v = -R; v <= R; ++v) {
@@ -157,7 +166,7 @@ struct CostU8 {
   __device__ static uint32_t eval_part(const void *Dav, const void *Dbv, int W, int H, int n, int x, int y, int fx,
                                        int fy, int g) {
     const uint4 *Da = static_cast<const uint4 *>(Dav), *Db = static_cast<const uint4 *>(Dbv);
-    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    const int Wm = W - 1, Hm = H - 1, l2 = map_log2(n), P = desc_pad(n), Wp = W + 2 * P;
     constexpr int D = 2 * R + 1;
     uint32_t s = 0;
     // unrolled: all of the lane's loads are in flight together
@@ -250,7 +259,7 @@ struct CostU8Sub {
     const int tx0 = tx >> 3, ty0 = ty >> 3, ax = tx & 7, ay = ty & 7;
     const int tx1 = tx0 + (ax != 0), ty1 = ty0 + (ay != 0);
     const uint32_t w00 = (8 - ax) * (8 - ay), w10 = ax * (8 - ay), w01 = (8 - ax) * ay, w11 = ax * ay;
-    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    const int Wm = W - 1, Hm = H - 1, l2 = map_log2(n), P = desc_pad(n), Wp = W + 2 * P;
     uint32_t sum = 0;
 #pragma unroll 1
     for (int v = -R; v <= R; ++v) {
@@ -285,7 +294,7 @@ struct CostU8Sub {
     const int tx0 = tx >> 3, ty0 = ty >> 3, ax = tx & 7, ay = ty & 7;
     const int tx1 = tx0 + (ax != 0), ty1 = ty0 + (ay != 0);
     const uint32_t w00 = (8 - ax) * (8 - ay), w10 = ax * (8 - ay), w01 = (8 - ax) * ay, w11 = ax * ay;
-    const int Wm = W - 1, Hm = H - 1, l2 = __builtin_ctz(n), P = desc_pad(n), Wp = W + 2 * P;
+    const int Wm = W - 1, Hm = H - 1, l2 = map_log2(n), P = desc_pad(n), Wp = W + 2 * P;
     constexpr int D = 2 * R + 1;
     uint32_t sum = 0;
 #pragma unroll

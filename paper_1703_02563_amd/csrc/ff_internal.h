@@ -109,6 +109,7 @@ struct LevelArgs {
   int ndir;
   int fcost;  // 0: byte descriptors, SAD; 1: float32 16-channel features, SSD; 2: byte descriptors, 1/8-px flows
   int W, H, n, Wn, Hn, radius;
+  int ns;     // patch scale of a sub-scale stage (patch p + ns (u, v), features of scale ns); 0: n
   int Rn, level, pass;
   uint64_t seed;
 };
@@ -125,6 +126,9 @@ hipError_t launch_rerank(const LevelArgs &a, const uint64_t *const *cand, int l,
 // One propagation step in serial order (anti-diagonal wavefronts over tiles;
 // integer costs only).
 hipError_t launch_propagate_raster(const LevelArgs &a, hipStream_t stream);
+// Patch-scale change on one grid (sub-scales): every set cell's cost at
+// patch scale a.ns, with a.ns's features in Da/Db.
+hipError_t launch_rescore(const LevelArgs &a, hipStream_t stream);
 
 // Temporally blocked run of propagation / random-search steps of one scale
 // (patch radius 3).  Passes [t_begin, t_end) of T; a random-search step

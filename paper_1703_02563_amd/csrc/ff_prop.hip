@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_init_coarse(ffh::LevelArgs a) {
     const int fx = ((int)(q % (uint32_t)a.W) - x) * (1 << Cost::kSub), fy = ((int)(q / (uint32_t)a.W) - y) * (1 << Cost::kSub);
     d.flow[m] = ffk::pack_flow(fx, fy);
     d.cost[m] = Cost::template eval<R>(d.Da, d.Db,
-                                   a.W, a.H, a.n, x, y, fx, fy);
+                                   a.W, a.H, a.ns > 0 ? a.ns : a.n, x, y, fx, fy);
     cnt = 1;
   }
   ffk::wave_count_add(d.n_evals, cnt);
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_seed_level(ffh::LevelArgs a) {
       if (d.ccost[kc] != kUnset) {
         f = d.cflow[kc];
         c = Cost::template eval<R>(d.Da, d.Db,
-                               a.W, a.H, a.n, i * a.n, j * a.n, ffk::flow_x(f), ffk::flow_y(f));
+                               a.W, a.H, a.ns > 0 ? a.ns : a.n, i * a.n, j * a.n, ffk::flow_x(f), ffk::flow_y(f));
         cnt = 1;
       }
     }
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
   const int kx = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int i = 2 * kx + ((colour + j) & 1);
-  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n;
+  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n, ns = a.ns > 0 ? a.ns : a.n;
   int cnt = 0, work = 0;
   if (i < Wn && j < Hn) {
     const int dir = a.pass & 3;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
     uint32_t eh = 0, ev = 0;
     work = (int)hv + (int)vcomp;
     if (hv || vcomp)
-      Cost::template eval2<R>(d.Da, d.Db, W, H, n,
+      Cost::template eval2<R>(d.Da, d.Db, W, H, ns,
                           x, y, ffk::flow_x(fh), ffk::flow_y(fh), hv, ffk::flow_x(fv), ffk::flow_y(fv), vcomp,
                           eh, ev);
     uint32_t bc = c0;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_prop_half(ffh::LevelArgs a, int colour)
       else {  // fv == f0 after the horizontal source replaced it; the stored
               // cost of a caller-made state need not equal E(p, f0)
         e = Cost::template eval<R>(d.Da, d.Db, W, H,
-                               n, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
+                               ns, x, y, ffk::flow_x(fv), ffk::flow_y(fv));
         work += 1;
       }
       if (e < bc) { bc = e; bf = fv; }
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_random_search(ffh::LevelArgs a) {
       const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
       const int x = i * a.n, y = j * a.n;
       if ((ox | oy) != 0 && ffk::target_in<Cost::kSub>(a.W, a.H, x, y, fx, fy)) {
-        const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.n, x, y, fx, fy);
+        const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.ns > 0 ? a.ns : a.n, x, y, fx, fy);
         cnt = 1;
         if (e < c0) {
           d.cost[k] = e;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_rerank(ffh::LevelArgs a, CandPtrs c, in
       const uint32_t q = (uint32_t)key;
       const int fx = ((int)(q % (uint32_t)a.W) - x) * (1 << Cost::kSub);
       const int fy = ((int)(q / (uint32_t)a.W) - y) * (1 << Cost::kSub);
-      const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.n, x, y, fx, fy);
+      const uint32_t e = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.ns > 0 ? a.ns : a.n, x, y, fx, fy);
       ++cnt;
       if (bk == ~0ull || e < bc) {
         bc = e;
@@ -249,6 +249,23 @@ __global__ __launch_bounds__(256) void k_rerank(ffh::LevelArgs a, CandPtrs c, in
   }
   ffk::wave_sum_add(d.n_evals, cnt > 0 ? cnt - 1 : 0);
   ffk::wave_sum_add2(d.n_work, cnt);
+}
+
+// Patch-scale change on one grid (sub-scales, Sec. 3.3): every set cell
+// keeps its flow and evaluates its cost at patch scale a.ns.
+template <int R, class Cost>
+__global__ __launch_bounds__(256) void k_rescore(ffh::LevelArgs a) {
+  const ffh::LevelDir d = a.dir[blockIdx.z];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = 0;
+  if (m < a.Wn * a.Hn && d.cost[m] != kUnset) {
+    const int32_t f = d.flow[m];
+    d.cost[m] = Cost::template eval<R>(d.Da, d.Db, a.W, a.H, a.ns > 0 ? a.ns : a.n, (m % a.Wn) * a.n,
+                                       (m / a.Wn) * a.n, ffk::flow_x(f), ffk::flow_y(f));
+    cnt = 1;
+  }
+  ffk::wave_count_add(d.n_evals, cnt);
+  ffk::wave_count_add2(d.n_work, cnt);
 }
 
 // One propagation step in the serial order of its direction (Sec. 3.1: a
@@ -271,7 +288,7 @@ __global__ __launch_bounds__(2 * kRasterTile * kRasterLanes) void k_prop_raster(
   __shared__ int32_t sf[S1 * S1];
   __shared__ uint32_t sc[S1 * S1];
   const ffh::LevelDir d = a.dir[blockIdx.z];
-  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n;
+  const int Wn = a.Wn, Hn = a.Hn, W = a.W, H = a.H, n = a.n, ns = a.ns > 0 ? a.ns : a.n;
   const int dir = a.pass & 3;
   const int hdi = (dir == 0 || dir == 3) ? -1 : 1;
   const int vdj = (dir == 0 || dir == 2) ? -1 : 1;
@@ -319,7 +336,7 @@ __global__ __launch_bounds__(2 * kRasterTile * kRasterLanes) void k_prop_raster(
       const int32_t fc = cand == 0 ? fh : fv;
       uint32_t part = 0;
       if (cand == 0 ? hv : vcomp)
-        part = Cost::template eval_part<R, G>(d.Da, d.Db, W, H, n, x, y, ffk::flow_x(fc), ffk::flow_y(fc), g);
+        part = Cost::template eval_part<R, G>(d.Da, d.Db, W, H, ns, x, y, ffk::flow_x(fc), ffk::flow_y(fc), g);
 #pragma unroll
       for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off);
       const uint32_t other = __shfl_xor(part, G);
@@ -572,6 +589,15 @@ hipError_t launch_rerank(const LevelArgs &a, const uint64_t *const *cand, int l,
   const int cells = a.Wn * a.Hn;
   dim3 grid((cells + 255) / 256, 1, a.ndir);
 #define CALL(R, C) hipLaunchKernelGGL((k_rerank<R, C>), grid, dim3(256), 0, stream, a, c, l)
+  FF_RADIUS_SWITCH(a, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore(const LevelArgs &a, hipStream_t stream) {
+  const int cells = a.Wn * a.Hn;
+  dim3 grid((cells + 255) / 256, 1, a.ndir);
+#define CALL(R, C) hipLaunchKernelGGL((k_rescore<R, C>), grid, dim3(256), 0, stream, a)
   FF_RADIUS_SWITCH(a, CALL)
 #undef CALL
   return hipGetLastError();

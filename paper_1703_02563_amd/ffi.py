@@ -50,6 +50,7 @@ class FFParams(C.Structure):
         ("nn_l", C.c_int32),
         ("raster", C.c_int32),
         ("fast_x2", C.c_int32),
+        ("subscales", C.c_int32),
     ]
 
 
@@ -70,6 +71,7 @@ _SIGS = {
     "ff_init_nn_l": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, C.c_size_t, _P, _P, _P, _P,
                                _P]),
     "ff_propagate_raster": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "ff_rescore_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_seed_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_propagate_level": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "ff_random_search": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, C.c_uint64, _I32, _I32, _I32, _P, _P,

@@ -67,11 +67,12 @@ class Params:
     nn_l: int = 1  # seed candidates: the nn_l nearest pixels, reranked by patch cost (Eq. 1 / Eq. 4)
     raster: bool = False  # propagation steps in serial order (anti-diagonal wavefronts)
     fast_x2: bool = False  # Flow Fields+ Fast x2: no finest scale, outputs on the grid of scale 2
+    subscales: bool = False  # Flow Fields+ sub-scales: a stage of patch scale 3n/2 before scale n
 
     def to_c(self) -> FFParams:
         p = FFParams(self.levels, self.iters, self.radius, self.R_num, self.R_den, self.eps, self.seed,
                      self.plus_iters, self.Rp_num, self.fine_iters, self.subpixel, None, self.nn_l,
-                     int(bool(self.raster)), int(bool(self.fast_x2)))
+                     int(bool(self.raster)), int(bool(self.fast_x2)), int(bool(self.subscales)))
         if self.tuning is not None:
             p._tuning = self.tuning.to_c()  # kept alive with the struct that points at it
             p.tuning = ctypes.pointer(p._tuning)
@@ -213,6 +214,14 @@ def propagate_level(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int 
     check(lib().ff_propagate_level(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), W, H, n, radius, pass_,
                                    _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
                                    _stream()), "ff_propagate_level")
+
+
+def rescore_level(desc_m_a, desc_m_b, W: int, H: int, n: int, m: int, flow, cost, radius: int = 3, n_evals=None):
+    """Costs of the grid of scale n moved to patch scale m (in place on cost);
+    desc_m_a/desc_m_b: descriptor maps of scale m."""
+    check(lib().ff_rescore_level(_ptr(desc_m_a, torch.uint8), _ptr(desc_m_b, torch.uint8), W, H, n, m, radius,
+                                 _ptr(flow, torch.int16), _ptr(cost, torch.int32), _ptr(n_evals, torch.int64),
+                                 _stream()), "ff_rescore_level")
 
 
 def propagate_raster(desc_a, desc_b, n: int, pass_: int, flow, cost, radius: int = 3, n_evals=None):

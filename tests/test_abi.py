@@ -71,7 +71,8 @@ def test_bad_arguments_return_before_any_launch():
                               None) == ffi.FF_ERR_WORKSPACE
     # bad sizes / scales / passes
     assert lib.ff_descriptors(fake, 0, 5, 1, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
-    assert lib.ff_descriptors(fake, 5, 5, 3, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 65, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
+    assert lib.ff_descriptors(fake, 5, 5, 0, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_descriptors(fake, 5, 5, 128, fake, fake, fake, None, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_propagate_level(fake, fake, 5, 5, 1, 3, -1, fake, fake, None, None) == ffi.FF_ERR_ARG
     assert lib.ff_random_search(fake, fake, 5, 5, 1, 3, -2, 1, 0, 0, 0, fake, fake, None, None) == ffi.FF_ERR_ARG
@@ -114,7 +115,9 @@ def test_descriptor_map_bytes():
     for W, H, n in [(1024, 436, 1), (1024, 436, 16), (1, 1, 64), (37, 53, 4)]:
         assert lib.ff_descriptor_map_bytes(W, H, n) == (W + 6 * n) * (H + 6 * n) * 16
     assert lib.ff_descriptor_map_bytes(0, 5, 1) == 0
-    assert lib.ff_descriptor_map_bytes(5, 5, 3) == 0
+    # a sub-scale (not a power of two) has the same padding: 3 n per side
+    assert lib.ff_descriptor_map_bytes(5, 5, 3) == (5 + 18) * (5 + 18) * 16
+    assert lib.ff_descriptor_map_bytes(5, 5, 65) == 0 and lib.ff_descriptor_map_bytes(5, 5, 0) == 0
     assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0
 
 
