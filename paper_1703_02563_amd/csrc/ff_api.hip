@@ -247,6 +247,7 @@ hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_p
   k.P = sst.P;
   k.seed = p->seed;
   k.T = T;
+  k.radius = p->radius;
   const ffh::Tuning tun = tuning_of(p->tuning);
   k.variant = k.fcost ? tun.variant_f32[lv] : tun.variant[lv];
   int runs[64][2];
@@ -643,7 +644,7 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
   if (params->subscales) return FF_ERR_UNSUPPORTED;  // a stage is not a scale: ff_flow_fields runs them
   const int n = 1 << level, r = params->radius;
   const ScaleSteps st = scale_steps(params, level);
-  if (r == 3 && params->subpixel == 0 && !params->raster) {
+  if (params->subpixel == 0 && !params->raster && ffh::level_blocked_ok(W, H, level + 1, r)) {
     ffh::LevelKArgs k{};
     k.ndir = 1;
     k.dir[0].Da = desc_a;
@@ -1337,7 +1338,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     if ((e = ffh::launch_rerank(ra, cand, params->nn_l, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
 
-  if (r == 3 && sb == 0 && !params->raster && !params->subscales) {
+  if (sb == 0 && !params->raster && !params->subscales && ffh::level_blocked_ok(W, H, L, r)) {
     // temporally blocked level kernels: one launch per run of passes
     int32_t *sflow[kMaxLevels][2];
     uint32_t *scost[kMaxLevels][2];

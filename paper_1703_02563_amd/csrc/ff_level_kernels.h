@@ -43,10 +43,10 @@ using ffk::kUnset;
 constexpr int kR = 3;
 constexpr int kHalo = ffh::kLevelHalo;
 
-template <int TW, int TH, int HALO = kHalo>
+template <int TW, int TH, int HALO = kHalo, int RR = kR>
 struct Geo {
   static constexpr int LW = TW + 2 * HALO, LH = TH + 2 * HALO;  // state window
-  static constexpr int DW = LW + 2 * kR, DH = LH + 2 * kR;        // descriptor window
+  static constexpr int DW = LW + 2 * RR, DH = LH + 2 * RR;        // descriptor window (patch radius RR)
   static_assert(2 * LW * LH < 65536, "queue entries are 16-bit: cell * 2 + vertical");
 };
 
@@ -58,12 +58,12 @@ struct Geo {
 // 0 rows one after another, 1 rows unrolled (the compiler interleaves),
 // 2 all 49 loads issued before any arithmetic (needs ~200 registers); EV 3
 // evaluates with a quad of lanes instead (eval_quad).
-template <int LOG2N, int DW, int EV>
+template <int LOG2N, int DW, int EV, int RR = kR>
 __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__restrict__ Db, int W, int bx, int by) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * RR + 1;
   const int Wp = W + 2 * P;
   uint32_t s = 0;
-  const uint4 *pb = Db + ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W);
+  const uint4 *pb = Db + ffk::desc_index(bx - RR * n, by - RR * n, LOG2N, W);
   if constexpr (EV == 2) {
     uint4 b[K * K];
 #pragma unroll
@@ -73,14 +73,14 @@ __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__re
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int v = 0; v < K; ++v) {
-      const uint4 *ra = pa + (v - kR) * DW - kR;
+      const uint4 *ra = pa + (v - RR) * DW - RR;
 #pragma unroll
       for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], b[v * K + u], s);
     }
   } else {
 #pragma unroll EV ? K : 1
     for (int v = 0; v < K; ++v) {
-      const uint4 *ra = pa + (v - kR) * DW - kR;
+      const uint4 *ra = pa + (v - RR) * DW - RR;
 #pragma unroll
       for (int u = 0; u < K; ++u) s = ffk::sad16(ra[u], pb[u], s);
       pb += (size_t)n * Wp;
@@ -97,13 +97,13 @@ __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__re
 // resource over its padded map (the row offset rides in the scalar offset);
 // the partial sums are added across the quad, every lane returns the total.
 // Requires a map of less than 2^31 bytes.
-template <int LOG2N, int DW>
+template <int LOG2N, int DW, int RR = kR>
 __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
                                               int r) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * RR + 1;
   const int rowb = n * (W + 2 * P) * 16;
   const int u1 = r, u2 = min(r + 4, K - 1);
-  const int off = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
+  const int off = (int)ffk::desc_index(bx - RR * n, by - RR * n, LOG2N, W) * 16;
   uint4 b1[K], b2[K], a1[K], a2[K];
 #pragma unroll
   for (int v = 0; v < K; ++v) {
@@ -115,7 +115,7 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
   // image a's samples from LDS while the global loads are in flight: the
   // first column's now, the second's once half of the first is summed (so
   // that fewer than 128 registers hold the whole evaluation)
-  const uint4 *ra1 = pa - kR * DW - kR + u1, *ra2 = pa - kR * DW - kR + u2;
+  const uint4 *ra1 = pa - RR * DW - RR + u1, *ra2 = pa - RR * DW - RR + u2;
 #pragma unroll
   for (int v = 0; v < K; ++v) a1[v] = ra1[v * DW];
   __builtin_amdgcn_sched_barrier(0);
@@ -138,14 +138,14 @@ __device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_r
 
 // The same with image a's patch also read from its padded map (a quad per
 // evaluation; the cells the weight-class evaluation does not cover).
-template <int LOG2N>
+template <int LOG2N, int RR = kR>
 __device__ __forceinline__ uint32_t eval_quad_gg(__amdgpu_buffer_rsrc_t da, __amdgpu_buffer_rsrc_t db, int W, int ax,
                                                  int ay, int bx, int by, int r) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * kR + 1;
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * RR + 1;
   const int rowb = n * (W + 2 * P) * 16;
   const int u1 = r, u2 = min(r + 4, K - 1);
-  const int offa = (int)ffk::desc_index(ax - kR * n, ay - kR * n, LOG2N, W) * 16;
-  const int offb = (int)ffk::desc_index(bx - kR * n, by - kR * n, LOG2N, W) * 16;
+  const int offa = (int)ffk::desc_index(ax - RR * n, ay - RR * n, LOG2N, W) * 16;
+  const int offb = (int)ffk::desc_index(bx - RR * n, by - RR * n, LOG2N, W) * 16;
   uint32_t s1 = 0, s2 = 0;
 #pragma unroll
   for (int v = 0; v < K; ++v) {
@@ -238,9 +238,12 @@ __device__ __forceinline__ uint32_t eval_quad_f32(const float4 *pa, const float4
 
 // The run of passes for tile `tile` of one direction `d` (a holds the
 // pair's sizes and the schedule).  All threads of the workgroup call it.
-template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo, int RR = kR>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
-  using G = Geo<TW, TH, HALO>;
+  // patch radius RR: 3, or 2 with the descriptor-quad evaluations (the
+  // weight-class maps and the float path hold radius-3 patches)
+  static_assert(RR == kR || (RR == 2 && EV == 3 && !F32), "radius 2 runs the descriptor-quad kernels only");
+  using G = Geo<TW, TH, HALO, RR>;
   constexpr int n = 1 << LOG2N;
   // EV 3 and float features: every evaluation by a quad of lanes
   // (eval_quad, eval_quad_f32); the candidate flows of a random-search step
@@ -307,7 +310,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 #pragma unroll
     for (int it = 0; it < NS; ++it) {
       const int k = min(it * kThreads + tid, G::DH * G::DW - 1);
-      const int vi = gi0 - kR + k % G::DW, vj = gj0 - kR + k / G::DW;
+      const int vi = gi0 - RR + k % G::DW, vj = gj0 - RR + k / G::DW;
       v[it] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
     }
   } else {
@@ -316,15 +319,15 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 #pragma unroll
     for (int it = 0; it < NS; ++it) {
       const int k = min(it * kThreads + tid, 4 * G::DH * G::DW - 1);
-      const int c = k >> 2, vi = gi0 - kR + c % G::DW, vj = gj0 - kR + c / G::DW;
+      const int c = k >> 2, vi = gi0 - RR + c % G::DW, vj = gj0 - RR + c / G::DW;
       v[it] = Da[4 * ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W) + (k & 3)];
     }
   }
   // E_n of grid cell (i, j) and target pixel (bx, by), one lane per
   // evaluation (byte descriptors, EV 0-2)
   auto evalc = [&](int i, int j, int bx, int by) -> uint32_t {
-    const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-    return eval_cell<LOG2N, G::DW, (EV < 3 ? EV : 1)>(pa, Db, W, bx, by);
+    const uint4 *pa = s_da + (j - gj0 + RR) * G::DW + (i - gi0 + RR);
+    return eval_cell<LOG2N, G::DW, (EV < 3 ? EV : 1), RR>(pa, Db, W, bx, by);
   };
   // the same by a quad of lanes (QUAD only)
   [[maybe_unused]] const __amdgpu_buffer_rsrc_t db_rsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -332,11 +335,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       (int)((size_t)(H + 2 * ffk::desc_pad(n)) * (W + 2 * ffk::desc_pad(n)) * 16), 0x00020000);
   auto evalq = [&](int i, int j, int bx, int by) -> uint32_t {
     if constexpr (F32) {
-      const float4 *pa = s_daf + 4 * ((j - gj0 + kR) * G::DW + (i - gi0 + kR));
+      const float4 *pa = s_daf + 4 * ((j - gj0 + RR) * G::DW + (i - gi0 + RR));
       return eval_quad_f32<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by, qr);
     } else {
-      const uint4 *pa = s_da + (j - gj0 + kR) * G::DW + (i - gi0 + kR);
-      return eval_quad<LOG2N, G::DW>(pa, db_rsrc, W, bx, by, qr);
+      const uint4 *pa = s_da + (j - gj0 + RR) * G::DW + (i - gi0 + RR);
+      return eval_quad<LOG2N, G::DW, RR>(pa, db_rsrc, W, bx, by, qr);
     }
   };
   // evaluations computed (the work counters; a no-op without them), called
@@ -364,7 +367,7 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     return eval_wform<LOG2N, G::LW>(s_wa + (j - gj0) * G::LW + (i - gi0), wb_rsrc, W, bx, by);
   };
   [[maybe_unused]] auto evalg = [&](int i, int j, int bx, int by) -> uint32_t {
-    return eval_quad_gg<LOG2N>(da_rsrc, db_rsrc, W, i * n, j * n, bx, by, qr);
+    return eval_quad_gg<LOG2N, RR>(da_rsrc, db_rsrc, W, i * n, j * n, bx, by, qr);
   };
   // append of the lanes with `on` set, at the front (inn) or the back (!inn)
   // of the queue: one LDS atomic per wave and end
@@ -866,11 +869,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 // One workgroup per (direction, tile) of one pair; XCD-aware order.  At most
 // four waves per SIMD (two with EV = 2): the register budget then keeps the
 // loads of a patch in flight together instead of one after another.
-template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, int HALO, int RR = kR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV >= 3 ? 4 : 1, EV == 2 ? 2 : 4))) void k_level(ffh::LevelKArgs a) {
   const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
   const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
-  level_body<LOG2N, TW, TH, kThreads, EV, false, HALO>(a, a.dir[wg / tiles], wg % tiles);
+  level_body<LOG2N, TW, TH, kThreads, EV, false, HALO, RR>(a, a.dir[wg / tiles], wg % tiles);
 }
 
 // Float learned features (padded float maps in LevelKDir::Da/Db).
@@ -919,9 +922,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(EV >= 
   });
 }
 
-template <int LOG2N, int TW, int TH, int THREADS, int EV, int HALO = ffh::kLevelHalo>
+template <int LOG2N, int TW, int TH, int THREADS, int EV, int HALO = ffh::kLevelHalo, int RR = kR>
 hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipStream_t stream) {
-  if (batch) {
+  if constexpr (RR != kR) {
+    if (batch) return hipErrorInvalidValue;  // batches run radius 3
+  } else if (batch) {
     if (batch->total <= 0) return hipSuccess;
     // persistent: enough workgroups to fill the chip, a multiple of 8
     const int grid = ((std::min(batch->total, 2048) + 7) / 8) * 8;
@@ -932,7 +937,8 @@ hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipS
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
-  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV, HALO>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream, b);
+  hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV, HALO, RR>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream,
+                     b);
   return hipGetLastError();
 }
 
@@ -998,6 +1004,27 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 28: return launch_v<LOG2N, 8, 8, 1024, 4>(a, batch, stream);
     case 29: return launch_v<LOG2N, 8, 8, 1024, 4, 4>(a, batch, stream);
     case 30: return launch_v<LOG2N, 16, 16, 1024, 3>(a, batch, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Patch radius 2 (the second backward field of Sec. 3.7 in the conference
+// setting, r2 = 2): the descriptor-quad variants, same tiles and halos as
+// the indices of launch_n; r2_variant in ff_level.hip maps every other index
+// onto one of these with the same window halo.
+template <int LOG2N>
+hipError_t launch_n_r2(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
+  switch (variant) {
+    case 11: return launch_v<LOG2N, 16, 16, 256, 3, 2, 2>(a, nullptr, stream);
+    case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2, 2>(a, nullptr, stream);
+    case 13: return launch_v<LOG2N, 16, 16, 256, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
+    case 14: return launch_v<LOG2N, 8, 8, 256, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
+    case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2, 2>(a, nullptr, stream);
+    case 16: return launch_v<LOG2N, 32, 16, 256, 3, 4, 2>(a, nullptr, stream);
+    case 17: return launch_v<LOG2N, 16, 16, 256, 3, 4, 2>(a, nullptr, stream);
+    case 26: return launch_v<LOG2N, 8, 8, 1024, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
+    case 27: return launch_v<LOG2N, 8, 8, 1024, 3, 4, 2>(a, nullptr, stream);
+    case 30: return launch_v<LOG2N, 16, 16, 1024, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -11,4 +11,8 @@ hipError_t launch_level_f32_scale1(const LevelKArgs &a, int variant, hipStream_t
   return launch_nf32<1>(a, variant, stream);
 }
 
+hipError_t launch_level_r2_scale1(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_n_r2<1>(a, variant, stream);
+}
+
 }  // namespace ffh

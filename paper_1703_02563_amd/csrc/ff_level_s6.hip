@@ -11,4 +11,8 @@ hipError_t launch_level_f32_scale6(const LevelKArgs &a, int variant, hipStream_t
   return launch_nf32<6>(a, variant, stream);
 }
 
+hipError_t launch_level_r2_scale6(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_n_r2<6>(a, variant, stream);
+}
+
 }  // namespace ffh
