@@ -161,18 +161,18 @@ const char *ff_status_str(ff_status s);
  * weight-class row map of scale n (output, ff_wform_map_bytes), which the
  * level kernels with weight-class evaluations read.
  * Descriptor map layout (every entry point that takes a "descriptor map"
- * expects it): P = 3n, Wp = W + 2P; Hp = H + 2P rows of Wp 16-byte entries;
+ * expects it): P = 4n, Wp = W + 2P; Hp = H + 2P rows of Wp 16-byte entries;
  * entry (y + P, col(x + P)) holds desc[clamp(y)][clamp(x)] for x in
  * [-P, W + P), y in [-P, H + P) (replicated border), where inside a row the
  * pixels are grouped by phase, col(c) = (c mod n)*floor(Wp/n) +
  * min(c mod n, Wp mod n) + floor(c/n): the samples x + n*u of a patch row
- * are adjacent and a radius-3 patch around any in-image pixel needs no
+ * are adjacent and a patch of radius up to 4 around any in-image pixel needs no
  * clamping.  A scale that is not a power of two (a sub-scale, Sec. 3.3)
  * keeps the pixels of a row in image order, col(c) = c.  1 <= n <= 64. */
 ff_status ff_descriptors(const uint8_t *img, int32_t W, int32_t H, int32_t n, uint16_t *hsum,
                          uint8_t *blurred, uint8_t *desc, uint8_t *desc_rowmajor, uint8_t *wform, void *stream);
 
-/* Bytes of a descriptor map of scale n (host): (W + 6n) * (H + 6n) * 16;
+/* Bytes of a descriptor map of scale n (host): (W + 8n) * (H + 8n) * 16;
  * 0 for invalid sizes. */
 size_t ff_descriptor_map_bytes(int32_t W, int32_t H, int32_t n);
 

@@ -119,8 +119,11 @@ __global__ __launch_bounds__(256) void k_desc(ffh::DescJobs jobs) {
     }
   }
   __syncthreads();
-  if (jb.wform) {
-    uint4 *wout = reinterpret_cast<uint4 *>(jb.wform) + (size_t)yp * W;
+  // the weight-class map's rows y in [-3n, H + 3n) are a band of the
+  // descriptor map's rows [-4n, H + 4n): stored row y + 3n
+  const int ywf = yr + ffk::kWformPad * n;
+  if (jb.wform && ywf >= 0 && ywf < H + 2 * ffk::kWformPad * n) {
+    uint4 *wout = reinterpret_cast<uint4 *>(jb.wform) + (size_t)ywf * W;
     for (int x = threadIdx.x; x < W; x += blockDim.x) wout[x] = wform_entry(s_rows + 4 * Ws, W, n, x);
   }
   uint4 *out = reinterpret_cast<uint4 *>(jb.desc) + (size_t)yp * Wp;
@@ -202,14 +205,16 @@ __global__ __launch_bounds__(256) void k_desc_batch(ffh::BatchStage st) {
       for (int yp = yp0; yp < yp1; ++yp) map[(size_t)yp * Wp + c] = d;
       if (r.lv == 0 && xr >= 0 && xr < W) reinterpret_cast<uint4 *>(r.bp->desc1[r.im])[(size_t)r.y * W + xr] = d;
     }
-    // weight-class rows: the same stored rows (y + 3n), the first and last
-    // image rows replicated into the border rows
+    // weight-class rows: stored row y + 3n, the first and last image rows
+    // replicated into the 3n border rows
     uint4 *wmap = reinterpret_cast<uint4 *>(r.bp->wform[r.im][r.lv]);
     if (wmap) {
+      const int Pw = ffk::kWformPad * n;
+      const int wy0 = r.y == 0 ? 0 : r.y + Pw, wy1 = r.y == H - 1 ? H + 2 * Pw : r.y + Pw + 1;
       const uint8_t *brow = b + (size_t)r.y * W;
       for (int x = threadIdx.x; x < W; x += blockDim.x) {
         const uint4 e = wform_entry(brow, W, n, x);
-        for (int yp = yp0; yp < yp1; ++yp) wmap[(size_t)yp * W + x] = e;
+        for (int yw = wy0; yw < wy1; ++yw) wmap[(size_t)yw * W + x] = e;
       }
     }
   });

@@ -39,9 +39,9 @@ __device__ __forceinline__ int desc_col(int x, int log2n, int W) {
 // Scale-n descriptor maps also carry a border of kDescPad * n replicated
 // pixels on every side: the map holds D(clamp(x), clamp(y)) for x in
 // [-P, W + P), y in [-P, H + P), P = kDescPad * n, rows of width W + 2P in
-// phase order.  A radius-3 patch around any in-image target then reads the
-// map without clamping.  P is a multiple of n, so phases are unchanged.
-constexpr int kDescPad = 3;
+// phase order.  A patch of radius up to 4 around any in-image target then
+// reads the map without clamping.  P is a multiple of n, so phases are unchanged.
+constexpr int kDescPad = 4;
 
 __host__ __device__ __forceinline__ int desc_pad(int n) { return kDescPad * n; }
 

@@ -169,7 +169,7 @@ struct LevelKArgs {
   int mode;
   int fcost;    // 0: byte descriptor maps; 1: padded float feature maps (64-byte entries)
   int variant;  // the launch table's variant of this scale (byte or float table by fcost)
-  int radius;   // patch radius: 3, or 2 (byte descriptors only); 0 means 3
+  int radius;   // patch radius: 3, or 2 and 4 (byte descriptors only); 0 means 3
   int tiles_x;  // set by launch_level
   int halo[4];
 };
@@ -181,7 +181,8 @@ struct BatchStage;
 #define FF_LEVEL_SCALE_DECL(k)                                                                          \
   hipError_t launch_level_scale##k(const LevelKArgs &a, const BatchStage *batch, int variant, hipStream_t s); \
   hipError_t launch_level_f32_scale##k(const LevelKArgs &a, int variant, hipStream_t s); \
-  hipError_t launch_level_r2_scale##k(const LevelKArgs &a, int variant, hipStream_t s);
+  hipError_t launch_level_r2_scale##k(const LevelKArgs &a, int variant, hipStream_t s); \
+  hipError_t launch_level_r4_scale##k(const LevelKArgs &a, int variant, hipStream_t s);
 FF_LEVEL_SCALE_DECL(0)
 FF_LEVEL_SCALE_DECL(1)
 FF_LEVEL_SCALE_DECL(2)
@@ -198,8 +199,9 @@ void level_halo(int t_begin, int t_end, int halo[4]);
 int level_variant_count();      // byte-descriptor variants + the step-wise schedule
 int level_variant_count_f32();
 bool level_stepwise(int variant);  // the variant index that selects the step-wise schedule
-// The blocked kernels run this patch radius at these sizes (radius 3; radius
-// 2 with descriptor maps inside the 32-bit offsets of the quad evaluations).
+// The blocked kernels run this patch radius at these sizes (radius 3; radii
+// 2 and 4 with descriptor maps inside the 32-bit offsets of the quad
+// evaluations).
 bool level_blocked_ok(int W, int H, int L, int radius);
 
 // ---- batches of pairs of different sizes (one launch per stage) ----------

@@ -41,12 +41,16 @@ constexpr ScaleLaunchF32 kScaleR2[7] = {ffh::launch_level_r2_scale0, ffh::launch
                                         ffh::launch_level_r2_scale2, ffh::launch_level_r2_scale3,
                                         ffh::launch_level_r2_scale4, ffh::launch_level_r2_scale5,
                                         ffh::launch_level_r2_scale6};
+constexpr ScaleLaunchF32 kScaleR4[7] = {ffh::launch_level_r4_scale0, ffh::launch_level_r4_scale1,
+                                        ffh::launch_level_r4_scale2, ffh::launch_level_r4_scale3,
+                                        ffh::launch_level_r4_scale4, ffh::launch_level_r4_scale5,
+                                        ffh::launch_level_r4_scale6};
 
-// Radius-2 kernel of a table entry: the descriptor-quad variant with the
-// same window halo (the run lengths follow the table's halo) -- a
+// Radius-2 / radius-4 kernel of a table entry: the descriptor-quad variant
+// with the same window halo (the run lengths follow the table's halo) -- a
 // weight-class variant's quad twin, or for a one-lane variant (all of halo
 // kLevelHalo) the quad variant of that halo and a tile of the same class.
-int r2_variant(int v) {
+int quad_variant(int v) {
   v = kVariants[v].nowf;
   switch (v) {
     case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 26: case 27: case 30: return v;
@@ -153,7 +157,7 @@ static bool dirs_have_wform(const LevelKArgs &a) {
 
 bool level_blocked_ok(int W, int H, int L, int radius) {
   if (radius == 3) return true;
-  if (radius != 2) return false;
+  if (radius != 2 && radius != 4) return false;
   for (int l = 0; l < L; ++l)
     if (!level_map_fits(W, H, l)) return false;
   return true;
@@ -165,11 +169,11 @@ hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
     if (l2 < 0 || l2 >= 7) return hipErrorInvalidValue;
     return kScaleF32[l2](a, a.variant, stream);
   }
-  if (a.radius == 2) {
+  if (a.radius == 2 || a.radius == 4) {
     const int v = blocked_variant(a.variant);
     if (l2 < 0 || l2 >= 7 || v < 0 || v >= kNumVariants || !level_map_fits(a.W, a.H, l2))
       return hipErrorInvalidValue;
-    return kScaleR2[l2](a, r2_variant(v), stream);
+    return (a.radius == 2 ? kScaleR2 : kScaleR4)[l2](a, quad_variant(v), stream);
   }
   return dispatch(a, nullptr, l2, launch_variant(a.variant, level_map_fits(a.W, a.H, l2), dirs_have_wform(a)),
                   stream);

@@ -97,45 +97,77 @@ __device__ __forceinline__ uint32_t eval_cell(const uint4 *pa, const uint4 *__re
 // resource over its padded map (the row offset rides in the scalar offset);
 // the partial sums are added across the quad, every lane returns the total.
 // Requires a map of less than 2^31 bytes.
-template <int LOG2N, int DW, int RR = kR>
-__device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
-                                              int r) {
-  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * RR + 1;
+// E_n(p, f) of a radius-4 patch (9 x 9) by a quad: lane r takes columns
+// r, r + 4 and r + 8 (the last for lane 0 only), one column after another.
+template <int LOG2N, int DW>
+__device__ __forceinline__ uint32_t eval_quad9(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
+                                               int r) {
+  constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, RR = 4, K = 2 * RR + 1;
   const int rowb = n * (W + 2 * P) * 16;
-  const int u1 = r, u2 = min(r + 4, K - 1);
   const int off = (int)ffk::desc_index(bx - RR * n, by - RR * n, LOG2N, W) * 16;
-  uint4 b1[K], b2[K], a1[K], a2[K];
+  uint32_t s = 0;
 #pragma unroll
-  for (int v = 0; v < K; ++v) {
-    const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u1 * 16, v * rowb, 0);
-    const auto y = __builtin_amdgcn_raw_buffer_load_b128(db, off + u2 * 16, v * rowb, 0);
-    b1[v] = make_uint4(x[0], x[1], x[2], x[3]);
-    b2[v] = make_uint4(y[0], y[1], y[2], y[3]);
+  for (int c = 0; c < 3; ++c) {
+    const int u = min(r + 4 * c, K - 1);
+    uint4 b[K];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u * 16, v * rowb, 0);
+      b[v] = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+    const uint4 *ra = pa - RR * DW - RR + u;
+    uint32_t t = 0;
+#pragma unroll
+    for (int v = 0; v < K; ++v) t = ffk::sad16(ra[v * DW], b[v], t);
+    s += (r + 4 * c < K) ? t : 0u;
   }
-  // image a's samples from LDS while the global loads are in flight: the
-  // first column's now, the second's once half of the first is summed (so
-  // that fewer than 128 registers hold the whole evaluation)
-  const uint4 *ra1 = pa - RR * DW - RR + u1, *ra2 = pa - RR * DW - RR + u2;
-#pragma unroll
-  for (int v = 0; v < K; ++v) a1[v] = ra1[v * DW];
-  __builtin_amdgcn_sched_barrier(0);
-  uint32_t s1 = 0, s2 = 0;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int v = 0; v < K; ++v) a2[v] = ra2[v * DW];
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int v = 4; v < K; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
-#pragma unroll
-  for (int v = 0; v < K; ++v) s2 = ffk::sad16(a2[v], b2[v], s2);
-  uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
   s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
   s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
   return s;
 }
 
+template <int LOG2N, int DW, int RR = kR>
+__device__ __forceinline__ uint32_t eval_quad(const uint4 *pa, __amdgpu_buffer_rsrc_t db, int W, int bx, int by,
+                                              int r) {
+  if constexpr (RR == 4) {
+    return eval_quad9<LOG2N, DW>(pa, db, W, bx, by, r);
+  } else {
+    constexpr int n = 1 << LOG2N, P = ffk::kDescPad * n, K = 2 * RR + 1;
+    const int rowb = n * (W + 2 * P) * 16;
+    const int u1 = r, u2 = min(r + 4, K - 1);
+    const int off = (int)ffk::desc_index(bx - RR * n, by - RR * n, LOG2N, W) * 16;
+    uint4 b1[K], b2[K], a1[K], a2[K];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const auto x = __builtin_amdgcn_raw_buffer_load_b128(db, off + u1 * 16, v * rowb, 0);
+      const auto y = __builtin_amdgcn_raw_buffer_load_b128(db, off + u2 * 16, v * rowb, 0);
+      b1[v] = make_uint4(x[0], x[1], x[2], x[3]);
+      b2[v] = make_uint4(y[0], y[1], y[2], y[3]);
+    }
+    // image a's samples from LDS while the global loads are in flight: the
+    // first column's now, the second's once half of the first is summed (so
+    // that fewer than 128 registers hold the whole evaluation)
+    const uint4 *ra1 = pa - RR * DW - RR + u1, *ra2 = pa - RR * DW - RR + u2;
+#pragma unroll
+    for (int v = 0; v < K; ++v) a1[v] = ra1[v * DW];
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < K; ++v) a2[v] = ra2[v * DW];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 4; v < K; ++v) s1 = ffk::sad16(a1[v], b1[v], s1);
+#pragma unroll
+    for (int v = 0; v < K; ++v) s2 = ffk::sad16(a2[v], b2[v], s2);
+    uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
+    s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    return s;
+}
+}
 // The same with image a's patch also read from its padded map (a quad per
 // evaluation; the cells the weight-class evaluation does not cover).
 template <int LOG2N, int RR = kR>
@@ -240,9 +272,10 @@ __device__ __forceinline__ uint32_t eval_quad_f32(const float4 *pa, const float4
 // pair's sizes and the schedule).  All threads of the workgroup call it.
 template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo, int RR = kR>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
-  // patch radius RR: 3, or 2 with the descriptor-quad evaluations (the
-  // weight-class maps and the float path hold radius-3 patches)
-  static_assert(RR == kR || (RR == 2 && EV == 3 && !F32), "radius 2 runs the descriptor-quad kernels only");
+  // patch radius RR: 3, or 2 and 4 with the descriptor-quad evaluations
+  // (the weight-class maps and the float path hold radius-3 patches)
+  static_assert(RR == kR || ((RR == 2 || RR == 4) && EV == 3 && !F32),
+                "radii 2 and 4 run the descriptor-quad kernels only");
   using G = Geo<TW, TH, HALO, RR>;
   constexpr int n = 1 << LOG2N;
   // EV 3 and float features: every evaluation by a quad of lanes
@@ -1008,23 +1041,24 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
   }
 }
 
-// Patch radius 2 (the second backward field of Sec. 3.7 in the conference
-// setting, r2 = 2): the descriptor-quad variants, same tiles and halos as
-// the indices of launch_n; r2_variant in ff_level.hip maps every other index
-// onto one of these with the same window halo.
-template <int LOG2N>
-hipError_t launch_n_r2(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
+// Patch radii 2 and 4 (the second backward field of Sec. 3.7 in the
+// conference setting, r2 = 2; the radius r = 4 of Flow Fields+, Sec. 4.1):
+// the descriptor-quad variants, same tiles and halos as the indices of
+// launch_n; quad_variant in ff_level.hip maps every other index onto one of
+// these with the same window halo.
+template <int LOG2N, int RR>
+hipError_t launch_n_rx(const ffh::LevelKArgs &a, int variant, hipStream_t stream) {
   switch (variant) {
-    case 11: return launch_v<LOG2N, 16, 16, 256, 3, 2, 2>(a, nullptr, stream);
-    case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2, 2>(a, nullptr, stream);
-    case 13: return launch_v<LOG2N, 16, 16, 256, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
-    case 14: return launch_v<LOG2N, 8, 8, 256, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
-    case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2, 2>(a, nullptr, stream);
-    case 16: return launch_v<LOG2N, 32, 16, 256, 3, 4, 2>(a, nullptr, stream);
-    case 17: return launch_v<LOG2N, 16, 16, 256, 3, 4, 2>(a, nullptr, stream);
-    case 26: return launch_v<LOG2N, 8, 8, 1024, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
-    case 27: return launch_v<LOG2N, 8, 8, 1024, 3, 4, 2>(a, nullptr, stream);
-    case 30: return launch_v<LOG2N, 16, 16, 1024, 3, ffh::kLevelHalo, 2>(a, nullptr, stream);
+    case 11: return launch_v<LOG2N, 16, 16, 256, 3, 2, RR>(a, nullptr, stream);
+    case 12: return launch_v<LOG2N, 32, 16, 256, 3, 2, RR>(a, nullptr, stream);
+    case 13: return launch_v<LOG2N, 16, 16, 256, 3, ffh::kLevelHalo, RR>(a, nullptr, stream);
+    case 14: return launch_v<LOG2N, 8, 8, 256, 3, ffh::kLevelHalo, RR>(a, nullptr, stream);
+    case 15: return launch_v<LOG2N, 8, 8, 256, 3, 2, RR>(a, nullptr, stream);
+    case 16: return launch_v<LOG2N, 32, 16, 256, 3, 4, RR>(a, nullptr, stream);
+    case 17: return launch_v<LOG2N, 16, 16, 256, 3, 4, RR>(a, nullptr, stream);
+    case 26: return launch_v<LOG2N, 8, 8, 1024, 3, ffh::kLevelHalo, RR>(a, nullptr, stream);
+    case 27: return launch_v<LOG2N, 8, 8, 1024, 3, 4, RR>(a, nullptr, stream);
+    case 30: return launch_v<LOG2N, 16, 16, 1024, 3, ffh::kLevelHalo, RR>(a, nullptr, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -12,7 +12,11 @@ hipError_t launch_level_f32_scale0(const LevelKArgs &a, int variant, hipStream_t
 }
 
 hipError_t launch_level_r2_scale0(const LevelKArgs &a, int variant, hipStream_t stream) {
-  return launch_n_r2<0>(a, variant, stream);
+  return launch_n_rx<0, 2>(a, variant, stream);
+}
+
+hipError_t launch_level_r4_scale0(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_n_rx<0, 4>(a, variant, stream);
 }
 
 }  // namespace ffh

@@ -12,7 +12,11 @@ hipError_t launch_level_f32_scale4(const LevelKArgs &a, int variant, hipStream_t
 }
 
 hipError_t launch_level_r2_scale4(const LevelKArgs &a, int variant, hipStream_t stream) {
-  return launch_n_r2<4>(a, variant, stream);
+  return launch_n_rx<4, 2>(a, variant, stream);
+}
+
+hipError_t launch_level_r4_scale4(const LevelKArgs &a, int variant, hipStream_t stream) {
+  return launch_n_rx<4, 4>(a, variant, stream);
 }
 
 }  // namespace ffh

@@ -106,19 +106,19 @@ def cells(W: int, H: int, n: int):
 
 def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False, wform: bool = False):
     """Scale-space image and the descriptor map of scale n: uint8
-    [H + 6n, W + 6n, 16], a replicated border of 3n pixels, the pixels of a
+    [H + 8n, W + 8n, 16], a replicated border of 4n pixels, the pixels of a
     row in phase order (x mod n, then x // n); the layout every entry point
     taking a descriptor map expects (see ff_descriptors).  rowmajor=True also
     returns the plain [H, W, 16] descriptors (the NN seed's input);
     wform=True also returns the weight-class row map uint8 [H + 6n, W, 16]
     (ff_wform_map_bytes).  Returns (blurred, desc[, plain][, wform])."""
     H, W = img.shape
-    P = 3 * n
+    P = 4 * n
     hsum = torch.empty((H, W), dtype=torch.int16, device=img.device)
     blurred = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     desc = torch.empty((H + 2 * P, W + 2 * P, 16), dtype=torch.uint8, device=img.device)
     plain = torch.empty((H, W, 16), dtype=torch.uint8, device=img.device) if rowmajor else None
-    wf = torch.empty((H + 2 * P, W, 16), dtype=torch.uint8, device=img.device) if wform else None
+    wf = torch.empty((H + 6 * n, W, 16), dtype=torch.uint8, device=img.device) if wform else None  # 3n border rows
     assert desc.numel() == int(lib().ff_descriptor_map_bytes(W, H, n))
     assert wf is None or wf.numel() == int(lib().ff_wform_map_bytes(W, H, n))
     check(lib().ff_descriptors(_ptr(img, torch.uint8, "img"), W, H, n, _ptr(hsum), _ptr(blurred), _ptr(desc),
@@ -134,9 +134,9 @@ def descriptors(img: torch.Tensor, n: int, rowmajor: bool = False, wform: bool =
 def _map_dims(desc_a, desc_b, n: int):
     """(W, H) of the image behind two descriptor maps of scale n."""
     Hp, Wp = desc_a.shape[:2]
-    W, H = Wp - 6 * n, Hp - 6 * n
+    W, H = Wp - 8 * n, Hp - 8 * n
     if W < 1 or H < 1 or tuple(desc_b.shape) != tuple(desc_a.shape) or desc_a.shape[2:] != (16,):
-        raise ValueError("descriptor maps must both be uint8 [H + 6n, W + 6n, 16]")
+        raise ValueError("descriptor maps must both be uint8 [H + 8n, W + 8n, 16]")
     return W, H
 
 

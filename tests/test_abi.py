@@ -110,13 +110,13 @@ def test_python_binding_rejects_host_tensors():
 
 
 def test_descriptor_map_bytes():
-    """Padded descriptor maps: (W + 6n) x (H + 6n) entries of 16 bytes."""
+    """Padded descriptor maps: (W + 8n) x (H + 8n) entries of 16 bytes."""
     lib = ff.lib()
     for W, H, n in [(1024, 436, 1), (1024, 436, 16), (1, 1, 64), (37, 53, 4)]:
-        assert lib.ff_descriptor_map_bytes(W, H, n) == (W + 6 * n) * (H + 6 * n) * 16
+        assert lib.ff_descriptor_map_bytes(W, H, n) == (W + 8 * n) * (H + 8 * n) * 16
     assert lib.ff_descriptor_map_bytes(0, 5, 1) == 0
-    # a sub-scale (not a power of two) has the same padding: 3 n per side
-    assert lib.ff_descriptor_map_bytes(5, 5, 3) == (5 + 18) * (5 + 18) * 16
+    # a sub-scale (not a power of two) has the same padding: 4 n per side
+    assert lib.ff_descriptor_map_bytes(5, 5, 3) == (5 + 24) * (5 + 24) * 16
     assert lib.ff_descriptor_map_bytes(5, 5, 65) == 0 and lib.ff_descriptor_map_bytes(5, 5, 0) == 0
     assert lib.ff_descriptor_map_bytes(5, 5, 128) == 0
 

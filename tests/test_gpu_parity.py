@@ -47,8 +47,8 @@ def phase_columns(Wp, n):
 
 def to_lib(D, n):
     """Row-major [H][W][16] descriptors -> the library's descriptor map:
-    replicated border of 3n pixels, rows in phase order."""
-    P = 3 * n
+    replicated border of 4n pixels, rows in phase order."""
+    P = 4 * n
     H, W = D.shape[:2]
     padded = D[np.clip(np.arange(-P, H + P), 0, H - 1)][:, np.clip(np.arange(-P, W + P), 0, W - 1)]
     out = np.empty_like(padded)
@@ -74,7 +74,7 @@ def wform_lib(B, n):
 
 def from_lib(M, n):
     """Descriptor map -> row-major [H][W][16] (drops the border)."""
-    P = 3 * n
+    P = 4 * n
     Hp, Wp = M.shape[:2]
     padded = M[:, phase_columns(Wp, n)]
     return np.ascontiguousarray(padded[P:Hp - P, P:Wp - P])
@@ -95,7 +95,7 @@ def test_descriptors_bit_exact(shape, n):
     assert np.array_equal(host(plain), ed)
     assert np.array_equal(from_lib(host(desc), n), ed)
     assert np.array_equal(host(desc), to_lib(ed, n))  # the replicated border as well
-    Wp = shape[1] + 6 * n
+    Wp = shape[1] + 8 * n
     assert sorted(phase_columns(Wp, n)) == list(range(Wp))  # a permutation
 
 

@@ -19,8 +19,8 @@ NT = max(1, min(16, os.cpu_count() or 1))
 
 def to_lib_plain(D, m):
     """Row-major descriptors -> the map of a sub-scale m: replicated border
-    of 3m pixels, the pixels of a row in image order."""
-    P = 3 * m
+    of 4m pixels, the pixels of a row in image order."""
+    P = 4 * m
     H, W = D.shape[:2]
     return np.ascontiguousarray(D[np.clip(np.arange(-P, H + P), 0, H - 1)][:, np.clip(np.arange(-P, W + P), 0, W - 1)])
 
