@@ -249,6 +249,8 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
     for name, kw, n_reps in (("plus", plus, reps), ("plus_fast", dict(plus, fine_iters=4), reps),
                              # Sec. 3.3: a stage of patch scale 3n/2 before every scale below the coarsest
                              ("plus_subscales", dict(plus, subscales=True), 5),
+                             # the paper's Flow Fields+ patch radius (Sec. 4.1: r = 4)
+                             ("plus_r4", dict(plus, radius=4), reps),
                              # Sec. 3.4: no finest scale, 4 x R on scale 2, one match per 2x2 region
                              ("plus_fast_x2", dict(plus, fine_iters=4, fast_x2=True), reps),
                              # Eq. 4 with the paper's leaf size l = 8 (Sec. 4.1)
@@ -275,7 +277,8 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
                      "steps": f"{prm.plus_iters} x R+ then {prm.iters} x R"
                               + (f", finest {prm.fine_iters} x R" if prm.fine_iters else "")
                               + (", finest scale skipped, grid of scale 2" if prm.fast_x2 else "")
-                              + (", sub-scales 3n/2" if prm.subscales else ""),
+                              + (", sub-scales 3n/2" if prm.subscales else "")
+                              + (f", patch radius {prm.radius}" if prm.radius != params.radius else ""),
                      "n_evals": [int(v) for v in out["n_evals"].cpu()], "epe_raw": round(q["epe"], 4),
                      "le3px": round(q["le3px"], 4), "kept_density": round(q["kept_density"], 4),
                      "kept_epe": round(q["kept_epe"], 4)}
@@ -299,7 +302,7 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
                        "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4),
                        "kept_density": round(q["kept_density"], 4), "kept_epe": round(q["kept_epe"], 4)}
     # the original schedule with the check against two backward fields (Sec. 3.7; second field: seed + 1,
-    # patch radius 2)
+    # patch radius 2; Sec. 4.1: r = 3, r2 = 2 for the conference approach)
     run2 = lambda: ff.flow_fields_two_backward(img1, img2, params, radius2=2)  # noqa: E731
     for _ in range(3):
         run2()
