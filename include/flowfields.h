@@ -452,9 +452,12 @@ ff_status ff_cost_f32_fwd(const float *f1, const float *f2, int32_t W, int32_t H
 /* Gradient of sum_e grad_cost[e] * cost[e] with respect to f1 and f2
  * (d/df1 = +2 g (f1 - f2), d/df2 = -2 g (f1 - f2) at every patch position).
  * Contributions are summed in 64-bit fixed point (2^-32 units) with integer
- * atomics, so the result is deterministic; every |2 g (f1 - f2)| must stay
- * below 2^31.  acc_scratch: int64 [2][H][W][16] scratch (cleared here);
- * grad_f1, grad_f2: float32 [H][W][16] outputs (overwritten). */
+ * atomics, so the result is deterministic.  A term |2 g (f1 - f2)| of 2^31
+ * or more, or a partial sum outside the int64 range, is detected and counted in
+ * the last word of acc_scratch; when that count is nonzero every value of
+ * grad_f1 and grad_f2 is NaN (never a wrapped sum).  acc_scratch: int64
+ * [2 * H * W * 16 + 1] scratch (cleared here); grad_f1, grad_f2: float32
+ * [H][W][16] outputs (overwritten). */
 ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
                           const int32_t *entries, int32_t count, const float *grad_cost, int64_t *acc_scratch,
                           float *grad_f1, float *grad_f2, void *stream);

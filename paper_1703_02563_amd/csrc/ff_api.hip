@@ -722,6 +722,7 @@ ff_status ff_cost_f32_bwd(const float *f1, const float *f2, int32_t W, int32_t H
   a.grad_cost = grad_cost;
   a.acc1 = acc_scratch;
   a.acc2 = acc_scratch + (size_t)W * H * 16;
+  a.overflow = acc_scratch + (size_t)2 * W * H * 16;
   a.grad_f1 = grad_f1;
   a.grad_f2 = grad_f2;
   return from_hip(ffh::launch_cost_bwd(a, (hipStream_t)stream));

@@ -13,7 +13,12 @@
 // per patch position.  Many entries touch the same pixels, and float
 // atomics would make the sums depend on arrival order; each contribution is
 // therefore rounded once to 64-bit fixed point (2^-32 units) and added with
-// integer atomics, which are associative: the result is deterministic.
+// integer atomics, which are associative: the result is deterministic.  A
+// term of magnitude 2^31 or more, or a sum that leaves the int64 range,
+// would wrap: both are detected (the atomic returns the previous value, so
+// the adding thread sees a signed overflow) and counted in an overflow word
+// after the accumulators; a nonzero count turns every gradient output into
+// NaN instead of a wrapped value.
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -66,6 +71,7 @@ __global__ __launch_bounds__(256) void k_cost_bwd(ffh::CostArgs a) {
   const int4 en = a.entries[e];
   const double g2 = 2.0 * (double)a.grad_cost[e];
   if (g2 == 0.0) return;
+  unsigned long long *over = reinterpret_cast<unsigned long long *>(a.overflow);
   const int Wm = a.W - 1, Hm = a.H - 1, n = a.n;
   const size_t q = (size_t)clampi(en.y + n * v, Hm) * a.W + clampi(en.x + n * u, Wm);
   const size_t t = (size_t)clampi(en.y + en.w + n * v, Hm) * a.W + clampi(en.x + en.z + n * u, Wm);
@@ -75,17 +81,26 @@ __global__ __launch_bounds__(256) void k_cost_bwd(ffh::CostArgs a) {
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     const double d = g2 * ((double)pa[c] - (double)pb[c]);
+    if (!(fabs(d) < 2147483648.0)) {  // |term| >= 2^31 (or NaN): no int64 fixed-point value
+      atomicAdd(over, 1ull);
+      continue;
+    }
     const long long fx = __double2ll_rn(d * kFix);
     if (fx != 0) {
-      atomicAdd(acc1 + c, (unsigned long long)fx);
-      atomicAdd(acc2 + c, (unsigned long long)(-fx));
+      // signed overflow of old + x: both operands of one sign, the sum of the other
+      const long long o1 = (long long)atomicAdd(acc1 + c, (unsigned long long)fx);
+      const long long o2 = (long long)atomicAdd(acc2 + c, (unsigned long long)(-fx));
+      const long long n1 = (long long)((unsigned long long)o1 + (unsigned long long)fx);
+      const long long n2 = (long long)((unsigned long long)o2 - (unsigned long long)fx);
+      if ((((o1 ^ n1) & (fx ^ n1)) | ((o2 ^ n2) & (-fx ^ n2))) < 0) atomicAdd(over, 1ull);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_fixed_to_float(const int64_t *acc, float *out, long long count) {
+__global__ __launch_bounds__(256) void k_fixed_to_float(const int64_t *acc, const int64_t *overflow, float *out,
+                                                        long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = (float)((double)acc[i] * (1.0 / kFix));
+  if (i < count) out[i] = *overflow ? __builtin_nanf("") : (float)((double)acc[i] * (1.0 / kFix));
 }
 
 // Padded, phase-ordered copy of a float feature map (the layout of the
@@ -131,16 +146,16 @@ hipError_t launch_cost_fwd(const CostArgs &a, hipStream_t stream) {
 
 hipError_t launch_cost_bwd(const CostArgs &a, hipStream_t stream) {
   const long long px = (long long)a.W * a.H * 16;
-  hipError_t e = launch_fill_u64(reinterpret_cast<uint64_t *>(a.acc1), 0, px, stream);
-  if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t *>(a.acc2), 0, px, stream);
+  // acc1, acc2 and the overflow word after them are one array
+  hipError_t e = launch_fill_u64(reinterpret_cast<uint64_t *>(a.acc1), 0, 2 * px + 1, stream);
   if (e != hipSuccess) return e;
   const int side = 2 * a.radius + 1;
   const long long work = (long long)a.count * side * side;
   if (work > 0)
     hipLaunchKernelGGL(k_cost_bwd, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, stream, a);
   const dim3 g((unsigned)((px + 255) / 256));
-  hipLaunchKernelGGL(k_fixed_to_float, g, dim3(256), 0, stream, a.acc1, a.grad_f1, px);
-  hipLaunchKernelGGL(k_fixed_to_float, g, dim3(256), 0, stream, a.acc2, a.grad_f2, px);
+  hipLaunchKernelGGL(k_fixed_to_float, g, dim3(256), 0, stream, a.acc1, a.overflow, a.grad_f1, px);
+  hipLaunchKernelGGL(k_fixed_to_float, g, dim3(256), 0, stream, a.acc2, a.overflow, a.grad_f2, px);
   return hipGetLastError();
 }
 

@@ -255,7 +255,8 @@ struct CostArgs {
   int W, H, n, radius;
   float *cost;            // forward output [count]
   const float *grad_cost; // backward input [count]
-  int64_t *acc1, *acc2;   // backward fixed-point accumulators [H][W][16]
+  int64_t *acc1, *acc2;   // backward fixed-point accumulators [H][W][16] (acc2 = acc1 + H*W*16)
+  int64_t *overflow;      // one word after acc2: count of terms or sums that left the fixed-point range
   float *grad_f1, *grad_f2;
 };
 hipError_t launch_cost_fwd(const CostArgs &a, hipStream_t stream);

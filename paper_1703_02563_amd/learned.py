@@ -25,12 +25,22 @@ def cost_f32(f1: torch.Tensor, f2: torch.Tensor, entries: torch.Tensor, n: int =
     return cost
 
 
+def acc_scratch(W: int, H: int, device):
+    """Scratch of ff_cost_f32_bwd: two int64 [H, W, 16] accumulators and one
+    overflow word."""
+    return torch.empty(2 * H * W * 16 + 1, dtype=torch.int64, device=device)
+
+
 def cost_f32_grad(f1, f2, entries, grad_cost, n: int = 1, radius: int = 3, out=None, acc=None):
     """Gradients (d/df1, d/df2) of sum_e grad_cost[e] * cost[e]; `out` may
-    name the two output tensors, `acc` the int64 [2, H, W, 16] scratch."""
+    name the two output tensors, `acc` the int64 [2 * H * W * 16 + 1] scratch
+    (the accumulators and their overflow count; the gradients are NaN when it
+    is nonzero)."""
     H, W, _ = f1.shape
     if acc is None:
-        acc = torch.empty((2, H, W, 16), dtype=torch.int64, device=f1.device)
+        acc = acc_scratch(W, H, f1.device)
+    if acc.dtype != torch.int64 or acc.numel() < 2 * H * W * 16 + 1 or not acc.is_contiguous():
+        raise ValueError("acc: contiguous int64 scratch of 2 * H * W * 16 + 1 words expected")
     g1, g2 = out if out is not None else (torch.empty_like(f1), torch.empty_like(f2))
     check(lib().ff_cost_f32_bwd(_ptr(f1, torch.float32, "f1"), _ptr(f2, torch.float32, "f2"), W, H, n, radius,
                                 _ptr(entries, torch.int32, "entries"), entries.shape[0],
@@ -287,7 +297,7 @@ def train_step(net: DescNet, batch, rng, samples: int = 4096, margin: float = 1.
         picks.append(torch.cat([pe, ne]).contiguous())
     total = sum(len(e) // 2 for e in picks)
     grad = torch.empty_like(feats)
-    acc = torch.empty((2, H, W, 16), dtype=torch.int64, device=dev)
+    acc = acc_scratch(W, H, dev)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     for k, entries in enumerate(picks):
         m = len(entries) // 2

@@ -384,3 +384,27 @@ def test_learned_level_kernel_costs_within_float64_bound(shape, L, T):
         ref = cost_f64(fa, fb, ent, 1, 3)
         got = bits_[ys, xs].view(np.float32).astype(np.float64)
         assert np.all(np.abs(got - ref) <= 784 * 2.0 ** -24 * ref + 1e-30), float(np.max(np.abs(got - ref) / ref))
+
+
+def test_cost_grad_overflow_gives_nan_not_a_wrapped_sum():
+    """The fixed-point accumulators cover |sum| < 2^31: a single term of 2^31
+    or more, and sums of smaller terms that pass 2^31, make every gradient
+    output NaN; the next call within range clears the overflow count."""
+    H, W = 12, 14
+    f1 = torch.zeros((H, W, 16), device="cuda")
+    f2 = torch.zeros((H, W, 16), device="cuda")
+    f1[..., 0] = 1.0  # f1 - f2 = 1 in channel 0 everywhere
+    one = torch.tensor([[3, 4, 2, 1]], dtype=torch.int32, device="cuda")
+    acc = Lm.acc_scratch(W, H, "cuda")
+    # one term 2 g (f1 - f2) = 2^31: out of range
+    g1, g2 = Lm.cost_f32_grad(f1, f2, one, torch.tensor([2.0 ** 30], device="cuda"), acc=acc)
+    assert torch.isnan(g1).all() and torch.isnan(g2).all()
+    # terms of 2^30 each, three on the same pixels: the sum passes 2^31
+    three = one.repeat(3, 1)
+    g1, g2 = Lm.cost_f32_grad(f1, f2, three, torch.full((3,), 2.0 ** 29, device="cuda"), acc=acc)
+    assert torch.isnan(g1).all() and torch.isnan(g2).all()
+    # within range on the same scratch: finite, exact sums of the terms
+    g1, g2 = Lm.cost_f32_grad(f1, f2, three, torch.full((3,), 2.0 ** 20, device="cuda"), acc=acc)
+    assert torch.isfinite(g1).all() and torch.isfinite(g2).all()
+    assert float(g1[..., 0].max()) == 3 * 2.0 ** 21 and float(g2[..., 0].min()) == -3 * 2.0 ** 21
+    assert float(g1[..., 1:].abs().max()) == 0.0
