@@ -343,9 +343,11 @@ def schedule_leg(ff, torch, img1, img2, params, pair, reps=20):
 
 def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
     """DescNet trained on the plain method's consistent matches (16 training
-    pairs of the learned workload), judged by the mean ground-truth EPE on
-    held-out pairs of that workload against the plain field (fallback to
-    plain when it is worse), then
+    pairs of the learned workload), judged on held-out pairs of that
+    workload against the plain field by the mean ground-truth EPE of the
+    whole field and of the matches the consistency check keeps (Sec. 3.7),
+    with the per-pair spread; fallback to plain when it is worse on either,
+    then
     timed on the 1024x436 pair: descriptor network on every scale image of
     both images + learned-feature fields fwd+bwd + consistency."""
     import numpy as np
@@ -377,12 +379,28 @@ def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
     def epe(o, p):
         return epe_stats(o["flow_fwd"].cpu().numpy(), p.flow_gt, p.occ, keep=o["keep_fwd"].cpu().numpy())
 
-    val_plain, val_learned = [], []
+    # the judge: raw EPE of the whole field and EPE of the matches the
+    # consistency check keeps, per held-out pair, plain beside learned
+    keys = ("epe", "kept_epe", "le3px", "kept_density")
+    val = {"plain": {k: [] for k in keys}, "learned": {k: [] for k in keys}}
     for k in range(args.val_pairs):
         p, i1, i2 = dev_pair(5, args.train_pairs + k)
-        val_plain.append(epe(ff.flow_fields(i1, i2, params), p)["epe"])
-        val_learned.append(epe(Lm.learned_flow_fields(net, i1, i2, params), p)["epe"])
-    fallback = float(np.mean(val_learned)) > float(np.mean(val_plain))
+        for name, o in (("plain", ff.flow_fields(i1, i2, params)),
+                        ("learned", Lm.learned_flow_fields(net, i1, i2, params))):
+            q = epe(o, p)
+            for key in keys:
+                val[name][key].append(round(q[key], 4))
+    mean = {name: {key: round(float(np.mean(v)), 4) for key, v in d.items()} for name, d in val.items()}
+    d_raw = np.subtract(val["learned"]["epe"], val["plain"]["epe"])
+    d_kept = np.subtract(val["learned"]["kept_epe"], val["plain"]["kept_epe"])
+    worse_raw = mean["learned"]["epe"] > mean["plain"]["epe"]
+    worse_kept = mean["learned"]["kept_epe"] > mean["plain"]["kept_epe"]
+    fallback = bool(worse_raw or worse_kept)
+    verdict = (f"learned {'worse' if worse_raw else 'better or equal'} on mean raw EPE by "
+               f"{abs(float(d_raw.mean())):.3f} px (better on {int((d_raw < 0).sum())}/{len(d_raw)} pairs), "
+               f"{'worse' if worse_kept else 'better or equal'} on mean kept EPE by {abs(float(d_kept.mean())):.3f} px "
+               f"(better on {int((d_kept < 0).sum())}/{len(d_kept)} pairs): "
+               f"{'fall back to plain descriptors' if fallback else 'learned descriptors kept'}")
 
     run = lambda: Lm.learned_flow_fields(net, img1, img2, params)  # noqa: E731
     for _ in range(2):
@@ -408,8 +426,11 @@ def learned_leg(ff, torch, img1, img2, params, pair, plain_ms, args):
             "descnet_ms": round(net_ms, 3), "ratio_vs_plain": round(plain_ms / ms, 4),
             "epe_raw": round(q["epe"], 4), "le3px": round(q["le3px"], 4), "kept_epe": round(q["kept_epe"], 4),
             "kept_density": round(q["kept_density"], 4),
-            "val_epe_plain": [round(v, 4) for v in val_plain], "val_epe_learned": [round(v, 4) for v in val_learned],
-            "fallback_to_plain": fallback, "train_pairs": args.train_pairs, "train_steps": args.train_steps,
+            "val_pairs": args.val_pairs, "val_per_pair": val, "val_mean": mean,
+            "val_learned_minus_plain": {"epe": [round(float(v), 4) for v in d_raw],
+                                        "kept_epe": [round(float(v), 4) for v in d_kept]},
+            "verdict": verdict, "fallback_to_plain": fallback,
+            "train_pairs": args.train_pairs, "train_steps": args.train_steps,
             "train_samples_per_pair": args.train_samples, "train_s": round(train_s, 2),
             "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)] if losses else None,
             "dtype": "bf16 network, f32 cost"}
@@ -428,7 +449,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 160x120 and 1242x375 pairs (GPU beside the oracle)")
     ap.add_argument("--train-steps", type=int, default=150)
-    ap.add_argument("--val-pairs", type=int, default=4, help="held-out pairs of the EPE judge")
+    ap.add_argument("--val-pairs", type=int, default=8, help="held-out pairs of the EPE judge")
     ap.add_argument("--train-pairs", type=int, default=16)
     ap.add_argument("--train-samples", type=int, default=1024, help="triplets per training pair and step")
     ap.add_argument("--train-lr", type=float, default=1e-3)

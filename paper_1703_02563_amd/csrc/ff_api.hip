@@ -1339,8 +1339,24 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
     if ((e = ffh::launch_rerank(ra, cand, params->nn_l, s)) != hipSuccess) return FF_ERR_LAUNCH;
   }
 
-  if (sb == 0 && !params->raster && !params->subscales && ffh::level_blocked_ok(W, H, L, r)) {
-    // temporally blocked level kernels: one launch per run of passes
+  // stages coarse to fine: (scale 2^lv, patch scale m, entry), entry 0:
+  // the NN initialisation, 1: the same grid at a new patch scale, 2: the
+  // hand-over from the coarser grid
+  int stage_lv[2 * kMaxLevels], stage_m[2 * kMaxLevels], stage_entry[2 * kMaxLevels], nst = 0;
+  if (params->subscales) {
+    nst = subscale_stages(L, stage_lv, stage_m);
+  } else {
+    for (int lv = L - 1; lv >= lmin; --lv, ++nst) {
+      stage_lv[nst] = lv;
+      stage_m[nst] = 1 << lv;
+    }
+  }
+  for (int k = 0; k < nst; ++k) stage_entry[k] = k == 0 ? 0 : (stage_lv[k - 1] == stage_lv[k] ? 1 : 2);
+
+  if (sb == 0 && !params->raster && ffh::level_blocked_ok(W, H, L, r)) {
+    // temporally blocked level kernels: one launch per run of passes (the
+    // sub-scale stages, whose patch scale differs from the grid scale, one
+    // launch per step)
     int32_t *sflow[kMaxLevels][2];
     uint32_t *scost[kMaxLevels][2];
     carve_second_grids(base, lay.sgrids, W, H, L, sflow, scost);
@@ -1350,7 +1366,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       k.dir[dr].n_evals = reinterpret_cast<unsigned long long *>(evals + dr);
       k.dir[dr].stream_id = dr;
     }
-    for (int lv = L - 1; lv >= lmin; --lv) {
+    for (int st = 0; st < nst; ++st) {
+      const int lv = stage_lv[st], m = stage_m[st], entry = stage_entry[st];
       for (int dr = 0; dr < nd; ++dr) {
         k.dir[dr].Da = desc[dr][lv];
         k.dir[dr].Db = desc[dr ^ 1][lv];
@@ -1362,18 +1379,30 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         k.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
         k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
-      if (ffh::level_stepwise(tuning_of(params->tuning).variant[lv])) {
+      const bool sub = m != (1 << lv);
+      if (sub || ffh::level_stepwise(tuning_of(params->tuning).variant[lv]) || entry == 1) {
         ffh::LevelArgs a{};
         a.ndir = nd;
         for (int dr = 0; dr < nd; ++dr) {
           const ffh::LevelKDir &kd = k.dir[dr];
-          a.dir[dr] = {kd.Da, kd.Db, kd.flow, kd.cost, kd.cflow, kd.ccost, kd.nn_key, desc1[dr], kd.n_evals,
-                       nullptr, dr};
+          a.dir[dr] = {sub ? sdesc[dr][lv] : kd.Da, sub ? sdesc[dr ^ 1][lv] : kd.Db, kd.flow, kd.cost, kd.cflow,
+                       kd.ccost, kd.nn_key, desc1[dr], kd.n_evals, nullptr, dr};
         }
-        if ((e = run_level_steps(a, W, H, lv, L, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
-        continue;
+        if (sub || ffh::level_stepwise(tuning_of(params->tuning).variant[lv])) {
+          if ((e = run_stage(a, W, H, lv, m, entry, st == nst - 1, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
+          continue;
+        }
+        // the grid at its own patch scale again: costs re-evaluated, then
+        // the blocked launches continue from that state
+        a.W = W;
+        a.H = H;
+        a.n = a.ns = m;
+        a.Wn = ceil_div(W, m);
+        a.Hn = ceil_div(H, m);
+        a.radius = r;
+        if ((e = ffh::launch_rescore(a, s)) != hipSuccess) return FF_ERR_LAUNCH;
       }
-      const int mode = lv == L - 1 ? ffh::kLevelInit : ffh::kLevelSeed;
+      const int mode = entry == 0 ? ffh::kLevelInit : entry == 2 ? ffh::kLevelSeed : ffh::kLevelContinue;
       if ((e = run_level_blocked(k, W, H, lv, params, mode, s, sflow[lv], scost[lv])) != hipSuccess)
         return FF_ERR_LAUNCH;
     }
@@ -1398,8 +1427,6 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   }
   if (params->subscales) {
     // stages (n, 3n/2), (n, n) for every scale below the coarsest but the finest
-    int stage_lv[2 * kMaxLevels], stage_m[2 * kMaxLevels];
-    const int nst = subscale_stages(L, stage_lv, stage_m);
     for (int k = 0; k < nst; ++k) {
       const int lv = stage_lv[k], m = stage_m[k];
       for (int dr = 0; dr < nd; ++dr) {
@@ -1412,8 +1439,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         a.dir[dr].cflow = lv + 1 < L ? gflow[lv + 1][dr] : nullptr;
         a.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
-      const int entry = k == 0 ? 0 : (stage_lv[k - 1] == lv ? 1 : 2);
-      if ((e = run_stage(a, W, H, lv, m, entry, k == nst - 1, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
+      if ((e = run_stage(a, W, H, lv, m, stage_entry[k], k == nst - 1, params, s)) != hipSuccess)
+        return FF_ERR_LAUNCH;
     }
   } else {
     for (int lv = L - 1; lv >= lmin; --lv) {
