@@ -64,22 +64,25 @@ def cpu_baseline(pair, c, threads):
             "host_logical_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def config_legs(ff, torch, threads, tuned, reps=20):
+def config_legs(ff, torch, threads, reps=20):
     """The other single-pair workloads, GPU beside the oracle: 160x120
     (3 scales x 4 steps) and 1242x375 radial expansion (5 scales x 6 steps,
-    R = 3/2); GPU ms per pair with HIP events, oracle ms on `threads` host
-    threads (and one thread for the small pair)."""
+    R = 3/2); GPU ms per pair with HIP events (launch tables cached for the
+    frame size, else the built-in ones), oracle ms on `threads` host threads
+    (and one thread for the small pair)."""
     import dataclasses
 
     from ffgen import CONFIG_PARAMS, make_pair
+    from paper_1703_02563_amd import autotune
     out = {}
     for cfg in (1, 3):
         p, c = make_pair(cfg), CONFIG_PARAMS[cfg]
         H, W = p.img1.shape
         prm = ff.Params(levels=c.levels, iters=c.iters, radius=c.radius, R_num=c.R_num, R_den=c.R_den, eps=c.eps,
                         seed=c.seed)
-        if tuned is not None and (W, H) == (1024, 436):
-            prm = dataclasses.replace(prm, tuning=tuned)
+        tab = autotune.load(W, H, prm)  # this frame size's cached tables, else the built-in ones
+        if tab is not None:
+            prm = dataclasses.replace(prm, tuning=tab)
         i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
         runner = ff.FlowFields(W, H, prm, device=i1.device)
         for _ in range(3):
@@ -539,7 +542,7 @@ def main():
     legs = None
     if not args.no_configs:
         log("bench: other single-pair workloads, GPU beside the oracle")
-        legs = config_legs(ff, torch, threads, tuned)
+        legs = config_legs(ff, torch, threads)
         log(f"bench: configs {legs}")
 
     base = None

@@ -78,14 +78,16 @@ constexpr int kHaloF32[] = {2, 2, 4, 6, 4};
 constexpr int kNumVariantsF32 = 5;
 static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float variant table");
 
-// The built-in launch tables.  Byte descriptors: one-lane 32x16 tiles at
-// n = 1, 2 and 16x16 tiles from n = 4 on, as many steps per launch as the
-// halo allows.  Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
+// The built-in launch tables.  Byte descriptors: weight-class evaluations
+// on 32x16 tiles (512 threads) at n = 1, 16x16 tiles at n = 2 and 4 (1024
+// threads at n = 4), 8x8 tiles with 1024 threads at n = 8, 16; three steps
+// per launch (the table tuned at 1024x436, which also halves the time of
+// the older one-lane table at 160x120 and 1242x375).  Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
 // on (16x16 tiles leave most compute units idle there), one step per launch
 // (the float evaluations are expensive enough that this is fastest at every
 // scale, measured at 1024x436).
-constexpr ffh::Tuning kDefaultTuning = {{2, 2, 3, 3, 3, 3, 3},
-                                        {0, 0, 0, 0, 0, 0, 0},
+constexpr ffh::Tuning kDefaultTuning = {{20, 19, 30, 26, 27, 3, 3},
+                                        {3, 3, 3, 3, 3, 0, 0},
                                         {0, 0, 1, 1, 1, 1, 1},
                                         {1, 1, 1, 1, 1, 1, 1}};
 

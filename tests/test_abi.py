@@ -128,7 +128,8 @@ def test_default_tuning_and_validation():
     assert lib.ff_level_variant_count_f32() == 5
     t = ff.default_tuning()
     assert t.variant_f32 == [0, 0, 1, 1, 1, 1, 1] and t.passes_f32 == [1] * 7
-    assert all(0 <= v < lib.ff_level_variant_count() for v in t.variant) and t.passes == [0] * 7
+    assert all(0 <= v < lib.ff_level_variant_count() for v in t.variant)
+    assert t.variant == [20, 19, 30, 26, 27, 3, 3] and t.passes == [3, 3, 3, 3, 3, 0, 0]
     fake = C.c_void_p(0x1000)
     for bad in (dict(variant=[lib.ff_level_variant_count()] * 7), dict(variant=[-1] * 7), dict(passes=[65] * 7),
                 dict(passes_f32=[-1] * 7), dict(variant_f32=[5] * 7)):
@@ -144,12 +145,12 @@ def test_level_launches_follow_the_run_length_table():
     """Launches per scale: the halo of the blocked kernel holds 6 steps
     (3 per side pair), the run-length table caps a run; tables per call."""
     lib = ff.lib()
-    t = ff.default_tuning()
+    t = ff.default_tuning().replace(variant=[3] * 7)  # 16x16 tiles, the widest halo
     for passes, T, expect in [(0, 6, 1), (0, 9, 2), (1, 6, 6), (2, 6, 3), (3, 6, 2), (4, 7, 2), (0, 1, 1)]:
         tc = t.replace(passes=[passes] * 7).to_c()
         assert lib.ff_level_launches(C.byref(tc), T, 1, 0) == expect, (passes, T)
         assert ff.level_launches(ff.Params(iters=T, tuning=t.replace(passes=[passes] * 7)), 1) == expect
-    assert lib.ff_level_launches(None, 6, 1, 0) == 1  # the built-in table
+    assert lib.ff_level_launches(None, 6, 1, 0) == 2  # the built-in table: 3 steps per launch at n = 2
     assert lib.ff_level_launches(None, 0, 1, 0) == -1 and lib.ff_level_launches(None, 6, 9, 0) == -1
     assert lib.ff_level_launches(None, 6, 1, 2) == -1
 
