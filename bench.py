@@ -118,9 +118,20 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
 # same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 10568.0 * 1024 * 2.0 + 3512.3 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "c1c65354e256ed3d"
-TRAFFIC_VARIANT, TRAFFIC_PASSES = 16, 2  # scale-1 launch table the counters were taken with
+TRAFFIC_BYTES = 11707.5 * 1024 * 2.0 + 3491.5 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "a50c2bef0406f12d"
+TRAFFIC_VARIANT, TRAFFIC_PASSES = 20, 3  # scale-1 launch table the counters were taken with
+# Vector-L1 tag accesses of 64 bytes per launch of the same kernel
+# (TCP_TOTAL_CACHE_ACCESSES_sum, same run conditions; the L1 data path moves
+# 64 bytes per clock per CU).
+L1_ACCESSES = 13544466.8
+L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
+# Matrix-core and VALU issue utilisation of the NN seed kernel (k_nn, both
+# directions) from SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU and
+# GRBM_GUI_ACTIVE (profiles/level_kernel_sq_1024x436.md); valid for the
+# ff_nn.hip it was measured on.
+NN_COUNTERS = {"mfma_busy": 0.183, "valu_issue": 0.734, "mfma_instructions": 1452160}
+NN_SOURCES_SHA = "3b4b65b8af50d83f"
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
                  "paper_1703_02563_amd/csrc/ff_internal.h")
@@ -191,16 +202,31 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     w_owned, w_all = (int(v) / launches for v in work.cpu())
     achieved = w_owned * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
     tun = params.tuning or ff.default_tuning()
-    traffic = None
+    traffic = l1 = None
     if level_sources_sha() == TRAFFIC_SOURCES_SHA and tun.variant[0] == TRAFFIC_VARIANT \
             and tun.passes[0] == TRAFFIC_PASSES:
         traffic = round(TRAFFIC_BYTES)
+        l1_tbps = L1_ACCESSES * 64 / (ms * 1e-3) / 1e12
+        l1 = {"bytes_per_launch": round(L1_ACCESSES * 64), "achieved_TBps": round(l1_tbps, 3),
+              "peak_TBps": round(L1_PEAK_TBPS, 2), "frac": round(l1_tbps / L1_PEAK_TBPS, 4)}
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
+            "vector_l1": l1,
             "kernel": f"k_level<0,*> (scale 1, forward; ff_run_level = {launches} launches, averages per launch)",
             "avg_launch_ms": round(ms, 5), "evals_per_launch": evals,
             "computed_owned_per_launch": w_owned, "computed_all_per_launch": w_all,
             "algorithmic_ops_per_launch": w_owned * SAD_OPS_PER_EVAL}
+
+
+def nn_counters():
+    """The NN seed kernel's counter figures, or None once ff_nn.hip has
+    changed since they were taken."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1703_02563_amd/csrc/ff_nn.hip"), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    if sha != NN_SOURCES_SHA:
+        return None
+    return dict(NN_COUNTERS, kernel="k_nn (both directions)", source="profiles/level_kernel_sq_1024x436.md")
 
 
 def batched_throughput(ff, torch, reps):
@@ -562,6 +588,7 @@ def main():
                    "kept_epe": round(q["kept_epe"], 4), "schedules": schedules, "batched": batched,
                    "learned": learned, "other_pairs": legs},
         "roofline": roof,
+        "nn_counters": nn_counters(),
         "cpu_baseline": base,
     }
     print(json.dumps(rec), flush=True)
