@@ -113,24 +113,25 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per patch evaluation
 
 
-# HBM traffic per launch of the scale-1 level kernel (one direction of the
-# 1024x436 pair, the launches of ff_run_level) from two rocprofv3 --pmc runs (FETCH_SIZE,
-# WRITE_SIZE; profiles/level_kernel_traffic_1024x436.md), scaled by what the
-# same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 11707.5 * 1024 * 2.0 + 3491.5 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "a50c2bef0406f12d"
+# HBM traffic per launch of the scale-1 level kernel (both directions of the
+# 1024x436 pair, as ff_flow_fields and the roofline leg launch it) from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE;
+# profiles/level_kernel_traffic_1024x436.md), scaled by what the same
+# counters read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x
+# 1.0).  Valid only for the kernel sources it was measured on.
+TRAFFIC_BYTES = 20613.3 * 1024 * 2.0 + 7032.0 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "6102493e6540b97b"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 20, 3  # scale-1 launch table the counters were taken with
 # Vector-L1 tag accesses of 64 bytes per launch of the same kernel
 # (TCP_TOTAL_CACHE_ACCESSES_sum, same run conditions; the L1 data path moves
 # 64 bytes per clock per CU).
-L1_ACCESSES = 13544466.8
+L1_ACCESSES = 26124843.0
 L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
 # Matrix-core and VALU issue utilisation of the NN seed kernel (k_nn, both
 # directions) from SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU and
 # GRBM_GUI_ACTIVE (profiles/level_kernel_sq_1024x436.md); valid for the
 # ff_nn.hip it was measured on.
-NN_COUNTERS = {"mfma_busy": 0.183, "valu_issue": 0.734, "mfma_instructions": 1452160}
+NN_COUNTERS = {"mfma_busy": 0.181, "valu_issue": 0.729, "mfma_instructions": 1452160}
 NN_SOURCES_SHA = "3b4b65b8af50d83f"
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",
@@ -147,12 +148,13 @@ def level_sources_sha():
 
 
 def roofline_level0(ff, torch, img1, img2, params, reps):
-    """Times the scale-1 level kernel (one direction, one ff_run_level call
-    from the scale-2 seeds) with HIP events on the current stream.
+    """Times the scale-1 level kernel as ff_flow_fields launches it: both
+    directions in one set of launches (ff_run_level_pair from the scale-2
+    states), HIP events on the current stream, averaged per launch.
     Algorithmic work = the evaluations the launches compute for the cells
-    they own (the work counters of ff_run_level; evaluations that a
-    consistent state makes unnecessary and recomputed halo cells are not
-    counted) x 196 v_sad_u8 lane-ops."""
+    they own (the kernel's work counter; evaluations that a consistent state
+    makes unnecessary and recomputed halo cells are not counted) x 196
+    v_sad_u8 lane-ops."""
     H, W = img1.shape
     L = params.levels
     ma = [ff.descriptors(img1, 1 << lv, wform=True) for lv in range(L)]
@@ -161,28 +163,29 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     Db, Wb = [m[1] for m in mb], [m[2] for m in mb]
     Da1 = ff.descriptors(img1, 1, rowmajor=True)[2]
     Db1 = ff.descriptors(img2, 1, rowmajor=True)[2]
-    _, _, key = ff.init_nn(Da1, Db1, Da[L - 1], Db[L - 1], 1 << (L - 1))
+    keys = [ff.init_nn(Da1, Db1, Da[L - 1], Db[L - 1], 1 << (L - 1))[2],
+            ff.init_nn(Db1, Da1, Db[L - 1], Da[L - 1], 1 << (L - 1))[2]]
     dev = img1.device
     prev = None
     for lv in range(L - 1, 0, -1):
         Wn, Hn = -(-W // (1 << lv)), -(-H // (1 << lv))
-        fl = torch.empty((Hn, Wn, 2), dtype=torch.int16, device=dev)
-        co = torch.empty((Hn, Wn), dtype=torch.int32, device=dev)
+        fl = [torch.empty((Hn, Wn, 2), dtype=torch.int16, device=dev) for _ in range(2)]
+        co = [torch.empty((Hn, Wn), dtype=torch.int32, device=dev) for _ in range(2)]
         if prev is None:
-            ff.run_level(Da[lv], Db[lv], lv, params, 0, 1, fl, co, nn_key=key, wform_a=Wa[lv], wform_b=Wb[lv])
+            ff.run_level_pair(Da[lv], Db[lv], lv, params, 1, fl, co, nn_keys=keys, wform_a=Wa[lv], wform_b=Wb[lv])
         else:
-            ff.run_level(Da[lv], Db[lv], lv, params, 0, 2, fl, co, coarse_flow=prev[0], coarse_cost=prev[1],
-                         wform_a=Wa[lv], wform_b=Wb[lv])
+            ff.run_level_pair(Da[lv], Db[lv], lv, params, 2, fl, co, coarse_flows=prev[0], coarse_costs=prev[1],
+                              wform_a=Wa[lv], wform_b=Wb[lv])
         prev = (fl, co)
-    fl0 = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
-    co0 = torch.empty((H, W), dtype=torch.int32, device=dev)
-    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    fl0 = [torch.empty((H, W, 2), dtype=torch.int16, device=dev) for _ in range(2)]
+    co0 = [torch.empty((H, W), dtype=torch.int32, device=dev) for _ in range(2)]
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     work = torch.zeros(2, dtype=torch.int64, device=dev)
-    scratch = torch.empty(int(ff.lib().ff_run_level_scratch_bytes(W, H, 0)), dtype=torch.uint8, device=dev)
+    scratch = torch.empty(2 * int(ff.lib().ff_run_level_scratch_bytes(W, H, 0)), dtype=torch.uint8, device=dev)
 
     def launch(counter=None, wk=None):
-        ff.run_level(Da[0], Db[0], 0, params, 0, 2, fl0, co0, coarse_flow=prev[0], coarse_cost=prev[1],
-                     n_evals=counter, n_work=wk, scratch=scratch, wform_a=Wa[0], wform_b=Wb[0])
+        ff.run_level_pair(Da[0], Db[0], 0, params, 2, fl0, co0, coarse_flows=prev[0], coarse_costs=prev[1],
+                          n_evals=counter, n_work=wk, scratch=scratch, wform_a=Wa[0], wform_b=Wb[0])
 
     for _ in range(3):
         launch()
@@ -195,10 +198,10 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     torch.cuda.synchronize()
     launch(cnt, work)  # the same call once more, counted (the counts do not vary between calls)
     torch.cuda.synchronize()
-    # one ff_run_level call = `launches` launches of the scale-1 level kernel
+    # one call = `launches` launches of the scale-1 level kernel
     launches = ff.level_launches(params, 0)
     ms = sum(a.elapsed_time(b) for a, b in ev) / reps / launches
-    evals = int(cnt.item()) / launches
+    evals = int(cnt.sum().item()) / launches
     w_owned, w_all = (int(v) / launches for v in work.cpu())
     achieved = w_owned * SAD_OPS_PER_EVAL / (ms * 1e-3) / 1e12
     tun = params.tuning or ff.default_tuning()
@@ -212,7 +215,8 @@ def roofline_level0(ff, torch, img1, img2, params, reps):
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "T int-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
             "vector_l1": l1,
-            "kernel": f"k_level<0,*> (scale 1, forward; ff_run_level = {launches} launches, averages per launch)",
+            "kernel": f"k_level<0,*> (scale 1, both directions per launch as in ff_flow_fields; "
+                      f"{launches} launches per call, averages per launch)",
             "avg_launch_ms": round(ms, 5), "evals_per_launch": evals,
             "computed_owned_per_launch": w_owned, "computed_all_per_launch": w_all,
             "algorithmic_ops_per_launch": w_owned * SAD_OPS_PER_EVAL}

@@ -398,6 +398,26 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
                        const int16_t *coarse_flow, const uint32_t *coarse_cost, int16_t *flow, uint32_t *cost,
                        void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream);
 
+/* ff_run_level for both directions of a pair in one set of launches, as
+ * ff_flow_fields runs a scale (Sec. 3.2: the forward and the backward field
+ * are computed together): direction 0 finds image a's cells in image b
+ * (desc_a/wform_a on the cell side, random-search stream id 0), direction
+ * 1 the reverse (stream id 1).  nn_key, coarse_flow, coarse_cost, flow and
+ * cost are host arrays of two device pointers, one per direction, with the
+ * meaning of ff_run_level (nn_key only read in mode 1, the coarse grids only
+ * in mode 2); n_evals: nullable device uint64 [2], one count per direction
+ * (added to); n_work: nullable device uint64 [2], summed over both
+ * directions.  scratch: device, at least 2 * ff_run_level_scratch_bytes.
+ * Same results as two ff_run_level calls.  The temporally blocked kernels
+ * only: FF_ERR_UNSUPPORTED with params->subpixel, raster or subscales, or a
+ * radius the blocked kernels do not run at this size; FF_ERR_ARG for
+ * invalid arguments, FF_ERR_WORKSPACE for a short scratch. */
+ff_status ff_run_level_pair(const uint8_t *desc_a, const uint8_t *desc_b, const uint8_t *wform_a,
+                            const uint8_t *wform_b, int32_t W, int32_t H, int32_t level, const ff_params *params,
+                            int32_t mode, const uint64_t *const *nn_key, const int16_t *const *coarse_flow,
+                            const uint32_t *const *coarse_cost, int16_t *const *flow, uint32_t *const *cost,
+                            void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream);
+
 /* Scratch bytes of ff_run_level (host): a second grid of scale 2^level
  * (flow and cost), which the launches of a scale alternate with flow/cost
  * so that no launch reads cells it is writing.  0 for invalid sizes. */

@@ -686,6 +686,51 @@ ff_status ff_run_level(const uint8_t *desc_a, const uint8_t *desc_b, const uint8
   return from_hip(e);
 }
 
+ff_status ff_run_level_pair(const uint8_t *desc_a, const uint8_t *desc_b, const uint8_t *wform_a,
+                            const uint8_t *wform_b, int32_t W, int32_t H, int32_t level, const ff_params *params,
+                            int32_t mode, const uint64_t *const *nn_key, const int16_t *const *coarse_flow,
+                            const uint32_t *const *coarse_cost, int16_t *const *flow, uint32_t *const *cost,
+                            void *scratch, size_t scratch_bytes, uint64_t *n_evals, uint64_t *n_work, void *stream) {
+  if (!desc_a || !desc_b || !flow || !cost || !dims_ok(W, H) || !params_ok(params) || level < 0 ||
+      level >= kMaxLevels || mode < 0 || mode > 2 || (mode == 1 && !nn_key) ||
+      (mode == 2 && (!coarse_flow || !coarse_cost)) || !sub_dims_ok(params, W, H))
+    return FF_ERR_ARG;
+  for (int dr = 0; dr < 2; ++dr)
+    if (!flow[dr] || !cost[dr] || (mode == 1 && !nn_key[dr]) ||
+        (mode == 2 && (!coarse_flow[dr] || !coarse_cost[dr])))
+      return FF_ERR_ARG;
+  const size_t one = ff_run_level_scratch_bytes(W, H, level);
+  if (!scratch || scratch_bytes < 2 * one) return FF_ERR_WORKSPACE;
+  if (params->subpixel || params->raster || params->subscales || !ffh::level_blocked_ok(W, H, level + 1, params->radius))
+    return FF_ERR_UNSUPPORTED;  // both directions in one launch: the blocked kernels only
+  const int n = 1 << level;
+  const size_t cells = (size_t)ceil_div(W, n) * ceil_div(H, n);
+  const uint8_t *D[2] = {desc_a, desc_b}, *Wf[2] = {wform_a, wform_b};
+  ffh::LevelKArgs k{};
+  k.ndir = 2;
+  int32_t *sf[2];
+  uint32_t *sc[2];
+  for (int dr = 0; dr < 2; ++dr) {
+    ffh::LevelKDir &d = k.dir[dr];
+    d.Da = D[dr];
+    d.Db = D[dr ^ 1];
+    d.Wa = Wf[dr];
+    d.Wb = Wf[dr ^ 1];
+    d.flow = reinterpret_cast<int32_t *>(flow[dr]);
+    d.cost = cost[dr];
+    d.nn_key = mode == 1 ? nn_key[dr] : nullptr;
+    d.cflow = mode == 2 ? reinterpret_cast<const int32_t *>(coarse_flow[dr]) : nullptr;
+    d.ccost = mode == 2 ? coarse_cost[dr] : nullptr;
+    d.n_evals = n_evals ? reinterpret_cast<unsigned long long *>(n_evals + dr) : nullptr;
+    d.n_work = reinterpret_cast<unsigned long long *>(n_work);
+    d.stream_id = dr;
+    sf[dr] = static_cast<int32_t *>(scratch) + (size_t)dr * 2 * cells;
+    sc[dr] = reinterpret_cast<uint32_t *>(sf[dr] + cells);
+  }
+  const int first = mode == 1 ? ffh::kLevelInit : (mode == 2 ? ffh::kLevelSeed : ffh::kLevelContinue);
+  return from_hip(run_level_blocked(k, W, H, level, params, first, (hipStream_t)stream, sf, sc));
+}
+
 ff_status ff_cost_f32_fwd(const float *f1, const float *f2, int32_t W, int32_t H, int32_t n, int32_t radius,
                           const int32_t *entries, int32_t count, float *cost, void *stream) {
   if (!f1 || !f2 || (count > 0 && (!entries || !cost)) || !dims_ok(W, H) || !is_pow2(n) || radius < 0 ||

@@ -89,6 +89,8 @@ _SIGS = {
     "ff_run_level": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _I32, _P, _P, _P, _P,
                                _P, _P, C.c_size_t, _P, _P, _P]),
     "ff_run_level_scratch_bytes": (C.c_size_t, [_I32, _I32, _I32]),
+    "ff_run_level_pair": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, C.POINTER(FFParams), _I32, _P, _P, _P, _P, _P,
+                                    _P, C.c_size_t, _P, _P, _P]),
     "ff_cost_f32_fwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "ff_cost_f32_bwd": (C.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),
     "ff_conv3x3_fwd": (C.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _P, _P, _I32, _P, _P, _P]),

@@ -264,6 +264,38 @@ def run_level(desc_a, desc_b, level: int, params: Params, stream_id: int, mode: 
                              _stream()), "ff_run_level")
 
 
+def run_level_pair(desc_a, desc_b, level: int, params: Params, mode: int, flows, costs, nn_keys=None,
+                   coarse_flows=None, coarse_costs=None, n_evals=None, n_work=None, scratch=None, wform_a=None,
+                   wform_b=None):
+    """One scale of both directions in one set of launches (see
+    ff_run_level_pair): flows/costs (and nn_keys, coarse_flows,
+    coarse_costs where the mode reads them) are pairs of tensors, direction
+    0 then 1; n_evals: optional int64 [2] per direction; n_work: optional
+    int64 [2] summed over both directions."""
+    W, H = _map_dims(desc_a, desc_b, 1 << level)
+    if (wform_a is None) != (wform_b is None):
+        raise ValueError("run_level_pair: both weight-class maps or neither")
+    nbytes = 2 * int(lib().ff_run_level_scratch_bytes(W, H, level))
+    if scratch is None:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=desc_a.device)
+    elif scratch.numel() * scratch.element_size() < nbytes:
+        raise ValueError("run_level_pair: scratch too small")
+
+    def pair(ts, dtype):
+        if ts is None:
+            return None
+        if len(ts) != 2:
+            raise ValueError("run_level_pair: two tensors per argument, one per direction")
+        return (ctypes.c_void_p * 2)(_ptr(ts[0], dtype).value, _ptr(ts[1], dtype).value)
+
+    check(lib().ff_run_level_pair(_ptr(desc_a, torch.uint8), _ptr(desc_b, torch.uint8), _ptr(wform_a, torch.uint8),
+                                  _ptr(wform_b, torch.uint8), W, H, level, params.to_c(), mode,
+                                  pair(nn_keys, torch.int64), pair(coarse_flows, torch.int16),
+                                  pair(coarse_costs, torch.int32), pair(flows, torch.int16), pair(costs, torch.int32),
+                                  _ptr(scratch), nbytes, _ptr(n_evals, torch.int64), _ptr(n_work, torch.int64),
+                                  _stream()), "ff_run_level_pair")
+
+
 def level_launches(params: Params, level: int, cost_kind: int = 0) -> int:
     """Blocked launches the call's tables give one scale (ff_level_launches)."""
     t = params.tuning.to_c() if params.tuning is not None else None

@@ -155,6 +155,30 @@ def test_level_launches_follow_the_run_length_table():
     assert lib.ff_level_launches(None, 6, 1, 2) == -1
 
 
+def test_run_level_pair_validation():
+    """ff_run_level_pair rejects bad arguments, a short scratch and the
+    forms the blocked kernels do not run, before anything is enqueued."""
+    lib = ff.lib()
+    fake = C.c_void_p(0x1000)
+    two = (C.c_void_p * 2)(0x1000, 0x2000)
+    one_null = (C.c_void_p * 2)(0x1000, None)
+    W, H, lv = 64, 48, 0
+    need = 2 * lib.ff_run_level_scratch_bytes(W, H, lv)
+
+    def call(prm=None, mode=0, flows=two, costs=two, keys=None, scratch_bytes=need):
+        q = (prm or ff.Params(levels=1, iters=2)).to_c()
+        return lib.ff_run_level_pair(fake, fake, None, None, W, H, lv, C.byref(q), mode, keys, None, None, flows,
+                                     costs, fake, scratch_bytes, None, None, None)
+
+    assert call(flows=None) == ffi.FF_ERR_ARG
+    assert call(costs=one_null) == ffi.FF_ERR_ARG
+    assert call(mode=1) == ffi.FF_ERR_ARG  # no NN keys
+    assert call(mode=3) == ffi.FF_ERR_ARG
+    assert call(scratch_bytes=need - 1) == ffi.FF_ERR_WORKSPACE
+    assert call(prm=ff.Params(levels=1, iters=2, subpixel=3)) == ffi.FF_ERR_UNSUPPORTED
+    assert call(prm=ff.Params(levels=1, iters=2, raster=True)) == ffi.FF_ERR_UNSUPPORTED
+
+
 def test_noalloc_region_filter_validation():
     """Sizes beyond the static scratch array and bad arguments return before
     anything is enqueued."""

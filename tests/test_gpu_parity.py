@@ -562,3 +562,64 @@ def test_run_level_work_counters(radius):
         assert owned == every
     else:
         assert every > owned and owned > 0.8 * ne
+
+
+@pytest.mark.parametrize("shape,level,T", [((61, 83), 0, 6), ((130, 200), 1, 5), ((45, 70), 0, 4)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("with_wform", [True, False])
+def test_run_level_pair_bit_exact(shape, level, T, mode, with_wform):
+    """ff_run_level_pair: both directions of one scale in one set of launches
+    (direction 0 image a's cells in image b, stream id 0; direction 1 the
+    reverse, stream id 1), each equal to the oracle's step sequence, with
+    per-direction evaluation counts."""
+    H, W = shape
+    n = 1 << level
+    prm = ff.Params(levels=level + 1, iters=T)
+    ia, ib = random_images(1300 + level * 10 + mode, H, W)
+    B = [oracle.blur(im, n) for im in (ia, ib)]
+    D = [oracle.descriptor(b, n) for b in B]
+    Wn, Hn = -(-W // n), -(-H // n)
+    Rn = oracle.rs_radius(n, prm.R_num, prm.R_den)
+    flows, costs, keys, cflows, ccosts, expect = [], [], [], [], [], []
+    for dr in range(2):
+        Da, Db = D[dr], D[dr ^ 1]
+        if mode == 0:
+            flow, cost = _random_level_state(30 + dr, H, W, n)
+            for j, i in zip(*np.nonzero(cost != oracle.UNSET)):
+                cost[j, i] = oracle.cost(Da, Db, n, 3, i * n, j * n, int(flow[j, i, 0]), int(flow[j, i, 1]))
+            ne = 0
+            flows.append(dev(flow))
+            costs.append(dev(cost.view(np.int32)))
+        else:
+            if mode == 1:
+                D1 = [oracle.descriptor(oracle.blur(im, 1), 1) for im in (ia, ib)]
+                idx, _ = oracle.nn(D1[dr], D1[dr ^ 1], n, nthreads=NT)
+                flow, cost, ne = oracle.init_coarse(idx, Da, Db, n)
+                keys.append(dev(idx.astype(np.int64)))
+            else:
+                cf, cc = _random_level_state(40 + dr, H, W, 2 * n)
+                flow, cost, ne = oracle.seed_level(cf, cc, Da, Db, n)
+                cflows.append(dev(cf))
+                ccosts.append(dev(cc.view(np.int32)))
+            flows.append(torch.empty((Hn, Wn, 2), dtype=torch.int16, device="cuda"))
+            costs.append(torch.empty((Hn, Wn), dtype=torch.int32, device="cuda"))
+        for t in range(T):
+            flow, cost, k = oracle.propagate(Da, Db, n, t, flow, cost, nthreads=NT)
+            ne += k
+            if t < T - 1:
+                flow, cost, k = oracle.random_search(Da, Db, n, Rn, prm.seed, dr, level, t, flow, cost, nthreads=NT)
+                ne += k
+        expect.append((flow, cost, ne))
+    wf = dict(wform_a=dev(wform_lib(B[0], n)), wform_b=dev(wform_lib(B[1], n))) if with_wform else {}
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    work = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ff.run_level_pair(dev(to_lib(D[0], n)), dev(to_lib(D[1], n)), level, prm, mode, flows, costs,
+                      nn_keys=keys or None, coarse_flows=cflows or None, coarse_costs=ccosts or None, n_evals=cnt,
+                      n_work=work, **wf)
+    for dr in range(2):
+        ef, ec, ne = expect[dr]
+        assert np.array_equal(host(flows[dr]), ef), dr
+        assert np.array_equal(as_u32(costs[dr]), ec), dr
+        assert int(host(cnt)[dr]) == ne, dr
+    owned, every = (int(v) for v in host(work))
+    assert 0 < owned <= every and owned <= int(host(cnt).sum())
