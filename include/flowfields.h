@@ -527,8 +527,13 @@ ff_status ff_conv3x3_bwd_data(const uint16_t *gout, int32_t B, int32_t H, int32_
 size_t ff_conv3x3_wgrad_scratch_bytes(int32_t B, int32_t H, int32_t cin, int32_t cout);
 
 /* gw[co][tap][ci] = sum_p gout[p][co] * in[p + d(tap)][ci], gbias[co] =
- * sum_p gout[p][co] (gbias nullable), float32; per-row-band partial sums are
- * added in a fixed order (deterministic).  in: bf16; gout: float32. */
+ * sum_p gout[p][co] (gbias nullable), float32: bf16 matrix-core products
+ * with float32 accumulation, gout split into two bf16 parts (hi + lo, within
+ * 2^-18 |gout| of it), so the error is at most (2^-18 + 3.1 P 2^-24) times
+ * the sum of |gout| |in| over the P pixels; per-workgroup partial sums are
+ * added in a fixed order (deterministic).  in: bf16, 16-byte aligned when
+ * cin > 1; gout: float32, 16-byte aligned; (cin, cout) = (1, 32), (32, 32)
+ * or (32, 16); FF_ERR_ARG otherwise. */
 ff_status ff_conv3x3_bwd_weight(const uint16_t *in, const float *gout, int32_t B, int32_t H, int32_t W,
                                 int32_t cin, int32_t cout, float *scratch, size_t scratch_bytes, float *gw,
                                 float *gbias, void *stream);

@@ -1140,6 +1140,8 @@ ff_status ff_conv3x3_bwd_weight(const uint16_t *in, const float *gout, int32_t B
                                 int32_t cout, float *scratch, size_t scratch_bytes, float *gw, float *gbias,
                                 void *stream) {
   if (!in || !gout || !scratch || !gw || !conv_shape_ok(B, H, W, cin, cout) || cin == 16) return FF_ERR_ARG;
+  // 16-byte loads: 8 input channels, 4 gradients at a time
+  if ((cin > 1 && !aligned16(in)) || !aligned16(gout)) return FF_ERR_ARG;
   if (scratch_bytes < ff_conv3x3_wgrad_scratch_bytes(B, H, cin, cout)) return FF_ERR_WORKSPACE;
   ffh::ConvArgs a{};
   a.in = in;

@@ -10,9 +10,10 @@
 // [Cout][9][Cin] (tap = 3 * (dy + 1) + (dx + 1)).
 //
 // The data gradient is the same convolution with the weights rotated by 180
-// degrees and transposed ([Cin][9][Cout]).  The weight gradient sums over
-// all pixels; each workgroup writes a partial sum of its rows and a second
-// kernel adds the partials in a fixed order, so it is deterministic.
+// degrees and transposed ([Cin][9][Cout]).  The weight gradient is a
+// contraction over all pixels, also on matrix cores; each workgroup writes
+// a partial sum of its rows and a second kernel adds the partials in a fixed
+// order, so it is deterministic.
 #include <algorithm>
 
 #include "ff_device.h"
@@ -171,74 +172,174 @@ __global__ __launch_bounds__(256) void k_flip(const uint16_t *w, uint16_t *wf, i
   wf[i] = w[((size_t)co * 9 + (8 - tap)) * cin + ci];
 }
 
-// Partial weight and bias gradients of one row band: item = (image, row).
-// Thread t accumulates output channels co = t % COUT and input channels
-// ci = t / COUT + k * (256 / COUT) for all 9 taps.
+// Partial weight and bias gradients of one row band on matrix cores.
+// gw[co][tap][ci] = sum over pixels p of g[p][co] * x[p + d(tap)][ci] is a
+// contraction over pixels: per tap, D[co][ci] (32 x 32) += A[co][16 pixels]
+// x B[16 pixels][ci] with v_mfma_f32_32x32x16_bf16.  x is bf16 already; the
+// float32 gradient is split as g_hi = bf16(g) and g_lo = bf16(g - g_hi) and
+// both parts are multiplied (bf16 products are exact in float32, and
+// |g - g_hi - g_lo| <= 2^-18 |g|), so every term keeps float32-level
+// accuracy.  The bias gradient sum_p g is one more product with B = 1 (for
+// Cin = 1 the nine taps and the bias are the columns of one product).  A
+// workgroup takes a band of rows; of every 64 pixels of a row each wave
+// takes 16.  The tile is staged in LDS channel-major (pixels of a channel
+// contiguous; 16-byte loads from global memory, 8 channels or 4 gradients
+// each): a lane's 8 pixels of one channel are one aligned 16-byte read, and
+// the taps one pixel left or right are assembled from two neighbouring
+// reads with byte alignment.  The four waves' sums are added in LDS in a
+// fixed order and each workgroup writes one partial; k_wgrad_reduce adds the
+// partials in a fixed order, so the result is deterministic.
+constexpr int kWgPx = 64;  // pixels of a row per step (16 per wave)
+constexpr int kWgX = 80;   // LDS row of image x: pixel x0 - 8 + i at entry i
+constexpr int kWgG = 72;   // LDS row of the gradient: pixel x0 + i at entry i
+
+// the 8 bf16 at entries e0 + s .. e0 + s + 7 (s = -1, 0, 1) of an LDS row,
+// from the aligned reads lo = [e0 - 8, e0), mid = [e0, e0 + 8), hi = [e0 + 8,
+// e0 + 16)
+__device__ __forceinline__ uint4 shifted8(uint4 lo, uint4 mid, uint4 hi, int s) {
+  if (s == 0) return mid;
+  if (s > 0)
+    return make_uint4(__builtin_amdgcn_alignbyte(mid.y, mid.x, 2), __builtin_amdgcn_alignbyte(mid.z, mid.y, 2),
+                      __builtin_amdgcn_alignbyte(mid.w, mid.z, 2), __builtin_amdgcn_alignbyte(hi.x, mid.w, 2));
+  return make_uint4(__builtin_amdgcn_alignbyte(mid.x, lo.w, 2), __builtin_amdgcn_alignbyte(mid.y, mid.x, 2),
+                    __builtin_amdgcn_alignbyte(mid.z, mid.y, 2), __builtin_amdgcn_alignbyte(mid.w, mid.z, 2));
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad_partial(ffh::ConvArgs a, int rows_per_block) {
-  constexpr int TPC = 256 / COUT;                  // threads per output channel
-  constexpr int CPT = (CIN + TPC - 1) / TPC;       // input channels per thread
-  __shared__ float s_g[64][COUT];
-  __shared__ float s_in[3][66][CIN];
-  const int tid = threadIdx.x, co = tid % COUT, cg = tid / COUT;
-  float acc[9][CPT];
-  float bacc = 0.0f;
+  static_assert((CIN == 1 || CIN == 32) && (COUT == 16 || COUT == 32), "Cin 1 or 32, Cout 16 or 32");
+  constexpr int NP = CIN == 1 ? 1 : 10;  // products per pixel block: 9 taps and the bias
+  __shared__ __attribute__((aligned(16))) uint16_t s_x[3][CIN][kWgX];  // [dy][ci][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t s_g[2][32][kWgG];   // [hi, lo][co][pixel]
+  __shared__ float s_red[4][32 * 32];                                  // the four waves' sums of one product
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, kh = lane >> 5;
+  f32x16 acc[NP];
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) acc[t][k] = 0.0f;
+  for (int t = 0; t < NP; ++t) acc[t] = f32x16{0};
+  const uint4 ones = make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u);  // bf16 1.0
+  for (int e = tid; e < 2 * (32 - COUT) * kWgG; e += 256)  // gradient rows beyond Cout stay zero
+    s_g[e / ((32 - COUT) * kWgG)][COUT + (e / kWgG) % (32 - COUT)][e % kWgG] = 0;
   const int nrows = a.B * a.H;
   const int r0 = blockIdx.x * rows_per_block, r1 = min(r0 + rows_per_block, nrows);
   for (int rr = r0; rr < r1; ++rr) {
     const int img = rr / a.H, y = rr % a.H;
-    for (int x0 = 0; x0 < a.W; x0 += 64) {
-      __syncthreads();
-      for (int k = tid; k < 64 * COUT; k += 256) {
-        const int px = k / COUT, c = k % COUT, x = x0 + px;
-        s_g[px][c] = x < a.W ? a.gout[(((long long)img * a.H + y) * a.W + x) * COUT + c] : 0.0f;
-      }
-      for (int k = tid; k < 3 * 66 * CIN; k += 256) {
-        const int c = k % CIN, xx = (k / CIN) % 66, dy = k / (CIN * 66);
-        const int sx = x0 + xx - 1, sy = y + dy - 1;
-        float v = 0.0f;
-        if (sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
-          v = bf16_to_f32(a.in[(((long long)img * a.H + sy) * a.W + sx) * CIN + c]);
-        s_in[dy][xx][c] = v;
-      }
-      __syncthreads();
-      const int np = min(64, a.W - x0);
-      for (int px = 0; px < np; ++px) {
-        const float g = s_g[px][co];
-        if (cg == 0) bacc += g;
+    const long long row = (long long)img * a.H + y;
+    for (int x0 = 0; x0 < a.W; x0 += kWgPx) {
+      __syncthreads();  // the previous step's operands are read
+      for (int e = tid; e < kWgPx * (COUT / 4); e += 256) {
+        const int v = e % (COUT / 4), px = e / (COUT / 4), x = x0 + px;
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (x < a.W) q = *reinterpret_cast<const float4 *>(a.gout + (row * a.W + x) * COUT + 4 * v);
+        const float g[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
+        for (int c = 0; c < 4; ++c) {
+          const uint16_t hi = f32_to_bf16(g[c]);
+          s_g[0][4 * v + c][px] = hi;
+          s_g[1][4 * v + c][px] = f32_to_bf16(g[c] - bf16_to_f32(hi));
+        }
+      }
+      if constexpr (CIN == 32) {
+        for (int e = tid; e < 3 * 66 * 4; e += 256) {
+          const int v = e & 3, px = (e >> 2) % 66, dy = (e >> 2) / 66;
+          const int sx = x0 + px - 1, sy = y + dy - 1;
+          uint4 q = make_uint4(0u, 0u, 0u, 0u);
+          if (sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+            q = *reinterpret_cast<const uint4 *>(a.in + (((long long)img * a.H + sy) * a.W + sx) * 32 + 8 * v);
+          const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-          for (int k = 0; k < CPT; ++k) {
-            const int ci = cg + k * TPC;
-            if (ci < CIN) acc[t][k] = __fmaf_rn(g, s_in[t / 3][px + t % 3][ci], acc[t][k]);
+          for (int c = 0; c < 8; ++c) s_x[dy][8 * v + c][px + 7] = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
+        }
+      } else {
+        for (int e = tid; e < 3 * 66; e += 256) {
+          const int px = e % 66, dy = e / 66;
+          const int sx = x0 + px - 1, sy = y + dy - 1;
+          uint16_t v = 0;
+          if (sx >= 0 && sx < a.W && sy >= 0 && sy < a.H) v = a.in[((long long)img * a.H + sy) * a.W + sx];
+          s_x[dy][0][px + 7] = v;
+        }
+      }
+      __syncthreads();
+      if (x0 + 16 * wave >= a.W) continue;  // wave-uniform: the wave's pixels are all outside the row
+      const int pb = 16 * wave + 8 * kh;    // this lane's 8 pixels (the K index of the products)
+      const bf16x8 ahi = as_bf16x8(*reinterpret_cast<const uint4 *>(&s_g[0][col][pb]));
+      const bf16x8 alo = as_bf16x8(*reinterpret_cast<const uint4 *>(&s_g[1][col][pb]));
+      if constexpr (CIN == 1) {
+        // column n of B: tap n (n < 9), the bias (n = 9), nothing beyond
+        uint4 bv = make_uint4(0u, 0u, 0u, 0u);
+        if (col < 9) {
+          const uint16_t *r = s_x[col / 3][0];
+          bv = shifted8(*reinterpret_cast<const uint4 *>(r + pb), *reinterpret_cast<const uint4 *>(r + pb + 8),
+                        *reinterpret_cast<const uint4 *>(r + pb + 16), col % 3 - 1);
+        } else if (col == 9) {
+          bv = ones;
+        }
+        const bf16x8 b = as_bf16x8(bv);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, b, acc[0], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, b, acc[0], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const uint16_t *r = s_x[dy][col];
+          const uint4 lo = *reinterpret_cast<const uint4 *>(r + pb), mid = *reinterpret_cast<const uint4 *>(r + pb + 8),
+                      hi = *reinterpret_cast<const uint4 *>(r + pb + 16);
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const bf16x8 b = as_bf16x8(shifted8(lo, mid, hi, dx - 1));
+            const int t = 3 * dy + dx;
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, b, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, b, acc[t], 0, 0, 0);
           }
+        }
+        const bf16x8 b1 = as_bf16x8(ones);
+        acc[9] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, b1, acc[9], 0, 0, 0);
+        acc[9] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, b1, acc[9], 0, 0, 0);
       }
     }
   }
+  // D[co][n]: a lane holds column n = col, rows co = 8 (r / 4) + 4 kh + r % 4.
+  // The four waves' sums of each product are added in a fixed order.
   float *part = a.partial + (size_t)blockIdx.x * (COUT * 9 * CIN + COUT);
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+  for (int t = 0; t < NP; ++t) {
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const int ci = cg + k * TPC;
-      if (ci < CIN) part[((size_t)co * 9 + t) * CIN + ci] = acc[t][k];
+    for (int r = 0; r < 16; ++r) s_red[wave][(8 * (r >> 2) + 4 * kh + (r & 3)) * 32 + col] = acc[t][r];
+    __syncthreads();
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int co = e >> 5, n = e & 31;
+      if (co >= COUT) continue;
+      const float v = ((s_red[0][e] + s_red[1][e]) + s_red[2][e]) + s_red[3][e];
+      if constexpr (CIN == 1) {
+        if (n < 9) part[co * 9 + n] = v;
+        else if (n == 9) part[COUT * 9 + co] = v;
+      } else if (t < 9) {
+        part[((size_t)co * 9 + t) * CIN + n] = v;
+      } else if (n == 0) {
+        part[COUT * 9 * CIN + co] = v;
+      }
     }
-  if (cg == 0) part[COUT * 9 * CIN + co] = bacc;
+  }
 }
 
-// Sum of the partials in block order.
+// Sum of the per-workgroup partials: 8 lanes per output, each adding a
+// contiguous eighth of the partials in order, then the eight sums in a fixed
+// tree (deterministic).
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, int nblocks, int len, float *gw,
                                                       float *gbias, int nw) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+  const int i = blockIdx.x * 32 + (threadIdx.x >> 3), seg = threadIdx.x & 7;
   float s = 0.0f;
-  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * len + i];
-  if (i < nw) gw[i] = s; else if (gbias) gbias[i - nw] = s;
+  if (i < len) {
+    const int b0 = (int)((long long)nblocks * seg / 8), b1 = (int)((long long)nblocks * (seg + 1) / 8);
+    for (int b = b0; b < b1; ++b) s += partial[(size_t)b * len + i];
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 4);
+  if (seg == 0 && i < len) {
+    if (i < nw) gw[i] = s;
+    else if (gbias) gbias[i - nw] = s;
+  }
 }
 
 // grad_pre = grad_post where the post-activation is positive, else 0; also
@@ -438,7 +539,8 @@ hipError_t launch_wgrad(const ConvArgs &a, float *gw, float *gbias, hipStream_t 
   else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_wgrad_partial<32, 16>), dim3(used), dim3(256), 0, stream, a, rpb);
   else return hipErrorInvalidValue;
   const int nw = a.cout * 9 * a.cin, len = nw + a.cout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_of(len)), dim3(256), 0, stream, a.partial, used, len, gw, gbias, nw);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((len + 31) / 32)), dim3(256), 0, stream, a.partial, used, len, gw,
+                     gbias, nw);
   return hipGetLastError();
 }
 
