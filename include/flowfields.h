@@ -549,6 +549,21 @@ ff_status ff_f32_to_bf16(const float *x, int64_t count, uint16_t *y, void *strea
 /* Network input from image bytes: v / 255 - 0.5 as bf16. */
 ff_status ff_image_to_bf16(const uint8_t *img, int64_t count, uint16_t *out, void *stream);
 
+/* DescNet inference (Sec. 3.5, the CNN data term; the network of the
+ * learned descriptor): the three 3x3 convolutions 1 -> 32 -> 32 -> 16 (ReLU
+ * after the first two, "same" zero padding) and, with normalize != 0, unit
+ * length per pixel (delta > 0 as in ff_l2norm16_fwd), in one launch whose
+ * activations stay on chip.  The features equal those of three
+ * ff_conv3x3_fwd calls (bf16 activations between the layers) and
+ * ff_l2norm16_fwd bit for bit.  in: bf16 [B][H][W] network input (as
+ * ff_image_to_bf16 writes it); w1 [32][9][1], w2 [32][9][32], w3
+ * [16][9][32] bf16 (w2, w3 16-byte aligned); b1 [32], b2 [32], b3 [16]
+ * float32; out: float32 [B][H][W][16], 16-byte aligned.  All device
+ * pointers; FF_ERR_ARG for invalid arguments. */
+ff_status ff_descnet_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, const uint16_t *w1, const float *b1,
+                         const uint16_t *w2, const float *b2, const uint16_t *w3, const float *b3, int32_t normalize,
+                         float delta, float *out, void *stream);
+
 /* Unit length per pixel of 16-channel float32 features [pixels][16]
  * (16-byte aligned): out = feat / sqrt(|feat|^2 + delta), delta > 0;
  * inv_norm (nullable, [pixels]) receives 1 / sqrt(|feat|^2 + delta) for the

@@ -1178,6 +1178,30 @@ ff_status ff_adam_step(float *param, const float *grad, float *m, float *v, int3
                                    (hipStream_t)stream));
 }
 
+ff_status ff_descnet_fwd(const uint16_t *in, int32_t B, int32_t H, int32_t W, const uint16_t *w1, const float *b1,
+                         const uint16_t *w2, const float *b2, const uint16_t *w3, const float *b3, int32_t normalize,
+                         float delta, float *out, void *stream) {
+  if (!in || !w1 || !b1 || !w2 || !b2 || !w3 || !b3 || !out || B < 1 || !dims_ok(W, H) ||
+      (long long)B * H * W >= (1ll << 31) || (normalize && !(delta > 0.0f)) || !aligned16(w2) || !aligned16(w3) ||
+      !aligned16(out))
+    return FF_ERR_ARG;
+  ffh::NetArgs a{};
+  a.in = in;
+  a.w1 = w1;
+  a.w2 = w2;
+  a.w3 = w3;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.b3 = b3;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  a.normalize = normalize != 0;
+  a.delta = delta;
+  a.out = out;
+  return from_hip(ffh::launch_descnet_fwd(a, (hipStream_t)stream));
+}
+
 ff_status ff_l2norm16_fwd(const float *feat, int64_t pixels, float delta, float *out, float *inv_norm, void *stream) {
   if (!feat || !out || pixels < 0 || !(delta > 0.0f) || !aligned16(feat) || !aligned16(out)) return FF_ERR_ARG;
   return from_hip(ffh::launch_l2norm16_fwd(feat, pixels, delta, out, inv_norm, (hipStream_t)stream));

@@ -39,6 +39,17 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
   return r;
 }
 
+// The 16 features of one pixel scaled to unit length; returns the scale.
+__device__ __forceinline__ float l2norm16(float4 v[4], float delta) {
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += v[k].x * v[k].x + v[k].y * v[k].y + v[k].z * v[k].z + v[k].w * v[k].w;
+  const float r = 1.0f / sqrtf(s + delta);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = make_float4(v[k].x * r, v[k].y * r, v[k].z * r, v[k].w * r);
+  return r;
+}
+
 // Single input channel (the first layer): K = 9 taps padded to 16, lane
 // half kh holds taps 8 * kh .. 8 * kh + 7 of one pixel.
 template <int CIN, int COUT>
@@ -161,6 +172,140 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         }
       }
     }
+  }
+}
+
+// The whole network for inference in one launch (1 -> 32 -> 32 -> 16, ReLU
+// after the first two layers, optionally unit length per pixel): a
+// workgroup computes a tile of 60 x kNetRows output pixels; the first
+// layer's outputs on the tile plus two pixels on every side and the second
+// layer's plus one stay in LDS (zero outside the image, the "same" padding
+// of the next layer), so the activations never leave the chip.  Every
+// layer issues exactly the matrix-core products of k_conv_fwd (first
+// layer) and k_conv_fwd_tile (32 pixels of a row per product, taps then
+// channel chunks, the same operands) and the same bias, ReLU and bf16
+// rounding, and the normalisation is l2norm16: the features are bit for bit
+// those of the three convolution launches and the normalisation launch.
+constexpr int kNetRows = 4, kNetTW = 60, kNetCols = 64, kNetPX = 5;  // 16-byte slots per staged pixel
+
+__global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
+  constexpr int R1 = kNetRows + 4, R2 = kNetRows + 2, R0 = kNetRows + 6, C0 = kNetCols + 2;
+  __shared__ uint16_t s_in[R0][C0];                    // network input, tile + 3 pixels
+  __shared__ uint4 s_a1[R1 * kNetCols * kNetPX];         // first layer's outputs, tile + 2 pixels
+  __shared__ uint4 s_a2[R2 * kNetCols * kNetPX];         // second layer's outputs, tile + 1 pixel
+  float *s_out = reinterpret_cast<float *>(s_a1);        // third layer's outputs (after s_a1 is read)
+  const int W = a.W, H = a.H;
+  const int tiles_x = (W + kNetTW - 1) / kNetTW, tiles_y = (H + kNetRows - 1) / kNetRows;
+  const int img = blockIdx.x / (tiles_x * tiles_y), t = blockIdx.x % (tiles_x * tiles_y);
+  const int x0 = (t % tiles_x) * kNetTW, y0 = (t / tiles_x) * kNetRows;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = lane & 31, kh = lane >> 5, col = row;
+  const size_t plane = (size_t)img * H * W;
+  auto inside = [&](int y, int x) { return y >= 0 && y < H && x >= 0 && x < W; };
+  // a tile whose first-layer region lies inside the image needs no border
+  // zeros (wave-uniform)
+  const bool interior = y0 >= 2 && y0 + kNetRows + 2 <= H && x0 >= 2 && x0 + kNetCols - 2 <= W;
+  // every weight operand first (the three layers' loads in flight together
+  // with the input tile's)
+  uint16_t bw1[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int tap = 8 * kh + e;
+    bw1[e] = tap < 9 ? a.w1[col * 9 + tap] : (uint16_t)0;
+  }
+  uint4 ub2[18], ub3[18];
+  const uint32_t wmask = col < 16 ? 0xFFFFFFFFu : 0u;  // third layer: columns beyond the 16 outputs multiply by zero
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      ub2[tap * 2 + cc] = reinterpret_cast<const uint4 *>(a.w2 + ((size_t)col * 9 + tap) * 32)[cc * 2 + kh];
+      const uint4 w = reinterpret_cast<const uint4 *>(a.w3 + ((size_t)min(col, 15) * 9 + tap) * 32)[cc * 2 + kh];
+      ub3[tap * 2 + cc] = make_uint4(w.x & wmask, w.y & wmask, w.z & wmask, w.w & wmask);
+    }
+  const float bias1 = a.b1[col], bias2 = a.b2[col], bias3 = col < 16 ? a.b3[col] : 0.0f;
+  uint4 ub1;
+  __builtin_memcpy(&ub1, bw1, 16);
+  for (int k = tid; k < R0 * C0; k += 256) {
+    const int ry = k / C0, cx = k % C0, y = y0 - 3 + ry, x = x0 - 3 + cx;
+    s_in[ry][cx] = inside(y, x) ? a.in[plane + (size_t)y * W + x] : (uint16_t)0;
+  }
+  __syncthreads();
+  // first layer: K = 9 taps padded to 16, lane half kh holds taps 8 kh .. 8 kh + 7
+  for (int item = wave; item < 2 * R1; item += 4) {
+    const int ry = item >> 1, c = 32 * (item & 1) + row;  // output pixel (y0 - 2 + ry, x0 - 2 + c)
+    uint16_t av[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int tap = 8 * kh + e;
+      av[e] = tap < 9 ? s_in[ry + tap / 3][c + tap % 3] : (uint16_t)0;
+    }
+    uint4 ua;
+    __builtin_memcpy(&ua, av, 16);
+    f32x16 acc = {0};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub1), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int cc = 32 * (item & 1) + 8 * (r >> 2) + 4 * kh + (r & 3);
+      const float v = fmaxf(acc[r] + bias1, 0.0f);
+      reinterpret_cast<uint16_t *>(&s_a1[(ry * kNetCols + cc) * kNetPX])[col] =
+          (interior || inside(y0 - 2 + ry, x0 - 2 + cc)) ? f32_to_bf16(v) : (uint16_t)0;
+    }
+  }
+  __syncthreads();
+  // second and third layers: 9 taps x 2 channel chunks of 16 per product, a
+  // wave running two row blocks at once (independent accumulator chains)
+  auto layer = [&](const uint4 *src_map, const uint4(&ub)[18], int nrows, auto &&store) {
+    for (int item = 2 * wave; item < 2 * nrows; item += 8) {
+      const int i2 = min(item + 1, 2 * nrows - 1);  // the pair's second block (a repeat when there is none)
+      const int ra = item >> 1, ba = 32 * (item & 1), rb = i2 >> 1, bb = 32 * (i2 & 1);
+      f32x16 acc0 = {0}, acc1 = {0};
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const uint4 *s0 = src_map + ((ra + tap / 3) * kNetCols + min(ba + row + tap % 3, kNetCols - 1)) * kNetPX;
+        const uint4 *s1 = src_map + ((rb + tap / 3) * kNetCols + min(bb + row + tap % 3, kNetCols - 1)) * kNetPX;
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s0[cc * 2 + kh]), as_bf16x8(ub[tap * 2 + cc]), acc0,
+                                                         0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s1[cc * 2 + kh]), as_bf16x8(ub[tap * 2 + cc]), acc1,
+                                                         0, 0, 0);
+        }
+      }
+      store(ra, ba, acc0);
+      if (i2 != item) store(rb, bb, acc1);
+    }
+  };
+  layer(s_a1, ub2, R2, [&](int ry, int blk, const f32x16 &acc) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int c = blk + 8 * (r >> 2) + 4 * kh + (r & 3);  // pixel (y0 - 1 + ry, x0 - 1 + c)
+      const float v = fmaxf(acc[r] + bias2, 0.0f);
+      reinterpret_cast<uint16_t *>(&s_a2[(ry * kNetCols + c) * kNetPX])[col] =
+          (interior || inside(y0 - 1 + ry, x0 - 1 + c)) ? f32_to_bf16(v) : (uint16_t)0;
+    }
+  });
+  __syncthreads();  // s_a2 complete; s_a1 no longer read
+  layer(s_a2, ub3, kNetRows, [&](int ry, int blk, const f32x16 &acc) {
+    if (col < 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = blk + 8 * (r >> 2) + 4 * kh + (r & 3);  // pixel (y0 + ry, x0 + c)
+        s_out[(ry * kNetCols + c) * 16 + col] = acc[r] + bias3;
+      }
+    }
+  });
+  __syncthreads();
+  for (int k = tid; k < kNetRows * kNetTW; k += 256) {
+    const int ry = k / kNetTW, c = k % kNetTW, y = y0 + ry, x = x0 + c;
+    if (!inside(y, x)) continue;
+    float4 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = reinterpret_cast<const float4 *>(s_out + (ry * kNetCols + c) * 16)[q];
+    if (a.normalize) l2norm16(v, a.delta);
+    float4 *dst = reinterpret_cast<float4 *>(a.out + (plane + (size_t)y * W + x) * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = v[q];
   }
 }
 
@@ -385,15 +530,11 @@ __global__ __launch_bounds__(256) void k_l2norm16_fwd(const float4 *f, long long
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   float4 v[4];
-  float s = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = f[p * 4 + k];
-    s += v[k].x * v[k].x + v[k].y * v[k].y + v[k].z * v[k].z + v[k].w * v[k].w;
-  }
-  const float r = 1.0f / sqrtf(s + delta);
+  for (int k = 0; k < 4; ++k) v[k] = f[p * 4 + k];
+  const float r = l2norm16(v, delta);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) y[p * 4 + k] = make_float4(v[k].x * r, v[k].y * r, v[k].z * r, v[k].w * r);
+  for (int k = 0; k < 4; ++k) y[p * 4 + k] = v[k];
   if (inv_norm) inv_norm[p] = r;
 }
 
@@ -520,6 +661,13 @@ hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t stream) {
   else if (a.cin == 32 && a.cout == 16) hipLaunchKernelGGL((k_conv_fwd_tile<32, 16>), tgrid, dim3(256), 0, stream, a);
   else if (a.cin == 16 && a.cout == 32) hipLaunchKernelGGL((k_conv_fwd_tile<16, 32>), tgrid, dim3(256), 0, stream, a);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_descnet_fwd(const NetArgs &a, hipStream_t stream) {
+  const long long tiles = (long long)a.B * ((a.W + kNetTW - 1) / kNetTW) * ((a.H + kNetRows - 1) / kNetRows);
+  if (tiles <= 0 || tiles > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_descnet_fwd, dim3((unsigned)tiles), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

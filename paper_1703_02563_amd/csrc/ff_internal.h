@@ -274,6 +274,16 @@ struct ConvArgs {
   float *partial;      // weight gradient: per-block partial sums
 };
 hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t stream);
+// The descriptor network 1 -> 32 -> 32 -> 16 for inference in one launch.
+struct NetArgs {
+  const uint16_t *in;             // [B][H][W] bf16 network input
+  const uint16_t *w1, *w2, *w3;   // bf16 [32][9][1], [32][9][32], [16][9][32]
+  const float *b1, *b2, *b3;      // [32], [32], [16]
+  int B, H, W, normalize;
+  float delta;
+  float *out;                     // [B][H][W][16]
+};
+hipError_t launch_descnet_fwd(const NetArgs &a, hipStream_t stream);
 hipError_t launch_weight_flip(const uint16_t *w, uint16_t *wf, int cin, int cout, hipStream_t stream);
 int wgrad_blocks(int B, int H);
 hipError_t launch_wgrad(const ConvArgs &a, float *gw, float *gbias, hipStream_t stream);

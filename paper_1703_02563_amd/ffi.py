@@ -103,6 +103,7 @@ _SIGS = {
     "ff_adam_step": (C.c_int, [_P, _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float, _I32, _P, _P]),
     "ff_triplet_hinge": (C.c_int, [_P, _I32, C.c_float, C.c_float, C.c_float, _P, _P, _P]),
     "ff_l2norm16_fwd": (C.c_int, [_P, C.c_int64, C.c_float, _P, _P, _P]),
+    "ff_descnet_fwd": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _I32, C.c_float, _P, _P]),
     "ff_l2norm16_bwd": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "ff_quantize_scratch_bytes": (C.c_size_t, []),
     "ff_quantize_u8": (C.c_int, [_P, C.c_int64, _P, _P, _P]),

@@ -204,6 +204,16 @@ class DescNet:
                                      _ptr(self.v[k]), p.numel(), lr, b1, b2, eps, self.step, _ptr(wbits), _stream()),
                   "ff_adam_step")
 
+    def infer(self, x_bits: torch.Tensor) -> torch.Tensor:
+        """Inference of the whole network in one launch (ff_descnet_fwd):
+        the same float32 features [B, H, W, 16] as forward(), bit for bit."""
+        B, H, W, _ = x_bits.shape
+        out = torch.empty((B, H, W, 16), dtype=torch.float32, device=x_bits.device)
+        check(lib().ff_descnet_fwd(_ptr(x_bits), B, H, W, _ptr(self.wb[0]), _ptr(self.b[0]), _ptr(self.wb[1]),
+                                   _ptr(self.b[1]), _ptr(self.wb[2]), _ptr(self.b[2]), int(self.normalize), self.delta,
+                                   _ptr(out), _stream()), "ff_descnet_fwd")
+        return out
+
     def features(self, img: torch.Tensor) -> torch.Tensor:
         """uint8 [H, W] -> float32 [H, W, 16]."""
         return self.forward(self.input_from_images(img[None]))[0]
@@ -321,8 +331,8 @@ def scale_images(img1: torch.Tensor, img2: torch.Tensor, levels: int) -> torch.T
 
 
 def learned_features(net: DescNet, scales: torch.Tensor) -> torch.Tensor:
-    """DescNet features of every scale image in one batched pass: float32 [2L, H, W, 16]."""
-    return net.forward(net.input_from_images(scales))
+    """DescNet features of every scale image in one launch: float32 [2L, H, W, 16]."""
+    return net.infer(net.input_from_images(scales))
 
 
 def learned_flow_fields(net: DescNet, img1: torch.Tensor, img2: torch.Tensor, params, scales=None) -> dict:

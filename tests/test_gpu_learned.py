@@ -418,3 +418,23 @@ def test_cost_grad_overflow_gives_nan_not_a_wrapped_sum():
     assert torch.isfinite(g1).all() and torch.isfinite(g2).all()
     assert float(g1[..., 0].max()) == 3 * 2.0 ** 21 and float(g2[..., 0].min()) == -3 * 2.0 ** 21
     assert float(g1[..., 1:].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("shape", [(1, 48, 64), (3, 37, 61), (2, 5, 3), (1, 1, 1), (1, 4, 121), (2, 436, 1024)])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_fused_network_equals_the_layer_launches(shape, normalize):
+    """ff_descnet_fwd (the whole network in one launch, activations on chip)
+    gives the features of the three convolution launches and the
+    normalisation launch bit for bit: ragged tiles (60 x 4 output pixels per
+    workgroup), tiny and full-size frames, with non-zero biases."""
+    B, H, W = shape
+    net = Lm.DescNet(seed=3, normalize=normalize)
+    g = torch.Generator().manual_seed(11)
+    for k in range(3):
+        net.b[k] = (torch.randn(net.b[k].shape, generator=g) * 0.1).cuda()
+    img = (torch.rand((B, H, W), generator=g) * 255).round().to(torch.uint8).cuda()
+    x = net.input_from_images(img)
+    ref = net.forward(x)
+    got = net.infer(x)
+    torch.cuda.synchronize()
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
