@@ -181,11 +181,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 // layer's outputs on the tile plus two pixels on every side and the second
 // layer's plus one stay in LDS (zero outside the image, the "same" padding
 // of the next layer), so the activations never leave the chip.  Every
-// layer issues exactly the matrix-core products of k_conv_fwd (first
-// layer) and k_conv_fwd_tile (32 pixels of a row per product, taps then
-// channel chunks, the same operands) and the same bias, ReLU and bf16
-// rounding, and the normalisation is l2norm16: the features are bit for bit
-// those of the three convolution launches and the normalisation launch.
+// layer issues the matrix-core products of k_conv_fwd (first layer) and
+// k_conv_fwd_tile (32 pixels of a row per product, taps then channel chunks,
+// the same operands, here as the transposed product) and the same bias,
+// ReLU and bf16 rounding, and the normalisation is l2norm16: the features
+// are bit for bit those of the three convolution launches and the
+// normalisation launch.
 constexpr int kNetRows = 4, kNetTW = 60, kNetCols = 64, kNetPX = 5;  // 16-byte slots per staged pixel
 
 __global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
@@ -223,7 +224,6 @@ __global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
       const uint4 w = reinterpret_cast<const uint4 *>(a.w3 + ((size_t)min(col, 15) * 9 + tap) * 32)[cc * 2 + kh];
       ub3[tap * 2 + cc] = make_uint4(w.x & wmask, w.y & wmask, w.z & wmask, w.w & wmask);
     }
-  const float bias1 = a.b1[col], bias2 = a.b2[col], bias3 = col < 16 ? a.b3[col] : 0.0f;
   uint4 ub1;
   __builtin_memcpy(&ub1, bw1, 16);
   for (int k = tid; k < R0 * C0; k += 256) {
@@ -231,9 +231,36 @@ __global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
     s_in[ry][cx] = inside(y, x) ? a.in[plane + (size_t)y * W + x] : (uint16_t)0;
   }
   __syncthreads();
+  // The products are taken transposed, D = W X (weights the first operand,
+  // the 32 pixels the columns): a lane then holds 16 output channels of one
+  // pixel, channels 8 g + 4 kh .. 8 g + 4 kh + 3 for g = 0..3, and writes
+  // them with four 8-byte stores.  Every output element is the same sum of
+  // the same products as in the per-layer kernels.
+  // bf16 outputs of one pixel (zero outside the image: the next layer's
+  // padding) into a staged map
+  // the biases of a lane's 16 output channels, per layer
+  auto lane_bias = [&](const float *b, int nout, float (&bl)[16]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int co = 8 * (r >> 2) + 4 * kh + (r & 3);
+      bl[r] = co < nout ? b[co] : 0.0f;
+    }
+  };
+  auto store_bf16 = [&](uint4 *map, int ry, int c, const f32x16 &acc, const float (&bl)[16], bool in_image) {
+    uint8_t *px = reinterpret_cast<uint8_t *>(&map[(ry * kNetCols + c) * kNetPX]);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint32_t h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = in_image ? f32_to_bf16(fmaxf(acc[4 * g + q] + bl[4 * g + q], 0.0f)) : 0u;
+      *reinterpret_cast<uint2 *>(px + 16 * g + 8 * kh) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+  };
   // first layer: K = 9 taps padded to 16, lane half kh holds taps 8 kh .. 8 kh + 7
+  float bl[16];
+  lane_bias(a.b1, 32, bl);
   for (int item = wave; item < 2 * R1; item += 4) {
-    const int ry = item >> 1, c = 32 * (item & 1) + row;  // output pixel (y0 - 2 + ry, x0 - 2 + c)
+    const int ry = item >> 1, c = 32 * (item & 1) + row;  // this lane's pixel (y0 - 2 + ry, x0 - 2 + c)
     uint16_t av[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -243,14 +270,8 @@ __global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
     uint4 ua;
     __builtin_memcpy(&ua, av, 16);
     f32x16 acc = {0};
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ua), as_bf16x8(ub1), acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int cc = 32 * (item & 1) + 8 * (r >> 2) + 4 * kh + (r & 3);
-      const float v = fmaxf(acc[r] + bias1, 0.0f);
-      reinterpret_cast<uint16_t *>(&s_a1[(ry * kNetCols + cc) * kNetPX])[col] =
-          (interior || inside(y0 - 2 + ry, x0 - 2 + cc)) ? f32_to_bf16(v) : (uint16_t)0;
-    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ub1), as_bf16x8(ua), acc, 0, 0, 0);
+    store_bf16(s_a1, ry, c, acc, bl, interior || inside(y0 - 2 + ry, x0 - 2 + c));
   }
   __syncthreads();
   // second and third layers: 9 taps x 2 channel chunks of 16 per product, a
@@ -266,33 +287,29 @@ __global__ __launch_bounds__(256) void k_descnet_fwd(ffh::NetArgs a) {
         const uint4 *s1 = src_map + ((rb + tap / 3) * kNetCols + min(bb + row + tap % 3, kNetCols - 1)) * kNetPX;
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s0[cc * 2 + kh]), as_bf16x8(ub[tap * 2 + cc]), acc0,
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ub[tap * 2 + cc]), as_bf16x8(s0[cc * 2 + kh]), acc0,
                                                          0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s1[cc * 2 + kh]), as_bf16x8(ub[tap * 2 + cc]), acc1,
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ub[tap * 2 + cc]), as_bf16x8(s1[cc * 2 + kh]), acc1,
                                                          0, 0, 0);
         }
       }
-      store(ra, ba, acc0);
-      if (i2 != item) store(rb, bb, acc1);
+      store(ra, ba + row, acc0);
+      if (i2 != item) store(rb, bb + row, acc1);
     }
   };
-  layer(s_a1, ub2, R2, [&](int ry, int blk, const f32x16 &acc) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int c = blk + 8 * (r >> 2) + 4 * kh + (r & 3);  // pixel (y0 - 1 + ry, x0 - 1 + c)
-      const float v = fmaxf(acc[r] + bias2, 0.0f);
-      reinterpret_cast<uint16_t *>(&s_a2[(ry * kNetCols + c) * kNetPX])[col] =
-          (interior || inside(y0 - 1 + ry, x0 - 1 + c)) ? f32_to_bf16(v) : (uint16_t)0;
-    }
+  lane_bias(a.b2, 32, bl);
+  layer(s_a1, ub2, R2, [&](int ry, int c, const f32x16 &acc) {  // pixel (y0 - 1 + ry, x0 - 1 + c)
+    store_bf16(s_a2, ry, c, acc, bl, interior || inside(y0 - 1 + ry, x0 - 1 + c));
   });
+  lane_bias(a.b3, 16, bl);
   __syncthreads();  // s_a2 complete; s_a1 no longer read
-  layer(s_a2, ub3, kNetRows, [&](int ry, int blk, const f32x16 &acc) {
-    if (col < 16) {
+  layer(s_a2, ub3, kNetRows, [&](int ry, int c, const f32x16 &acc) {  // pixel (y0 + ry, x0 + c): channels < 16
+    float *px = s_out + (ry * kNetCols + c) * 16;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int c = blk + 8 * (r >> 2) + 4 * kh + (r & 3);  // pixel (y0 + ry, x0 + c)
-        s_out[(ry * kNetCols + c) * 16 + col] = acc[r] + bias3;
-      }
+    for (int g = 0; g < 2; ++g) {
+      const int co = 8 * g + 4 * kh;
+      *reinterpret_cast<float4 *>(px + co) = make_float4(acc[4 * g] + bl[4 * g], acc[4 * g + 1] + bl[4 * g + 1],
+                                                         acc[4 * g + 2] + bl[4 * g + 2], acc[4 * g + 3] + bl[4 * g + 3]);
     }
   });
   __syncthreads();
