@@ -274,6 +274,8 @@ template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
   // patch radius RR: 3, or 2 and 4 with the descriptor-quad evaluations
   // (the weight-class maps and the float path hold radius-3 patches)
+  static_assert(Geo<TW, TH, HALO, RR>::LW * Geo<TW, TH, HALO, RR>::LH + kThreads < 65536,
+                "the cell index of a half-sweep must stay below 2^16 (cell_of's division)");
   static_assert(RR == kR || ((RR == 2 || RR == 4) && EV == 3 && !F32),
                 "radii 2 and 4 run the descriptor-quad kernels only");
   using G = Geo<TW, TH, HALO, RR>;
@@ -466,10 +468,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   auto rs_after = [&](int t) { return t != a.P - 1 && t != a.T - 1; };
   // random-search candidate of cell (i, j) at step t from its current state
   [[maybe_unused]] auto rs_candidate = [&](int i, int j, int l, int t, int32_t &fc) {
-    if (s_cost[l] == kUnset) return false;
+    const uint32_t c0 = s_cost[l];
+    const int32_t f0 = s_flow[l];
+    if (c0 == kUnset) return false;
     int ox, oy;
     ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, t < a.P ? a.Rnp : a.Rn, ox, oy);
-    const int32_t f0 = s_flow[l];
     const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
     const int tx = i * n + fx, ty = j * n + fy;
     fc = ffk::pack_flow(fx, fy);
@@ -604,10 +607,14 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       if (vdj < 0) --mt; else --mb;
       const int rl = max(ti0 - ml, 0), rr = min(oi1 + mr, Wn), rt = max(tj0 - mt, 0), rb = min(oj1 + mb, Hn);
       const int hw = (rr - rl + 1) >> 1, rh = rb - rt;
+      // k / hw as a multiply-high by ceil(2^32 / hw): exact for k, hw < 2^16
+      // (the error term k (m - 2^32 / hw) / 2^32 stays below 1 / hw)
+      const uint32_t hwm = hw > 1 ? 0xFFFFFFFFu / (uint32_t)hw + 1u : 0u;
       // Cells of this colour in the valid window, thread-strided.
       auto cell_of = [&](int c, int k, int &i, int &j) {
-        j = rt + (k < hw * rh ? k / hw : 0);
-        i = rl + ((c + j + rl) & 1) + 2 * (k % max(hw, 1));
+        const int q = hw > 1 ? (int)__umulhi((uint32_t)k, hwm) : k;
+        j = rt + (k < hw * rh ? q : 0);
+        i = rl + ((c + j + rl) & 1) + 2 * (hw > 1 ? k - q * hw : 0);
         return k < hw * rh && i < rr;
       };
       auto cell = [&](int k, int &i, int &j) { return cell_of(colour, k, i, j); };
@@ -626,20 +633,27 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         bool hv = false, vcomp = false;
         [[maybe_unused]] bool hin = false, vin = false;  // weight-class path: cell and target inside
         if (live) {
-          const uint32_t c0 = s_cost[l];
-          const int32_t f0 = s_flow[l];
+          // the state of the cell and of both sources in one round of LDS
+          // reads: a source cell lies inside the window for every live cell
+          // (the valid region shrinks towards it), so the reads need no
+          // guard; an outside-grid source's slot holds nothing used
+          const int lh = l + hdi, lv = l + vdj * G::LW;
+          uint32_t c0 = s_cost[l], chs = s_cost[lh], cvs = s_cost[lv];
+          int32_t f0 = s_flow[l], fhs = s_flow[lh], fvs = s_flow[lv];
+          // keeps the compiler from sinking the reads into the branches below
+          asm volatile("" : "+v"(c0), "+v"(chs), "+v"(cvs), "+v"(f0), "+v"(fhs), "+v"(fvs));
           const bool set0 = c0 != kUnset;
           const int x = i * n, y = j * n;
           bool vb = false, vsame_h = false, vsame_0 = false;
           int32_t fh = 0;
-          if (i + hdi >= 0 && i + hdi < Wn && s_cost[l + hdi] != kUnset) {
-            fh = s_flow[l + hdi];
+          if (i + hdi >= 0 && i + hdi < Wn && chs != kUnset) {
+            fh = fhs;
             const int tx = x + ffk::flow_x(fh), ty = y + ffk::flow_y(fh);
             hv = !(set0 && fh == f0) && tx >= 0 && tx < W && ty >= 0 && ty < H;
             if constexpr (WF) hin = inner(i, j, tx, ty);
           }
-          if (j + vdj >= 0 && j + vdj < Hn && s_cost[l + vdj * G::LW] != kUnset) {
-            const int32_t fv = s_flow[l + vdj * G::LW];
+          if (j + vdj >= 0 && j + vdj < Hn && cvs != kUnset) {
+            const int32_t fv = fvs;
             const int tx = x + ffk::flow_x(fv), ty = y + ffk::flow_y(fv);
             vb = tx >= 0 && tx < W && ty >= 0 && ty < H;
             vsame_h = hv && fv == fh;
@@ -741,6 +755,10 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
         const int l = (j - gj0) * G::LW + (i - gi0);
         int cnt = 0;
         if (live) {
+          // both source flows read with the key and flags (one round of
+          // LDS reads; the sources lie inside the window, as in the check)
+          int32_t fhs = s_flow[l + hdi], fvs = s_flow[l + vdj * G::LW];
+          asm volatile("" : "+v"(fhs), "+v"(fvs));
           bool unset;
           int rank;
           uint32_t cost;
@@ -761,48 +779,43 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
           // the vertical source counts as evaluated unless it equals the
           // best flow after the horizontal step
           if (vb) cnt += vsame_h ? (rank == 0) : vsame_0 ? (rank == 1) : 1;
-          if (rank) s_flow[l] = s_flow[rank == 1 ? l + hdi : l + vdj * G::LW];
+          if (rank) s_flow[l] = rank == 1 ? fhs : fvs;
           s_cost[l] = cost;
           if (!owned(i, j)) cnt = 0;
         }
         if constexpr (QUAD) {
           // after the second half-sweep of a step with a random search:
-          // the cell is final, draw its candidate now
+          // the cell is final, draw its candidate now, and that of the cell
+          // of the other colour with the same index (final since the first
+          // half-sweep; the same number of cells): the two hashes are
+          // independent, so they run interleaved
           if (colour == 0 && rs_after(t)) {
-            int32_t fc = 0;
+            int i1, j1;
+            const bool live1 = cell_of(1, base + tid, i1, j1);
+            const int l1 = (j1 - gj0) * G::LW + (i1 - gi0);
+            int32_t fc = 0, fc1 = 0;
             const bool act = live && rs_candidate(i, j, l, t, fc);
+            const bool act1 = live1 && rs_candidate(i1, j1, l1, t, fc1);
             if (act) {
               s_flags[l] = (uint32_t)fc;
               cnt += owned(i, j);
             }
-            if constexpr (WF)
+            if (act1) s_flags[l1] = (uint32_t)fc1;
+            const int tot1 = __popcll(__ballot(act1 && owned(i1, j1)));
+            if ((tid & 63) == 0 && tot1) atomicAdd(&s_cnt, (unsigned)tot1);
+            if constexpr (WF) {
               enqueue2(act, act && inner(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc)), (uint16_t)l, s_rlen,
                        s_rblen);
-            else
+              enqueue2(act1, act1 && inner(i1, j1, i1 * n + ffk::flow_x(fc1), j1 * n + ffk::flow_y(fc1)),
+                       (uint16_t)l1, s_rlen, s_rblen);
+            } else {
               enqueue(act, (uint16_t)l, s_rlen);
+              enqueue(act1, (uint16_t)l1, s_rlen);
+            }
           }
         }
         const int tot = __popcll(__ballot(cnt >= 1)) + __popcll(__ballot(cnt >= 2)) + __popcll(__ballot(cnt >= 3));
         if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
-      }
-      if constexpr (QUAD) {
-        if (colour == 0 && rs_after(t)) {  // the other colour is final since the first half-sweep
-          for (int base = 0; base < hw * rh; base += kThreads) {
-            int i, j;
-            const bool live = cell_of(1, base + tid, i, j);
-            const int l = (j - gj0) * G::LW + (i - gi0);
-            int32_t fc = 0;
-            const bool act = live && rs_candidate(i, j, l, t, fc);
-            if (act) s_flags[l] = (uint32_t)fc;
-            const int tot = __popcll(__ballot(act && owned(i, j)));
-            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt, (unsigned)tot);
-            if constexpr (WF)
-              enqueue2(act, act && inner(i, j, i * n + ffk::flow_x(fc), j * n + ffk::flow_y(fc)), (uint16_t)l, s_rlen,
-                       s_rblen);
-            else
-              enqueue(act, (uint16_t)l, s_rlen);
-          }
-        }
       }
       __syncthreads();
     }
