@@ -154,7 +154,9 @@ const char *ff_status_str(ff_status s);
  * blurred[y][x] = round-half-up mean of img over the (2h+1)^2 window,
  * h = max(1, n/2), replicate border; desc[y][x][4*gy+gx] =
  * blurred[clamp(y + n*(2gy-3))][clamp(x + n*(2gx-3))], gx, gy in 0..3.
- * img: [H][W]; blurred: [H][W] output; hsum: [H][W] uint16 scratch;
+ * img: [H][W]; blurred: [H][W] output; hsum: [H][W] uint16 scratch
+ * (required; this single-image path keeps its row sums in LDS and leaves it
+ * untouched);
  * desc: the descriptor MAP of scale n (output, ff_descriptor_map_bytes);
  * desc_rowmajor (nullable): the same descriptors as plain [H][W][16] (the
  * input of ff_init_nn's nearest-neighbour search); wform (nullable): the

@@ -3,7 +3,8 @@
 //
 // I^n: integer box filter of half-width h = max(1, n/2), rounded half up,
 // computed separably (row sums, then column sums of the row sums; both are
-// exact in integers).  Descriptor of scale n: the 16 samples of I^n on a 4x4
+// exact in integers), per 64 x 64 tile in LDS (batches: through a row-sum
+// buffer).  Descriptor of scale n: the 16 samples of I^n on a 4x4
 // grid with spacing 2n around the pixel, stored as one 16-byte vector per
 // pixel so that a patch position costs one 128-bit load; the pixels of each
 // row are stored in phase order (x mod n, then x / n), and the map carries a
@@ -20,47 +21,80 @@ namespace {
 
 using ffk::clampi;
 
-// Row sums: a thread takes kRun consecutive pixels of a row and slides the
-// window along them (2h + kRun loads for kRun sums instead of (2h + 1) each).
-constexpr int kRun = 8;
+// Box filter of one (image, scale) job on a 64 x 64 tile of outputs: the
+// input tile with its h-wide border (edge pixels replicated) is staged in
+// LDS, every staged row gets the row sums of the tile's 64 columns by a
+// sliding window over 8 consecutive columns, then every output takes the
+// column sum of 2h + 1 row sums, also sliding over 8 rows, rounded half up
+// over the box area.  These are the integer sums of the separable
+// definition (exact in any order), in one pass over the image.
+constexpr int kBT = 64, kBHmax = 32, kBS = kBT + 2 * kBHmax;  // tile, largest half-width (n <= 64), staged side
 
-__global__ __launch_bounds__(256) void k_hsum(ffh::DescJobs jobs) {
+__global__ __launch_bounds__(256) void k_blur(ffh::DescJobs jobs) {
+  __shared__ uint8_t s_in[kBS * kBS];
+  __shared__ uint16_t s_row[kBS * kBT];  // (2h + 1) * 255 fits 16 bits
   const ffh::DescJob &jb = jobs.job[blockIdx.z];
   const int W = jobs.W, H = jobs.H;
-  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * kRun, y = blockIdx.y;
-  if (x0 >= W || y >= H) return;
-  const int h = max(1, jb.n >> 1);
-  const uint8_t *row = jb.img + (size_t)y * W;
-  uint16_t *out = jb.hsum + (size_t)y * W;
-  uint32_t s = 0;
-  for (int dx = -h; dx <= h; ++dx) s += row[clampi(x0 + dx, W - 1)];
-  out[x0] = (uint16_t)s;
-  const int x1 = min(x0 + kRun, W);
-  for (int x = x0 + 1; x < x1; ++x) {
-    s += row[clampi(x + h, W - 1)];
-    s -= row[clampi(x - h - 1, W - 1)];
-    out[x] = (uint16_t)s;
+  const int h = max(1, jb.n >> 1), S = kBT + 2 * h;  // staged rows and columns
+  const int x0 = blockIdx.x * kBT, y0 = blockIdx.y * kBT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // staged rows ty + 4u, columns tx and tx + 64: 16 loads in flight per
+  // thread before their LDS stores (rows past S read a clamped row, unused)
+  const int xa = clampi(x0 - h + tx, W - 1), xb = clampi(x0 - h + tx + 64, W - 1);
+  for (int u0 = 0; u0 < S; u0 += 32) {
+    uint32_t va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint8_t *row = jb.img + (size_t)clampi(y0 - h + u0 + ty + 4 * u, H - 1) * W;
+      va[u] = row[xa];
+      vb[u] = row[xb];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = u0 + ty + 4 * u;
+      if (r < S) {
+        s_in[r * S + tx] = (uint8_t)va[u];
+        if (tx + 64 < S) s_in[r * S + tx + 64] = (uint8_t)vb[u];
+      }
+    }
   }
-}
-
-// Column sums of the row sums, divided by the box area: a thread takes kRun
-// consecutive rows of a column and slides the window down them.
-__global__ __launch_bounds__(256) void k_vsum(ffh::DescJobs jobs) {
-  const ffh::DescJob &jb = jobs.job[blockIdx.z];
-  const int W = jobs.W, H = jobs.H;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y * kRun;
-  if (x >= W || y0 >= H) return;
-  const int h = max(1, jb.n >> 1);
+  __syncthreads();
+  // row sums of staged row r for output columns c0 .. c0 + 7 (window of
+  // output column c: staged columns c .. c + 2h)
+  for (int k = threadIdx.x; k < S * (kBT / 8); k += 256) {
+    const int r = k >> 3, c0 = (k & 7) * 8;
+    const uint8_t *row = s_in + r * S + c0;
+    uint16_t *out = s_row + r * kBT + c0;
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (int dx = 0; dx <= 2 * h; ++dx) sum += row[dx];
+    out[0] = (uint16_t)sum;
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+      sum += row[c + 2 * h];
+      sum -= row[c - 1];
+      out[c] = (uint16_t)sum;
+    }
+  }
+  __syncthreads();
+  // column sums for output column c, rows r0 .. r0 + 7 (window of output
+  // row r: staged rows r .. r + 2h)
   const uint32_t area = (uint32_t)((2 * h + 1) * (2 * h + 1));
-  const uint16_t *col = jb.hsum + x;
-  uint32_t s = 0;
-  for (int dy = -h; dy <= h; ++dy) s += col[(size_t)clampi(y0 + dy, H - 1) * W];
-  jb.blurred[(size_t)y0 * W + x] = (uint8_t)((s + area / 2) / area);
-  const int y1 = min(y0 + kRun, H);
-  for (int y = y0 + 1; y < y1; ++y) {
-    s += col[(size_t)clampi(y + h, H - 1) * W];
-    s -= col[(size_t)clampi(y - h - 1, H - 1) * W];
-    jb.blurred[(size_t)y * W + x] = (uint8_t)((s + area / 2) / area);
+  for (int k = threadIdx.x; k < kBT * (kBT / 8); k += 256) {
+    const int c = k & (kBT - 1), r0 = (k / kBT) * 8, x = x0 + c;
+    const uint16_t *col = s_row + r0 * kBT + c;
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (int dy = 0; dy <= 2 * h; ++dy) sum += col[dy * kBT];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r > 0) {
+        sum += col[(r + 2 * h) * kBT];
+        sum -= col[(r - 1) * kBT];
+      }
+      const int y = y0 + r0 + r;
+      if (x < W && y < H) jb.blurred[(size_t)y * W + x] = (uint8_t)((sum + area / 2) / area);
+    }
   }
 }
 
@@ -235,10 +269,10 @@ hipError_t launch_batch_descriptors(const BatchStage &rows, hipStream_t stream) 
 
 hipError_t launch_descriptors(const DescJobs &jobs, hipStream_t stream) {
   if (jobs.count <= 0) return hipSuccess;
-  const dim3 ghs((jobs.W + 256 * kRun - 1) / (256 * kRun), jobs.H, jobs.count);
-  hipLaunchKernelGGL(k_hsum, ghs, dim3(256), 0, stream, jobs);
-  const dim3 gvs((jobs.W + 255) / 256, (jobs.H + kRun - 1) / kRun, jobs.count);
-  hipLaunchKernelGGL(k_vsum, gvs, dim3(256), 0, stream, jobs);
+  for (int k = 0; k < jobs.count; ++k)
+    if (jobs.job[k].n < 1 || jobs.job[k].n > 2 * kBHmax + 1) return hipErrorInvalidValue;
+  const dim3 gb((jobs.W + kBT - 1) / kBT, (jobs.H + kBT - 1) / kBT, jobs.count);
+  hipLaunchKernelGGL(k_blur, gb, dim3(256), 0, stream, jobs);
   int pmax = 0;
   for (int k = 0; k < jobs.count; ++k) pmax = std::max(pmax, ffk::desc_pad(jobs.job[k].n));
   const size_t lds = 5 * (size_t)desc_row_stride(jobs.W);
