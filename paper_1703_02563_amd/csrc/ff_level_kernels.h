@@ -467,16 +467,16 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   // of Flow Fields+ end at P - 1, the scale at T - 1)
   auto rs_after = [&](int t) { return t != a.P - 1 && t != a.T - 1; };
   // random-search candidate of cell (i, j) at step t from its current state
+  // (branch-free, so that two draws in one block can interleave)
   [[maybe_unused]] auto rs_candidate = [&](int i, int j, int l, int t, int32_t &fc) {
     const uint32_t c0 = s_cost[l];
     const int32_t f0 = s_flow[l];
-    if (c0 == kUnset) return false;
     int ox, oy;
     ffk::rs_offset(a.seed, d.stream_id, a.level, t, j, i, t < a.P ? a.Rnp : a.Rn, ox, oy);
     const int fx = ffk::flow_x(f0) + ox, fy = ffk::flow_y(f0) + oy;
     const int tx = i * n + fx, ty = j * n + fy;
     fc = ffk::pack_flow(fx, fy);
-    return (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
+    return c0 != kUnset && (ox | oy) != 0 && tx >= 0 && tx < W && ty >= 0 && ty < H;
   };
 
   // initial state of the valid window: the state of every cell of a thread
@@ -794,8 +794,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
             const bool live1 = cell_of(1, base + tid, i1, j1);
             const int l1 = (j1 - gj0) * G::LW + (i1 - gi0);
             int32_t fc = 0, fc1 = 0;
-            const bool act = live && rs_candidate(i, j, l, t, fc);
-            const bool act1 = live1 && rs_candidate(i1, j1, l1, t, fc1);
+            bool act = false, act1 = false;
+            if (__ballot(live || live1)) {  // (a cell index past the valid region reads slot 0)
+              act = rs_candidate(i, j, live ? l : 0, t, fc) && live;
+              act1 = rs_candidate(i1, j1, live1 ? l1 : 0, t, fc1) && live1;
+            }
             if (act) {
               s_flags[l] = (uint32_t)fc;
               cnt += owned(i, j);
