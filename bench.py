@@ -119,13 +119,13 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # profiles/level_kernel_traffic_1024x436.md), scaled by what the same
 # counters read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x
 # 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 20619.0 * 1024 * 2.0 + 6992.8 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "2f96740cda4e738a"
+TRAFFIC_BYTES = 20624.5 * 1024 * 2.0 + 6992.8 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "7cf6c2fbc3fcc483"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 20, 3  # scale-1 launch table the counters were taken with
 # Vector-L1 tag accesses of 64 bytes per launch of the same kernel
 # (TCP_TOTAL_CACHE_ACCESSES_sum, same run conditions; the L1 data path moves
 # 64 bytes per clock per CU).
-L1_ACCESSES = 26123563.6
+L1_ACCESSES = 26123086.4
 L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
 # Matrix-core and VALU issue utilisation of the NN seed kernel (k_nn, both
 # directions) from SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU and
