@@ -1281,7 +1281,12 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
   char *base = static_cast<char *>(ws);
   const uint8_t *img[2] = {img1, img2};
 
-  // descriptors of both images at every scale
+  // descriptors of both images at every scale; the weight-class row maps
+  // only where the table's level-kernel variant evaluates on them
+  const ffh::Tuning tun = tuning_of(params->tuning);
+  auto wform_used = [&](int lv) {
+    return lv >= lmin && params->subpixel == 0 && !params->raster && r == 3 && ffh::level_uses_wform(tun.variant[lv]);
+  };
   uint8_t *desc[2][kMaxLevels], *desc1[2];
   ffh::DescJobs jobs{};
   jobs.W = W;
@@ -1296,7 +1301,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       jobs.job[z] = {img[im], reinterpret_cast<uint16_t *>(base + lay.hsum) + (size_t)z * lay.N,
                      reinterpret_cast<uint8_t *>(base + lay.blur) + (size_t)z * lay.N,
                      lv < lmin ? nullptr : desc[im][lv], lv == 0 ? desc1[im] : nullptr,
-                     lv < lmin ? nullptr : reinterpret_cast<uint8_t *>(base + lay.wform[im][lv]), 1 << lv};
+                     wform_used(lv) ? reinterpret_cast<uint8_t *>(base + lay.wform[im][lv]) : nullptr, 1 << lv};
     }
   }
   hipError_t e = ffh::launch_descriptors(jobs, s);
@@ -1442,8 +1447,8 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
       for (int dr = 0; dr < nd; ++dr) {
         k.dir[dr].Da = desc[dr][lv];
         k.dir[dr].Db = desc[dr ^ 1][lv];
-        k.dir[dr].Wa = reinterpret_cast<const uint8_t *>(base + lay.wform[dr][lv]);
-        k.dir[dr].Wb = reinterpret_cast<const uint8_t *>(base + lay.wform[dr ^ 1][lv]);
+        k.dir[dr].Wa = wform_used(lv) ? reinterpret_cast<const uint8_t *>(base + lay.wform[dr][lv]) : nullptr;
+        k.dir[dr].Wb = wform_used(lv) ? reinterpret_cast<const uint8_t *>(base + lay.wform[dr ^ 1][lv]) : nullptr;
         k.dir[dr].flow = gflow[lv][dr];
         k.dir[dr].cost = gcost[lv][dr];
         k.dir[dr].nn_key = keys + (size_t)dr * lay.M;
