@@ -17,10 +17,10 @@ constexpr int kH = ffh::kLevelHalo;
 // the grid is too small to give every compute unit a tile.  A variant with
 // quad evaluations addresses image b with 32-bit offsets; for a larger map
 // its fallback (a halo at least as wide; batches count their work items
-// with level_tiles, which follows the fallback) runs instead.  Variants 18-23
-// evaluate interior cells on the weight-class row maps; without those maps
-// (a caller that passes none) their descriptor-quad twin (`nowf`, same tile
-// and halo) runs.
+// with level_tiles, which follows the fallback) runs instead.  Variants 18-25,
+// 28, 29 and 31 evaluate interior cells on the weight-class row maps; without
+// those maps (a caller that passes none) their descriptor-quad twin (`nowf`,
+// same halo, the same tile where one exists) runs.
 struct Variant {
   int tw, th, halo, fallback, nowf;
 };
@@ -31,8 +31,8 @@ constexpr Variant kVariants[] = {
     {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},   {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},
     {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},
     {64, 32, 4, 0, 16},   {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},     {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},
-    {16, 16, kH, 10, 30}};
-constexpr int kNumVariants = 31;
+    {16, 16, kH, 10, 30}, {32, 12, 2, 2, 12}};
+constexpr int kNumVariants = 32;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);
@@ -79,14 +79,16 @@ constexpr int kNumVariantsF32 = 5;
 static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float variant table");
 
 // The built-in launch tables.  Byte descriptors: weight-class evaluations
-// on 32x16 tiles (512 threads) at n = 1, 16x16 tiles at n = 2 and 4 (1024
-// threads at n = 4), 8x8 tiles with 1024 threads at n = 8, 16; three steps
-// per launch (the table tuned at 1024x436, which also halves the time of
-// the older one-lane table at 160x120 and 1242x375).  Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
+// on 32x12 tiles (256 threads, six workgroups per compute unit; two steps
+// per launch) at n = 1 and on 16x16 tiles at n = 2, descriptor quads with
+// 1024 threads on 16x16 tiles at n = 4 and on 8x8 tiles at n = 8, 16; at
+// most three steps per launch (the table tuned at 1024x436, which also
+// halves the time of the older one-lane table at 160x120 and 1242x375).
+// Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
 // on (16x16 tiles leave most compute units idle there), one step per launch
 // (the float evaluations are expensive enough that this is fastest at every
 // scale, measured at 1024x436).
-constexpr ffh::Tuning kDefaultTuning = {{20, 19, 30, 26, 27, 3, 3},
+constexpr ffh::Tuning kDefaultTuning = {{31, 19, 30, 26, 27, 3, 3},
                                         {3, 3, 3, 3, 3, 0, 0},
                                         {0, 0, 1, 1, 1, 1, 1},
                                         {1, 1, 1, 1, 1, 1, 1}};

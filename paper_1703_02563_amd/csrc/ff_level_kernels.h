@@ -919,14 +919,21 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
 // the register budget keeps the loads of a patch in flight together instead
 // of one after another; five for the weight-class kernels (EV = 4) whose LDS
 // window lets five waves per SIMD be resident (their 13 row loads fit 80
-// registers; measured 1.6 % faster per pair at 1024x436).
+// registers; measured 1.6 % faster per pair at 1024x436), and up to seven
+// for the smaller weight-class tiles whose window lets six or seven
+// workgroups share a compute unit: the launch is bound by the latency of
+// its barrier-separated phases, which more resident workgroups hide.
 template <int TW, int TH, int kThreads, int EV, int HALO>
 constexpr int level_waves() {
   if constexpr (EV == 2) return 2;
   if constexpr (EV != 4) return 4;
   using G = Geo<TW, TH, HALO>;
   constexpr int lds = G::LH * G::LW * 14 + (G::LH + 12) * G::LW * 16;  // state, flags, queue; image a's rows
-  return (160 * 1024 / lds) * (kThreads / 64) >= 20 ? 5 : 4;
+  constexpr int fit = 160 * 1024 / lds * (kThreads / 64) / 4;           // waves per SIMD the LDS allows
+  // a tile whose area is not a power of two (32x12) is sized for six or
+  // seven resident workgroups
+  if constexpr (kThreads == 256 && ((TW * TH) & (TW * TH - 1)) != 0) return fit < 5 ? 4 : (fit > 7 ? 7 : fit);
+  return fit >= 5 ? 5 : 4;
 }
 
 // One workgroup per (direction, tile) of one pair; XCD-aware order.
@@ -1067,6 +1074,7 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 28: return launch_v<LOG2N, 8, 8, 1024, 4>(a, batch, stream);
     case 29: return launch_v<LOG2N, 8, 8, 1024, 4, 4>(a, batch, stream);
     case 30: return launch_v<LOG2N, 16, 16, 1024, 3>(a, batch, stream);
+    case 31: return launch_v<LOG2N, 32, 12, 256, 4, 2>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }
