@@ -99,6 +99,22 @@ def test_descriptors_bit_exact(shape, n):
     assert sorted(phase_columns(Wp, n)) == list(range(Wp))  # a permutation
 
 
+@pytest.mark.parametrize("shape", [(37, 53), (120, 160), (9, 300), (200, 131)])
+@pytest.mark.parametrize("n", [3, 6, 12, 24, 32, 48, 64])
+def test_blur_sub_and_large_scales_bit_exact(shape, n):
+    """The box filter at the sub-scales n* = 3n/2 and at the largest scales
+    (half-widths up to 32, the widest tile border the one-launch blur
+    stages), on frames that span several 64 x 64 tiles with ragged edges;
+    the row-major descriptors at the same scale."""
+    img, _ = random_images(300 + n, *shape, kind="uniform")
+    blurred, desc, plain = ff.descriptors(dev(img), n, rowmajor=True)
+    eb = oracle.blur(img, n)
+    assert np.array_equal(host(blurred), eb)
+    assert np.array_equal(host(plain), oracle.descriptor(eb, n))
+    if n & (n - 1) == 0:  # power-of-two scales: the phase-ordered map too
+        assert np.array_equal(host(desc), to_lib(oracle.descriptor(eb, n), n))
+
+
 def _descs(img, levels):
     return oracle.descriptors_all(img, levels)
 
