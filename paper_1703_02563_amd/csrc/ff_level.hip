@@ -80,15 +80,16 @@ static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float 
 
 // The built-in launch tables.  Byte descriptors: weight-class evaluations
 // on 32x12 tiles (256 threads, six workgroups per compute unit; two steps
-// per launch) at n = 1 and on 16x16 tiles at n = 2, descriptor quads with
-// 1024 threads on 16x16 tiles at n = 4 and on 8x8 tiles at n = 8, 16; at
-// most three steps per launch (the table tuned at 1024x436, which also
-// halves the time of the older one-lane table at 160x120 and 1242x375).
+// per launch) at n = 1, descriptor quads on 16x16 tiles with 256 threads
+// and a halo of 2 at n = 2, with 1024 threads on 16x16 tiles at n = 4 and
+// on 8x8 tiles at n = 8, 16; at most three steps per launch (the table
+// tuned at 1024x436, which also halves the time of the older one-lane
+// table at 160x120 and 1242x375).
 // Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
 // on (16x16 tiles leave most compute units idle there), one step per launch
 // (the float evaluations are expensive enough that this is fastest at every
 // scale, measured at 1024x436).
-constexpr ffh::Tuning kDefaultTuning = {{31, 19, 30, 26, 27, 3, 3},
+constexpr ffh::Tuning kDefaultTuning = {{31, 11, 30, 26, 27, 3, 3},
                                         {3, 3, 3, 3, 3, 0, 0},
                                         {0, 0, 1, 1, 1, 1, 1},
                                         {1, 1, 1, 1, 1, 1, 1}};

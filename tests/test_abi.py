@@ -129,7 +129,7 @@ def test_default_tuning_and_validation():
     t = ff.default_tuning()
     assert t.variant_f32 == [0, 0, 1, 1, 1, 1, 1] and t.passes_f32 == [1] * 7
     assert all(0 <= v < lib.ff_level_variant_count() for v in t.variant)
-    assert t.variant == [31, 19, 30, 26, 27, 3, 3] and t.passes == [3, 3, 3, 3, 3, 0, 0]
+    assert t.variant == [31, 11, 30, 26, 27, 3, 3] and t.passes == [3, 3, 3, 3, 3, 0, 0]
     fake = C.c_void_p(0x1000)
     for bad in (dict(variant=[lib.ff_level_variant_count()] * 7), dict(variant=[-1] * 7), dict(passes=[65] * 7),
                 dict(passes_f32=[-1] * 7), dict(variant_f32=[5] * 7)):
@@ -150,7 +150,8 @@ def test_level_launches_follow_the_run_length_table():
         tc = t.replace(passes=[passes] * 7).to_c()
         assert lib.ff_level_launches(C.byref(tc), T, 1, 0) == expect, (passes, T)
         assert ff.level_launches(ff.Params(iters=T, tuning=t.replace(passes=[passes] * 7)), 1) == expect
-    assert lib.ff_level_launches(None, 6, 1, 0) == 2  # the built-in table: 3 steps per launch at n = 2
+    assert lib.ff_level_launches(None, 6, 1, 0) == 3  # the built-in table at n = 2: a halo of 2, 2 steps per launch
+    assert lib.ff_level_launches(None, 6, 2, 0) == 2  # at n = 4: a halo of 6 capped at 3 steps per launch
     assert lib.ff_level_launches(None, 0, 1, 0) == -1 and lib.ff_level_launches(None, 6, 9, 0) == -1
     assert lib.ff_level_launches(None, 6, 1, 2) == -1
 
