@@ -31,8 +31,8 @@ constexpr Variant kVariants[] = {
     {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},   {32, 16, 4, 2, 16},   {16, 16, 4, 3, 17},
     {32, 16, 2, 2, 12},   {16, 16, 2, 3, 11},   {8, 8, kH, 8, 14},    {8, 8, 2, 8, 15},     {32, 16, 4, 2, 16},
     {64, 32, 4, 0, 16},   {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},     {8, 8, kH, 8, 26},    {8, 8, 4, 8, 27},
-    {16, 16, kH, 10, 30}, {32, 12, 2, 2, 12}};
-constexpr int kNumVariants = 32;
+    {16, 16, kH, 10, 30}, {32, 12, 2, 2, 12},   {4, 4, 4, 8, 32}};
+constexpr int kNumVariants = 33;
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 
 using ScaleLaunch = hipError_t (*)(const ffh::LevelKArgs &, const ffh::BatchStage *, int, hipStream_t);
@@ -81,15 +81,16 @@ static_assert(sizeof(kHaloF32) / sizeof(kHaloF32[0]) == kNumVariantsF32, "float 
 // The built-in launch tables.  Byte descriptors: weight-class evaluations
 // on 32x12 tiles (256 threads, six workgroups per compute unit; two steps
 // per launch) at n = 1, descriptor quads on 16x16 tiles with 256 threads
-// and a halo of 2 at n = 2, with 1024 threads on 16x16 tiles at n = 4 and
-// on 8x8 tiles at n = 8, 16; at most three steps per launch (the table
-// tuned at 1024x436, which also halves the time of the older one-lane
-// table at 160x120 and 1242x375).
+// and a halo of 2 at n = 2, with 1024 threads on 16x16 tiles at n = 4, on
+// 8x8 tiles at n = 8 and on 4x4 tiles at n = 16 (so that the small grid
+// still gives most compute units a workgroup); at most three steps per
+// launch (the table tuned at 1024x436, which also halves the time of the
+// older one-lane table at 160x120 and 1242x375).
 // Float features: 16x16 tiles at n <= 2, 8x8 tiles from n = 4
 // on (16x16 tiles leave most compute units idle there), one step per launch
 // (the float evaluations are expensive enough that this is fastest at every
 // scale, measured at 1024x436).
-constexpr ffh::Tuning kDefaultTuning = {{31, 11, 30, 26, 27, 3, 3},
+constexpr ffh::Tuning kDefaultTuning = {{31, 11, 30, 26, 32, 3, 3},
                                         {3, 3, 3, 3, 3, 0, 0},
                                         {0, 0, 1, 1, 1, 1, 1},
                                         {1, 1, 1, 1, 1, 1, 1}};

@@ -1075,6 +1075,7 @@ hipError_t launch_n(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, int 
     case 29: return launch_v<LOG2N, 8, 8, 1024, 4, 4>(a, batch, stream);
     case 30: return launch_v<LOG2N, 16, 16, 1024, 3>(a, batch, stream);
     case 31: return launch_v<LOG2N, 32, 12, 256, 4, 2>(a, batch, stream);
+    case 32: return launch_v<LOG2N, 4, 4, 1024, 3, 4>(a, batch, stream);
     default: return hipErrorInvalidValue;
   }
 }

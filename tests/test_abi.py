@@ -129,7 +129,7 @@ def test_default_tuning_and_validation():
     t = ff.default_tuning()
     assert t.variant_f32 == [0, 0, 1, 1, 1, 1, 1] and t.passes_f32 == [1] * 7
     assert all(0 <= v < lib.ff_level_variant_count() for v in t.variant)
-    assert t.variant == [31, 11, 30, 26, 27, 3, 3] and t.passes == [3, 3, 3, 3, 3, 0, 0]
+    assert t.variant == [31, 11, 30, 26, 32, 3, 3] and t.passes == [3, 3, 3, 3, 3, 0, 0]
     fake = C.c_void_p(0x1000)
     for bad in (dict(variant=[lib.ff_level_variant_count()] * 7), dict(variant=[-1] * 7), dict(passes=[65] * 7),
                 dict(passes_f32=[-1] * 7), dict(variant_f32=[5] * 7)):
