@@ -119,19 +119,19 @@ SAD_OPS_PER_EVAL = 7 * 7 * 16 // 4  # 784 byte differences = 196 v_sad_u8 per pa
 # profiles/level_kernel_traffic_1024x436.md), scaled by what the same
 # counters read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x
 # 1.0).  Valid only for the kernel sources it was measured on.
-TRAFFIC_BYTES = 20606.1 * 1024 * 2.0 + 6998.2 * 1024 * 1.0
-TRAFFIC_SOURCES_SHA = "d1c9fd5f2875b0e8"
+TRAFFIC_BYTES = 20606.3 * 1024 * 2.0 + 6998.2 * 1024 * 1.0
+TRAFFIC_SOURCES_SHA = "7ee290fff2ddf513"
 TRAFFIC_VARIANT, TRAFFIC_PASSES = 31, 3  # scale-1 launch table the counters were taken with
 # Vector-L1 tag accesses of 64 bytes per launch of the same kernel
 # (TCP_TOTAL_CACHE_ACCESSES_sum, same run conditions; the L1 data path moves
 # 64 bytes per clock per CU).
-L1_ACCESSES = 26902916.4
+L1_ACCESSES = 26903544.8
 L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
 # Matrix-core and VALU issue utilisation of the NN seed kernel (k_nn, both
 # directions) from SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU and
 # GRBM_GUI_ACTIVE (profiles/level_kernel_sq_1024x436.md); valid for the
 # ff_nn.hip it was measured on.
-NN_COUNTERS = {"mfma_busy": 0.186, "valu_issue": 0.742, "mfma_instructions": 1562624}
+NN_COUNTERS = {"mfma_busy": 0.185, "valu_issue": 0.740, "mfma_instructions": 1562624}
 NN_SOURCES_SHA = "3b4b65b8af50d83f"
 LEVEL_SOURCES = ("paper_1703_02563_amd/csrc/ff_level.hip", "paper_1703_02563_amd/csrc/ff_level_kernels.h",
                  "paper_1703_02563_amd/csrc/ff_level_s0.hip", "paper_1703_02563_amd/csrc/ff_device.h",

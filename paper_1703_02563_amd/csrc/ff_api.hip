@@ -232,16 +232,23 @@ int level_runs(const ffh::Tuning &tun, int lv, int T, int fcost, int runs[][2]) 
 // reads cells another workgroup of the same launch is writing; the last
 // launch writes flow/cost.
 hipError_t run_level_blocked(ffh::LevelKArgs k, int W, int H, int lv, const ff_params *p, int first_mode,
-                             hipStream_t s, int32_t *const *sflow = nullptr, uint32_t *const *scost = nullptr) {
+                             hipStream_t s, int32_t *const *sflow = nullptr, uint32_t *const *scost = nullptr,
+                             int sub_m = 0) {
   const int n = 1 << lv;
-  const ScaleSteps sst = scale_steps(p, lv);
+  // a sub-scale stage (patch scale sub_m, Sec. 3.3) runs the Flow Fields+
+  // step groups at the random-search distances of its patch scale; its
+  // generator level field is lv + 16 (as in the per-step kernels)
+  const ScaleSteps sst = sub_m ? ScaleSteps{p->plus_iters, p->iters, rs_radius(sub_m, p->R_num, p->R_den),
+                                            rs_radius(sub_m, p->Rp_num, p->R_den)}
+                               : scale_steps(p, lv);
   const int T = sst.total();
   k.W = W;
   k.H = H;
   k.n = n;
   k.Wn = ceil_div(W, n);
   k.Hn = ceil_div(H, n);
-  k.level = lv;
+  k.level = lv + (sub_m ? 16 : 0);
+  k.sub_m = sub_m;
   k.Rn = sst.Rn;
   k.Rnp = sst.Rnp;
   k.P = sst.P;
@@ -1456,7 +1463,23 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
         k.dir[dr].ccost = lv + 1 < L ? gcost[lv + 1][dr] : nullptr;
       }
       const bool sub = m != (1 << lv);
-      if (sub || ffh::level_stepwise(tuning_of(params->tuning).variant[lv]) || entry == 1) {
+      const bool stepwise = ffh::level_stepwise(tuning_of(params->tuning).variant[lv]);
+      // a sub-scale stage on the blocked quad kernels: radius 3, its map
+      // addressed with 32-bit offsets, not the last stage (the Fast step
+      // count applies there), entered from the coarser grid
+      if (sub && !stepwise && r == 3 && entry == 2 && st != nst - 1 &&
+          (size_t)(W + 2 * ffk::desc_pad(m)) * (H + 2 * ffk::desc_pad(m)) * 16 < ((size_t)1 << 31)) {
+        for (int dr = 0; dr < nd; ++dr) {
+          k.dir[dr].Da = sdesc[dr][lv];
+          k.dir[dr].Db = sdesc[dr ^ 1][lv];
+          k.dir[dr].Wa = nullptr;
+          k.dir[dr].Wb = nullptr;
+        }
+        if ((e = run_level_blocked(k, W, H, lv, params, ffh::kLevelSeed, s, sflow[lv], scost[lv], m)) != hipSuccess)
+          return FF_ERR_LAUNCH;
+        continue;
+      }
+      if (sub || stepwise || entry == 1) {
         ffh::LevelArgs a{};
         a.ndir = nd;
         for (int dr = 0; dr < nd; ++dr) {
@@ -1464,7 +1487,7 @@ ff_status ff_flow_fields(const uint8_t *img1, const uint8_t *img2, int32_t W, in
           a.dir[dr] = {sub ? sdesc[dr][lv] : kd.Da, sub ? sdesc[dr ^ 1][lv] : kd.Db, kd.flow, kd.cost, kd.cflow,
                        kd.ccost, kd.nn_key, desc1[dr], kd.n_evals, nullptr, dr};
         }
-        if (sub || ffh::level_stepwise(tuning_of(params->tuning).variant[lv])) {
+        if (sub || stepwise) {
           if ((e = run_stage(a, W, H, lv, m, entry, st == nst - 1, params, s)) != hipSuccess) return FF_ERR_LAUNCH;
           continue;
         }

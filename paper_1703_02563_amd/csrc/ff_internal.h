@@ -172,6 +172,7 @@ struct LevelKArgs {
   int radius;   // patch radius: 3, or 2 and 4 (byte descriptors only); 0 means 3
   int tiles_x;  // set by launch_level
   int halo[4];
+  int sub_m;    // a sub-scale stage's patch scale m (Da/Db: image-order maps of scale m, radius 3); 0: n
 };
 // Padded, phase-ordered copy of a float [H][W][16] feature map of scale n.
 hipError_t launch_pad_features(const float *f, int W, int H, int n, float *out, hipStream_t stream);

@@ -175,6 +175,11 @@ hipError_t launch_level(LevelKArgs a, hipStream_t stream) {
     if (l2 < 0 || l2 >= 7) return hipErrorInvalidValue;
     return kScaleF32[l2](a, a.variant, stream);
   }
+  if (a.sub_m) {  // a sub-scale stage: the descriptor-quad kernel of the table's window halo
+    const int v = blocked_variant(a.variant);
+    if (l2 < 0 || l2 >= 7 || v < 0 || v >= kNumVariants || (a.radius != 0 && a.radius != 3)) return hipErrorInvalidValue;
+    return dispatch(a, nullptr, l2, quad_variant(v), stream);
+  }
   if (a.radius == 2 || a.radius == 4) {
     const int v = blocked_variant(a.variant);
     if (l2 < 0 || l2 >= 7 || v < 0 || v >= kNumVariants || !level_map_fits(a.W, a.H, l2))

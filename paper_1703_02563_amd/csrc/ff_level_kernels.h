@@ -194,6 +194,37 @@ __device__ __forceinline__ uint32_t eval_quad_gg(__amdgpu_buffer_rsrc_t da, __am
   return s;
 }
 
+// E(p, f) at the patch scale m of a sub-scale stage (Sec. 3.3) by a quad,
+// both images read from their image-order maps of scale m (border
+// P = kDescPad * m, rows of W + 2P entries; a sample p + m (u, v) of a patch
+// around an in-image pixel lies inside the border, so no clamping): lane r
+// sums columns r and r + 4 of the 7 x 7 samples, the quad adds the lanes.
+// Integer sums: the value is that of the per-step kernels' patch_cost.
+template <int RR = kR>
+__device__ __forceinline__ uint32_t eval_quad_sub(__amdgpu_buffer_rsrc_t da, __amdgpu_buffer_rsrc_t db, int W, int m,
+                                                  int ax, int ay, int bx, int by, int r) {
+  constexpr int K = 2 * RR + 1;
+  const int P = ffk::desc_pad(m), Wp = W + 2 * P;
+  const int rowb = m * Wp * 16, colb = m * 16;
+  const int u1 = r, u2 = min(r + 4, K - 1);
+  const int offa = ((ay - RR * m + P) * Wp + (ax - RR * m + P)) * 16;
+  const int offb = ((by - RR * m + P) * Wp + (bx - RR * m + P)) * 16;
+  uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+  for (int v = 0; v < K; ++v) {
+    const auto a1 = __builtin_amdgcn_raw_buffer_load_b128(da, offa + u1 * colb, v * rowb, 0);
+    const auto a2 = __builtin_amdgcn_raw_buffer_load_b128(da, offa + u2 * colb, v * rowb, 0);
+    const auto b1 = __builtin_amdgcn_raw_buffer_load_b128(db, offb + u1 * colb, v * rowb, 0);
+    const auto b2 = __builtin_amdgcn_raw_buffer_load_b128(db, offb + u2 * colb, v * rowb, 0);
+    s1 = ffk::sad16(make_uint4(a1[0], a1[1], a1[2], a1[3]), make_uint4(b1[0], b1[1], b1[2], b1[3]), s1);
+    s2 = ffk::sad16(make_uint4(a2[0], a2[1], a2[2], a2[3]), make_uint4(b2[0], b2[1], b2[2], b2[3]), s2);
+  }
+  uint32_t s = s1 + (r < K - 4 ? s2 : 0u);
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  return s;
+}
+
 // E_n(p, f) by one lane from the weight-class row maps (wform_index), for a
 // cell p and a target (bx, by) both at least 3n inside the image: the 13
 // rows y + n b (b = -6..6) of image a come from LDS (`pa`: the cell's entry
@@ -270,8 +301,11 @@ __device__ __forceinline__ uint32_t eval_quad_f32(const float4 *pa, const float4
 
 // The run of passes for tile `tile` of one direction `d` (a holds the
 // pair's sizes and the schedule).  All threads of the workgroup call it.
-template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo, int RR = kR>
+template <int LOG2N, int TW, int TH, int kThreads, int EV, bool F32 = false, int HALO = kHalo, int RR = kR,
+          bool SUB = false>
 __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::LevelKDir &d, int tile) {
+  // SUB: a sub-scale stage (patch scale a.sub_m, image-order maps), descriptor quads at radius 3
+  static_assert(!SUB || (EV == 3 && !F32 && RR == kR), "sub-scale stages run the radius-3 quad kernels");
   // patch radius RR: 3, or 2 and 4 with the descriptor-quad evaluations
   // (the weight-class maps and the float path hold radius-3 patches)
   static_assert(Geo<TW, TH, HALO, RR>::LW * Geo<TW, TH, HALO, RR>::LH + kThreads < 65536,
@@ -342,11 +376,13 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
   } else if constexpr (!F32) {
     const uint4 *Da = reinterpret_cast<const uint4 *>(d.Da);
     uint4 *v = sv;
+    if constexpr (!SUB) {  // a sub-scale stage reads image a from its map instead
 #pragma unroll
-    for (int it = 0; it < NS; ++it) {
-      const int k = min(it * kThreads + tid, G::DH * G::DW - 1);
-      const int vi = gi0 - RR + k % G::DW, vj = gj0 - RR + k / G::DW;
-      v[it] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
+      for (int it = 0; it < NS; ++it) {
+        const int k = min(it * kThreads + tid, G::DH * G::DW - 1);
+        const int vi = gi0 - RR + k % G::DW, vj = gj0 - RR + k / G::DW;
+        v[it] = Da[ffk::desc_index(clampi(vi * n, W - 1), clampi(vj * n, H - 1), LOG2N, W)];
+      }
     }
   } else {
     const float4 *Da = reinterpret_cast<const float4 *>(d.Da);
@@ -372,6 +408,16 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
     if constexpr (F32) {
       const float4 *pa = s_daf + 4 * ((j - gj0 + RR) * G::DW + (i - gi0 + RR));
       return eval_quad_f32<LOG2N, G::DW>(pa, reinterpret_cast<const float4 *>(d.Db), W, bx, by, qr);
+    } else if constexpr (SUB) {
+      // both maps of patch scale a.sub_m (image order) through resources
+      // of their size
+      const int sm = a.sub_m;
+      const int bytes = (int)((size_t)(H + 2 * ffk::desc_pad(sm)) * (W + 2 * ffk::desc_pad(sm)) * 16);
+      const __amdgpu_buffer_rsrc_t ra =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(d.Da), (short)0, bytes, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rb =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(d.Db), (short)0, bytes, 0x00020000);
+      return eval_quad_sub<RR>(ra, rb, W, sm, i * n, j * n, bx, by, qr);
     } else {
       const uint4 *pa = s_da + (j - gj0 + RR) * G::DW + (i - gi0 + RR);
       return eval_quad<LOG2N, G::DW, RR>(pa, db_rsrc, W, bx, by, qr);
@@ -522,9 +568,11 @@ __device__ __forceinline__ void level_body(const ffh::LevelKArgs &a, const ffh::
       for (int it = 0; it < NS; ++it)
         if (it * kThreads + tid < NSTAGE) s_wa[it * kThreads + tid] = sv[it];
     } else if constexpr (!F32) {
+      if constexpr (!SUB) {
 #pragma unroll
-      for (int it = 0; it < NS; ++it)
-        if (it * kThreads + tid < G::DH * G::DW) s_da[it * kThreads + tid] = sv[it];
+        for (int it = 0; it < NS; ++it)
+          if (it * kThreads + tid < G::DH * G::DW) s_da[it * kThreads + tid] = sv[it];
+      }
     } else {
 #pragma unroll
       for (int it = 0; it < NS; ++it)
@@ -945,6 +993,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   level_body<LOG2N, TW, TH, kThreads, EV, false, HALO, RR>(a, a.dir[wg / tiles], wg % tiles);
 }
 
+// A sub-scale stage (Sec. 3.3: patch scale a.sub_m on the grid of scale n):
+// the radius-3 descriptor-quad kernel reading both images' image-order maps.
+template <int LOG2N, int TW, int TH, int kThreads, int HALO>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    level_waves<TW, TH, kThreads, 3, HALO>(), level_waves<TW, TH, kThreads, 3, HALO>()))) void k_level_sub(ffh::LevelKArgs a) {
+  const int tiles = a.tiles_x * ((a.Hn + TH - 1) / TH);
+  const int wg = ffk::xcd_remap(blockIdx.x, gridDim.x);
+  level_body<LOG2N, TW, TH, kThreads, 3, false, HALO, kR, true>(a, a.dir[wg / tiles], wg % tiles);
+}
+
 // Float learned features (padded float maps in LevelKDir::Da/Db).
 template <int LOG2N, int TW, int TH, int kThreads, int HALO>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_level_f32(
@@ -1007,6 +1065,15 @@ hipError_t launch_v(const ffh::LevelKArgs &a, const ffh::BatchStage *batch, hipS
   ffh::LevelKArgs b = a;
   b.tiles_x = (a.Wn + TW - 1) / TW;
   const int tiles = b.tiles_x * ((a.Hn + TH - 1) / TH);
+  if (a.sub_m) {
+    if constexpr (EV == 3 && RR == kR) {
+      hipLaunchKernelGGL((k_level_sub<LOG2N, TW, TH, THREADS, HALO>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream,
+                         b);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   hipLaunchKernelGGL((k_level<LOG2N, TW, TH, THREADS, EV, HALO, RR>), dim3(tiles * a.ndir), dim3(THREADS), 0, stream,
                      b);
   return hipGetLastError();

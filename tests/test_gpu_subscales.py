@@ -12,6 +12,7 @@ import oracle
 import paper_1703_02563_amd as ff
 from ffgen import CONFIG_PARAMS, make_pair, random_images
 from test_gpu_parity import _random_level_state, as_u32, counter, dev, host, to_lib
+from tuning_util import with_tuning
 
 pytestmark = pytest.mark.gpu
 NT = max(1, min(16, os.cpu_count() or 1))
@@ -75,6 +76,23 @@ def test_subscale_fields_bit_exact(shape, L, T, kw):
     ia, ib = random_images(2300 + H + W, H, W)
     g, o = _run(ia, ib, L, T, **kw)
     _compare(g, o)
+
+
+def test_subscale_stages_every_variant():
+    """The (n, 3n/2) stages run on the blocked descriptor-quad kernel of the
+    table's window halo: every variant of the table (one-lane, quad and
+    weight-class entries, each mapped to its quad kernel) gives the oracle's
+    fields, costs and counts."""
+    H, W = 61, 95
+    ia, ib = random_images(2417, H, W)
+    kw = dict(plus_iters=4, Rp_num=2)
+    o = oracle.flow_fields(ia, ib, 3, 6, nthreads=NT, subscales=True, **kw)
+    for v in range(int(ff.lib().ff_level_variant_count())):
+        for passes in (0, 2):
+            prm = with_tuning(ff.Params(levels=3, iters=6, subscales=True, **kw), variant=[v] * 7,
+                              passes=[passes] * 7)
+            g = ff.flow_fields(dev(ia), dev(ib), prm)
+            _compare(g, o)
 
 
 def test_subscales_config1_bit_exact():
