@@ -135,7 +135,9 @@ typedef struct {
      * the costs at the new patch scale (ff_rescore_level); every stage runs
      * the plus_iters / iters steps (fine_iters on the last one); the
      * generator's level field is log2 n, plus 16 on a sub-scale stage.  Runs
-     * on the per-step kernels.  Not with fast_x2 (FF_ERR_ARG); ff_run_level,
+     * on the temporally blocked kernels at radius 3 (the sub-scale stages on
+     * descriptor-quad kernels reading both images' maps), else on the
+     * per-step kernels.  Not with fast_x2 (FF_ERR_ARG); ff_run_level,
      * the batched and the learned calls return FF_ERR_UNSUPPORTED. */
     int32_t subscales;
 } ff_params;
